@@ -1,0 +1,220 @@
+"""Oracle likelihoods: brute force (Eq. logl_basic), mode-factorised
+(Eq. logl_complete, corrected) and the meshfree online stage (Sec. II D).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain float64 numpy.
+
+Reading of Eq. logl_complete used here (the printed form has a Y_lm where
+Y_{l,-m} belongs in its first term, drops the real part and the -1/2 of
+the second term):
+
+  ln L = sum_k [ r Re sum_a conj(A_ka) z_ka(tau_k)
+                 - r^2/2 Re sum_ab conj(A_ka) A_kb sigma_k,ab ],
+  A_k,lm = [(F+ + i Fx) Y_{l,-m} + (-1)^l (F+ - i Fx) conj(Y_{lm})] / 2,
+  z_ka(tau) = 4 df sum_f conj(h_a) d_k e^{+2 pi i f tau} / S_k,
+  sigma_k,ab = 4 df sum_f conj(h_a) h_b / S_k,  r = d_ref / d_L,
+  tau_k = t_c + dt_k.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.interpolate import CubicSpline
+
+from . import physics as ph
+from .startup import Artefacts, Event, gaussian_kernel, output_layout, poly_matrix
+
+
+# ----------------------------------------------------------------------------
+# Brute force and the exact mode-factorised form
+# ----------------------------------------------------------------------------
+
+def brute_lnl(ev: Event, phys, ext, t_c: float, d_l: float) -> float:
+    """ln L = sum_k <h_k|d_k> - 1/2 <h_k|h_k> with the projected signal of
+    Eq. projected_h_fd (Eq. logl_basic)."""
+    total = 0.0
+    for k in range(ev.n_det):
+        h = ph.detector_signal(ev.grid, ev.modes, phys, d_l, ext, t_c, ev.det_tensor[k], ev.det_pos[k])
+        total += ph.inner(h, ev.data[k], ev.psd[k], ev.grid) - 0.5 * ph.inner(h, h, ev.psd[k], ev.grid)
+    return total
+
+
+def exact_z(ev: Event, phys, k: int, a: int, tau: float) -> complex:
+    """z_ka(tau) by the direct sum over the band (no FFT, no interpolation)."""
+    l, m = ev.modes[a]
+    h = ph.waveform_mode(ev.grid, l, m, phys, ev.d_inj)
+    return ph.overlap(h * ph.shift_factor(ev.grid, tau), ev.data[k], ev.psd[k], ev.grid)
+
+
+def exact_sigma(ev: Event, phys, k: int) -> np.ndarray:
+    hs = [ph.waveform_mode(ev.grid, l, m, phys, ev.d_inj) for (l, m) in ev.modes]
+    n = len(hs)
+    out = np.zeros((n, n), dtype=np.complex128)
+    for a in range(n):
+        for b in range(n):
+            out[a, b] = ph.overlap(hs[a], hs[b], ev.psd[k], ev.grid)
+    return out
+
+
+def combine(A: np.ndarray, z: np.ndarray, sigma: np.ndarray, r) -> np.ndarray:
+    """One detector's term: r Re sum_a conj(A_a) z_a - r^2/2 Re sum_ab conj(A_a) A_b sigma_ab.
+    A, z: [..., n]; sigma: [..., n, n]."""
+    zt = np.real(np.sum(np.conj(A) * z, axis=-1))
+    st = np.real(np.einsum("...a,...b,...ab->...", np.conj(A), A, sigma))
+    return r * zt - 0.5 * r * r * st
+
+
+def factorised_lnl(ev: Event, phys, ext, t_c: float, d_l: float) -> float:
+    """Eq. logl_complete (corrected reading) with z and sigma computed exactly."""
+    alpha, dec, psi, iota, phi = ext
+    r = ev.d_inj / d_l
+    total = 0.0
+    for k in range(ev.n_det):
+        fp, fc = ph.antenna_pattern(ev.det_tensor[k], alpha, dec, psi)
+        tau = t_c + ph.time_delay(ev.det_pos[k], alpha, dec)
+        A = np.array([ph.mode_factor(l, m, fp, fc, iota, phi) for (l, m) in ev.modes])
+        z = np.array([exact_z(ev, phys, k, a, tau) for a in range(len(ev.modes))])
+        total += float(combine(A, z, exact_sigma(ev, phys, k), r))
+    return total
+
+
+# ----------------------------------------------------------------------------
+# Sub-sample time interpolation (Sec. II D: cubic spline through ~10 samples)
+# ----------------------------------------------------------------------------
+
+def spline_table() -> np.ndarray:
+    """w[s][p]: the not-a-knot cubic spline through 10 samples at abscissae
+    0..9, evaluated at 4 + f (f in [0, 1)), equals sum_s w_s(f) y_s with
+    w_s(f) = sum_p w[s][p] f^p.  Obtained by splining each unit vector."""
+    xs = np.arange(10.0)
+    tab = np.zeros((10, 4))
+    for s in range(10):
+        e = np.zeros(10)
+        e[s] = 1.0
+        c = CubicSpline(xs, e, bc_type="not-a-knot").c[:, 4]   # (x-4)^3, ^2, ^1, ^0
+        tab[s] = c[::-1]
+    return tab
+
+
+def spline_weights(f: np.ndarray, tab: np.ndarray) -> np.ndarray:
+    """[n][10] weights at fractional offsets f."""
+    f = np.asarray(f, dtype=np.float64)
+    return tab[None, :, 0] + f[:, None] * (tab[None, :, 1] + f[:, None] * (tab[None, :, 2] + f[:, None] * tab[None, :, 3]))
+
+
+# ----------------------------------------------------------------------------
+# Vectorised extrinsic factors
+# ----------------------------------------------------------------------------
+
+def antenna_patterns(D: np.ndarray, alpha, dec, psi):
+    alpha, dec, psi = (np.asarray(v, dtype=np.float64) for v in (alpha, dec, psi))
+    zero = np.zeros_like(alpha)
+    e_a = np.stack([-np.sin(alpha), np.cos(alpha), zero], axis=-1)
+    e_d = np.stack([-np.sin(dec) * np.cos(alpha), -np.sin(dec) * np.sin(alpha), np.cos(dec)], axis=-1)
+    X = -np.cos(psi)[..., None] * e_a + np.sin(psi)[..., None] * e_d
+    Y = np.sin(psi)[..., None] * e_a + np.cos(psi)[..., None] * e_d
+    fp = np.einsum("ij,ni,nj->n", D, X, X) - np.einsum("ij,ni,nj->n", D, Y, Y)
+    fc = np.einsum("ij,ni,nj->n", D, X, Y) + np.einsum("ij,ni,nj->n", D, Y, X)
+    return fp, fc
+
+
+def time_delays(pos: np.ndarray, alpha, dec):
+    s = np.stack([np.cos(dec) * np.cos(alpha), np.cos(dec) * np.sin(alpha), np.sin(dec)], axis=-1)
+    return -(s @ pos)
+
+
+def ylm_vec(l, m, iota, phi):
+    iota = np.asarray(iota, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    d = np.array([ph.wigner_d(l, m, 2, float(b)) for b in iota.ravel()]).reshape(iota.shape)
+    return math.sqrt((2 * l + 1) / (4.0 * math.pi)) * d * np.exp(1j * m * phi)
+
+
+def mode_factors(modes, fp, fc, iota, phi) -> np.ndarray:
+    """[n_q][n_modes] A_{k,lm} for one detector."""
+    out = []
+    for (l, m) in modes:
+        out.append(0.5 * ((fp + 1j * fc) * ylm_vec(l, -m, iota, phi)
+                          + (-1.0) ** l * (fp - 1j * fc) * np.conj(ylm_vec(l, m, iota, phi))))
+    return np.stack(out, axis=-1)
+
+
+# ----------------------------------------------------------------------------
+# Meshfree online stage
+# ----------------------------------------------------------------------------
+
+def rbf_eval(art: Artefacts, x: np.ndarray) -> np.ndarray:
+    """Y(x) = sum_i W_i phi(|x - x_i|) + sum_j W_{N+j} p_j(x) (Eq. rbfcoeff), [n][K]."""
+    basis = np.concatenate([gaussian_kernel(x, art.x_nodes, art.eps), poly_matrix(x, art.degree)], axis=1)
+    return basis @ art.W
+
+
+def domain(art: Artefacts, x: np.ndarray) -> np.ndarray:
+    """Inside the unit ball (the ellipsoid) and physical (eta <= 1/4, |chi| <= chi_max)."""
+    from .startup import physical_mask
+    inside = np.sum(x * x, axis=1) <= 1.0
+    ok, _ = physical_mask(art.frame, x, art.ev.grid.f_low, art.cfg.chi_max)
+    return inside & ok
+
+
+def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np.ndarray, d_l: np.ndarray,
+                   Y: np.ndarray | None = None):
+    """Online stage for a batch.  delta_e: [n][4] displacement along the
+    eigen-axes; ext: [n][5] (alpha, dec, psi, iota, phi); t_c, d_l: [n].
+    Returns (ln L [n] with -inf outside the domain or the time window,
+    z [n][n_det][n_modes], sigma [n][n_det][n][n], valid mask)."""
+    ev = art.ev
+    x = delta_e / art.frame.semi[None, :]
+    n_q = x.shape[0]
+    valid = domain(art, x)
+    if Y is None:
+        Y = rbf_eval(art, x)
+    n_modes = len(ev.modes)
+    K, coef_off, sig_off = output_layout(ev.n_det, n_modes, art.q)
+    tab = spline_table()
+    T = art.basis.shape[2]
+    r = art.d_ref / d_l
+    alpha, dec, psi, iota, phi = (ext[:, i] for i in range(5))
+    lnl = np.zeros(n_q)
+    zs = np.zeros((n_q, ev.n_det, n_modes), dtype=np.complex128)
+    sigs = np.zeros((n_q, ev.n_det, n_modes, n_modes), dtype=np.complex128)
+    for k in range(ev.n_det):
+        fp, fc = antenna_patterns(ev.det_tensor[k], alpha, dec, psi)
+        s = (t_c + time_delays(ev.det_pos[k], alpha, dec) - ev.t_trig) * ev.grid.fs + art.half_w
+        n0 = np.floor(s)
+        f = s - n0
+        n0 = n0.astype(np.int64)
+        ok = (n0 >= 4) & (n0 <= T - 6)
+        valid &= ok
+        n0c = np.where(ok, n0, 4)
+        w = spline_weights(f, tab)                                   # [n][10]
+        rows = n0c[:, None] + np.arange(-4, 6)[None, :]              # [n][10]
+        for a in range(n_modes):
+            o = coef_off[k][a]
+            C = Y[:, o:o + 2 * art.q:2] + 1j * Y[:, o + 1:o + 2 * art.q:2]
+            btilde = np.einsum("ns,nsi->ni", w, art.basis[k, a][rows])
+            zs[:, k, a] = np.sum(C * btilde, axis=1)
+        o = sig_off[k]
+        for a in range(n_modes):
+            sigs[:, k, a, a] = Y[:, o + a]
+        p = o + n_modes
+        for a in range(n_modes):
+            for b in range(a + 1, n_modes):
+                sigs[:, k, a, b] = Y[:, p] + 1j * Y[:, p + 1]
+                sigs[:, k, b, a] = Y[:, p] - 1j * Y[:, p + 1]
+                p += 2
+        A = mode_factors(ev.modes, fp, fc, iota, phi)
+        lnl += combine(A, zs[:, k], sigs[:, k], r)
+    lnl = np.where(valid, lnl, -np.inf)
+    return lnl, zs, sigs, valid
+
+
+def meshfree_lnl(art: Artefacts, delta_e, ext, t_c, d_l) -> np.ndarray:
+    return meshfree_parts(art, delta_e, ext, t_c, d_l)[0]
+
+
+def query_params(art: Artefacts, qd) -> tuple:
+    """Turn a normalised query draw into the paper's coordinates with this
+    side's own frame and reference distance."""
+    delta_e = qd.x * art.frame.semi[None, :]
+    return delta_e, qd.ext, art.ev.t_trig + qd.dt, art.d_ref * qd.dist_ratio
