@@ -114,7 +114,7 @@ def theta_to_phys(theta, f0: float):
     76 eta chi_s / 113.  eta is returned unclipped so callers can test the
     physical boundary eta <= 1/4; m1, m2, chi are NaN where eta > 1/4.
     """
-    th0, th3, th3s, th3b = (np.asarray(t, dtype=np.float64) for t in theta)
+    th0, th3, th3s, th3b = (np.asarray(t) for t in theta)
     with np.errstate(invalid="ignore", divide="ignore"):
         u = 5.0 * th3 / (32.0 * math.pi * th0)            # pi M f0
         m_s = u / (math.pi * f0)
@@ -146,7 +146,8 @@ def pn_phase_22(f, m1, m2, chi1, chi2):
     chi_s = 0.5 * (chi1 + chi2)
     chi_a = 0.5 * (chi1 - chi2)
     pi = math.pi
-    v = np.cbrt(pi * m_s * np.asarray(f, dtype=np.float64))
+    u = pi * m_s * np.asarray(f)
+    v = u ** (1.0 / 3.0) if np.iscomplexobj(u) else np.cbrt(u.astype(np.float64))
     logv = np.log(v)
     p2 = 3715.0 / 756.0 + 55.0 * eta / 9.0
     p3 = (-16.0 * pi + 113.0 / 3.0 * delta * chi_a

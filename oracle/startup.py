@@ -75,16 +75,18 @@ def make_event(cfg, white: np.ndarray | None, inj_ext: np.ndarray) -> Event:
 # Metric ellipsoid (Eqs. Match, MisMatch) and its eigen-frame
 # ----------------------------------------------------------------------------
 
-def metric(grid: ph.Grid, psd: np.ndarray, center_phys, rel_step: float = 1e-5) -> np.ndarray:
+def metric(grid: ph.Grid, psd: np.ndarray, center_phys, cstep: float = 1e-20) -> np.ndarray:
     """Phase-and-time-maximised (projected) metric of the normalised (2,2)
-    template in Theta = (theta0, theta3, theta3s, theta3s_bar).
+    template in Theta = (theta0, theta3, theta3s, theta3s_bar), Eq. MisMatch.
 
-    With weights w(f) = |h22|^2 / S normalised to one, phase derivatives
-    d_a Psi (a = t_c and the four Theta; d_t Psi = 2 pi f) and covariances
-    C_ab = E_w[d_a Psi d_b Psi] - E_w[d_a Psi] E_w[d_b Psi], the mismatch
-    is g_ij dTheta^i dTheta^j with g = (C_TT - C_Tt C_tT / C_tt) / 2.
-    Theta derivatives are five-point central differences through the
-    closed-form inverse map; steps are rel_step * (theta0, theta3, theta3, theta3).
+    With weights w(f) = |h22|^2 / S normalised to one, the mismatch of a
+    small step is half the weighted variance of the phase change left after
+    the best constant phase and time shift, so g_ij = <d_i Psi, d_j Psi>_w / 2
+    where d_i Psi are the Theta-derivatives of the phase with their weighted
+    projections on 1 and 2 pi f removed (weighted Gram-Schmidt: centre, then
+    remove the component along the centred 2 pi f).  The derivatives are
+    complex-step derivatives through the closed-form inverse map,
+    Im Psi(Theta + i h e_i) / h (Squire & Trapp 1998), exact to rounding.
     """
     m1, m2, c1, c2 = center_phys
     j0, j1 = ph.mode_band(grid, 2, m1, m2)
@@ -92,20 +94,20 @@ def metric(grid: ph.Grid, psd: np.ndarray, center_phys, rel_step: float = 1e-5) 
     w = f ** (-7.0 / 3.0) / psd[j0:j1]
     w /= w.sum()
     th_c = ph.phys_to_theta(center_phys, grid.f_low)
-    steps = rel_step * np.array([th_c[0], th_c[1], th_c[1], th_c[1]])
-    derivs = [2.0 * math.pi * f]
+    t = 2.0 * math.pi * f
+    t = t - w @ t
+    derivs = []
     for i in range(4):
-        vals = []
-        for k in (-2, -1, 1, 2):
-            th = th_c.copy()
-            th[i] += k * steps[i]
-            p1, p2, x1, x2, _ = ph.theta_to_phys(th, grid.f_low)
-            vals.append(ph.pn_phase_22(f, p1, p2, x1, x2))
-        derivs.append((vals[0] - 8.0 * vals[1] + 8.0 * vals[2] - vals[3]) / (12.0 * steps[i]))
-    d = np.stack(derivs)                       # [5][n_f]: t, theta0..3
-    mean = d @ w
-    cov = (d * w) @ d.T - np.outer(mean, mean)
-    g = 0.5 * (cov[1:, 1:] - np.outer(cov[1:, 0], cov[0, 1:]) / cov[0, 0])
+        th = th_c.astype(np.complex128)
+        h = cstep * abs(th_c[1])
+        th[i] += 1j * h
+        p1, p2, x1, x2, _ = ph.theta_to_phys(th, grid.f_low)
+        d = np.imag(ph.pn_phase_22(f.astype(np.complex128), p1, p2, x1, x2)) / h
+        d = d - w @ d
+        d = d - (w @ (d * t)) / (w @ (t * t)) * t
+        derivs.append(d)
+    d = np.stack(derivs)
+    g = 0.5 * (d * w) @ d.T
     return 0.5 * (g + g.T)
 
 
