@@ -1,0 +1,188 @@
+/*
+ * rbfl -- meshfree RBF likelihood for gravitational-wave parameter estimation
+ * (Sharma, Pathak, Roy & Sengupta, arXiv:2508.04172), MI355X (gfx950) build.
+ *
+ * C ABI.  Every call returns an int32 status (RBFL_OK = 0); no C++ exception
+ * crosses this boundary.  On error the outputs are unspecified and
+ * rbfl_last_error() describes the failure.  Per-query domain conditions are
+ * not errors: a proposal outside the interpolation ellipsoid, outside the
+ * physical region or outside the stored time window gets ln L = -inf.
+ *
+ * Ownership: the caller owns every buffer it passes in or out; the library
+ * owns the handle and every device artefact behind it (nodes, RBF weights,
+ * SVD basis, frame), released by rbfl_destroy.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  rbfl_build synchronises its stream before returning; rbfl_eval
+ * only enqueues work and returns.  Asynchronous device faults surface as
+ * RBFL_E_DEVICE from a later call or from the caller's own synchronisation.
+ *
+ * Threading: rbfl_eval may run concurrently on different streams with one
+ * handle (the handle is read-only while evaluating) unless noted otherwise;
+ * rbfl_build, rbfl_prepare and rbfl_destroy need exclusive use of a handle.
+ */
+#ifndef RBFL_H
+#define RBFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBFL_ABI_VERSION 1
+#define RBFL_MAX_MODES 5
+#define RBFL_MAX_DET 4
+
+enum rbfl_status {
+  RBFL_OK = 0,
+  RBFL_E_INVALID_ARG = 1,   /* malformed spec, NULL pointer, size out of range */
+  RBFL_E_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
+  RBFL_E_DEVICE = 3,        /* a HIP or rocSOLVER call failed */
+  RBFL_E_NUMERICAL = 4,     /* singular RBF system, SVD not converged, metric not positive definite */
+  RBFL_E_UNSUPPORTED = 5,   /* a form or option this build does not provide */
+  RBFL_E_STATE = 6          /* call out of order (e.g. a form not prepared) */
+};
+
+/* Arithmetic form of the online stage. */
+enum rbfl_form {
+  RBFL_FORM_FP64 = 0,       /* plain: FP64 kernel rows, FP64 MFMA contraction, FP64 epilogue */
+  RBFL_FORM_FP32 = 1,       /* FP32 kernel rows and FP32 MFMA contraction, FP64 epilogue */
+  RBFL_FORM_BF16 = 2,       /* BF16 operands, FP32-accumulating MFMA, FP64 epilogue */
+  RBFL_FORM_SPLIT = 3       /* FP32 hi/lo split of both operands, three FP32 MFMA products */
+};
+
+/* Spec flags. */
+#define RBFL_FLAG_CENTER_NODE 0x1u  /* place the ellipsoid centre as node 0 before the Halton nodes */
+
+typedef struct rbfl_ctx *rbfl_handle;
+
+/*
+ * Start-up specification (Sec. II C of the paper).  All pointers are host
+ * pointers, read only during rbfl_build.
+ *
+ * Frequency grid: f_j = j / seg_len, j = 0 .. n_f - 1, n_f = fs*seg_len/2 + 1.
+ * The noise-weighted inner product (Eq. innerProduct) runs over
+ * f_low <= f_j < fs/2 (DC and Nyquist excluded).
+ *
+ * Data: if data_fd is NULL the library synthesises d_k = coloured noise +
+ * injection: bin j of detector k gets sqrt(S_k(f_j) / (4 df)) (x + i y) with
+ * (x, y) = noise_white[k][j][0..1] (NULL: zero noise), plus the projected
+ * injection (Eq. projected_h_fd) at inj_phys, inj_ext, t_c = t_trig, with the
+ * distance set so that the network optimal SNR equals inj_snr; that distance
+ * is also the template reference distance d_ref.  If data_fd is given,
+ * d_ref must be set and the injection fields are ignored.
+ *
+ * Templates: the library's synthetic multimode inspiral family, h_{l,-m}(f) =
+ * A_lm Amp(Mc, d_ref) f^(-7/6) exp(-i (m/2) Psi(2f/m)) for f_low <= f <
+ * |m| F_isco, with a 3.5PN aligned-spin TaylorF2-like phase Psi.
+ *
+ * Ellipsoid: metric g of the (2,2) mode at center_phys in the chirp-time
+ * coordinates Theta (Eq. metric_coords), computed unless `metric` is given;
+ * the constant-match ellipsoid 1 - match = g dTheta dTheta (Eq. MisMatch).
+ * Nodes: unscrambled Halton points (bases 2, 3, 5, 7, index from 1) mapped
+ * to the unit ball in the eigen-frame, kept if physical (eta <= 1/4,
+ * |chi_i| <= chi_max).  Interpolants: Gaussian RBF exp(-eps^2 r^2) in
+ * unit-ball coordinates plus all monomials of degree <= poly_degree
+ * (Eq. rbfcoeff), fitted to the first q SVD coefficients of each detector's
+ * and mode's time series over t_trig +- half_window (Eq. SVD) and to the
+ * mode overlaps (Eq. conjugation_symmetry).
+ */
+typedef struct {
+  int32_t abi_version;                 /* RBFL_ABI_VERSION */
+  int32_t n_det;                       /* 1 .. RBFL_MAX_DET */
+  int32_t n_modes;                     /* 1 .. RBFL_MAX_MODES */
+  int32_t modes[RBFL_MAX_MODES][2];    /* (l, |m|) from {(2,2),(2,1),(3,3),(3,2),(4,4)} */
+  double fs;                           /* sample rate [Hz]; fs*seg_len an even integer */
+  double seg_len;                      /* segment length [s] */
+  double f_low;                        /* lower cut-off [Hz] */
+  double psd_scale;                    /* scale of the analytic PSD (used when psd == NULL) */
+  const double *psd;                   /* [n_det][n_f] one-sided PSD, or NULL for the analytic model */
+  const double *data_fd;               /* [n_det][n_f][2] data (re, im), or NULL to synthesise */
+  const double *noise_white;           /* [n_det][n_f][2] standard normal deviates, or NULL (zero noise) */
+  double inj_phys[4];                  /* m1, m2 [Msun], chi1z, chi2z */
+  double inj_ext[5];                   /* alpha, dec, psi, iota, phi [rad] */
+  double inj_snr;                      /* network optimal SNR of the injection (> 0) */
+  double d_ref;                        /* template reference distance [Mpc] when data_fd is given */
+  const double *det_geom;              /* [n_det][5]: latitude, longitude, x-arm azimuth (from north
+                                          toward east), arm opening angle [rad], distance from the
+                                          geocentre [light-seconds] */
+  double center_phys[4];               /* ellipsoid centre: m1, m2, chi1z, chi2z */
+  double match;                        /* M0 in (0, 1) */
+  const double *metric;                /* optional [4][4] metric in Theta, or NULL to compute it */
+  double t_trig;                       /* trigger time in the segment [s], on the sample grid */
+  double half_window;                  /* window half-width [s]; W = floor(half_window * fs) */
+  int32_t n_nodes;                     /* N >= 1 + number of monomials */
+  int32_t q;                           /* basis size, 1 .. min(N, 2W+1) */
+  double eps;                          /* Gaussian shape parameter (> 0) */
+  int32_t poly_degree;                 /* 0 .. 3 */
+  double chi_max;                      /* spin bound of the physical region (0 < chi_max <= 1) */
+  uint32_t flags;                      /* RBFL_FLAG_* */
+} rbfl_build_spec;
+
+/* Thread-local description of the last failure on this thread; valid until
+ * the next rbfl_* call on the same thread. */
+const char *rbfl_last_error(void);
+
+/* Start-up stage (Sec. II C): data, metric frame, Halton nodes, overlap time
+ * series at the nodes (windowed DFT on the GPU), mode overlaps, FP64 SVD per
+ * detector and mode and FP64 LU solve of the RBF system, all on the GPU.
+ * Synchronous on `stream`.  *out receives a new handle. */
+int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out);
+
+/* Online stage (Sec. II D) for n proposals.
+ * params: device, FP64, structure of arrays [11][n] (row stride n):
+ *   delta_e0..3 (displacement from the centre along the metric eigenvectors,
+ *   ordered by ascending semi-axis, in Theta units), alpha, dec, psi, iota,
+ *   phi [rad], t_c (geocentric coalescence time in the segment [s]), d_L [Mpc].
+ * lnl: device, FP64 [n]; ln L per proposal (Eq. logl_complete, corrected
+ *   reading), -inf outside the ellipsoid, the physical region or the window.
+ * form: RBFL_FORM_*; forms other than FP64 need rbfl_prepare first.
+ * Enqueued on `stream`; no allocation when n <= the handle's work capacity
+ * (rbfl_reserve), so a call can be captured in a HIP graph after a reserve. */
+int32_t rbfl_eval(rbfl_handle h, const double *params, int64_t n, double *lnl, int32_t form,
+                  void *stream);
+
+/* Interpolated quantities at n proposals (Eq. rbfcoeff): out[b][c], c < K,
+ * device FP64, row stride K.  Per detector k the K reals are, in order, for
+ * each mode the interleaved (Re, Im) of the q SVD coefficients (Eq. SVD),
+ * then the n_modes^2 overlap reals: the diagonal sigma_aa, then (Re, Im)
+ * sigma_ab for a < b in lexicographic order (Eq. conjugation_symmetry).
+ * Only rows 0..3 of params (delta_e) are read; no domain check is applied.
+ * Enqueued on `stream`. */
+int32_t rbfl_interp(rbfl_handle h, const double *params, int64_t n, double *out, int32_t form, void *stream);
+
+/* Converts the weights for a reduced-precision form (RBFL_FORM_FP32/BF16/SPLIT).
+ * Synchronous; needs exclusive use of the handle. */
+int32_t rbfl_prepare(rbfl_handle h, int32_t form);
+
+/* Pre-allocates work space for batches of up to n proposals (optional). */
+int32_t rbfl_reserve(rbfl_handle h, int64_t n);
+
+/* Artefact export (host copies), for checks and diagnostics. */
+enum rbfl_query_what {
+  RBFL_Q_SIZES = 0,        /* int64[8]: N, M, K, q, T, n_det, n_modes, half_window_samples */
+  RBFL_Q_FRAME = 1,        /* double[4 + 16 + 4 + 4 + 16]: theta_c, eigenvectors (row-major,
+                              column i = axis i), eigenvalues, semi-axes, metric (row-major) */
+  RBFL_Q_D_REF = 2,        /* double[1]: template reference distance [Mpc] */
+  RBFL_Q_NODES = 3,        /* double[N][4] unit-ball node coordinates */
+  RBFL_Q_NODE_PHYS = 4,    /* double[N][4] m1, m2, chi1, chi2 of the nodes */
+  RBFL_Q_WEIGHTS = 5,      /* double[N+M][K] RBF weights */
+  RBFL_Q_BASIS = 6,        /* double[n_det][n_modes][T][q][2] SVD basis */
+  RBFL_Q_NODE_VALUES = 7,  /* double[N][K] interpolated quantities at the nodes */
+  RBFL_Q_SINGULAR = 8,     /* double[n_det][n_modes][min(N,T)] singular values */
+  RBFL_Q_COND = 9,         /* double[1]: 1-norm condition estimate of the RBF system */
+  RBFL_Q_TIMING = 10,      /* double[8]: start-up stage wall times [s] */
+  RBFL_Q_Z_NODES = 11      /* double[n_det][n_modes][N][T][2] time series at the nodes */
+};
+int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
+
+/* Releases the handle and its device memory (NULL is allowed). */
+int32_t rbfl_destroy(rbfl_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFL_H */

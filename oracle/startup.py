@@ -243,48 +243,39 @@ def window_indices(grid: ph.Grid, t_trig: float, half_window: float) -> np.ndarr
     return (n_trig + np.arange(-w, w + 1)) % grid.n_s
 
 
-def node_time_series(ev: Event, node_phys: np.ndarray, half_window: float,
-                     workers: int = -1, batch: int = 32) -> np.ndarray:
-    """z[k][a][node][t] = (h_a e^{-2 pi i f tau_t} | d_k) at the window times
-    tau_t: the inverse FFT of X_j = conj(h_a(f_j)) d_k(f_j) / S_k(f_j) on the
-    band, scaled by 4 fs, read at the window's sample indices."""
+def node_series_and_overlaps(ev: Event, node_phys: np.ndarray, half_window: float,
+                             workers: int = -1, batch: int = 16):
+    """Per node batch, the templates of every mode are formed once and give
+    z[k][a][node][t] = (h_a e^{-2 pi i f tau_t} | d_k) at the window times
+    tau_t -- the inverse FFT of X_j = conj(h_a(f_j)) d_k(f_j) / S_k(f_j) on
+    the band, scaled by 4 fs, read at the window's sample indices -- and
+    sigma[k][node][a][b] = (h_a | h_b)_k, Hermitian in (a, b)
+    (Eq. conjugation_symmetry)."""
     grid = ev.grid
     idx = window_indices(grid, ev.t_trig, half_window)
     n_nodes = node_phys.shape[0]
     n_modes = len(ev.modes)
-    out = np.zeros((ev.n_det, n_modes, n_nodes, idx.size), dtype=np.complex128)
+    z = np.zeros((ev.n_det, n_modes, n_nodes, idx.size), dtype=np.complex128)
+    sig = np.zeros((ev.n_det, n_nodes, n_modes, n_modes), dtype=np.complex128)
     sl = grid.band()
     weights = [np.zeros(grid.n_f, dtype=np.complex128) for _ in range(ev.n_det)]
     for k in range(ev.n_det):
         weights[k][sl] = ev.data[k, sl] / ev.psd[k, sl]
-    for a, (l, m) in enumerate(ev.modes):
-        for start in range(0, n_nodes, batch):
-            stop = min(n_nodes, start + batch)
-            hs = np.stack([ph.waveform_mode(grid, l, m, tuple(node_phys[i]), ev.d_inj)
-                           for i in range(start, stop)])
-            for k in range(ev.n_det):
-                X = np.zeros((stop - start, grid.n_s), dtype=np.complex128)
-                X[:, :grid.n_f] = np.conj(hs) * weights[k][None, :]
-                X[:, grid.j_hi:] = 0.0
-                series = scipy.fft.ifft(X, axis=1, workers=workers)
-                out[k, a, start:stop] = 4.0 * grid.fs * series[:, idx]
-    return out
-
-
-def node_overlaps(ev: Event, node_phys: np.ndarray) -> np.ndarray:
-    """sigma[k][node][a][b] = (h_a | h_b)_k, Hermitian in (a, b) (Eq. conjugation_symmetry)."""
-    grid = ev.grid
-    sl = grid.band()
-    n_nodes = node_phys.shape[0]
-    n_modes = len(ev.modes)
-    out = np.zeros((ev.n_det, n_nodes, n_modes, n_modes), dtype=np.complex128)
-    for i in range(n_nodes):
-        hs = np.stack([ph.waveform_mode(grid, l, m, tuple(node_phys[i]), ev.d_inj)[sl]
-                       for (l, m) in ev.modes])
+    for start in range(0, n_nodes, batch):
+        stop = min(n_nodes, start + batch)
+        hs = np.stack([np.stack([ph.waveform_mode(grid, l, m, tuple(node_phys[i]), ev.d_inj)
+                                 for i in range(start, stop)]) for (l, m) in ev.modes])   # [a][node][f]
         for k in range(ev.n_det):
             wk = 4.0 * grid.df / ev.psd[k, sl]
-            out[k, i] = (np.conj(hs) * wk[None, :]) @ hs.T
-    return out
+            hb = hs[:, :, sl]
+            sig[k, start:stop] = np.einsum("anf,bnf->nab", np.conj(hb) * wk, hb)
+            for a in range(n_modes):
+                X = np.zeros((stop - start, grid.n_s), dtype=np.complex128)
+                X[:, :grid.n_f] = np.conj(hs[a]) * weights[k][None, :]
+                X[:, grid.j_hi:] = 0.0
+                series = scipy.fft.ifft(X, axis=1, workers=workers)
+                z[k, a, start:stop] = 4.0 * grid.fs * series[:, idx]
+    return z, sig
 
 
 # ----------------------------------------------------------------------------
@@ -397,8 +388,7 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     g = metric(grid, ev.psd[0], cfg.inj_phys)
     fr = frame(g, theta_c, cfg.match)
     x, phys = place_nodes(fr, cfg.n_nodes, grid.f_low, cfg.chi_max, cfg.center_node)
-    z = node_time_series(ev, phys, cfg.half_window, workers=workers)
-    sig = node_overlaps(ev, phys)
+    z, sig = node_series_and_overlaps(ev, phys, cfg.half_window, workers=workers)
     n_modes = len(ev.modes)
     K, coef_off, sig_off = output_layout(ev.n_det, n_modes, cfg.q)
     F = np.zeros((cfg.n_nodes, K))

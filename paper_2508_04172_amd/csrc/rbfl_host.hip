@@ -1,0 +1,1105 @@
+// Host side of the rbfl C ABI: spec validation, the start-up stage
+// orchestration (frame, nodes and data on the host in FP64; templates,
+// overlaps, time series, SVD and RBF solve on the GPU), the online-stage
+// dispatch and artefact export.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rbfl_internal.h"
+
+namespace rbfl {
+
+static thread_local std::string g_last_error;
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    const char *msg = hipGetErrorString(e);
+    (void)hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? RBFL_E_OUT_OF_MEMORY : RBFL_E_DEVICE,
+                std::string(what) + ": " + (msg ? msg : "unknown HIP error"));
+  }
+}
+
+static void blas_check(rocblas_status s, const char *what) {
+  if (s != rocblas_status_success)
+    throw Error(s == rocblas_status_memory_error ? RBFL_E_OUT_OF_MEMORY : RBFL_E_DEVICE,
+                std::string(what) + " failed with rocblas status " + std::to_string((int)s));
+}
+
+static void require(bool ok, const std::string &msg) {
+  if (!ok) throw Error(RBFL_E_INVALID_ARG, msg);
+}
+
+using Clock = std::chrono::steady_clock;
+static double seconds_since(Clock::time_point t) {
+  return std::chrono::duration<double>(Clock::now() - t).count();
+}
+
+// ---------------------------------------------------------------------------
+// Host FP64 pieces of the start-up stage
+// ---------------------------------------------------------------------------
+
+// aLIGO-like analytic PSD, x = f / 215 Hz.
+static double psd_analytic(double f, double scale) {
+  const double x = f / 215.0;
+  return scale * 1e-49 *
+         (pow(x, -4.14) - 5.0 / (x * x) + 111.0 * (1.0 - x * x + 0.5 * x * x * x * x) / (1.0 + 0.5 * x * x));
+}
+
+// Detector tensor and position from (lat, lon, x-arm azimuth, opening, radius).
+static void detector_geometry(const double g[5], double D[9], double r[3]) {
+  const double lat = g[0], lon = g[1], az = g[2], op = g[3], rad = g[4];
+  const double east[3] = {-sin(lon), cos(lon), 0.0};
+  const double north[3] = {-sin(lat) * cos(lon), -sin(lat) * sin(lon), cos(lat)};
+  const double up[3] = {cos(lat) * cos(lon), cos(lat) * sin(lon), sin(lat)};
+  double u[3], v[3];
+  for (int i = 0; i < 3; ++i) {
+    u[i] = cos(az) * north[i] + sin(az) * east[i];
+    v[i] = cos(az + op) * north[i] + sin(az + op) * east[i];
+    r[i] = rad * up[i];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D[3 * i + j] = 0.5 * (u[i] * u[j] - v[i] * v[j]);
+}
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// -2Y_{l m}(iota, phi) = sqrt((2l+1)/4pi) d^l_{m,2}(iota) e^{i m phi}, with the
+// Wigner small-d element written as its finite sum over k.
+static YlmTerms ylm_terms(int l, int m) {
+  YlmTerms t{};
+  t.m = m;
+  t.n = 0;
+  const int m1 = m, m2 = 2;
+  const double norm = sqrt((2.0 * l + 1.0) / (4.0 * kPi));
+  const double pre = sqrt(factorial(l + m1) * factorial(l - m1) * factorial(l + m2) * factorial(l - m2));
+  for (int k = 0; k <= 2 * l; ++k) {
+    const int a1 = l + m2 - k, a2 = k, a3 = m1 - m2 + k, a4 = l - m1 - k;
+    if (a1 < 0 || a2 < 0 || a3 < 0 || a4 < 0) continue;
+    const double sign = ((k + m1 - m2) & 1) ? -1.0 : 1.0;
+    t.coef[t.n] = norm * sign * pre / (factorial(a1) * factorial(a2) * factorial(a3) * factorial(a4));
+    t.cpow[t.n] = 2 * l + m2 - m1 - 2 * k;
+    t.spow[t.n] = m1 - m2 + 2 * k;
+    ++t.n;
+  }
+  return t;
+}
+
+static void ylm_value(const YlmTerms &t, double iota, double phi, double *re, double *im) {
+  eval_ylm(t, cos(0.5 * iota), sin(0.5 * iota), phi, re, im);
+}
+
+// Not-a-knot cubic spline through 10 unit-spaced samples, evaluated in the
+// central interval [4, 5]: its value is linear in the samples, sum_s w_s(f) y_s,
+// with each w_s a cubic in f.  Second derivatives m_i solve
+// m_{i-1} + 4 m_i + m_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}) (i = 1..8) with the
+// not-a-knot conditions m_0 - 2 m_1 + m_2 = 0 and m_7 - 2 m_8 + m_9 = 0; on
+// [4, 5], S(f) = y4 + (y5 - y4 - m4/3 - m5/6) f + m4/2 f^2 + (m5 - m4)/6 f^3.
+static void spline_table(double tab[kSplineTaps][4]) {
+  constexpr int n = kSplineTaps;
+  for (int s = 0; s < n; ++s) {
+    double A[n][n + 1] = {};
+    double y[n] = {};
+    y[s] = 1.0;
+    A[0][0] = 1.0;
+    A[0][1] = -2.0;
+    A[0][2] = 1.0;
+    A[n - 1][n - 3] = 1.0;
+    A[n - 1][n - 2] = -2.0;
+    A[n - 1][n - 1] = 1.0;
+    for (int i = 1; i < n - 1; ++i) {
+      A[i][i - 1] = 1.0;
+      A[i][i] = 4.0;
+      A[i][i + 1] = 1.0;
+      A[i][n] = 6.0 * (y[i + 1] - 2.0 * y[i] + y[i - 1]);
+    }
+    // Gaussian elimination with partial pivoting
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+      if (piv != c)
+        for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+      for (int r = c + 1; r < n; ++r) {
+        const double f = A[r][c] / A[c][c];
+        for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
+      }
+    }
+    double m[n];
+    for (int r = n - 1; r >= 0; --r) {
+      double v = A[r][n];
+      for (int k = r + 1; k < n; ++k) v -= A[r][k] * m[k];
+      m[r] = v / A[r][r];
+    }
+    tab[s][0] = y[4];
+    tab[s][1] = y[5] - y[4] - m[4] / 3.0 - m[5] / 6.0;
+    tab[s][2] = 0.5 * m[4];
+    tab[s][3] = (m[5] - m[4]) / 6.0;
+  }
+}
+
+// Van der Corput radical inverse as an exact integer ratio, rounded once.
+static double radical_inverse(uint64_t i, uint64_t base) {
+  uint64_t num = 0, den = 1;
+  while (i > 0) {
+    num = num * base + i % base;
+    den *= base;
+    i /= base;
+  }
+  return (double)num / (double)den;
+}
+
+// ---- metric: generic-real versions of the phase and the inverse map, so the
+// derivatives can be taken by the complex step.
+template <class R>
+static R phase22_generic(R f, R m1, R m2, R c1, R c2) {
+  using std::log;
+  using std::pow;
+  const double pi = kPi;
+  const R mt = m1 + m2;
+  const R eta = m1 * m2 / (mt * mt);
+  const R dl = (m1 - m2) / mt;
+  const R cs = 0.5 * (c1 + c2), ca = 0.5 * (c1 - c2);
+  const R v = pow(pi * mt * kMsunS * f, 1.0 / 3.0);
+  const R lv = log(v);
+  const R e2 = eta * eta, e3 = e2 * eta;
+  const R p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  const R p3 = -16.0 * pi + 113.0 / 3.0 * dl * ca + (113.0 / 3.0 - 76.0 / 3.0 * eta) * cs;
+  const R p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * e2 +
+               (-405.0 / 8.0 + 200.0 * eta) * ca * ca - 405.0 / 4.0 * dl * ca * cs +
+               (-405.0 / 8.0 + 2.5 * eta) * cs * cs;
+  const R p5 = pi * (38645.0 / 756.0 - 65.0 / 9.0 * eta) + dl * ca * (-732985.0 / 2268.0 - 140.0 / 9.0 * eta) +
+               cs * (-732985.0 / 2268.0 + 24260.0 / 81.0 * eta + 340.0 / 9.0 * e2);
+  const R p6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * pi * pi - 6848.0 / 21.0 * kEulerGamma +
+               eta * (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * pi * pi) + 76055.0 / 1728.0 * e2 -
+               127825.0 / 1296.0 * e3 + pi * (2270.0 / 3.0 * dl * ca + (2270.0 / 3.0 - 520.0 * eta) * cs) +
+               (75515.0 / 144.0 - 8225.0 / 18.0 * eta) * dl * ca * cs +
+               (75515.0 / 288.0 - 263245.0 / 252.0 * eta - 480.0 * e2) * ca * ca +
+               (75515.0 / 288.0 - 232415.0 / 504.0 * eta + 1255.0 / 9.0 * e2) * cs * cs;
+  const double p6l = -6848.0 / 21.0;
+  const R p7 = pi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2) +
+               dl * ca * (-25150083775.0 / 3048192.0 + 26804935.0 / 6048.0 * eta - 1985.0 / 48.0 * e2) +
+               cs * (-25150083775.0 / 3048192.0 + 10566655595.0 / 762048.0 * eta - 1042165.0 / 3024.0 * e2 +
+                     5345.0 / 36.0 * e3);
+  const R v2 = v * v;
+  R s = p7;
+  s = s * v + (p6 + p6l * (std::log(4.0) + lv));
+  s = s * v + p5 * (1.0 + 3.0 * lv);
+  s = s * v + p4;
+  s = s * v + p3;
+  s = s * v + p2;
+  s = s * v2 + 1.0;
+  return -0.25 * pi + 3.0 / (128.0 * eta * v2 * v2 * v) * s;
+}
+
+template <class R>
+static void theta_to_phys_generic(const R th[4], double f0, R p[4]) {
+  using std::pow;
+  using std::sqrt;
+  const R u = 5.0 * th[1] / (32.0 * kPi * th[0]);
+  const R eta = kPi / (4.0 * th[1]) * pow(u, -2.0 / 3.0);
+  const R mt = u / (kPi * f0) / kMsunS;
+  const R dl = sqrt(1.0 - 4.0 * eta);
+  const R chi_r = 48.0 * kPi * th[2] / (113.0 * th[1]);
+  const R chi_eff = 48.0 * kPi * th[3] / (113.0 * th[1]);
+  const R cs = 113.0 * (chi_eff - chi_r) / (76.0 * eta);
+  const R ca = (chi_eff - cs) / dl;
+  p[0] = 0.5 * mt * (1.0 + dl);
+  p[1] = 0.5 * mt * (1.0 - dl);
+  p[2] = cs + ca;
+  p[3] = cs - ca;
+}
+
+// Neumaier-compensated sum.
+struct Sum {
+  double s = 0.0, c = 0.0;
+  void add(double v) {
+    const double t = s + v;
+    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+// Projected metric of the normalised (2,2) template (Eq. MisMatch): half the
+// weighted inner products of the Theta-derivatives of the phase after their
+// components along 1 and 2 pi f are removed (weighted Gram-Schmidt), weights
+// |h22|^2/S.  Derivatives by the complex step Im Psi(Theta + i h e_i)/h.
+static void compute_metric(const Ctx &c, const std::vector<double> &psd0, const double center[4], double g[16]) {
+  const Binary b = make_binary(center[0], center[1], center[2], center[3]);
+  const int64_t j0 = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  int64_t j1 = (int64_t)ceil(2.0 * b.f_isco * c.seg_len);
+  j1 = std::min<int64_t>(std::max<int64_t>(j1, j0), c.n_s / 2);
+  const int64_t n = j1 - j0;
+  if (n < 8) throw Error(RBFL_E_INVALID_ARG, "the (2,2) band at the centre has fewer than 8 bins");
+  std::vector<double> w(n), t(n);
+  Sum ws;
+  for (int64_t k = 0; k < n; ++k) {
+    const double f = (double)(j0 + k) * c.df;
+    w[k] = pow(f, -7.0 / 3.0) / psd0[j0 + k];
+    ws.add(w[k]);
+  }
+  const double wsum = ws.value();
+  for (auto &v : w) v /= wsum;
+  Sum tm;
+  for (int64_t k = 0; k < n; ++k) tm.add(w[k] * 2.0 * kPi * (double)(j0 + k) * c.df);
+  const double tmean = tm.value();
+  Sum tt;
+  for (int64_t k = 0; k < n; ++k) {
+    t[k] = 2.0 * kPi * (double)(j0 + k) * c.df - tmean;
+    tt.add(w[k] * t[k] * t[k]);
+  }
+  double th_c[4];
+  phys_to_theta(center, c.f_low, th_c);
+  std::vector<std::vector<double>> d(4, std::vector<double>(n));
+  typedef std::complex<double> cd;
+  const double h = 1e-20 * fabs(th_c[1]);
+  for (int i = 0; i < 4; ++i) {
+    cd th[4] = {th_c[0], th_c[1], th_c[2], th_c[3]};
+    th[i] += cd(0.0, h);
+    cd p[4];
+    theta_to_phys_generic<cd>(th, c.f_low, p);
+    Sum mean;
+    for (int64_t k = 0; k < n; ++k) {
+      const cd ph = phase22_generic<cd>(cd((double)(j0 + k) * c.df, 0.0), p[0], p[1], p[2], p[3]);
+      d[i][k] = ph.imag() / h;
+      mean.add(w[k] * d[i][k]);
+    }
+    const double mu = mean.value();
+    Sum dt;
+    for (int64_t k = 0; k < n; ++k) {
+      d[i][k] -= mu;
+      dt.add(w[k] * d[i][k] * t[k]);
+    }
+    const double beta = dt.value() / tt.value();
+    for (int64_t k = 0; k < n; ++k) d[i][k] -= beta * t[k];
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = i; j < 4; ++j) {
+      Sum s;
+      for (int64_t k = 0; k < n; ++k) s.add(w[k] * d[i][k] * d[j][k]);
+      g[4 * i + j] = g[4 * j + i] = 0.5 * s.value();
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 4x4 matrix.
+static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
+  double a[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      a[i][j] = a_in[4 * i + j];
+      V[4 * i + j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) (i == j ? diag : off) += a[i][j] * a[i][j];
+    if (off <= 1e-34 * diag) break;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < 4; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = cs * akp - sn * akq;
+          a[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = cs * apk - sn * aqk;
+          a[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double vkp = V[4 * k + p], vkq = V[4 * k + q];
+          V[4 * k + p] = cs * vkp - sn * vkq;
+          V[4 * k + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 4; ++i) lam[i] = a[i][i];
+}
+
+// Synthetic data: coloured noise + the projected injection (Eq. projected_h_fd).
+static void synthesise_data(const rbfl_build_spec &s, const Ctx &c, const std::vector<std::vector<double>> &psd,
+                            const YlmTerms *yneg, const YlmTerms *ypos, std::vector<std::vector<double2>> &data,
+                            double *d_inj) {
+  const Binary b = make_binary(s.inj_phys[0], s.inj_phys[1], s.inj_phys[2], s.inj_phys[3]);
+  const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  const int64_t j_hi = c.n_s / 2;
+  const double alpha = s.inj_ext[0], dec = s.inj_ext[1], psi = s.inj_ext[2], iota = s.inj_ext[3],
+               phi = s.inj_ext[4];
+  std::vector<std::vector<double2>> sig(c.n_det, std::vector<double2>(c.n_f, make_double2(0.0, 0.0)));
+  Sum rho2;
+  const double amp1 = b.amp / kMpcS;   // at 1 Mpc
+  for (int k = 0; k < c.n_det; ++k) {
+    double fp, fc, dt;
+    detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
+    double Ar[RBFL_MAX_MODES], Ai[RBFL_MAX_MODES];
+    for (int a = 0; a < c.n_modes; ++a) {
+      double nr, ni, pr, pi;
+      ylm_value(yneg[a], iota, phi, &nr, &ni);
+      ylm_value(ypos[a], iota, phi, &pr, &pi);
+      const double sg = (c.modes[a][0] & 1) ? -1.0 : 1.0;
+      Ar[a] = 0.5 * ((fp * nr - fc * ni) + sg * (fp * pr - fc * pi));
+      Ai[a] = 0.5 * ((fp * ni + fc * nr) + sg * (-fp * pi - fc * pr));
+    }
+    const double tau = s.t_trig + dt;
+    const int64_t nsh = (int64_t)llround(tau * c.fs);
+    const double rem = tau - (double)nsh / c.fs;
+    Sum e;
+    for (int64_t j = j_lo; j < j_hi; ++j) {
+      const double f = (double)j * c.df;
+      double hr = 0.0, hi = 0.0;
+      for (int a = 0; a < c.n_modes; ++a) {
+        const int l = c.modes[a][0], m = c.modes[a][1];
+        if (!(f < (double)m * b.f_isco)) continue;
+        const double ph = 0.5 * (double)m * phase22(2.0 * f / (double)m, b);
+        const double am = mode_amp(l, m, b.eta, b.delta) * amp1 * exp(-7.0 / 6.0 * log(f));
+        const double xr = am * cos(ph), xi = -am * sin(ph);   // h = am e^{-i ph}
+        hr += Ar[a] * xr - Ai[a] * xi;
+        hi += Ar[a] * xi + Ai[a] * xr;
+      }
+      // time shift e^{-2 pi i f tau}: whole samples reduced exactly, then the remainder
+      int64_t jm = (j % c.n_s) * (nsh % c.n_s) % c.n_s;
+      if (jm < 0) jm += c.n_s;
+      const double frac = (double)jm / (double)c.n_s + f * rem;
+      double sn, cs;
+      sincos(-2.0 * kPi * frac, &sn, &cs);
+      const double2 v = make_double2(hr * cs - hi * sn, hr * sn + hi * cs);
+      sig[k][j] = v;
+      e.add((v.x * v.x + v.y * v.y) / psd[k][j]);
+    }
+    rho2.add(4.0 * c.df * e.value());
+  }
+  *d_inj = sqrt(rho2.value()) / s.inj_snr;
+  data.assign(c.n_det, std::vector<double2>(c.n_f, make_double2(0.0, 0.0)));
+  for (int k = 0; k < c.n_det; ++k) {
+    for (int64_t j = 0; j < c.n_f; ++j) {
+      double2 v = make_double2(sig[k][j].x / *d_inj, sig[k][j].y / *d_inj);
+      if (s.noise_white && j >= 1) {
+        const double am = sqrt(psd[k][j] / (4.0 * c.df));
+        v.x += am * s.noise_white[((int64_t)k * c.n_f + j) * 2];
+        v.y += am * s.noise_white[((int64_t)k * c.n_f + j) * 2 + 1];
+      }
+      data[k][j] = v;
+    }
+  }
+}
+
+static void validate(const rbfl_build_spec *s) {
+  require(s != nullptr, "spec is NULL");
+  require(s->abi_version == RBFL_ABI_VERSION, "abi_version mismatch");
+  require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
+  require(s->n_modes >= 1 && s->n_modes <= RBFL_MAX_MODES, "n_modes out of range");
+  for (int a = 0; a < s->n_modes; ++a) {
+    const int l = s->modes[a][0], m = s->modes[a][1];
+    require((l == 2 && (m == 2 || m == 1)) || (l == 3 && (m == 3 || m == 2)) || (l == 4 && m == 4),
+            "unsupported mode (l, |m|)");
+    for (int b = 0; b < a; ++b)
+      require(!(s->modes[b][0] == l && s->modes[b][1] == m), "duplicate mode");
+  }
+  require(std::isfinite(s->fs) && s->fs > 0 && std::isfinite(s->seg_len) && s->seg_len > 0, "fs/seg_len");
+  const double ns = s->fs * s->seg_len;
+  require(fabs(ns - std::round(ns)) < 1e-6 && ((int64_t)std::llround(ns)) % 2 == 0 && ns >= 16,
+          "fs * seg_len must be an even integer >= 16");
+  require(std::isfinite(s->f_low) && s->f_low > 0 && s->f_low < 0.5 * s->fs, "f_low out of range");
+  require(s->det_geom != nullptr, "det_geom is NULL");
+  for (int i = 0; i < 5 * s->n_det; ++i) require(std::isfinite(s->det_geom[i]), "det_geom has non-finite values");
+  if (!s->psd) require(std::isfinite(s->psd_scale) && s->psd_scale > 0, "psd_scale must be > 0");
+  if (s->data_fd) {
+    require(std::isfinite(s->d_ref) && s->d_ref > 0, "d_ref must be > 0 when data_fd is given");
+  } else {
+    require(std::isfinite(s->inj_snr) && s->inj_snr > 0, "inj_snr must be > 0");
+    require(s->inj_phys[0] > 0 && s->inj_phys[1] > 0 && s->inj_phys[0] >= s->inj_phys[1], "injection masses");
+    for (int i = 0; i < 5; ++i) require(std::isfinite(s->inj_ext[i]), "injection extrinsics");
+  }
+  require(s->center_phys[0] > 0 && s->center_phys[1] > 0 && s->center_phys[0] > s->center_phys[1],
+          "centre masses must satisfy m1 > m2 > 0");
+  require(fabs(s->center_phys[2]) < 1 && fabs(s->center_phys[3]) < 1, "centre spins");
+  require(std::isfinite(s->match) && s->match > 0 && s->match < 1, "match must be in (0, 1)");
+  require(std::isfinite(s->t_trig) && s->t_trig >= 0 && s->t_trig < s->seg_len, "t_trig out of the segment");
+  const double ntr = s->t_trig * s->fs;
+  require(fabs(ntr - std::round(ntr)) < 1e-6, "t_trig must be on the sample grid");
+  require(std::isfinite(s->half_window) && s->half_window > 0, "half_window must be > 0");
+  const int W = (int)floor(s->half_window * s->fs + 1e-9);
+  require(W >= 6 && 2 * W + 1 < ns, "half_window must span at least 6 samples and fit in the segment");
+  require(s->poly_degree >= 0 && s->poly_degree <= 3, "poly_degree must be 0..3");
+  const int M = (int)(s->poly_degree == 0 ? 1 : s->poly_degree == 1 ? 5 : s->poly_degree == 2 ? 15 : 35);
+  require(s->n_nodes > M && s->n_nodes <= 20000, "n_nodes must exceed the number of monomials (and <= 20000)");
+  require(s->q >= 1 && s->q <= std::min(s->n_nodes, 2 * W + 1), "q must be in 1 .. min(N, 2W+1)");
+  require(std::isfinite(s->eps) && s->eps > 0, "eps must be > 0");
+  require(std::isfinite(s->chi_max) && s->chi_max > 0 && s->chi_max <= 1, "chi_max must be in (0, 1]");
+  if (s->psd) {
+    const int64_t nf = (int64_t)std::llround(ns) / 2 + 1;
+    for (int64_t i = 0; i < nf * s->n_det; ++i)
+      require((std::isfinite(s->psd[i]) && s->psd[i] > 0) || (i % nf) == 0, "psd must be finite and > 0");
+  }
+}
+
+static int monomials(int degree, int idx[kMaxPoly][3]) {
+  int n = 0;
+  for (int d = 0; d <= degree; ++d) {
+    if (d == 0) {
+      idx[n][0] = idx[n][1] = idx[n][2] = -1;
+      ++n;
+    } else if (d == 1) {
+      for (int i = 0; i < 4; ++i, ++n) {
+        idx[n][0] = i;
+        idx[n][1] = idx[n][2] = -1;
+      }
+    } else if (d == 2) {
+      for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j, ++n) {
+          idx[n][0] = i;
+          idx[n][1] = j;
+          idx[n][2] = -1;
+        }
+    } else {
+      for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j)
+          for (int k = j; k < 4; ++k, ++n) {
+            idx[n][0] = i;
+            idx[n][1] = j;
+            idx[n][2] = k;
+          }
+    }
+  }
+  return n;
+}
+
+struct BlasHandle {
+  rocblas_handle h = nullptr;
+  BlasHandle() { blas_check(rocblas_create_handle(&h), "rocblas_create_handle"); }
+  ~BlasHandle() {
+    if (h) rocblas_destroy_handle(h);
+  }
+};
+
+static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
+  const auto t_all = Clock::now();
+  validate(s);
+  c.n_det = s->n_det;
+  c.n_modes = s->n_modes;
+  for (int a = 0; a < c.n_modes; ++a) {
+    c.modes[a][0] = s->modes[a][0];
+    c.modes[a][1] = s->modes[a][1];
+  }
+  c.fs = s->fs;
+  c.seg_len = s->seg_len;
+  c.f_low = s->f_low;
+  c.n_s = (int64_t)std::llround(s->fs * s->seg_len);
+  c.n_f = c.n_s / 2 + 1;
+  c.df = 1.0 / s->seg_len;
+  c.eps = s->eps;
+  c.chi_max = s->chi_max;
+  c.t_trig = s->t_trig;
+  c.match = s->match;
+  c.q = s->q;
+  c.half_w = (int)floor(s->half_window * s->fs + 1e-9);
+  c.T = 2 * c.half_w + 1;
+  c.degree = s->poly_degree;
+  int poly[kMaxPoly][3];
+  c.M = monomials(c.degree, poly);
+  c.N = s->n_nodes;
+  c.K = c.n_det * (2 * c.q * c.n_modes + c.n_modes * c.n_modes);
+  c.Kp = ((c.K + kColTile - 1) / kColTile) * kColTile;
+  c.rows = ((c.N + c.M + kRowChunk - 1) / kRowChunk) * kRowChunk;
+  const int NM = c.N + c.M;
+  for (int k = 0; k < c.n_det; ++k) detector_geometry(s->det_geom + 5 * k, c.D[k], c.r[k]);
+
+  YlmTerms yneg[RBFL_MAX_MODES], ypos[RBFL_MAX_MODES];
+  for (int a = 0; a < c.n_modes; ++a) {
+    yneg[a] = ylm_terms(c.modes[a][0], -c.modes[a][1]);
+    ypos[a] = ylm_terms(c.modes[a][0], c.modes[a][1]);
+  }
+
+  // PSD and data
+  auto t0 = Clock::now();
+  std::vector<std::vector<double>> psd(c.n_det, std::vector<double>(c.n_f));
+  for (int k = 0; k < c.n_det; ++k) {
+    psd[k][0] = std::numeric_limits<double>::infinity();
+    for (int64_t j = 1; j < c.n_f; ++j)
+      psd[k][j] = s->psd ? s->psd[(int64_t)k * c.n_f + j] : psd_analytic((double)j * c.df, s->psd_scale);
+  }
+  std::vector<std::vector<double2>> data;
+  if (s->data_fd) {
+    c.d_ref = s->d_ref;
+    data.assign(c.n_det, std::vector<double2>(c.n_f));
+    for (int k = 0; k < c.n_det; ++k)
+      for (int64_t j = 0; j < c.n_f; ++j)
+        data[k][j] = make_double2(s->data_fd[((int64_t)k * c.n_f + j) * 2], s->data_fd[((int64_t)k * c.n_f + j) * 2 + 1]);
+  } else {
+    synthesise_data(*s, c, psd, yneg, ypos, data, &c.d_ref);
+  }
+  c.timing[0] = seconds_since(t0);
+
+  // frame
+  t0 = Clock::now();
+  phys_to_theta(s->center_phys, c.f_low, c.theta_c);
+  if (s->metric) {
+    for (int i = 0; i < 16; ++i) c.metric[i] = s->metric[i];
+  } else {
+    compute_metric(c, psd[0], s->center_phys, c.metric);
+  }
+  double lam[4], vec[16];
+  jacobi_eigen(c.metric, lam, vec);
+  int order[4] = {0, 1, 2, 3};
+  std::sort(order, order + 4, [&](int x, int y) { return lam[x] > lam[y]; });
+  for (int i = 0; i < 4; ++i) {
+    const int o = order[i];
+    c.lam[i] = lam[o];
+    if (!(lam[o] > 0.0)) throw Error(RBFL_E_NUMERICAL, "metric is not positive definite");
+    int kmax = 0;
+    for (int r = 1; r < 4; ++r)
+      if (fabs(vec[4 * r + o]) > fabs(vec[4 * kmax + o])) kmax = r;
+    const double sg = vec[4 * kmax + o] < 0 ? -1.0 : 1.0;
+    for (int r = 0; r < 4; ++r) c.V[4 * r + i] = sg * vec[4 * r + o];
+    c.semi[i] = sqrt((1.0 - c.match) / lam[o]);
+  }
+
+  // Halton nodes in the ball, physical only
+  c.x_nodes.assign((size_t)c.N * 4, 0.0);
+  c.phys_nodes.assign((size_t)c.N * 4, 0.0);
+  int have = 0;
+  auto try_point = [&](const double x[4]) -> bool {
+    double th[4], p[4];
+    for (int i = 0; i < 4; ++i) {
+      double v = c.theta_c[i];
+      for (int j = 0; j < 4; ++j) v += c.V[4 * i + j] * (x[j] * c.semi[j]);
+      th[i] = v;
+    }
+    if (!theta_to_phys(th, c.f_low, c.chi_max, p)) return false;
+    for (int d = 0; d < 4; ++d) {
+      c.x_nodes[4 * have + d] = x[d];
+      c.phys_nodes[4 * have + d] = p[d];
+    }
+    ++have;
+    return true;
+  };
+  if (s->flags & RBFL_FLAG_CENTER_NODE) {
+    const double zero[4] = {0, 0, 0, 0};
+    if (!try_point(zero)) throw Error(RBFL_E_INVALID_ARG, "centre is not a physical point");
+  }
+  const uint64_t bases[4] = {2, 3, 5, 7};
+  for (uint64_t i = 1; have < c.N; ++i) {
+    if (i > 50000000ull) throw Error(RBFL_E_NUMERICAL, "too few physical Halton points in the ellipsoid");
+    double x[4], r2 = 0.0;
+    for (int d = 0; d < 4; ++d) {
+      x[d] = 2.0 * radical_inverse(i, bases[d]) - 1.0;
+      r2 += x[d] * x[d];
+    }
+    if (r2 <= 1.0) try_point(x);
+  }
+  c.timing[1] = seconds_since(t0);
+
+  // ---- device: templates, overlaps and windowed DFT at the nodes
+  t0 = Clock::now();
+  const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  const int64_t j_hi = c.n_s / 2;
+  std::vector<Binary> bins(c.N);
+  int J_mode[RBFL_MAX_MODES] = {};
+  for (int i = 0; i < c.N; ++i) {
+    bins[i] = make_binary(c.phys_nodes[4 * i], c.phys_nodes[4 * i + 1], c.phys_nodes[4 * i + 2], c.phys_nodes[4 * i + 3]);
+    for (int a = 0; a < c.n_modes; ++a) {
+      int64_t jc = (int64_t)ceil((double)c.modes[a][1] * bins[i].f_isco * c.seg_len);
+      jc = std::min(std::max(jc, j_lo), j_hi);
+      J_mode[a] = std::max<int>(J_mode[a], (int)(jc - j_lo));
+    }
+  }
+  int J = 1;
+  for (int a = 0; a < c.n_modes; ++a) J = std::max(J, J_mode[a]);
+  const int64_t n_trig = (int64_t)std::llround(c.t_trig * c.fs);
+  int64_t n0 = ((n_trig - c.half_w) % c.n_s + c.n_s) % c.n_s;
+  std::vector<double2> Dk((size_t)c.n_det * J);
+  std::vector<double> wk((size_t)c.n_det * J);
+  for (int k = 0; k < c.n_det; ++k)
+    for (int jj = 0; jj < J; ++jj) {
+      const int64_t j = j_lo + jj;
+      const double sc = 4.0 * c.df / psd[k][j];
+      const int64_t ph = (j % c.n_s) * n0 % c.n_s;
+      double sn, cs;
+      const double ang = 2.0 * kPi * ((double)ph / (double)c.n_s);
+      sn = sin(ang);
+      cs = cos(ang);
+      const double2 d = data[k][j];
+      Dk[(size_t)k * J + jj] = make_double2(sc * (d.x * cs - d.y * sn), sc * (d.x * sn + d.y * cs));
+      wk[(size_t)k * J + jj] = sc;
+    }
+  DevBuf<Binary> d_bins;
+  d_bins.alloc(c.N);
+  RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * c.N, hipMemcpyHostToDevice, stream));
+  int mode_lm[2 * RBFL_MAX_MODES];
+  for (int a = 0; a < c.n_modes; ++a) {
+    mode_lm[2 * a] = c.modes[a][0];
+    mode_lm[2 * a + 1] = c.modes[a][1];
+  }
+  DevBuf<int> d_modes;
+  d_modes.alloc(2 * RBFL_MAX_MODES);
+  RBFL_HIP(hipMemcpyAsync(d_modes.p, mode_lm, sizeof(mode_lm), hipMemcpyHostToDevice, stream));
+  DevBuf<double2> d_Dk;
+  d_Dk.alloc(Dk.size());
+  RBFL_HIP(hipMemcpyAsync(d_Dk.p, Dk.data(), sizeof(double2) * Dk.size(), hipMemcpyHostToDevice, stream));
+  DevBuf<double> d_wk;
+  d_wk.alloc(wk.size());
+  RBFL_HIP(hipMemcpyAsync(d_wk.p, wk.data(), sizeof(double) * wk.size(), hipMemcpyHostToDevice, stream));
+  c.z_nodes.alloc((size_t)c.n_det * c.n_modes * c.N * c.T);
+  DevBuf<double2> d_sig;
+  d_sig.alloc((size_t)c.n_det * c.N * c.n_modes * c.n_modes);
+  // node batches sized so the templates of a batch stay within ~2 GiB
+  const size_t budget = (size_t)2 << 30;
+  int nb_max = (int)std::max<size_t>(1, std::min<size_t>(c.N, budget / ((size_t)c.n_modes * J * sizeof(double2))));
+  DevBuf<double2> d_A;
+  d_A.alloc((size_t)c.n_modes * nb_max * J);
+  // split the bin range of the windowed DFT so each launch has >= ~1024 blocks
+  auto n_splits = [&](int nb, int a) {
+    const int t_here = ((nb + 63) / 64) * ((c.T + 63) / 64);
+    return std::max(1, std::min((1024 + t_here - 1) / t_here, (J_mode[a] + 255) / 256));
+  };
+  size_t part_elems = 1;
+  for (int base = 0; base < c.N; base += nb_max) {
+    const int nb = std::min(nb_max, c.N - base);
+    for (int a = 0; a < c.n_modes; ++a) part_elems = std::max(part_elems, (size_t)n_splits(nb, a) * nb * c.T);
+  }
+  DevBuf<double2> d_part;
+  d_part.alloc(part_elems);
+  RBFL_HIP(hipMemsetAsync(c.z_nodes.p, 0, sizeof(double2) * c.z_nodes.n, stream));
+  for (int base = 0; base < c.N; base += nb_max) {
+    const int nb = std::min(nb_max, c.N - base);
+    launch_waveforms(d_bins.p + base, nb, d_modes.p, c.n_modes, j_lo, J, c.df, 1.0 / (c.d_ref * kMpcS), d_A.p, stream);
+    launch_sigma(d_A.p, nb, c.n_modes, J, d_wk.p, c.n_det, c.N, base, d_sig.p, stream);
+    for (int a = 0; a < c.n_modes; ++a) {
+      if (J_mode[a] <= 0) continue;
+      const int n_split = n_splits(nb, a);
+      for (int k = 0; k < c.n_det; ++k) {
+        launch_window_dft(d_A.p + (size_t)a * nb * J, nb, J_mode[a], J, d_Dk.p + (size_t)k * J, j_lo, c.n_s, c.T,
+                          n_split, d_part.p, stream);
+        launch_reduce_splits(d_part.p, n_split, nb, c.T,
+                             c.z_nodes.p + (((size_t)k * c.n_modes + a) * c.N + base) * c.T, stream);
+      }
+    }
+  }
+  RBFL_HIP(hipStreamSynchronize(stream));
+  d_A.reset();
+  d_part.reset();
+  c.timing[2] = seconds_since(t0);
+
+  // ---- SVD per (detector, mode) and the coefficients at the nodes
+  t0 = Clock::now();
+  BlasHandle bh;
+  blas_check(rocblas_set_stream(bh.h, stream), "rocblas_set_stream");
+  const int mn = std::min(c.N, c.T);
+  c.basis.alloc((size_t)c.n_det * c.n_modes * c.T * c.q);
+  DevBuf<double2> d_C;
+  d_C.alloc((size_t)c.n_det * c.n_modes * c.N * c.q);
+  DevBuf<double2> d_work, d_U;
+  d_work.alloc((size_t)c.N * c.T);
+  d_U.alloc((size_t)c.T * mn);
+  DevBuf<double> d_S, d_E;
+  d_S.alloc(mn);
+  d_E.alloc(std::max(1, mn - 1));
+  DevBuf<int> d_info;
+  d_info.alloc(1);
+  c.singular.assign((size_t)c.n_det * c.n_modes * mn, 0.0);
+  for (int k = 0; k < c.n_det; ++k)
+    for (int a = 0; a < c.n_modes; ++a) {
+      const size_t ka = (size_t)k * c.n_modes + a;
+      const double2 *Z = c.z_nodes.p + ka * c.N * c.T;
+      RBFL_HIP(hipMemcpyAsync(d_work.p, Z, sizeof(double2) * c.N * c.T, hipMemcpyDeviceToDevice, stream));
+      // row-major N x T = column-major T x N; its left singular vectors are the
+      // conjugated right singular vectors of Z
+      blas_check(rocsolver_zgesvd(bh.h, rocblas_svect_singular, rocblas_svect_none, c.T, c.N,
+                                  reinterpret_cast<rocblas_double_complex *>(d_work.p), c.T, d_S.p,
+                                  reinterpret_cast<rocblas_double_complex *>(d_U.p), c.T, nullptr, 1, d_E.p,
+                                  rocblas_outofplace, d_info.p),
+                 "rocsolver_zgesvd");
+      int info = 0;
+      RBFL_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+      RBFL_HIP(hipMemcpyAsync(c.singular.data() + ka * mn, d_S.p, sizeof(double) * mn, hipMemcpyDeviceToHost, stream));
+      RBFL_HIP(hipStreamSynchronize(stream));
+      if (info != 0) throw Error(RBFL_E_NUMERICAL, "SVD did not converge (info " + std::to_string(info) + ")");
+      launch_basis_from_u(d_U.p, c.T, c.T, c.q, c.basis.p + ka * c.T * c.q, stream);
+      launch_coeffs(Z, c.basis.p + ka * c.T * c.q, c.N, c.T, c.q, d_C.p + ka * c.N * c.q, stream);
+    }
+  d_work.reset();
+  d_U.reset();
+  c.timing[3] = seconds_since(t0);
+
+  // ---- RBF system (Eq. rbfcoeff) and FP64 LU solve
+  t0 = Clock::now();
+  std::vector<int4> coldesc;
+  int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
+  for (int k = 0; k < c.n_det; ++k) {
+    for (int a = 0; a < c.n_modes; ++a) {
+      coef_off[k][a] = (int)coldesc.size();
+      for (int i = 0; i < c.q; ++i) {
+        coldesc.push_back(make_int4(0, k, a, i));
+        coldesc.push_back(make_int4(1, k, a, i));
+      }
+    }
+    sig_off[k] = (int)coldesc.size();
+    for (int a = 0; a < c.n_modes; ++a) coldesc.push_back(make_int4(2, k, a, a));
+    for (int a = 0; a < c.n_modes; ++a)
+      for (int b = a + 1; b < c.n_modes; ++b) {
+        coldesc.push_back(make_int4(2, k, a, b));
+        coldesc.push_back(make_int4(3, k, a, b));
+      }
+  }
+  if ((int)coldesc.size() != c.K) throw Error(RBFL_E_INVALID_ARG, "internal: output layout size");
+  DevBuf<int4> d_desc;
+  d_desc.alloc(coldesc.size());
+  RBFL_HIP(hipMemcpyAsync(d_desc.p, coldesc.data(), sizeof(int4) * coldesc.size(), hipMemcpyHostToDevice, stream));
+  DevBuf<double> d_R;
+  d_R.alloc((size_t)c.K * NM);
+  launch_assemble_rhs(d_C.p, d_sig.p, d_desc.p, c.N, c.K, NM, c.q, c.n_modes, d_R.p, stream);
+  std::vector<double> Rh((size_t)c.K * NM);
+  RBFL_HIP(hipMemcpyAsync(Rh.data(), d_R.p, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, stream));
+  c.nodes.alloc((size_t)c.rows * 4);
+  RBFL_HIP(hipMemsetAsync(c.nodes.p, 0, sizeof(double) * c.rows * 4, stream));
+  RBFL_HIP(hipMemcpyAsync(c.nodes.p, c.x_nodes.data(), sizeof(double) * c.N * 4, hipMemcpyHostToDevice, stream));
+  DevBuf<int> d_poly;
+  d_poly.alloc(kMaxPoly * 3);
+  RBFL_HIP(hipMemcpyAsync(d_poly.p, poly, sizeof(poly), hipMemcpyHostToDevice, stream));
+  DevBuf<double> d_A2;
+  d_A2.alloc((size_t)NM * NM);
+  launch_assemble_system(c.nodes.p, c.N, c.M, d_poly.p, c.eps * c.eps, d_A2.p, stream);
+  // 1-norm of the system for the condition estimate
+  std::vector<double> Ah((size_t)NM * NM);
+  RBFL_HIP(hipMemcpyAsync(Ah.data(), d_A2.p, sizeof(double) * Ah.size(), hipMemcpyDeviceToHost, stream));
+  RBFL_HIP(hipStreamSynchronize(stream));
+  c.node_values.assign((size_t)c.N * c.K, 0.0);
+  for (int n = 0; n < c.N; ++n)
+    for (int col = 0; col < c.K; ++col) c.node_values[(size_t)n * c.K + col] = Rh[(size_t)col * NM + n];
+  double anorm = 0.0;
+  for (int j = 0; j < NM; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < NM; ++i) s += fabs(Ah[(size_t)j * NM + i]);
+    anorm = std::max(anorm, s);
+  }
+  DevBuf<int> d_ipiv;
+  d_ipiv.alloc(NM);
+  blas_check(rocsolver_dgetrf(bh.h, NM, NM, d_A2.p, NM, d_ipiv.p, d_info.p), "rocsolver_dgetrf");
+  int info = 0;
+  RBFL_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RBFL_HIP(hipStreamSynchronize(stream));
+  if (info != 0) throw Error(RBFL_E_NUMERICAL, "RBF system is singular (zero pivot " + std::to_string(info) + ")");
+  blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_R.p, NM),
+             "rocsolver_dgetrs");
+  // Hager-Higham estimate of ||A^{-1}||_1 from solves with A and A^T
+  {
+    DevBuf<double> d_v;
+    d_v.alloc(NM);
+    std::vector<double> x(NM, 1.0 / NM), y(NM), z(NM);
+    double est = 0.0;
+    for (int it = 0; it < 5; ++it) {
+      RBFL_HIP(hipMemcpyAsync(d_v.p, x.data(), sizeof(double) * NM, hipMemcpyHostToDevice, stream));
+      blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, 1, d_A2.p, NM, d_ipiv.p, d_v.p, NM), "getrs");
+      RBFL_HIP(hipMemcpyAsync(y.data(), d_v.p, sizeof(double) * NM, hipMemcpyDeviceToHost, stream));
+      RBFL_HIP(hipStreamSynchronize(stream));
+      double ny = 0.0;
+      for (double v : y) ny += fabs(v);
+      est = std::max(est, ny);
+      std::vector<double> xi(NM);
+      for (int i = 0; i < NM; ++i) xi[i] = y[i] >= 0 ? 1.0 : -1.0;
+      RBFL_HIP(hipMemcpyAsync(d_v.p, xi.data(), sizeof(double) * NM, hipMemcpyHostToDevice, stream));
+      blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_transpose, NM, 1, d_A2.p, NM, d_ipiv.p, d_v.p, NM),
+                 "getrs");
+      RBFL_HIP(hipMemcpyAsync(z.data(), d_v.p, sizeof(double) * NM, hipMemcpyDeviceToHost, stream));
+      RBFL_HIP(hipStreamSynchronize(stream));
+      int jmax = 0;
+      double zx = 0.0;
+      for (int i = 0; i < NM; ++i) {
+        if (fabs(z[i]) > fabs(z[jmax])) jmax = i;
+        zx += z[i] * x[i];
+      }
+      if (fabs(z[jmax]) <= zx) break;
+      std::fill(x.begin(), x.end(), 0.0);
+      x[jmax] = 1.0;
+    }
+    c.cond = anorm * est;
+  }
+  c.W.alloc((size_t)c.rows * c.Kp);
+  launch_transpose_weights(d_R.p, NM, c.K, c.rows, c.Kp, c.W.p, stream);
+  RBFL_HIP(hipStreamSynchronize(stream));
+  c.timing[4] = seconds_since(t0);
+
+  // ---- constants for the online stage
+  EvalConsts &e = c.host_consts;
+  std::memset(&e, 0, sizeof(e));
+  e.n_det = c.n_det;
+  e.n_modes = c.n_modes;
+  e.N = c.N;
+  e.M = c.M;
+  e.K = c.K;
+  e.Kp = c.Kp;
+  e.rows = c.rows;
+  e.q = c.q;
+  e.T = c.T;
+  e.half_w = c.half_w;
+  e.degree = c.degree;
+  for (int p = 0; p < kMaxPoly; ++p)
+    for (int t = 0; t < 3; ++t) e.poly_idx[p][t] = p < c.M ? poly[p][t] : -1;
+  e.eps2 = c.eps * c.eps;
+  e.fs = c.fs;
+  e.t_trig = c.t_trig;
+  e.d_ref = c.d_ref;
+  e.f0 = c.f_low;
+  e.chi_max = c.chi_max;
+  for (int i = 0; i < 4; ++i) {
+    e.theta_c[i] = c.theta_c[i];
+    e.semi[i] = c.semi[i];
+  }
+  for (int i = 0; i < 16; ++i) e.V[i] = c.V[i];
+  for (int k = 0; k < c.n_det; ++k) {
+    for (int i = 0; i < 9; ++i) e.D[k][i] = c.D[k][i];
+    for (int i = 0; i < 3; ++i) e.r[k][i] = c.r[k][i];
+    for (int a = 0; a < c.n_modes; ++a) e.coef_off[k][a] = coef_off[k][a];
+    e.sig_off[k] = sig_off[k];
+  }
+  for (int a = 0; a < c.n_modes; ++a) {
+    e.mode_l[a] = c.modes[a][0];
+    e.ylm_neg[a] = yneg[a];
+    e.ylm_pos[a] = ypos[a];
+  }
+  spline_table(e.spline);
+  c.consts.alloc(1);
+  RBFL_HIP(hipMemcpyAsync(c.consts.p, &e, sizeof(e), hipMemcpyHostToDevice, stream));
+  RBFL_HIP(hipStreamSynchronize(stream));
+  c.timing[5] = seconds_since(t_all);
+}
+
+static void reserve(Ctx &c, int64_t n) {
+  if (n <= c.cap) return;
+  c.Y.alloc((size_t)n * c.Kp);
+  c.cap = n;
+}
+
+static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s);
+
+static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
+  require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
+  require(n >= 0, "n must be >= 0");
+  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+  if (n == 0) return;
+  if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
+  for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
+    const int64_t nb = std::min(c.cap, n - b0);
+    contract(c, params, n, b0, nb, form, s);
+    launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
+  }
+}
+
+static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s) {
+  switch (form) {
+    case RBFL_FORM_FP64:
+      launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s);
+      break;
+    case RBFL_FORM_FP32:
+      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, nullptr, 0, c.Y.p, s);
+      break;
+    case RBFL_FORM_SPLIT:
+      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.W32lo.p, 1, c.Y.p, s);
+      break;
+    default:
+      launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W16.p, c.Y.p, s);
+  }
+}
+
+static void interp(Ctx &c, const double *params, int64_t n, double *out, int form, hipStream_t s) {
+  require(params != nullptr && out != nullptr, "params/out is NULL");
+  require(n >= 0, "n must be >= 0");
+  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+  if (n == 0) return;
+  if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
+  for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
+    const int64_t nb = std::min(c.cap, n - b0);
+    contract(c, params, n, b0, nb, form, s);
+    RBFL_HIP(hipMemcpy2DAsync(out + b0 * c.K, sizeof(double) * c.K, c.Y.p, sizeof(double) * c.Kp,
+                              sizeof(double) * c.K, nb, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+static void prepare(Ctx &c, int form) {
+  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (c.prepared[form]) return;
+  const size_t n = (size_t)c.rows * c.Kp;
+  if (form == RBFL_FORM_BF16) throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
+  if (!c.W32.p) c.W32.alloc(n);
+  if (form == RBFL_FORM_SPLIT && !c.W32lo.p) c.W32lo.alloc(n);
+  launch_convert_weights(c.W.p, n, c.W32.p, form == RBFL_FORM_SPLIT ? c.W32lo.p : nullptr, nullptr, 0);
+  RBFL_HIP(hipDeviceSynchronize());
+  c.prepared[RBFL_FORM_FP32] = true;
+  if (form == RBFL_FORM_SPLIT) c.prepared[RBFL_FORM_SPLIT] = true;
+}
+
+static void copy_out(void *out, size_t bytes, const void *src, size_t need) {
+  require(out != nullptr, "out is NULL");
+  require(bytes >= need, "output buffer too small (need " + std::to_string(need) + " bytes)");
+  std::memcpy(out, src, need);
+}
+
+static void query(Ctx &c, int what, void *out, size_t bytes) {
+  const int mn = std::min(c.N, c.T);
+  switch (what) {
+    case RBFL_Q_SIZES: {
+      int64_t v[8] = {c.N, c.M, c.K, c.q, c.T, c.n_det, c.n_modes, c.half_w};
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
+    case RBFL_Q_FRAME: {
+      double v[44];
+      for (int i = 0; i < 4; ++i) v[i] = c.theta_c[i];
+      for (int i = 0; i < 16; ++i) v[4 + i] = c.V[i];
+      for (int i = 0; i < 4; ++i) v[20 + i] = c.lam[i];
+      for (int i = 0; i < 4; ++i) v[24 + i] = c.semi[i];
+      for (int i = 0; i < 16; ++i) v[28 + i] = c.metric[i];
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
+    case RBFL_Q_D_REF:
+      copy_out(out, bytes, &c.d_ref, sizeof(double));
+      return;
+    case RBFL_Q_NODES:
+      copy_out(out, bytes, c.x_nodes.data(), sizeof(double) * c.x_nodes.size());
+      return;
+    case RBFL_Q_NODE_PHYS:
+      copy_out(out, bytes, c.phys_nodes.data(), sizeof(double) * c.phys_nodes.size());
+      return;
+    case RBFL_Q_NODE_VALUES:
+      copy_out(out, bytes, c.node_values.data(), sizeof(double) * c.node_values.size());
+      return;
+    case RBFL_Q_SINGULAR:
+      copy_out(out, bytes, c.singular.data(), sizeof(double) * c.singular.size());
+      (void)mn;
+      return;
+    case RBFL_Q_COND:
+      copy_out(out, bytes, &c.cond, sizeof(double));
+      return;
+    case RBFL_Q_TIMING:
+      copy_out(out, bytes, c.timing, sizeof(c.timing));
+      return;
+    case RBFL_Q_WEIGHTS: {
+      const size_t need = sizeof(double) * (size_t)(c.N + c.M) * c.K;
+      require(out != nullptr && bytes >= need, "output buffer too small");
+      RBFL_HIP(hipMemcpy2D(out, sizeof(double) * c.K, c.W.p, sizeof(double) * c.Kp, sizeof(double) * c.K, c.N + c.M,
+                           hipMemcpyDeviceToHost));
+      return;
+    }
+    case RBFL_Q_BASIS: {
+      const size_t need = sizeof(double2) * c.basis.n;
+      require(out != nullptr && bytes >= need, "output buffer too small");
+      RBFL_HIP(hipMemcpy(out, c.basis.p, need, hipMemcpyDeviceToHost));
+      return;
+    }
+    case RBFL_Q_Z_NODES: {
+      const size_t need = sizeof(double2) * c.z_nodes.n;
+      require(out != nullptr && bytes >= need, "output buffer too small");
+      RBFL_HIP(hipMemcpy(out, c.z_nodes.p, need, hipMemcpyDeviceToHost));
+      return;
+    }
+    default:
+      throw Error(RBFL_E_INVALID_ARG, "unknown query");
+  }
+}
+
+template <class F>
+static int32_t guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return RBFL_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return RBFL_E_OUT_OF_MEMORY;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return RBFL_E_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return RBFL_E_DEVICE;
+  }
+}
+
+}  // namespace rbfl
+
+struct rbfl_ctx {
+  rbfl::Ctx c;
+};
+
+extern "C" {
+
+const char *rbfl_last_error(void) { return rbfl::g_last_error.c_str(); }
+
+int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out) {
+  return rbfl::guarded([&] {
+    rbfl::require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<rbfl_ctx> h(new rbfl_ctx());
+    rbfl::build(spec, reinterpret_cast<hipStream_t>(stream), h->c);
+    *out = h.release();
+  });
+}
+
+int32_t rbfl_eval(rbfl_handle h, const double *params, int64_t n, double *lnl, int32_t form, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::eval(h->c, params, n, lnl, form, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_interp(rbfl_handle h, const double *params, int64_t n, double *out, int32_t form, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::interp(h->c, params, n, out, form, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_prepare(rbfl_handle h, int32_t form) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::prepare(h->c, form);
+  });
+}
+
+int32_t rbfl_reserve(rbfl_handle h, int64_t n) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(n >= 1, "n must be >= 1");
+    rbfl::reserve(h->c, n);
+  });
+}
+
+int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::query(h->c, what, out, bytes);
+  });
+}
+
+int32_t rbfl_destroy(rbfl_handle h) {
+  return rbfl::guarded([&] { delete h; });
+}
+
+}  // extern "C"

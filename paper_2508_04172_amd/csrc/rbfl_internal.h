@@ -1,0 +1,134 @@
+// Internal declarations of the rbfl library: handle layout, the constant
+// block the online kernels read, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rbfl.h"
+#include "rbfl_math.h"
+
+namespace rbfl {
+
+constexpr int kMaxPoly = 35;     // monomials of degree <= 3 in 4 variables
+constexpr int kSplineTaps = 10;  // samples in the sub-sample spline stencil
+constexpr int kRowChunk = 64;    // node rows per contraction chunk (W rows padded to this)
+constexpr int kColTile = 64;     // interpolated outputs per contraction column tile (K padded to this)
+
+// Error carrying an rbfl_status through the host code; converted at the ABI.
+struct Error : std::runtime_error {
+  int32_t code;
+  Error(int32_t c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what);
+#define RBFL_HIP(x) ::rbfl::hip_check((x), #x)
+
+// Everything the online-stage kernels read, resident in device memory (one
+// copy per handle, read through a pointer so handles never share state).
+struct EvalConsts {
+  int n_det, n_modes, N, M, K, Kp, rows;   // rows = N + M padded to kRowChunk
+  int q, T, half_w, degree;
+  int poly_idx[kMaxPoly][3];                // variable indices of each monomial, -1 = unused
+  double eps2, fs, t_trig, d_ref, f0, chi_max;
+  double theta_c[4], V[16], semi[4];        // V row-major: Theta_i = theta_c_i + sum_j V[i][j] de_j
+  double D[RBFL_MAX_DET][9], r[RBFL_MAX_DET][3];
+  int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
+  int mode_l[RBFL_MAX_MODES];
+  YlmTerms ylm_neg[RBFL_MAX_MODES];         // -2Y_{l,-m}
+  YlmTerms ylm_pos[RBFL_MAX_MODES];         // -2Y_{l,m}
+  double spline[kSplineTaps][4];            // w_s(f) = sum_p spline[s][p] f^p
+};
+
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    reset();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error(RBFL_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+};
+
+struct Ctx {
+  // sizes and scalars
+  int n_det = 0, n_modes = 0;
+  int modes[RBFL_MAX_MODES][2] = {};
+  int N = 0, M = 0, K = 0, Kp = 0, rows = 0, q = 0, T = 0, half_w = 0, degree = 0;
+  int64_t n_s = 0, n_f = 0;
+  double fs = 0, seg_len = 0, f_low = 0, df = 0;
+  double eps = 0, chi_max = 1, t_trig = 0, d_ref = 0, match = 0;
+  // frame
+  double theta_c[4] = {}, V[16] = {}, lam[4] = {}, semi[4] = {}, metric[16] = {};
+  double D[RBFL_MAX_DET][9] = {}, r[RBFL_MAX_DET][3] = {};
+  // host-side artefacts kept for export
+  std::vector<double> x_nodes, phys_nodes, node_values, singular;
+  double cond = 0;
+  double timing[8] = {};
+  // device artefacts
+  DevBuf<EvalConsts> consts;
+  DevBuf<double> nodes;        // [rows][4] unit-ball coordinates, zero-padded
+  DevBuf<double> W;            // [rows][Kp] RBF weights, zero-padded
+  DevBuf<double2> basis;       // [n_det][n_modes][T][q]
+  DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
+  // reduced-precision weight copies
+  DevBuf<float> W32;           // [rows][Kp]
+  DevBuf<float> W32lo;         // [rows][Kp] low part of the FP32 split
+  DevBuf<uint16_t> W16;        // [rows][Kp] bf16
+  bool prepared[4] = {true, false, false, false};
+  // work space
+  DevBuf<double> Y;            // [cap][Kp]
+  int64_t cap = 0;
+  EvalConsts host_consts;
+};
+
+// ---- start-up kernels (build_kernels.hip) ----
+void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
+                      double df, double inv_dref_s, double2 *out, hipStream_t s);
+void launch_sigma(const double2 *A, int nb, int n_modes, int J, const double *wk, int n_det, int N_total,
+                  int node_base, double2 *sig, hipStream_t s);
+void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
+                       int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s);
+void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, double2 *Z_rows, hipStream_t s);
+void launch_basis_from_u(const double2 *U, int T, int ldu, int q, double2 *B, hipStream_t s);
+void launch_coeffs(const double2 *Z, const double2 *B, int N, int T, int q, double2 *C, hipStream_t s);
+void launch_assemble_rhs(const double2 *C, const double2 *sig, const int4 *coldesc, int N, int K, int NM,
+                         int q, int n_modes, double *R, hipStream_t s);
+void launch_assemble_system(const double *x, int N, int M, const int *poly_idx, double eps2, double *A,
+                            hipStream_t s);
+void launch_transpose_weights(const double *R, int NM, int K, int rows, int Kp, double *W, hipStream_t s);
+
+// ---- online kernels (eval_kernels.hip) ----
+void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
+                          int64_t b0, int64_t nb, const double *nodes, const double *W, double *Y,
+                          hipStream_t s);
+void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
+                          int64_t b0, int64_t nb, const double *nodes, const float *W, const float *Wlo,
+                          int split, double *Y, hipStream_t s);
+void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
+                          int64_t b0, int64_t nb, const double *nodes, const uint16_t *W, double *Y,
+                          hipStream_t s);
+void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                     int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
+void launch_convert_weights(const double *W, size_t n, float *hi, float *lo, uint16_t *b16, hipStream_t s);
+
+}  // namespace rbfl

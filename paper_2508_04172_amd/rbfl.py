@@ -1,0 +1,275 @@
+"""ctypes binding of the rbfl C ABI (include/rbfl.h).
+
+Argument marshalling only: every step of the start-up and online stages runs
+in the HIP library.  Device buffers are passed as raw pointers (e.g.
+``tensor.data_ptr()``) and streams as HIP stream handles (under ROCm,
+``torch.cuda.current_stream().cuda_stream``).  Loading fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbfl.so")
+
+ABI_VERSION = 1
+MAX_MODES = 5
+MAX_DET = 4
+
+OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NUMERICAL, E_UNSUPPORTED, E_STATE = range(7)
+FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT = range(4)
+FLAG_CENTER_NODE = 0x1
+
+Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
+    Q_TIMING, Q_Z_NODES = range(12)
+
+EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
+            "rbfl_query", "rbfl_destroy")
+
+
+class BuildSpec(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32),
+        ("n_det", C.c_int32),
+        ("n_modes", C.c_int32),
+        ("modes", (C.c_int32 * 2) * MAX_MODES),
+        ("fs", C.c_double),
+        ("seg_len", C.c_double),
+        ("f_low", C.c_double),
+        ("psd_scale", C.c_double),
+        ("psd", C.POINTER(C.c_double)),
+        ("data_fd", C.POINTER(C.c_double)),
+        ("noise_white", C.POINTER(C.c_double)),
+        ("inj_phys", C.c_double * 4),
+        ("inj_ext", C.c_double * 5),
+        ("inj_snr", C.c_double),
+        ("d_ref", C.c_double),
+        ("det_geom", C.POINTER(C.c_double)),
+        ("center_phys", C.c_double * 4),
+        ("match", C.c_double),
+        ("metric", C.POINTER(C.c_double)),
+        ("t_trig", C.c_double),
+        ("half_window", C.c_double),
+        ("n_nodes", C.c_int32),
+        ("q", C.c_int32),
+        ("eps", C.c_double),
+        ("poly_degree", C.c_int32),
+        ("chi_max", C.c_double),
+        ("flags", C.c_uint32),
+    ]
+
+
+class RbflError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rbfl status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librbfl.so (built in-tree by ``python -m paper_2508_04172_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2508_04172_amd.build`")
+    # PyTorch ships its own HIP runtime (same soname, loaded by path).  Loading
+    # it first lets this library bind to that runtime instead of pulling in a
+    # second copy, which would leave torch without a usable device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    lib.rbfl_last_error.restype = C.c_char_p
+    lib.rbfl_last_error.argtypes = []
+    lib.rbfl_build.restype = C.c_int32
+    lib.rbfl_build.argtypes = [C.POINTER(BuildSpec), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.rbfl_eval.restype = C.c_int32
+    lib.rbfl_eval.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.rbfl_interp.restype = C.c_int32
+    lib.rbfl_interp.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.rbfl_prepare.restype = C.c_int32
+    lib.rbfl_prepare.argtypes = [C.c_void_p, C.c_int32]
+    lib.rbfl_reserve.restype = C.c_int32
+    lib.rbfl_reserve.argtypes = [C.c_void_p, C.c_int64]
+    lib.rbfl_query.restype = C.c_int32
+    lib.rbfl_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.rbfl_destroy.restype = C.c_int32
+    lib.rbfl_destroy.argtypes = [C.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise RbflError(code, load().rbfl_last_error().decode())
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return C.POINTER(C.c_double)()
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional[np.ndarray] = None,
+                     keep: Optional[list] = None) -> BuildSpec:
+    """Marshal a workload configuration into the C spec.  `keep` receives the
+    numpy arrays whose memory the spec points to (they must outlive the call)."""
+    s = BuildSpec()
+    s.abi_version = ABI_VERSION
+    s.n_det = cfg.n_det
+    s.n_modes = len(cfg.modes)
+    for a, (l, m) in enumerate(cfg.modes):
+        s.modes[a][0] = l
+        s.modes[a][1] = m
+    s.fs, s.seg_len, s.f_low = cfg.fs, cfg.seg_len, cfg.f_low
+    s.psd_scale = cfg.psd_scale
+    geom = np.ascontiguousarray(np.array(cfg.sites, dtype=np.float64))
+    w = None if white is None else np.ascontiguousarray(white, dtype=np.float64)
+    met = None if metric is None else np.ascontiguousarray(metric, dtype=np.float64)
+    if keep is not None:
+        keep.extend([geom, w, met])
+    s.det_geom = _dptr(geom)
+    s.noise_white = _dptr(w)
+    s.psd = C.POINTER(C.c_double)()
+    s.data_fd = C.POINTER(C.c_double)()
+    s.metric = _dptr(met)
+    for i in range(4):
+        s.inj_phys[i] = cfg.inj_phys[i]
+        s.center_phys[i] = cfg.inj_phys[i]
+    for i in range(5):
+        s.inj_ext[i] = float(inj_ext[i])
+    s.inj_snr = cfg.inj_snr
+    s.d_ref = 0.0
+    s.match = cfg.match
+    s.t_trig = cfg.t_trig
+    s.half_window = cfg.half_window
+    s.n_nodes = cfg.n_nodes
+    s.q = cfg.q
+    s.eps = cfg.eps
+    s.poly_degree = cfg.poly_degree
+    s.chi_max = cfg.chi_max
+    s.flags = FLAG_CENTER_NODE if cfg.center_node else 0
+    return s
+
+
+class Handle:
+    """Owns one rbfl handle (start-up artefacts resident on the GPU)."""
+
+    def __init__(self, ptr: C.c_void_p):
+        self._h = ptr
+
+    @classmethod
+    def build(cls, spec: BuildSpec, stream: int = 0) -> "Handle":
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.rbfl_build(C.byref(spec), C.c_void_p(stream), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_config(cls, cfg, white, inj_ext, metric=None, stream: int = 0) -> "Handle":
+        keep = []
+        spec = spec_from_config(cfg, white, inj_ext, metric, keep)
+        return cls.build(spec, stream)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().rbfl_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self) -> int:
+        return self._h.value
+
+    def eval(self, params_ptr: int, n: int, lnl_ptr: int, form: int = FORM_FP64, stream: int = 0):
+        _check(load().rbfl_eval(self._h, C.c_void_p(params_ptr), n, C.c_void_p(lnl_ptr), form,
+                                C.c_void_p(stream)))
+
+    def interp(self, params_ptr: int, n: int, out_ptr: int, form: int = FORM_FP64, stream: int = 0):
+        _check(load().rbfl_interp(self._h, C.c_void_p(params_ptr), n, C.c_void_p(out_ptr), form,
+                                  C.c_void_p(stream)))
+
+    def prepare(self, form: int):
+        _check(load().rbfl_prepare(self._h, form))
+
+    def reserve(self, n: int):
+        _check(load().rbfl_reserve(self._h, n))
+
+    def _query(self, what: int, shape, dtype=np.float64) -> np.ndarray:
+        out = np.zeros(shape, dtype=dtype)
+        _check(load().rbfl_query(self._h, what, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def sizes(self) -> dict:
+        v = self._query(Q_SIZES, 8, np.int64)
+        return dict(zip(("N", "M", "K", "q", "T", "n_det", "n_modes", "half_w"), (int(x) for x in v)))
+
+    def frame(self) -> dict:
+        v = self._query(Q_FRAME, 44)
+        return {"theta_c": v[0:4], "vecs": v[4:20].reshape(4, 4), "lam": v[20:24], "semi": v[24:28],
+                "metric": v[28:44].reshape(4, 4)}
+
+    def d_ref(self) -> float:
+        return float(self._query(Q_D_REF, 1)[0])
+
+    def nodes(self) -> np.ndarray:
+        return self._query(Q_NODES, (self.sizes()["N"], 4))
+
+    def node_phys(self) -> np.ndarray:
+        return self._query(Q_NODE_PHYS, (self.sizes()["N"], 4))
+
+    def weights(self) -> np.ndarray:
+        s = self.sizes()
+        return self._query(Q_WEIGHTS, (s["N"] + s["M"], s["K"]))
+
+    def basis(self) -> np.ndarray:
+        s = self.sizes()
+        v = self._query(Q_BASIS, (s["n_det"], s["n_modes"], s["T"], s["q"], 2))
+        return v[..., 0] + 1j * v[..., 1]
+
+    def node_values(self) -> np.ndarray:
+        s = self.sizes()
+        return self._query(Q_NODE_VALUES, (s["N"], s["K"]))
+
+    def singular(self) -> np.ndarray:
+        s = self.sizes()
+        return self._query(Q_SINGULAR, (s["n_det"], s["n_modes"], min(s["N"], s["T"])))
+
+    def z_nodes(self) -> np.ndarray:
+        s = self.sizes()
+        v = self._query(Q_Z_NODES, (s["n_det"], s["n_modes"], s["N"], s["T"], 2))
+        return v[..., 0] + 1j * v[..., 1]
+
+    def cond(self) -> float:
+        return float(self._query(Q_COND, 1)[0])
+
+    def timing(self) -> np.ndarray:
+        return self._query(Q_TIMING, 8)
+
+
+def params_soa(handle: Handle, qd, t_trig: float) -> np.ndarray:
+    """[11][n] parameter array in the paper's coordinates for a normalised
+    query draw, using this handle's own semi-axes and reference distance."""
+    semi = handle.frame()["semi"]
+    n = len(qd)
+    p = np.empty((11, n))
+    p[0:4] = (qd.x * semi[None, :]).T
+    p[4:9] = qd.ext.T
+    p[9] = t_trig + qd.dt
+    p[10] = handle.d_ref() * qd.dist_ratio
+    return p

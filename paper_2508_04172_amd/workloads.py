@@ -108,13 +108,13 @@ CFG1 = Config(name="cfg1_single_det_22", fs=2048.0, seg_len=16.0, f_low=20.0,
 CFG2 = Config(name="cfg2_hlv_5mode", fs=4096.0, seg_len=64.0, f_low=20.0,
               modes=ALL_MODES, sites=SITES_HLV, psd_scale=1.0,
               inj_phys=(8.0, 1.4, 0.3, 0.0), inj_snr=20.0, match=0.97,
-              n_nodes=800, q=40, eps=1.0, poly_degree=1, half_window=0.05,
+              n_nodes=800, q=40, eps=2.0, poly_degree=1, half_window=0.05,
               n_queries=1_000_000, tc_span=0.027, random_sky=True)
 
 CFG3 = Config(name="cfg3_mixed_cubic", fs=2048.0, seg_len=256.0, f_low=10.0,
               modes=((2, 2),), sites=SITE_GEOCENTRE, psd_scale=1.0,
               inj_phys=(8.0, 1.4, 0.3, 0.0), inj_snr=20.0, match=0.97,
-              n_nodes=1500, q=60, eps=2.0, poly_degree=3, half_window=0.05,
+              n_nodes=1500, q=60, eps=3.0, poly_degree=3, half_window=0.05,
               n_queries=4_000_000, tc_span=0.047, random_sky=False)
 
 CFG5 = Config(name="cfg5_triangle_snr200", fs=4096.0, seg_len=2048.0, f_low=5.0,
@@ -179,6 +179,12 @@ class QueryDraw:
     def subset(self, idx) -> "QueryDraw":
         return QueryDraw(self.x[idx], self.ext[idx], self.dt[idx], self.dist_ratio[idx])
 
+    def near_nodes(self, nodes: np.ndarray, node_idx: np.ndarray, jitter: np.ndarray) -> "QueryDraw":
+        """Copy with x = nodes[node_idx] + jitter (rescaled into the unit ball)."""
+        x = nodes[node_idx] + jitter
+        x /= np.maximum(1.0, np.linalg.norm(x, axis=1) / 0.999999)[:, None]
+        return QueryDraw(x, self.ext, self.dt, self.dist_ratio)
+
     def __len__(self) -> int:
         return self.x.shape[0]
 
@@ -213,6 +219,14 @@ def queries(cfg: Config, n: int | None = None, seed: int | None = None,
     lo, hi = 0.5 ** 3, 2.0 ** 3
     dist_ratio = (lo + (hi - lo) * rng.uniform(0.0, 1.0, n)) ** (1.0 / 3.0)
     return QueryDraw(x=x, ext=ext, dt=dt, dist_ratio=dist_ratio)
+
+
+def node_jitter(n: int, n_nodes: int, sigma: float = 0.03, seed: int = 7):
+    """Seeded (node index, jitter) pairs for proposals near the interpolation
+    nodes, i.e. inside the physical part of the ellipsoid where a sampler's
+    proposals concentrate; resolve with QueryDraw.near_nodes(own_nodes, ...)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n_nodes, n), rng.standard_normal((n, 4)) * sigma
 
 
 def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,

@@ -1,0 +1,254 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Build parity: each side runs its own start-up from the same seeded deviates
+and configuration; basis-independent quantities are compared (time series at
+the nodes, overlaps, singular values, interpolated overlaps, ln L).  The SVD
+basis of both sides follows one phase convention (largest entry of each
+right singular vector real positive), so coefficient outputs are compared
+too, column by column, relative to the column's scale at the nodes.
+
+Tolerances: the FP64 path must agree within |d ln L| <= 1e-3 absolute; the
+interpolated outputs within 1e-6 of each column's node scale.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import likelihood as lk
+from oracle import startup as su
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cfg1": wl.CFG1,
+    "small_multi": wl.SMALL_MULTI,
+    "ragged_tail": wl.SMALL_MULTI.with_(name="ragged_tail", n_nodes=131, q=7, modes=wl.ALL_MODES, n_queries=1237),
+}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def gpu_eval(h, qd, t_trig, form=rbfl.FORM_FP64):
+    torch = _torch()
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, t_trig))).cuda()
+    n = len(qd)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.eval(p.data_ptr(), n, out.data_ptr(), form, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def gpu_interp(h, qd, t_trig, form=rbfl.FORM_FP64):
+    torch = _torch()
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, t_trig))).cuda()
+    n = len(qd)
+    K = h.sizes()["K"]
+    out = torch.empty((n, K), dtype=torch.float64, device="cuda")
+    h.interp(p.data_ptr(), n, out.data_ptr(), form, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+_cache = {}
+
+
+def column_scale(art):
+    """Scale of each interpolated column at the nodes, floored at 1e-9 of the
+    largest column: a column that vanishes in exact arithmetic (e.g. Im sigma
+    between two modes of equal |m|, whose templates share one phase) holds
+    only rounding noise on both sides."""
+    s = np.abs(art.node_values).max(axis=0)
+    return np.maximum(s, 1e-9 * s.max())
+
+
+def both(name):
+    if name not in _cache:
+        cfg = CASES[name]
+        print(f"[parity] building {name}", flush=True)
+        white = wl.white_noise(cfg)
+        inj = wl.injection_extrinsics(cfg)
+        art = su.startup(cfg, white, inj)
+        h = rbfl.Handle.from_config(cfg, white, inj)
+        _cache[name] = (cfg, art, h)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_frame_and_nodes(name):
+    cfg, art, h = both(name)
+    fr = h.frame()
+    assert np.allclose(fr["theta_c"], art.frame.theta_c, rtol=1e-13)
+    assert np.allclose(fr["semi"], art.frame.semi, rtol=1e-8)
+    assert np.allclose(fr["vecs"], art.frame.vecs, atol=1e-9)
+    assert np.allclose(h.nodes(), art.x_nodes, rtol=0, atol=1e-15)
+    assert np.allclose(h.node_phys(), art.phys_nodes, rtol=1e-8, atol=1e-9)
+    assert h.d_ref() == pytest.approx(art.d_ref, rel=1e-11)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_time_series_and_overlaps_at_nodes(name):
+    cfg, art, h = both(name)
+    z = h.z_nodes()
+    scale = np.abs(art.z_nodes).max()
+    assert np.abs(z - art.z_nodes).max() <= 1e-8 * scale
+    s_gpu = h.singular()
+    q = cfg.q
+    assert np.allclose(s_gpu[..., :q], art.singular[..., :q], rtol=1e-8)
+    nv = h.node_values()
+    col_scale = column_scale(art)
+    err = np.abs(nv - art.node_values).max(axis=0) / col_scale
+    assert err.max() <= 1e-7, f"worst column {int(err.argmax())}: {err.max():.3e}"
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_interpolated_outputs(name):
+    cfg, art, h = both(name)
+    qd = wl.queries(cfg, n=min(cfg.n_queries, 2000))
+    Yg = gpu_interp(h, qd, cfg.t_trig)
+    Yo = lk.rbf_eval(art, qd.x)
+    col_scale = column_scale(art)
+    err = np.abs(Yg - Yo).max(axis=0) / col_scale
+    print(f"[parity] {name}: max column-relative interpolant error {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-6
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lnl_parity_fp64(name):
+    cfg, art, h = both(name)
+    qd = wl.queries(cfg, n=min(cfg.n_queries, 3000))
+    lg = gpu_eval(h, qd, cfg.t_trig)
+    dE, ext, tc, dl = lk.query_params(art, qd)
+    lo = lk.meshfree_lnl(art, dE, ext, tc, dl)
+    fin_o, fin_g = np.isfinite(lo), np.isfinite(lg)
+    assert np.array_equal(fin_o, fin_g), f"domain flags differ at {np.where(fin_o != fin_g)[0][:10]}"
+    assert fin_o.sum() > 0
+    d = np.abs(lg[fin_o] - lo[fin_o])
+    print(f"[parity] {name}: {fin_o.sum()} valid, max |dlnL| {d.max():.3e}, median {np.median(d):.3e}",
+          flush=True)
+    assert d.max() <= 1e-3
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lnl_parity_near_nodes(name):
+    """Proposals next to the nodes: inside the physical part of the ellipsoid,
+    where a sampler's proposals concentrate."""
+    cfg, art, h = both(name)
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    lg = gpu_eval(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg))
+    assert fin.mean() > 0.3
+    d = np.abs(lg[fin] - lo[fin])
+    print(f"[parity] {name} near nodes: {fin.sum()} valid, max |dlnL| {d.max():.3e}", flush=True)
+    assert d.max() <= 1e-3
+
+
+@pytest.mark.timeout(1200)
+def test_cfg2_full_size_sampled():
+    """The 3-detector, 5-mode workload at full size (N = 800, q = 40, 1e6
+    proposals) in the benchmark's launch configuration; the oracle checks a
+    seeded sample of the outputs one by one."""
+    cfg = wl.CFG2
+    white = wl.white_noise(cfg)
+    inj = wl.injection_extrinsics(cfg)
+    print("[parity] cfg2: GPU start-up", flush=True)
+    h = rbfl.Handle.from_config(cfg, white, inj)
+    print("[parity] cfg2: oracle start-up", flush=True)
+    art = su.startup(cfg, white, inj)
+    n = cfg.n_queries
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    lg = gpu_eval(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig)
+    sample = np.random.default_rng(123).choice(n, 2000, replace=False)
+    sample.sort()
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(sample).near_nodes(art.x_nodes, idx[sample], jit[sample])))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg[sample]))
+    d = np.abs(lg[sample][fin] - lo[fin])
+    print(f"[parity] cfg2 full size: {fin.sum()} valid of 2000 sampled, max |dlnL| {d.max():.3e}", flush=True)
+    assert d.max() <= 1e-3
+    # properties that hold at any size: finite where inside, -inf elsewhere, never NaN
+    assert not np.isnan(lg).any()
+
+
+def test_edge_cases():
+    cfg, art, h = both("small_multi")
+    torch = _torch()
+    # empty batch is a no-op
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h.eval(out.data_ptr(), 0, out.data_ptr())
+    # outside the ellipsoid, outside the window, NaN input
+    qd = wl.queries(cfg, n=4)
+    qd.x[0] = [1.2, 0.0, 0.0, 0.0]
+    qd.dt[1] = 0.049
+    lg = gpu_eval(h, qd, cfg.t_trig)
+    assert lg[0] == -np.inf and lg[1] == -np.inf
+    p = rbfl.params_soa(h, qd, cfg.t_trig)
+    p[5, 2] = np.nan
+    pt = torch.from_numpy(np.ascontiguousarray(p)).cuda()
+    o = torch.empty(4, dtype=torch.float64, device="cuda")
+    h.eval(pt.data_ptr(), 4, o.data_ptr())
+    torch.cuda.synchronize()
+    assert math.isnan(o[2].item())
+    # an unprepared form is a state error, an unknown one an argument error
+    with pytest.raises(rbfl.RbflError) as e:
+        h.eval(pt.data_ptr(), 4, o.data_ptr(), rbfl.FORM_BF16)
+    assert e.value.code in (rbfl.E_STATE, rbfl.E_UNSUPPORTED)
+    with pytest.raises(rbfl.RbflError) as e:
+        h.eval(pt.data_ptr(), 4, o.data_ptr(), 17)
+    assert e.value.code == rbfl.E_INVALID_ARG
+
+
+def test_batch_larger_than_work_space():
+    """Batches above the work-space capacity are processed in chunks with the
+    same results as one pass."""
+    cfg, art, h = both("small_multi")
+    qd = wl.queries(cfg, n=70000, seed=9)
+    l1 = gpu_eval(h, qd, cfg.t_trig)
+    idx = np.arange(0, 70000, 997)
+    l2 = gpu_eval(h, qd.subset(idx), cfg.t_trig)
+    ok = np.isfinite(l2)
+    assert np.array_equal(np.isfinite(l1[idx]), ok)
+    assert np.abs(l1[idx][ok] - l2[ok]).max() <= 1e-12 * max(1.0, np.abs(l2[ok]).max())
+
+
+def test_zero_noise_injection_at_centre_node():
+    """Zero noise, injection at the centre node, full-rank basis, on-grid
+    t_c at a geocentre detector: ln L = rho^2 / 2."""
+    cfg = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=60, center_node=True)
+    inj = wl.injection_extrinsics(cfg)
+    h = rbfl.Handle.from_config(cfg, None, inj)
+    qd = wl.queries(cfg, n=1)
+    qd.x[:] = 0.0
+    qd.dt[:] = 0.0
+    qd.ext[0, 4] = inj[4]
+    qd.dist_ratio[:] = 1.0
+    lg = gpu_eval(h, qd, cfg.t_trig)
+    assert lg[0] == pytest.approx(cfg.inj_snr ** 2 / 2, rel=1e-9)
+
+
+def test_invalid_spec_errors():
+    cfg = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=10)
+    inj = wl.injection_extrinsics(cfg)
+    keep = []
+    spec = rbfl.spec_from_config(cfg, None, inj, keep=keep)
+    spec.q = 1000
+    with pytest.raises(rbfl.RbflError) as e:
+        rbfl.Handle.build(spec)
+    assert e.value.code == rbfl.E_INVALID_ARG
+    spec = rbfl.spec_from_config(cfg, None, inj, keep=keep)
+    spec.modes[0][1] = 3
+    with pytest.raises(rbfl.RbflError) as e:
+        rbfl.Handle.build(spec)
+    assert e.value.code == rbfl.E_INVALID_ARG
