@@ -174,9 +174,18 @@ enum rbfl_query_what {
   RBFL_Q_SINGULAR = 8,     /* double[n_det][n_modes][min(N,T)] singular values */
   RBFL_Q_COND = 9,         /* double[1]: 1-norm condition estimate of the RBF system */
   RBFL_Q_TIMING = 10,      /* double[8]: start-up stage wall times [s] */
-  RBFL_Q_Z_NODES = 11      /* double[n_det][n_modes][N][T][2] time series at the nodes */
+  RBFL_Q_Z_NODES = 11,     /* double[n_det][n_modes][N][T][2] time series at the nodes */
+  RBFL_Q_KERNEL_STATS = 12 /* double[6]: contraction ms, launches, proposals; epilogue ms, launches,
+                              proposals -- summed HIP-event durations since rbfl_profile was switched
+                              on (synchronises the recorded events; resets the sums) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
+
+/* Switches per-launch timing of the online kernels on (1) or off (0): with it
+ * on, rbfl_eval records a HIP event pair around every contraction and
+ * epilogue launch on the caller's stream; RBFL_Q_KERNEL_STATS reports the
+ * sums.  Not for use under graph capture. */
+int32_t rbfl_profile(rbfl_handle h, int32_t on);
 
 /* Releases the handle and its device memory (NULL is allowed). */
 int32_t rbfl_destroy(rbfl_handle h);

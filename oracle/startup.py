@@ -321,9 +321,12 @@ def gaussian_kernel(xa: np.ndarray, xb: np.ndarray, eps: float) -> np.ndarray:
     return np.exp(-(eps * eps) * d2)
 
 
-def rbf_solve(x: np.ndarray, F: np.ndarray, eps: float, degree: int):
+def rbf_solve(x: np.ndarray, F: np.ndarray, eps: float, degree: int, refine: int = 2):
     """Solve [[Phi, P], [P^T, 0]] W = [F; 0] by LU with partial pivoting.
     The side condition sum_i a_i p_j(x_i) = 0 fixes the polynomial part.
+    The solution is then refined `refine` times, W += A^{-1} (rhs - A W),
+    with the residual formed in extended precision (x87 80-bit long double),
+    so W is accurate to FP64 rounding rather than to cond(A) * eps.
     Returns (W [(N+M)][K], 1-norm condition estimate of the system)."""
     n = x.shape[0]
     P = poly_matrix(x, degree)
@@ -336,6 +339,11 @@ def rbf_solve(x: np.ndarray, F: np.ndarray, eps: float, degree: int):
     rhs[:n] = F
     lu = scipy.linalg.lu_factor(A)
     W = scipy.linalg.lu_solve(lu, rhs)
+    A_ext = A.astype(np.longdouble)
+    rhs_ext = rhs.astype(np.longdouble)
+    for _ in range(refine):
+        r = (rhs_ext - A_ext @ W.astype(np.longdouble)).astype(np.float64)
+        W = W + scipy.linalg.lu_solve(lu, r)
     cond = np.linalg.cond(A, 1)
     return W, cond
 

@@ -283,7 +283,46 @@ __global__ void k_transpose_weights(const double *__restrict__ R, int NM, int K,
   W[e] = (r < NM && c < K) ? R[(int64_t)c * NM + r] : 0.0;
 }
 
+// res[c][i] = rhs[c][i] - sum_j A[i][j] W[c][j] (column-major, A symmetric)
+// accumulated in double-double: each product split exactly with an FMA
+// (p + e = a w), each sum with the branch-free two-sum, rounded once at the
+// end.  Used for iterative refinement of the RBF solve.
+__global__ void k_residual_dd(const double *__restrict__ A, const double *__restrict__ rhs,
+                              const double *__restrict__ W, int NM, double *__restrict__ res) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= NM) return;
+  const double *w = W + (int64_t)c * NM;
+  double hi = rhs[(int64_t)c * NM + i], lo = 0.0;
+  for (int j = 0; j < NM; ++j) {
+    const double a = A[(int64_t)j * NM + i];
+    const double p = -a * w[j];
+    const double e = fma(-a, w[j], -p);
+    const double t = hi + p;
+    const double bp = t - hi;
+    lo += ((hi - (t - bp)) + (p - bp)) + e;
+    hi = t;
+  }
+  res[(int64_t)c * NM + i] = hi + lo;
+}
+
+__global__ void k_add(double *__restrict__ y, const double *__restrict__ x, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) y[e] += x[e];
+}
+
 }  // namespace
+
+void launch_residual_dd(const double *A, const double *rhs, const double *W, int NM, int K, double *res,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_dd, dim3(grid1(NM, kBlock), K), dim3(kBlock), 0, s, A, rhs, W, NM, res);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_add(double *y, const double *x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add, dim3(grid1(n, kBlock)), dim3(kBlock), 0, s, y, x, n);
+  RBFL_HIP(hipGetLastError());
+}
 
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
                       double df, double inv_dref_s, double2 *out, hipStream_t s) {

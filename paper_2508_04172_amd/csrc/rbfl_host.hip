@@ -793,6 +793,13 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
     for (int i = 0; i < NM; ++i) s += fabs(Ah[(size_t)j * NM + i]);
     anorm = std::max(anorm, s);
   }
+  // unfactored copies of the system and the right-hand side for refinement
+  DevBuf<double> d_A0, d_F, d_res;
+  d_A0.alloc((size_t)NM * NM);
+  d_F.alloc((size_t)c.K * NM);
+  d_res.alloc((size_t)c.K * NM);
+  RBFL_HIP(hipMemcpyAsync(d_A0.p, d_A2.p, sizeof(double) * NM * NM, hipMemcpyDeviceToDevice, stream));
+  RBFL_HIP(hipMemcpyAsync(d_F.p, d_R.p, sizeof(double) * c.K * NM, hipMemcpyDeviceToDevice, stream));
   DevBuf<int> d_ipiv;
   d_ipiv.alloc(NM);
   blas_check(rocsolver_dgetrf(bh.h, NM, NM, d_A2.p, NM, d_ipiv.p, d_info.p), "rocsolver_dgetrf");
@@ -802,6 +809,17 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   if (info != 0) throw Error(RBFL_E_NUMERICAL, "RBF system is singular (zero pivot " + std::to_string(info) + ")");
   blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_R.p, NM),
              "rocsolver_dgetrs");
+  // two steps of iterative refinement with double-double residuals: LU alone
+  // leaves a forward error ~ cond(A) * eps; refinement takes W to FP64 rounding
+  for (int it = 0; it < 2; ++it) {
+    launch_residual_dd(d_A0.p, d_F.p, d_R.p, NM, c.K, d_res.p, stream);
+    blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_res.p, NM),
+               "rocsolver_dgetrs");
+    launch_add(d_R.p, d_res.p, (int64_t)c.K * NM, stream);
+  }
+  d_A0.reset();
+  d_F.reset();
+  d_res.reset();
   // Hager-Higham estimate of ||A^{-1}||_1 from solves with A and A^T
   {
     DevBuf<double> d_v;
@@ -902,6 +920,25 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
   for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
     const int64_t nb = std::min(c.cap, n - b0);
+    if (c.profile) {
+      Ctx::Timed t0{}, t1{};
+      RBFL_HIP(hipEventCreate(&t0.a));
+      RBFL_HIP(hipEventCreate(&t0.b));
+      RBFL_HIP(hipEventCreate(&t1.a));
+      RBFL_HIP(hipEventCreate(&t1.b));
+      t0.kind = 0;
+      t1.kind = 1;
+      t0.n = t1.n = nb;
+      RBFL_HIP(hipEventRecord(t0.a, s));
+      contract(c, params, n, b0, nb, form, s);
+      RBFL_HIP(hipEventRecord(t0.b, s));
+      RBFL_HIP(hipEventRecord(t1.a, s));
+      launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
+      RBFL_HIP(hipEventRecord(t1.b, s));
+      c.timed.push_back(t0);
+      c.timed.push_back(t1);
+      continue;
+    }
     contract(c, params, n, b0, nb, form, s);
     launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
   }
@@ -1016,6 +1053,22 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       RBFL_HIP(hipMemcpy(out, c.z_nodes.p, need, hipMemcpyDeviceToHost));
       return;
     }
+    case RBFL_Q_KERNEL_STATS: {
+      double v[6] = {0, 0, 0, 0, 0, 0};
+      for (auto &t : c.timed) {
+        RBFL_HIP(hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        RBFL_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        v[3 * t.kind] += ms;
+        v[3 * t.kind + 1] += 1.0;
+        v[3 * t.kind + 2] += (double)t.n;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+      }
+      c.timed.clear();
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
     default:
       throw Error(RBFL_E_INVALID_ARG, "unknown query");
   }
@@ -1095,6 +1148,13 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
     rbfl::query(h->c, what, out, bytes);
+  });
+}
+
+int32_t rbfl_profile(rbfl_handle h, int32_t on) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    h->c.profile = on != 0;
   });
 }
 

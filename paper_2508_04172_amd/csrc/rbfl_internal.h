@@ -99,6 +99,20 @@ struct Ctx {
   DevBuf<double> Y;            // [cap][Kp]
   int64_t cap = 0;
   EvalConsts host_consts;
+  // optional per-launch timing (rbfl_profile)
+  bool profile = false;
+  struct Timed {
+    hipEvent_t a, b;
+    int kind;          // 0 contraction, 1 epilogue
+    int64_t n;         // proposals in the launch
+  };
+  std::vector<Timed> timed;
+  ~Ctx() {
+    for (auto &t : timed) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+  }
 };
 
 // ---- start-up kernels (build_kernels.hip) ----
@@ -115,6 +129,9 @@ void launch_assemble_rhs(const double2 *C, const double2 *sig, const int4 *colde
                          int q, int n_modes, double *R, hipStream_t s);
 void launch_assemble_system(const double *x, int N, int M, const int *poly_idx, double eps2, double *A,
                             hipStream_t s);
+void launch_residual_dd(const double *A, const double *rhs, const double *W, int NM, int K, double *res,
+                        hipStream_t s);
+void launch_add(double *y, const double *x, int64_t n, hipStream_t s);
 void launch_transpose_weights(const double *R, int NM, int K, int rows, int Kp, double *W, hipStream_t s);
 
 // ---- online kernels (eval_kernels.hip) ----

@@ -26,10 +26,10 @@ FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT = range(4)
 FLAG_CENTER_NODE = 0x1
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES = range(12)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS = range(13)
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
-            "rbfl_query", "rbfl_destroy")
+            "rbfl_query", "rbfl_profile", "rbfl_destroy")
 
 
 class BuildSpec(C.Structure):
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_reserve.argtypes = [C.c_void_p, C.c_int64]
     lib.rbfl_query.restype = C.c_int32
     lib.rbfl_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.rbfl_profile.restype = C.c_int32
+    lib.rbfl_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_destroy.restype = C.c_int32
     lib.rbfl_destroy.argtypes = [C.c_void_p]
     _lib = lib
@@ -260,6 +262,14 @@ class Handle:
 
     def timing(self) -> np.ndarray:
         return self._query(Q_TIMING, 8)
+
+    def profile(self, on: bool):
+        _check(load().rbfl_profile(self._h, 1 if on else 0))
+
+    def kernel_stats(self) -> dict:
+        v = self._query(Q_KERNEL_STATS, 6)
+        return {"contract_ms": v[0], "contract_launches": int(v[1]), "contract_n": int(v[2]),
+                "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5])}
 
 
 def params_soa(handle: Handle, qd, t_trig: float) -> np.ndarray:
