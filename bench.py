@@ -39,7 +39,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--check-sample", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -77,6 +77,12 @@ def main():
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     h.reserve(65536)
+    tune = {}
+    for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32)):
+        if form != rbfl.FORM_FP64:
+            h.prepare(form)
+        tune[name] = h.autotune(params.data_ptr(), n, form, sp)
+        log(f"autotune {name}: variant {tune[name]['variant']}, ms per launch {tune[name]['ms']}")
 
     def run_form(form, steps, warmup):
         for _ in range(warmup):
@@ -109,7 +115,6 @@ def main():
                       "epilogue_ms_per_launch": ks["epilogue_ms"] / max(1, ks["epilogue_launches"])}}
     outs = {"fp64": l64}
     for name, form in (("fp32", rbfl.FORM_FP32),):
-        h.prepare(form)
         w2, ks2, lf = run_form(form, max(3, args.steps // 2), 1)
         v2 = n * max(3, args.steps // 2) / w2
         c2 = ks2["contract_ms"] / max(1, ks2["contract_launches"])
@@ -140,6 +145,7 @@ def main():
                      "traffic": None, "flop_per_launch": flop_per_query * per_launch_n,
                      "launch_ms": contract_ms},
         "forms": forms,
+        "autotune": tune,
     }
 
     # accuracy of every form against the FP64 oracle on a seeded sample, and

@@ -76,7 +76,7 @@ __device__ __forceinline__ float basis_row_fp32(int row, int N, int NM, const fl
 // outputs.  MFMA f64 16x16x4 operand layout (measured on gfx950): lane l
 // holds A[l%16][l/16] and B[l/16][l%16]; accumulator element i of lane l is
 // D[l/16 + 4i][l%16].
-template <int RT, int CT>
+template <int RT, int CT, int CH>
 __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__restrict__ cp,
                                                             const double *__restrict__ params, int64_t ld,
                                                             int64_t b0, int64_t nb,
@@ -84,8 +84,9 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
                                                             const double *__restrict__ W, double *__restrict__ Y) {
   constexpr int CW = CT * 16;
   constexpr int QT = kWaves * RT * 16;
-  __shared__ double Ws[kRowChunk][CW + kLdsPad];
-  __shared__ double Xs[kRowChunk][4];
+  static_assert(kRowChunk % CH == 0, "row chunk");
+  __shared__ double Ws[CH][CW + kLdsPad];
+  __shared__ double Xs[CH][4];
   __shared__ int poly[kMaxPoly][3];
   const EvalConsts &c = *cp;
   const int lane = threadIdx.x & 63;
@@ -111,16 +112,16 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int kk = lane >> 4;
-  for (int r0 = 0; r0 < rows; r0 += kRowChunk) {
+  for (int r0 = 0; r0 < rows; r0 += CH) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kRowChunk * CW; e += kThreads) {
+    for (int e = threadIdx.x; e < CH * CW; e += kThreads) {
       const int r = e / CW, cc = e % CW;
       Ws[r][cc] = W[(int64_t)(r0 + r) * Kp + col0 + cc];
     }
-    for (int e = threadIdx.x; e < kRowChunk * 4; e += kThreads) Xs[e >> 2][e & 3] = nodes[(int64_t)r0 * 4 + e];
+    for (int e = threadIdx.x; e < CH * 4; e += kThreads) Xs[e >> 2][e & 3] = nodes[(int64_t)r0 * 4 + e];
     __syncthreads();
 #pragma unroll 2
-    for (int s = 0; s < kRowChunk / 4; ++s) {
+    for (int s = 0; s < CH / 4; ++s) {
       const int rr = 4 * s + kk;
       double a[RT];
 #pragma unroll
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
 // lane l is D[4(l/16) + i][l%16]).  With split != 0
 // the weights are W32 + W32lo (two FP32 products per step), which removes the
 // weight rounding but not the FP32 rounding of the basis rows or of the sums.
-template <int RT, int CT>
+template <int RT, int CT, int CH>
 __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__restrict__ cp,
                                                             const double *__restrict__ params, int64_t ld,
                                                             int64_t b0, int64_t nb,
@@ -161,9 +162,9 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
                                                             double *__restrict__ Y) {
   constexpr int CW = CT * 16;
   constexpr int QT = kWaves * RT * 16;
-  __shared__ float Ws[kRowChunk][CW + kLdsPad];
-  __shared__ float Wl[kRowChunk][CW + kLdsPad];
-  __shared__ float Xs[kRowChunk][4];
+  __shared__ float Ws[CH][CW + kLdsPad];
+  __shared__ float Wl[CH][CW + kLdsPad];
+  __shared__ float Xs[CH][4];
   __shared__ int poly[kMaxPoly][3];
   const EvalConsts &c = *cp;
   const int lane = threadIdx.x & 63;
@@ -186,18 +187,18 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   const int kk = lane >> 4;
-  for (int r0 = 0; r0 < rows; r0 += kRowChunk) {
+  for (int r0 = 0; r0 < rows; r0 += CH) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kRowChunk * CW; e += kThreads) {
+    for (int e = threadIdx.x; e < CH * CW; e += kThreads) {
       const int r = e / CW, cc = e % CW;
       Ws[r][cc] = W[(int64_t)(r0 + r) * Kp + col0 + cc];
       if (split) Wl[r][cc] = Wlo[(int64_t)(r0 + r) * Kp + col0 + cc];
     }
-    for (int e = threadIdx.x; e < kRowChunk * 4; e += kThreads)
+    for (int e = threadIdx.x; e < CH * 4; e += kThreads)
       Xs[e >> 2][e & 3] = (float)nodes[(int64_t)r0 * 4 + e];
     __syncthreads();
 #pragma unroll 2
-    for (int s = 0; s < kRowChunk / 4; ++s) {
+    for (int s = 0; s < CH / 4; ++s) {
       const int rr = 4 * s + kk;
       float a[RT];
 #pragma unroll
@@ -229,26 +230,15 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-// Neumaier-compensated accumulation.
-struct Comp {
-  double s = 0.0, c = 0.0;
-  __device__ void add(double v) {
-    const double t = s + v;
-    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-    s = t;
-  }
-  __device__ double value() const { return s + c; }
-};
-
-// One wave per proposal.  Lanes split the q basis coefficients of each
-// (detector, mode); the gathered basis rows are contiguous in the
-// coefficient index, so the 10-sample stencil loads are coalesced.
+// One wave per proposal.  The wave's lanes are split over the (detector,
+// mode) pairs -- G = 64 / (n_det * n_modes) lanes per pair -- and each pair's
+// lanes stride over its q basis coefficients, so every pair's reconstruction
+// runs at once: lane g of pair (k, a) accumulates sum_i C_i sum_s w_s
+// B[n0-4+s][i] over i = g, g+G, ... (the basis rows are contiguous in i, so
+// the G lanes of a pair read adjacent entries).  Each lane evaluates only its
+// own detector's response and arrival time and its own mode's harmonics.
+// Partial sums meet in the pair's first lane by shuffles; that lane forms
+// Re(conj(A) z), the detector's first lane the overlap term, lane 0 the sum.
 __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restrict__ cp,
                                                        const double *__restrict__ params, int64_t ld, int64_t b0,
                                                        int64_t nb, const double *__restrict__ Y,
@@ -256,8 +246,17 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
   const EvalConsts &c = *cp;
   const int lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (b >= nb) return;
+  if (b >= nb) return;   // whole wave leaves together
   const int64_t g = b0 + b;
+  const int n_modes = c.n_modes, q = c.q, T = c.T;
+  const int P = c.n_det * n_modes;
+  const int G = 64 / P;
+  const int pair = lane / G;
+  const int gl = lane - pair * G;
+  const bool active = pair < P;
+  const int k = active ? pair / n_modes : 0;
+  const int a = active ? pair - k * n_modes : 0;
+
   double p[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) p[i] = params[i * ld + g];
@@ -275,88 +274,111 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
     r2 += x * x;
   }
   bool valid = r2 <= 1.0;
-  double th[4], phys[4];
-  for (int i = 0; i < 4; ++i) {
-    double t = c.theta_c[i];
-    for (int j = 0; j < 4; ++j) t += c.V[4 * i + j] * p[j];
-    th[i] = t;
+  {
+    double th[4], phys[4];
+    for (int i = 0; i < 4; ++i) {
+      double t = c.theta_c[i];
+      for (int j = 0; j < 4; ++j) t += c.V[4 * i + j] * p[j];
+      th[i] = t;
+    }
+    valid = valid && theta_to_phys(th, c.f0, c.chi_max, phys);
   }
-  valid = valid && theta_to_phys(th, c.f0, c.chi_max, phys);
   const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
   const double rr = c.d_ref / dl;
-  const int n_modes = c.n_modes, q = c.q, T = c.T;
-  // harmonics at (iota, phi)
+
+  // a4: this lane's detector -- response, arrival time, stencil and weights
+  double fp, fc, dt;
+  detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
+  const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
+  const double fl = floor(s);
+  const bool in_window = fl >= 4.0 && fl <= (double)(T - 6);
+  valid = valid && __all(!active || in_window);
+  if (!valid) {
+    if (lane == 0) lnl[g] = -__builtin_huge_val();
+    return;
+  }
+  const double f = s - fl;
+  const int n0 = (int)fl;
+  double w[kSplineTaps];
+#pragma unroll
+  for (int t = 0; t < kSplineTaps; ++t)
+    w[t] = c.spline[t][0] + f * (c.spline[t][1] + f * (c.spline[t][2] + f * c.spline[t][3]));
+  // a6: A_{k,lm} = [(F+ + iFx) Y_{l,-m} + (-1)^l (F+ - iFx) conj(Y_{lm})] / 2
   double ch, sh;
   sincos(0.5 * iota, &sh, &ch);
-  double yn_r[RBFL_MAX_MODES], yn_i[RBFL_MAX_MODES], yp_r[RBFL_MAX_MODES], yp_i[RBFL_MAX_MODES];
-  for (int a = 0; a < n_modes; ++a) {
-    eval_ylm(c.ylm_neg[a], ch, sh, phi, &yn_r[a], &yn_i[a]);
-    eval_ylm(c.ylm_pos[a], ch, sh, phi, &yp_r[a], &yp_i[a]);
-  }
+  double ynr, yni, ypr, ypi;
+  eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr, &yni);
+  eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr, &ypi);
+  const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
+  const double ar = 0.5 * ((fp * ynr - fc * yni) + sg * (fp * ypr - fc * ypi));
+  const double ai = 0.5 * ((fp * yni + fc * ynr) + sg * (-fp * ypi - fc * ypr));
+  // a5: partial reconstruction of z_{k,a} over this lane's coefficients
   const double *y = Y + b * c.Kp;
-  Comp total;
-  for (int k = 0; k < c.n_det && valid; ++k) {
-    double fp, fc, dt;
-    detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
-    const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
-    const double fl = floor(s);
-    const double f = s - fl;
-    if (!(fl >= 4.0 && fl <= (double)(T - 6))) {
-      valid = false;
-      break;
-    }
-    const int n0 = (int)fl;
-    double w[kSplineTaps];
+  double zr = 0.0, zi = 0.0;
+  if (active) {
+    const int o = c.coef_off[k][a];
+    const double2 *base = basis + ((int64_t)(k * n_modes + a) * T + (n0 - 4)) * q;
+    for (int i = gl; i < q; i += G) {
+      const double cr = y[o + 2 * i], ci = y[o + 2 * i + 1];
+      double br = 0.0, bi = 0.0;
 #pragma unroll
-    for (int t = 0; t < kSplineTaps; ++t)
-      w[t] = c.spline[t][0] + f * (c.spline[t][1] + f * (c.spline[t][2] + f * c.spline[t][3]));
-    // A_{k,lm} = [(F+ + iFx) Y_{l,-m} + (-1)^l (F+ - iFx) conj(Y_{lm})] / 2
-    double ar[RBFL_MAX_MODES], ai[RBFL_MAX_MODES];
-    for (int a = 0; a < n_modes; ++a) {
-      const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
-      ar[a] = 0.5 * ((fp * yn_r[a] - fc * yn_i[a]) + sg * (fp * yp_r[a] - fc * yp_i[a]));
-      ai[a] = 0.5 * ((fp * yn_i[a] + fc * yn_r[a]) + sg * (-fp * yp_i[a] - fc * yp_r[a]));
-    }
-    Comp zt;
-    for (int a = 0; a < n_modes; ++a) {
-      const int o = c.coef_off[k][a];
-      const double2 *base = basis + ((int64_t)(k * n_modes + a) * T + (n0 - 4)) * q;
-      double zr = 0.0, zi = 0.0;
-      for (int i = lane; i < q; i += 64) {
-        const double cr = y[o + 2 * i], ci = y[o + 2 * i + 1];
-        double br = 0.0, bi = 0.0;
-#pragma unroll
-        for (int t = 0; t < kSplineTaps; ++t) {
-          const double2 v = base[t * q + i];
-          br = fma(w[t], v.x, br);
-          bi = fma(w[t], v.y, bi);
-        }
-        zr += cr * br - ci * bi;
-        zi += cr * bi + ci * br;
+      for (int t = 0; t < kSplineTaps; ++t) {
+        const double2 v = base[t * q + i];
+        br = fma(w[t], v.x, br);
+        bi = fma(w[t], v.y, bi);
       }
-      zr = wave_sum(zr);
-      zi = wave_sum(zi);
-      zt.add(ar[a] * zr + ai[a] * zi);   // Re(conj(A) z)
+      zr += cr * br - ci * bi;
+      zi += cr * bi + ci * br;
     }
-    // sigma term: sum_a |A_a|^2 s_aa + 2 sum_{a<b} Re(conj(A_a) A_b s_ab)
+  }
+  // combine the G partials of each pair in its first lane (fixed order)
+  const int lead = pair * G;
+  double tr = 0.0, ti = 0.0;
+  for (int j = 0; j < G; ++j) {
+    tr += __shfl(zr, lead + j, 64);
+    ti += __shfl(zi, lead + j, 64);
+  }
+  const double zterm = ar * tr + ai * ti;   // Re(conj(A) z), valid in pair leaders
+  // overlap term of detector k in its first pair's leader: needs every A_{k,b}
+  const int det_lead = k * n_modes * G;
+  double st_s = 0.0, st_c = 0.0, zt_s = 0.0, zt_c = 0.0;
+  {
+    double Ar[RBFL_MAX_MODES], Ai[RBFL_MAX_MODES], Zt[RBFL_MAX_MODES];
+    for (int m = 0; m < n_modes; ++m) {
+      const int src = det_lead + m * G;
+      Ar[m] = __shfl(ar, src, 64);
+      Ai[m] = __shfl(ai, src, 64);
+      Zt[m] = __shfl(zterm, src, 64);
+    }
     const int so = c.sig_off[k];
-    Comp st;
-    for (int a = 0; a < n_modes; ++a) st.add((ar[a] * ar[a] + ai[a] * ai[a]) * y[so + a]);
+    auto add = [](double &sum, double &comp, double v) {
+      const double t = sum + v;
+      comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
+      sum = t;
+    };
+    for (int m = 0; m < n_modes; ++m) {
+      add(zt_s, zt_c, Zt[m]);
+      add(st_s, st_c, (Ar[m] * Ar[m] + Ai[m] * Ai[m]) * y[so + m]);
+    }
     int pidx = so + n_modes;
-    for (int a = 0; a < n_modes; ++a) {
-      for (int bb = a + 1; bb < n_modes; ++bb) {
+    for (int m = 0; m < n_modes; ++m)
+      for (int mm = m + 1; mm < n_modes; ++mm) {
         const double sr = y[pidx], si = y[pidx + 1];
         pidx += 2;
-        // conj(A_a) A_b = (ar_a ar_b + ai_a ai_b) + i (ar_a ai_b - ai_a ar_b)
-        const double pr = ar[a] * ar[bb] + ai[a] * ai[bb];
-        const double pi = ar[a] * ai[bb] - ai[a] * ar[bb];
-        st.add(2.0 * (pr * sr - pi * si));
+        const double pr = Ar[m] * Ar[mm] + Ai[m] * Ai[mm];
+        const double pi = Ar[m] * Ai[mm] - Ai[m] * Ar[mm];
+        add(st_s, st_c, 2.0 * (pr * sr - pi * si));
       }
-    }
-    total.add(rr * zt.value());
-    total.add(-0.5 * rr * rr * st.value());
   }
-  if (lane == 0) lnl[g] = valid ? total.value() : -__builtin_huge_val();
+  const double term = rr * (zt_s + zt_c) - 0.5 * rr * rr * (st_s + st_c);   // valid in detector leaders
+  double tot = 0.0, comp = 0.0;
+  for (int kk = 0; kk < c.n_det; ++kk) {
+    const double v = __shfl(term, kk * n_modes * G, 64);
+    const double t = tot + v;
+    comp += fabs(tot) >= fabs(v) ? (tot - t) + v : (v - t) + tot;
+    tot = t;
+  }
+  if (lane == 0) lnl[g] = tot + comp;
 }
 
 __global__ void k_convert_weights(const double *__restrict__ W, size_t n, float *__restrict__ hi,
@@ -377,25 +399,56 @@ __global__ void k_convert_weights(const double *__restrict__ W, size_t n, float 
 
 }  // namespace
 
-void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
-                          int64_t nb, const double *nodes, const double *W, double *Y, hipStream_t s) {
-  constexpr int RT = 2, CT = 4;
-  static_assert(CT * 16 == kColTile, "column tile");
+template <int RT, int CT, int CH>
+static void launch_fp64_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
+                                int64_t b0, int64_t nb, const double *nodes, const double *W, double *Y,
+                                hipStream_t s) {
+  static_assert(kColTile % (CT * 16) == 0, "K is padded to a multiple of every column tile");
   const int64_t qt = kWaves * RT * 16;
-  dim3 grid((unsigned)((nb + qt - 1) / qt), (unsigned)(hc.Kp / (CT * 16)));
-  hipLaunchKernelGGL((k_contract_fp64<RT, CT>), grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, nodes, W, Y);
+  const int cw = CT * 16;
+  dim3 grid((unsigned)((nb + qt - 1) / qt), (unsigned)((hc.Kp + cw - 1) / cw));
+  hipLaunchKernelGGL((k_contract_fp64<RT, CT, CH>), grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, nodes, W, Y);
+  RBFL_HIP(hipGetLastError());
+}
+
+int contract_variants(int form) { return form == RBFL_FORM_FP64 ? 4 : 2; }
+
+const char *contract_variant_name(int form, int v) {
+  static const char *f64[] = {"fp64 rt2 ct4 ch64", "fp64 rt2 ct8 ch32", "fp64 rt4 ct4 ch32", "fp64 rt1 ct8 ch64"};
+  static const char *f32[] = {"fp32 rt2 ct4 ch64", "fp32 rt2 ct8 ch32"};
+  return form == RBFL_FORM_FP64 ? f64[v] : f32[v];
+}
+
+void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                          int64_t nb, const double *nodes, const double *W, double *Y, hipStream_t s, int variant) {
+  switch (variant) {
+    case 1: launch_fp64_variant<2, 8, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    case 2: launch_fp64_variant<4, 4, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    case 3: launch_fp64_variant<1, 8, 64>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    default: launch_fp64_variant<2, 4, 64>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
+  }
+}
+
+template <int RT, int CT, int CH>
+static void launch_fp32_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
+                                int64_t b0, int64_t nb, const double *nodes, const float *W, const float *Wlo,
+                                int split, double *Y, hipStream_t s) {
+  static_assert(kColTile % (CT * 16) == 0, "K is padded to a multiple of every column tile");
+  const int64_t qt = kWaves * RT * 16;
+  const int cw = CT * 16;
+  dim3 grid((unsigned)((nb + qt - 1) / qt), (unsigned)((hc.Kp + cw - 1) / cw));
+  hipLaunchKernelGGL((k_contract_fp32<RT, CT, CH>), grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, nodes, W,
+                     Wlo, split, Y);
   RBFL_HIP(hipGetLastError());
 }
 
 void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                           int64_t nb, const double *nodes, const float *W, const float *Wlo, int split, double *Y,
-                          hipStream_t s) {
-  constexpr int RT = 2, CT = 4;
-  const int64_t qt = kWaves * RT * 16;
-  dim3 grid((unsigned)((nb + qt - 1) / qt), (unsigned)(hc.Kp / (CT * 16)));
-  hipLaunchKernelGGL((k_contract_fp32<RT, CT>), grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, nodes, W, Wlo,
-                     split, Y);
-  RBFL_HIP(hipGetLastError());
+                          hipStream_t s, int variant) {
+  if (variant == 1)
+    launch_fp32_variant<2, 8, 32>(c, hc, params, ld, b0, nb, nodes, W, Wlo, split, Y, s);
+  else
+    launch_fp32_variant<2, 4, 64>(c, hc, params, ld, b0, nb, nodes, W, Wlo, split, Y, s);
 }
 
 void launch_contract_bf16(const EvalConsts *, const EvalConsts &, const double *, int64_t, int64_t, int64_t,

@@ -947,13 +947,16 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
 static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s) {
   switch (form) {
     case RBFL_FORM_FP64:
-      launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s);
+      launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s,
+                           c.variant[form]);
       break;
     case RBFL_FORM_FP32:
-      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, nullptr, 0, c.Y.p, s);
+      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, nullptr, 0, c.Y.p, s,
+                           c.variant[form]);
       break;
     case RBFL_FORM_SPLIT:
-      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.W32lo.p, 1, c.Y.p, s);
+      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.W32lo.p, 1, c.Y.p, s,
+                           c.variant[form]);
       break;
     default:
       launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W16.p, c.Y.p, s);
@@ -973,6 +976,48 @@ static void interp(Ctx &c, const double *params, int64_t n, double *out, int for
     RBFL_HIP(hipMemcpy2DAsync(out + b0 * c.K, sizeof(double) * c.K, c.Y.p, sizeof(double) * c.Kp,
                               sizeof(double) * c.K, nb, hipMemcpyDeviceToDevice, s));
   }
+}
+
+// Times every contraction tile variant of `form` on the first min(n, work
+// capacity) proposals of `params` (HIP events, median of 3 after a warm-up)
+// and keeps the fastest for later rbfl_eval/rbfl_interp calls.
+static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStream_t s) {
+  require(params != nullptr && n >= 1, "autotune needs proposals");
+  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+  if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
+  const int64_t nb = std::min(c.cap, n);
+  const int nv = contract_variants(form == RBFL_FORM_SPLIT ? RBFL_FORM_FP32 : form);
+  hipEvent_t e0, e1;
+  RBFL_HIP(hipEventCreate(&e0));
+  RBFL_HIP(hipEventCreate(&e1));
+  int best = 0;
+  double best_ms = 1e300;
+  const int saved = c.variant[form];
+  for (int v = 0; v < nv && v < 8; ++v) {
+    c.variant[form] = v;
+    contract(c, params, n, 0, nb, form, s);   // warm-up
+    double t[3];
+    for (int r = 0; r < 3; ++r) {
+      RBFL_HIP(hipEventRecord(e0, s));
+      contract(c, params, n, 0, nb, form, s);
+      RBFL_HIP(hipEventRecord(e1, s));
+      RBFL_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      t[r] = ms;
+    }
+    std::sort(t, t + 3);
+    c.tune_ms[form][v] = t[1];
+    if (t[1] < best_ms) {
+      best_ms = t[1];
+      best = v;
+    }
+  }
+  (void)saved;
+  c.variant[form] = best;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 static void prepare(Ctx &c, int form) {
@@ -1051,6 +1096,16 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       const size_t need = sizeof(double2) * c.z_nodes.n;
       require(out != nullptr && bytes >= need, "output buffer too small");
       RBFL_HIP(hipMemcpy(out, c.z_nodes.p, need, hipMemcpyDeviceToHost));
+      return;
+    }
+    case RBFL_Q_TUNE: {
+      // per form: chosen variant, then 8 timings [ms] (0 = not timed)
+      double v[4 * 9];
+      for (int f = 0; f < 4; ++f) {
+        v[9 * f] = c.variant[f];
+        for (int i = 0; i < 8; ++i) v[9 * f + 1 + i] = c.tune_ms[f][i];
+      }
+      copy_out(out, bytes, v, sizeof(v));
       return;
     }
     case RBFL_Q_KERNEL_STATS: {
@@ -1148,6 +1203,13 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
     rbfl::query(h->c, what, out, bytes);
+  });
+}
+
+int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::autotune(h->c, params, n, form, reinterpret_cast<hipStream_t>(stream));
   });
 }
 

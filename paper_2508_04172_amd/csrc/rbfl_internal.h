@@ -16,7 +16,7 @@ namespace rbfl {
 constexpr int kMaxPoly = 35;     // monomials of degree <= 3 in 4 variables
 constexpr int kSplineTaps = 10;  // samples in the sub-sample spline stencil
 constexpr int kRowChunk = 64;    // node rows per contraction chunk (W rows padded to this)
-constexpr int kColTile = 64;     // interpolated outputs per contraction column tile (K padded to this)
+constexpr int kColTile = 128;    // widest contraction column tile; K is padded to a multiple of it
 
 // Error carrying an rbfl_status through the host code; converted at the ABI.
 struct Error : std::runtime_error {
@@ -95,6 +95,8 @@ struct Ctx {
   DevBuf<float> W32lo;         // [rows][Kp] low part of the FP32 split
   DevBuf<uint16_t> W16;        // [rows][Kp] bf16
   bool prepared[4] = {true, false, false, false};
+  int variant[4] = {0, 0, 0, 0};   // contraction tile variant per form (rbfl_autotune)
+  double tune_ms[4][8] = {};       // last autotune timings per variant
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   int64_t cap = 0;
@@ -135,12 +137,14 @@ void launch_add(double *y, const double *x, int64_t n, hipStream_t s);
 void launch_transpose_weights(const double *R, int NM, int K, int rows, int Kp, double *W, hipStream_t s);
 
 // ---- online kernels (eval_kernels.hip) ----
+int contract_variants(int form);
+const char *contract_variant_name(int form, int variant);
 void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const double *W, double *Y,
-                          hipStream_t s);
+                          hipStream_t s, int variant);
 void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const float *W, const float *Wlo,
-                          int split, double *Y, hipStream_t s);
+                          int split, double *Y, hipStream_t s, int variant);
 void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const uint16_t *W, double *Y,
                           hipStream_t s);

@@ -26,10 +26,10 @@ FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT = range(4)
 FLAG_CENTER_NODE = 0x1
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS = range(13)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE = range(14)
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
-            "rbfl_query", "rbfl_profile", "rbfl_destroy")
+            "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_destroy")
 
 
 class BuildSpec(C.Structure):
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_reserve.argtypes = [C.c_void_p, C.c_int64]
     lib.rbfl_query.restype = C.c_int32
     lib.rbfl_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.rbfl_autotune.restype = C.c_int32
+    lib.rbfl_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
     lib.rbfl_profile.restype = C.c_int32
     lib.rbfl_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_destroy.restype = C.c_int32
@@ -262,6 +264,11 @@ class Handle:
 
     def timing(self) -> np.ndarray:
         return self._query(Q_TIMING, 8)
+
+    def autotune(self, params_ptr: int, n: int, form: int = FORM_FP64, stream: int = 0) -> dict:
+        _check(load().rbfl_autotune(self._h, C.c_void_p(params_ptr), n, form, C.c_void_p(stream)))
+        v = self._query(Q_TUNE, 36).reshape(4, 9)
+        return {"variant": int(v[form, 0]), "ms": [float(x) for x in v[form, 1:] if x > 0]}
 
     def profile(self, on: bool):
         _check(load().rbfl_profile(self._h, 1 if on else 0))
