@@ -75,7 +75,9 @@ __device__ __forceinline__ float basis_row_fp32(int row, int N, int NM, const fl
 // by CT x 16 outputs; the block covers kWaves*RT*16 proposals and CT*16
 // outputs.  MFMA f64 16x16x4 operand layout (measured on gfx950): lane l
 // holds A[l%16][l/16] and B[l/16][l%16]; accumulator element i of lane l is
-// D[l/16 + 4i][l%16].
+// D[l/16 + 4i][l%16].  Weight rows stream through two LDS buffers of CH rows:
+// while the MFMAs consume one, each thread's share of the next chunk is
+// already in flight from global memory into registers.
 template <int RT, int CT, int CH>
 __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__restrict__ cp,
                                                             const double *__restrict__ params, int64_t ld,
@@ -84,9 +86,10 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
                                                             const double *__restrict__ W, double *__restrict__ Y) {
   constexpr int CW = CT * 16;
   constexpr int QT = kWaves * RT * 16;
-  static_assert(kRowChunk % CH == 0, "row chunk");
-  __shared__ double Ws[CH][CW + kLdsPad];
-  __shared__ double Xs[CH][4];
+  constexpr int PER = CH * CW / kThreads;
+  static_assert(kRowChunk % CH == 0 && (CH * CW) % kThreads == 0 && CH * 4 <= kThreads, "tile");
+  __shared__ double Ws[2][CH][CW + kLdsPad];
+  __shared__ double Xs[2][CH][4];
   __shared__ int poly[kMaxPoly][3];
   const EvalConsts &c = *cp;
   const int lane = threadIdx.x & 63;
@@ -104,36 +107,55 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
 #pragma unroll
     for (int d = 0; d < 4; ++d) xq[rt][d] = b < nb ? params[d * ld + b0 + b] / c.semi[d] : 0.0;
   }
-
   d4 acc[RT][CT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int kk = lane >> 4;
-  for (int r0 = 0; r0 < rows; r0 += CH) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < CH * CW; e += kThreads) {
-      const int r = e / CW, cc = e % CW;
-      Ws[r][cc] = W[(int64_t)(r0 + r) * Kp + col0 + cc];
+  double wreg[PER];
+  double xreg = 0.0;
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      wreg[u] = W[(int64_t)(r0 + e / CW) * Kp + col0 + e % CW];
     }
-    for (int e = threadIdx.x; e < CH * 4; e += kThreads) Xs[e >> 2][e & 3] = nodes[(int64_t)r0 * 4 + e];
-    __syncthreads();
+    if (threadIdx.x < CH * 4) xreg = nodes[(int64_t)r0 * 4 + threadIdx.x];
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      Ws[buf][e / CW][e % CW] = wreg[u];
+    }
+    if (threadIdx.x < CH * 4) Xs[buf][threadIdx.x >> 2][threadIdx.x & 3] = xreg;
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int kk = lane >> 4;
+  const int n_chunks = rows / CH;
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    const int cur = ch & 1;
+    const int r0 = ch * CH;
+    if (ch + 1 < n_chunks) fetch(r0 + CH);
 #pragma unroll 2
     for (int s = 0; s < CH / 4; ++s) {
       const int rr = 4 * s + kk;
       double a[RT];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) a[rt] = basis_row_fp64(r0 + rr, N, NM, xq[rt], Xs[rr], eps2, poly);
+      for (int rt = 0; rt < RT; ++rt) a[rt] = basis_row_fp64(r0 + rr, N, NM, xq[rt], Xs[cur][rr], eps2, poly);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        const double bv = Ws[rr][ct * 16 + (lane & 15)];
+        const double bv = Ws[cur][rr][ct * 16 + (lane & 15)];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
           acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], bv, acc[rt][ct], 0, 0, 0);
       }
     }
+    if (ch + 1 < n_chunks) stash(cur ^ 1);
+    __syncthreads();
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
@@ -411,10 +433,11 @@ static void launch_fp64_variant(const EvalConsts *c, const EvalConsts &hc, const
   RBFL_HIP(hipGetLastError());
 }
 
-int contract_variants(int form) { return form == RBFL_FORM_FP64 ? 4 : 2; }
+int contract_variants(int form) { return form == RBFL_FORM_FP64 ? 5 : 2; }
 
 const char *contract_variant_name(int form, int v) {
-  static const char *f64[] = {"fp64 rt2 ct4 ch64", "fp64 rt2 ct8 ch32", "fp64 rt4 ct4 ch32", "fp64 rt1 ct8 ch64"};
+  static const char *f64[] = {"fp64 rt2 ct4 ch32", "fp64 rt2 ct4 ch16", "fp64 rt2 ct8 ch16", "fp64 rt4 ct4 ch16",
+                              "fp64 rt4 ct2 ch32"};
   static const char *f32[] = {"fp32 rt2 ct4 ch64", "fp32 rt2 ct8 ch32"};
   return form == RBFL_FORM_FP64 ? f64[v] : f32[v];
 }
@@ -422,10 +445,11 @@ const char *contract_variant_name(int form, int v) {
 void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                           int64_t nb, const double *nodes, const double *W, double *Y, hipStream_t s, int variant) {
   switch (variant) {
-    case 1: launch_fp64_variant<2, 8, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
-    case 2: launch_fp64_variant<4, 4, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
-    case 3: launch_fp64_variant<1, 8, 64>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
-    default: launch_fp64_variant<2, 4, 64>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
+    case 1: launch_fp64_variant<2, 4, 16>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    case 2: launch_fp64_variant<2, 8, 16>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    case 3: launch_fp64_variant<4, 4, 16>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    case 4: launch_fp64_variant<4, 2, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s); break;
+    default: launch_fp64_variant<2, 4, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
   }
 }
 
