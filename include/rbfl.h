@@ -195,6 +195,40 @@ int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t fo
  * sums.  Not for use under graph capture. */
 int32_t rbfl_profile(rbfl_handle h, int32_t on);
 
+/*
+ * Multi-event batches: one launch evaluates the proposals of several events
+ * (handles of different N, K, q, mode sets), each event's proposals a
+ * contiguous range of one concatenated parameter array.
+ *
+ * A plan fixes the events, their proposal counts and the device buffers
+ * params (FP64 [11][total], row stride total = sum of counts, event e's
+ * proposals in columns [sum_{e'<e} counts[e'], ...)) and lnl (FP64 [total]).
+ * Execution: a persistent FP64 contraction kernel takes (event, proposal
+ * tile, column tile) items, events ordered by decreasing cost
+ * proposals x (N+M) x K, from an atomic counter; then one wave per proposal
+ * finishes ln L with its own event's frame and basis.  RBFL_PLAN_AUTOTUNE
+ * times each tile variant on the whole batch (HIP events) and keeps the
+ * fastest; RBFL_PLAN_GRAPH captures the launch in a HIP graph, replayed by
+ * rbfl_plan_launch -- a sampler step writes new proposals into `params` and
+ * launches again, without re-capturing.  The handles must outlive the plan;
+ * plan creation allocates (work space for every event's outputs), launches
+ * do not.  Launches of one plan must not overlap.
+ */
+#define RBFL_PLAN_GRAPH 0x1u
+#define RBFL_PLAN_AUTOTUNE 0x2u
+typedef struct rbfl_plan_ctx *rbfl_plan;
+int32_t rbfl_plan_create(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
+                         double *lnl, uint32_t flags, void *stream, rbfl_plan *out);
+int32_t rbfl_plan_launch(rbfl_plan plan, void *stream);
+/* out double[12]: tile variant, work items, persistent grid size, proposals, then the
+ * autotuner's median time [ms] of each variant (0 = not timed). */
+int32_t rbfl_plan_query(rbfl_plan plan, double *out, size_t bytes);
+int32_t rbfl_plan_destroy(rbfl_plan plan);
+/* One-shot multi-event evaluation (creates a plan without graph or autotune,
+ * runs it and synchronises `stream`). */
+int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
+                         double *lnl, void *stream);
+
 /* Releases the handle and its device memory (NULL is allowed). */
 int32_t rbfl_destroy(rbfl_handle h);
 

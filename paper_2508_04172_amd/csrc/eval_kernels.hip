@@ -78,12 +78,15 @@ __device__ __forceinline__ float basis_row_fp32(int row, int N, int NM, const fl
 // D[l/16 + 4i][l%16].  Weight rows stream through two LDS buffers of CH rows:
 // while the MFMAs consume one, each thread's share of the next chunk is
 // already in flight from global memory into registers.
+// One (proposal tile, column tile) of the FP64 contraction; called by the
+// per-handle kernel and by the persistent multi-event kernel.  Must be entered
+// by the whole block; ends with a block barrier, so the block may run another
+// tile right after.
 template <int RT, int CT, int CH>
-__global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__restrict__ cp,
-                                                            const double *__restrict__ params, int64_t ld,
-                                                            int64_t b0, int64_t nb,
-                                                            const double *__restrict__ nodes,
-                                                            const double *__restrict__ W, double *__restrict__ Y) {
+__device__ __forceinline__ void contract_tile_fp64(const EvalConsts &c, const double *__restrict__ params,
+                                                   int64_t ld, int64_t b0, int64_t nb,
+                                                   const double *__restrict__ nodes, const double *__restrict__ W,
+                                                   double *__restrict__ Y, int tile_q, int tile_c) {
   constexpr int CW = CT * 16;
   constexpr int QT = kWaves * RT * 16;
   constexpr int PER = CH * CW / kThreads;
@@ -91,11 +94,10 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
   __shared__ double Ws[2][CH][CW + kLdsPad];
   __shared__ double Xs[2][CH][4];
   __shared__ int poly[kMaxPoly][3];
-  const EvalConsts &c = *cp;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int col0 = blockIdx.y * CW;
-  const int64_t qbase = (int64_t)blockIdx.x * QT + wave * RT * 16;
+  const int col0 = tile_c * CW;
+  const int64_t qbase = (int64_t)tile_q * QT + wave * RT * 16;
   const int N = c.N, NM = c.N + c.M, rows = c.rows, Kp = c.Kp;
   const double eps2 = c.eps2;
   for (int e = threadIdx.x; e < kMaxPoly * 3; e += kThreads) poly[e / 3][e % 3] = c.poly_idx[e / 3][e % 3];
@@ -167,6 +169,15 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__
       for (int ct = 0; ct < CT; ++ct) Y[b * Kp + col0 + ct * 16 + (lane & 15)] = acc[rt][ct][i];
     }
   }
+}
+
+template <int RT, int CT, int CH>
+__global__ void __launch_bounds__(kThreads) k_contract_fp64(const EvalConsts *__restrict__ cp,
+                                                            const double *__restrict__ params, int64_t ld,
+                                                            int64_t b0, int64_t nb,
+                                                            const double *__restrict__ nodes,
+                                                            const double *__restrict__ W, double *__restrict__ Y) {
+  contract_tile_fp64<RT, CT, CH>(*cp, params, ld, b0, nb, nodes, W, Y, blockIdx.x, blockIdx.y);
 }
 
 // FP32 form: basis rows in FP32 (hardware exp), FP32 weights, FP32-accumulating
@@ -261,15 +272,12 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
 // own detector's response and arrival time and its own mode's harmonics.
 // Partial sums meet in the pair's first lane by shuffles; that lane forms
 // Re(conj(A) z), the detector's first lane the overlap term, lane 0 the sum.
-__global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restrict__ cp,
-                                                       const double *__restrict__ params, int64_t ld, int64_t b0,
-                                                       int64_t nb, const double *__restrict__ Y,
-                                                       const double2 *__restrict__ basis, double *__restrict__ lnl) {
-  const EvalConsts &c = *cp;
+// ln L of proposal g (column g of params) from its interpolated row y; one
+// whole wave per call.
+__device__ __forceinline__ void epilogue_one(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
+                                             int64_t g, const double *__restrict__ y,
+                                             const double2 *__restrict__ basis, double *__restrict__ lnl) {
   const int lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (b >= nb) return;   // whole wave leaves together
-  const int64_t g = b0 + b;
   const int n_modes = c.n_modes, q = c.q, T = c.T;
   const int P = c.n_det * n_modes;
   const int G = 64 / P;
@@ -335,7 +343,6 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
   const double ar = 0.5 * ((fp * ynr - fc * yni) + sg * (fp * ypr - fc * ypi));
   const double ai = 0.5 * ((fp * yni + fc * ynr) + sg * (-fp * ypi - fc * ypr));
   // a5: partial reconstruction of z_{k,a} over this lane's coefficients
-  const double *y = Y + b * c.Kp;
   double zr = 0.0, zi = 0.0;
   if (active) {
     const int o = c.coef_off[k][a];
@@ -401,6 +408,64 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
     tot = t;
   }
   if (lane == 0) lnl[g] = tot + comp;
+}
+
+__global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restrict__ cp,
+                                                       const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                       int64_t nb, const double *__restrict__ Y,
+                                                       const double2 *__restrict__ basis, double *__restrict__ lnl) {
+  const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (b >= nb) return;   // whole wave leaves together
+  epilogue_one(*cp, params, ld, b0 + b, Y + b * cp->Kp, basis, lnl);
+}
+
+// ---- multi-event (ragged) batch --------------------------------------------
+
+// Persistent contraction over the work list of every event: items are
+// (event, proposal tile, column tile), numbered event by event in the
+// caller's cost order; each block takes the next item from an atomic counter
+// until the list is exhausted (every block reaches that exit).
+template <int RT, int CT, int CH>
+__global__ void __launch_bounds__(kThreads) k_ragged_contract_fp64(const EventDesc *__restrict__ ev, int n_ev,
+                                                                   int64_t total_items,
+                                                                   unsigned long long *__restrict__ counter,
+                                                                   const double *__restrict__ params, int64_t ld) {
+  __shared__ long long item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t item = item_s;
+    __syncthreads();
+    if (item >= total_items) break;
+    int e = 0;
+    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
+    const EventDesc &d = ev[e];
+    const int64_t local = item - d.item0;
+    const int tq = (int)(local % d.tiles_q);
+    const int tc = (int)(local / d.tiles_q);
+    contract_tile_fp64<RT, CT, CH>(*d.consts, params, ld, d.q0, d.n, d.nodes, d.W, d.Y, tq, tc);
+  }
+}
+
+__global__ void k_zero_counter(unsigned long long *counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
+}
+
+// One wave per proposal of the concatenated batch; the proposal's event is
+// found by binary search over the events' first proposals (caller order).
+__global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *__restrict__ ev, int n_ev,
+                                                              const double *__restrict__ params, int64_t total,
+                                                              double *__restrict__ lnl) {
+  const int64_t g = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (g >= total) return;
+  int lo = 0, hi = n_ev - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ev[mid].q0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const EventDesc &d = ev[lo];
+  epilogue_one(*d.consts, params, total, g, d.Y + (g - d.q0) * d.Kp, d.basis, lnl);
 }
 
 __global__ void k_convert_weights(const double *__restrict__ W, size_t n, float *__restrict__ hi,
@@ -478,6 +543,40 @@ void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const doubl
 void launch_contract_bf16(const EvalConsts *, const EvalConsts &, const double *, int64_t, int64_t, int64_t,
                           const double *, const uint16_t *, double *, hipStream_t) {
   throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
+}
+
+int ragged_variants() { return 3; }
+
+void ragged_tile(int variant, int *qt, int *cw) {
+  static const int q[] = {128, 128, 128}, w[] = {128, 64, 64};
+  *qt = q[variant];
+  *cw = w[variant];
+}
+
+template <int RT, int CT, int CH>
+static void launch_ragged_variant(const EventDesc *ev, int n_ev, int64_t total_items, unsigned long long *counter,
+                                  const double *params, int64_t ld, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+  RBFL_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_ragged_contract_fp64<RT, CT, CH>), dim3(grid), dim3(kThreads), 0, s, ev, n_ev, total_items,
+                     counter, params, ld);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_ragged_contract(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
+                            unsigned long long *counter, const double *params, int64_t ld, int grid, hipStream_t s) {
+  switch (variant) {
+    case 1: launch_ragged_variant<2, 4, 32>(ev, n_ev, total_items, counter, params, ld, grid, s); break;
+    case 2: launch_ragged_variant<2, 4, 16>(ev, n_ev, total_items, counter, params, ld, grid, s); break;
+    default: launch_ragged_variant<2, 8, 16>(ev, n_ev, total_items, counter, params, ld, grid, s);
+  }
+}
+
+void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params, int64_t total, double *lnl,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_ragged_epilogue, dim3((unsigned)((total + kWaves - 1) / kWaves)), dim3(kThreads), 0, s, ev,
+                     n_ev, params, total, lnl);
+  RBFL_HIP(hipGetLastError());
 }
 
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,

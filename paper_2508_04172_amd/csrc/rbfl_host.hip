@@ -11,6 +11,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -1129,6 +1130,83 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
   }
 }
 
+// ---- multi-event batches -----------------------------------------------------
+
+struct Plan {
+  std::vector<Ctx *> ctx;
+  std::vector<int64_t> counts;
+  int64_t total = 0;
+  const double *params = nullptr;
+  double *lnl = nullptr;
+  DevBuf<EventDesc> ev_work, ev_param;
+  DevBuf<double> Y;
+  DevBuf<unsigned long long> counter;
+  int64_t total_items = 0;
+  int grid = 0;
+  int variant = 0;
+  double tune_ms[8] = {};
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+// Event descriptors for tile variant v: caller order (for the epilogue) and
+// decreasing-cost order with consecutive work-item ranges (for the persistent
+// contraction).  Cost of an event = proposals x (N+M) x K.
+static void plan_layout(Plan &p, int v, hipStream_t s) {
+  int qt, cw;
+  ragged_tile(v, &qt, &cw);
+  const int n_ev = (int)p.ctx.size();
+  std::vector<EventDesc> d(n_ev);
+  int64_t q0 = 0, yoff = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    Ctx &c = *p.ctx[e];
+    d[e].consts = c.consts.p;
+    d[e].nodes = c.nodes.p;
+    d[e].W = c.W.p;
+    d[e].basis = c.basis.p;
+    d[e].Y = p.Y.p + yoff;
+    d[e].q0 = q0;
+    d[e].n = p.counts[e];
+    d[e].tiles_q = (int)((p.counts[e] + qt - 1) / qt);
+    d[e].tiles_c = c.Kp / cw;
+    d[e].Kp = c.Kp;
+    q0 += p.counts[e];
+    yoff += p.counts[e] * c.Kp;
+  }
+  std::vector<int> order(n_ev);
+  for (int e = 0; e < n_ev; ++e) order[e] = e;
+  auto cost = [&](int e) { return (double)p.counts[e] * (p.ctx[e]->N + p.ctx[e]->M) * p.ctx[e]->K; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<EventDesc> w(n_ev);
+  int64_t item = 0;
+  for (int i = 0; i < n_ev; ++i) {
+    w[i] = d[order[i]];
+    w[i].item0 = item;
+    item += (int64_t)w[i].tiles_q * w[i].tiles_c;
+  }
+  p.total_items = item;
+  int dev = 0, cus = 0;
+  RBFL_HIP(hipGetDevice(&dev));
+  RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.total_items, (int64_t)cus * 2));
+  RBFL_HIP(hipMemcpyAsync(p.ev_work.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  p.variant = v;
+}
+
+static void plan_run(Plan &p, hipStream_t s) {
+  const int n_ev = (int)p.ctx.size();
+  launch_ragged_contract(p.variant, p.ev_work.p, n_ev, p.total_items, p.counter.p, p.params, p.total, p.grid, s);
+  launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
+}
+
 template <class F>
 static int32_t guarded(F &&f) {
   try {
@@ -1155,6 +1233,82 @@ static int32_t guarded(F &&f) {
 struct rbfl_ctx {
   rbfl::Ctx c;
 };
+
+struct rbfl_plan_ctx {
+  rbfl::Plan p;
+};
+
+namespace rbfl {
+static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t *counts, const double *params,
+                                  double *lnl, uint32_t flags, hipStream_t s) {
+  require(hs != nullptr && counts != nullptr && params != nullptr && lnl != nullptr, "NULL argument");
+  require(n_ev >= 1 && n_ev <= 4096, "n_events must be in 1 .. 4096");
+  std::unique_ptr<rbfl_plan_ctx> pc(new rbfl_plan_ctx());
+  Plan &p = pc->p;
+  int64_t yelems = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    require(hs[e] != nullptr, "NULL handle in the event list");
+    require(counts[e] >= 1, "every event needs at least one proposal");
+    p.ctx.push_back(&hs[e]->c);
+    p.counts.push_back(counts[e]);
+    p.total += counts[e];
+    yelems += counts[e] * hs[e]->c.Kp;
+  }
+  p.params = params;
+  p.lnl = lnl;
+  p.ev_work.alloc(n_ev);
+  p.ev_param.alloc(n_ev);
+  p.Y.alloc((size_t)yelems);
+  p.counter.alloc(1);
+  if (flags & RBFL_PLAN_AUTOTUNE) {
+    hipEvent_t e0, e1;
+    RBFL_HIP(hipEventCreate(&e0));
+    RBFL_HIP(hipEventCreate(&e1));
+    int best = 0;
+    double best_ms = 1e300;
+    for (int v = 0; v < ragged_variants() && v < 8; ++v) {
+      plan_layout(p, v, s);
+      plan_run(p, s);
+      double t[3];
+      for (int r = 0; r < 3; ++r) {
+        RBFL_HIP(hipEventRecord(e0, s));
+        plan_run(p, s);
+        RBFL_HIP(hipEventRecord(e1, s));
+        RBFL_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t[r] = ms;
+      }
+      std::sort(t, t + 3);
+      p.tune_ms[v] = t[1];
+      if (t[1] < best_ms) {
+        best_ms = t[1];
+        best = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan_layout(p, best, s);
+  } else {
+    plan_layout(p, 0, s);
+  }
+  if (flags & RBFL_PLAN_GRAPH) {
+    RBFL_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+    RBFL_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      plan_run(p, p.cap_stream);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(p.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    RBFL_HIP(hipStreamEndCapture(p.cap_stream, &p.graph));
+    RBFL_HIP(hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0));
+  }
+  return pc.release();
+}
+}  // namespace rbfl
 
 extern "C" {
 
@@ -1217,6 +1371,50 @@ int32_t rbfl_profile(rbfl_handle h, int32_t on) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
     h->c.profile = on != 0;
+  });
+}
+
+int32_t rbfl_plan_create(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
+                         double *lnl, uint32_t flags, void *stream, rbfl_plan *out) {
+  return rbfl::guarded([&] {
+    rbfl::require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    *out = rbfl::plan_create(hs, n_events, counts, params, lnl, flags, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_plan_launch(rbfl_plan plan, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(plan != nullptr, "plan is NULL");
+    rbfl::Plan &p = plan->p;
+    if (p.exec)
+      RBFL_HIP(hipGraphLaunch(p.exec, reinterpret_cast<hipStream_t>(stream)));
+    else
+      rbfl::plan_run(p, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_plan_query(rbfl_plan plan, double *out, size_t bytes) {
+  return rbfl::guarded([&] {
+    rbfl::require(plan != nullptr, "plan is NULL");
+    const rbfl::Plan &p = plan->p;
+    double v[12] = {(double)p.variant, (double)p.total_items, (double)p.grid, (double)p.total};
+    for (int i = 0; i < 8; ++i) v[4 + i] = p.tune_ms[i];
+    rbfl::copy_out(out, bytes, v, sizeof(v));
+  });
+}
+
+int32_t rbfl_plan_destroy(rbfl_plan plan) {
+  return rbfl::guarded([&] { delete plan; });
+}
+
+int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
+                         double *lnl, void *stream) {
+  return rbfl::guarded([&] {
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::unique_ptr<rbfl_plan_ctx> hold(rbfl::plan_create(hs, n_events, counts, params, lnl, 0u, s));
+    rbfl::plan_run(hold->p, s);
+    RBFL_HIP(hipStreamSynchronize(s));
   });
 }
 

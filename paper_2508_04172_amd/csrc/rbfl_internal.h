@@ -43,6 +43,18 @@ struct EvalConsts {
   double spline[kSplineTaps][4];            // w_s(f) = sum_p spline[s][p] f^p
 };
 
+// One event of a multi-event batch, as the persistent kernels read it.
+struct EventDesc {
+  const EvalConsts *consts;
+  const double *nodes;
+  const double *W;
+  const double2 *basis;
+  double *Y;           // this event's rows of the shared work space, [n][Kp]
+  int64_t q0, n;       // first proposal (column of the concatenated params) and count
+  int64_t item0;       // first work item of this event (work order)
+  int tiles_q, tiles_c, Kp, pad;
+};
+
 template <class T>
 struct DevBuf {
   T *p = nullptr;
@@ -148,6 +160,12 @@ void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const doubl
 void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const uint16_t *W, double *Y,
                           hipStream_t s);
+int ragged_variants();
+void ragged_tile(int variant, int *proposals_per_tile, int *columns_per_tile);
+void launch_ragged_contract(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
+                            unsigned long long *counter, const double *params, int64_t ld, int grid, hipStream_t s);
+void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params, int64_t total, double *lnl,
+                            hipStream_t s);
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
 void launch_convert_weights(const double *W, size_t n, float *hi, float *lo, uint16_t *b16, hipStream_t s);

@@ -29,7 +29,9 @@ Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALU
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE = range(14)
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
-            "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_destroy")
+            "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
+            "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_destroy")
+PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
 
 
 class BuildSpec(C.Structure):
@@ -106,6 +108,18 @@ def load(path: str = LIB_PATH):
     lib.rbfl_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
     lib.rbfl_profile.restype = C.c_int32
     lib.rbfl_profile.argtypes = [C.c_void_p, C.c_int32]
+    lib.rbfl_plan_create.restype = C.c_int32
+    lib.rbfl_plan_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64), C.c_void_p,
+                                     C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.rbfl_plan_launch.restype = C.c_int32
+    lib.rbfl_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
+    lib.rbfl_plan_query.restype = C.c_int32
+    lib.rbfl_plan_query.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.rbfl_plan_destroy.restype = C.c_int32
+    lib.rbfl_plan_destroy.argtypes = [C.c_void_p]
+    lib.rbfl_eval_ragged.restype = C.c_int32
+    lib.rbfl_eval_ragged.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64), C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
     lib.rbfl_destroy.restype = C.c_int32
     lib.rbfl_destroy.argtypes = [C.c_void_p]
     _lib = lib
@@ -277,6 +291,48 @@ class Handle:
         v = self._query(Q_KERNEL_STATS, 6)
         return {"contract_ms": v[0], "contract_launches": int(v[1]), "contract_n": int(v[2]),
                 "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5])}
+
+
+class Plan:
+    """A multi-event batch plan (rbfl_plan_*): fixed events, proposal counts and
+    device buffers; launch() replays it (as a HIP graph with PLAN_GRAPH)."""
+
+    def __init__(self, handles, counts, params_ptr: int, lnl_ptr: int, flags: int = PLAN_GRAPH | PLAN_AUTOTUNE,
+                 stream: int = 0):
+        self._handles = list(handles)          # keep the events alive as long as the plan
+        arr = (C.c_void_p * len(handles))(*[h.ptr for h in handles])
+        cnt = (C.c_int64 * len(counts))(*[int(x) for x in counts])
+        p = C.c_void_p()
+        _check(load().rbfl_plan_create(arr, len(handles), cnt, C.c_void_p(params_ptr), C.c_void_p(lnl_ptr), flags,
+                                       C.c_void_p(stream), C.byref(p)))
+        self._p = p
+
+    def launch(self, stream: int = 0):
+        _check(load().rbfl_plan_launch(self._p, C.c_void_p(stream)))
+
+    def info(self) -> dict:
+        v = np.zeros(12)
+        _check(load().rbfl_plan_query(self._p, v.ctypes.data_as(C.c_void_p), v.nbytes))
+        return {"variant": int(v[0]), "items": int(v[1]), "grid": int(v[2]), "proposals": int(v[3]),
+                "tune_ms": [float(x) for x in v[4:] if x > 0]}
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            _check(load().rbfl_plan_destroy(self._p))
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_ragged(handles, counts, params_ptr: int, lnl_ptr: int, stream: int = 0):
+    arr = (C.c_void_p * len(handles))(*[h.ptr for h in handles])
+    cnt = (C.c_int64 * len(counts))(*[int(x) for x in counts])
+    _check(load().rbfl_eval_ragged(arr, len(handles), cnt, C.c_void_p(params_ptr), C.c_void_p(lnl_ptr),
+                                   C.c_void_p(stream)))
 
 
 def params_soa(handle: Handle, qd, t_trig: float) -> np.ndarray:

@@ -230,7 +230,8 @@ def node_jitter(n: int, n_nodes: int, sigma: float = 0.03, seed: int = 7):
 
 
 def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
-                  base: Config = CFG2) -> List[Config]:
+                  base: Config = CFG2, seg_range=(8.0, 512.0), node_range=(200, 1500),
+                  q_range=(20, 60)) -> List[Config]:
     """Uneven events for the multi-event batch: segment length log-uniform in
     [8, 512] s, m1 ~ U[5, 20], m2 ~ U[1, 3], chi1 ~ U[-0.998, 0.998],
     chi2 ~ U[-0.05, 0.05] (the paper's NSBH injection ranges), 1-5 modes,
@@ -240,14 +241,14 @@ def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
     out = []
     msun_s = 4.925490947641267e-06
     for e in range(n_events):
-        seg = float(round(math.exp(rng.uniform(math.log(8.0), math.log(512.0)))))
+        seg = float(round(math.exp(rng.uniform(math.log(seg_range[0]), math.log(seg_range[1])))))
         m1 = rng.uniform(5.0, 20.0)
         m2 = rng.uniform(1.0, 3.0)
         c1 = rng.uniform(-0.998, 0.998)
         c2 = rng.uniform(-0.05, 0.05)
         n_modes = int(rng.integers(1, 6))
-        n_nodes = int(rng.integers(200, 1501))
-        q = int(rng.integers(20, 61))
+        n_nodes = int(rng.integers(node_range[0], node_range[1] + 1))
+        q = int(rng.integers(q_range[0], q_range[1] + 1))
         mc = (m1 * m2) ** 0.6 / (m1 + m2) ** 0.2 * msun_s
         # Newtonian chirp time from f: (5/256) (pi f)^(-8/3) Mc^(-5/3)
         f_low = 20.0

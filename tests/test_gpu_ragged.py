@@ -1,0 +1,126 @@
+"""Multi-event (ragged) batches: the persistent kernel and the captured plan
+against the oracle and against per-event evaluation."""
+import numpy as np
+import pytest
+
+from oracle import likelihood as lk
+from oracle import startup as su
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+EVENTS = wl.ragged_events(6, seed=11, seg_range=(4.0, 16.0), node_range=(60, 200), q_range=(5, 20),
+                          base=wl.SMALL_MULTI)
+COUNTS = [131, 700, 1, 257, 64, 383]          # tile remainders, a single proposal, exact tiles
+_state = {}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def events():
+    if "h" not in _state:
+        hs, arts = [], []
+        for cfg in EVENTS:
+            print(f"[ragged] building {cfg.name}: T={cfg.seg_len}s modes={len(cfg.modes)} N={cfg.n_nodes} q={cfg.q}",
+                  flush=True)
+            white = wl.white_noise(cfg)
+            inj = wl.injection_extrinsics(cfg)
+            hs.append(rbfl.Handle.from_config(cfg, white, inj))
+            arts.append(su.startup(cfg, white, inj, workers=1))
+        _state["h"], _state["art"] = hs, arts
+    return _state["h"], _state["art"]
+
+
+def proposals(step):
+    """Per event: near-node proposals (different draws per sampler step)."""
+    hs, arts = events()
+    gpu, cpu = [], []
+    for e, (cfg, h, art) in enumerate(zip(EVENTS, hs, arts)):
+        n = COUNTS[e]
+        idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=100 * step + e)
+        qd = wl.queries(cfg, n=n, seed=1000 * step + e)
+        gpu.append(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig))
+        cpu.append(lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+    return np.ascontiguousarray(np.concatenate(gpu, axis=1)), cpu
+
+
+def per_event_gpu(hs, params):
+    torch = _torch()
+    out, off = [], 0
+    for h, n in zip(hs, COUNTS):
+        p = torch.from_numpy(np.ascontiguousarray(params[:, off:off + n])).cuda()
+        o = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.eval(p.data_ptr(), n, o.data_ptr())
+        torch.cuda.synchronize()
+        out.append(o.cpu().numpy())
+        off += n
+    return np.concatenate(out)
+
+
+def test_ragged_matches_oracle_and_per_event():
+    torch = _torch()
+    hs, arts = events()
+    params, cpu = proposals(0)
+    total = sum(COUNTS)
+    p = torch.from_numpy(params).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    rbfl.eval_ragged(hs, COUNTS, p.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    lr = out.cpu().numpy()
+    le = per_event_gpu(hs, params)
+    fin = np.isfinite(le)
+    assert np.array_equal(fin, np.isfinite(lr))
+    assert np.abs(lr[fin] - le[fin]).max() <= 1e-12 * max(1.0, np.abs(le[fin]).max())
+    off = 0
+    for e, (art, n) in enumerate(zip(arts, COUNTS)):
+        lo = lk.meshfree_lnl(art, *cpu[e])
+        lg = lr[off:off + n]
+        f = np.isfinite(lo)
+        assert np.array_equal(f, np.isfinite(lg)), f"event {e}: domain flags differ"
+        if f.any():
+            d = np.abs(lg[f] - lo[f]).max()
+            print(f"[ragged] event {e}: {f.sum()}/{n} valid, max |dlnL| vs oracle {d:.3e}", flush=True)
+            assert d <= 1e-3
+        off += n
+
+
+def test_plan_graph_replays_follow_new_proposals():
+    """Capture once, then per sampler step write new proposals into the same
+    device buffer, with eager work in between, and check every replay."""
+    torch = _torch()
+    hs, _ = events()
+    total = sum(COUNTS)
+    params0, _ = proposals(0)
+    p = torch.from_numpy(params0).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), rbfl.PLAN_GRAPH | rbfl.PLAN_AUTOTUNE, stream)
+    info = plan.info()
+    print(f"[ragged] plan: {info}", flush=True)
+    assert info["items"] > 0 and info["proposals"] == total
+    for step in range(4):
+        params, _ = proposals(step + 1)
+        p.copy_(torch.from_numpy(params))
+        torch.cuda.synchronize()
+        plan.launch(stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want = per_event_gpu(hs, params)
+        fin = np.isfinite(want)
+        assert np.array_equal(fin, np.isfinite(got)), f"replay {step}"
+        assert np.abs(got[fin] - want[fin]).max() <= 1e-12 * max(1.0, np.abs(want[fin]).max()), f"replay {step}"
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # unrelated eager work between replays
+    plan.close()
+
+
+def test_plan_rejects_bad_arguments():
+    torch = _torch()
+    hs, _ = events()
+    buf = torch.zeros(11, dtype=torch.float64, device="cuda")
+    with pytest.raises(rbfl.RbflError) as e:
+        rbfl.Plan(hs[:2], [5, 0], buf.data_ptr(), buf.data_ptr(), 0)
+    assert e.value.code == rbfl.E_INVALID_ARG
