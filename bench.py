@@ -43,6 +43,9 @@ def main():
     ap.add_argument("--check-sample", type=int, default=2000)
     ap.add_argument("--ragged-events", type=int, default=16,
                     help="events in the multi-event batch form (0 = skip)")
+    ap.add_argument("--surrogate-train", type=int, default=200000,
+                    help="training proposals for the surrogate form (0 = skip)")
+    ap.add_argument("--surrogate-epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
@@ -125,6 +128,8 @@ def main():
         outs[name] = lf
         log(f"{name}: {v2:.4e} evals/s")
 
+    if args.surrogate_train > 0:
+        forms["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64)
     if args.ragged_events > 0:
         forms["ragged"] = bench_ragged(args, np, torch, rbfl, wl)
 
@@ -185,6 +190,53 @@ def main():
                                 "meets_1e-3": bool(agree and d.max() <= 1e-3)})
         result["config"]["valid_fraction"] = float(fin.mean())
     print(json.dumps(result), flush=True)
+
+
+def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
+    """Surrogate form: MLP 4 -> 256 -> 256 -> K trained by the library's own
+    kernels on proposals whose targets the FP64 interpolant computes; judged on
+    1e4 held-out proposals at |d ln L| <= 1e-3 (fallback to the interpolant
+    otherwise).  The network path's throughput is reported either way."""
+    n = params.shape[1]
+    K = h.sizes()["K"]
+    hidden = 256
+    z = wl.mlp_normals(rbfl.mlp_param_count(4, hidden, K))
+
+    def dev(m, seed):
+        idx, jit = wl.node_jitter(m, cfg.n_nodes, seed=seed)
+        qd = wl.queries(cfg, n=m, seed=seed).near_nodes(h.nodes(), idx, jit)
+        return torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))).cuda()
+
+    tr = dev(args.surrogate_train, 5)
+    ho = dev(10000, 6)
+    log(f"surrogate: training on {args.surrogate_train} proposals, {args.surrogate_epochs} epochs")
+    st = h.surrogate_train(z, tr.data_ptr(), args.surrogate_train, ho.data_ptr(), 10000, hidden=hidden,
+                           batch=1024, epochs=args.surrogate_epochs, lr=1e-3, threshold=1e-3)
+    log(f"surrogate: {st}")
+    h.surrogate_force(True)
+    sp = torch.cuda.current_stream().cuda_stream
+    h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SURROGATE, sp)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    t = time.perf_counter()
+    for _ in range(steps):
+        h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SURROGATE, sp)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    ls = lnl.cpu().numpy()
+    h.surrogate_force(False)
+    fin = np.isfinite(l64) & np.isfinite(ls)
+    d = np.abs(ls[fin] - l64[fin])
+    flop = 2.0 * (4 * hidden + hidden * hidden + hidden * K)
+    res = {"network_evals_per_s": n * steps / wall, "network_ms_per_step": wall / steps * 1e3,
+           "accepted": st["accepted"], "holdout_max_dlnl": st["holdout_max_dlnl"],
+           "holdout_median_dlnl": st["holdout_median_dlnl"], "train_s": st["train_s"],
+           "n_train": st["n_train"], "epochs": st["epochs"], "first_loss": st["first_loss"],
+           "last_loss": st["last_loss"], "max_dlnl_vs_fp64_gpu_all": float(d.max()),
+           "median_dlnl_vs_fp64_gpu_all": float(np.median(d)), "network_flop_per_eval": flop,
+           "note": "the surrogate form evaluates the FP64 interpolant unless accepted"}
+    log(f"surrogate: network path {res['network_evals_per_s']:.4e} evals/s, accepted={st['accepted']}")
+    return res
 
 
 def bench_ragged(args, np, torch, rbfl, wl):

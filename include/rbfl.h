@@ -50,7 +50,9 @@ enum rbfl_form {
   RBFL_FORM_FP64 = 0,       /* plain: FP64 kernel rows, FP64 MFMA contraction, FP64 epilogue */
   RBFL_FORM_FP32 = 1,       /* FP32 kernel rows and FP32 MFMA contraction, FP64 epilogue */
   RBFL_FORM_BF16 = 2,       /* BF16 operands, FP32-accumulating MFMA, FP64 epilogue */
-  RBFL_FORM_SPLIT = 3       /* FP32 hi/lo split of both operands, three FP32 MFMA products */
+  RBFL_FORM_SPLIT = 3,      /* FP32 kernel rows, hi/lo FP32 split of the weights (two FP32 MFMA products) */
+  RBFL_FORM_SURROGATE = 4   /* trained surrogate network in place of the interpolant contraction, FP64
+                               epilogue; the FP64 interpolant when no surrogate passed its held-out check */
 };
 
 /* Spec flags. */
@@ -178,8 +180,11 @@ enum rbfl_query_what {
   RBFL_Q_KERNEL_STATS = 12, /* double[6]: contraction ms, launches, proposals; epilogue ms, launches,
                                proposals -- summed HIP-event durations since rbfl_profile was switched
                                on (synchronises the recorded events; resets the sums) */
-  RBFL_Q_TUNE = 13          /* double[4][9]: per form, the chosen contraction tile variant and the
+  RBFL_Q_TUNE = 13,         /* double[4][9]: per form, the chosen contraction tile variant and the
                                autotuner's median time [ms] of each variant (0 = not timed) */
+  RBFL_Q_SURROGATE = 14     /* double[8]: accepted (1/0), held-out max |d ln L|, held-out median
+                               |d ln L|, first-epoch loss, last-epoch loss, epochs, training seconds,
+                               training proposals */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
@@ -228,6 +233,55 @@ int32_t rbfl_plan_destroy(rbfl_plan plan);
  * runs it and synchronises `stream`). */
 int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
                          double *lnl, void *stream);
+
+/*
+ * Learned surrogate (not in the paper: a network that replaces the
+ * interpolant contraction, keeping the interpolant as fallback and judge).
+ * A multilayer perceptron x -> H -> H -> K with SiLU activations maps the
+ * unit-ball coordinates x = delta_e / a to the K interpolated reals
+ * (standardised per column by the training set's mean and deviation).  It is
+ * trained on proposals whose targets the handle's FP64 interpolant computes,
+ * with mean-squared error and Adam, by the library's own FP32 kernels.  After
+ * training, ln L of the held-out proposals through the network is compared
+ * with ln L through the interpolant; the surrogate is used by
+ * RBFL_FORM_SURROGATE only if the largest |difference| (and every domain
+ * decision) stays within `threshold`, otherwise that form evaluates the FP64
+ * interpolant.  The surrogate form's work space is per handle: calls with it
+ * on one handle must not overlap.
+ *
+ * Parameters (shared layout): W1 [H][4], b1 [H], W2 [H][H], b2 [H],
+ * W3 [K][H], b3 [K], weights row-major; initialised from standard normal
+ * deviates z in the same layout as W = z / sqrt(fan_in), b = 0.
+ */
+typedef struct {
+  int32_t hidden;                /* H, 8 .. 1024 */
+  int32_t batch;                 /* mini-batch size */
+  int32_t epochs;                /* passes over the training proposals */
+  double lr, beta1, beta2, adam_eps;
+  const double *init_normals;    /* host [n_params] standard normal deviates */
+  const double *train_params;    /* device FP64 [11][n_train]; rows 0..3 (delta_e) are read */
+  int64_t n_train;               /* >= batch */
+  const double *holdout_params;  /* device FP64 [11][n_holdout] proposals, or NULL (then never accepted) */
+  int64_t n_holdout;
+  double threshold;              /* acceptance bar on max |d ln L| over the held-out proposals */
+} rbfl_train_spec;
+int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream);
+/* Overrides the held-out judge (on = 1: the surrogate form uses the network
+ * even if it failed the check; 0: back to the judge's decision).  For
+ * measuring the network path; RBFL_E_STATE if no surrogate was trained. */
+int32_t rbfl_surrogate_force(rbfl_handle h, int32_t on);
+
+/* The surrogate network on its own (for checks of its forward and backward
+ * passes): x device FP32 [B][n_in], y/t device FP32 [B][n_out]; loss is a
+ * host double (the call synchronises); rbfl_mlp_get copies the parameters
+ * (what = 0) or the last gradients (what = 1) to host FP32 [n_params]. */
+typedef struct rbfl_mlp_ctx *rbfl_mlp;
+int32_t rbfl_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, const double *normals, rbfl_mlp *out);
+int32_t rbfl_mlp_forward(rbfl_mlp m, const float *x, int64_t B, float *y, void *stream);
+int32_t rbfl_mlp_loss_grad(rbfl_mlp m, const float *x, const float *t, int64_t B, double *loss, void *stream);
+int32_t rbfl_mlp_adam(rbfl_mlp m, double lr, double beta1, double beta2, double eps, void *stream);
+int32_t rbfl_mlp_get(rbfl_mlp m, int32_t what, float *out, size_t bytes);
+int32_t rbfl_mlp_destroy(rbfl_mlp m);
 
 /* Releases the handle and its device memory (NULL is allowed). */
 int32_t rbfl_destroy(rbfl_handle h);

@@ -468,6 +468,65 @@ __global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *_
   epilogue_one(*d.consts, params, total, g, d.Y + (g - d.q0) * d.Kp, d.basis, lnl);
 }
 
+// Surrogate inputs: x = delta_e / a in FP32, [nb][4].
+__global__ void k_sur_inputs(const double *__restrict__ params, int64_t ld, int64_t b0, int64_t nb,
+                             const EvalConsts *__restrict__ c, float *__restrict__ x) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  for (int d = 0; d < 4; ++d) x[b * 4 + d] = (float)(params[d * ld + b0 + b] / c->semi[d]);
+}
+
+// Surrogate outputs: Y[b][k] = mu_k + sd_k ys[b][k] in FP64, padded rows of Kp.
+__global__ void k_sur_outputs(const float *__restrict__ ys, const float *__restrict__ mu,
+                              const float *__restrict__ sd, int64_t nb, int K, int Kp, double *__restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nb * K) return;
+  const int64_t b = e / K;
+  const int k = (int)(e % K);
+  Y[b * Kp + k] = (double)mu[k] + (double)sd[k] * (double)ys[e];
+}
+
+// Per-column mean and standard deviation of Y [n][K] (two passes, FP64).
+__global__ void k_col_stats(const double *__restrict__ Y, int64_t n, int K, float *__restrict__ mu,
+                            float *__restrict__ sd) {
+  const int k = blockIdx.x;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < n; b += 256) s += Y[b * K + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  __syncthreads();
+  double v = 0.0;
+  for (int64_t b = threadIdx.x; b < n; b += 256) {
+    const double d = Y[b * K + k] - mean;
+    v += d * d;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mu[k] = (float)mean;
+    const double sdev = sqrt(red[0] / (double)n);
+    sd[k] = (float)(sdev > 0.0 ? sdev : 1.0);
+  }
+}
+
+__global__ void k_standardise(const double *__restrict__ Y, int64_t n, int K, const float *__restrict__ mu,
+                              const float *__restrict__ sd, float *__restrict__ T) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * K) return;
+  const int k = (int)(e % K);
+  T[e] = (float)((Y[e] - (double)mu[k]) / (double)sd[k]);
+}
+
 __global__ void k_convert_weights(const double *__restrict__ W, size_t n, float *__restrict__ hi,
                                   float *__restrict__ lo, uint16_t *__restrict__ b16) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -584,6 +643,30 @@ void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *pa
   (void)hc;
   dim3 grid((unsigned)((nb + kWaves - 1) / kWaves));
   hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_inputs, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, params, ld, b0, nb, c, x);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_outputs, dim3((unsigned)((nb * K + 255) / 256)), dim3(256), 0, s, ys, mu, sd, nb, K, Kp,
+                     Y);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_stats, dim3(K), dim3(256), 0, s, Y, n, K, mu, sd);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_standardise(const double *Y, int64_t n, int K, const float *mu, const float *sd, float *T,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_standardise, dim3((unsigned)((n * K + 255) / 256)), dim3(256), 0, s, Y, n, K, mu, sd, T);
   RBFL_HIP(hipGetLastError());
 }
 

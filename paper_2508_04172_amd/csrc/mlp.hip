@@ -1,0 +1,230 @@
+// Surrogate network kernels: a multilayer perceptron in -> H -> H -> out with
+// SiLU activations, trained by the project's own forward, backward and Adam
+// kernels (FP32 arithmetic, FP32 master weights).
+//
+// Parameter layout: W1 [H][in], b1 [H], W2 [H][H], b2 [H], W3 [out][H],
+// b3 [out], weights row-major.  Initialisation from caller-provided standard
+// normal deviates z: W = z / sqrt(fan_in), b = 0.
+#include "rbfl_internal.h"
+
+namespace rbfl {
+
+namespace {
+
+constexpr int kT = 256;
+
+// C[m][n] = act(sum_k A(m,k) B(k,n) + bias[n]) with A(m,k) = A[m*sam + k*sak]
+// and B(k,n) = B[k*sbk + n*sbn] (strides express the transposes).  64x64
+// tile per block, 16-deep k steps through LDS, 4x4 outputs per thread.
+// With Z != nullptr the pre-activation is stored too.
+template <int ACT>
+__global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const float *__restrict__ A, int64_t sam,
+                                                 int64_t sak, const float *__restrict__ B, int64_t sbk, int64_t sbn,
+                                                 const float *__restrict__ bias, float *__restrict__ Z,
+                                                 float *__restrict__ C, int64_t ldc) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += kT) {
+      const int kk = e >> 6, mm = e & 63;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
+      const int n = n0 + mm;
+      Bs[kk][mm] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty + 16 * i;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + 16 * j;
+      if (n >= N) continue;
+      float v = acc[i][j] + (bias ? bias[n] : 0.0f);
+      if (Z) Z[(int64_t)m * ldc + n] = v;
+      if (ACT == 1) v = v / (1.0f + __expf(-v));
+      C[(int64_t)m * ldc + n] = v;
+    }
+  }
+}
+
+// dY = 2 (Y - T) / count; per-block partial sums of (Y - T)^2 (fixed order).
+__global__ void __launch_bounds__(kT) k_mse(const float *__restrict__ Y, const float *__restrict__ T, int64_t n,
+                                            float scale, float *__restrict__ dY, double *__restrict__ part) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT) {
+    const float r = Y[e] - T[e];
+    dY[e] = 2.0f * r * scale;
+    s += (double)r * (double)r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const double *__restrict__ part, int n, double scale, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+  }
+}
+
+// dZ = dH * silu'(Z), silu'(z) = s (1 + z (1 - s)), s = 1 / (1 + e^-z).
+__global__ void k_silu_back(const float *__restrict__ dH, const float *__restrict__ Z, int64_t n,
+                            float *__restrict__ dZ) {
+  const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (e >= n) return;
+  const float z = Z[e];
+  const float s = 1.0f / (1.0f + __expf(-z));
+  dZ[e] = dH[e] * s * (1.0f + z * (1.0f - s));
+}
+
+// db[n] = sum_b dZ[b][n].
+__global__ void k_colsum(const float *__restrict__ dZ, int B, int N, float *__restrict__ db) {
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += dZ[(int64_t)b * N + n];
+  db[n] = s;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2) {
+  const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (e >= n) return;
+  const float ge = g[e];
+  const float me = b1 * m[e] + (1.0f - b1) * ge;
+  const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
+  m[e] = me;
+  v[e] = ve;
+  p[e] -= lr * (me / bc1) / (sqrtf(ve / bc2) + eps);
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+}  // namespace
+
+void Mlp::init(int n_in, int hidden, int n_out, const double *normals) {
+  in = n_in;
+  hid = hidden;
+  out = n_out;
+  o_w1 = 0;
+  o_b1 = o_w1 + (int64_t)hid * in;
+  o_w2 = o_b1 + hid;
+  o_b2 = o_w2 + (int64_t)hid * hid;
+  o_w3 = o_b2 + hid;
+  o_b3 = o_w3 + (int64_t)out * hid;
+  np = o_b3 + out;
+  std::vector<float> h(np, 0.0f);
+  for (int64_t i = 0; i < (int64_t)hid * in; ++i) h[o_w1 + i] = (float)(normals[o_w1 + i] / sqrt((double)in));
+  for (int64_t i = 0; i < (int64_t)hid * hid; ++i) h[o_w2 + i] = (float)(normals[o_w2 + i] / sqrt((double)hid));
+  for (int64_t i = 0; i < (int64_t)out * hid; ++i) h[o_w3 + i] = (float)(normals[o_w3 + i] / sqrt((double)hid));
+  p.alloc(np);
+  g.alloc(np);
+  m.alloc(np);
+  v.alloc(np);
+  RBFL_HIP(hipMemcpy(p.p, h.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+  RBFL_HIP(hipMemset(g.p, 0, sizeof(float) * np));
+  RBFL_HIP(hipMemset(m.p, 0, sizeof(float) * np));
+  RBFL_HIP(hipMemset(v.p, 0, sizeof(float) * np));
+  loss.alloc(1);
+  t = 0;
+}
+
+void Mlp::reserve(int64_t B) {
+  if (B <= cap) return;
+  Z1.alloc((size_t)B * hid);
+  H1.alloc((size_t)B * hid);
+  Z2.alloc((size_t)B * hid);
+  H2.alloc((size_t)B * hid);
+  Yb.alloc((size_t)B * out);
+  dY.alloc((size_t)B * out);
+  dA.alloc((size_t)B * hid);
+  dB.alloc((size_t)B * hid);
+  part.alloc(1024);
+  cap = B;
+}
+
+static void gemm(int act, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
+                 int64_t sbn, const float *bias, float *Z, float *C, int64_t ldc, hipStream_t s) {
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+  if (act)
+    hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(kT), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, Z, C, ldc);
+  else
+    hipLaunchKernelGGL(k_gemm_f32<0>, grid, dim3(kT), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, Z, C, ldc);
+  RBFL_HIP(hipGetLastError());
+}
+
+void Mlp::forward(const float *X, int64_t B, float *Y, hipStream_t s) {
+  reserve(B);
+  const int b = (int)B;
+  gemm(1, b, hid, in, X, in, 1, p.p + o_w1, 1, in, p.p + o_b1, Z1.p, H1.p, hid, s);
+  gemm(1, b, hid, hid, H1.p, hid, 1, p.p + o_w2, 1, hid, p.p + o_b2, Z2.p, H2.p, hid, s);
+  gemm(0, b, out, hid, H2.p, hid, 1, p.p + o_w3, 1, hid, p.p + o_b3, nullptr, Y, out, s);
+}
+
+void Mlp::loss_grad(const float *X, const float *T, int64_t B, hipStream_t s) {
+  reserve(B);
+  const int b = (int)B;
+  forward(X, B, Yb.p, s);
+  const int64_t n = B * out;
+  const int nblk = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
+  hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(kT), 0, s, Yb.p, T, n, (float)(1.0 / (double)n), dY.p, part.p);
+  RBFL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part.p, nblk, 1.0 / (double)n, loss.p);
+  RBFL_HIP(hipGetLastError());
+  // layer 3: dW3 = dY^T H2, db3 = colsum dY, dH2 = dY W3
+  gemm(0, out, hid, b, dY.p, 1, out, H2.p, hid, 1, nullptr, nullptr, g.p + o_w3, hid, s);
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(out)), dim3(kT), 0, s, dY.p, b, out, g.p + o_b3);
+  RBFL_HIP(hipGetLastError());
+  gemm(0, b, hid, out, dY.p, out, 1, p.p + o_w3, hid, 1, nullptr, nullptr, dA.p, hid, s);
+  hipLaunchKernelGGL(k_silu_back, dim3(blocks((int64_t)b * hid)), dim3(kT), 0, s, dA.p, Z2.p, (int64_t)b * hid, dB.p);
+  RBFL_HIP(hipGetLastError());
+  // layer 2: dW2 = dZ2^T H1, db2, dH1 = dZ2 W2
+  gemm(0, hid, hid, b, dB.p, 1, hid, H1.p, hid, 1, nullptr, nullptr, g.p + o_w2, hid, s);
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(hid)), dim3(kT), 0, s, dB.p, b, hid, g.p + o_b2);
+  RBFL_HIP(hipGetLastError());
+  gemm(0, b, hid, hid, dB.p, hid, 1, p.p + o_w2, hid, 1, nullptr, nullptr, dA.p, hid, s);
+  hipLaunchKernelGGL(k_silu_back, dim3(blocks((int64_t)b * hid)), dim3(kT), 0, s, dA.p, Z1.p, (int64_t)b * hid, dB.p);
+  RBFL_HIP(hipGetLastError());
+  // layer 1: dW1 = dZ1^T X, db1
+  gemm(0, hid, in, b, dB.p, 1, hid, X, in, 1, nullptr, nullptr, g.p + o_w1, in, s);
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(hid)), dim3(kT), 0, s, dB.p, b, hid, g.p + o_b1);
+  RBFL_HIP(hipGetLastError());
+}
+
+void Mlp::adam(double lr, double b1, double b2, double eps, hipStream_t s) {
+  ++t;
+  const float bc1 = (float)(1.0 - pow(b1, t)), bc2 = (float)(1.0 - pow(b2, t));
+  hipLaunchKernelGGL(k_adam, dim3(blocks(np)), dim3(kT), 0, s, p.p, g.p, m.p, v.p, np, (float)lr, (float)b1,
+                     (float)b2, (float)eps, bc1, bc2);
+  RBFL_HIP(hipGetLastError());
+}
+
+}  // namespace rbfl

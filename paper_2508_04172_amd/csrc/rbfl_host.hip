@@ -908,6 +908,11 @@ static void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
   c.Y.alloc((size_t)n * c.Kp);
   c.cap = n;
+  if (c.sur) {
+    c.sur_x.alloc((size_t)n * 4);
+    c.sur_y.alloc((size_t)n * c.K);
+    c.sur->reserve(n);
+  }
 }
 
 static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s);
@@ -915,7 +920,7 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
 static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
   require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
   require(n >= 0, "n must be >= 0");
-  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
   if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
   if (n == 0) return;
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
@@ -959,6 +964,16 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
       launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.W32lo.p, 1, c.Y.p, s,
                            c.variant[form]);
       break;
+    case RBFL_FORM_SURROGATE:
+      if (c.sur && c.sur_ok) {
+        launch_sur_inputs(params, ld, b0, nb, c.consts.p, c.sur_x.p, s);
+        c.sur->forward(c.sur_x.p, nb, c.sur_y.p, s);
+        launch_sur_outputs(c.sur_y.p, c.sur_mu.p, c.sur_sd.p, nb, c.K, c.Kp, c.Y.p, s);
+      } else {
+        launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s,
+                             c.variant[RBFL_FORM_FP64]);
+      }
+      break;
     default:
       launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W16.p, c.Y.p, s);
   }
@@ -967,7 +982,7 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
 static void interp(Ctx &c, const double *params, int64_t n, double *out, int form, hipStream_t s) {
   require(params != nullptr && out != nullptr, "params/out is NULL");
   require(n >= 0, "n must be >= 0");
-  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
   if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
   if (n == 0) return;
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
@@ -984,7 +999,7 @@ static void interp(Ctx &c, const double *params, int64_t n, double *out, int for
 // and keeps the fastest for later rbfl_eval/rbfl_interp calls.
 static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStream_t s) {
   require(params != nullptr && n >= 1, "autotune needs proposals");
-  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown or untunable form");
   if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
   const int64_t nb = std::min(c.cap, n);
@@ -1032,6 +1047,92 @@ static void prepare(Ctx &c, int form) {
   RBFL_HIP(hipDeviceSynchronize());
   c.prepared[RBFL_FORM_FP32] = true;
   if (form == RBFL_FORM_SPLIT) c.prepared[RBFL_FORM_SPLIT] = true;
+}
+
+static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
+  require(sp != nullptr, "spec is NULL");
+  require(sp->hidden >= 8 && sp->hidden <= 1024, "hidden must be 8 .. 1024");
+  require(sp->batch >= 1 && sp->batch <= 65536, "batch must be 1 .. 65536");
+  require(sp->epochs >= 1, "epochs must be >= 1");
+  require(sp->init_normals != nullptr && sp->train_params != nullptr, "NULL init or training proposals");
+  require(sp->n_train >= sp->batch, "n_train must be >= batch");
+  require(sp->n_holdout >= 0 && (sp->n_holdout == 0 || sp->holdout_params != nullptr), "held-out proposals");
+  require(std::isfinite(sp->lr) && sp->lr > 0 && sp->beta1 >= 0 && sp->beta1 < 1 && sp->beta2 >= 0 &&
+              sp->beta2 < 1 && sp->adam_eps > 0 && sp->threshold > 0,
+          "Adam settings / threshold");
+  const auto t0 = Clock::now();
+  delete c.sur;
+  c.sur = nullptr;
+  c.sur_ok = false;
+  c.sur = new Mlp();
+  c.sur->init(4, sp->hidden, c.K, sp->init_normals);
+  if (c.cap == 0) reserve(c, 65536);
+  c.sur_x.alloc((size_t)c.cap * 4);
+  c.sur_y.alloc((size_t)c.cap * c.K);
+  c.sur->reserve(std::max<int64_t>(c.cap, sp->batch));
+  // targets: the FP64 interpolant at the training proposals, standardised per column
+  const int64_t n = sp->n_train;
+  DevBuf<double> Ytr;
+  Ytr.alloc((size_t)n * c.K);
+  interp(c, sp->train_params, n, Ytr.p, RBFL_FORM_FP64, s);
+  c.sur_mu.alloc(c.K);
+  c.sur_sd.alloc(c.K);
+  launch_col_stats(Ytr.p, n, c.K, c.sur_mu.p, c.sur_sd.p, s);
+  DevBuf<float> T, X;
+  T.alloc((size_t)n * c.K);
+  X.alloc((size_t)n * 4);
+  launch_standardise(Ytr.p, n, c.K, c.sur_mu.p, c.sur_sd.p, T.p, s);
+  launch_sur_inputs(sp->train_params, n, 0, n, c.consts.p, X.p, s);
+  RBFL_HIP(hipStreamSynchronize(s));
+  Ytr.reset();
+  double first = 0.0, last = 0.0;
+  const int64_t steps = n / sp->batch;
+  for (int ep = 0; ep < sp->epochs; ++ep) {
+    for (int64_t st = 0; st < steps; ++st) {
+      const int64_t b0 = st * sp->batch;
+      c.sur->loss_grad(X.p + b0 * 4, T.p + b0 * c.K, sp->batch, s);
+      c.sur->adam(sp->lr, sp->beta1, sp->beta2, sp->adam_eps, s);
+    }
+    double l = 0.0;
+    RBFL_HIP(hipMemcpyAsync(&l, c.sur->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    if (ep == 0) first = l;
+    last = l;
+  }
+  const double train_s = seconds_since(t0);
+  // held-out judge: ln L through the network against ln L through the interpolant
+  double dmax = std::numeric_limits<double>::infinity(), dmed = dmax;
+  bool accepted = false;
+  if (sp->n_holdout > 0) {
+    const int64_t m = sp->n_holdout;
+    DevBuf<double> l_rbf, l_sur;
+    l_rbf.alloc(m);
+    l_sur.alloc(m);
+    eval(c, sp->holdout_params, m, l_rbf.p, RBFL_FORM_FP64, s);
+    c.sur_ok = true;
+    eval(c, sp->holdout_params, m, l_sur.p, RBFL_FORM_SURROGATE, s);
+    c.sur_ok = false;
+    std::vector<double> a(m), b(m);
+    RBFL_HIP(hipMemcpyAsync(a.data(), l_rbf.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipMemcpyAsync(b.data(), l_sur.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    bool domains = true;
+    std::vector<double> d;
+    for (int64_t i = 0; i < m; ++i) {
+      const bool fa = std::isfinite(a[i]), fb = std::isfinite(b[i]);
+      if (fa != fb) domains = false;
+      if (fa && fb) d.push_back(fabs(a[i] - b[i]));
+    }
+    if (!d.empty()) {
+      std::sort(d.begin(), d.end());
+      dmax = d.back();
+      dmed = d[d.size() / 2];
+    }
+    accepted = domains && !d.empty() && dmax <= sp->threshold;
+  }
+  c.sur_ok = accepted;
+  const double st[8] = {accepted ? 1.0 : 0.0, dmax, dmed, first, last, (double)sp->epochs, train_s, (double)n};
+  for (int i = 0; i < 8; ++i) c.sur_stats[i] = st[i];
 }
 
 static void copy_out(void *out, size_t bytes, const void *src, size_t need) {
@@ -1099,6 +1200,9 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       RBFL_HIP(hipMemcpy(out, c.z_nodes.p, need, hipMemcpyDeviceToHost));
       return;
     }
+    case RBFL_Q_SURROGATE:
+      copy_out(out, bytes, c.sur_stats, sizeof(c.sur_stats));
+      return;
     case RBFL_Q_TUNE: {
       // per form: chosen variant, then 8 timings [ms] (0 = not timed)
       double v[4 * 9];
@@ -1236,6 +1340,10 @@ struct rbfl_ctx {
 
 struct rbfl_plan_ctx {
   rbfl::Plan p;
+};
+
+struct rbfl_mlp_ctx {
+  rbfl::Mlp m;
 };
 
 namespace rbfl {
@@ -1416,6 +1524,71 @@ int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t 
     rbfl::plan_run(hold->p, s);
     RBFL_HIP(hipStreamSynchronize(s));
   });
+}
+
+int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::surrogate_train(h->c, spec, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_surrogate_force(rbfl_handle h, int32_t on) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    if (!h->c.sur) throw rbfl::Error(RBFL_E_STATE, "no surrogate trained");
+    h->c.sur_ok = on ? true : (h->c.sur_stats[0] != 0.0);
+  });
+}
+
+int32_t rbfl_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, const double *normals, rbfl_mlp *out) {
+  return rbfl::guarded([&] {
+    rbfl::require(out != nullptr && normals != nullptr, "NULL argument");
+    rbfl::require(n_in >= 1 && hidden >= 1 && n_out >= 1 && hidden <= 4096 && n_out <= 65536, "sizes");
+    std::unique_ptr<rbfl_mlp_ctx> m(new rbfl_mlp_ctx());
+    m->m.init(n_in, hidden, n_out, normals);
+    *out = m.release();
+  });
+}
+
+int32_t rbfl_mlp_forward(rbfl_mlp m, const float *x, int64_t B, float *y, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(m != nullptr && x != nullptr && y != nullptr && B >= 1 && B <= 65536, "arguments");
+    m->m.forward(x, B, y, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_mlp_loss_grad(rbfl_mlp m, const float *x, const float *t, int64_t B, double *loss, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(m != nullptr && x != nullptr && t != nullptr && B >= 1 && B <= 65536, "arguments");
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->m.loss_grad(x, t, B, s);
+    double l = 0.0;
+    RBFL_HIP(hipMemcpyAsync(&l, m->m.loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+  });
+}
+
+int32_t rbfl_mlp_adam(rbfl_mlp m, double lr, double beta1, double beta2, double eps, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(m != nullptr, "NULL mlp");
+    m->m.adam(lr, beta1, beta2, eps, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_mlp_get(rbfl_mlp m, int32_t what, float *out, size_t bytes) {
+  return rbfl::guarded([&] {
+    rbfl::require(m != nullptr && out != nullptr && (what == 0 || what == 1), "arguments");
+    const size_t need = sizeof(float) * (size_t)m->m.np;
+    rbfl::require(bytes >= need, "output buffer too small");
+    RBFL_HIP(hipDeviceSynchronize());
+    RBFL_HIP(hipMemcpy(out, what == 0 ? m->m.p.p : m->m.g.p, need, hipMemcpyDeviceToHost));
+  });
+}
+
+int32_t rbfl_mlp_destroy(rbfl_mlp m) {
+  return rbfl::guarded([&] { delete m; });
 }
 
 int32_t rbfl_destroy(rbfl_handle h) {

@@ -81,6 +81,23 @@ struct DevBuf {
   }
 };
 
+// Surrogate network in -> H -> H -> out (SiLU), FP32 parameters and Adam
+// state on the device (mlp.hip).
+struct Mlp {
+  int in = 0, hid = 0, out = 0;
+  int64_t np = 0, o_w1 = 0, o_b1 = 0, o_w2 = 0, o_b2 = 0, o_w3 = 0, o_b3 = 0;
+  DevBuf<float> p, g, m, v;
+  DevBuf<float> Z1, H1, Z2, H2, Yb, dY, dA, dB;
+  DevBuf<double> part, loss;
+  int64_t cap = 0;
+  int t = 0;
+  void init(int n_in, int hidden, int n_out, const double *normals);
+  void reserve(int64_t B);
+  void forward(const float *X, int64_t B, float *Y, hipStream_t s);
+  void loss_grad(const float *X, const float *T, int64_t B, hipStream_t s);   // loss -> this->loss
+  void adam(double lr, double b1, double b2, double eps, hipStream_t s);
+};
+
 struct Ctx {
   // sizes and scalars
   int n_det = 0, n_modes = 0;
@@ -106,13 +123,19 @@ struct Ctx {
   DevBuf<float> W32;           // [rows][Kp]
   DevBuf<float> W32lo;         // [rows][Kp] low part of the FP32 split
   DevBuf<uint16_t> W16;        // [rows][Kp] bf16
-  bool prepared[4] = {true, false, false, false};
-  int variant[4] = {0, 0, 0, 0};   // contraction tile variant per form (rbfl_autotune)
-  double tune_ms[4][8] = {};       // last autotune timings per variant
+  bool prepared[5] = {true, false, false, false, true};
+  int variant[5] = {0, 0, 0, 0, 0};   // contraction tile variant per form (rbfl_autotune)
+  double tune_ms[5][8] = {};          // last autotune timings per variant
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   int64_t cap = 0;
   EvalConsts host_consts;
+  // surrogate (rbfl_surrogate_train)
+  Mlp *sur = nullptr;
+  DevBuf<float> sur_mu, sur_sd;       // per-column standardisation of the outputs
+  DevBuf<float> sur_x, sur_y;         // work space [cap][4], [cap][K]
+  bool sur_ok = false;                // held-out check passed
+  double sur_stats[8] = {};
   // optional per-launch timing (rbfl_profile)
   bool profile = false;
   struct Timed {
@@ -122,6 +145,7 @@ struct Ctx {
   };
   std::vector<Timed> timed;
   ~Ctx() {
+    delete sur;
     for (auto &t : timed) {
       (void)hipEventDestroy(t.a);
       (void)hipEventDestroy(t.b);
@@ -168,6 +192,12 @@ void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params,
                             hipStream_t s);
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
+void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
+                       hipStream_t s);
+void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,
+                        hipStream_t s);
+void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s);
+void launch_standardise(const double *Y, int64_t n, int K, const float *mu, const float *sd, float *T, hipStream_t s);
 void launch_convert_weights(const double *W, size_t n, float *hi, float *lo, uint16_t *b16, hipStream_t s);
 
 }  // namespace rbfl

@@ -22,15 +22,17 @@ MAX_MODES = 5
 MAX_DET = 4
 
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NUMERICAL, E_UNSUPPORTED, E_STATE = range(7)
-FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT = range(4)
+FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
 FLAG_CENTER_NODE = 0x1
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE = range(14)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE = range(15)
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
-            "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_destroy")
+            "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
+            "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
+            "rbfl_mlp_destroy", "rbfl_destroy")
 PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
 
 
@@ -64,6 +66,28 @@ class BuildSpec(C.Structure):
         ("chi_max", C.c_double),
         ("flags", C.c_uint32),
     ]
+
+
+class TrainSpec(C.Structure):
+    _fields_ = [
+        ("hidden", C.c_int32),
+        ("batch", C.c_int32),
+        ("epochs", C.c_int32),
+        ("lr", C.c_double),
+        ("beta1", C.c_double),
+        ("beta2", C.c_double),
+        ("adam_eps", C.c_double),
+        ("init_normals", C.POINTER(C.c_double)),
+        ("train_params", C.c_void_p),
+        ("n_train", C.c_int64),
+        ("holdout_params", C.c_void_p),
+        ("n_holdout", C.c_int64),
+        ("threshold", C.c_double),
+    ]
+
+
+def mlp_param_count(n_in: int, hidden: int, n_out: int) -> int:
+    return hidden * n_in + hidden + hidden * hidden + hidden + n_out * hidden + n_out
 
 
 class RbflError(RuntimeError):
@@ -120,6 +144,23 @@ def load(path: str = LIB_PATH):
     lib.rbfl_eval_ragged.restype = C.c_int32
     lib.rbfl_eval_ragged.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
+    lib.rbfl_surrogate_train.restype = C.c_int32
+    lib.rbfl_surrogate_train.argtypes = [C.c_void_p, C.POINTER(TrainSpec), C.c_void_p]
+    lib.rbfl_surrogate_force.restype = C.c_int32
+    lib.rbfl_surrogate_force.argtypes = [C.c_void_p, C.c_int32]
+    lib.rbfl_mlp_create.restype = C.c_int32
+    lib.rbfl_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_void_p)]
+    lib.rbfl_mlp_forward.restype = C.c_int32
+    lib.rbfl_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    lib.rbfl_mlp_loss_grad.restype = C.c_int32
+    lib.rbfl_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_double),
+                                       C.c_void_p]
+    lib.rbfl_mlp_adam.restype = C.c_int32
+    lib.rbfl_mlp_adam.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
+    lib.rbfl_mlp_get.restype = C.c_int32
+    lib.rbfl_mlp_get.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.rbfl_mlp_destroy.restype = C.c_int32
+    lib.rbfl_mlp_destroy.argtypes = [C.c_void_p]
     lib.rbfl_destroy.restype = C.c_int32
     lib.rbfl_destroy.argtypes = [C.c_void_p]
     _lib = lib
@@ -284,6 +325,25 @@ class Handle:
         v = self._query(Q_TUNE, 36).reshape(4, 9)
         return {"variant": int(v[form, 0]), "ms": [float(x) for x in v[form, 1:] if x > 0]}
 
+    def surrogate_train(self, init_normals: np.ndarray, train_ptr: int, n_train: int, holdout_ptr: int,
+                        n_holdout: int, hidden: int = 256, batch: int = 1024, epochs: int = 20, lr: float = 1e-3,
+                        beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8,
+                        threshold: float = 1e-3, stream: int = 0) -> dict:
+        z = np.ascontiguousarray(init_normals, dtype=np.float64)
+        sp = TrainSpec(hidden, batch, epochs, lr, beta1, beta2, adam_eps, _dptr(z), C.c_void_p(train_ptr), n_train,
+                       C.c_void_p(holdout_ptr), n_holdout, threshold)
+        _check(load().rbfl_surrogate_train(self._h, C.byref(sp), C.c_void_p(stream)))
+        return self.surrogate_stats()
+
+    def surrogate_force(self, on: bool):
+        _check(load().rbfl_surrogate_force(self._h, 1 if on else 0))
+
+    def surrogate_stats(self) -> dict:
+        v = self._query(Q_SURROGATE, 8)
+        return {"accepted": bool(v[0]), "holdout_max_dlnl": float(v[1]), "holdout_median_dlnl": float(v[2]),
+                "first_loss": float(v[3]), "last_loss": float(v[4]), "epochs": int(v[5]),
+                "train_s": float(v[6]), "n_train": int(v[7])}
+
     def profile(self, on: bool):
         _check(load().rbfl_profile(self._h, 1 if on else 0))
 
@@ -319,6 +379,46 @@ class Plan:
     def close(self):
         if self._p is not None and self._p.value:
             _check(load().rbfl_plan_destroy(self._p))
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The library's surrogate network on its own (rbfl_mlp_*), FP32 on the device."""
+
+    def __init__(self, n_in: int, hidden: int, n_out: int, normals: np.ndarray):
+        z = np.ascontiguousarray(normals, dtype=np.float64)
+        assert z.size == mlp_param_count(n_in, hidden, n_out)
+        p = C.c_void_p()
+        _check(load().rbfl_mlp_create(n_in, hidden, n_out, _dptr(z), C.byref(p)))
+        self._p = p
+        self.n_params = z.size
+
+    def forward(self, x_ptr: int, B: int, y_ptr: int, stream: int = 0):
+        _check(load().rbfl_mlp_forward(self._p, C.c_void_p(x_ptr), B, C.c_void_p(y_ptr), C.c_void_p(stream)))
+
+    def loss_grad(self, x_ptr: int, t_ptr: int, B: int, stream: int = 0) -> float:
+        l = C.c_double()
+        _check(load().rbfl_mlp_loss_grad(self._p, C.c_void_p(x_ptr), C.c_void_p(t_ptr), B, C.byref(l),
+                                         C.c_void_p(stream)))
+        return l.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream: int = 0):
+        _check(load().rbfl_mlp_adam(self._p, lr, beta1, beta2, eps, C.c_void_p(stream)))
+
+    def get(self, what: int) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().rbfl_mlp_get(self._p, what, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            _check(load().rbfl_mlp_destroy(self._p))
         self._p = None
 
     def __del__(self):

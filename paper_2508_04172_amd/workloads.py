@@ -229,6 +229,11 @@ def node_jitter(n: int, n_nodes: int, sigma: float = 0.03, seed: int = 7):
     return rng.integers(0, n_nodes, n), rng.standard_normal((n, 4)) * sigma
 
 
+def mlp_normals(n_params: int, seed: int = 4) -> np.ndarray:
+    """Standard normal deviates for the surrogate network's initial weights."""
+    return np.random.default_rng(seed).standard_normal(n_params)
+
+
 def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
                   base: Config = CFG2, seg_range=(8.0, 512.0), node_range=(200, 1500),
                   q_range=(20, 60)) -> List[Config]:

@@ -1,0 +1,128 @@
+"""Surrogate network: GPU forward/backward/Adam against the FP64 oracle,
+training, the held-out judge and the RBF fallback, and what the network
+gains over the interpolant it replaces."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_gpu_gradients_and_adam_match_oracle():
+    torch = _torch()
+    n_in, hidden, n_out, B = 4, 48, 37, 96
+    z = wl.mlp_normals(rbfl.mlp_param_count(n_in, hidden, n_out))
+    rng = np.random.default_rng(21)
+    X = rng.uniform(-1, 1, (B, n_in))
+    T = rng.standard_normal((B, n_out))
+    net = rbfl.Mlp(n_in, hidden, n_out, z)
+    xg = torch.from_numpy(X.astype(np.float32)).cuda()
+    tg = torch.from_numpy(T.astype(np.float32)).cuda()
+    yg = torch.empty((B, n_out), dtype=torch.float32, device="cuda")
+    vec = omlp.init_from_normals(z, n_in, hidden, n_out)
+    assert np.allclose(net.get(0), vec, rtol=1e-6, atol=1e-7)
+    net.forward(xg.data_ptr(), B, yg.data_ptr())
+    torch.cuda.synchronize()
+    Yo, _ = omlp.forward(vec, X, n_in, hidden, n_out)
+    assert np.abs(yg.cpu().numpy() - Yo).max() <= 1e-5 * max(1.0, np.abs(Yo).max())
+    loss = net.loss_grad(xg.data_ptr(), tg.data_ptr(), B)
+    Lo, go = omlp.loss_and_grad(vec, X, T, n_in, hidden, n_out)
+    assert loss == pytest.approx(Lo, rel=1e-5)
+    gg = net.get(1)
+    assert np.abs(gg - go).max() <= 1e-4 * np.abs(go).max()
+    net.adam(lr=1e-3)
+    new, _, _ = omlp.adam_step(vec, go, np.zeros_like(vec), np.zeros_like(vec), 1, lr=1e-3)
+    # the first Adam step is ~lr * sign(g): compare where |g| is not at FP32 noise level
+    big = np.abs(go) > 1e-4 * np.abs(go).max()
+    step = np.abs(net.get(0) - new)
+    assert step[big].max() <= 1e-5
+    assert step.max() <= 2.1e-3
+    net.close()
+
+
+def _params_device(torch, h, cfg, n, seed, near=True):
+    if near:
+        idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=seed)
+        qd = wl.queries(cfg, n=n, seed=seed).near_nodes(h.nodes(), idx, jit)
+    else:
+        qd = wl.queries(cfg, n=n, seed=seed)
+    return torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))).cuda()
+
+
+def test_training_judge_and_fallback():
+    torch = _torch()
+    cfg = wl.SMALL_MULTI
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    K = h.sizes()["K"]
+    hidden = 64
+    z = wl.mlp_normals(rbfl.mlp_param_count(4, hidden, K))
+    tr = _params_device(torch, h, cfg, 16384, seed=5)
+    ho = _params_device(torch, h, cfg, 4096, seed=6)
+    st = h.surrogate_train(z, tr.data_ptr(), 16384, ho.data_ptr(), 4096, hidden=hidden, batch=512, epochs=30,
+                           lr=3e-3, threshold=1e-3)
+    print(f"[surrogate] {st}", flush=True)
+    assert st["last_loss"] < 0.8 * st["first_loss"]     # the network learns (but underfits: see the design doc)
+    n = 4096
+    lf = torch.empty(n, dtype=torch.float64, device="cuda")
+    ls = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.eval(ho.data_ptr(), n, lf.data_ptr(), rbfl.FORM_FP64)
+    h.eval(ho.data_ptr(), n, ls.data_ptr(), rbfl.FORM_SURROGATE)
+    torch.cuda.synchronize()
+    a, b = lf.cpu().numpy(), ls.cpu().numpy()
+    if not st["accepted"]:
+        # rejected: the surrogate form is the interpolant, exactly
+        assert np.array_equal(np.isfinite(a), np.isfinite(b))
+        fin = np.isfinite(a)
+        assert np.array_equal(a[fin], b[fin])
+    # a loose bar accepts, and the surrogate form then runs the network
+    st2 = h.surrogate_train(z, tr.data_ptr(), 16384, ho.data_ptr(), 4096, hidden=hidden, batch=512, epochs=30,
+                            lr=3e-3, threshold=1e12)
+    assert st2["accepted"]
+    h.eval(ho.data_ptr(), n, ls.data_ptr(), rbfl.FORM_SURROGATE)
+    torch.cuda.synchronize()
+    b = ls.cpu().numpy()
+    fin = np.isfinite(a) & np.isfinite(b)
+    d = np.abs(a[fin] - b[fin])
+    assert d.max() == pytest.approx(st2["holdout_max_dlnl"], rel=1e-9)
+    assert d.max() > 0.0
+
+
+def test_surrogate_gain_over_interpolant():
+    """Throughput of the network path against the FP64 interpolant it
+    replaces, on the same proposals (accuracy is what the judge reports)."""
+    torch = _torch()
+    cfg = wl.SMALL_MULTI.with_(n_nodes=400)
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    K = h.sizes()["K"]
+    z = wl.mlp_normals(rbfl.mlp_param_count(4, 64, K))
+    tr = _params_device(torch, h, cfg, 8192, seed=5)
+    ho = _params_device(torch, h, cfg, 2048, seed=6)
+    st = h.surrogate_train(z, tr.data_ptr(), 8192, ho.data_ptr(), 2048, hidden=64, batch=512, epochs=5,
+                           threshold=1e12)
+    assert st["accepted"]
+    n = 262144
+    p = _params_device(torch, h, cfg, n, seed=8)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    times = {}
+    for name, form in (("fp64", rbfl.FORM_FP64), ("surrogate", rbfl.FORM_SURROGATE)):
+        h.eval(p.data_ptr(), n, out.data_ptr(), form)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            h.eval(p.data_ptr(), n, out.data_ptr(), form)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t) / 5
+    print(f"[surrogate] evals/s fp64 {n / times['fp64']:.3e}, surrogate {n / times['surrogate']:.3e}, "
+          f"held-out max |dlnL| {st['holdout_max_dlnl']:.3e}", flush=True)
+    assert np.isfinite(times["surrogate"])
