@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ln L evals/s at |dlnL|<=1e-3 vs FP64 oracle: plain vs mixed/batched/surrogate"
 PEAK_FP64 = 78.6e12     # dense FP64 MFMA, MI355X
 PEAK_FP32 = 157.3e12    # dense FP32 MFMA, MI355X
+PEAK_INT8 = 5.0e15      # dense int8 MFMA, MI355X
 
 
 def log(msg):
@@ -46,6 +47,8 @@ def main():
     ap.add_argument("--surrogate-train", type=int, default=200000,
                     help="training proposals for the surrogate form (0 = skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one elementwise 512 MiB copy kernel (known bytes, for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
@@ -67,6 +70,13 @@ def main():
     white = wl.white_noise(cfg)
     inj = wl.injection_extrinsics(cfg)
 
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")     # 512 MiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)       # one elementwise kernel: 512 MiB read, 512 MiB written
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 512 MiB read + 512 MiB written")
     log("GPU start-up (rbfl_build)")
     t0 = time.time()
     h = rbfl.Handle.from_config(cfg, white, inj)
@@ -83,7 +93,7 @@ def main():
     sp = stream.cuda_stream
     h.reserve(65536)
     tune = {}
-    for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32)):
+    for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32), ("split", rbfl.FORM_SPLIT)):
         if form != rbfl.FORM_FP64:
             h.prepare(form)
         tune[name] = h.autotune(params.data_ptr(), n, form, sp)
@@ -119,14 +129,21 @@ def main():
                       "contract_tflops": achieved / 1e12,
                       "epilogue_ms_per_launch": ks["epilogue_ms"] / max(1, ks["epilogue_launches"])}}
     outs = {"fp64": l64}
-    for name, form in (("fp32", rbfl.FORM_FP32),):
+    for name, form in (("fp32", rbfl.FORM_FP32), ("split", rbfl.FORM_SPLIT)):
         w2, ks2, lf = run_form(form, max(3, args.steps // 2), 1)
         v2 = n * max(3, args.steps // 2) / w2
         c2 = ks2["contract_ms"] / max(1, ks2["contract_launches"])
         forms[name] = {"evals_per_s": v2, "ms_per_step": w2 / max(3, args.steps // 2) * 1e3,
+                       "contract_ms_per_launch": c2,
                        "contract_tflops": flop_per_query * per_launch_n / (c2 * 1e-3) / 1e12}
+        if form == rbfl.FORM_SPLIT:
+            # int8 products actually issued: one per slice pair i + j < S
+            S = tune["split"]["slices"]
+            pairs = S * (S + 1) // 2
+            tops = pairs * flop_per_query * per_launch_n / (c2 * 1e-3)
+            forms[name].update({"slices": S, "int8_tops": tops / 1e12, "int8_frac": tops / PEAK_INT8})
         outs[name] = lf
-        log(f"{name}: {v2:.4e} evals/s")
+        log(f"{name}: {v2:.4e} evals/s, contraction {c2:.3f} ms/launch")
 
     if args.surrogate_train > 0:
         forms["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64)

@@ -50,7 +50,12 @@ enum rbfl_form {
   RBFL_FORM_FP64 = 0,       /* plain: FP64 kernel rows, FP64 MFMA contraction, FP64 epilogue */
   RBFL_FORM_FP32 = 1,       /* FP32 kernel rows and FP32 MFMA contraction, FP64 epilogue */
   RBFL_FORM_BF16 = 2,       /* BF16 operands, FP32-accumulating MFMA, FP64 epilogue */
-  RBFL_FORM_SPLIT = 3,      /* FP32 kernel rows, hi/lo FP32 split of the weights (two FP32 MFMA products) */
+  RBFL_FORM_SPLIT = 3,      /* error-free split products: FP64 kernel rows and weight columns, each
+                               scaled by a power of two into [-1, 1], cut into S int8 slices of 7
+                               bits; every slice pair i + j < S on int8 MFMA with exact int32 sums
+                               per level, levels combined in FP64 (per kernel row at most
+                               (S + 3) 2^(-7S) of the two scales); FP64 epilogue.  S is chosen by
+                               rbfl_autotune (default 8) */
   RBFL_FORM_SURROGATE = 4   /* trained surrogate network in place of the interpolant contraction, FP64
                                epilogue; the FP64 interpolant when no surrogate passed its held-out check */
 };
@@ -182,16 +187,24 @@ enum rbfl_query_what {
                                on (synchronises the recorded events; resets the sums) */
   RBFL_Q_TUNE = 13,         /* double[4][9]: per form, the chosen contraction tile variant and the
                                autotuner's median time [ms] of each variant (0 = not timed) */
-  RBFL_Q_SURROGATE = 14     /* double[8]: accepted (1/0), held-out max |d ln L|, held-out median
+  RBFL_Q_SURROGATE = 14,    /* double[8]: accepted (1/0), held-out max |d ln L|, held-out median
                                |d ln L|, first-epoch loss, last-epoch loss, epochs, training seconds,
                                training proposals */
+  RBFL_Q_SPLIT_ERR = 15     /* double[8]: per split-form variant, max |d ln L| against the FP64 form
+                               on the last rbfl_autotune's proposals (0 = not measured) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
 /* Tile autotuner: times each contraction tile variant of `form` on the
  * first min(n, work capacity) proposals of `params` (device [11][n]) with HIP
  * events on `stream` and keeps the fastest for this handle (RBFL_Q_TUNE
- * reports the timings).  Synchronous; needs exclusive use of the handle. */
+ * reports the timings).  Split-form variants differ in slice count S (5..8,
+ * variant v has S = 5 + v/2): only those whose ln L on these proposals stays
+ * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
+ * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible, or
+ * without autotuning, the split form uses S = 8.  Synchronous; needs
+ * exclusive use of the handle. */
+#define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it

@@ -908,6 +908,10 @@ static void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
   c.Y.alloc((size_t)n * c.Kp);
   c.cap = n;
+  if (c.prepared[RBFL_FORM_SPLIT]) {
+    c.AS.alloc((size_t)split_max_slices() * n * c.rows);
+    c.ASscale.alloc(n);
+  }
   if (c.sur) {
     c.sur_x.alloc((size_t)n * 4);
     c.sur_y.alloc((size_t)n * c.K);
@@ -957,12 +961,12 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
                            c.variant[form]);
       break;
     case RBFL_FORM_FP32:
-      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, nullptr, 0, c.Y.p, s,
+      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.Y.p, s,
                            c.variant[form]);
       break;
     case RBFL_FORM_SPLIT:
-      launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.W32lo.p, 1, c.Y.p, s,
-                           c.variant[form]);
+      launch_contract_split(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.AS.p, c.ASscale.p, c.WS.p, c.WSscale.p,
+                            c.Y.p, s, c.variant[form]);
       break;
     case RBFL_FORM_SURROGATE:
       if (c.sur && c.sur_ok) {
@@ -997,21 +1001,54 @@ static void interp(Ctx &c, const double *params, int64_t n, double *out, int for
 // Times every contraction tile variant of `form` on the first min(n, work
 // capacity) proposals of `params` (HIP events, median of 3 after a warm-up)
 // and keeps the fastest for later rbfl_eval/rbfl_interp calls.
+// ln L of the first nb proposals with the current variant of `form`, to host.
+static std::vector<double> lnl_probe(Ctx &c, const double *params, int64_t n, int64_t nb, int form, double *dev,
+                                     hipStream_t s) {
+  contract(c, params, n, 0, nb, form, s);
+  launch_epilogue(c.consts.p, c.host_consts, params, n, 0, nb, c.Y.p, c.basis.p, dev, s);
+  std::vector<double> h(nb);
+  RBFL_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
 static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStream_t s) {
   require(params != nullptr && n >= 1, "autotune needs proposals");
   if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown or untunable form");
   if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
   const int64_t nb = std::min(c.cap, n);
-  const int nv = contract_variants(form == RBFL_FORM_SPLIT ? RBFL_FORM_FP32 : form);
+  const int nv = contract_variants(form);
+  // The split form's slice count sets its accuracy: a variant is eligible
+  // only if its ln L stays within RBFL_SPLIT_TOL of the FP64 form's on these
+  // proposals (same domain flags, finite entries compared).
+  std::vector<double> ref;
+  DevBuf<double> probe;
+  if (form == RBFL_FORM_SPLIT) {
+    probe.alloc(nb);
+    ref = lnl_probe(c, params, n, nb, RBFL_FORM_FP64, probe.p, s);
+  }
   hipEvent_t e0, e1;
   RBFL_HIP(hipEventCreate(&e0));
   RBFL_HIP(hipEventCreate(&e1));
-  int best = 0;
+  int best = -1;
   double best_ms = 1e300;
-  const int saved = c.variant[form];
   for (int v = 0; v < nv && v < 8; ++v) {
     c.variant[form] = v;
+    bool eligible = true;
+    if (form == RBFL_FORM_SPLIT) {
+      const std::vector<double> got = lnl_probe(c, params, n, nb, form, probe.p, s);
+      double err = 0.0;
+      for (int64_t i = 0; i < nb; ++i) {
+        if (std::isfinite(ref[i]) != std::isfinite(got[i]) || std::isnan(ref[i]) != std::isnan(got[i])) {
+          err = INFINITY;
+          break;
+        }
+        if (std::isfinite(ref[i])) err = std::max(err, std::fabs(got[i] - ref[i]));
+      }
+      c.split_err[v] = err;
+      eligible = err <= RBFL_SPLIT_TOL;
+    }
     contract(c, params, n, 0, nb, form, s);   // warm-up
     double t[3];
     for (int r = 0; r < 3; ++r) {
@@ -1025,13 +1062,12 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     }
     std::sort(t, t + 3);
     c.tune_ms[form][v] = t[1];
-    if (t[1] < best_ms) {
+    if (eligible && t[1] < best_ms) {
       best_ms = t[1];
       best = v;
     }
   }
-  (void)saved;
-  c.variant[form] = best;
+  c.variant[form] = best >= 0 ? best : kSplitDefaultVariant;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -1041,12 +1077,22 @@ static void prepare(Ctx &c, int form) {
   if (c.prepared[form]) return;
   const size_t n = (size_t)c.rows * c.Kp;
   if (form == RBFL_FORM_BF16) throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
+  if (form == RBFL_FORM_SPLIT) {
+    c.WS.alloc((size_t)split_max_slices() * c.Kp * c.rows);
+    c.WSscale.alloc(c.Kp);
+    launch_split_prepare(c.W.p, c.rows, c.Kp, c.WSscale.p, c.WS.p, 0);
+    if (c.cap == 0) reserve(c, 65536);
+    c.AS.alloc((size_t)split_max_slices() * c.cap * c.rows);
+    c.ASscale.alloc(c.cap);
+    RBFL_HIP(hipDeviceSynchronize());
+    c.variant[RBFL_FORM_SPLIT] = kSplitDefaultVariant;
+    c.prepared[RBFL_FORM_SPLIT] = true;
+    return;
+  }
   if (!c.W32.p) c.W32.alloc(n);
-  if (form == RBFL_FORM_SPLIT && !c.W32lo.p) c.W32lo.alloc(n);
-  launch_convert_weights(c.W.p, n, c.W32.p, form == RBFL_FORM_SPLIT ? c.W32lo.p : nullptr, nullptr, 0);
+  launch_convert_weights(c.W.p, n, c.W32.p, nullptr, 0);
   RBFL_HIP(hipDeviceSynchronize());
   c.prepared[RBFL_FORM_FP32] = true;
-  if (form == RBFL_FORM_SPLIT) c.prepared[RBFL_FORM_SPLIT] = true;
 }
 
 static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
@@ -1213,6 +1259,9 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       copy_out(out, bytes, v, sizeof(v));
       return;
     }
+    case RBFL_Q_SPLIT_ERR:
+      copy_out(out, bytes, c.split_err, sizeof(c.split_err));
+      return;
     case RBFL_Q_KERNEL_STATS: {
       double v[6] = {0, 0, 0, 0, 0, 0};
       for (auto &t : c.timed) {

@@ -121,11 +121,15 @@ struct Ctx {
   DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
-  DevBuf<float> W32lo;         // [rows][Kp] low part of the FP32 split
   DevBuf<uint16_t> W16;        // [rows][Kp] bf16
+  DevBuf<int8_t> WS;           // split form: weight slices [S][Kp][rows]
+  DevBuf<double> WSscale;      // split form: power-of-two column scales [Kp]
+  DevBuf<int8_t> AS;           // split form: kernel-row slices of one chunk [S][cap][rows]
+  DevBuf<double> ASscale;      // split form: power-of-two row scales of one chunk [cap]
   bool prepared[5] = {true, false, false, false, true};
   int variant[5] = {0, 0, 0, 0, 0};   // contraction tile variant per form (rbfl_autotune)
   double tune_ms[5][8] = {};          // last autotune timings per variant
+  double split_err[8] = {};           // last split autotune: max |d ln L| vs the FP64 form per variant
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   int64_t cap = 0;
@@ -179,8 +183,8 @@ void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const doubl
                           int64_t b0, int64_t nb, const double *nodes, const double *W, double *Y,
                           hipStream_t s, int variant);
 void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
-                          int64_t b0, int64_t nb, const double *nodes, const float *W, const float *Wlo,
-                          int split, double *Y, hipStream_t s, int variant);
+                          int64_t b0, int64_t nb, const double *nodes, const float *W, double *Y, hipStream_t s,
+                          int variant);
 void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const uint16_t *W, double *Y,
                           hipStream_t s);
@@ -192,12 +196,19 @@ void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params,
                             hipStream_t s);
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
+int split_max_slices();
+int split_variant_slices(int variant);
+constexpr int kSplitDefaultVariant = 6;    // 8 slices: within a few units of FP64 rounding
+void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8_t *BS, hipStream_t s);
+void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                           int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                           const double *scale, double *Y, hipStream_t s, int variant);
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s);
 void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,
                         hipStream_t s);
 void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s);
 void launch_standardise(const double *Y, int64_t n, int K, const float *mu, const float *sd, float *T, hipStream_t s);
-void launch_convert_weights(const double *W, size_t n, float *hi, float *lo, uint16_t *b16, hipStream_t s);
+void launch_convert_weights(const double *W, size_t n, float *hi, uint16_t *b16, hipStream_t s);
 
 }  // namespace rbfl

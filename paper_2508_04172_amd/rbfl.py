@@ -26,7 +26,8 @@ FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
 FLAG_CENTER_NODE = 0x1
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE = range(15)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR = range(16)
+SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
@@ -323,7 +324,11 @@ class Handle:
     def autotune(self, params_ptr: int, n: int, form: int = FORM_FP64, stream: int = 0) -> dict:
         _check(load().rbfl_autotune(self._h, C.c_void_p(params_ptr), n, form, C.c_void_p(stream)))
         v = self._query(Q_TUNE, 36).reshape(4, 9)
-        return {"variant": int(v[form, 0]), "ms": [float(x) for x in v[form, 1:] if x > 0]}
+        out = {"variant": int(v[form, 0]), "ms": [float(x) for x in v[form, 1:] if x > 0]}
+        if form == FORM_SPLIT:
+            out["slices"] = split_slices(out["variant"])
+            out["max_dlnl_vs_fp64"] = [float(x) for x in self._query(Q_SPLIT_ERR, 8)]
+        return out
 
     def surrogate_train(self, init_normals: np.ndarray, train_ptr: int, n_train: int, holdout_ptr: int,
                         n_holdout: int, hidden: int = 256, batch: int = 1024, epochs: int = 20, lr: float = 1e-3,
@@ -351,6 +356,11 @@ class Handle:
         v = self._query(Q_KERNEL_STATS, 6)
         return {"contract_ms": v[0], "contract_launches": int(v[1]), "contract_n": int(v[2]),
                 "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5])}
+
+
+def split_slices(variant: int) -> int:
+    """Slice count S of a split-form contraction variant."""
+    return 5 + variant // 2
 
 
 class Plan:

@@ -1,0 +1,131 @@
+"""Mixed-precision contraction forms against the FP64 oracle.
+
+Split form: every product of int8 slices is summed exactly in int32, so its
+only errors are the dropped slice pairs and the slice remainders, at most
+(S + 3) 2^(-7S) of s_q s_c per kernel row (s_q, s_c the power-of-two scales
+of the proposal's row and of the weight column).  With its default S = 8 it
+is held to the FP64 bars: |d ln L| <= 1e-3 and, per interpolated column, the
+FP64 bar widened by that worst-case bound.  After rbfl_autotune (which keeps
+only slice counts within 1e-4 of the FP64 form on the tuning proposals) it is
+held to 1e-3 against the oracle on other proposals.
+
+FP32 form: reported, not held to 1e-3 (its FP32 kernel rows and sums lose
+what the interpolant's cancellation amplifies); the test checks only that it
+runs, keeps the FP64 domain flags and stays finite where they are set.
+"""
+import numpy as np
+import pytest
+
+from oracle import likelihood as lk
+from oracle import startup as su
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+from test_gpu_parity import CASES, both, column_scale, gpu_eval, gpu_interp
+
+pytestmark = pytest.mark.gpu
+
+SLICES = 8      # the split form's slice count until rbfl_autotune picks one
+
+
+def _prepared(name, form):
+    cfg, art, h = both(name)
+    h.prepare(form)
+    return cfg, art, h
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_interpolant(name):
+    cfg, art, h = _prepared(name, rbfl.FORM_SPLIT)
+    qd = wl.queries(cfg, n=min(cfg.n_queries, 2000))
+    Ys = gpu_interp(h, qd, cfg.t_trig, rbfl.FORM_SPLIT)
+    Yd = gpu_interp(h, qd, cfg.t_trig, rbfl.FORM_FP64)
+    Yo = lk.rbf_eval(art, qd.x)
+    col_scale = column_scale(art)
+    basis = np.concatenate([su.gaussian_kernel(qd.x, art.x_nodes, art.eps), su.poly_matrix(qd.x, art.degree)], 1)
+    amp = (np.abs(basis) @ np.abs(art.W)).max(axis=0) / col_scale
+    # worst case of the split arithmetic: power-of-two scales bound |W_rc| and |B_r|
+    s_c = 2.0 ** np.ceil(np.log2(np.maximum(np.abs(art.W).max(axis=0), 1e-300)))
+    s_q = 2.0 ** np.ceil(np.log2(np.maximum(1.0, np.abs(basis).max(axis=1))))
+    split_bound = (SLICES + 3) * 2.0 ** (-7 * SLICES) * basis.shape[1] * s_q.max() * s_c / col_scale
+    bar = np.maximum(1e-6, 1e-13 * amp) + split_bound
+    err = np.abs(Ys - Yo).max(axis=0) / col_scale
+    vs64 = np.abs(Ys - Yd).max(axis=0) / col_scale
+    print(f"[mixed] {name} split: max column-relative error vs oracle {err.max():.3e}, "
+          f"vs the FP64 form {vs64.max():.3e}", flush=True)
+    assert np.all(err <= bar), f"column {int(np.argmax(err / bar))}: {err.max():.3e}"
+    assert np.all(np.abs(Ys - Yd).max(axis=0) <= split_bound * col_scale + 1e-15 * amp * col_scale)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_lnl(name):
+    cfg, art, h = _prepared(name, rbfl.FORM_SPLIT)
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    for label, qg, qo in (("uniform", qd, qd),
+                          ("near nodes", qd.near_nodes(h.nodes(), idx, jit), qd.near_nodes(art.x_nodes, idx, jit))):
+        lg = gpu_eval(h, qg, cfg.t_trig, rbfl.FORM_SPLIT)
+        lo = lk.meshfree_lnl(art, *lk.query_params(art, qo))
+        fin = np.isfinite(lo)
+        assert np.array_equal(fin, np.isfinite(lg))
+        d = np.abs(lg[fin] - lo[fin])
+        print(f"[mixed] {name} split {label}: {fin.sum()} valid, max |dlnL| {d.max():.3e}, "
+              f"median {np.median(d):.3e}", flush=True)
+        assert d.max() <= 1e-3
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_reported(name):
+    cfg, art, h = _prepared(name, rbfl.FORM_FP32)
+    qd = wl.queries(cfg, n=min(cfg.n_queries, 3000))
+    lg = gpu_eval(h, qd, cfg.t_trig, rbfl.FORM_FP32)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isinf(lg) == False)  # noqa: E712
+    assert not np.isnan(lg).any()
+    d = np.abs(lg[fin] - lo[fin])
+    q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    print(f"[mixed] {name} fp32: |dlnL| median {q[0]:.3e}, 90% {q[1]:.3e}, 99% {q[2]:.3e}, max {q[3]:.3e}",
+          flush=True)
+
+
+def test_split_chunked_matches_single_pass():
+    """Batches above the work-space capacity give the same split-form results
+    as one pass (the slice buffer is re-filled per chunk)."""
+    cfg, art, h = _prepared("small_multi", rbfl.FORM_SPLIT)
+    qd = wl.queries(cfg, n=70000, seed=9)
+    l1 = gpu_eval(h, qd, cfg.t_trig, rbfl.FORM_SPLIT)
+    idx = np.arange(0, 70000, 997)
+    l2 = gpu_eval(h, qd.subset(idx), cfg.t_trig, rbfl.FORM_SPLIT)
+    ok = np.isfinite(l2)
+    assert np.array_equal(np.isfinite(l1[idx]), ok)
+    assert np.array_equal(l1[idx][ok], l2[ok])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_autotuned_slices(name):
+    """The autotuner's slice count: within 1e-4 of the FP64 form on its own
+    proposals, within 1e-3 of the oracle on a fresh seeded set."""
+    cfg, art, h = _prepared(name, rbfl.FORM_SPLIT)
+    torch = pytest.importorskip("torch")
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=17)
+    qd = wl.queries(cfg, n=n, seed=5)
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit),
+                                                              cfg.t_trig))).cuda()
+    tune = h.autotune(p.data_ptr(), n, rbfl.FORM_SPLIT, torch.cuda.current_stream().cuda_stream)
+    errs = tune["max_dlnl_vs_fp64"]
+    print(f"[mixed] {name} split autotune: S = {tune['slices']}, max |dlnL| vs FP64 per variant "
+          f"{['%.1e' % e for e in errs]}, ms {['%.3f' % m for m in tune['ms']]}", flush=True)
+    assert errs[tune["variant"]] <= rbfl.SPLIT_TOL
+    # the 8-slice variants (6, 7) sit within a few units of FP64 rounding
+    assert errs[6] <= rbfl.SPLIT_TOL and errs[7] <= rbfl.SPLIT_TOL
+    qd2 = wl.queries(cfg, n=n, seed=11)
+    lg = gpu_eval(h, qd2, cfg.t_trig, rbfl.FORM_SPLIT)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd2))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg))
+    d = np.abs(lg[fin] - lo[fin])
+    print(f"[mixed] {name} split S = {tune['slices']} on fresh proposals: max |dlnL| {d.max():.3e}", flush=True)
+    assert d.max() <= 1e-3
