@@ -51,11 +51,11 @@ enum rbfl_form {
   RBFL_FORM_FP32 = 1,       /* FP32 kernel rows and FP32 MFMA contraction, FP64 epilogue */
   RBFL_FORM_BF16 = 2,       /* BF16 operands, FP32-accumulating MFMA, FP64 epilogue */
   RBFL_FORM_SPLIT = 3,      /* error-free split products: FP64 kernel rows and weight columns, each
-                               scaled by a power of two into [-1, 1], cut into S int8 slices of 7
-                               bits; every slice pair i + j < S on int8 MFMA with exact int32 sums
-                               per level, levels combined in FP64 (per kernel row at most
-                               (S + 3) 2^(-7S) of the two scales); FP64 epilogue.  S is chosen by
-                               rbfl_autotune (default 8) */
+                               scaled by a power of two into [-1, 1], written in S signed base-254
+                               int8 digits; every digit pair i + j < S on int8 MFMA with exact int32
+                               sums per level, levels combined in FP64 (per kernel row at most
+                               (S + 3) 254^-S of the two scales); FP64 epilogue.  S is chosen by
+                               rbfl_autotune (default 7).  Needs N + M <= 16384 */
   RBFL_FORM_SURROGATE = 4   /* trained surrogate network in place of the interpolant contraction, FP64
                                epilogue; the FP64 interpolant when no surrogate passed its held-out check */
 };
@@ -161,7 +161,8 @@ int32_t rbfl_eval(rbfl_handle h, const double *params, int64_t n, double *lnl, i
 int32_t rbfl_interp(rbfl_handle h, const double *params, int64_t n, double *out, int32_t form, void *stream);
 
 /* Converts the weights for a reduced-precision form (RBFL_FORM_FP32/BF16/SPLIT).
- * Synchronous; needs exclusive use of the handle. */
+ * Synchronous; needs exclusive use of the handle.  RBFL_E_UNSUPPORTED for a
+ * form this build or this handle's size does not support. */
 int32_t rbfl_prepare(rbfl_handle h, int32_t form);
 
 /* Pre-allocates work space for batches of up to n proposals (optional). */
@@ -198,11 +199,11 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 /* Tile autotuner: times each contraction tile variant of `form` on the
  * first min(n, work capacity) proposals of `params` (device [11][n]) with HIP
  * events on `stream` and keeps the fastest for this handle (RBFL_Q_TUNE
- * reports the timings).  Split-form variants differ in slice count S (5..8,
- * variant v has S = 5 + v/2): only those whose ln L on these proposals stays
+ * reports the timings).  Split-form variants differ in digit count S (5..8,
+ * variant v has S = 5 + v): only those whose ln L on these proposals stays
  * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
  * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible, or
- * without autotuning, the split form uses S = 8.  Synchronous; needs
+ * without autotuning, the split form uses S = 7.  Synchronous; needs
  * exclusive use of the handle. */
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);

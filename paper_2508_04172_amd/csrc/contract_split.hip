@@ -1,0 +1,298 @@
+// Split form of the interpolant contraction Y = [Phi | P] W (Eq. rbfcoeff)
+// on the int8 matrix cores, exact up to the truncation of its operands.
+//
+// Digits.  A real v with |v| <= 1 is written in signed base-254 digits,
+//   v = sum_i a_i u_i + rest,  u_i = 1 / (127 * 254^i),  |a_i| <= 127,
+// a_0 = rint(127 v), then repeatedly r <- 254 r - a_i (one FMA, remainder in
+// [-1/2, 1/2]) and a_{i+1} = rint(254 r).  After S digits |rest| <= u_{S-1}/2
+// = 254^-S (the FMA rounding adds ~2^-54 of a digit unit per step).  The
+// digits of a value do not depend on S: the weights are cut once into
+// kMaxSlices digits and an S-digit variant reads the first S.
+//
+// Scales.  Each proposal's kernel row is divided by a power of two s_q above
+// max_r |B_r(x_q)| (Gaussian rows are at most 1; the M monomials are
+// evaluated), each weight column by a power of two s_c above max_r |W_rc|.
+//
+// Products.  sum_r B_r W_rc = s_q s_c sum_l 254^-l D_l / 127^2 with
+// D_l = sum_{i+j=l} sum_r a_i(r) b_j(r).  Every D_l with l < S is an exact
+// int32 sum on the MFMA (at most 8 pairs * rows * 127^2 < 2^31 for
+// rows <= 16384); the levels are combined once in FP64.  Dropping the pairs
+// with i + j >= S and the digit remainders costs at most (S + 3) 254^-S of
+// s_q s_c per kernel row.
+//
+// Tiles.  A workgroup of 4 waves (2 x 2) computes 64 proposals x 64 columns;
+// each wave one 32 x 32 tile with v_mfma_i32_32x32x32_i8, whose lane l holds
+// A[l%32][16(l/32) + e] and B[16(l/32) + e][l%32] (e < 16, 16 int8 in 4
+// VGPRs) and accumulator element i = D[8(i/4) + 4(l/32) + i%4][l%32]
+// (measured on gfx950).  Digits of 32 kernel rows of both operands are
+// staged through LDS per step, double-buffered, the next step's global loads
+// in flight during the current step's MFMAs.
+//
+// Memory layout of the digits (16-row groups g, G = rows / 16 of them):
+//   rows   AS[i][g][q][16]   (q < nb, one chunk of proposals)
+//   weights BS[j][g][c][16]  (c < Kp)
+// so a workgroup's stage is one contiguous 1 KiB run per (digit, group).
+#include "basis_rows.h"
+#include "rbfl_internal.h"
+
+namespace rbfl {
+
+namespace {
+
+constexpr int kMaxSlices = 8;
+constexpr int kSplitQ = 64;      // proposals per workgroup
+constexpr int kSplitC = 64;      // columns per workgroup
+constexpr int kSplitThreads = 256;
+constexpr int kMaxSplitRows = 16384;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Base-254 digits of v (|v| <= 1), packed one per byte.
+template <int S>
+__device__ __forceinline__ void digits(double v, int8_t out[S]) {
+  double a = fmin(127.0, fmax(-127.0, rint(v * 127.0)));
+  out[0] = (int8_t)a;
+  double r = fma(v, 127.0, -a);
+#pragma unroll
+  for (int i = 1; i < S; ++i) {
+    a = fmin(127.0, fmax(-127.0, rint(r * 254.0)));
+    out[i] = (int8_t)a;
+    r = fma(r, 254.0, -a);
+  }
+}
+
+__device__ __forceinline__ v4i pack16(const int8_t *b) {
+  v4i v;
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    v[w] = (int)(uint8_t)b[4 * w] | ((int)(uint8_t)b[4 * w + 1] << 8) | ((int)(uint8_t)b[4 * w + 2] << 16) |
+           ((int)(uint8_t)b[4 * w + 3] << 24);
+  return v;
+}
+
+// The first S digits of the kernel rows of nb proposals and their row scales.
+// Thread t = g * nb + q: proposal q, rows 16g .. 16g + 15.
+template <int S>
+__global__ void __launch_bounds__(256) k_split_rows(const EvalConsts *__restrict__ cp,
+                                                    const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                    int64_t nb, const double *__restrict__ nodes,
+                                                    v4i *__restrict__ AS, double *__restrict__ rscale) {
+  const EvalConsts &c = *cp;
+  const int G = c.rows / 16;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)G * nb) return;
+  const int g = (int)(t / nb);
+  const int64_t q = t - (int64_t)g * nb;
+  double x[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) x[d] = params[d * ld + b0 + q] / c.semi[d];
+  const int N = c.N, NM = c.N + c.M;
+  double bound = 1.0;
+  for (int p = 0; p < c.M; ++p) bound = fmax(bound, fabs(basis_row_fp64(N + p, N, NM, x, nodes, c.eps2, c.poly_idx)));
+  int e = 0;
+  frexp(bound, &e);
+  const double inv = ldexp(1.0, -e);
+  if (g == 0) rscale[q] = ldexp(1.0, e);
+  int8_t dg[S][16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = 16 * g + k;
+    int8_t a[S];
+    digits<S>(basis_row_fp64(r, N, NM, x, nodes + 4 * (int64_t)r, c.eps2, c.poly_idx) * inv, a);
+#pragma unroll
+    for (int i = 0; i < S; ++i) dg[i][k] = a[i];
+  }
+#pragma unroll
+  for (int i = 0; i < S; ++i) AS[((int64_t)i * G + g) * nb + q] = pack16(dg[i]);
+}
+
+// Power-of-two scale of each weight column: 2^e > max_r |W[r][c]|.
+__global__ void __launch_bounds__(256) k_col_scale(const double *__restrict__ W, int rows, int Kp,
+                                                   double *__restrict__ scale) {
+  const int col = blockIdx.x;
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) m = fmax(m, fabs(W[(int64_t)r * Kp + col]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int e = 0;
+    const double mx = red[0];
+    if (mx > 0.0) frexp(mx, &e);
+    scale[col] = mx > 0.0 ? ldexp(1.0, e) : 1.0;
+  }
+}
+
+// All kMaxSlices digits of the scaled weights.  Thread t = g * Kp + col.
+__global__ void __launch_bounds__(256) k_split_weights(const double *__restrict__ W, int rows, int Kp,
+                                                       const double *__restrict__ scale, v4i *__restrict__ BS) {
+  const int G = rows / 16;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)G * Kp) return;
+  const int g = (int)(t / Kp), col = (int)(t - (int64_t)g * Kp);
+  const double inv = 1.0 / scale[col];    // a power of two: exact
+  int8_t dg[kMaxSlices][16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    int8_t b[kMaxSlices];
+    digits<kMaxSlices>(W[(int64_t)(16 * g + k) * Kp + col] * inv, b);
+#pragma unroll
+    for (int j = 0; j < kMaxSlices; ++j) dg[j][k] = b[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxSlices; ++j) BS[((int64_t)j * G + g) * Kp + col] = pack16(dg[j]);
+}
+
+// Workgroups are dealt to the 8 XCDs in turn; this gives each XCD a
+// contiguous range of logical tiles (a bijection for any grid size), so the
+// column tiles of one proposal tile run on one XCD and share its L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
+  const int64_t x = b & 7, slot = b >> 3, base = nblk >> 3, extra = nblk & 7;
+  return x * base + (x < extra ? x : extra) + slot;
+}
+
+// Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2 over the digit pairs
+// i + j < S.  One-dimensional grid over (proposal tile, column tile), the
+// column tile fastest.
+template <int S>
+__global__ void __launch_bounds__(kSplitThreads, 2)
+    k_split_contract(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
+                     const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
+                     double *__restrict__ Y) {
+  constexpr int kPer = S * 2 * 64;                       // v4i entries per operand per stage
+  constexpr int kLoads = (kPer + kSplitThreads - 1) / kSplitThreads;
+  __shared__ v4i As[2][S][2][64];
+  __shared__ v4i Bs[2][S][2][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 1, wc = wave >> 1;
+  const int G = rows / 16;
+  const int n_ct = Kp / kSplitC;
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int c0 = (int)(tile % n_ct) * kSplitC;
+  const int64_t q0 = (tile / n_ct) * kSplitQ;
+
+  v4i ra[kLoads], rb[kLoads];
+  auto fetch = [&](int g0) {
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int e = tid + k * kSplitThreads;
+      if (e < kPer) {
+        const int i = e >> 7, kh = (e >> 6) & 1, m = e & 63;
+        const int64_t q = q0 + m;
+        ra[k] = q < nb ? AS[((int64_t)i * G + g0 + kh) * nb + q] : v4i{0, 0, 0, 0};
+        rb[k] = BS[((int64_t)i * G + g0 + kh) * Kp + c0 + m];
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int e = tid + k * kSplitThreads;
+      if (e < kPer) {
+        const int i = e >> 7, kh = (e >> 6) & 1, m = e & 63;
+        As[buf][i][kh][m] = ra[k];
+        Bs[buf][i][kh][m] = rb[k];
+      }
+    }
+  };
+
+  v16i acc[S];
+#pragma unroll
+  for (int l = 0; l < S; ++l)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[l][r] = 0;
+
+  const int n_steps = rows / 32;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int kh = lane >> 5, ml = lane & 31;
+  for (int st = 0; st < n_steps; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < n_steps) fetch(2 * (st + 1));
+    v4i b[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) b[j] = Bs[cur][j][kh][wc * 32 + ml];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const v4i a = As[cur][i][kh][wq * 32 + ml];
+#pragma unroll
+      for (int j = 0; i + j < S; ++j) acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[j], acc[i + j], 0, 0, 0);
+    }
+    if (st + 1 < n_steps) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+  const int col = c0 + wc * 32 + ml;
+  const double sc = cscale[col] * (1.0 / 16129.0);
+  constexpr double kInv254 = 1.0 / 254.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t q = q0 + wq * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+    if (q >= nb) continue;
+    double y = (double)acc[S - 1][r];
+#pragma unroll
+    for (int l = S - 2; l >= 0; --l) y = fma(y, kInv254, (double)acc[l][r]);
+    Y[q * Kp + col] = y * sc * rscale[q];
+  }
+}
+
+template <int S>
+void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                    int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                    const double *cscale, double *Y, hipStream_t s) {
+  static_assert(S <= kMaxSlices && kColTile % kSplitC == 0 && kRowChunk % 32 == 0,
+                "K and the rows are padded to whole tiles");
+  const int64_t G = hc.rows / 16;
+  hipLaunchKernelGGL((k_split_rows<S>), dim3((unsigned)((G * nb + 255) / 256)), dim3(256), 0, s, c, params, ld, b0,
+                     nb, nodes, reinterpret_cast<v4i *>(AS), rscale);
+  RBFL_HIP(hipGetLastError());
+  const int64_t nblk = (nb + kSplitQ - 1) / kSplitQ * (hc.Kp / kSplitC);
+  hipLaunchKernelGGL((k_split_contract<S>), dim3((unsigned)nblk), dim3(kSplitThreads), 0, s,
+                     reinterpret_cast<const v4i *>(AS), nb, hc.rows, reinterpret_cast<const v4i *>(BS), cscale,
+                     rscale, hc.Kp, Y);
+  RBFL_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int split_max_slices() { return kMaxSlices; }
+int split_max_rows() { return kMaxSplitRows; }
+int split_variant_count() { return 4; }
+int split_variant_slices(int variant) { return 5 + variant; }
+
+const char *split_variant_name(int v) {
+  static const char *names[] = {"split s5 32x32x32", "split s6 32x32x32", "split s7 32x32x32", "split s8 32x32x32"};
+  return names[v];
+}
+
+void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8_t *BS, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_scale, dim3(Kp), dim3(256), 0, s, W, rows, Kp, scale);
+  RBFL_HIP(hipGetLastError());
+  const int64_t n = (int64_t)(rows / 16) * Kp;
+  hipLaunchKernelGGL(k_split_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, rows, Kp, scale,
+                     reinterpret_cast<v4i *>(BS));
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                           int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                           const double *cscale, double *Y, hipStream_t s, int variant) {
+  if (hc.rows > kMaxSplitRows || hc.rows % 32 != 0 || hc.Kp % kSplitC != 0)
+    throw Error(RBFL_E_UNSUPPORTED, "split form: rows must be a multiple of 32 and at most 16384");
+  switch (variant) {
+    case 0: launch_variant<5>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
+    case 1: launch_variant<6>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
+    case 2: launch_variant<7>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
+    case 3: launch_variant<8>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
+    default: throw Error(RBFL_E_INVALID_ARG, "unknown split-form variant");
+  }
+}
+
+}  // namespace rbfl

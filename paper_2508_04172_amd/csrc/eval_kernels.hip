@@ -9,6 +9,7 @@
 //   of each detector's and mode's z(tau) from the interpolated SVD
 //   coefficients (Eq. SVD) and the extrinsic combination of Eq. logl_complete
 //   (corrected reading) with compensated summation.
+#include "basis_rows.h"
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -21,55 +22,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kLdsPad = 16;   // doubles of padding per LDS row (bank spread across the 4 k-groups)
-
-// Value of basis row `row` at x.  xn: the node's coordinates (row < N).
-__device__ __forceinline__ double basis_row_fp64(int row, int N, int NM, const double x[4], const double *xn,
-                                                 double eps2, const int (*poly)[3]) {
-  if (row < N) {
-    double d2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const double t = x[d] - xn[d];
-      d2 = fma(t, t, d2);
-    }
-    return exp(-eps2 * d2);
-  }
-  if (row < NM) {
-    const int p = row - N;
-    double v = 1.0;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int id = poly[p][s];
-      if (id >= 0) v *= x[id];
-    }
-    return v;
-  }
-  return 0.0;
-}
-
-__device__ __forceinline__ float basis_row_fp32(int row, int N, int NM, const float x[4], const float *xn,
-                                                float eps2, const int (*poly)[3]) {
-  if (row < N) {
-    float d2 = 0.0f;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const float t = x[d] - xn[d];
-      d2 = fmaf(t, t, d2);
-    }
-    return __expf(-eps2 * d2);
-  }
-  if (row < NM) {
-    const int p = row - N;
-    float v = 1.0f;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int id = poly[p][s];
-      if (id >= 0) v *= x[id];
-    }
-    return v;
-  }
-  return 0.0f;
-}
 
 // Block tile: kWaves waves along the proposals, each wave RT x 16 proposals
 // by CT x 16 outputs; the block covers kWaves*RT*16 proposals and CT*16
@@ -516,180 +468,6 @@ __global__ void k_standardise(const double *__restrict__ Y, int64_t n, int K, co
   T[e] = (float)((Y[e] - (double)mu[k]) / (double)sd[k]);
 }
 
-// ---- split form: error-free products of int8 slices -------------------------
-//
-// A real v with |v| <= 1 is cut into int8 slices a_i = rint(v_i 2^(6+7i)),
-// v_0 = v, v_{i+1} = v_i - a_i 2^(-6-7i) (exact: a_i 2^(-6-7i) lies within
-// half a slice unit of v_i), so |a_i| <= 64 and, after S slices,
-// |v - sum_{i<S} a_i 2^(-6-7i)| <= 2^(-7S).  The slices of one value do not
-// depend on S, so the weights are cut once into kMaxSlices slices and a form
-// with S slices uses the first S.  Kernel rows are divided by a power of two
-// s_q >= max_r |B_r(x_q)| (Gaussian rows are <= 1; the monomials are
-// evaluated), each weight column by a power of two s_c >= max_r |W_rc|.
-// The product keeps every slice pair with i + j < S; the pairs of one level
-// l = i + j share the scale 2^(-12-7l), so each level is summed exactly in
-// int32 by the int8 MFMA (|sum| <= 8 * 64 * 64 * rows < 2^31 for rows
-// < 65536) and the levels are combined once in FP64.  Per kernel row the
-// result is off by at most (S + 3) 2^(-7S) s_q s_c.  The int8 MFMA 16x16x64
-// (measured on gfx950) holds A[l%16][16(l/16)+e] and B[16(l/16)+e][l%16]
-// (e < 16) in lane l and accumulator element i = D[4(l/16)+i][l%16].
-constexpr int kMaxSlices = 8;
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-template <int S>
-__device__ __forceinline__ void slice_value(double v, int8_t out[S]) {
-#pragma unroll
-  for (int i = 0; i < S; ++i) {
-    const double unit = ldexp(1.0, 6 + 7 * i);
-    double a = rint(v * unit);
-    a = fmin(64.0, fmax(-64.0, a));
-    out[i] = (int8_t)a;
-    v -= a / unit;
-  }
-}
-
-// The first S slices of the kernel rows of nb proposals: AS[i][q][r] (rows
-// contiguous), and each proposal's row scale rscale[q].
-template <int S>
-__global__ void __launch_bounds__(256) k_split_rows(const EvalConsts *__restrict__ cp,
-                                                    const double *__restrict__ params, int64_t ld, int64_t b0,
-                                                    int64_t nb, const double *__restrict__ nodes,
-                                                    int8_t *__restrict__ AS, double *__restrict__ rscale) {
-  const EvalConsts &c = *cp;
-  const int64_t q = blockIdx.x;
-  if (q >= nb) return;
-  double x[4];
-  for (int d = 0; d < 4; ++d) x[d] = params[d * ld + b0 + q] / c.semi[d];
-  const int N = c.N, NM = c.N + c.M, rows = c.rows;
-  double bound = 1.0;
-  for (int p = 0; p < c.M; ++p) bound = fmax(bound, fabs(basis_row_fp64(N + p, N, NM, x, nodes, c.eps2, c.poly_idx)));
-  int e = 0;
-  frexp(bound, &e);
-  const double inv = ldexp(1.0, -e);
-  if (threadIdx.x == 0) rscale[q] = ldexp(1.0, e);
-  for (int r = threadIdx.x; r < rows; r += 256) {
-    const double v = basis_row_fp64(r, N, NM, x, nodes + 4 * (int64_t)r, c.eps2, c.poly_idx) * inv;
-    int8_t a[S];
-    slice_value<S>(v, a);
-#pragma unroll
-    for (int i = 0; i < S; ++i) AS[((int64_t)i * nb + q) * rows + r] = a[i];
-  }
-}
-
-// Power-of-two scale of each weight column: 2^e > max_r |W[r][c]|.
-__global__ void __launch_bounds__(256) k_col_scale(const double *__restrict__ W, int rows, int Kp,
-                                                   double *__restrict__ scale) {
-  const int col = blockIdx.x;
-  __shared__ double red[256];
-  double m = 0.0;
-  for (int r = threadIdx.x; r < rows; r += 256) m = fmax(m, fabs(W[(int64_t)r * Kp + col]));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    int e = 0;
-    const double mx = red[0];
-    if (mx > 0.0) frexp(mx, &e);
-    scale[col] = mx > 0.0 ? ldexp(1.0, e) : 1.0;
-  }
-}
-
-// All kMaxSlices weight slices BS[j][c][r] (rows contiguous per column).
-__global__ void k_split_weights(const double *__restrict__ W, int rows, int Kp, const double *__restrict__ scale,
-                                int8_t *__restrict__ BS) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)rows * Kp) return;
-  const int r = (int)(e / Kp), col = (int)(e % Kp);
-  int8_t b[kMaxSlices];
-  slice_value<kMaxSlices>(W[e] / scale[col], b);
-#pragma unroll
-  for (int j = 0; j < kMaxSlices; ++j) BS[((int64_t)j * Kp + col) * rows + r] = b[j];
-}
-
-// Workgroups are dealt to the 8 XCDs in turn; this gives each XCD a
-// contiguous range of logical tiles (a bijection for any grid size), so the
-// column tiles of one proposal tile run on one XCD and share its L2.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
-  const int64_t x = b & 7, slot = b >> 3, base = nblk >> 3, extra = nblk & 7;
-  return x * base + (x < extra ? x : extra) + slot;
-}
-
-// Y[q][c] = s_q s_c sum_l 2^(-12-7l) sum_{i+j=l} sum_r a_i[q][r] b_j[r][c].
-// Block: 4 waves along the proposals, each RT x 16 proposals by CT x 16
-// columns; the block's weight slices for a 64-row step are staged in LDS.
-// One-dimensional grid over (proposal tile, column tile), column tile fastest.
-template <int S, int RT, int CT>
-__global__ void __launch_bounds__(kThreads) k_split_contract(const int8_t *__restrict__ AS, int64_t nb, int rows,
-                                                             const int8_t *__restrict__ BS,
-                                                             const double *__restrict__ scale,
-                                                             const double *__restrict__ rscale, int Kp,
-                                                             double *__restrict__ Y) {
-  constexpr int CW = CT * 16;
-  constexpr int QT = kWaves * RT * 16;
-  __shared__ v4i Bs[S][CW][4];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int n_ct = Kp / CW;
-  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int c0 = (int)(tile % n_ct) * CW;
-  const int64_t q0 = (tile / n_ct) * QT + wave * RT * 16;
-  v4i acc[S][RT][CT];
-#pragma unroll
-  for (int l = 0; l < S; ++l)
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[l][rt][ct] = v4i{0, 0, 0, 0};
-  for (int r0 = 0; r0 < rows; r0 += 64) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < S * CW * 4; e += kThreads) {
-      const int j = e / (CW * 4), rem = e % (CW * 4), col = rem >> 2, ch = rem & 3;
-      Bs[j][col][ch] = *reinterpret_cast<const v4i *>(BS + ((int64_t)j * Kp + c0 + col) * rows + r0 + 16 * ch);
-    }
-    __syncthreads();
-    v4i a[S][RT];
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const int64_t q = q0 + rt * 16 + (lane & 15);
-        a[i][rt] = q < nb ? *reinterpret_cast<const v4i *>(AS + ((int64_t)i * nb + q) * rows + r0 + 16 * (lane >> 4))
-                          : v4i{0, 0, 0, 0};
-      }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-#pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const v4i b = Bs[j][ct * 16 + (lane & 15)][lane >> 4];
-#pragma unroll
-        for (int i = 0; i + j < S; ++i)
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt)
-            acc[i + j][rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i][rt], b, acc[i + j][rt][ct], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int col = c0 + ct * 16 + (lane & 15);
-      const double sc = scale[col];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t q = q0 + rt * 16 + 4 * (lane >> 4) + i;
-        if (q >= nb) continue;
-        double y = 0.0;
-#pragma unroll
-        for (int l = S - 1; l >= 0; --l) y += ldexp((double)acc[l][rt][ct][i], -12 - 7 * l);
-        Y[q * Kp + col] = sc * rscale[q] * y;
-      }
-    }
-}
-
 __global__ void k_convert_weights(const double *__restrict__ W, size_t n, float *__restrict__ hi,
                                   uint16_t *__restrict__ b16) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -719,15 +497,15 @@ static void launch_fp64_variant(const EvalConsts *c, const EvalConsts &hc, const
   RBFL_HIP(hipGetLastError());
 }
 
-int contract_variants(int form) { return form == RBFL_FORM_FP64 ? 5 : form == RBFL_FORM_SPLIT ? 8 : 2; }
+int contract_variants(int form) {
+  return form == RBFL_FORM_FP64 ? 5 : form == RBFL_FORM_SPLIT ? split_variant_count() : 2;
+}
 
 const char *contract_variant_name(int form, int v) {
   static const char *f64[] = {"fp64 rt2 ct4 ch32", "fp64 rt2 ct4 ch16", "fp64 rt2 ct8 ch16", "fp64 rt4 ct4 ch16",
                               "fp64 rt4 ct2 ch32"};
   static const char *f32[] = {"fp32 rt2 ct4 ch64", "fp32 rt2 ct8 ch32"};
-  static const char *split[] = {"split s5 rt2 ct2", "split s5 rt1 ct4", "split s6 rt2 ct2", "split s6 rt1 ct4",
-                                "split s7 rt2 ct2", "split s7 rt1 ct4", "split s8 rt2 ct2", "split s8 rt1 ct4"};
-  return form == RBFL_FORM_FP64 ? f64[v] : form == RBFL_FORM_SPLIT ? split[v] : f32[v];
+  return form == RBFL_FORM_FP64 ? f64[v] : form == RBFL_FORM_SPLIT ? split_variant_name(v) : f32[v];
 }
 
 void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
@@ -806,55 +584,6 @@ void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *pa
   dim3 grid((unsigned)((nb + kWaves - 1) / kWaves));
   hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
   RBFL_HIP(hipGetLastError());
-}
-
-int split_max_slices() { return kMaxSlices; }
-int split_variant_slices(int variant) { return 5 + variant / 2; }
-
-template <int S, int RT, int CT>
-static void launch_split_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
-                                 int64_t b0, int64_t nb, const double *nodes, int8_t *AS, double *rscale,
-                                 const int8_t *BS, const double *scale, double *Y, hipStream_t s) {
-  static_assert(S <= kMaxSlices && kColTile % (CT * 16) == 0 && kRowChunk % 64 == 0,
-                "K and the rows are padded to whole tiles");
-  hipLaunchKernelGGL((k_split_rows<S>), dim3((unsigned)nb), dim3(256), 0, s, c, params, ld, b0, nb, nodes, AS, rscale);
-  RBFL_HIP(hipGetLastError());
-  const int64_t qt = kWaves * RT * 16;
-  const int64_t nblk = (nb + qt - 1) / qt * (hc.Kp / (CT * 16));
-  hipLaunchKernelGGL((k_split_contract<S, RT, CT>), dim3((unsigned)nblk), dim3(kThreads), 0, s, AS, nb, hc.rows, BS,
-                     scale, rscale, hc.Kp, Y);
-  RBFL_HIP(hipGetLastError());
-}
-
-void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8_t *BS, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_scale, dim3(Kp), dim3(256), 0, s, W, rows, Kp, scale);
-  RBFL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_split_weights, dim3((unsigned)(((int64_t)rows * Kp + 255) / 256)), dim3(256), 0, s, W, rows,
-                     Kp, scale, BS);
-  RBFL_HIP(hipGetLastError());
-}
-
-// Variant v: S = 5 + v/2 slices, tile (RT, CT) = (2, 2) for even v, (1, 4) for odd v.
-void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
-                           int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
-                           const double *scale, double *Y, hipStream_t s, int variant) {
-#define RBFL_SPLIT_CASE(V, S, RT, CT) \
-  case V:                            \
-    launch_split_variant<S, RT, CT>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, scale, Y, s); \
-    break;
-  switch (variant) {
-    RBFL_SPLIT_CASE(0, 5, 2, 2)
-    RBFL_SPLIT_CASE(1, 5, 1, 4)
-    RBFL_SPLIT_CASE(2, 6, 2, 2)
-    RBFL_SPLIT_CASE(3, 6, 1, 4)
-    RBFL_SPLIT_CASE(4, 7, 2, 2)
-    RBFL_SPLIT_CASE(5, 7, 1, 4)
-    RBFL_SPLIT_CASE(6, 8, 2, 2)
-    RBFL_SPLIT_CASE(7, 8, 1, 4)
-    default:
-      throw Error(RBFL_E_INVALID_ARG, "unknown split-form variant");
-  }
-#undef RBFL_SPLIT_CASE
 }
 
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,

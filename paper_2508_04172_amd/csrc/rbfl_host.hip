@@ -1078,6 +1078,8 @@ static void prepare(Ctx &c, int form) {
   const size_t n = (size_t)c.rows * c.Kp;
   if (form == RBFL_FORM_BF16) throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
   if (form == RBFL_FORM_SPLIT) {
+    if (c.rows > split_max_rows())
+      throw Error(RBFL_E_UNSUPPORTED, "the split form needs N + M <= " + std::to_string(split_max_rows()));
     c.WS.alloc((size_t)split_max_slices() * c.Kp * c.rows);
     c.WSscale.alloc(c.Kp);
     launch_split_prepare(c.W.p, c.rows, c.Kp, c.WSscale.p, c.WS.p, 0);

@@ -197,8 +197,11 @@ void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params,
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
 int split_max_slices();
+int split_max_rows();
+int split_variant_count();
 int split_variant_slices(int variant);
-constexpr int kSplitDefaultVariant = 6;    // 8 slices: within a few units of FP64 rounding
+const char *split_variant_name(int variant);
+constexpr int kSplitDefaultVariant = 2;    // 7 base-254 digits: within a few units of FP64 rounding
 void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8_t *BS, hipStream_t s);
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                            int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,

@@ -359,8 +359,8 @@ class Handle:
 
 
 def split_slices(variant: int) -> int:
-    """Slice count S of a split-form contraction variant."""
-    return 5 + variant // 2
+    """Digit count S of a split-form contraction variant."""
+    return 5 + variant
 
 
 class Plan:

@@ -1,12 +1,12 @@
 """Mixed-precision contraction forms against the FP64 oracle.
 
-Split form: every product of int8 slices is summed exactly in int32, so its
-only errors are the dropped slice pairs and the slice remainders, at most
-(S + 3) 2^(-7S) of s_q s_c per kernel row (s_q, s_c the power-of-two scales
-of the proposal's row and of the weight column).  With its default S = 8 it
+Split form: every product of int8 digits is summed exactly in int32, so its
+only errors are the dropped digit pairs and the digit remainders, at most
+(S + 3) 254^-S of s_q s_c per kernel row (s_q, s_c the power-of-two scales
+of the proposal's row and of the weight column).  With its default S = 7 it
 is held to the FP64 bars: |d ln L| <= 1e-3 and, per interpolated column, the
 FP64 bar widened by that worst-case bound.  After rbfl_autotune (which keeps
-only slice counts within 1e-4 of the FP64 form on the tuning proposals) it is
+only digit counts within 1e-4 of the FP64 form on the tuning proposals) it is
 held to 1e-3 against the oracle on other proposals.
 
 FP32 form: reported, not held to 1e-3 (its FP32 kernel rows and sums lose
@@ -25,7 +25,7 @@ from test_gpu_parity import CASES, both, column_scale, gpu_eval, gpu_interp
 
 pytestmark = pytest.mark.gpu
 
-SLICES = 8      # the split form's slice count until rbfl_autotune picks one
+SLICES = 7      # the split form's digit count until rbfl_autotune picks one
 
 
 def _prepared(name, form):
@@ -47,7 +47,7 @@ def test_split_interpolant(name):
     # worst case of the split arithmetic: power-of-two scales bound |W_rc| and |B_r|
     s_c = 2.0 ** np.ceil(np.log2(np.maximum(np.abs(art.W).max(axis=0), 1e-300)))
     s_q = 2.0 ** np.ceil(np.log2(np.maximum(1.0, np.abs(basis).max(axis=1))))
-    split_bound = (SLICES + 3) * 2.0 ** (-7 * SLICES) * basis.shape[1] * s_q.max() * s_c / col_scale
+    split_bound = (SLICES + 3) * 254.0 ** (-SLICES) * basis.shape[1] * s_q.max() * s_c / col_scale
     bar = np.maximum(1e-6, 1e-13 * amp) + split_bound
     err = np.abs(Ys - Yo).max(axis=0) / col_scale
     vs64 = np.abs(Ys - Yd).max(axis=0) / col_scale
@@ -92,7 +92,7 @@ def test_fp32_reported(name):
 
 def test_split_chunked_matches_single_pass():
     """Batches above the work-space capacity give the same split-form results
-    as one pass (the slice buffer is re-filled per chunk)."""
+    as one pass (the digit buffer is re-filled per chunk)."""
     cfg, art, h = _prepared("small_multi", rbfl.FORM_SPLIT)
     qd = wl.queries(cfg, n=70000, seed=9)
     l1 = gpu_eval(h, qd, cfg.t_trig, rbfl.FORM_SPLIT)
@@ -105,7 +105,7 @@ def test_split_chunked_matches_single_pass():
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_split_autotuned_slices(name):
-    """The autotuner's slice count: within 1e-4 of the FP64 form on its own
+    """The autotuner's digit count: within 1e-4 of the FP64 form on its own
     proposals, within 1e-3 of the oracle on a fresh seeded set."""
     cfg, art, h = _prepared(name, rbfl.FORM_SPLIT)
     torch = pytest.importorskip("torch")
@@ -119,8 +119,8 @@ def test_split_autotuned_slices(name):
     print(f"[mixed] {name} split autotune: S = {tune['slices']}, max |dlnL| vs FP64 per variant "
           f"{['%.1e' % e for e in errs]}, ms {['%.3f' % m for m in tune['ms']]}", flush=True)
     assert errs[tune["variant"]] <= rbfl.SPLIT_TOL
-    # the 8-slice variants (6, 7) sit within a few units of FP64 rounding
-    assert errs[6] <= rbfl.SPLIT_TOL and errs[7] <= rbfl.SPLIT_TOL
+    # 7 and 8 digits (variants 2, 3) sit within a few units of FP64 rounding
+    assert errs[2] <= rbfl.SPLIT_TOL and errs[3] <= rbfl.SPLIT_TOL
     qd2 = wl.queries(cfg, n=n, seed=11)
     lg = gpu_eval(h, qd2, cfg.t_trig, rbfl.FORM_SPLIT)
     lo = lk.meshfree_lnl(art, *lk.query_params(art, qd2))
