@@ -122,12 +122,21 @@ def main():
     per_launch_n = ks["contract_n"] / max(1, ks["contract_launches"])
     contract_ms = ks["contract_ms"] / max(1, ks["contract_launches"])
     achieved = flop_per_query * per_launch_n / (contract_ms * 1e-3)
-    log(f"FP64: {value:.4e} evals/s, {ms_per_step:.2f} ms/step; contraction {contract_ms:.3f} ms/launch "
-        f"({achieved / 1e12:.2f} TFLOP/s), epilogue {ks['epilogue_ms'] / max(1, ks['epilogue_launches']):.3f} ms/launch")
+    rows_ms = ks["rows_ms"] / max(1, ks["rows_launches"])
+    epi_ms = ks["epilogue_ms"] / max(1, ks["epilogue_launches"])
+    # basis-row stage: writes 8 bytes per padded row per proposal, reads 32 bytes of coordinates
+    rows_padded = (NM + 63) // 64 * 64
+    rows_bytes = (8.0 * rows_padded + 32.0) * per_launch_n
+    fp64_variant = tune["fp64"]["variant"]
+    fused = fp64_variant >= 4
+    log(f"FP64: {value:.4e} evals/s, {ms_per_step:.2f} ms/step; rows {rows_ms:.3f} ms/launch, contraction "
+        f"{contract_ms:.3f} ms/launch ({achieved / 1e12:.2f} TFLOP/s), epilogue {epi_ms:.3f} ms/launch")
 
-    forms = {"fp64": {"evals_per_s": value, "ms_per_step": ms_per_step,
-                      "contract_tflops": achieved / 1e12,
-                      "epilogue_ms_per_launch": ks["epilogue_ms"] / max(1, ks["epilogue_launches"])}}
+    forms = {"fp64": {"evals_per_s": value, "ms_per_step": ms_per_step, "variant": fp64_variant,
+                      "contract_ms_per_launch": contract_ms, "contract_tflops": achieved / 1e12,
+                      "rows_ms_per_launch": rows_ms,
+                      "rows_gbs": rows_bytes / (rows_ms * 1e-3) / 1e9 if rows_ms > 0 else None,
+                      "epilogue_ms_per_launch": epi_ms}}
     outs = {"fp64": l64}
     for name, form in (("fp32", rbfl.FORM_FP32), ("split", rbfl.FORM_SPLIT)):
         w2, ks2, lf = run_form(form, max(3, args.steps // 2), 1)
@@ -167,7 +176,8 @@ def main():
                    "n_det": cfg.n_det, "modes": len(cfg.modes), "nodes": cfg.n_nodes, "q": cfg.q,
                    "K": K, "poly_degree": cfg.poly_degree, "eps": cfg.eps, "fs": cfg.fs,
                    "seg_len": cfg.seg_len, "f_low": cfg.f_low, "startup_s": round(build_s, 3)},
-        "roofline": {"bound": "mfma", "kernel": "k_contract_fp64", "achieved": achieved / 1e12,
+        "roofline": {"bound": "mfma", "kernel": "k_contract_fp64 (fused rows)" if fused else "k_gemm_fp64",
+                     "achieved": achieved / 1e12,
                      "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                      "traffic": None, "flop_per_launch": flop_per_query * per_launch_n,
                      "launch_ms": contract_ms},

@@ -183,9 +183,11 @@ enum rbfl_query_what {
   RBFL_Q_COND = 9,         /* double[1]: 1-norm condition estimate of the RBF system */
   RBFL_Q_TIMING = 10,      /* double[8]: start-up stage wall times [s] */
   RBFL_Q_Z_NODES = 11,     /* double[n_det][n_modes][N][T][2] time series at the nodes */
-  RBFL_Q_KERNEL_STATS = 12, /* double[6]: contraction ms, launches, proposals; epilogue ms, launches,
-                               proposals -- summed HIP-event durations since rbfl_profile was switched
-                               on (synchronises the recorded events; resets the sums) */
+  RBFL_Q_KERNEL_STATS = 12, /* double[9]: MFMA contraction ms, launches, proposals; epilogue ms,
+                               launches, proposals; basis-row stage ms, launches, proposals (zero time
+                               for forms without one) -- summed HIP-event durations since
+                               rbfl_profile was switched on (synchronises the recorded events; resets
+                               the sums) */
   RBFL_Q_TUNE = 13,         /* double[4][9]: per form, the chosen contraction tile variant and the
                                autotuner's median time [ms] of each variant (0 = not timed) */
   RBFL_Q_SURROGATE = 14,    /* double[8]: accepted (1/0), held-out max |d ln L|, held-out median
@@ -209,9 +211,9 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it
- * on, rbfl_eval records a HIP event pair around every contraction and
- * epilogue launch on the caller's stream; RBFL_Q_KERNEL_STATS reports the
- * sums.  Not for use under graph capture. */
+ * on, rbfl_eval records HIP events around the basis-row, contraction and
+ * epilogue launches of every chunk on the caller's stream;
+ * RBFL_Q_KERNEL_STATS reports the sums.  Not for use under graph capture. */
 int32_t rbfl_profile(rbfl_handle h, int32_t on);
 
 /*

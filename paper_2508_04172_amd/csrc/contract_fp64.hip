@@ -1,0 +1,214 @@
+// FP64 form of the interpolant contraction Y = [Phi | P] W (Eq. rbfcoeff) as
+// two kernels: the basis rows of a chunk of proposals are written to HBM by a
+// VALU-only kernel, then a DGEMM-shaped FP64 MFMA kernel contracts them with
+// the weights.
+//
+// Why not fused: on gfx950 an FP64 MFMA and any VALU instruction of the same
+// SIMD do not execute concurrently (the co-execution counter stays at zero),
+// so the ~45 VALU instructions of each fused exp(-eps^2 d^2) row value (plus
+// its recomputation for every column tile) are added to the MFMA time.  Apart
+// from the rows the GEMM's inner loop issues only LDS reads and MFMAs; the
+// rows cost one HBM round trip of 8 (N + M) bytes per proposal.
+//
+// Layouts: rows Bt[r][q] (row r of proposal q, leading dimension ldb, a
+// multiple of 8 >= nb, zero beyond nb); weights W[r][c] (Kp columns).
+// GEMM tiles: 4 waves (2 x 2), each RT x CT tiles of 16 x 16 on
+// v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16], B[l/16][l%16];
+// accumulator element i is D[l/16 + 4i][l%16], measured on gfx950); row
+// chunks of KC rows of both operands staged through LDS, double-buffered.
+#include "basis_rows.h"
+#include "rbfl_internal.h"
+
+namespace rbfl {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int kGemmThreads = 256;
+
+// Basis rows 16*blockIdx.y .. +15 of proposals q = blockIdx.x*256 + tid (zero
+// for nb <= q < ldb).
+__global__ void __launch_bounds__(256) k_rows_fp64(const EvalConsts *__restrict__ cp,
+                                                   const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                   int64_t nb, int64_t ldb, const double *__restrict__ nodes,
+                                                   double *__restrict__ Bt) {
+  const EvalConsts &c = *cp;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= ldb) return;
+  const int r0 = 16 * blockIdx.y;
+  if (q >= nb) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Bt[(int64_t)(r0 + k) * ldb + q] = 0.0;
+    return;
+  }
+  double x[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) x[d] = params[d * ld + b0 + q] / c.semi[d];
+  const int N = c.N, NM = c.N + c.M;
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const int r = r0 + k;
+    Bt[(int64_t)r * ldb + q] = basis_row_fp64(r, N, NM, x, nodes + 4 * (int64_t)r, c.eps2, c.poly_idx);
+  }
+}
+
+// Workgroups are dealt to the 8 XCDs in turn; this gives each XCD a
+// contiguous range of logical tiles (a bijection for any grid size), so the
+// column tiles of one proposal tile run on one XCD and share its L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
+  const int64_t x = b & 7, slot = b >> 3, base = nblk >> 3, extra = nblk & 7;
+  return x * base + (x < extra ? x : extra) + slot;
+}
+
+// Y[q][c] = sum_r Bt[r][q] W[r][c].  One-dimensional grid over (proposal
+// tile, column tile), column tile fastest.
+template <int RT, int CT, int KC>
+__global__ void __launch_bounds__(kGemmThreads, 2)
+    k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
+                int Kp, double *__restrict__ Y) {
+  constexpr int QT = 2 * RT * 16, CW = 2 * CT * 16;
+  constexpr int A2 = KC * QT / 2, W2 = KC * CW / 2;                 // double2 entries per chunk
+  constexpr int LA = A2 / kGemmThreads, LW = W2 / kGemmThreads;
+  static_assert(KC % 4 == 0 && A2 % kGemmThreads == 0 && W2 % kGemmThreads == 0, "whole k-steps, even staging");
+  __shared__ double As[2][KC][QT];
+  __shared__ double Ws[2][KC][CW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 1, wc = wave >> 1;
+  const int n_ct = Kp / CW;
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int c0 = (int)(tile % n_ct) * CW;
+  const int64_t q0 = (tile / n_ct) * QT;
+
+  // per-thread source pointers of the staged entries, advanced by KC rows per chunk
+  const double *pa[LA];
+  const double *pw[LW];
+  bool va[LA];
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + u * kGemmThreads;
+    const int k = e / (QT / 2), q2 = e % (QT / 2);
+    pa[u] = Bt + (int64_t)k * ldb + q0 + 2 * q2;
+    va[u] = q0 + 2 * q2 < ldb;
+  }
+#pragma unroll
+  for (int u = 0; u < LW; ++u) {
+    const int e = tid + u * kGemmThreads;
+    pw[u] = W + (int64_t)(e / (CW / 2)) * Kp + c0 + 2 * (e % (CW / 2));
+  }
+  const int64_t stepA = (int64_t)KC * ldb, stepW = (int64_t)KC * Kp;
+  d2 ra[LA], rw[LW];
+  auto fetch = [&]() {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      ra[u] = va[u] ? *reinterpret_cast<const d2 *>(pa[u]) : d2{0.0, 0.0};
+      pa[u] += stepA;
+    }
+#pragma unroll
+    for (int u = 0; u < LW; ++u) {
+      rw[u] = *reinterpret_cast<const d2 *>(pw[u]);
+      pw[u] += stepW;
+    }
+  };
+  auto stash = [&](int buf) {
+    // keeps the compiler from hoisting these LDS writes (and the wait for
+    // their global loads) above the current chunk's MFMAs
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + u * kGemmThreads;
+      *reinterpret_cast<d2 *>(&As[buf][e / (QT / 2)][2 * (e % (QT / 2))]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LW; ++u) {
+      const int e = tid + u * kGemmThreads;
+      *reinterpret_cast<d2 *>(&Ws[buf][e / (CW / 2)][2 * (e % (CW / 2))]) = rw[u];
+    }
+  };
+
+  d4 acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int kk = lane >> 4, ll = lane & 15;
+  const int n_chunks = rows / KC;
+  fetch();
+  stash(0);
+  __syncthreads();
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < n_chunks) fetch();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = 4 * s + kk;
+      double a[RT], b[CT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = As[cur][k][wq * (QT / 2) + 16 * t + ll];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[u] = Ws[cur][k][wc * (CW / 2) + 16 * u + ll];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+    }
+    if (ch + 1 < n_chunks) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t q = q0 + wq * (QT / 2) + 16 * t + kk + 4 * i;
+      if (q >= nb) continue;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) Y[q * Kp + c0 + wc * (CW / 2) + 16 * u + ll] = acc[t][u][i];
+    }
+}
+
+template <int RT, int CT, int KC>
+void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc, const double *W, double *Y,
+                 hipStream_t s) {
+  constexpr int QT = 2 * RT * 16, CW = 2 * CT * 16;
+  static_assert(kColTile % CW == 0 && kRowChunk % KC == 0, "K and the rows are padded to whole tiles");
+  const int64_t nblk = (nb + QT - 1) / QT * (hc.Kp / CW);
+  hipLaunchKernelGGL((k_gemm_fp64<RT, CT, KC>), dim3((unsigned)nblk), dim3(kGemmThreads), 0, s, Bt, nb, ldb, hc.rows,
+                     W, hc.Kp, Y);
+  RBFL_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int64_t rows_ld(int64_t n) { return (n + 7) & ~int64_t(7); }
+
+int gemm_fp64_variants() { return 4; }
+
+const char *gemm_fp64_variant_name(int v) {
+  static const char *names[] = {"rows + gemm 128x128 kc16", "rows + gemm 128x128 kc8", "rows + gemm 64x128 kc16",
+                                "rows + gemm 128x64 kc16"};
+  return names[v];
+}
+
+void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                      int64_t nb, const double *nodes, double *Bt, hipStream_t s) {
+  const int64_t ldb = rows_ld(nb);
+  dim3 grid((unsigned)((ldb + 255) / 256), (unsigned)(hc.rows / 16));
+  hipLaunchKernelGGL(k_rows_fp64, grid, dim3(256), 0, s, c, params, ld, b0, nb, ldb, nodes, Bt);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_gemm_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const double *W, double *Y, hipStream_t s,
+                      int variant) {
+  const int64_t ldb = rows_ld(nb);
+  switch (variant) {
+    case 0: launch_gemm<4, 4, 16>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 1: launch_gemm<4, 4, 8>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 2: launch_gemm<2, 4, 16>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 3: launch_gemm<4, 2, 16>(Bt, nb, ldb, hc, W, Y, s); break;
+    default: throw Error(RBFL_E_INVALID_ARG, "unknown FP64 GEMM variant");
+  }
+}
+
+}  // namespace rbfl

@@ -191,6 +191,9 @@ __global__ void __launch_bounds__(kSplitThreads, 2)
     }
   };
   auto stash = [&](int buf) {
+    // keeps the compiler from hoisting these LDS writes (and the wait for
+    // their global loads) above the current step's MFMAs
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < kLoads; ++k) {
       const int e = tid + k * kSplitThreads;
@@ -246,13 +249,14 @@ __global__ void __launch_bounds__(kSplitThreads, 2)
 template <int S>
 void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                     int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
-                    const double *cscale, double *Y, hipStream_t s) {
+                    const double *cscale, double *Y, hipStream_t s, hipEvent_t mid) {
   static_assert(S <= kMaxSlices && kColTile % kSplitC == 0 && kRowChunk % 32 == 0,
                 "K and the rows are padded to whole tiles");
   const int64_t G = hc.rows / 16;
   hipLaunchKernelGGL((k_split_rows<S>), dim3((unsigned)((G * nb + 255) / 256)), dim3(256), 0, s, c, params, ld, b0,
                      nb, nodes, reinterpret_cast<v4i *>(AS), rscale);
   RBFL_HIP(hipGetLastError());
+  if (mid) RBFL_HIP(hipEventRecord(mid, s));
   const int64_t nblk = (nb + kSplitQ - 1) / kSplitQ * (hc.Kp / kSplitC);
   hipLaunchKernelGGL((k_split_contract<S>), dim3((unsigned)nblk), dim3(kSplitThreads), 0, s,
                      reinterpret_cast<const v4i *>(AS), nb, hc.rows, reinterpret_cast<const v4i *>(BS), cscale,
@@ -283,14 +287,14 @@ void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8
 
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                            int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
-                           const double *cscale, double *Y, hipStream_t s, int variant) {
+                           const double *cscale, double *Y, hipStream_t s, int variant, hipEvent_t mid) {
   if (hc.rows > kMaxSplitRows || hc.rows % 32 != 0 || hc.Kp % kSplitC != 0)
     throw Error(RBFL_E_UNSUPPORTED, "split form: rows must be a multiple of 32 and at most 16384");
   switch (variant) {
-    case 0: launch_variant<5>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
-    case 1: launch_variant<6>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
-    case 2: launch_variant<7>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
-    case 3: launch_variant<8>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s); break;
+    case 0: launch_variant<5>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s, mid); break;
+    case 1: launch_variant<6>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s, mid); break;
+    case 2: launch_variant<7>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s, mid); break;
+    case 3: launch_variant<8>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, Y, s, mid); break;
     default: throw Error(RBFL_E_INVALID_ARG, "unknown split-form variant");
   }
 }

@@ -505,7 +505,8 @@ const char *contract_variant_name(int form, int v) {
   static const char *f64[] = {"fp64 rt2 ct4 ch32", "fp64 rt2 ct4 ch16", "fp64 rt2 ct8 ch16", "fp64 rt4 ct4 ch16",
                               "fp64 rt4 ct2 ch32"};
   static const char *f32[] = {"fp32 rt2 ct4 ch64", "fp32 rt2 ct8 ch32"};
-  return form == RBFL_FORM_FP64 ? f64[v] : form == RBFL_FORM_SPLIT ? split_variant_name(v) : f32[v];
+  if (form == RBFL_FORM_FP64) return v < gemm_fp64_variants() ? gemm_fp64_variant_name(v) : "fused rt2 ct8 ch16";
+  return form == RBFL_FORM_SPLIT ? split_variant_name(v) : f32[v];
 }
 
 void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,

@@ -907,6 +907,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
 static void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
   c.Y.alloc((size_t)n * c.Kp);
+  c.Bt.alloc((size_t)c.rows * rows_ld(n));
   c.cap = n;
   if (c.prepared[RBFL_FORM_SPLIT]) {
     c.AS.alloc((size_t)split_max_slices() * n * c.rows);
@@ -919,7 +920,8 @@ static void reserve(Ctx &c, int64_t n) {
   }
 }
 
-static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s);
+static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s,
+                     hipEvent_t *marks = nullptr);
 
 static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
   require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
@@ -931,22 +933,18 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
   for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
     const int64_t nb = std::min(c.cap, n - b0);
     if (c.profile) {
-      Ctx::Timed t0{}, t1{};
-      RBFL_HIP(hipEventCreate(&t0.a));
-      RBFL_HIP(hipEventCreate(&t0.b));
-      RBFL_HIP(hipEventCreate(&t1.a));
-      RBFL_HIP(hipEventCreate(&t1.b));
-      t0.kind = 0;
-      t1.kind = 1;
-      t0.n = t1.n = nb;
-      RBFL_HIP(hipEventRecord(t0.a, s));
-      contract(c, params, n, b0, nb, form, s);
-      RBFL_HIP(hipEventRecord(t0.b, s));
-      RBFL_HIP(hipEventRecord(t1.a, s));
+      // stages: basis rows (kind 2), MFMA contraction (kind 0), epilogue (kind 1)
+      hipEvent_t ev[4];
+      for (auto &e : ev) {
+        RBFL_HIP(hipEventCreate(&e));
+        c.timed_events.push_back(e);
+      }
+      contract(c, params, n, b0, nb, form, s, ev);
       launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
-      RBFL_HIP(hipEventRecord(t1.b, s));
-      c.timed.push_back(t0);
-      c.timed.push_back(t1);
+      RBFL_HIP(hipEventRecord(ev[3], s));
+      c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
+      c.timed.push_back(Ctx::Timed{ev[1], ev[2], 0, nb});
+      c.timed.push_back(Ctx::Timed{ev[2], ev[3], 1, nb});
       continue;
     }
     contract(c, params, n, b0, nb, form, s);
@@ -954,33 +952,54 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
   }
 }
 
-static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s) {
+// The contraction of proposals [b0, b0 + nb) into the work space Y, in two
+// stages where the form has them (basis rows, then the MFMA product); marks,
+// when given, are recorded before, between and after the stages.
+static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s,
+                     hipEvent_t *marks) {
+  auto mark = [&](int i) {
+    if (marks) RBFL_HIP(hipEventRecord(marks[i], s));
+  };
+  auto fp64 = [&]() {
+    const int v = c.variant[RBFL_FORM_FP64];
+    if (v < gemm_fp64_variants()) {
+      launch_rows_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.Bt.p, s);
+      mark(1);
+      launch_gemm_fp64(c.Bt.p, nb, c.host_consts, c.W.p, c.Y.p, s, v);
+    } else {
+      mark(1);
+      launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s, 2);
+    }
+  };
+  mark(0);
   switch (form) {
     case RBFL_FORM_FP64:
-      launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s,
-                           c.variant[form]);
+      fp64();
       break;
     case RBFL_FORM_FP32:
+      mark(1);
       launch_contract_fp32(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W32.p, c.Y.p, s,
                            c.variant[form]);
       break;
     case RBFL_FORM_SPLIT:
-      launch_contract_split(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.AS.p, c.ASscale.p, c.WS.p, c.WSscale.p,
-                            c.Y.p, s, c.variant[form]);
+      launch_contract_split(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.AS.p, c.ASscale.p, c.WS.p,
+                            c.WSscale.p, c.Y.p, s, c.variant[form], marks ? marks[1] : nullptr);
       break;
     case RBFL_FORM_SURROGATE:
       if (c.sur && c.sur_ok) {
         launch_sur_inputs(params, ld, b0, nb, c.consts.p, c.sur_x.p, s);
+        mark(1);
         c.sur->forward(c.sur_x.p, nb, c.sur_y.p, s);
         launch_sur_outputs(c.sur_y.p, c.sur_mu.p, c.sur_sd.p, nb, c.K, c.Kp, c.Y.p, s);
       } else {
-        launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, c.Y.p, s,
-                             c.variant[RBFL_FORM_FP64]);
+        fp64();
       }
       break;
     default:
+      mark(1);
       launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W16.p, c.Y.p, s);
   }
+  mark(2);
 }
 
 static void interp(Ctx &c, const double *params, int64_t n, double *out, int form, hipStream_t s) {
@@ -1265,7 +1284,7 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       copy_out(out, bytes, c.split_err, sizeof(c.split_err));
       return;
     case RBFL_Q_KERNEL_STATS: {
-      double v[6] = {0, 0, 0, 0, 0, 0};
+      double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (auto &t : c.timed) {
         RBFL_HIP(hipEventSynchronize(t.b));
         float ms = 0.0f;
@@ -1273,10 +1292,8 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
         v[3 * t.kind] += ms;
         v[3 * t.kind + 1] += 1.0;
         v[3 * t.kind + 2] += (double)t.n;
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
       }
-      c.timed.clear();
+      c.drop_timed();
       copy_out(out, bytes, v, sizeof(v));
       return;
     }

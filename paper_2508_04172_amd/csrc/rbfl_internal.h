@@ -132,6 +132,7 @@ struct Ctx {
   double split_err[8] = {};           // last split autotune: max |d ln L| vs the FP64 form per variant
   // work space
   DevBuf<double> Y;            // [cap][Kp]
+  DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
   int64_t cap = 0;
   EvalConsts host_consts;
   // surrogate (rbfl_surrogate_train)
@@ -144,16 +145,19 @@ struct Ctx {
   bool profile = false;
   struct Timed {
     hipEvent_t a, b;
-    int kind;          // 0 contraction, 1 epilogue
+    int kind;          // 0 MFMA contraction, 1 epilogue, 2 basis rows
     int64_t n;         // proposals in the launch
   };
   std::vector<Timed> timed;
+  std::vector<hipEvent_t> timed_events;   // owned by the handle until the stats are read
+  void drop_timed() {
+    for (auto e : timed_events) (void)hipEventDestroy(e);
+    timed_events.clear();
+    timed.clear();
+  }
   ~Ctx() {
     delete sur;
-    for (auto &t : timed) {
-      (void)hipEventDestroy(t.a);
-      (void)hipEventDestroy(t.b);
-    }
+    drop_timed();
   }
 };
 
@@ -179,6 +183,14 @@ void launch_transpose_weights(const double *R, int NM, int K, int rows, int Kp, 
 // ---- online kernels (eval_kernels.hip) ----
 int contract_variants(int form);
 const char *contract_variant_name(int form, int variant);
+// ---- FP64 rows + GEMM (contract_fp64.hip) ----
+int64_t rows_ld(int64_t n);
+int gemm_fp64_variants();
+const char *gemm_fp64_variant_name(int variant);
+void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                      int64_t nb, const double *nodes, double *Bt, hipStream_t s);
+void launch_gemm_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const double *W, double *Y, hipStream_t s,
+                      int variant);
 void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const double *W, double *Y,
                           hipStream_t s, int variant);
@@ -205,7 +217,7 @@ constexpr int kSplitDefaultVariant = 2;    // 7 base-254 digits: within a few un
 void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8_t *BS, hipStream_t s);
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                            int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
-                           const double *scale, double *Y, hipStream_t s, int variant);
+                           const double *scale, double *Y, hipStream_t s, int variant, hipEvent_t mid);
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s);
 void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,

@@ -353,9 +353,10 @@ class Handle:
         _check(load().rbfl_profile(self._h, 1 if on else 0))
 
     def kernel_stats(self) -> dict:
-        v = self._query(Q_KERNEL_STATS, 6)
+        v = self._query(Q_KERNEL_STATS, 9)
         return {"contract_ms": v[0], "contract_launches": int(v[1]), "contract_n": int(v[2]),
-                "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5])}
+                "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5]),
+                "rows_ms": v[6], "rows_launches": int(v[7]), "rows_n": int(v[8])}
 
 
 def split_slices(variant: int) -> int:
