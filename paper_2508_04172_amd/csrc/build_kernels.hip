@@ -354,6 +354,40 @@ void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, do
   RBFL_HIP(hipGetLastError());
 }
 
+// Spline-folded basis for the online reconstruction: with the not-a-knot
+// weights w_t(f) = sum_p spline[t][p] f^p of the 10-sample stencil,
+//   B4[pair][n][i][p] = sum_t spline[t][p] B[pair][n - 4 + t][i]
+// for stencil bases 4 <= n <= T - 6 (zero elsewhere), so that the
+// interpolated basis at n + f is sum_p f^p B4[pair][n][i][p].
+__global__ void __launch_bounds__(kBlock) k_fold_spline(const double2 *__restrict__ B, int n_pairs, int T, int q,
+                                                        const EvalConsts *__restrict__ c, double2 *__restrict__ B4) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)n_pairs * T * q) return;
+  const int i = (int)(e % q);
+  const int n = (int)((e / q) % T);
+  const int64_t pair = e / ((int64_t)q * T);
+  double2 out[4] = {};
+  if (n >= 4 && n <= T - 6) {
+    for (int t = 0; t < kSplineTaps; ++t) {
+      const double2 v = B[(pair * T + n - 4 + t) * q + i];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        out[p].x = fma(c->spline[t][p], v.x, out[p].x);
+        out[p].y = fma(c->spline[t][p], v.y, out[p].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) B4[e * 4 + p] = out[p];
+}
+
+void launch_fold_spline(const double2 *B, int n_pairs, int T, int q, const EvalConsts *c, double2 *B4,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_spline, dim3(grid1((int64_t)n_pairs * T * q, kBlock)), dim3(kBlock), 0, s, B, n_pairs,
+                     T, q, c, B4);
+  RBFL_HIP(hipGetLastError());
+}
+
 void launch_basis_from_u(const double2 *U, int T, int ldu, int q, double2 *B, hipStream_t s) {
   hipLaunchKernelGGL(k_basis_from_u, dim3(q), dim3(kBlock), 0, s, U, T, ldu, q, B);
   RBFL_HIP(hipGetLastError());

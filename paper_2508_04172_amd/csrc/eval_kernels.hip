@@ -204,38 +204,47 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
   }
 }
 
-// One wave per proposal.  The wave's lanes are split over the (detector,
+// The epilogue runs in two phases per block of kEpiBatch proposals.
+//
+// Setup (one lane per proposal): the proposal's domain flags (inside the
+// ellipsoid, physical, every detector's spline stencil inside the window, no
+// NaN input), each detector's arrival-time position (stencil base and
+// fraction), each (detector, mode) amplitude A_{k,lm} =
+// [(F+ + iFx) Y_{l,-m} + (-1)^l (F+ - iFx) conj(Y_lm)] / 2 (Eq. logl_complete,
+// corrected reading) and d_ref / d_L, into LDS.  These need transcendental
+// functions but not the interpolated coefficients, so a lane per proposal
+// does them once instead of a wave per proposal.
+//
+// Reduction (one wave per proposal): the lanes are split over the (detector,
 // mode) pairs -- G = 64 / (n_det * n_modes) lanes per pair -- and each pair's
-// lanes stride over its q basis coefficients, so every pair's reconstruction
-// runs at once: lane g of pair (k, a) accumulates sum_i C_i sum_s w_s
-// B[n0-4+s][i] over i = g, g+G, ... (the basis rows are contiguous in i, so
-// the G lanes of a pair read adjacent entries).  Each lane evaluates only its
-// own detector's response and arrival time and its own mode's harmonics.
-// Partial sums meet in the pair's first lane by shuffles; that lane forms
-// Re(conj(A) z), the detector's first lane the overlap term, lane 0 the sum.
-// ln L of proposal g (column g of params) from its interpolated row y; one
-// whole wave per call.
-__device__ __forceinline__ void epilogue_one(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
-                                             int64_t g, const double *__restrict__ y,
-                                             const double2 *__restrict__ basis, double *__restrict__ lnl) {
-  const int lane = threadIdx.x & 63;
-  const int n_modes = c.n_modes, q = c.q, T = c.T;
-  const int P = c.n_det * n_modes;
-  const int G = 64 / P;
-  const int pair = lane / G;
-  const int gl = lane - pair * G;
-  const bool active = pair < P;
-  const int k = active ? pair / n_modes : 0;
-  const int a = active ? pair - k * n_modes : 0;
+// lanes stride over its q basis coefficients: lane g of pair (k, a)
+// accumulates sum_i C_i sum_p f^p B4[n0][i][p] over i = g, g+G, ... with the
+// spline-folded basis B4 (the entries of one row are contiguous in i, so the
+// G lanes of a pair read adjacent 64-byte groups).  Partial sums meet in the pair's first lane by shuffles; that lane
+// forms Re(conj(A) z), the detector's first lane the overlap term, lane 0 the
+// sum, all with compensated (Neumaier) additions.
+constexpr int kEpiBatch = 64;
 
+struct EpiSetup {
+  int status;                       // 0 evaluate, 1 outside the domain (-inf), 2 NaN input
+  int event;                        // multi-event batches: the proposal's event
+  int n0[RBFL_MAX_DET];             // spline stencil base sample per detector
+  double f[RBFL_MAX_DET];           // fractional sample position per detector
+  double rr;                        // d_ref / d_L
+  double Ar[RBFL_MAX_DET][RBFL_MAX_MODES], Ai[RBFL_MAX_DET][RBFL_MAX_MODES];
+};
+
+__device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
+                                          int64_t g, EpiSetup &o) {
   double p[11];
-#pragma unroll
-  for (int i = 0; i < 11; ++i) p[i] = params[i * ld + g];
   bool any_nan = false;
 #pragma unroll
-  for (int i = 0; i < 11; ++i) any_nan |= isnan(p[i]);
+  for (int i = 0; i < 11; ++i) {
+    p[i] = params[i * ld + g];
+    any_nan |= isnan(p[i]);
+  }
   if (any_nan) {
-    if (lane == 0) lnl[g] = __builtin_nan("");
+    o.status = 2;
     return;
   }
   // a1: inside the ellipsoid and physical
@@ -255,50 +264,67 @@ __device__ __forceinline__ void epilogue_one(const EvalConsts &c, const double *
     valid = valid && theta_to_phys(th, c.f0, c.chi_max, phys);
   }
   const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
-  const double rr = c.d_ref / dl;
-
-  // a4: this lane's detector -- response, arrival time, stencil and weights
-  double fp, fc, dt;
-  detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
-  const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
-  const double fl = floor(s);
-  const bool in_window = fl >= 4.0 && fl <= (double)(T - 6);
-  valid = valid && __all(!active || in_window);
-  if (!valid) {
-    if (lane == 0) lnl[g] = -__builtin_huge_val();
-    return;
-  }
-  const double f = s - fl;
-  const int n0 = (int)fl;
-  double w[kSplineTaps];
-#pragma unroll
-  for (int t = 0; t < kSplineTaps; ++t)
-    w[t] = c.spline[t][0] + f * (c.spline[t][1] + f * (c.spline[t][2] + f * c.spline[t][3]));
-  // a6: A_{k,lm} = [(F+ + iFx) Y_{l,-m} + (-1)^l (F+ - iFx) conj(Y_{lm})] / 2
+  o.rr = c.d_ref / dl;
   double ch, sh;
   sincos(0.5 * iota, &sh, &ch);
-  double ynr, yni, ypr, ypi;
-  eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr, &yni);
-  eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr, &ypi);
-  const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
-  const double ar = 0.5 * ((fp * ynr - fc * yni) + sg * (fp * ypr - fc * ypi));
-  const double ai = 0.5 * ((fp * yni + fc * ynr) + sg * (-fp * ypi - fc * ypr));
-  // a5: partial reconstruction of z_{k,a} over this lane's coefficients
+  double ynr[RBFL_MAX_MODES], yni[RBFL_MAX_MODES], ypr[RBFL_MAX_MODES], ypi[RBFL_MAX_MODES];
+  for (int a = 0; a < c.n_modes; ++a) {
+    eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr[a], &yni[a]);
+    eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr[a], &ypi[a]);
+  }
+  const int T = c.T;
+  for (int k = 0; k < c.n_det; ++k) {
+    // a4: detector response, arrival time and spline stencil
+    double fp, fc, dt;
+    detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
+    const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
+    const double fl = floor(s);
+    valid = valid && fl >= 4.0 && fl <= (double)(T - 6);
+    o.n0[k] = valid ? (int)fl : 4;
+    o.f[k] = s - fl;
+    // a6: amplitudes of every mode at this detector
+    for (int a = 0; a < c.n_modes; ++a) {
+      const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
+      o.Ar[k][a] = 0.5 * ((fp * ynr[a] - fc * yni[a]) + sg * (fp * ypr[a] - fc * ypi[a]));
+      o.Ai[k][a] = 0.5 * ((fp * yni[a] + fc * ynr[a]) + sg * (-fp * ypi[a] - fc * ypr[a]));
+    }
+  }
+  o.status = valid ? 0 : 1;
+}
+
+// ln L of one proposal from its setup o and interpolated row y; one whole
+// wave per call, result written to *out by lane 0.
+__device__ __forceinline__ void epi_reduce(const EvalConsts &c, const EpiSetup &o, const double *__restrict__ y,
+                                           const double2 *__restrict__ basis4, double *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  if (o.status != 0) {
+    if (lane == 0) *out = o.status == 2 ? __builtin_nan("") : -__builtin_huge_val();
+    return;
+  }
+  const int n_modes = c.n_modes, q = c.q, T = c.T;
+  const int P = c.n_det * n_modes;
+  const int G = 64 / P;
+  const int pair = lane / G;
+  const int gl = lane - pair * G;
+  const bool active = pair < P;
+  const int k = active ? pair / n_modes : 0;
+  const int a = active ? pair - k * n_modes : 0;
+  const double f = o.f[k];
+  const int n0 = o.n0[k];
+  const double ar = o.Ar[k][a], ai = o.Ai[k][a];
+  // a5: partial reconstruction of z_{k,a} over this lane's coefficients; the
+  // spline-folded basis gives the interpolated basis value as a cubic in f
   double zr = 0.0, zi = 0.0;
   if (active) {
-    const int o = c.coef_off[k][a];
-    const double2 *base = basis + ((int64_t)(k * n_modes + a) * T + (n0 - 4)) * q;
+    const int off = c.coef_off[k][a];
+    const double2 *base = basis4 + ((int64_t)(k * n_modes + a) * T + n0) * q * 4;
     for (int i = gl; i < q; i += G) {
-      const double cr = y[o + 2 * i], ci = y[o + 2 * i + 1];
-      double br = 0.0, bi = 0.0;
-#pragma unroll
-      for (int t = 0; t < kSplineTaps; ++t) {
-        const double2 v = base[t * q + i];
-        br = fma(w[t], v.x, br);
-        bi = fma(w[t], v.y, bi);
-      }
-      zr += cr * br - ci * bi;
-      zi += cr * bi + ci * br;
+      const double2 cc = *reinterpret_cast<const double2 *>(y + off + 2 * i);
+      const double2 v0 = base[4 * i], v1 = base[4 * i + 1], v2 = base[4 * i + 2], v3 = base[4 * i + 3];
+      const double br = fma(fma(fma(v3.x, f, v2.x), f, v1.x), f, v0.x);
+      const double bi = fma(fma(fma(v3.y, f, v2.y), f, v1.y), f, v0.y);
+      zr += cc.x * br - cc.y * bi;
+      zi += cc.x * bi + cc.y * br;
     }
   }
   // combine the G partials of each pair in its first lane (fixed order)
@@ -309,37 +335,31 @@ __device__ __forceinline__ void epilogue_one(const EvalConsts &c, const double *
     ti += __shfl(zi, lead + j, 64);
   }
   const double zterm = ar * tr + ai * ti;   // Re(conj(A) z), valid in pair leaders
-  // overlap term of detector k in its first pair's leader: needs every A_{k,b}
+  // overlap term of detector k: every A_{k,b} is in the setup
   const int det_lead = k * n_modes * G;
   double st_s = 0.0, st_c = 0.0, zt_s = 0.0, zt_c = 0.0;
   {
-    double Ar[RBFL_MAX_MODES], Ai[RBFL_MAX_MODES], Zt[RBFL_MAX_MODES];
-    for (int m = 0; m < n_modes; ++m) {
-      const int src = det_lead + m * G;
-      Ar[m] = __shfl(ar, src, 64);
-      Ai[m] = __shfl(ai, src, 64);
-      Zt[m] = __shfl(zterm, src, 64);
-    }
-    const int so = c.sig_off[k];
     auto add = [](double &sum, double &comp, double v) {
       const double t = sum + v;
       comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
       sum = t;
     };
+    const int so = c.sig_off[k];
     for (int m = 0; m < n_modes; ++m) {
-      add(zt_s, zt_c, Zt[m]);
-      add(st_s, st_c, (Ar[m] * Ar[m] + Ai[m] * Ai[m]) * y[so + m]);
+      add(zt_s, zt_c, __shfl(zterm, det_lead + m * G, 64));
+      add(st_s, st_c, (o.Ar[k][m] * o.Ar[k][m] + o.Ai[k][m] * o.Ai[k][m]) * y[so + m]);
     }
     int pidx = so + n_modes;
     for (int m = 0; m < n_modes; ++m)
       for (int mm = m + 1; mm < n_modes; ++mm) {
         const double sr = y[pidx], si = y[pidx + 1];
         pidx += 2;
-        const double pr = Ar[m] * Ar[mm] + Ai[m] * Ai[mm];
-        const double pi = Ar[m] * Ai[mm] - Ai[m] * Ar[mm];
+        const double pr = o.Ar[k][m] * o.Ar[k][mm] + o.Ai[k][m] * o.Ai[k][mm];
+        const double pi = o.Ar[k][m] * o.Ai[k][mm] - o.Ai[k][m] * o.Ar[k][mm];
         add(st_s, st_c, 2.0 * (pr * sr - pi * si));
       }
   }
+  const double rr = o.rr;
   const double term = rr * (zt_s + zt_c) - 0.5 * rr * rr * (st_s + st_c);   // valid in detector leaders
   double tot = 0.0, comp = 0.0;
   for (int kk = 0; kk < c.n_det; ++kk) {
@@ -348,16 +368,23 @@ __device__ __forceinline__ void epilogue_one(const EvalConsts &c, const double *
     comp += fabs(tot) >= fabs(v) ? (tot - t) + v : (v - t) + tot;
     tot = t;
   }
-  if (lane == 0) lnl[g] = tot + comp;
+  if (lane == 0) *out = tot + comp;
 }
 
 __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restrict__ cp,
                                                        const double *__restrict__ params, int64_t ld, int64_t b0,
                                                        int64_t nb, const double *__restrict__ Y,
-                                                       const double2 *__restrict__ basis, double *__restrict__ lnl) {
-  const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (b >= nb) return;   // whole wave leaves together
-  epilogue_one(*cp, params, ld, b0 + b, Y + b * cp->Kp, basis, lnl);
+                                                       const double2 *__restrict__ basis4, double *__restrict__ lnl) {
+  __shared__ EpiSetup su[kEpiBatch];
+  const EvalConsts &c = *cp;
+  const int64_t first = (int64_t)blockIdx.x * kEpiBatch;
+  if (threadIdx.x < kEpiBatch && first + threadIdx.x < nb) epi_setup(c, params, ld, b0 + first + threadIdx.x, su[threadIdx.x]);
+  __syncthreads();
+  for (int j = threadIdx.x >> 6; j < kEpiBatch; j += kWaves) {
+    const int64_t b = first + j;
+    if (b >= nb) break;   // whole wave leaves together
+    epi_reduce(c, su[j], Y + b * c.Kp, basis4, lnl + b0 + b);
+  }
 }
 
 // ---- multi-event (ragged) batch --------------------------------------------
@@ -392,21 +419,32 @@ __global__ void k_zero_counter(unsigned long long *counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
-// One wave per proposal of the concatenated batch; the proposal's event is
-// found by binary search over the events' first proposals (caller order).
+// The epilogue's two phases over the concatenated batch; each proposal's
+// event is found in the setup phase by binary search over the events' first
+// proposals (caller order).
 __global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *__restrict__ ev, int n_ev,
                                                               const double *__restrict__ params, int64_t total,
                                                               double *__restrict__ lnl) {
-  const int64_t g = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (g >= total) return;
-  int lo = 0, hi = n_ev - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ev[mid].q0 <= g) lo = mid;
-    else hi = mid - 1;
+  __shared__ EpiSetup su[kEpiBatch];
+  const int64_t first = (int64_t)blockIdx.x * kEpiBatch;
+  if (threadIdx.x < kEpiBatch && first + threadIdx.x < total) {
+    const int64_t g = first + threadIdx.x;
+    int lo = 0, hi = n_ev - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ev[mid].q0 <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    epi_setup(*ev[lo].consts, params, total, g, su[threadIdx.x]);
+    su[threadIdx.x].event = lo;
   }
-  const EventDesc &d = ev[lo];
-  epilogue_one(*d.consts, params, total, g, d.Y + (g - d.q0) * d.Kp, d.basis, lnl);
+  __syncthreads();
+  for (int j = threadIdx.x >> 6; j < kEpiBatch; j += kWaves) {
+    const int64_t g = first + j;
+    if (g >= total) break;   // whole wave leaves together
+    const EventDesc &d = ev[su[j].event];
+    epi_reduce(*d.consts, su[j], d.Y + (g - d.q0) * d.Kp, d.basis, lnl + g);
+  }
 }
 
 // Surrogate inputs: x = delta_e / a in FP32, [nb][4].
@@ -574,15 +612,15 @@ void launch_ragged_contract(int variant, const EventDesc *ev, int n_ev, int64_t 
 
 void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params, int64_t total, double *lnl,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_ragged_epilogue, dim3((unsigned)((total + kWaves - 1) / kWaves)), dim3(kThreads), 0, s, ev,
-                     n_ev, params, total, lnl);
+  hipLaunchKernelGGL(k_ragged_epilogue, dim3((unsigned)((total + kEpiBatch - 1) / kEpiBatch)), dim3(kThreads), 0, s,
+                     ev, n_ev, params, total, lnl);
   RBFL_HIP(hipGetLastError());
 }
 
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s) {
   (void)hc;
-  dim3 grid((unsigned)((nb + kWaves - 1) / kWaves));
+  dim3 grid((unsigned)((nb + kEpiBatch - 1) / kEpiBatch));
   hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
   RBFL_HIP(hipGetLastError());
 }

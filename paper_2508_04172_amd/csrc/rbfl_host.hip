@@ -900,6 +900,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   spline_table(e.spline);
   c.consts.alloc(1);
   RBFL_HIP(hipMemcpyAsync(c.consts.p, &e, sizeof(e), hipMemcpyHostToDevice, stream));
+  c.basis4.alloc((size_t)c.n_det * c.n_modes * c.T * c.q * 4);
+  launch_fold_spline(c.basis.p, c.n_det * c.n_modes, c.T, c.q, c.consts.p, c.basis4.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
   c.timing[5] = seconds_since(t_all);
 }
@@ -940,7 +942,7 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
         c.timed_events.push_back(e);
       }
       contract(c, params, n, b0, nb, form, s, ev);
-      launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
+      launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis4.p, lnl, s);
       RBFL_HIP(hipEventRecord(ev[3], s));
       c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
       c.timed.push_back(Ctx::Timed{ev[1], ev[2], 0, nb});
@@ -948,7 +950,7 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
       continue;
     }
     contract(c, params, n, b0, nb, form, s);
-    launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis.p, lnl, s);
+    launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis4.p, lnl, s);
   }
 }
 
@@ -1024,7 +1026,7 @@ static void interp(Ctx &c, const double *params, int64_t n, double *out, int for
 static std::vector<double> lnl_probe(Ctx &c, const double *params, int64_t n, int64_t nb, int form, double *dev,
                                      hipStream_t s) {
   contract(c, params, n, 0, nb, form, s);
-  launch_epilogue(c.consts.p, c.host_consts, params, n, 0, nb, c.Y.p, c.basis.p, dev, s);
+  launch_epilogue(c.consts.p, c.host_consts, params, n, 0, nb, c.Y.p, c.basis4.p, dev, s);
   std::vector<double> h(nb);
   RBFL_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
   RBFL_HIP(hipStreamSynchronize(s));
@@ -1341,7 +1343,7 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
     d[e].consts = c.consts.p;
     d[e].nodes = c.nodes.p;
     d[e].W = c.W.p;
-    d[e].basis = c.basis.p;
+    d[e].basis = c.basis4.p;
     d[e].Y = p.Y.p + yoff;
     d[e].q0 = q0;
     d[e].n = p.counts[e];

@@ -48,7 +48,7 @@ struct EventDesc {
   const EvalConsts *consts;
   const double *nodes;
   const double *W;
-  const double2 *basis;
+  const double2 *basis;         // spline-folded basis [pair][T][q][4]
   double *Y;           // this event's rows of the shared work space, [n][Kp]
   int64_t q0, n;       // first proposal (column of the concatenated params) and count
   int64_t item0;       // first work item of this event (work order)
@@ -118,6 +118,7 @@ struct Ctx {
   DevBuf<double> nodes;        // [rows][4] unit-ball coordinates, zero-padded
   DevBuf<double> W;            // [rows][Kp] RBF weights, zero-padded
   DevBuf<double2> basis;       // [n_det][n_modes][T][q]
+  DevBuf<double2> basis4;      // spline-folded basis [n_det][n_modes][T][q][4]
   DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
@@ -169,6 +170,8 @@ void launch_sigma(const double2 *A, int nb, int n_modes, int J, const double *wk
 void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
                        int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s);
 void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, double2 *Z_rows, hipStream_t s);
+void launch_fold_spline(const double2 *B, int n_pairs, int T, int q, const EvalConsts *c, double2 *B4,
+                        hipStream_t s);
 void launch_basis_from_u(const double2 *U, int T, int ldu, int q, double2 *B, hipStream_t s);
 void launch_coeffs(const double2 *Z, const double2 *B, int N, int T, int q, double2 *C, hipStream_t s);
 void launch_assemble_rhs(const double2 *C, const double2 *sig, const int4 *coldesc, int N, int K, int NM,
