@@ -93,7 +93,8 @@ def main():
     sp = stream.cuda_stream
     h.reserve(65536)
     tune = {}
-    for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32), ("split", rbfl.FORM_SPLIT)):
+    for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32), ("bf16", rbfl.FORM_BF16),
+                       ("split", rbfl.FORM_SPLIT)):
         if form != rbfl.FORM_FP64:
             h.prepare(form)
         tune[name] = h.autotune(params.data_ptr(), n, form, sp)
@@ -125,7 +126,7 @@ def main():
     rows_ms = ks["rows_ms"] / max(1, ks["rows_launches"])
     epi_ms = ks["epilogue_ms"] / max(1, ks["epilogue_launches"])
     # basis-row stage: writes 8 bytes per padded row per proposal, reads 32 bytes of coordinates
-    rows_padded = (NM + 63) // 64 * 64
+    rows_padded = (NM + 31) // 32 * 32      # the library pads N + M to a multiple of 32
     rows_bytes = (8.0 * rows_padded + 32.0) * per_launch_n
     fp64_variant = tune["fp64"]["variant"]
     fused = fp64_variant >= 4
@@ -138,7 +139,7 @@ def main():
                       "rows_gbs": rows_bytes / (rows_ms * 1e-3) / 1e9 if rows_ms > 0 else None,
                       "epilogue_ms_per_launch": epi_ms}}
     outs = {"fp64": l64}
-    for name, form in (("fp32", rbfl.FORM_FP32), ("split", rbfl.FORM_SPLIT)):
+    for name, form in (("fp32", rbfl.FORM_FP32), ("bf16", rbfl.FORM_BF16), ("split", rbfl.FORM_SPLIT)):
         w2, ks2, lf = run_form(form, max(3, args.steps // 2), 1)
         v2 = n * max(3, args.steps // 2) / w2
         c2 = ks2["contract_ms"] / max(1, ks2["contract_launches"])

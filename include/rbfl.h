@@ -49,7 +49,9 @@ enum rbfl_status {
 enum rbfl_form {
   RBFL_FORM_FP64 = 0,       /* plain: FP64 kernel rows, FP64 MFMA contraction, FP64 epilogue */
   RBFL_FORM_FP32 = 1,       /* FP32 kernel rows and FP32 MFMA contraction, FP64 epilogue */
-  RBFL_FORM_BF16 = 2,       /* BF16 operands, FP32-accumulating MFMA, FP64 epilogue */
+  RBFL_FORM_BF16 = 2,       /* kernel rows and weights rounded to BF16, FP32-accumulating MFMA
+                               16x16x32, FP64 epilogue (for its error report: an 8-bit
+                               significand does not carry the interpolant's cancellation) */
   RBFL_FORM_SPLIT = 3,      /* error-free split products: FP64 kernel rows and weight columns, each
                                scaled by a power of two into [-1, 1], written in S signed base-254
                                int8 digits; every digit pair i + j < S on int8 MFMA with exact int32

@@ -536,14 +536,15 @@ static void launch_fp64_variant(const EvalConsts *c, const EvalConsts &hc, const
 }
 
 int contract_variants(int form) {
-  return form == RBFL_FORM_FP64 ? 5 : form == RBFL_FORM_SPLIT ? split_variant_count() : 2;
+  return form == RBFL_FORM_FP64 ? 5 : form == RBFL_FORM_SPLIT ? split_variant_count() : form == RBFL_FORM_BF16 ? 1 : 2;
 }
 
 const char *contract_variant_name(int form, int v) {
   static const char *f64[] = {"fp64 rt2 ct4 ch32", "fp64 rt2 ct4 ch16", "fp64 rt2 ct8 ch16", "fp64 rt4 ct4 ch16",
                               "fp64 rt4 ct2 ch32"};
-  static const char *f32[] = {"fp32 rt2 ct4 ch64", "fp32 rt2 ct8 ch32"};
+  static const char *f32[] = {"fp32 rt2 ct4 ch32", "fp32 rt2 ct8 ch32"};
   if (form == RBFL_FORM_FP64) return v < gemm_fp64_variants() ? gemm_fp64_variant_name(v) : "fused rt2 ct8 ch16";
+  if (form == RBFL_FORM_BF16) return "bf16 64x64 16x16x32";
   return form == RBFL_FORM_SPLIT ? split_variant_name(v) : f32[v];
 }
 
@@ -562,7 +563,7 @@ template <int RT, int CT, int CH>
 static void launch_fp32_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                                 int64_t b0, int64_t nb, const double *nodes, const float *W, double *Y,
                                 hipStream_t s) {
-  static_assert(kColTile % (CT * 16) == 0, "K is padded to a multiple of every column tile");
+  static_assert(kColTile % (CT * 16) == 0 && kRowChunk % CH == 0, "K and the rows are padded to whole tiles");
   const int64_t qt = kWaves * RT * 16;
   const int cw = CT * 16;
   dim3 grid((unsigned)((nb + qt - 1) / qt), (unsigned)((hc.Kp + cw - 1) / cw));
@@ -575,13 +576,9 @@ void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const doubl
   if (variant == 1)
     launch_fp32_variant<2, 8, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
   else
-    launch_fp32_variant<2, 4, 64>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
+    launch_fp32_variant<2, 4, 32>(c, hc, params, ld, b0, nb, nodes, W, Y, s);
 }
 
-void launch_contract_bf16(const EvalConsts *, const EvalConsts &, const double *, int64_t, int64_t, int64_t,
-                          const double *, const uint16_t *, double *, hipStream_t) {
-  throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
-}
 
 int ragged_variants() { return 3; }
 

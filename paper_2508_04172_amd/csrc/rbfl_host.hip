@@ -911,6 +911,7 @@ static void reserve(Ctx &c, int64_t n) {
   c.Y.alloc((size_t)n * c.Kp);
   c.Bt.alloc((size_t)c.rows * rows_ld(n));
   c.cap = n;
+  if (c.prepared[RBFL_FORM_BF16]) c.A16.alloc((size_t)c.rows * n);
   if (c.prepared[RBFL_FORM_SPLIT]) {
     c.AS.alloc((size_t)split_max_slices() * n * c.rows);
     c.ASscale.alloc(n);
@@ -998,8 +999,8 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
       }
       break;
     default:
-      mark(1);
-      launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W16.p, c.Y.p, s);
+      launch_contract_bf16(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.A16.p, c.W16.p, c.Y.p, s,
+                           marks ? marks[1] : nullptr);
   }
   mark(2);
 }
@@ -1097,7 +1098,15 @@ static void prepare(Ctx &c, int form) {
   if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
   if (c.prepared[form]) return;
   const size_t n = (size_t)c.rows * c.Kp;
-  if (form == RBFL_FORM_BF16) throw Error(RBFL_E_UNSUPPORTED, "the BF16 form is not available in this build");
+  if (form == RBFL_FORM_BF16) {
+    c.W16.alloc(n);
+    launch_bf16_prepare(c.W.p, c.rows, c.Kp, c.W16.p, 0);
+    if (c.cap == 0) reserve(c, 65536);
+    c.A16.alloc((size_t)c.rows * c.cap);
+    RBFL_HIP(hipDeviceSynchronize());
+    c.prepared[RBFL_FORM_BF16] = true;
+    return;
+  }
   if (form == RBFL_FORM_SPLIT) {
     if (c.rows > split_max_rows())
       throw Error(RBFL_E_UNSUPPORTED, "the split form needs N + M <= " + std::to_string(split_max_rows()));

@@ -15,7 +15,7 @@ namespace rbfl {
 
 constexpr int kMaxPoly = 35;     // monomials of degree <= 3 in 4 variables
 constexpr int kSplineTaps = 10;  // samples in the sub-sample spline stencil
-constexpr int kRowChunk = 64;    // node rows per contraction chunk (W rows padded to this)
+constexpr int kRowChunk = 32;    // W rows padded to a multiple of this (every row step divides it)
 constexpr int kColTile = 128;    // widest contraction column tile; K is padded to a multiple of it
 
 // Error carrying an rbfl_status through the host code; converted at the ABI.
@@ -122,7 +122,8 @@ struct Ctx {
   DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
-  DevBuf<uint16_t> W16;        // [rows][Kp] bf16
+  DevBuf<uint16_t> W16;        // BF16 form: weights in 8-row groups [rows/8][Kp][8]
+  DevBuf<uint16_t> A16;        // BF16 form: kernel rows of one chunk [rows/8][cap][8]
   DevBuf<int8_t> WS;           // split form: weight slices [S][Kp][rows]
   DevBuf<double> WSscale;      // split form: power-of-two column scales [Kp]
   DevBuf<int8_t> AS;           // split form: kernel-row slices of one chunk [S][cap][rows]
@@ -200,9 +201,10 @@ void launch_contract_fp64(const EvalConsts *c, const EvalConsts &hc, const doubl
 void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
                           int64_t b0, int64_t nb, const double *nodes, const float *W, double *Y, hipStream_t s,
                           int variant);
-void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld,
-                          int64_t b0, int64_t nb, const double *nodes, const uint16_t *W, double *Y,
-                          hipStream_t s);
+void launch_bf16_prepare(const double *W, int rows, int Kp, uint16_t *WB, hipStream_t s);
+void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                          int64_t nb, const double *nodes, uint16_t *AB, const uint16_t *WB, double *Y,
+                          hipStream_t s, hipEvent_t mid);
 int ragged_variants();
 void ragged_tile(int variant, int *proposals_per_tile, int *columns_per_tile);
 void launch_ragged_contract(int variant, const EventDesc *ev, int n_ev, int64_t total_items,

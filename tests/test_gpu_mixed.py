@@ -9,9 +9,10 @@ FP64 bar widened by that worst-case bound.  After rbfl_autotune (which keeps
 only digit counts within 1e-4 of the FP64 form on the tuning proposals) it is
 held to 1e-3 against the oracle on other proposals.
 
-FP32 form: reported, not held to 1e-3 (its FP32 kernel rows and sums lose
-what the interpolant's cancellation amplifies); the test checks only that it
-runs, keeps the FP64 domain flags and stays finite where they are set.
+FP32 and BF16 forms: reported, not held to 1e-3 (their kernel rows, weights
+and sums lose what the interpolant's cancellation amplifies); the tests check
+only that they run, keep the FP64 domain flags and stay finite where those
+are set.
 """
 import numpy as np
 import pytest
@@ -87,6 +88,23 @@ def test_fp32_reported(name):
     d = np.abs(lg[fin] - lo[fin])
     q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
     print(f"[mixed] {name} fp32: |dlnL| median {q[0]:.3e}, 90% {q[1]:.3e}, 99% {q[2]:.3e}, max {q[3]:.3e}",
+          flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bf16_reported(name):
+    """The BF16 form: runs, keeps the FP64 domain flags, stays finite where they
+    are set; its error distribution is reported."""
+    cfg, art, h = _prepared(name, rbfl.FORM_BF16)
+    qd = wl.queries(cfg, n=min(cfg.n_queries, 3000))
+    lg = gpu_eval(h, qd, cfg.t_trig, rbfl.FORM_BF16)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isinf(lg) == False)  # noqa: E712
+    assert not np.isnan(lg).any()
+    d = np.abs(lg[fin] - lo[fin])
+    q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    print(f"[mixed] {name} bf16: |dlnL| median {q[0]:.3e}, 90% {q[1]:.3e}, 99% {q[2]:.3e}, max {q[3]:.3e}",
           flush=True)
 
 

@@ -212,13 +212,18 @@ def test_edge_cases():
     h.eval(pt.data_ptr(), 4, o.data_ptr())
     torch.cuda.synchronize()
     assert math.isnan(o[2].item())
-    # an unprepared form is a state error, an unknown one an argument error
-    with pytest.raises(rbfl.RbflError) as e:
-        h.eval(pt.data_ptr(), 4, o.data_ptr(), rbfl.FORM_BF16)
-    assert e.value.code in (rbfl.E_STATE, rbfl.E_UNSUPPORTED)
+    # an unknown form is an argument error, an unprepared one a state error (on
+    # a fresh handle: the cached ones may have been prepared by other tests)
     with pytest.raises(rbfl.RbflError) as e:
         h.eval(pt.data_ptr(), 4, o.data_ptr(), 17)
     assert e.value.code == rbfl.E_INVALID_ARG
+    small = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=10)
+    fresh = rbfl.Handle.from_config(small, None, wl.injection_extrinsics(small))
+    p2 = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(fresh, wl.queries(small, n=4), small.t_trig))).cuda()
+    for form in (rbfl.FORM_FP32, rbfl.FORM_BF16, rbfl.FORM_SPLIT):
+        with pytest.raises(rbfl.RbflError) as e:
+            fresh.eval(p2.data_ptr(), 4, o.data_ptr(), form)
+        assert e.value.code == rbfl.E_STATE
 
 
 def test_batch_larger_than_work_space():
