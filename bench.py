@@ -33,6 +33,39 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_gemm_fp64_cfg2_hlv_5mode.md")
+
+
+def gemm_source_hash() -> str:
+    """Hash of what fixes the FP64 GEMM's memory traffic: its source file and
+    the row and column padding of the library."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2508_04172_amd", "csrc")
+    h = hashlib.sha256(open(os.path.join(csrc, "contract_fp64.hip"), "rb").read())
+    consts = open(os.path.join(csrc, "rbfl_internal.h")).read()
+    for name in ("kRowChunk", "kColTile"):
+        h.update(re.search(rf"constexpr int {name} = (\d+);", consts).group(0).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(variant: int, per_launch_n: float):
+    """HBM bytes per launch of k_gemm_fp64 (FETCH_SIZE and WRITE_SIZE, each
+    scaled by the copy-kernel calibration) from the committed profile summary,
+    for this source and tile variant, scaled to the average launch; None when
+    the kernel has changed since the counters were taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    src = gemm_source_hash()
+    for line in open(PROFILE):
+        if not line.startswith("traffic-record:"):
+            continue
+        kv = dict(f.split("=", 1) for f in line.split()[1:])
+        if kv.get("kernel") == "k_gemm_fp64" and kv.get("source") == src and int(kv["variant"]) == variant:
+            return float(kv["bytes"]) * per_launch_n / float(kv["proposals"])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,7 +162,7 @@ def main():
     rows_padded = (NM + 31) // 32 * 32      # the library pads N + M to a multiple of 32
     rows_bytes = (8.0 * rows_padded + 32.0) * per_launch_n
     fp64_variant = tune["fp64"]["variant"]
-    fused = fp64_variant >= 4
+    fused = fp64_variant == len(tune["fp64"]["ms"]) - 1    # the last FP64 variant is the fused kernel
     log(f"FP64: {value:.4e} evals/s, {ms_per_step:.2f} ms/step; rows {rows_ms:.3f} ms/launch, contraction "
         f"{contract_ms:.3f} ms/launch ({achieved / 1e12:.2f} TFLOP/s), epilogue {epi_ms:.3f} ms/launch")
 
@@ -180,7 +213,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_contract_fp64 (fused rows)" if fused else "k_gemm_fp64",
                      "achieved": achieved / 1e12,
                      "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                     "traffic": None, "flop_per_launch": flop_per_query * per_launch_n,
+                     "traffic": None if fused else recorded_traffic(fp64_variant, per_launch_n),
+                     "flop_per_launch": flop_per_query * per_launch_n,
                      "launch_ms": contract_ms},
         "forms": forms,
         "autotune": tune,

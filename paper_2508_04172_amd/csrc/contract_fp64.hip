@@ -183,11 +183,11 @@ void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc
 
 int64_t rows_ld(int64_t n) { return (n + 7) & ~int64_t(7); }
 
-int gemm_fp64_variants() { return 4; }
+int gemm_fp64_variants() { return 5; }
 
 const char *gemm_fp64_variant_name(int v) {
-  static const char *names[] = {"rows + gemm 128x128 kc16", "rows + gemm 128x128 kc8", "rows + gemm 64x128 kc16",
-                                "rows + gemm 128x64 kc16"};
+  static const char *names[] = {"rows + gemm 64x128 kc8",  "rows + gemm 128x64 kc8", "rows + gemm 64x128 kc16",
+                                "rows + gemm 128x64 kc16", "rows + gemm 64x64 kc8"};
   return names[v];
 }
 
@@ -203,10 +203,11 @@ void launch_gemm_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const 
                       int variant) {
   const int64_t ldb = rows_ld(nb);
   switch (variant) {
-    case 0: launch_gemm<4, 4, 16>(Bt, nb, ldb, hc, W, Y, s); break;
-    case 1: launch_gemm<4, 4, 8>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 0: launch_gemm<2, 4, 8>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 1: launch_gemm<4, 2, 8>(Bt, nb, ldb, hc, W, Y, s); break;
     case 2: launch_gemm<2, 4, 16>(Bt, nb, ldb, hc, W, Y, s); break;
     case 3: launch_gemm<4, 2, 16>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 4: launch_gemm<2, 2, 8>(Bt, nb, ldb, hc, W, Y, s); break;
     default: throw Error(RBFL_E_INVALID_ARG, "unknown FP64 GEMM variant");
   }
 }

@@ -536,7 +536,7 @@ static void launch_fp64_variant(const EvalConsts *c, const EvalConsts &hc, const
 }
 
 int contract_variants(int form) {
-  return form == RBFL_FORM_FP64 ? 5 : form == RBFL_FORM_SPLIT ? split_variant_count() : form == RBFL_FORM_BF16 ? 1 : 2;
+  return form == RBFL_FORM_FP64 ? gemm_fp64_variants() + 1 : form == RBFL_FORM_SPLIT ? split_variant_count() : form == RBFL_FORM_BF16 ? 1 : 2;
 }
 
 const char *contract_variant_name(int form, int v) {

@@ -1055,9 +1055,11 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
   RBFL_HIP(hipEventCreate(&e1));
   int best = -1;
   double best_ms = 1e300;
+  // accuracy of each split variant, and one warm-up launch of every variant
+  bool eligible[8];
   for (int v = 0; v < nv && v < 8; ++v) {
     c.variant[form] = v;
-    bool eligible = true;
+    eligible[v] = true;
     if (form == RBFL_FORM_SPLIT) {
       const std::vector<double> got = lnl_probe(c, params, n, nb, form, probe.p, s);
       double err = 0.0;
@@ -1069,23 +1071,35 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
         if (std::isfinite(ref[i])) err = std::max(err, std::fabs(got[i] - ref[i]));
       }
       c.split_err[v] = err;
-      eligible = err <= RBFL_SPLIT_TOL;
+      eligible[v] = err <= RBFL_SPLIT_TOL;
     }
-    contract(c, params, n, 0, nb, form, s);   // warm-up
-    double t[3];
-    for (int r = 0; r < 3; ++r) {
-      RBFL_HIP(hipEventRecord(e0, s));
-      contract(c, params, n, 0, nb, form, s);
-      RBFL_HIP(hipEventRecord(e1, s));
-      RBFL_HIP(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
-      t[r] = ms;
+    contract(c, params, n, 0, nb, form, s);
+  }
+  // two interleaved rounds of three timed launches per variant (so that no
+  // variant is timed alone while the clocks settle); keep each variant's
+  // smaller round median
+  double med[8];
+  for (int v = 0; v < 8; ++v) med[v] = 1e300;
+  for (int round = 0; round < 2; ++round)
+    for (int v = 0; v < nv && v < 8; ++v) {
+      c.variant[form] = v;
+      double t[3];
+      for (int r = 0; r < 3; ++r) {
+        RBFL_HIP(hipEventRecord(e0, s));
+        contract(c, params, n, 0, nb, form, s);
+        RBFL_HIP(hipEventRecord(e1, s));
+        RBFL_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t[r] = ms;
+      }
+      std::sort(t, t + 3);
+      med[v] = std::min(med[v], t[1]);
     }
-    std::sort(t, t + 3);
-    c.tune_ms[form][v] = t[1];
-    if (eligible && t[1] < best_ms) {
-      best_ms = t[1];
+  for (int v = 0; v < nv && v < 8; ++v) {
+    c.tune_ms[form][v] = med[v];
+    if (eligible[v] && med[v] < best_ms) {
+      best_ms = med[v];
       best = v;
     }
   }

@@ -238,8 +238,9 @@ def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
                   base: Config = CFG2, seg_range=(8.0, 512.0), node_range=(200, 1500),
                   q_range=(20, 60)) -> List[Config]:
     """Uneven events for the multi-event batch: segment length log-uniform in
-    [8, 512] s, m1 ~ U[5, 20], m2 ~ U[1, 3], chi1 ~ U[-0.998, 0.998],
-    chi2 ~ U[-0.05, 0.05] (the paper's NSBH injection ranges), 1-5 modes,
+    [8, 512] s, m1 ~ U[5, 20], m2 ~ U[1, 3] with m1 / m2 <= 10,
+    chi1 ~ U[-0.998, 0.998], chi2 ~ U[-0.05, 0.05] (the paper's NSBH injection
+    ranges, Sec. III A and Table I), 1-5 modes,
     200-1500 nodes, q in 20-60.  f_low is raised above 20 Hz where needed so
     that the Newtonian chirp time fits in 90% of the segment."""
     rng = np.random.default_rng(seed)
@@ -249,6 +250,9 @@ def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
         seg = float(round(math.exp(rng.uniform(math.log(seg_range[0]), math.log(seg_range[1])))))
         m1 = rng.uniform(5.0, 20.0)
         m2 = rng.uniform(1.0, 3.0)
+        while m1 > 10.0 * m2:              # Table I keeps the mass ratio within [1, 10]
+            m1 = rng.uniform(5.0, 20.0)
+            m2 = rng.uniform(1.0, 3.0)
         c1 = rng.uniform(-0.998, 0.998)
         c2 = rng.uniform(-0.05, 0.05)
         n_modes = int(rng.integers(1, 6))
