@@ -226,16 +226,19 @@ int32_t rbfl_profile(rbfl_handle h, int32_t on);
  * A plan fixes the events, their proposal counts and the device buffers
  * params (FP64 [11][total], row stride total = sum of counts, event e's
  * proposals in columns [sum_{e'<e} counts[e'], ...)) and lnl (FP64 [total]).
- * Execution: a persistent FP64 contraction kernel takes (event, proposal
- * tile, column tile) items, events ordered by decreasing cost
- * proposals x (N+M) x K, from an atomic counter; then one wave per proposal
- * finishes ln L with its own event's frame and basis.  RBFL_PLAN_AUTOTUNE
- * times each tile variant on the whole batch (HIP events) and keeps the
- * fastest; RBFL_PLAN_GRAPH captures the launch in a HIP graph, replayed by
- * rbfl_plan_launch -- a sampler step writes new proposals into `params` and
- * launches again, without re-capturing.  The handles must outlive the plan;
- * plan creation allocates (work space for every event's outputs), launches
- * do not.  Launches of one plan must not overlap.
+ * Execution: one launch writes the FP64 basis rows of every event; a
+ * persistent FP64 GEMM kernel then takes (event, proposal tile, column tile)
+ * items, events ordered by decreasing cost proposals x (N+M) x K, from an
+ * atomic counter (reset by a kernel); then the epilogue finishes ln L of each
+ * proposal with its own event's frame and basis.  Variants 0-2 instead form
+ * the rows inside the persistent contraction (fused), variants 3-4 are the
+ * rows + GEMM tiles (the default).  RBFL_PLAN_AUTOTUNE times each variant on
+ * the whole batch (HIP events) and keeps the fastest; RBFL_PLAN_GRAPH captures
+ * the launch in a HIP graph, replayed by rbfl_plan_launch -- a sampler step
+ * writes new proposals into `params` and launches again, without
+ * re-capturing.  The handles must outlive the plan; plan creation allocates
+ * (work space for every event's rows and outputs), launches do not.  Launches
+ * of one plan must not overlap.
  */
 #define RBFL_PLAN_GRAPH 0x1u
 #define RBFL_PLAN_AUTOTUNE 0x2u

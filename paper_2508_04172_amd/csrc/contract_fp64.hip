@@ -62,12 +62,12 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
-// Y[q][c] = sum_r Bt[r][q] W[r][c].  One-dimensional grid over (proposal
-// tile, column tile), column tile fastest.
+// One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
+// columns tc*CW ..; called by every thread of the workgroup.
 template <int RT, int CT, int KC>
-__global__ void __launch_bounds__(kGemmThreads, 2)
-    k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
-                int Kp, double *__restrict__ Y) {
+__device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
+                                          const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
+                                          int tc) {
   constexpr int QT = 2 * RT * 16, CW = 2 * CT * 16;
   constexpr int A2 = KC * QT / 2, W2 = KC * CW / 2;                 // double2 entries per chunk
   constexpr int LA = A2 / kGemmThreads, LW = W2 / kGemmThreads;
@@ -76,10 +76,8 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
   __shared__ double Ws[2][KC][CW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wq = wave & 1, wc = wave >> 1;
-  const int n_ct = Kp / CW;
-  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int c0 = (int)(tile % n_ct) * CW;
-  const int64_t q0 = (tile / n_ct) * QT;
+  const int c0 = tc * CW;
+  const int64_t q0 = tq * QT;
 
   // per-thread source pointers of the staged entries, advanced by KC rows per chunk
   const double *pa[LA];
@@ -168,6 +166,76 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
     }
 }
 
+// One-dimensional grid over (proposal tile, column tile), column tile fastest.
+template <int RT, int CT, int KC>
+__global__ void __launch_bounds__(kGemmThreads, 2)
+    k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
+                int Kp, double *__restrict__ Y) {
+  const int n_ct = Kp / (2 * CT * 16);
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  gemm_tile<RT, CT, KC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
+}
+
+// Multi-event batches: basis rows of every event in one launch.  blockIdx.y
+// runs over the 16-row groups of all events (event e owns groups rg0 ..);
+// blockIdx.x * 256 + tid is the proposal within the event.
+__global__ void __launch_bounds__(256) k_ragged_rows_fp64(const EventDesc *__restrict__ ev, int n_ev,
+                                                          const double *__restrict__ params, int64_t ld) {
+  const int64_t gy = blockIdx.y;
+  int lo = 0, hi = n_ev - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ev[mid].rg0 <= gy) lo = mid;
+    else hi = mid - 1;
+  }
+  const EventDesc &d = ev[lo];
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= d.ldb) return;
+  const int r0 = 16 * (int)(gy - d.rg0);
+  if (q >= d.n) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d.Bt[(int64_t)(r0 + k) * d.ldb + q] = 0.0;
+    return;
+  }
+  const EvalConsts &c = *d.consts;
+  double x[4];
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd) x[dd] = params[dd * ld + d.q0 + q] / c.semi[dd];
+  const int N = c.N, NM = c.N + c.M;
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const int r = r0 + k;
+    d.Bt[(int64_t)r * d.ldb + q] = basis_row_fp64(r, N, NM, x, d.nodes + 4 * (int64_t)r, c.eps2, c.poly_idx);
+  }
+}
+
+// Persistent GEMM over the work list of every event: items are (event,
+// proposal tile, column tile), column tile fastest within an event, events in
+// the caller's cost order; each workgroup takes the next item from an atomic
+// counter until the list is exhausted (every workgroup reaches that exit).
+template <int RT, int CT, int KC>
+__global__ void __launch_bounds__(kGemmThreads, 2)
+    k_ragged_gemm_fp64(const EventDesc *__restrict__ ev, int n_ev, int64_t total_items,
+                       unsigned long long *__restrict__ counter) {
+  __shared__ long long item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t item = item_s;
+    __syncthreads();
+    if (item >= total_items) break;
+    int e = 0;
+    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
+    const EventDesc &d = ev[e];
+    const int64_t local = item - d.item0;
+    gemm_tile<RT, CT, KC>(d.Bt, d.n, d.ldb, d.rows, d.W, d.Kp, d.Y, local / d.tiles_c, (int)(local % d.tiles_c));
+  }
+}
+
+__global__ void k_zero_item_counter(unsigned long long *counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
+}
+
 template <int RT, int CT, int KC>
 void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc, const double *W, double *Y,
                  hipStream_t s) {
@@ -196,6 +264,28 @@ void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *p
   const int64_t ldb = rows_ld(nb);
   dim3 grid((unsigned)((ldb + 255) / 256), (unsigned)(hc.rows / 16));
   hipLaunchKernelGGL(k_rows_fp64, grid, dim3(256), 0, s, c, params, ld, b0, nb, ldb, nodes, Bt);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_ragged_rows_fp64(const EventDesc *ev, int n_ev, int64_t total_groups, int64_t max_ldb,
+                             const double *params, int64_t ld, hipStream_t s) {
+  dim3 grid((unsigned)((max_ldb + 255) / 256), (unsigned)total_groups);
+  hipLaunchKernelGGL(k_ragged_rows_fp64, grid, dim3(256), 0, s, ev, n_ev, params, ld);
+  RBFL_HIP(hipGetLastError());
+}
+
+// Multi-event GEMM tiles: variant 0 is 64 x 128 with 8-row chunks, variant 1
+// 64 x 128 with 16-row chunks.
+void launch_ragged_gemm_fp64(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
+                             unsigned long long *counter, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_item_counter, dim3(1), dim3(64), 0, s, counter);
+  RBFL_HIP(hipGetLastError());
+  if (variant == 1)
+    hipLaunchKernelGGL((k_ragged_gemm_fp64<2, 4, 16>), dim3(grid), dim3(kGemmThreads), 0, s, ev, n_ev, total_items,
+                       counter);
+  else
+    hipLaunchKernelGGL((k_ragged_gemm_fp64<2, 4, 8>), dim3(grid), dim3(kGemmThreads), 0, s, ev, n_ev, total_items,
+                       counter);
   RBFL_HIP(hipGetLastError());
 }
 

@@ -580,10 +580,14 @@ void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const doubl
 }
 
 
-int ragged_variants() { return 3; }
+// Multi-event variants: 0-2 the fused persistent kernel, 3-4 basis rows +
+// persistent GEMM (64 x 128 tiles, 8- and 16-row chunks).
+int ragged_variants() { return 5; }
+int ragged_fused_variants() { return 3; }
+int ragged_blocks_per_cu(int variant) { return variant < 3 ? 2 : variant == 3 ? 4 : 3; }
 
 void ragged_tile(int variant, int *qt, int *cw) {
-  static const int q[] = {128, 128, 128}, w[] = {128, 64, 64};
+  static const int q[] = {128, 128, 128, 64, 64}, w[] = {128, 64, 64, 128, 128};
   *qt = q[variant];
   *cw = w[variant];
 }

@@ -1,6 +1,6 @@
 // Surrogate network kernels: a multilayer perceptron in -> H -> H -> out with
 // SiLU activations, trained by the project's own forward, backward and Adam
-// kernels (FP32 arithmetic, FP32 master weights).
+// kernels (FP32 arithmetic on the FP32 matrix cores, FP32 master weights).
 //
 // Parameter layout: W1 [H][in], b1 [H], W2 [H][H], b2 [H], W3 [out][H],
 // b3 [out], weights row-major.  Initialisation from caller-provided standard
@@ -13,10 +13,14 @@ namespace {
 
 constexpr int kT = 256;
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 // C[m][n] = act(sum_k A(m,k) B(k,n) + bias[n]) with A(m,k) = A[m*sam + k*sak]
 // and B(k,n) = B[k*sbk + n*sbn] (strides express the transposes).  64x64
-// tile per block, 16-deep k steps through LDS, 4x4 outputs per thread.
-// With Z != nullptr the pre-activation is stored too.
+// tile per block, 16-deep k chunks through LDS; 4 waves (2 x 2), each 2 x 2
+// tiles of 16 x 16 on v_mfma_f32_16x16x4f32 (lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element i is D[4(l/16) + i][l%16], measured on
+// gfx950).  With Z != nullptr the pre-activation is stored too.
 template <int ACT>
 __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const float *__restrict__ A, int64_t sam,
                                                  int64_t sak, const float *__restrict__ B, int64_t sbk, int64_t sbn,
@@ -24,47 +28,55 @@ __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const floa
                                                  float *__restrict__ C, int64_t ldc) {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 1, wc = wave >> 1;
+  const int kk = lane >> 4, ll = lane & 15;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
+  f4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = tid; e < 16 * 64; e += kT) {
-      const int kk = e >> 6, mm = e & 63;
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
-      const int n = n0 + mm;
-      Bs[kk][mm] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
+      const int ek = e >> 6, em = e & 63;
+      const int m = m0 + em, k = k0 + ek;
+      As[ek][em] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
+      const int n = n0 + em;
+      Bs[ek][em] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + kk;
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int t = 0; t < 2; ++t) a[t] = As[k][wq * 32 + 16 * t + ll];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int u = 0; u < 2; ++u) b[u] = Bs[k][wc * 32 + 16 * u + ll];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int u = 0; u < 2; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[u], acc[t][u], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + ty + 16 * i;
-    if (m >= M) continue;
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx + 16 * j;
-      if (n >= N) continue;
-      float v = acc[i][j] + (bias ? bias[n] : 0.0f);
-      if (Z) Z[(int64_t)m * ldc + n] = v;
-      if (ACT == 1) v = v / (1.0f + __expf(-v));
-      C[(int64_t)m * ldc + n] = v;
+    for (int i = 0; i < 4; ++i) {
+      const int m = m0 + wq * 32 + 16 * t + 4 * kk + i;
+      if (m >= M) continue;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int n = n0 + wc * 32 + 16 * u + ll;
+        if (n >= N) continue;
+        float v = acc[t][u][i] + (bias ? bias[n] : 0.0f);
+        if (Z) Z[(int64_t)m * ldc + n] = v;
+        if (ACT == 1) v = v / (1.0f + __expf(-v));
+        C[(int64_t)m * ldc + n] = v;
+      }
     }
-  }
 }
 
 // dY = 2 (Y - T) / count; per-block partial sums of (Y - T)^2 (fixed order).

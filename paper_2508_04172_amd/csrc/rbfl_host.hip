@@ -1336,7 +1336,8 @@ struct Plan {
   const double *params = nullptr;
   double *lnl = nullptr;
   DevBuf<EventDesc> ev_work, ev_param;
-  DevBuf<double> Y;
+  DevBuf<double> Y, Bt;
+  int64_t total_groups = 0, max_ldb = 0;
   DevBuf<unsigned long long> counter;
   int64_t total_items = 0;
   int grid = 0;
@@ -1360,7 +1361,8 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
   ragged_tile(v, &qt, &cw);
   const int n_ev = (int)p.ctx.size();
   std::vector<EventDesc> d(n_ev);
-  int64_t q0 = 0, yoff = 0;
+  int64_t q0 = 0, yoff = 0, boff = 0, rg = 0;
+  p.max_ldb = 0;
   for (int e = 0; e < n_ev; ++e) {
     Ctx &c = *p.ctx[e];
     d[e].consts = c.consts.p;
@@ -1368,14 +1370,22 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
     d[e].W = c.W.p;
     d[e].basis = c.basis4.p;
     d[e].Y = p.Y.p + yoff;
+    d[e].Bt = p.Bt.p + boff;
     d[e].q0 = q0;
     d[e].n = p.counts[e];
+    d[e].ldb = rows_ld(p.counts[e]);
+    d[e].rg0 = rg;
     d[e].tiles_q = (int)((p.counts[e] + qt - 1) / qt);
     d[e].tiles_c = c.Kp / cw;
     d[e].Kp = c.Kp;
+    d[e].rows = c.rows;
     q0 += p.counts[e];
     yoff += p.counts[e] * c.Kp;
+    boff += (int64_t)c.rows * d[e].ldb;
+    rg += c.rows / 16;
+    p.max_ldb = std::max(p.max_ldb, d[e].ldb);
   }
+  p.total_groups = rg;
   std::vector<int> order(n_ev);
   for (int e = 0; e < n_ev; ++e) order[e] = e;
   auto cost = [&](int e) { return (double)p.counts[e] * (p.ctx[e]->N + p.ctx[e]->M) * p.ctx[e]->K; };
@@ -1391,7 +1401,7 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
   int dev = 0, cus = 0;
   RBFL_HIP(hipGetDevice(&dev));
   RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.total_items, (int64_t)cus * 2));
+  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.total_items, (int64_t)cus * ragged_blocks_per_cu(v)));
   RBFL_HIP(hipMemcpyAsync(p.ev_work.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
   RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
   RBFL_HIP(hipStreamSynchronize(s));
@@ -1400,7 +1410,13 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
 
 static void plan_run(Plan &p, hipStream_t s) {
   const int n_ev = (int)p.ctx.size();
-  launch_ragged_contract(p.variant, p.ev_work.p, n_ev, p.total_items, p.counter.p, p.params, p.total, p.grid, s);
+  if (p.variant < ragged_fused_variants()) {
+    launch_ragged_contract(p.variant, p.ev_work.p, n_ev, p.total_items, p.counter.p, p.params, p.total, p.grid, s);
+  } else {
+    launch_ragged_rows_fp64(p.ev_param.p, n_ev, p.total_groups, p.max_ldb, p.params, p.total, s);
+    launch_ragged_gemm_fp64(p.variant - ragged_fused_variants(), p.ev_work.p, n_ev, p.total_items, p.counter.p,
+                            p.grid, s);
+  }
   launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
 }
 
@@ -1446,7 +1462,7 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
   require(n_ev >= 1 && n_ev <= 4096, "n_events must be in 1 .. 4096");
   std::unique_ptr<rbfl_plan_ctx> pc(new rbfl_plan_ctx());
   Plan &p = pc->p;
-  int64_t yelems = 0;
+  int64_t yelems = 0, belems = 0;
   for (int e = 0; e < n_ev; ++e) {
     require(hs[e] != nullptr, "NULL handle in the event list");
     require(counts[e] >= 1, "every event needs at least one proposal");
@@ -1454,12 +1470,14 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
     p.counts.push_back(counts[e]);
     p.total += counts[e];
     yelems += counts[e] * hs[e]->c.Kp;
+    belems += (int64_t)hs[e]->c.rows * rows_ld(counts[e]);
   }
   p.params = params;
   p.lnl = lnl;
   p.ev_work.alloc(n_ev);
   p.ev_param.alloc(n_ev);
   p.Y.alloc((size_t)yelems);
+  p.Bt.alloc((size_t)belems);
   p.counter.alloc(1);
   if (flags & RBFL_PLAN_AUTOTUNE) {
     hipEvent_t e0, e1;
@@ -1491,7 +1509,7 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
     (void)hipEventDestroy(e1);
     plan_layout(p, best, s);
   } else {
-    plan_layout(p, 0, s);
+    plan_layout(p, ragged_fused_variants(), s);
   }
   if (flags & RBFL_PLAN_GRAPH) {
     RBFL_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));

@@ -50,9 +50,12 @@ struct EventDesc {
   const double *W;
   const double2 *basis;         // spline-folded basis [pair][T][q][4]
   double *Y;           // this event's rows of the shared work space, [n][Kp]
+  double *Bt;          // this event's basis rows (rows + GEMM variants), [rows][ldb]
   int64_t q0, n;       // first proposal (column of the concatenated params) and count
   int64_t item0;       // first work item of this event (work order)
-  int tiles_q, tiles_c, Kp, pad;
+  int64_t ldb;         // leading dimension of Bt
+  int64_t rg0;         // first 16-row group of this event in the row kernel's grid
+  int tiles_q, tiles_c, Kp, rows;
 };
 
 template <class T>
@@ -206,6 +209,12 @@ void launch_contract_bf16(const EvalConsts *c, const EvalConsts &hc, const doubl
                           int64_t nb, const double *nodes, uint16_t *AB, const uint16_t *WB, double *Y,
                           hipStream_t s, hipEvent_t mid);
 int ragged_variants();
+int ragged_fused_variants();          // variants below this use the fused persistent kernel
+int ragged_blocks_per_cu(int variant);
+void launch_ragged_rows_fp64(const EventDesc *ev, int n_ev, int64_t total_groups, int64_t max_ldb,
+                             const double *params, int64_t ld, hipStream_t s);
+void launch_ragged_gemm_fp64(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
+                             unsigned long long *counter, int grid, hipStream_t s);
 void ragged_tile(int variant, int *proposals_per_tile, int *columns_per_tile);
 void launch_ragged_contract(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
                             unsigned long long *counter, const double *params, int64_t ld, int grid, hipStream_t s);
