@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--surrogate-train", type=int, default=200000,
                     help="training proposals for the surrogate form (0 = skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--mixed-cfg3", action="store_true",
+                    help="also report every arithmetic form on the 10 Hz single-detector cubic-tail workload "
+                         "(N=1500, M=35, q=60, 4e6 proposals), errors against its oracle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 512 MiB copy kernel (known bytes, for counter scaling)")
     args = ap.parse_args()
@@ -251,6 +254,8 @@ def main():
                                 "median_dlnl": float(np.median(d)), "domain_agrees": agree,
                                 "meets_1e-3": bool(agree and d.max() <= 1e-3)})
         result["config"]["valid_fraction"] = float(fin.mean())
+    if args.mixed_cfg3:
+        result["mixed_cfg3"] = bench_mixed(args, np, torch, rbfl, wl, wl.CFG3)
     print(json.dumps(result), flush=True)
 
 
@@ -299,6 +304,70 @@ def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
            "note": "the surrogate form evaluates the FP64 interpolant unless accepted"}
     log(f"surrogate: network path {res['network_evals_per_s']:.4e} evals/s, accepted={st['accepted']}")
     return res
+
+
+def bench_mixed(args, np, torch, rbfl, wl, cfg):
+    """Every arithmetic form on one more workload: throughput of a pass over
+    the workload's proposals (near the nodes) and max |d ln L| against the
+    FP64 oracle on a seeded sample of them."""
+    n = cfg.n_queries
+    log(f"mixed {cfg.name}: GPU start-up")
+    t0 = time.time()
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    build_s = time.time() - t0
+    sz = h.sizes()
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    params = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit),
+                                                                   cfg.t_trig))).cuda()
+    lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+    sp = torch.cuda.current_stream().cuda_stream
+    h.reserve(65536)
+    flop = 2.0 * (sz["N"] + sz["M"]) * sz["K"]
+    out = {"workload": cfg.name, "proposals": n, "N": sz["N"], "M": sz["M"], "K": sz["K"], "q": sz["q"],
+           "startup_s": round(build_s, 3), "cond": h.cond(), "forms": {}}
+    res = {}
+    for name, form in (("fp64", rbfl.FORM_FP64), ("split", rbfl.FORM_SPLIT), ("fp32", rbfl.FORM_FP32),
+                       ("bf16", rbfl.FORM_BF16)):
+        if form != rbfl.FORM_FP64:
+            h.prepare(form)
+        tune = h.autotune(params.data_ptr(), n, form, sp)
+        h.eval(params.data_ptr(), n, lnl.data_ptr(), form, sp)
+        torch.cuda.synchronize()
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            h.eval(params.data_ptr(), n, lnl.data_ptr(), form, sp)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / reps
+        res[name] = lnl.cpu().numpy()
+        f = {"evals_per_s": n / wall, "ms_per_pass": wall * 1e3, "contract_tflops_equiv": flop * n / wall / 1e12}
+        if form == rbfl.FORM_SPLIT:
+            f["slices"] = tune["slices"]
+            f["max_dlnl_vs_fp64_per_slice_count"] = tune["max_dlnl_vs_fp64"][:4]
+        out["forms"][name] = f
+        log(f"mixed {cfg.name} {name}: {n / wall:.4e} evals/s")
+    if not args.no_cpu_baseline:
+        from oracle import likelihood as lk
+        from oracle import startup as su
+        log(f"mixed {cfg.name}: oracle start-up on the host (not timed)")
+        art = su.startup(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+        m = min(20000, n)
+        sample = np.sort(np.random.default_rng(321).choice(n, m, replace=False))
+        lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(sample).near_nodes(art.x_nodes, idx[sample],
+                                                                                     jit[sample])))
+        fin = np.isfinite(lo)
+        out["check_sample"] = m
+        out["valid_fraction"] = float(fin.mean())
+        for name, l in res.items():
+            lg = l[sample]
+            agree = bool(np.array_equal(fin, np.isfinite(lg)))
+            d = np.abs(lg[fin] - lo[fin]) if fin.any() else np.array([np.inf])
+            out["forms"][name].update({"max_dlnl": float(d.max()), "p99_dlnl": float(np.quantile(d, 0.99)),
+                                       "median_dlnl": float(np.median(d)), "domain_agrees": agree,
+                                       "meets_1e-3": bool(agree and d.max() <= 1e-3)})
+            log(f"mixed {cfg.name} {name}: max |dlnL| {d.max():.3e}")
+    return out
 
 
 def bench_ragged(args, np, torch, rbfl, wl):
