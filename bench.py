@@ -127,7 +127,10 @@ def main():
     lnl = torch.empty(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
-    h.reserve(65536)
+    # one chunk per step: the work space for 1e6 proposals (Y 10 GB, basis rows
+    # 6.7 GB for this workload) fits easily in 288 GB of HBM, and one launch
+    # per stage avoids the gaps and tails of sixteen smaller ones
+    h.reserve(min(n, 1 << 20))
     tune = {}
     for name, form in (("fp64", rbfl.FORM_FP64), ("fp32", rbfl.FORM_FP32), ("bf16", rbfl.FORM_BF16),
                        ("split", rbfl.FORM_SPLIT)):
