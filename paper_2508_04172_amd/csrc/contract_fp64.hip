@@ -64,18 +64,18 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
 
 // One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
 // columns tc*CW ..; called by every thread of the workgroup.
-template <int RT, int CT, int KC>
+template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
 __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
                                           const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
                                           int tc) {
-  constexpr int QT = 2 * RT * 16, CW = 2 * CT * 16;
+  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16, NT = 64 * WQ * WC;
   constexpr int A2 = KC * QT / 2, W2 = KC * CW / 2;                 // double2 entries per chunk
-  constexpr int LA = A2 / kGemmThreads, LW = W2 / kGemmThreads;
-  static_assert(KC % 4 == 0 && A2 % kGemmThreads == 0 && W2 % kGemmThreads == 0, "whole k-steps, even staging");
+  constexpr int LA = A2 / NT, LW = W2 / NT;
+  static_assert(KC % 4 == 0 && A2 % NT == 0 && W2 % NT == 0, "whole k-steps, even staging");
   __shared__ double As[2][KC][QT];
   __shared__ double Ws[2][KC][CW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wq = wave & 1, wc = wave >> 1;
+  const int wq = wave % WQ, wc = wave / WQ;
   const int c0 = tc * CW;
   const int64_t q0 = tq * QT;
 
@@ -85,14 +85,14 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
   bool va[LA];
 #pragma unroll
   for (int u = 0; u < LA; ++u) {
-    const int e = tid + u * kGemmThreads;
+    const int e = tid + u * NT;
     const int k = e / (QT / 2), q2 = e % (QT / 2);
     pa[u] = Bt + (int64_t)k * ldb + q0 + 2 * q2;
     va[u] = q0 + 2 * q2 < ldb;
   }
 #pragma unroll
   for (int u = 0; u < LW; ++u) {
-    const int e = tid + u * kGemmThreads;
+    const int e = tid + u * NT;
     pw[u] = W + (int64_t)(e / (CW / 2)) * Kp + c0 + 2 * (e % (CW / 2));
   }
   const int64_t stepA = (int64_t)KC * ldb, stepW = (int64_t)KC * Kp;
@@ -115,12 +115,12 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
     asm volatile("" ::: "memory");
 #pragma unroll
     for (int u = 0; u < LA; ++u) {
-      const int e = tid + u * kGemmThreads;
+      const int e = tid + u * NT;
       *reinterpret_cast<d2 *>(&As[buf][e / (QT / 2)][2 * (e % (QT / 2))]) = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < LW; ++u) {
-      const int e = tid + u * kGemmThreads;
+      const int e = tid + u * NT;
       *reinterpret_cast<d2 *>(&Ws[buf][e / (CW / 2)][2 * (e % (CW / 2))]) = rw[u];
     }
   };
@@ -144,9 +144,9 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
       const int k = 4 * s + kk;
       double a[RT], b[CT];
 #pragma unroll
-      for (int t = 0; t < RT; ++t) a[t] = As[cur][k][wq * (QT / 2) + 16 * t + ll];
+      for (int t = 0; t < RT; ++t) a[t] = As[cur][k][wq * RT * 16 + 16 * t + ll];
 #pragma unroll
-      for (int u = 0; u < CT; ++u) b[u] = Ws[cur][k][wc * (CW / 2) + 16 * u + ll];
+      for (int u = 0; u < CT; ++u) b[u] = Ws[cur][k][wc * CT * 16 + 16 * u + ll];
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -159,21 +159,22 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t q = q0 + wq * (QT / 2) + 16 * t + kk + 4 * i;
+      const int64_t q = q0 + wq * RT * 16 + 16 * t + kk + 4 * i;
       if (q >= nb) continue;
 #pragma unroll
-      for (int u = 0; u < CT; ++u) Y[q * Kp + c0 + wc * (CW / 2) + 16 * u + ll] = acc[t][u][i];
+      for (int u = 0; u < CT; ++u) Y[q * Kp + c0 + wc * CT * 16 + 16 * u + ll] = acc[t][u][i];
     }
 }
 
-// One-dimensional grid over (proposal tile, column tile), column tile fastest.
-template <int RT, int CT, int KC>
-__global__ void __launch_bounds__(kGemmThreads, 2)
+// One-dimensional grid over (proposal tile, column tile), column tile fastest;
+// WQ x WC waves per workgroup.
+template <int RT, int CT, int KC, int WQ, int WC>
+__global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
     k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
                 int Kp, double *__restrict__ Y) {
-  const int n_ct = Kp / (2 * CT * 16);
+  const int n_ct = Kp / (WC * CT * 16);
   const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
-  gemm_tile<RT, CT, KC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
+  gemm_tile<RT, CT, KC, WQ, WC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
 }
 
 // Multi-event batches: basis rows of every event in one launch.  blockIdx.y
@@ -236,14 +237,14 @@ __global__ void k_zero_item_counter(unsigned long long *counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
-template <int RT, int CT, int KC>
+template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
 void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc, const double *W, double *Y,
                  hipStream_t s) {
-  constexpr int QT = 2 * RT * 16, CW = 2 * CT * 16;
+  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16;
   static_assert(kColTile % CW == 0 && kRowChunk % KC == 0, "K and the rows are padded to whole tiles");
   const int64_t nblk = (nb + QT - 1) / QT * (hc.Kp / CW);
-  hipLaunchKernelGGL((k_gemm_fp64<RT, CT, KC>), dim3((unsigned)nblk), dim3(kGemmThreads), 0, s, Bt, nb, ldb, hc.rows,
-                     W, hc.Kp, Y);
+  hipLaunchKernelGGL((k_gemm_fp64<RT, CT, KC, WQ, WC>), dim3((unsigned)nblk), dim3(64 * WQ * WC), 0, s, Bt, nb, ldb,
+                     hc.rows, W, hc.Kp, Y);
   RBFL_HIP(hipGetLastError());
 }
 
@@ -251,12 +252,20 @@ void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc
 
 int64_t rows_ld(int64_t n) { return (n + 7) & ~int64_t(7); }
 
-int gemm_fp64_variants() { return 5; }
+int gemm_fp64_variants() { return 7; }
 
 const char *gemm_fp64_variant_name(int v) {
   static const char *names[] = {"rows + gemm 64x128 kc8",  "rows + gemm 128x64 kc8", "rows + gemm 64x128 kc16",
-                                "rows + gemm 128x64 kc16", "rows + gemm 64x64 kc8"};
+                                "rows + gemm 128x64 kc16", "rows + gemm 64x64 kc8",
+                                "rows + gemm 256x128 kc8 (8 waves)", "rows + gemm 128x128 kc8 (8 waves)"};
   return names[v];
+}
+
+// Operand reuse of a variant's workgroup tile, QT CW / (QT + CW): the
+// algorithmic bytes over the bytes the workgroups read, up to a constant.
+double gemm_fp64_reuse(int v) {
+  static const double qt[] = {64, 128, 64, 128, 64, 256, 128}, cw[] = {128, 64, 128, 64, 64, 128, 128};
+  return qt[v] * cw[v] / (qt[v] + cw[v]);
 }
 
 void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
@@ -298,6 +307,8 @@ void launch_gemm_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const 
     case 2: launch_gemm<2, 4, 16>(Bt, nb, ldb, hc, W, Y, s); break;
     case 3: launch_gemm<4, 2, 16>(Bt, nb, ldb, hc, W, Y, s); break;
     case 4: launch_gemm<2, 2, 8>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 5: launch_gemm<4, 4, 8, 4, 2>(Bt, nb, ldb, hc, W, Y, s); break;
+    case 6: launch_gemm<2, 4, 8, 4, 2>(Bt, nb, ldb, hc, W, Y, s); break;
     default: throw Error(RBFL_E_INVALID_ARG, "unknown FP64 GEMM variant");
   }
 }

@@ -1103,6 +1103,13 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
       best = v;
     }
   }
+  // FP64 GEMM tiles within 2% of the fastest time: keep the one whose larger
+  // workgroup tile re-reads the least (the difference is within run-to-run
+  // noise; the bandwidth saved is not)
+  if (form == RBFL_FORM_FP64 && best >= 0 && best < gemm_fp64_variants()) {
+    for (int v = 0; v < gemm_fp64_variants() && v < nv && v < 8; ++v)
+      if (med[v] <= 1.02 * best_ms && gemm_fp64_reuse(v) > gemm_fp64_reuse(best)) best = v;
+  }
   c.variant[form] = best >= 0 ? best : kSplitDefaultVariant;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -194,6 +194,7 @@ const char *contract_variant_name(int form, int variant);
 int64_t rows_ld(int64_t n);
 int gemm_fp64_variants();
 const char *gemm_fp64_variant_name(int variant);
+double gemm_fp64_reuse(int variant);
 void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                       int64_t nb, const double *nodes, double *Bt, hipStream_t s);
 void launch_gemm_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const double *W, double *Y, hipStream_t s,
