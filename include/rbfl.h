@@ -140,6 +140,17 @@ const char *rbfl_last_error(void);
  * Synchronous on `stream`.  *out receives a new handle. */
 int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out);
 
+/* Exact ln L for n proposals, without the interpolant: the reference the
+ * meshfree method approximates (Eq. logl_basic for the projected signal of
+ * Eq. projected_h_fd, evaluated as Eq. logl_complete with z and the mode
+ * overlaps as direct sums over the band at each proposal's own templates).
+ * params, lnl: as rbfl_eval (device, SoA [11][n], FP64 [n]).  Defined on the
+ * whole physical region (no ellipsoid or window restriction): -inf for an
+ * unphysical intrinsic point, NaN for a NaN input.  Enqueued on `stream`,
+ * allocates nothing; cost ~ n x bins x modes x detectors (one workgroup per
+ * proposal). */
+int32_t rbfl_brute(rbfl_handle h, const double *params, int64_t n, double *lnl, void *stream);
+
 /* Online stage (Sec. II D) for n proposals.
  * params: device, FP64, structure of arrays [11][n] (row stride n):
  *   delta_e0..3 (displacement from the centre along the metric eigenvectors,

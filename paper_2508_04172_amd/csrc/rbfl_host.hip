@@ -644,6 +644,24 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
       Dk[(size_t)k * J + jj] = make_double2(sc * (d.x * cs - d.y * sn), sc * (d.x * sn + d.y * cs));
       wk[(size_t)k * J + jj] = sc;
     }
+  {
+    // whole band for the exact ln L at arbitrary proposals
+    c.brute_j_lo = j_lo;
+    c.brute_J = j_hi - j_lo;
+    std::vector<double2> bd((size_t)c.n_det * c.brute_J);
+    std::vector<double> bw((size_t)c.n_det * c.brute_J);
+    for (int k = 0; k < c.n_det; ++k)
+      for (int64_t j = j_lo; j < j_hi; ++j) {
+        const double sc = 4.0 * c.df / psd[k][j];
+        bd[(size_t)k * c.brute_J + (j - j_lo)] = make_double2(sc * data[k][j].x, sc * data[k][j].y);
+        bw[(size_t)k * c.brute_J + (j - j_lo)] = sc;
+      }
+    c.brute_D.alloc(bd.size());
+    c.brute_w.alloc(bw.size());
+    RBFL_HIP(hipMemcpyAsync(c.brute_D.p, bd.data(), sizeof(double2) * bd.size(), hipMemcpyHostToDevice, stream));
+    RBFL_HIP(hipMemcpyAsync(c.brute_w.p, bw.data(), sizeof(double) * bw.size(), hipMemcpyHostToDevice, stream));
+    RBFL_HIP(hipStreamSynchronize(stream));
+  }
   DevBuf<Binary> d_bins;
   d_bins.alloc(c.N);
   RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * c.N, hipMemcpyHostToDevice, stream));
@@ -894,6 +912,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   }
   for (int a = 0; a < c.n_modes; ++a) {
     e.mode_l[a] = c.modes[a][0];
+    e.mode_m[a] = c.modes[a][1];
     e.ylm_neg[a] = yneg[a];
     e.ylm_pos[a] = ypos[a];
   }
@@ -1547,6 +1566,17 @@ int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out) 
     std::unique_ptr<rbfl_ctx> h(new rbfl_ctx());
     rbfl::build(spec, reinterpret_cast<hipStream_t>(stream), h->c);
     *out = h.release();
+  });
+}
+
+int32_t rbfl_brute(rbfl_handle h, const double *params, int64_t n, double *lnl, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
+    rbfl::require(n >= 0 && n <= 2147483647, "n must be in 0 .. 2^31 - 1");
+    rbfl::Ctx &c = h->c;
+    rbfl::launch_brute(c.consts.p, params, n, n, c.brute_D.p, c.brute_w.p, c.brute_j_lo, c.brute_J, c.n_s, c.df,
+                       1.0 / (c.d_ref * rbfl::kMpcS), lnl, reinterpret_cast<hipStream_t>(stream));
   });
 }
 

@@ -37,7 +37,7 @@ struct EvalConsts {
   double theta_c[4], V[16], semi[4];        // V row-major: Theta_i = theta_c_i + sum_j V[i][j] de_j
   double D[RBFL_MAX_DET][9], r[RBFL_MAX_DET][3];
   int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
-  int mode_l[RBFL_MAX_MODES];
+  int mode_l[RBFL_MAX_MODES], mode_m[RBFL_MAX_MODES];
   YlmTerms ylm_neg[RBFL_MAX_MODES];         // -2Y_{l,-m}
   YlmTerms ylm_pos[RBFL_MAX_MODES];         // -2Y_{l,m}
   double spline[kSplineTaps][4];            // w_s(f) = sum_p spline[s][p] f^p
@@ -123,6 +123,9 @@ struct Ctx {
   DevBuf<double2> basis;       // [n_det][n_modes][T][q]
   DevBuf<double2> basis4;      // spline-folded basis [n_det][n_modes][T][q][4]
   DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
+  DevBuf<double2> brute_D;     // exact ln L: 4 df d_k / S_k over bins j_lo .. n_s/2 - 1, [n_det][brute_J]
+  DevBuf<double> brute_w;      // exact ln L: 4 df / S_k, [n_det][brute_J]
+  int64_t brute_j_lo = 0, brute_J = 0;
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
   DevBuf<uint16_t> W16;        // BF16 form: weights in 8-row groups [rows/8][Kp][8]
@@ -174,6 +177,9 @@ void launch_sigma(const double2 *A, int nb, int n_modes, int J, const double *wk
 void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
                        int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s);
 void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, double2 *Z_rows, hipStream_t s);
+void launch_brute(const EvalConsts *c, const double *params, int64_t ld, int64_t n, const double2 *Dd,
+                  const double *wk, int64_t j_lo, int64_t J, int64_t n_s, double df, double inv_dref_s, double *lnl,
+                  hipStream_t s);
 void launch_fold_spline(const double2 *B, int n_pairs, int T, int q, const EvalConsts *c, double2 *B4,
                         hipStream_t s);
 void launch_basis_from_u(const double2 *U, int T, int ldu, int q, double2 *B, hipStream_t s);

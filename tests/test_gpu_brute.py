@@ -1,0 +1,134 @@
+"""Exact ln L on the GPU (rbfl_brute) against the oracle's brute force.
+
+Both sides form each proposal's templates on the frequency grid and sum the
+band directly (Eq. logl_basic for the projected signal of Eq.
+projected_h_fd); they differ only in summation order, so they agree to
+rounding (1e-9 of max(1, |ln L|)).  Also: the zero-noise injection gives
+rho^2 / 2 exactly, NaN and unphysical inputs, and the meshfree method's error
+against the exact value near the nodes (reported; bounded loosely).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import likelihood as lk
+from oracle import physics as ph
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+from test_gpu_parity import both, gpu_eval
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def gpu_brute(h, params):
+    torch = _torch()
+    p = torch.from_numpy(np.ascontiguousarray(params)).cuda()
+    n = params.shape[1]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.brute(p.data_ptr(), n, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_brute(art, h, params, cfg):
+    """The oracle's brute force at the physical points the library's own frame
+    gives these parameters (so both sides evaluate the same binary; the two
+    frames agree only to ~1e-9), -inf if unphysical."""
+    fr = h.frame()
+    theta = fr["theta_c"][None, :] + params[0:4].T @ fr["vecs"].T
+    m1, m2, c1, c2, eta = ph.theta_to_phys(theta.T, cfg.f_low)
+    with np.errstate(invalid="ignore"):
+        ok = (eta <= 0.25) & (np.abs(c1) <= cfg.chi_max) & (np.abs(c2) <= cfg.chi_max) & np.isfinite(c1 + c2)
+    out = np.full(params.shape[1], -np.inf)
+    for i in np.flatnonzero(ok):
+        out[i] = lk.brute_lnl(art.ev, (m1[i], m2[i], c1[i], c2[i]), params[4:9, i], params[9, i], params[10, i])
+    return out
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_multi"])
+def test_brute_matches_oracle(name):
+    cfg, art, h = both(name)
+    n = 24
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=29)
+    qd = wl.queries(cfg, n=n, seed=31)
+    params = rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig)
+    lg = gpu_brute(h, params)
+    lo = oracle_brute(art, h, params, cfg)
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg))
+    assert fin.sum() >= n // 2
+    d = np.abs(lg[fin] - lo[fin])
+    print(f"[brute] {name}: {fin.sum()} physical, max |d lnL| vs oracle brute force {d.max():.3e}", flush=True)
+    assert np.all(d <= 1e-9 * np.maximum(1.0, np.abs(lo[fin])))
+
+
+def test_brute_zero_noise_injection():
+    """Zero noise, the injection's own parameters: ln L = rho^2 / 2."""
+    cfg = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=60, center_node=True)
+    inj = wl.injection_extrinsics(cfg)
+    h = rbfl.Handle.from_config(cfg, None, inj)
+    qd = wl.queries(cfg, n=1)
+    qd.x[:] = 0.0
+    qd.dt[:] = 0.0
+    qd.ext[0, 4] = inj[4]
+    qd.dist_ratio[:] = 1.0
+    lg = gpu_brute(h, rbfl.params_soa(h, qd, cfg.t_trig))
+    assert lg[0] == pytest.approx(cfg.inj_snr ** 2 / 2, rel=1e-10)
+
+
+def test_brute_nan_and_unphysical():
+    cfg, art, h = both("small_multi")
+    qd = wl.queries(cfg, n=3)
+    p = rbfl.params_soa(h, qd, cfg.t_trig)
+    p[6, 0] = np.nan                   # psi
+    p[0:4, 1] = 1e6 * h.frame()["semi"]  # far outside any physical region
+    lg = gpu_brute(h, p)
+    assert math.isnan(lg[0]) and lg[1] == -np.inf
+
+
+def test_meshfree_equals_exact_at_nodes():
+    """Where the method makes no approximation -- proposals exactly at the
+    nodes, t_c on the sample grid, q = N (the basis holds every node's time
+    series) -- the meshfree ln L equals the exact one up to the solve's
+    rounding."""
+    cfg = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=60)
+    inj = wl.injection_extrinsics(cfg)
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), inj)
+    n = 60
+    qd = wl.queries(cfg, n=n, seed=43)
+    qd.x[:] = h.nodes()
+    qd.dt[:] = np.round(qd.dt * cfg.fs) / cfg.fs
+    params = rbfl.params_soa(h, qd, cfg.t_trig)
+    lm = gpu_eval(h, qd, cfg.t_trig)
+    lb = gpu_brute(h, params)
+    fin = np.isfinite(lm)
+    assert fin.sum() >= n // 2
+    d = np.abs(lm[fin] - lb[fin])
+    print(f"[brute] at the nodes: {fin.sum()} points, max |meshfree - exact| {d.max():.3e}", flush=True)
+    assert np.all(d <= 1e-6 * np.maximum(1.0, np.abs(lb[fin])))
+
+
+def test_meshfree_method_error_near_nodes():
+    """The method's own error (interpolation, basis truncation, spline) against
+    the exact ln L near the nodes of a small configuration: reported."""
+    cfg, art, h = both("small_multi")
+    n = 2000
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=37)
+    qd = wl.queries(cfg, n=n, seed=41).near_nodes(h.nodes(), idx, jit)
+    p = rbfl.params_soa(h, qd, cfg.t_trig)
+    lm = gpu_eval(h, qd, cfg.t_trig)
+    lb = gpu_brute(h, p)
+    fin = np.isfinite(lm)
+    assert fin.sum() > n // 4 and np.all(np.isfinite(lb[fin]))
+    d = np.abs(lm[fin] - lb[fin])
+    q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    print(f"[brute] small_multi (N=150, q=12) method error: median {q[0]:.3e}, 90% {q[1]:.3e}, "
+          f"99% {q[2]:.3e}, max {q[3]:.3e} (|lnL| median {np.median(np.abs(lb[fin])):.1f})", flush=True)
