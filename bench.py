@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--mixed-cfg3", action="store_true",
                     help="also report every arithmetic form on the 10 Hz single-detector cubic-tail workload "
                          "(N=1500, M=35, q=60, 4e6 proposals), errors against its oracle")
+    ap.add_argument("--method-error", action="store_true",
+                    help="also report the method's error against the exact ln L (rbfl_brute) at matches "
+                         "0.90/0.95/0.97/0.99 on the single-detector workload (1e4 proposals each) and on "
+                         "the 3-detector workload, with the exact path's throughput")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 512 MiB copy kernel (known bytes, for counter scaling)")
     args = ap.parse_args()
@@ -257,6 +261,8 @@ def main():
                                 "median_dlnl": float(np.median(d)), "domain_agrees": agree,
                                 "meets_1e-3": bool(agree and d.max() <= 1e-3)})
         result["config"]["valid_fraction"] = float(fin.mean())
+    if args.method_error:
+        result["method_error"] = bench_method_error(np, torch, rbfl, wl, h, cfg, qd, idx, jit)
     if args.mixed_cfg3:
         result["mixed_cfg3"] = bench_mixed(args, np, torch, rbfl, wl, wl.CFG3)
     print(json.dumps(result), flush=True)
@@ -307,6 +313,63 @@ def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
            "note": "the surrogate form evaluates the FP64 interpolant unless accepted"}
     log(f"surrogate: network path {res['network_evals_per_s']:.4e} evals/s, accepted={st['accepted']}")
     return res
+
+
+def bench_method_error(np, torch, rbfl, wl, h2, cfg2, qd2, idx2, jit2):
+    """The meshfree approximation against the exact ln L on the same GPU: the
+    single-detector (2,2) workload at four ellipsoid matches with 1e4 proposals
+    uniform in the ball (the paper's Fig. 3 protocol), and the 3-detector
+    workload on 2e3 of the bench's proposals.  The error is split with
+    rbfl_exact_parts into the RBF interpolation (meshfree vs exact outputs on
+    the time basis), the basis truncation (basis vs raw window samples) and
+    the sub-sample spline (samples vs exact); with the exact path's
+    throughput (one workgroup per proposal, direct band sums)."""
+    sp = torch.cuda.current_stream().cuda_stream
+    out = {"protocol": "|dlnL| quantiles over proposals where the meshfree ln L is finite; "
+                       "parts: rbf = |meshfree - exact outputs on the basis|, truncation = |basis - raw samples|, "
+                       "spline = |raw samples - exact|"}
+
+    def q4(v):
+        return {k: float(x) for k, x in zip(("median", "p90", "p99", "max"), np.quantile(v, [0.5, 0.9, 0.99, 1.0]))}
+
+    def compare(h, params, n):
+        p = torch.from_numpy(np.ascontiguousarray(params)).cuda()
+        lm = torch.empty(n, dtype=torch.float64, device="cuda")
+        lb = torch.empty(n, dtype=torch.float64, device="cuda")
+        parts = torch.empty((2, n), dtype=torch.float64, device="cuda")
+        h.eval(p.data_ptr(), n, lm.data_ptr(), rbfl.FORM_FP64, sp)
+        h.brute(p.data_ptr(), n, lb.data_ptr(), sp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        h.brute(p.data_ptr(), n, lb.data_ptr(), sp)
+        torch.cuda.synchronize()
+        brute_s = time.perf_counter() - t
+        h.exact_parts(p.data_ptr(), n, parts.data_ptr(), sp)
+        torch.cuda.synchronize()
+        a, b, pr = lm.cpu().numpy(), lb.cpu().numpy(), parts.cpu().numpy()
+        fin = np.isfinite(a)
+        if not fin.any():
+            return {"valid": 0}
+        return {"valid": int(fin.sum()), "total": q4(np.abs(a[fin] - b[fin])),
+                "rbf": q4(np.abs(a[fin] - pr[0][fin])), "truncation": q4(np.abs(pr[0][fin] - pr[1][fin])),
+                "spline": q4(np.abs(pr[1][fin] - b[fin])),
+                "median_abs_lnl": float(np.median(np.abs(b[fin]))), "max_lnl": float(np.max(b[fin])),
+                "exact_evals_per_s": n / brute_s}
+
+    cases = {}
+    for match in (0.90, 0.95, 0.97, 0.99):
+        cfg = wl.CFG1.with_(name=f"cfg1_match{match:.2f}", match=match)
+        h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+        n = 10000
+        qd = wl.queries(cfg, n=n)
+        cases[cfg.name] = compare(h, rbfl.params_soa(h, qd, cfg.t_trig), n)
+        log(f"method error {cfg.name}: {cases[cfg.name]}")
+    n = 2000
+    p2 = rbfl.params_soa(h2, qd2.near_nodes(h2.nodes(), idx2, jit2), cfg2.t_trig)[:, :n]
+    cases[cfg2.name] = compare(h2, p2, n)
+    log(f"method error {cfg2.name}: {cases[cfg2.name]}")
+    out["cases"] = cases
+    return out
 
 
 def bench_mixed(args, np, torch, rbfl, wl, cfg):

@@ -151,6 +151,25 @@ int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out);
  * proposal). */
 int32_t rbfl_brute(rbfl_handle h, const double *params, int64_t n, double *lnl, void *stream);
 
+/* Where the meshfree ln L loses accuracy (Sec. II D, the three approximations
+ * of the online stage): the quantities the interpolants approximate are
+ * computed exactly at each proposal with the start-up kernels (its own
+ * templates, the mode overlaps, the windowed DFT giving z at the T window
+ * samples, and that series' coefficients on the handle's time basis), then
+ *   out[0 .. n)   ln L through the online stage's own epilogue from those
+ *                 exact coefficients and overlaps: equal to rbfl_eval but for
+ *                 the RBF interpolation;
+ *   out[n .. 2n)  ln L from the exact window samples with the same spline
+ *                 stencil, no time basis: equal to out[0..n) but for the
+ *                 truncation to q basis vectors, and to rbfl_brute but for
+ *                 the sub-sample spline.
+ * params: as rbfl_eval (device, SoA [11][n]); out: device FP64 [2][n].  Same
+ * domain, window and NaN rules as rbfl_eval.  Synchronous on `stream`;
+ * allocates work space for up to 4096 proposals at a time (templates of a
+ * batch kept within ~2 GiB) and frees it before returning.  Cost
+ * ~ n x bins x modes x detectors x T: a diagnostic, not a hot path. */
+int32_t rbfl_exact_parts(rbfl_handle h, const double *params, int64_t n, double *out, void *stream);
+
 /* Online stage (Sec. II D) for n proposals.
  * params: device, FP64, structure of arrays [11][n] (row stride n):
  *   delta_e0..3 (displacement from the centre along the metric eigenvectors,

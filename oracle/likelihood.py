@@ -213,6 +213,78 @@ def meshfree_lnl(art: Artefacts, delta_e, ext, t_c, d_l) -> np.ndarray:
     return meshfree_parts(art, delta_e, ext, t_c, d_l)[0]
 
 
+def exact_parts(art: Artefacts, delta_e, ext, t_c, d_l):
+    """The online stage's approximations taken one at a time (Sec. II D).
+    At each proposal the quantities the interpolants stand for are computed
+    exactly, with the start-up's own definitions applied to the proposal's
+    template: z at the window samples and the mode overlaps.  Returns two
+    ln L arrays (-inf / NaN as meshfree_lnl):
+      projected: the window series projected on the time basis (exact SVD
+                 coefficients) and the exact overlaps, through the online
+                 stage -- everything but the RBF interpolation;
+      samples:   the spline through the exact window samples, no basis --
+                 everything but the basis truncation and the RBF."""
+    from .startup import node_series_and_overlaps, physical_mask
+    ev = art.ev
+    n_q = delta_e.shape[0]
+    x = delta_e / art.frame.semi[None, :]
+    valid = domain(art, x)
+    nan_in = np.any(np.isnan(np.concatenate([delta_e, ext, t_c[:, None], d_l[:, None]], axis=1)), axis=1)
+    idx = np.flatnonzero(valid & ~nan_in)
+    n_modes = len(ev.modes)
+    K, coef_off, sig_off = output_layout(ev.n_det, n_modes, art.q)
+    T = art.basis.shape[2]
+    Z = np.zeros((ev.n_det, n_modes, n_q, T), dtype=np.complex128)
+    S = np.zeros((ev.n_det, n_q, n_modes, n_modes), dtype=np.complex128)
+    if idx.size:
+        _, phys = physical_mask(art.frame, x[idx], ev.grid.f_low, art.cfg.chi_max)
+        z, sig = node_series_and_overlaps(ev, phys, art.cfg.half_window)
+        Z[:, :, idx] = z
+        S[:, idx] = sig
+    # outputs in the interpolants' layout, from the exact series and overlaps
+    Y = np.zeros((n_q, K))
+    for k in range(ev.n_det):
+        for a in range(n_modes):
+            Cc = Z[k, a] @ np.conj(art.basis[k, a])            # C_i = sum_t z(t) conj(B[t, i])
+            o = coef_off[k][a]
+            Y[:, o:o + 2 * art.q:2] = Cc.real
+            Y[:, o + 1:o + 2 * art.q:2] = Cc.imag
+        o = sig_off[k]
+        for a in range(n_modes):
+            Y[:, o + a] = S[k, :, a, a].real
+        p = o + n_modes
+        for a in range(n_modes):
+            for b in range(a + 1, n_modes):
+                Y[:, p] = S[k, :, a, b].real
+                Y[:, p + 1] = S[k, :, a, b].imag
+                p += 2
+    projected = meshfree_parts(art, delta_e, ext, t_c, d_l, Y=Y)[0]
+    # spline through the exact samples
+    tab = spline_table()
+    r = art.d_ref / d_l
+    alpha, dec, psi, iota, phi = (ext[:, i] for i in range(5))
+    samples = np.zeros(n_q)
+    ok_all = valid.copy()
+    for k in range(ev.n_det):
+        fp, fc = antenna_patterns(ev.det_tensor[k], alpha, dec, psi)
+        s = (t_c + time_delays(ev.det_pos[k], alpha, dec) - ev.t_trig) * ev.grid.fs + art.half_w
+        with np.errstate(invalid="ignore"):
+            n0 = np.floor(s)
+        f = s - n0
+        ok = np.isfinite(n0) & (n0 >= 4) & (n0 <= T - 6)
+        ok_all &= ok
+        n0c = np.where(ok, n0, 4).astype(np.int64)
+        w = spline_weights(np.where(ok, f, 0.0), tab)
+        rows = n0c[:, None] + np.arange(-4, 6)[None, :]
+        z = np.stack([np.sum(w * np.take_along_axis(Z[k, a], rows, axis=1), axis=1) for a in range(n_modes)], axis=-1)
+        A = mode_factors(ev.modes, fp, fc, iota, phi)
+        samples += combine(A, z, S[k], r)
+    samples = np.where(ok_all, samples, -np.inf)
+    samples = np.where(nan_in, np.nan, samples)
+    projected = np.where(nan_in, np.nan, projected)
+    return projected, samples
+
+
 def query_params(art: Artefacts, qd) -> tuple:
     """Turn a normalised query draw into the paper's coordinates with this
     side's own frame and reference distance."""

@@ -419,4 +419,95 @@ void launch_transpose_weights(const double *R, int NM, int K, int rows, int Kp, 
   RBFL_HIP(hipGetLastError());
 }
 
+// ---- exact outputs at arbitrary proposals -----------------------------------
+// The start-up kernels above applied to proposals instead of nodes give the
+// quantities the interpolants approximate, at the proposal itself: the window
+// samples of z, their coefficients on the time basis and the overlaps.
+
+namespace {
+
+// Physical point of each proposal of a batch; an unphysical or NaN proposal
+// gets f_isco = 0, so its templates vanish (its ln L is decided by the
+// online stage's own domain test).
+__global__ void __launch_bounds__(kBlock) k_proposal_bins(const EvalConsts *__restrict__ cp,
+                                                          const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                          int nb, Binary *__restrict__ bins) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nb) return;
+  const EvalConsts &c = *cp;
+  double th[4], phys[4];
+  bool ok = true;
+  for (int r = 0; r < 4; ++r) {
+    double t = c.theta_c[r];
+    for (int j = 0; j < 4; ++j) t += c.V[4 * r + j] * params[j * ld + b0 + i];
+    th[r] = t;
+    ok = ok && !isnan(t);
+  }
+  ok = ok && theta_to_phys(th, c.f0, c.chi_max, phys);
+  Binary b = make_binary(ok ? phys[0] : 2.0, ok ? phys[1] : 1.0, ok ? phys[2] : 0.0, ok ? phys[3] : 0.0);
+  if (!ok) b.f_isco = 0.0;
+  bins[i] = b;
+}
+
+// Band data with the phase of the window's first sample n0 folded in:
+// out[k][jj] = D[k][jj] e^{2 pi i j n0 / n_s}, j = j_lo + jj (the product
+// j n0 is reduced exactly in integers).
+__global__ void k_rotate_band(const double2 *__restrict__ D, int64_t total, int64_t J, int64_t j_lo, int64_t n0,
+                              int64_t n_s, double2 *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const int64_t j = j_lo + e % J;
+  const int64_t ph = ((j % n_s) * n0) % n_s;
+  double sn, cs;
+  sincospi(2.0 * ((double)ph / (double)n_s), &sn, &cs);
+  const double2 d = D[e];
+  out[e] = make_double2(d.x * cs - d.y * sn, d.x * sn + d.y * cs);
+}
+
+// Output rows Y[n][Kp] of a batch in the interpolants' column layout
+// (coldesc as for the right-hand side) from coefficients
+// C[n_det][n_modes][nb][q] and overlaps sig[n_det][nb][n_modes][n_modes];
+// padding columns are zero.
+__global__ void k_outputs_rows(const double2 *__restrict__ C, const double2 *__restrict__ sig,
+                               const int4 *__restrict__ coldesc, int nb, int K, int Kp, int q, int n_modes,
+                               double *__restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (int64_t)nb * Kp) return;
+  const int n = (int)(e / Kp), col = (int)(e % Kp);
+  double v = 0.0;
+  if (col < K) {
+    const int4 d = coldesc[col];
+    if (d.x <= 1) {
+      const double2 cv = C[(((int64_t)d.y * n_modes + d.z) * nb + n) * q + d.w];
+      v = d.x == 0 ? cv.x : cv.y;
+    } else {
+      const double2 sv = sig[(((int64_t)d.y * nb + n) * n_modes + d.z) * n_modes + d.w];
+      v = d.x == 2 ? sv.x : sv.y;
+    }
+  }
+  Y[e] = v;
+}
+
+}  // namespace
+
+void launch_proposal_bins(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int nb, Binary *bins,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_proposal_bins, dim3(grid1(nb, kBlock)), dim3(kBlock), 0, s, c, params, ld, b0, nb, bins);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_rotate_band(const double2 *D, int n_det, int64_t J, int64_t j_lo, int64_t n0, int64_t n_s,
+                        double2 *out, hipStream_t s) {
+  const int64_t total = (int64_t)n_det * J;
+  hipLaunchKernelGGL(k_rotate_band, dim3(grid1(total, kBlock)), dim3(kBlock), 0, s, D, total, J, j_lo, n0, n_s, out);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_outputs_rows(const double2 *C, const double2 *sig, const int4 *coldesc, int nb, int K, int Kp, int q,
+                         int n_modes, double *Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_outputs_rows, dim3(grid1((int64_t)nb * Kp, kBlock)), dim3(kBlock), 0, s, C, sig, coldesc, nb,
+                     K, Kp, q, n_modes, Y);
+  RBFL_HIP(hipGetLastError());
+}
+
 }  // namespace rbfl

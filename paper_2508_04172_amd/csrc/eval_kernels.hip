@@ -387,6 +387,55 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
   }
 }
 
+// ln L of a batch straight from window samples (no time basis): per detector
+// and mode, z at the arrival time is the spline through the 10 samples of
+// Z[n_det][n_modes][nb][T] around it; overlaps sig[n_det][nb][n_modes][n_modes].
+// Domain, window and NaN handling as in the epilogue.  One thread per
+// proposal (a reference path, not a tuned one).
+__global__ void __launch_bounds__(kThreads) k_series_lnl(const EvalConsts *__restrict__ cp,
+                                                         const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                         int64_t nb, const double2 *__restrict__ Z,
+                                                         const double2 *__restrict__ sig, double *__restrict__ lnl) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b >= nb) return;
+  const EvalConsts &c = *cp;
+  EpiSetup o;
+  epi_setup(c, params, ld, b0 + b, o);
+  if (o.status != 0) {
+    lnl[b0 + b] = o.status == 2 ? __builtin_nan("") : -__builtin_huge_val();
+    return;
+  }
+  const int n_modes = c.n_modes, T = c.T;
+  double tot = 0.0, comp = 0.0;
+  for (int k = 0; k < c.n_det; ++k) {
+    const double f = o.f[k];
+    double w[kSplineTaps];
+    for (int t = 0; t < kSplineTaps; ++t)
+      w[t] = fma(fma(fma(c.spline[t][3], f, c.spline[t][2]), f, c.spline[t][1]), f, c.spline[t][0]);
+    double zt = 0.0, st = 0.0;
+    for (int a = 0; a < n_modes; ++a) {
+      const double2 *za = Z + ((int64_t)(k * n_modes + a) * nb + b) * T + o.n0[k] - 4;
+      double zr = 0.0, zi = 0.0;
+      for (int t = 0; t < kSplineTaps; ++t) {
+        zr = fma(w[t], za[t].x, zr);
+        zi = fma(w[t], za[t].y, zi);
+      }
+      zt += o.Ar[k][a] * zr + o.Ai[k][a] * zi;                       // Re(conj(A_a) z_a)
+      for (int m = 0; m < n_modes; ++m) {
+        const double2 sv = sig[(((int64_t)k * nb + b) * n_modes + a) * n_modes + m];
+        const double pr = o.Ar[k][a] * o.Ar[k][m] + o.Ai[k][a] * o.Ai[k][m];
+        const double pim = o.Ar[k][a] * o.Ai[k][m] - o.Ai[k][a] * o.Ar[k][m];
+        st += pr * sv.x - pim * sv.y;                                 // Re(conj(A_a) A_m sigma_am)
+      }
+    }
+    const double v = o.rr * zt - 0.5 * o.rr * o.rr * st;
+    const double t = tot + v;
+    comp += fabs(tot) >= fabs(v) ? (tot - t) + v : (v - t) + tot;
+    tot = t;
+  }
+  lnl[b0 + b] = tot + comp;
+}
+
 // ---- multi-event (ragged) batch --------------------------------------------
 
 // Persistent contraction over the work list of every event: items are
@@ -623,6 +672,13 @@ void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *pa
   (void)hc;
   dim3 grid((unsigned)((nb + kEpiBatch - 1) / kEpiBatch));
   hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_series_lnl(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int64_t nb,
+                       const double2 *Z, const double2 *sig, double *lnl, hipStream_t s) {
+  hipLaunchKernelGGL(k_series_lnl, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, c, params,
+                     ld, b0, nb, Z, sig, lnl);
   RBFL_HIP(hipGetLastError());
 }
 

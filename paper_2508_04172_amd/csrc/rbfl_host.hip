@@ -782,12 +782,11 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
       }
   }
   if ((int)coldesc.size() != c.K) throw Error(RBFL_E_INVALID_ARG, "internal: output layout size");
-  DevBuf<int4> d_desc;
-  d_desc.alloc(coldesc.size());
-  RBFL_HIP(hipMemcpyAsync(d_desc.p, coldesc.data(), sizeof(int4) * coldesc.size(), hipMemcpyHostToDevice, stream));
+  c.coldesc.alloc(coldesc.size());
+  RBFL_HIP(hipMemcpyAsync(c.coldesc.p, coldesc.data(), sizeof(int4) * coldesc.size(), hipMemcpyHostToDevice, stream));
   DevBuf<double> d_R;
   d_R.alloc((size_t)c.K * NM);
-  launch_assemble_rhs(d_C.p, d_sig.p, d_desc.p, c.N, c.K, NM, c.q, c.n_modes, d_R.p, stream);
+  launch_assemble_rhs(d_C.p, d_sig.p, c.coldesc.p, c.N, c.K, NM, c.q, c.n_modes, d_R.p, stream);
   std::vector<double> Rh((size_t)c.K * NM);
   RBFL_HIP(hipMemcpyAsync(Rh.data(), d_R.p, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, stream));
   c.nodes.alloc((size_t)c.rows * 4);
@@ -923,6 +922,72 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   launch_fold_spline(c.basis.p, c.n_det * c.n_modes, c.T, c.q, c.consts.p, c.basis4.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
   c.timing[5] = seconds_since(t_all);
+}
+
+// The quantities the interpolants approximate, computed exactly at each
+// proposal with the start-up kernels (templates, overlaps, windowed DFT, time
+// basis coefficients), then turned into ln L two ways: out[0..n) through the
+// online stage's own epilogue (only the time basis and the spline remain
+// approximate), out[n..2n) from the window samples with the spline alone.
+static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t J = c.brute_J, j_lo = c.brute_j_lo;
+  const int nm = c.n_modes, nd = c.n_det, T = c.T, q = c.q;
+  if (!c.win_D.p) {
+    const int64_t n_trig = (int64_t)std::llround(c.t_trig * c.fs);
+    const int64_t n0 = ((n_trig - c.half_w) % c.n_s + c.n_s) % c.n_s;
+    c.win_D.alloc((size_t)nd * J);
+    launch_rotate_band(c.brute_D.p, nd, J, j_lo, n0, c.n_s, c.win_D.p, s);
+  }
+  // proposals per batch: templates within ~2 GiB
+  const size_t budget = (size_t)2 << 30;
+  const int nb_max = (int)std::max<int64_t>(
+      1, std::min<int64_t>({n, 4096, (int64_t)(budget / ((size_t)nm * J * sizeof(double2)))}));
+  auto n_splits = [&](int nb) {
+    const int t_here = ((nb + 63) / 64) * ((T + 63) / 64);
+    return (int)std::max<int64_t>(1, std::min<int64_t>((1024 + t_here - 1) / t_here, (J + 255) / 256));
+  };
+  DevBuf<Binary> bins;
+  bins.alloc(nb_max);
+  DevBuf<double2> A, Z, sig, C, part;
+  A.alloc((size_t)nm * nb_max * J);
+  Z.alloc((size_t)nd * nm * nb_max * T);
+  sig.alloc((size_t)nd * nb_max * nm * nm);
+  C.alloc((size_t)nd * nm * nb_max * q);
+  const int nb_last = (int)(n - (n - 1) / nb_max * nb_max);   // the last batch may split further
+  part.alloc((size_t)std::max<int64_t>((int64_t)n_splits(nb_max) * nb_max, (int64_t)n_splits(nb_last) * nb_last) * T);
+  DevBuf<double> Yb;
+  Yb.alloc((size_t)nb_max * c.Kp);
+  int mode_lm[2 * RBFL_MAX_MODES] = {};
+  for (int a = 0; a < nm; ++a) {
+    mode_lm[2 * a] = c.modes[a][0];
+    mode_lm[2 * a + 1] = c.modes[a][1];
+  }
+  DevBuf<int> d_modes;
+  d_modes.alloc(2 * RBFL_MAX_MODES);
+  RBFL_HIP(hipMemcpyAsync(d_modes.p, mode_lm, sizeof(mode_lm), hipMemcpyHostToDevice, s));
+  for (int64_t b0 = 0; b0 < n; b0 += nb_max) {
+    const int nb = (int)std::min<int64_t>(nb_max, n - b0);
+    launch_proposal_bins(c.consts.p, params, n, b0, nb, bins.p, s);
+    launch_waveforms(bins.p, nb, d_modes.p, nm, j_lo, (int)J, c.df, 1.0 / (c.d_ref * kMpcS), A.p, s);
+    launch_sigma(A.p, nb, nm, (int)J, c.brute_w.p, nd, nb, 0, sig.p, s);
+    const int n_split = n_splits(nb);
+    for (int a = 0; a < nm; ++a)
+      for (int k = 0; k < nd; ++k) {
+        launch_window_dft(A.p + (size_t)a * nb * J, nb, (int)J, (int)J, c.win_D.p + (size_t)k * J, j_lo, c.n_s, T,
+                          n_split, part.p, s);
+        launch_reduce_splits(part.p, n_split, nb, T, Z.p + ((size_t)k * nm + a) * nb * T, s);
+      }
+    for (int k = 0; k < nd; ++k)
+      for (int a = 0; a < nm; ++a) {
+        const size_t ka = (size_t)k * nm + a;
+        launch_coeffs(Z.p + ka * nb * T, c.basis.p + ka * T * q, nb, T, q, C.p + ka * nb * q, s);
+      }
+    launch_outputs_rows(C.p, sig.p, c.coldesc.p, nb, c.K, c.Kp, q, nm, Yb.p, s);
+    launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, Yb.p, c.basis4.p, out, s);
+    launch_series_lnl(c.consts.p, params, n, b0, nb, Z.p, sig.p, out + n, s);
+  }
+  RBFL_HIP(hipStreamSynchronize(s));
 }
 
 static void reserve(Ctx &c, int64_t n) {
@@ -1577,6 +1642,15 @@ int32_t rbfl_brute(rbfl_handle h, const double *params, int64_t n, double *lnl, 
     rbfl::Ctx &c = h->c;
     rbfl::launch_brute(c.consts.p, params, n, n, c.brute_D.p, c.brute_w.p, c.brute_j_lo, c.brute_J, c.n_s, c.df,
                        1.0 / (c.d_ref * rbfl::kMpcS), lnl, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_exact_parts(rbfl_handle h, const double *params, int64_t n, double *out, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(params != nullptr && out != nullptr, "params/out is NULL");
+    rbfl::require(n >= 0 && n <= 2147483647, "n must be in 0 .. 2^31 - 1");
+    rbfl::exact_parts(h->c, params, n, out, reinterpret_cast<hipStream_t>(stream));
   });
 }
 

@@ -126,6 +126,8 @@ struct Ctx {
   DevBuf<double2> brute_D;     // exact ln L: 4 df d_k / S_k over bins j_lo .. n_s/2 - 1, [n_det][brute_J]
   DevBuf<double> brute_w;      // exact ln L: 4 df / S_k, [n_det][brute_J]
   int64_t brute_j_lo = 0, brute_J = 0;
+  DevBuf<double2> win_D;       // exact outputs: brute_D with the window start's phase, made on first use
+  DevBuf<int4> coldesc;        // output column layout (kind, detector, mode, index), [K]
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
   DevBuf<uint16_t> W16;        // BF16 form: weights in 8-row groups [rows/8][Kp][8]
@@ -180,6 +182,14 @@ void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, do
 void launch_brute(const EvalConsts *c, const double *params, int64_t ld, int64_t n, const double2 *Dd,
                   const double *wk, int64_t j_lo, int64_t J, int64_t n_s, double df, double inv_dref_s, double *lnl,
                   hipStream_t s);
+void launch_proposal_bins(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int nb, Binary *bins,
+                          hipStream_t s);
+void launch_rotate_band(const double2 *D, int n_det, int64_t J, int64_t j_lo, int64_t n0, int64_t n_s,
+                        double2 *out, hipStream_t s);
+void launch_outputs_rows(const double2 *C, const double2 *sig, const int4 *coldesc, int nb, int K, int Kp, int q,
+                         int n_modes, double *Y, hipStream_t s);
+void launch_series_lnl(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int64_t nb,
+                       const double2 *Z, const double2 *sig, double *lnl, hipStream_t s);
 void launch_fold_spline(const double2 *B, int n_pairs, int T, int q, const EvalConsts *c, double2 *B4,
                         hipStream_t s);
 void launch_basis_from_u(const double2 *U, int T, int ldu, int q, double2 *B, hipStream_t s);

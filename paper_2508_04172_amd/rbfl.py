@@ -29,7 +29,7 @@ Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALU
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR = range(16)
 SPLIT_TOL = 1e-4
 
-EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
+EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_build.argtypes = [C.POINTER(BuildSpec), C.c_void_p, C.POINTER(C.c_void_p)]
     lib.rbfl_brute.restype = C.c_int32
     lib.rbfl_brute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    lib.rbfl_exact_parts.restype = C.c_int32
+    lib.rbfl_exact_parts.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     lib.rbfl_eval.restype = C.c_int32
     lib.rbfl_eval.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
     lib.rbfl_interp.restype = C.c_int32
@@ -261,6 +263,10 @@ class Handle:
     def brute(self, params_ptr: int, n: int, lnl_ptr: int, stream: int = 0):
         """Exact ln L without the interpolant (rbfl_brute)."""
         _check(load().rbfl_brute(self._h, C.c_void_p(params_ptr), n, C.c_void_p(lnl_ptr), C.c_void_p(stream)))
+
+    def exact_parts(self, params_ptr: int, n: int, out_ptr: int, stream: int = 0):
+        """ln L from exact outputs at the proposals, [2][n] (rbfl_exact_parts)."""
+        _check(load().rbfl_exact_parts(self._h, C.c_void_p(params_ptr), n, C.c_void_p(out_ptr), C.c_void_p(stream)))
 
     def eval(self, params_ptr: int, n: int, lnl_ptr: int, form: int = FORM_FP64, stream: int = 0):
         _check(load().rbfl_eval(self._h, C.c_void_p(params_ptr), n, C.c_void_p(lnl_ptr), form,

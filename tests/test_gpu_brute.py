@@ -7,6 +7,7 @@ rounding (1e-9 of max(1, |ln L|)).  Also: the zero-noise injection gives
 rho^2 / 2 exactly, NaN and unphysical inputs, and the meshfree method's error
 against the exact value near the nodes (reported; bounded loosely).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -14,6 +15,7 @@ import pytest
 
 from oracle import likelihood as lk
 from oracle import physics as ph
+from oracle import startup as su
 from paper_2508_04172_amd import rbfl
 from paper_2508_04172_amd import workloads as wl
 
@@ -132,3 +134,73 @@ def test_meshfree_method_error_near_nodes():
     q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
     print(f"[brute] small_multi (N=150, q=12) method error: median {q[0]:.3e}, 90% {q[1]:.3e}, "
           f"99% {q[2]:.3e}, max {q[3]:.3e} (|lnL| median {np.median(np.abs(lb[fin])):.1f})", flush=True)
+
+
+def gpu_parts(h, params):
+    torch = _torch()
+    p = torch.from_numpy(np.ascontiguousarray(params)).cuda()
+    n = params.shape[1]
+    out = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    h.exact_parts(p.data_ptr(), n, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_multi"])
+def test_exact_parts_match_oracle(name):
+    """rbfl_exact_parts against the oracle's exact_parts on the same
+    proposals: the oracle takes the library's frame (the two frames agree
+    only to ~1e-9, and ln L is steep in the physical point), its own basis."""
+    cfg, art, h = both(name)
+    n = 40
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=47)
+    qd = wl.queries(cfg, n=n, seed=53).near_nodes(h.nodes(), idx, jit)
+    qd.dt[:6] = np.array([-0.2, 0.2, 0.049, -0.049, 0.0, 0.01])   # outside / at the edges of the window
+    params = rbfl.params_soa(h, qd, cfg.t_trig)
+    params[10, 6] = np.nan
+    got = gpu_parts(h, params)
+    fr = h.frame()
+    art_g = dataclasses.replace(art, frame=su.Frame(theta_c=fr["theta_c"], metric=fr["metric"], vecs=fr["vecs"],
+                                                    lam=fr["lam"], semi=fr["semi"]))
+    pj, sm = lk.exact_parts(art_g, params[0:4].T, params[4:9].T, params[9], params[10])
+    for label, g, o in (("projected", got[0], pj), ("samples", got[1], sm)):
+        np.testing.assert_array_equal(np.isnan(g), np.isnan(o))
+        np.testing.assert_array_equal(np.isneginf(g), np.isneginf(o))
+        fin = np.isfinite(o)
+        assert fin.sum() >= n // 3
+        d = np.abs(g[fin] - o[fin])
+        print(f"[parts] {name} {label}: {fin.sum()} valid, max |d lnL| vs oracle {d.max():.3e}", flush=True)
+        assert np.all(d <= 1e-8 * np.maximum(1.0, np.abs(o[fin])))
+
+
+def test_exact_parts_bracket_the_method_error():
+    """The two parts sit between the meshfree and the exact ln L: at the
+    nodes with q = N and on-grid times all four agree; near the nodes the
+    differences are reported per approximation."""
+    cfg = wl.CFG1.with_(seg_len=8.0, n_nodes=60, q=60)
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    n = 60
+    qd = wl.queries(cfg, n=n, seed=43)
+    qd.x[:] = h.nodes()
+    qd.dt[:] = np.round(qd.dt * cfg.fs) / cfg.fs
+    params = rbfl.params_soa(h, qd, cfg.t_trig)
+    parts = gpu_parts(h, params)
+    lb = gpu_brute(h, params)
+    lm = gpu_eval(h, qd, cfg.t_trig)
+    fin = np.isfinite(lm)
+    assert fin.sum() >= n // 2
+    for v in (parts[0], parts[1], lm):
+        assert np.all(np.abs(v[fin] - lb[fin]) <= 1e-6 * np.maximum(1.0, np.abs(lb[fin])))
+    # near the nodes of the small multi-detector case: report the split
+    cfg2, art, h2 = both("small_multi")
+    m = 500
+    idx, jit = wl.node_jitter(m, cfg2.n_nodes, seed=59)
+    q2 = wl.queries(cfg2, n=m, seed=61).near_nodes(h2.nodes(), idx, jit)
+    p2 = rbfl.params_soa(h2, q2, cfg2.t_trig)
+    pr = gpu_parts(h2, p2)
+    ex = gpu_brute(h2, p2)
+    mf = gpu_eval(h2, q2, cfg2.t_trig)
+    ok = np.isfinite(mf)
+    med = lambda a, b: float(np.median(np.abs(a[ok] - b[ok])))
+    print(f"[parts] small_multi medians: rbf {med(mf, pr[0]):.3e}, truncation {med(pr[0], pr[1]):.3e}, "
+          f"spline {med(pr[1], ex):.3e}, total {med(mf, ex):.3e}", flush=True)

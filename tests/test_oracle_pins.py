@@ -420,3 +420,65 @@ def test_domain_boundaries(tiny_art):
     assert lk.meshfree_lnl(art, np.zeros((1, 4)), ev.inj_ext[None], np.array([far]), np.array([art.d_ref]))[0] == -np.inf
     near = ev.t_trig + (art.half_w - 6) / ev.grid.fs
     assert np.isfinite(lk.meshfree_lnl(art, np.zeros((1, 4)), ev.inj_ext[None], np.array([near]), np.array([art.d_ref]))[0])
+
+
+# ---------------------------------------------------------------- method-error parts
+
+def test_exact_parts_projected_equals_meshfree_at_nodes(multi_art):
+    """At a node the RBF interpolant reproduces the node values, so ln L from
+    the exact outputs projected on the time basis equals the meshfree ln L
+    there, for any q and any arrival time inside the window."""
+    art = multi_art
+    rng = np.random.default_rng(17)
+    nodes = np.array([0, 7, 21, 40])
+    n = nodes.size
+    ext = np.stack([rng.uniform(0, 6.28, n), rng.uniform(-1.2, 1.2, n), rng.uniform(0, 3, n),
+                    rng.uniform(0.1, 3, n), rng.uniform(0, 6, n)], axis=1)
+    tc = art.ev.t_trig + rng.uniform(-0.02, 0.02, n)
+    dl = art.d_ref * rng.uniform(0.6, 1.8, n)
+    de = art.x_nodes[nodes] * art.frame.semi
+    projected, _ = lk.exact_parts(art, de, ext, tc, dl)
+    meshfree = lk.meshfree_lnl(art, de, ext, tc, dl)
+    assert np.all(np.isfinite(meshfree))
+    np.testing.assert_allclose(projected, meshfree, rtol=1e-8, atol=1e-7)
+
+
+def test_exact_parts_samples_equal_brute_force_on_grid():
+    """With every arrival time on the sample grid the spline returns the sample
+    itself, so ln L from the exact window samples equals the brute-force ln L
+    at any physical proposal, not only at the nodes.  Co-located detectors at
+    the geocentre keep the arrival times on the grid."""
+    sites = tuple((0.8, -2.0, az, math.pi / 2, 0.0) for az in (0.3, 1.1, 2.0))
+    cfg = TINY_MULTI.with_(sites=sites)
+    art = su.startup(cfg, wl.white_noise(cfg), workers=1)
+    idx, jit = wl.node_jitter(12, cfg.n_nodes, seed=19)
+    qd = wl.queries(cfg, n=12, seed=23).near_nodes(art.x_nodes, idx, jit)
+    de, ext, tc, dl = lk.query_params(art, qd)
+    tc = art.ev.t_trig + np.round((tc - art.ev.t_trig) * art.ev.grid.fs) / art.ev.grid.fs
+    _, samples = lk.exact_parts(art, de, ext, tc, dl)
+    ok = np.isfinite(samples)
+    assert ok.sum() >= 6
+    _, phys = su.physical_mask(art.frame, de[ok] / art.frame.semi, art.ev.grid.f_low, cfg.chi_max)
+    want = [lk.brute_lnl(art.ev, tuple(p), e, t, d) for p, e, t, d in zip(phys, ext[ok], tc[ok], dl[ok])]
+    np.testing.assert_allclose(samples[ok], want, rtol=1e-9, atol=1e-8)
+
+
+def test_exact_parts_full_basis_projection_is_lossless():
+    """With q = T the time basis spans every window series (it needs N >= T),
+    so the projection loses nothing: both parts agree at any proposal and any
+    arrival time; NaN inputs give NaN in both."""
+    cfg = TINY.with_(half_window=0.01, n_nodes=40, q=21)
+    art = su.startup(cfg, wl.white_noise(cfg), workers=1)
+    assert art.basis.shape[2] == 21
+    idx, jit = wl.node_jitter(10, cfg.n_nodes, seed=29)
+    qd = wl.queries(cfg, n=10, seed=31).near_nodes(art.x_nodes, idx, jit)
+    de, ext, tc, dl = lk.query_params(art, qd)
+    tc = art.ev.t_trig + np.random.default_rng(3).uniform(-0.004, 0.004, 10)
+    dl = dl.copy()
+    dl[0] = np.nan
+    projected, samples = lk.exact_parts(art, de, ext, tc, dl)
+    assert np.isnan(projected[0]) and np.isnan(samples[0])
+    ok = np.isfinite(samples)
+    assert ok.sum() >= 5
+    np.testing.assert_array_equal(ok, np.isfinite(projected))
+    np.testing.assert_allclose(projected[ok], samples[ok], rtol=1e-9, atol=1e-8)
