@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 1
+#define RBFL_ABI_VERSION 2
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
 
@@ -85,7 +85,10 @@ typedef struct rbfl_ctx *rbfl_handle;
  *
  * Templates: the library's synthetic multimode inspiral family, h_{l,-m}(f) =
  * A_lm Amp(Mc, d_ref) f^(-7/6) exp(-i (m/2) Psi(2f/m)) for f_low <= f <
- * |m| F_isco, with a 3.5PN aligned-spin TaylorF2-like phase Psi.
+ * |m| F_isco, with a 3.5PN aligned-spin TaylorF2-like phase Psi whose time
+ * and phase are referenced at f_ref: Psi(f) = Psi_PN(f) - Psi_PN(f_ref) -
+ * Psi_PN'(f_ref) (f - f_ref), so t_c and phi_c are the time and phase at
+ * which the (2,2) mode passes f_ref (the injection uses the same convention).
  *
  * Ellipsoid: metric g of the (2,2) mode at center_phys in the chirp-time
  * coordinates Theta (Eq. metric_coords), computed unless `metric` is given;
@@ -128,6 +131,10 @@ typedef struct {
   int32_t poly_degree;                 /* 0 .. 3 */
   double chi_max;                      /* spin bound of the physical region (0 < chi_max <= 1) */
   uint32_t flags;                      /* RBFL_FLAG_* */
+  double f_ref;                        /* template time/phase reference frequency [Hz]: > 0 as given,
+                                          0 = the mean frequency of the centre's (2,2) band under the
+                                          weights f^(-7/3) / S_0 (the metric's), < 0 = the formal
+                                          coalescence (no reference shift) */
 } rbfl_build_spec;
 
 /* Thread-local description of the last failure on this thread; valid until
@@ -225,8 +232,9 @@ enum rbfl_query_what {
   RBFL_Q_SURROGATE = 14,    /* double[8]: accepted (1/0), held-out max |d ln L|, held-out median
                                |d ln L|, first-epoch loss, last-epoch loss, epochs, training seconds,
                                training proposals */
-  RBFL_Q_SPLIT_ERR = 15     /* double[8]: per split-form variant, max |d ln L| against the FP64 form
+  RBFL_Q_SPLIT_ERR = 15,    /* double[8]: per split-form variant, max |d ln L| against the FP64 form
                                on the last rbfl_autotune's proposals (0 = not measured) */
+  RBFL_Q_F_REF = 16         /* double[1]: template time/phase reference frequency [Hz] (0: coalescence) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 

@@ -20,10 +20,12 @@ EULER_GAMMA = 0.5772156649015329
 
 @dataclass
 class Grid:
-    """DFT grid of a segment: f_j = j / seg_len, j = 0 .. n_s/2."""
+    """DFT grid of a segment: f_j = j / seg_len, j = 0 .. n_s/2.  f_ref is the
+    templates' time/phase reference frequency (0: the formal coalescence)."""
     fs: float
     seg_len: float
     f_low: float
+    f_ref: float = 0.0
 
     @property
     def n_s(self) -> int:
@@ -179,6 +181,31 @@ def pn_phase_22(f, m1, m2, chi1, chi2):
     return -pi / 4.0 + 3.0 / (128.0 * eta * v ** 5) * series
 
 
+def referenced_phase_22(f, m1, m2, chi1, chi2, f_ref: float):
+    """The (2,2) phase with the template's time and phase referenced at f_ref
+    (the values a LAL-style approximant fixes at a reference frequency):
+    Psi(f) - Psi(f_ref) - Psi'(f_ref) (f - f_ref), so that the shifted phase
+    and its slope vanish at f_ref and t_c, phi_c become the time and phase at
+    which the (2,2) mode passes f_ref.  Psi' by the complex step
+    Im Psi(f_ref + i h) / h (exact to rounding).  f_ref <= 0: Psi itself."""
+    psi = pn_phase_22(f, m1, m2, chi1, chi2)
+    if f_ref <= 0.0:
+        return psi
+    h = 1e-20 * f_ref
+    p0 = float(np.real(pn_phase_22(np.array([f_ref]), m1, m2, chi1, chi2))[0])
+    dp = float(np.imag(pn_phase_22(np.array([f_ref + 1j * h]), m1, m2, chi1, chi2))[0]) / h
+    return psi - p0 - dp * (np.asarray(f) - f_ref)
+
+
+def reference_frequency(grid: Grid, psd: np.ndarray, phys) -> float:
+    """Mean frequency of the (2,2) band of `phys` under the weights
+    |h22|^2 / S = f^(-7/3) / S (the metric's weights)."""
+    j0, j1 = mode_band(grid, 2, phys[0], phys[1])
+    f = np.arange(j0, j1) * grid.df
+    w = f ** (-7.0 / 3.0) / psd[j0:j1]
+    return float(np.sum(f * w) / np.sum(w))
+
+
 def mode_amplitude(l: int, m: int, eta: float, delta: float) -> float:
     """Relative mode amplitudes of the synthetic family: A22 = 1, A21 = 0.1 delta,
     A33 = 0.3 delta, A32 = 0.05 (1 - 3 eta), A44 = 0.1 (1 - 3 eta)."""
@@ -207,7 +234,8 @@ def mode_band(grid: Grid, m: int, m1, m2):
 def waveform_mode(grid: Grid, l: int, m: int, phys, d_mpc: float) -> np.ndarray:
     """h_{l,-m}(f_j) on the whole grid (zeros outside the mode's band):
 
-    h_{l,-m}(f) = A_lm * Amp * f^(-7/6) * exp(-i (m/2) Psi(2 f / m)).
+    h_{l,-m}(f) = A_lm * Amp * f^(-7/6) * exp(-i (m/2) Psi(2 f / m)),
+    Psi referenced at grid.f_ref.
     """
     m1, m2, c1, c2 = phys
     _, eta, delta = mass_params(m1, m2)
@@ -216,7 +244,7 @@ def waveform_mode(grid: Grid, l: int, m: int, phys, d_mpc: float) -> np.ndarray:
     if j1 <= j0:
         return out
     f = np.arange(j0, j1) * grid.df
-    psi = pn_phase_22(2.0 * f / m, m1, m2, c1, c2)
+    psi = referenced_phase_22(2.0 * f / m, m1, m2, c1, c2, grid.f_ref)
     amp = mode_amplitude(l, m, eta, delta) * newtonian_amplitude(m1, m2, d_mpc) * f ** (-7.0 / 6.0)
     out[j0:j1] = amp * np.exp(-1j * (0.5 * m) * psi)
     return out

@@ -54,6 +54,13 @@ def make_event(cfg, white: np.ndarray | None, inj_ext: np.ndarray) -> Event:
     pos = [g[1] for g in geo]
     n_det = len(D)
     psd = np.stack([ph.psd_on_grid(grid, cfg.psd_scale) for _ in range(n_det)])
+    # template time/phase reference: as given, automatic (the mean frequency of
+    # the centre's band under the metric's weights; the centre is the
+    # injection here) or the coalescence (f_ref < 0)
+    f_ref = getattr(cfg, "f_ref", 0.0)
+    if f_ref == 0.0:
+        f_ref = ph.reference_frequency(grid, psd[0], cfg.inj_phys)
+    grid.f_ref = max(f_ref, 0.0)
     # signal at 1 Mpc, then scale the distance to the requested SNR
     sig1 = [ph.detector_signal(grid, cfg.modes, cfg.inj_phys, 1.0, inj_ext, cfg.t_trig, D[k], pos[k])
             for k in range(n_det)]

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kBruteThreads) k_brute(const EvalConsts *__res
     if (threadIdx.x == 0) lnl[g] = -__builtin_huge_val();
     return;
   }
-  const Binary b = make_binary(phys[0], phys[1], phys[2], phys[3]);
+  const Binary b = make_binary(phys[0], phys[1], phys[2], phys[3], c.f_ref);
   const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
   const double rr = c.d_ref / dl;
   const int n_modes = c.n_modes;

@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_proposal_bins(const EvalConsts *__re
     ok = ok && !isnan(t);
   }
   ok = ok && theta_to_phys(th, c.f0, c.chi_max, phys);
-  Binary b = make_binary(ok ? phys[0] : 2.0, ok ? phys[1] : 1.0, ok ? phys[2] : 0.0, ok ? phys[3] : 0.0);
+  Binary b = make_binary(ok ? phys[0] : 2.0, ok ? phys[1] : 1.0, ok ? phys[2] : 0.0, ok ? phys[3] : 0.0, c.f_ref);
   if (!ok) b.f_isco = 0.0;
   bins[i] = b;
 }

@@ -243,7 +243,7 @@ struct Sum {
 // components along 1 and 2 pi f are removed (weighted Gram-Schmidt), weights
 // |h22|^2/S.  Derivatives by the complex step Im Psi(Theta + i h e_i)/h.
 static void compute_metric(const Ctx &c, const std::vector<double> &psd0, const double center[4], double g[16]) {
-  const Binary b = make_binary(center[0], center[1], center[2], center[3]);
+  const Binary b = make_binary(center[0], center[1], center[2], center[3], 0.0);   // band only
   const int64_t j0 = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
   int64_t j1 = (int64_t)ceil(2.0 * b.f_isco * c.seg_len);
   j1 = std::min<int64_t>(std::max<int64_t>(j1, j0), c.n_s / 2);
@@ -299,6 +299,28 @@ static void compute_metric(const Ctx &c, const std::vector<double> &psd0, const 
     }
 }
 
+// Reference frequency of the template time and phase: the mean frequency of
+// the centre's (2,2) band under the metric's weights |h22|^2 / S_0, i.e.
+// f^(-7/3) / S_0.  There the time and constant-phase shifts that the match
+// maximises over are uncorrelated, so with the template phase referenced
+// there the overlap series of neighbouring templates stay aligned in time
+// and phase across the ellipsoid.
+static double reference_frequency(const Ctx &c, const std::vector<double> &psd0, const double center[4]) {
+  const Binary b = make_binary(center[0], center[1], center[2], center[3], 0.0);
+  const int64_t j0 = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  int64_t j1 = (int64_t)ceil(2.0 * b.f_isco * c.seg_len);
+  j1 = std::min<int64_t>(std::max<int64_t>(j1, j0), c.n_s / 2);
+  if (j1 <= j0) throw Error(RBFL_E_INVALID_ARG, "the (2,2) band at the centre is empty");
+  Sum w, fw;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double f = (double)j * c.df;
+    const double v = pow(f, -7.0 / 3.0) / psd0[j];
+    w.add(v);
+    fw.add(f * v);
+  }
+  return fw.value() / w.value();
+}
+
 // Cyclic Jacobi eigen-decomposition of a symmetric 4x4 matrix.
 static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
   double a[4][4];
@@ -342,7 +364,7 @@ static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
 static void synthesise_data(const rbfl_build_spec &s, const Ctx &c, const std::vector<std::vector<double>> &psd,
                             const YlmTerms *yneg, const YlmTerms *ypos, std::vector<std::vector<double2>> &data,
                             double *d_inj) {
-  const Binary b = make_binary(s.inj_phys[0], s.inj_phys[1], s.inj_phys[2], s.inj_phys[3]);
+  const Binary b = make_binary(s.inj_phys[0], s.inj_phys[1], s.inj_phys[2], s.inj_phys[3], c.f_ref);
   const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
   const int64_t j_hi = c.n_s / 2;
   const double alpha = s.inj_ext[0], dec = s.inj_ext[1], psi = s.inj_ext[2], iota = s.inj_ext[3],
@@ -408,6 +430,7 @@ static void synthesise_data(const rbfl_build_spec &s, const Ctx &c, const std::v
 static void validate(const rbfl_build_spec *s) {
   require(s != nullptr, "spec is NULL");
   require(s->abi_version == RBFL_ABI_VERSION, "abi_version mismatch");
+  require(std::isfinite(s->f_ref) && s->f_ref < 0.5 * s->fs, "f_ref must be finite and below fs / 2");
   require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
   require(s->n_modes >= 1 && s->n_modes <= RBFL_MAX_MODES, "n_modes out of range");
   for (int a = 0; a < s->n_modes; ++a) {
@@ -540,6 +563,12 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
     for (int64_t j = 1; j < c.n_f; ++j)
       psd[k][j] = s->psd ? s->psd[(int64_t)k * c.n_f + j] : psd_analytic((double)j * c.df, s->psd_scale);
   }
+  if (s->f_ref > 0.0)
+    c.f_ref = s->f_ref;
+  else if (s->f_ref == 0.0)
+    c.f_ref = reference_frequency(c, psd[0], s->center_phys);
+  else
+    c.f_ref = 0.0;
   std::vector<std::vector<double2>> data;
   if (s->data_fd) {
     c.d_ref = s->d_ref;
@@ -618,7 +647,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   std::vector<Binary> bins(c.N);
   int J_mode[RBFL_MAX_MODES] = {};
   for (int i = 0; i < c.N; ++i) {
-    bins[i] = make_binary(c.phys_nodes[4 * i], c.phys_nodes[4 * i + 1], c.phys_nodes[4 * i + 2], c.phys_nodes[4 * i + 3]);
+    bins[i] = make_binary(c.phys_nodes[4 * i], c.phys_nodes[4 * i + 1], c.phys_nodes[4 * i + 2], c.phys_nodes[4 * i + 3],
+                          c.f_ref);
     for (int a = 0; a < c.n_modes; ++a) {
       int64_t jc = (int64_t)ceil((double)c.modes[a][1] * bins[i].f_isco * c.seg_len);
       jc = std::min(std::max(jc, j_lo), j_hi);
@@ -898,6 +928,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   e.d_ref = c.d_ref;
   e.f0 = c.f_low;
   e.chi_max = c.chi_max;
+  e.f_ref = c.f_ref;
   for (int i = 0; i < 4; ++i) {
     e.theta_c[i] = c.theta_c[i];
     e.semi[i] = c.semi[i];
@@ -1344,6 +1375,9 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     }
     case RBFL_Q_D_REF:
       copy_out(out, bytes, &c.d_ref, sizeof(double));
+      return;
+    case RBFL_Q_F_REF:
+      copy_out(out, bytes, &c.f_ref, sizeof(double));
       return;
     case RBFL_Q_NODES:
       copy_out(out, bytes, c.x_nodes.data(), sizeof(double) * c.x_nodes.size());

@@ -34,6 +34,7 @@ struct EvalConsts {
   int q, T, half_w, degree;
   int poly_idx[kMaxPoly][3];                // variable indices of each monomial, -1 = unused
   double eps2, fs, t_trig, d_ref, f0, chi_max;
+  double f_ref;                             // template time/phase reference frequency (0: coalescence)
   double theta_c[4], V[16], semi[4];        // V row-major: Theta_i = theta_c_i + sum_j V[i][j] de_j
   double D[RBFL_MAX_DET][9], r[RBFL_MAX_DET][3];
   int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
@@ -109,6 +110,7 @@ struct Ctx {
   int64_t n_s = 0, n_f = 0;
   double fs = 0, seg_len = 0, f_low = 0, df = 0;
   double eps = 0, chi_max = 1, t_trig = 0, d_ref = 0, match = 0;
+  double f_ref = 0;            // template time/phase reference frequency (0: coalescence)
   // frame
   double theta_c[4] = {}, V[16] = {}, lam[4] = {}, semi[4] = {}, metric[16] = {};
   double D[RBFL_MAX_DET][9] = {}, r[RBFL_MAX_DET][3] = {};

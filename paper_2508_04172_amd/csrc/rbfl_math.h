@@ -27,9 +27,17 @@ struct Binary {
   double p2, p3, p4, p5, p6, p6l, p7;
   double amp;       // sqrt(5/24) pi^(-2/3) Mc^(5/6) in seconds (divide by the distance in seconds)
   double f_isco;    // orbital ISCO frequency 1 / (2 pi 6^(3/2) M)
+  // time and phase reference: with f_ref > 0 the template phase is
+  // Psi(f) - Psi(f_ref) - Psi'(f_ref) (f - f_ref), so t_c and phi_c are the
+  // time and phase at which the (2,2) mode passes f_ref; f_ref = 0 keeps the
+  // formal coalescence as the reference
+  double f_ref, psi_ref, dpsi_ref;
 };
 
-__host__ __device__ inline Binary make_binary(double m1, double m2, double c1, double c2) {
+__host__ __device__ inline double phase22_pn(double f, const Binary &b);
+__host__ __device__ inline double dphase22_pn(double f, const Binary &b);
+
+__host__ __device__ inline Binary make_binary(double m1, double m2, double c1, double c2, double f_ref) {
   Binary b;
   const double mt = m1 + m2;
   b.m_s = mt * kMsunS;
@@ -64,10 +72,14 @@ __host__ __device__ inline Binary make_binary(double m1, double m2, double c1, d
   const double mc = pow(m1 * m2, 0.6) / pow(mt, 0.2) * kMsunS;
   b.amp = sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) * pow(mc, 5.0 / 6.0);
   b.f_isco = 1.0 / (2.0 * kPi * pow(6.0, 1.5) * b.m_s);
+  b.f_ref = f_ref > 0.0 ? f_ref : 0.0;
+  b.psi_ref = f_ref > 0.0 ? phase22_pn(f_ref, b) : 0.0;
+  b.dpsi_ref = f_ref > 0.0 ? dphase22_pn(f_ref, b) : 0.0;
   return b;
 }
 
-__host__ __device__ inline double phase22(double f, const Binary &b) {
+// The PN phase series at the formal coalescence reference.
+__host__ __device__ inline double phase22_pn(double f, const Binary &b) {
   const double v = cbrt(kPi * b.m_s * f);
   const double lv = log(v);
   const double v2 = v * v;
@@ -80,6 +92,36 @@ __host__ __device__ inline double phase22(double f, const Binary &b) {
   s = s * v + b.p2;
   s = s * v2 + 1.0;
   return -0.25 * kPi + b.pre / v5 * s;
+}
+
+// dPsi/df of the PN series: with v = (pi M f)^(1/3), dv/df = v / (3 f) and
+// Psi = -pi/4 + pre v^-5 S(v), dPsi/df = pre v^-5 (v S'(v) - 5 S(v)) / (3 f).
+__host__ __device__ inline double dphase22_pn(double f, const Binary &b) {
+  const double v = cbrt(kPi * b.m_s * f);
+  const double lv = log(v);
+  const double v2 = v * v;
+  const double v5 = v2 * v2 * v;
+  const double l6 = b.p6 + b.p6l * (1.3862943611198906 + lv);
+  double s = b.p7;                       // S(v)
+  s = s * v + l6;
+  s = s * v + b.p5 * (1.0 + 3.0 * lv);
+  s = s * v + b.p4;
+  s = s * v + b.p3;
+  s = s * v + b.p2;
+  s = s * v2 + 1.0;
+  double ds = 7.0 * b.p7;                // v S'(v) / v^2
+  ds = ds * v + (6.0 * l6 + b.p6l);
+  ds = ds * v + b.p5 * (8.0 + 15.0 * lv);
+  ds = ds * v + 4.0 * b.p4;
+  ds = ds * v + 3.0 * b.p3;
+  ds = ds * v + 2.0 * b.p2;
+  ds *= v2;
+  return b.pre / v5 * (ds - 5.0 * s) / (3.0 * f);
+}
+
+// Template phase with the binary's time and phase reference applied.
+__host__ __device__ inline double phase22(double f, const Binary &b) {
+  return phase22_pn(f, b) - b.psi_ref - b.dpsi_ref * (f - b.f_ref);
 }
 
 // Relative amplitudes A22 = 1, A21 = 0.1 delta, A33 = 0.3 delta,

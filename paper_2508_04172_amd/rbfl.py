@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_MODES = 5
 MAX_DET = 4
 
@@ -26,7 +26,7 @@ FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
 FLAG_CENTER_NODE = 0x1
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR = range(16)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF = range(17)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
@@ -66,6 +66,7 @@ class BuildSpec(C.Structure):
         ("poly_degree", C.c_int32),
         ("chi_max", C.c_double),
         ("flags", C.c_uint32),
+        ("f_ref", C.c_double),
     ]
 
 
@@ -223,6 +224,7 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
     s.poly_degree = cfg.poly_degree
     s.chi_max = cfg.chi_max
     s.flags = FLAG_CENTER_NODE if cfg.center_node else 0
+    s.f_ref = cfg.f_ref
     return s
 
 
@@ -295,6 +297,9 @@ class Handle:
         v = self._query(Q_FRAME, 44)
         return {"theta_c": v[0:4], "vecs": v[4:20].reshape(4, 4), "lam": v[20:24], "semi": v[24:28],
                 "metric": v[28:44].reshape(4, 4)}
+
+    def f_ref(self) -> float:
+        return float(self._query(Q_F_REF, 1)[0])
 
     def d_ref(self) -> float:
         return float(self._query(Q_D_REF, 1)[0])

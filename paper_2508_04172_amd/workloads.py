@@ -67,6 +67,7 @@ class Config:
     inj_seed: int = 2
     chi_max: float = 1.0
     center_node: bool = False
+    f_ref: float = 0.0                            # template time/phase reference [Hz]; 0 = automatic, < 0 = coalescence
 
     @property
     def n_det(self) -> int:

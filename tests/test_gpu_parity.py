@@ -91,6 +91,7 @@ def test_frame_and_nodes(name):
     assert np.allclose(h.nodes(), art.x_nodes, rtol=0, atol=1e-15)
     assert np.allclose(h.node_phys(), art.phys_nodes, rtol=1e-8, atol=1e-9)
     assert h.d_ref() == pytest.approx(art.d_ref, rel=1e-11)
+    assert h.f_ref() == pytest.approx(art.ev.grid.f_ref, rel=1e-12) and h.f_ref() > 0.0
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -482,3 +482,45 @@ def test_exact_parts_full_basis_projection_is_lossless():
     assert ok.sum() >= 5
     np.testing.assert_array_equal(ok, np.isfinite(projected))
     np.testing.assert_allclose(projected[ok], samples[ok], rtol=1e-9, atol=1e-8)
+
+
+# ---------------------------------------------------------------- time/phase reference
+
+def test_referenced_phase_vanishes_with_its_slope_at_f_ref():
+    """Psi(f) - Psi(f_ref) - Psi'(f_ref)(f - f_ref): zero with zero slope at
+    f_ref (central differences, independent of the complex step) and an
+    affine function of f away from the PN phase (second differences vanish)."""
+    phys = (8.0, 1.4, 0.3, -0.2)
+    f_ref = 137.0
+    h = 1e-3
+    fr = np.array([f_ref - h, f_ref, f_ref + h])
+    p = ph.referenced_phase_22(fr, *phys, f_ref)
+    assert abs(p[1]) < 1e-9
+    assert abs((p[2] - p[0]) / (2 * h)) < 1e-5
+    f = np.linspace(30.0, 400.0, 7)
+    diff = ph.referenced_phase_22(f, *phys, f_ref) - ph.pn_phase_22(f, *phys)
+    assert np.allclose(np.diff(diff, 2), 0.0, atol=1e-6 * np.max(np.abs(diff)))
+
+
+def test_reference_frequency_with_flat_weights_is_the_band_midpoint():
+    """With S(f) = f^(-7/3) the weights are flat, so the weighted mean
+    frequency is the mean of the band's bins."""
+    grid = ph.Grid(2048.0, 8.0, 20.0)
+    f = grid.freqs
+    psd = np.full(grid.n_f, np.inf)
+    psd[1:] = f[1:] ** (-7.0 / 3.0)
+    phys = (8.0, 1.4, 0.3, 0.0)
+    j0, j1 = ph.mode_band(grid, 2, phys[0], phys[1])
+    assert ph.reference_frequency(grid, psd, phys) == pytest.approx(0.5 * (j0 + j1 - 1) * grid.df, rel=1e-12)
+
+
+def test_match_does_not_depend_on_the_time_phase_reference():
+    """Eq. Match maximises over time and phase, so moving the templates'
+    reference (a shift affine in f) leaves every match unchanged."""
+    a, b = (8.0, 1.4, 0.3, 0.0), (7.6, 1.45, 0.1, 0.4)
+    vals = []
+    for f_ref in (0.0, 60.0, 137.0):
+        grid = ph.Grid(2048.0, 8.0, 20.0, f_ref)
+        vals.append(su.match_22(grid, ph.psd_on_grid(grid), a, b))
+    assert vals[0] < 0.999
+    assert vals[1] == pytest.approx(vals[0], abs=1e-9) and vals[2] == pytest.approx(vals[0], abs=1e-9)
