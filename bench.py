@@ -317,9 +317,10 @@ def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
 
 def bench_method_error(np, torch, rbfl, wl, h2, cfg2, qd2, idx2, jit2):
     """The meshfree approximation against the exact ln L on the same GPU: the
-    single-detector (2,2) workload at four ellipsoid matches with 1e4 proposals
-    uniform in the ball (the paper's Fig. 3 protocol), and the 3-detector
-    workload on 2e3 of the bench's proposals.  The error is split with
+    single-detector (2,2) workload at four ellipsoid matches, unsqueezed and
+    squeezed, with 1e4 proposals uniform in the ball and the extrinsic
+    parameters at their injected values (the paper's Fig. 3 protocol), and
+    the 3-detector workload on 2e3 of the bench's proposals.  The error is split with
     rbfl_exact_parts into the RBF interpolation (meshfree vs exact outputs on
     the time basis), the basis truncation (basis vs raw window samples) and
     the sub-sample spline (samples vs exact); with the exact path's
@@ -357,17 +358,36 @@ def bench_method_error(np, torch, rbfl, wl, h2, cfg2, qd2, idx2, jit2):
                 "exact_evals_per_s": n / brute_s}
 
     cases = {}
-    for match in (0.90, 0.95, 0.97, 0.99):
-        cfg = wl.CFG1.with_(name=f"cfg1_match{match:.2f}", match=match)
-        h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    # the paper's Fig. 3 protocol: intrinsic points uniform in the ellipsoid,
+    # every extrinsic parameter (sky, polarisation, inclination, phase,
+    # distance, t_c) at its injected value
+    runs = [(m, sq, 200, 1.0) for sq in (False, True) for m in (0.90, 0.95, 0.97, 0.99)]
+    runs.append((0.97, True, 800, 2.0))
+    for match, squeeze, n_nodes, eps in runs:
+        name = f"cfg1_match{match:.2f}" + ("_squeezed" if squeeze else "") + (f"_N{n_nodes}" if n_nodes != 200 else "")
+        cfg = wl.CFG1.with_(name=name, match=match, squeeze=squeeze, n_nodes=n_nodes, eps=eps)
+        inj = wl.injection_extrinsics(cfg)
+        h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), inj)
         n = 10000
         qd = wl.queries(cfg, n=n)
-        cases[cfg.name] = compare(h, rbfl.params_soa(h, qd, cfg.t_trig), n)
-        log(f"method error {cfg.name}: {cases[cfg.name]}")
+        qd.dt[:] = 0.0
+        qd.ext[:, 4] = inj[4]
+        qd.dist_ratio[:] = 1.0
+        cases[name] = compare(h, rbfl.params_soa(h, qd, cfg.t_trig), n)
+        cases[name].update(squeeze_factor=h.squeeze()[0], n_nodes=n_nodes, eps=eps, cond=h.cond())
+        log(f"method error {name}: {cases[name]}")
     n = 2000
     p2 = rbfl.params_soa(h2, qd2.near_nodes(h2.nodes(), idx2, jit2), cfg2.t_trig)[:, :n]
     cases[cfg2.name] = compare(h2, p2, n)
     log(f"method error {cfg2.name}: {cases[cfg2.name]}")
+    cfg2s = cfg2.with_(name=cfg2.name + "_squeezed", squeeze=True)
+    t0 = time.time()
+    h2s = rbfl.Handle.from_config(cfg2s, wl.white_noise(cfg2s), wl.injection_extrinsics(cfg2s))
+    log(f"squeezed start-up {time.time() - t0:.2f} s, factor {h2s.squeeze()}")
+    p2s = rbfl.params_soa(h2s, qd2.near_nodes(h2s.nodes(), idx2, jit2), cfg2.t_trig)[:, :n]
+    cases[cfg2s.name] = compare(h2s, p2s, n)
+    cases[cfg2s.name]["squeeze_factor"] = h2s.squeeze()[0]
+    log(f"method error {cfg2s.name}: {cases[cfg2s.name]}")
     out["cases"] = cases
     return out
 

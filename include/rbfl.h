@@ -64,6 +64,12 @@ enum rbfl_form {
 
 /* Spec flags. */
 #define RBFL_FLAG_CENTER_NODE 0x1u  /* place the ellipsoid centre as node 0 before the Halton nodes */
+#define RBFL_FLAG_SQUEEZE 0x2u      /* squeeze the longest ellipsoid axis (Sec. II C.1, Fig. 2): scale it to
+                                       the first point, scanning outward in steps of 1/64 along both
+                                       directions, where the true match (Eq. Match) of the (2,2) template
+                                       with the centre's falls below M0 (spins taken at face value, a
+                                       direction that leaves eta <= 1/4 first sets no limit; the crossing
+                                       bisected to 1e-12); RBFL_Q_SQUEEZE reports the factor */
 
 typedef struct rbfl_ctx *rbfl_handle;
 
@@ -234,7 +240,9 @@ enum rbfl_query_what {
                                training proposals */
   RBFL_Q_SPLIT_ERR = 15,    /* double[8]: per split-form variant, max |d ln L| against the FP64 form
                                on the last rbfl_autotune's proposals (0 = not measured) */
-  RBFL_Q_F_REF = 16         /* double[1]: template time/phase reference frequency [Hz] (0: coalescence) */
+  RBFL_Q_F_REF = 16,        /* double[1]: template time/phase reference frequency [Hz] (0: coalescence) */
+  RBFL_Q_SQUEEZE = 17       /* double[2]: factor applied to the longest semi-axis (1 = none) and the true
+                               match at the squeezed tip (0 when not squeezed) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 

@@ -193,6 +193,70 @@ def physical_mask(fr: Frame, x: np.ndarray, f0: float, chi_max: float = 1.0):
 
 
 # ----------------------------------------------------------------------------
+# Squeezing the ellipsoid along its longest axis (Sec. II C.1, Fig. 2)
+# ----------------------------------------------------------------------------
+
+def squeeze(fr: Frame, grid: ph.Grid, psd0: np.ndarray, centre_phys, match: float, f0: float,
+            n_scan: int = 64):
+    """Contract the longest semi-axis to where the true match with the centre
+    template first falls to M0.  Reading used: along +e and -e of the longest
+    axis (index 3), the points s = i / n_scan, i = 1 .. n_scan, are visited
+    outward, with the template family's formulas taken at face value in the
+    spins (the spin bound acts later, through node rejection: the squeezed
+    ellipsoid of Fig. 2 still holds unphysical parts).  The first point whose
+    match is below M0 brackets the crossing s* with the point before it; a
+    step that leaves the binaries (eta > 1/4) is cut at that boundary (found
+    by bisection to 1e-12) and brackets a crossing only if the match at the
+    boundary is below M0, else the direction sets no limit.  s* comes from a
+    bracketing root finder.  The axis is scaled by the smaller s* (1 when
+    neither direction crosses), keeping the ellipsoid centred.  Returns
+    (new frame, factor)."""
+    import scipy.optimize
+
+    def true_match(s):
+        x = np.zeros((1, 4))
+        x[0, 3] = s
+        ok, phys = physical_mask(fr, x, f0, np.inf)
+        if not ok[0]:
+            return None
+        return match_22(grid, psd0, tuple(centre_phys), tuple(phys[0]))
+
+    def is_binary(s):
+        x = np.zeros((1, 4))
+        x[0, 3] = s
+        return bool(physical_mask(fr, x, f0, np.inf)[0][0])
+
+    factor = 1.0
+    for sign in (1.0, -1.0):
+        lo = 0.0
+        for i in range(1, n_scan + 1):
+            s = i / n_scan
+            m = true_match(sign * s)
+            if m is None:
+                a, b = lo, s
+                while b - a > 1e-12:
+                    mid = 0.5 * (a + b)
+                    if is_binary(sign * mid):
+                        a = mid
+                    else:
+                        b = mid
+                m_edge = true_match(sign * a)
+                if m_edge is None or m_edge >= match:
+                    break
+                s = a
+                m = m_edge
+            if m < match:
+                hi = s
+                factor = min(factor, scipy.optimize.brentq(lambda t: true_match(sign * t) - match, lo, hi,
+                                                           xtol=1e-12, rtol=1e-14))
+                break
+            lo = s
+    semi = fr.semi.copy()
+    semi[3] *= factor
+    return Frame(theta_c=fr.theta_c, metric=fr.metric, vecs=fr.vecs, lam=fr.lam, semi=semi), factor
+
+
+# ----------------------------------------------------------------------------
 # Halton nodes
 # ----------------------------------------------------------------------------
 
@@ -375,6 +439,7 @@ class Artefacts:
     node_values: np.ndarray  # [N][K] interpolated quantities at the nodes
     z_nodes: np.ndarray      # [n_det][n_modes][N][T]
     sigma_nodes: np.ndarray  # [n_det][N][n][n]
+    squeeze_factor: float = 1.0   # scale applied to the longest semi-axis
 
     @property
     def d_ref(self) -> float:
@@ -402,6 +467,9 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     theta_c = ph.phys_to_theta(cfg.inj_phys, grid.f_low)
     g = metric(grid, ev.psd[0], cfg.inj_phys)
     fr = frame(g, theta_c, cfg.match)
+    squeeze_factor = 1.0
+    if getattr(cfg, "squeeze", False):
+        fr, squeeze_factor = squeeze(fr, grid, ev.psd[0], cfg.inj_phys, cfg.match, grid.f_low)
     x, phys = place_nodes(fr, cfg.n_nodes, grid.f_low, cfg.chi_max, cfg.center_node)
     z, sig = node_series_and_overlaps(ev, phys, cfg.half_window, workers=workers)
     n_modes = len(ev.modes)
@@ -434,4 +502,4 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=x, phys_nodes=phys, W=W, basis=basis,
                      half_w=half_w, eps=cfg.eps, degree=cfg.poly_degree, q=cfg.q, cond=cond,
                      discarded=discarded, singular=singular, node_values=F, z_nodes=z,
-                     sigma_nodes=sig)
+                     sigma_nodes=sig, squeeze_factor=squeeze_factor)

@@ -321,6 +321,171 @@ static double reference_frequency(const Ctx &c, const std::vector<double> &psd0,
   return fw.value() / w.value();
 }
 
+// ---- true match (Eq. Match) and the squeeze of the longest axis (Sec. II C.1)
+
+typedef std::complex<double> cplx;
+
+// In-place radix-2 transform y_m = sum_j x_j e^{+2 pi i j m / L}, L a power of
+// two; bit-reversal permutation then butterflies with a table of the L/2
+// twiddles e^{2 pi i k / L}.
+static void fft_plus_pow2(std::vector<cplx> &x) {
+  const size_t L = x.size();
+  for (size_t i = 1, j = 0; i < L; ++i) {
+    size_t bit = L >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(x[i], x[j]);
+  }
+  std::vector<cplx> tw(L / 2);
+  for (size_t k = 0; k < L / 2; ++k) {
+    const double a = 2.0 * kPi * (double)k / (double)L;
+    tw[k] = cplx(cos(a), sin(a));
+  }
+  for (size_t len = 2; len <= L; len <<= 1) {
+    const size_t half = len >> 1, stride = L / len;
+    for (size_t i = 0; i < L; i += len)
+      for (size_t k = 0; k < half; ++k) {
+        const cplx u = x[i + k], v = x[i + k + half] * tw[k * stride];
+        x[i + k] = u + v;
+        x[i + k + half] = u - v;
+      }
+  }
+}
+
+// Match of the normalised (2,2) templates of a and b under detector 0's PSD,
+// maximised over phase (the modulus) and time: the coarse peak of
+// |sum_j X_j e^{2 pi i f_j t}| on a grid of seg_len / L (L >= 2 n_s) from one
+// transform, then a golden-section refinement within one grid step.
+static double match22(const Ctx &c, const std::vector<double> &psd0, const Binary &a, const Binary &b) {
+  const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  auto band_end = [&](const Binary &x) {
+    return std::min<int64_t>(std::max<int64_t>((int64_t)ceil(2.0 * x.f_isco * c.seg_len), j_lo), c.n_s / 2);
+  };
+  const int64_t ja = band_end(a), jb = band_end(b), jc = std::min(ja, jb);
+  auto tmpl = [&](const Binary &x, int64_t j) {
+    const double f = (double)j * c.df;
+    return std::polar(pow(f, -7.0 / 6.0), -phase22(f, x));
+  };
+  Sum na, nb;
+  for (int64_t j = j_lo; j < ja; ++j) na.add(std::norm(tmpl(a, j)) / psd0[j]);
+  for (int64_t j = j_lo; j < jb; ++j) nb.add(std::norm(tmpl(b, j)) / psd0[j]);
+  const double norm = 1.0 / sqrt(na.value() * nb.value());
+  if (jc <= j_lo) return 0.0;
+  std::vector<cplx> X((size_t)(jc - j_lo));
+  for (int64_t j = j_lo; j < jc; ++j) X[j - j_lo] = std::conj(tmpl(a, j)) * tmpl(b, j) / psd0[j] * norm;
+  size_t L = 1;
+  while (L < (size_t)(2 * c.n_s)) L <<= 1;
+  std::vector<cplx> y(L, cplx(0.0, 0.0));
+  for (int64_t j = j_lo; j < jc; ++j) y[(size_t)j] = X[j - j_lo];
+  fft_plus_pow2(y);
+  size_t best = 0;
+  for (size_t m = 1; m < L; ++m)
+    if (std::abs(y[m]) > std::abs(y[best])) best = m;
+  // |sum_j X_j e^{2 pi i j t / seg_len}|, phases re-seeded every 256 bins
+  auto g = [&](double t) {
+    cplx s(0.0, 0.0);
+    const double w = 2.0 * kPi * t / c.seg_len;
+    const cplx step = std::polar(1.0, w);
+    cplx e(0.0, 0.0);
+    for (int64_t j = j_lo; j < jc; ++j) {
+      if (((j - j_lo) & 255) == 0) e = std::polar(1.0, w * (double)j);
+      s += X[j - j_lo] * e;
+      e *= step;
+    }
+    return std::abs(s);
+  };
+  const double dt = c.seg_len / (double)L;
+  double lo = ((double)best - 1.0) * dt, hi = ((double)best + 1.0) * dt;
+  const double r = 0.5 * (sqrt(5.0) - 1.0);
+  double x1 = hi - r * (hi - lo), x2 = lo + r * (hi - lo);
+  double g1 = g(x1), g2 = g(x2);
+  for (int it = 0; it < 80 && hi - lo > 1e-13 * c.seg_len; ++it) {
+    if (g1 >= g2) {
+      hi = x2;
+      x2 = x1;
+      g2 = g1;
+      x1 = hi - r * (hi - lo);
+      g1 = g(x1);
+    } else {
+      lo = x1;
+      x1 = x2;
+      g1 = g2;
+      x2 = lo + r * (hi - lo);
+      g2 = g(x2);
+    }
+  }
+  return std::max({g1, g2, std::abs(y[best])});
+}
+
+// Squeeze (Fig. 2): scale of the longest semi-axis (index 3) such that the
+// true match with the centre template first falls to M0 there.  Outward
+// scan s = i/64 along +e and -e with the family's formulas taken at face
+// value in the spins (the spin bound acts through node rejection).  The first
+// point below M0 brackets the crossing with the point before it; a step that
+// leaves the binaries (eta > 1/4) is cut at that boundary (bisected to
+// 1e-12) and brackets a crossing only if the match there is below M0, else
+// the direction sets no limit.  The crossing is bisected to 1e-12.  Returns
+// the smaller crossing, 1 if none; *tip_match receives the match at the tip.
+static double squeeze_factor(const Ctx &c, const std::vector<double> &psd0, const double center[4],
+                             double *tip_match) {
+  const Binary bc = make_binary(center[0], center[1], center[2], center[3], c.f_ref);
+  auto at = [&](double s, bool *ok) {
+    double th[4], p[4];
+    for (int i = 0; i < 4; ++i) th[i] = c.theta_c[i] + c.V[4 * i + 3] * s * c.semi[3];
+    *ok = theta_to_phys(th, c.f_low, std::numeric_limits<double>::infinity(), p);
+    if (!*ok) return 0.0;
+    return match22(c, psd0, bc, make_binary(p[0], p[1], p[2], p[3], c.f_ref));
+  };
+  double factor = 1.0, factor_sign = 1.0;
+  const int n_scan = 64;
+  for (const double sign : {1.0, -1.0}) {
+    double lo = 0.0;
+    for (int i = 1; i <= n_scan; ++i) {
+      const double s = (double)i / n_scan;
+      bool ok = false;
+      double m = at(sign * s, &ok);
+      double hi = s;
+      if (!ok) {
+        // the step leaves the binaries: cut it at the boundary
+        double a = lo, b = s;
+        while (b - a > 1e-12) {
+          const double mid = 0.5 * (a + b);
+          double th[4], p[4];
+          for (int r = 0; r < 4; ++r) th[r] = c.theta_c[r] + c.V[4 * r + 3] * sign * mid * c.semi[3];
+          if (theta_to_phys(th, c.f_low, std::numeric_limits<double>::infinity(), p))
+            a = mid;
+          else
+            b = mid;
+        }
+        m = at(sign * a, &ok);
+        if (!ok || m >= c.match) break;
+        hi = a;
+      }
+      if (m < c.match) {
+        double a = lo, b = hi;
+        while (b - a > 1e-12) {
+          const double mid = 0.5 * (a + b);
+          bool okm = false;
+          const double mm = at(sign * mid, &okm);
+          if (okm && mm >= c.match)
+            a = mid;
+          else
+            b = mid;
+        }
+        if (0.5 * (a + b) < factor) {
+          factor = 0.5 * (a + b);
+          factor_sign = sign;
+        }
+        break;
+      }
+      lo = s;
+    }
+  }
+  bool ok = false;
+  *tip_match = factor < 1.0 ? at(factor_sign * factor, &ok) : 0.0;
+  return factor;
+}
+
 // Cyclic Jacobi eigen-decomposition of a symmetric 4x4 matrix.
 static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
   double a[4][4];
@@ -431,6 +596,7 @@ static void validate(const rbfl_build_spec *s) {
   require(s != nullptr, "spec is NULL");
   require(s->abi_version == RBFL_ABI_VERSION, "abi_version mismatch");
   require(std::isfinite(s->f_ref) && s->f_ref < 0.5 * s->fs, "f_ref must be finite and below fs / 2");
+  require((s->flags & ~(uint32_t)(RBFL_FLAG_CENTER_NODE | RBFL_FLAG_SQUEEZE)) == 0, "unknown flag bits");
   require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
   require(s->n_modes >= 1 && s->n_modes <= RBFL_MAX_MODES, "n_modes out of range");
   for (int a = 0; a < s->n_modes; ++a) {
@@ -603,6 +769,12 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
     const double sg = vec[4 * kmax + o] < 0 ? -1.0 : 1.0;
     for (int r = 0; r < 4; ++r) c.V[4 * r + i] = sg * vec[4 * r + o];
     c.semi[i] = sqrt((1.0 - c.match) / lam[o]);
+  }
+  c.squeeze[0] = 1.0;
+  c.squeeze[1] = 0.0;
+  if (s->flags & RBFL_FLAG_SQUEEZE) {
+    c.squeeze[0] = squeeze_factor(c, psd[0], s->center_phys, &c.squeeze[1]);
+    c.semi[3] *= c.squeeze[0];
   }
 
   // Halton nodes in the ball, physical only
@@ -1378,6 +1550,9 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       return;
     case RBFL_Q_F_REF:
       copy_out(out, bytes, &c.f_ref, sizeof(double));
+      return;
+    case RBFL_Q_SQUEEZE:
+      copy_out(out, bytes, c.squeeze, sizeof(c.squeeze));
       return;
     case RBFL_Q_NODES:
       copy_out(out, bytes, c.x_nodes.data(), sizeof(double) * c.x_nodes.size());

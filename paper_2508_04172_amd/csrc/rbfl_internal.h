@@ -111,6 +111,7 @@ struct Ctx {
   double fs = 0, seg_len = 0, f_low = 0, df = 0;
   double eps = 0, chi_max = 1, t_trig = 0, d_ref = 0, match = 0;
   double f_ref = 0;            // template time/phase reference frequency (0: coalescence)
+  double squeeze[2] = {1, 0};  // factor applied to the longest semi-axis, true match at its new tip
   // frame
   double theta_c[4] = {}, V[16] = {}, lam[4] = {}, semi[4] = {}, metric[16] = {};
   double D[RBFL_MAX_DET][9] = {}, r[RBFL_MAX_DET][3] = {};

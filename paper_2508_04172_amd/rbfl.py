@@ -23,10 +23,10 @@ MAX_DET = 4
 
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NUMERICAL, E_UNSUPPORTED, E_STATE = range(7)
 FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
-FLAG_CENTER_NODE = 0x1
+FLAG_CENTER_NODE, FLAG_SQUEEZE = 0x1, 0x2
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF = range(17)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE = range(18)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
@@ -223,7 +223,7 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
     s.eps = cfg.eps
     s.poly_degree = cfg.poly_degree
     s.chi_max = cfg.chi_max
-    s.flags = FLAG_CENTER_NODE if cfg.center_node else 0
+    s.flags = (FLAG_CENTER_NODE if cfg.center_node else 0) | (FLAG_SQUEEZE if cfg.squeeze else 0)
     s.f_ref = cfg.f_ref
     return s
 
@@ -297,6 +297,11 @@ class Handle:
         v = self._query(Q_FRAME, 44)
         return {"theta_c": v[0:4], "vecs": v[4:20].reshape(4, 4), "lam": v[20:24], "semi": v[24:28],
                 "metric": v[28:44].reshape(4, 4)}
+
+    def squeeze(self) -> tuple:
+        """(factor applied to the longest semi-axis, true match at its new tip)."""
+        v = self._query(Q_SQUEEZE, 2)
+        return float(v[0]), float(v[1])
 
     def f_ref(self) -> float:
         return float(self._query(Q_F_REF, 1)[0])

@@ -68,6 +68,7 @@ class Config:
     chi_max: float = 1.0
     center_node: bool = False
     f_ref: float = 0.0                            # template time/phase reference [Hz]; 0 = automatic, < 0 = coalescence
+    squeeze: bool = False                         # contract the longest ellipsoid axis to the true-match crossing
 
     @property
     def n_det(self) -> int:

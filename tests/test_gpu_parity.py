@@ -27,6 +27,7 @@ CASES = {
     "cfg1": wl.CFG1,
     "small_multi": wl.SMALL_MULTI,
     "ragged_tail": wl.SMALL_MULTI.with_(name="ragged_tail", n_nodes=131, q=7, modes=wl.ALL_MODES, n_queries=1237),
+    "squeezed": wl.SMALL_MULTI.with_(name="small_hlv_3mode_squeezed", squeeze=True),
 }
 
 
@@ -92,6 +93,10 @@ def test_frame_and_nodes(name):
     assert np.allclose(h.node_phys(), art.phys_nodes, rtol=1e-8, atol=1e-9)
     assert h.d_ref() == pytest.approx(art.d_ref, rel=1e-11)
     assert h.f_ref() == pytest.approx(art.ev.grid.f_ref, rel=1e-12) and h.f_ref() > 0.0
+    factor, tip = h.squeeze()
+    assert factor == pytest.approx(art.squeeze_factor, rel=1e-8)
+    if cfg.squeeze:
+        assert factor < 1.0 and tip == pytest.approx(cfg.match, abs=1e-9)
 
 
 @pytest.mark.parametrize("name", list(CASES))

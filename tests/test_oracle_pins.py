@@ -524,3 +524,35 @@ def test_match_does_not_depend_on_the_time_phase_reference():
         vals.append(su.match_22(grid, ph.psd_on_grid(grid), a, b))
     assert vals[0] < 0.999
     assert vals[1] == pytest.approx(vals[0], abs=1e-9) and vals[2] == pytest.approx(vals[0], abs=1e-9)
+
+
+# ---------------------------------------------------------------- squeeze (Fig. 2)
+
+def test_squeeze_stops_at_the_first_true_match_crossing():
+    """The squeezed tip of the longest axis has true match M0 with the centre
+    (Eq. Match, brute force), every point of the axis inside it at least M0
+    (the first crossing, not a later one), and only that axis changes."""
+    cfg = TINY.with_(squeeze=True)
+    ev = su.make_event(cfg, None, wl.injection_extrinsics(cfg))
+    g = su.metric(ev.grid, ev.psd[0], cfg.inj_phys)
+    fr0 = su.frame(g, ph.phys_to_theta(cfg.inj_phys, ev.grid.f_low), cfg.match)
+    fr, factor = su.squeeze(fr0, ev.grid, ev.psd[0], cfg.inj_phys, cfg.match, ev.grid.f_low)
+    assert 0.0 < factor < 1.0
+    np.testing.assert_array_equal(fr.semi[:3], fr0.semi[:3])
+    assert fr.semi[3] == factor * fr0.semi[3]
+
+    def match_at(s):
+        x = np.zeros((1, 4))
+        x[0, 3] = s
+        ok, phys = su.physical_mask(fr0, x, ev.grid.f_low, np.inf)
+        return su.match_22(ev.grid, ev.psd[0], cfg.inj_phys, tuple(phys[0])) if ok[0] else None
+
+    tips = [match_at(sgn * factor) for sgn in (1.0, -1.0)]
+    assert any(t is not None and abs(t - cfg.match) < 1e-9 for t in tips)
+    for sgn in (1.0, -1.0):
+        for s in np.linspace(0.02, 0.999, 25) * factor:
+            m = match_at(sgn * s)
+            assert m is None or m >= cfg.match - 1e-12
+    art = su.startup(cfg, None, workers=1)
+    assert art.squeeze_factor == factor
+    assert np.all(np.sum(art.x_nodes ** 2, axis=1) <= 1.0)
