@@ -350,6 +350,80 @@ int32_t rbfl_mlp_adam(rbfl_mlp m, double lr, double beta1, double beta2, double 
 int32_t rbfl_mlp_get(rbfl_mlp m, int32_t what, float *out, size_t bytes);
 int32_t rbfl_mlp_destroy(rbfl_mlp m);
 
+/*
+ * Ensemble sampler on the GPU (Sec. II D: sampling in the Delta e
+ * coordinates of the ellipsoid; the paper drives a nested sampler on the CPU,
+ * this drives the online stage from device-resident walkers).  Parameters as
+ * rbfl_eval's 11 rows.  Sampled prior: uniform in Delta e within the unit
+ * ball and the physical region, alpha, psi, phi uniform (periods 2 pi, pi,
+ * 2 pi), dec with density cos(dec), iota with sin(iota), t_c uniform in
+ * [t_lo, t_hi], d_L with density d_L^d_exp in [d_lo, d_hi] (Table I; the
+ * paper's runs use d_exp = 0).  Moves: differential-evolution Metropolis
+ * (ter Braak 2006) over two halves of the ensemble: walker i of one half
+ * proposes X_i + g (X_j - X_k) with j != k from the other half, g = gamma
+ * (1 + 0.01 n), n standard normal, or g = 1 with probability p_jump; the
+ * angles wrap.  The proposal is symmetric, so a proposal is accepted with
+ * probability min(1, posterior ratio); a walker at zero posterior takes any
+ * proposal of non-zero posterior.  Random numbers: Philox4x32-10 (Salmon et
+ * al. 2011), key = seed, counter = (walker, step mod 2^32, step / 2^32 mod
+ * 2^31 | half << 31, call): call 0 gives the partner indices
+ * j = floor(u0 M), k = floor(u1 (M - 1)) (+1 if k >= j), call 1 the
+ * Box-Muller pair (u2, u3) of n, call 3 the jump draw u4, call 2 the
+ * acceptance uniform; u = ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53 from each
+ * pair of 32-bit words.  Walkers 0 .. M-1 move first, M .. 2M-1 second.
+ */
+#define RBFL_SAMPLER_PRIOR_ONLY 0x1u   /* ln L taken as 0: samples the prior (for checks) */
+typedef struct {
+  int32_t walkers;      /* W, even, 8 .. 2^30 */
+  int32_t form;         /* RBFL_FORM_* used for ln L (prepared) */
+  uint64_t seed;
+  double t_lo, t_hi;    /* t_c prior range [s] */
+  double d_lo, d_hi;    /* d_L prior range [Mpc], 0 < d_lo < d_hi */
+  double d_exp;         /* d_L prior density exponent (0: uniform, 2: uniform in volume) */
+  double gamma;         /* differential-evolution scale; 0 = 2.38 / sqrt(2 * 11) */
+  double p_jump;        /* probability of a g = 1 move, 0 .. 1 */
+  uint32_t flags;       /* RBFL_SAMPLER_* */
+} rbfl_sampler_spec;
+typedef struct rbfl_sampler_ctx *rbfl_sampler;
+
+/* Creates the walkers: from init (device FP64 [11][W], copied) or, if init is
+ * NULL, drawn from the prior (Delta e by rejection from the cube to the unit
+ * ball and the physical region, the rest by inverse transforms; Philox
+ * counter step 2^63 - 1, half 1), evaluates their ln L, and captures one
+ * sampler step (both halves) as a HIP graph over the handle's work space
+ * (reserved here for W/2 proposals, at most 2^20 per launch).  The handle
+ * must outlive the sampler and is not to be used on another stream while the
+ * sampler runs; while a sampler exists the handle refuses calls that would
+ * reallocate what the graph uses (rbfl_reserve beyond the reserved size,
+ * rbfl_surrogate_train: RBFL_E_STATE; preparing another form only adds
+ * buffers).  Synchronous on `stream`. */
+int32_t rbfl_sampler_create(rbfl_handle h, const rbfl_sampler_spec *spec, const double *init, void *stream,
+                            rbfl_sampler *out);
+
+/* Runs `steps` steps (graph replays) on `stream`, asynchronously.  Every
+ * `thin` steps the walkers' positions and ln L go to chain (device FP64
+ * [12][slots][W]: row m of sample (s, w) at m * slots * W + s * W + w, row 11
+ * = ln L; at most `slots` samples kept; chain may be NULL). */
+int32_t rbfl_sampler_run(rbfl_sampler s, int64_t steps, int32_t thin, double *chain, int64_t slots, void *stream);
+
+/* what = 0: walkers, host FP64 [12][W] (positions, ln L); 1: accepted moves
+ * per walker, host FP64 [W]; 2: host FP64 [2] = steps run, mean acceptance
+ * fraction.  Synchronises the sampler's last stream. */
+int32_t rbfl_sampler_query(rbfl_sampler s, int32_t what, double *out, size_t bytes);
+int32_t rbfl_sampler_destroy(rbfl_sampler s);
+
+/* Prior reweighting (Sec. III A: w = p_target / p_sampled) of n samples
+ * (device FP64, rows of stride ld: the 11 parameters): the sampled intrinsic
+ * prior is uniform in Delta e, the target uniform in (m1, m2, chi1, chi2)
+ * inside box = {m1_lo, m1_hi, m2_lo, m2_hi, chi1_lo, chi1_hi, chi2_lo,
+ * chi2_hi}, and the target distance density is d_L^d_exp times the sampled
+ * one: logw = log |det d(m1, m2, chi1, chi2) / d Delta e| + d_exp log d_L
+ * (central differences, steps 1e-7 |Theta|), -inf outside the box.  logw:
+ * device FP64 [n].  If n_eff is not NULL the call synchronises and stores
+ * (sum w)^2 / sum w^2 there. */
+int32_t rbfl_prior_weights(rbfl_handle h, const double *params, int64_t ld, int64_t n, const double box[8],
+                           double d_exp, double *logw, double *n_eff, void *stream);
+
 /* Releases the handle and its device memory (NULL is allowed). */
 int32_t rbfl_destroy(rbfl_handle h);
 

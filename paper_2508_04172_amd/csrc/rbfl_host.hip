@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "rbfl_internal.h"
+#include "sampler.h"
 
 namespace rbfl {
 
@@ -1195,6 +1196,7 @@ static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hi
 
 static void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
+  if (c.graph_users > 0) throw Error(RBFL_E_STATE, "the work space is captured by a sampler: it cannot grow");
   c.Y.alloc((size_t)n * c.Kp);
   c.Bt.alloc((size_t)c.rows * rows_ld(n));
   c.cap = n;
@@ -1436,6 +1438,7 @@ static void prepare(Ctx &c, int form) {
 }
 
 static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
+  if (c.graph_users > 0) throw Error(RBFL_E_STATE, "a sampler holds this handle's buffers: train before creating it");
   require(sp != nullptr, "spec is NULL");
   require(sp->hidden >= 8 && sp->hidden <= 1024, "hidden must be 8 .. 1024");
   require(sp->batch >= 1 && sp->batch <= 65536, "batch must be 1 .. 65536");
@@ -1755,6 +1758,186 @@ struct rbfl_mlp_ctx {
   rbfl::Mlp m;
 };
 
+struct rbfl_sampler_ctx {
+  rbfl::Ctx *c = nullptr;
+  rbfl_sampler_spec spec{};
+  rbfl::SamplerPrior prior{};
+  int W = 0, M = 0;
+  double gamma = 0.0;
+  rbfl::DevBuf<double> X, Y, lnl_x, lnl_y, lp_x;
+  rbfl::DevBuf<unsigned long long> acc;
+  rbfl::DevBuf<rbfl::SamplerState> st;
+  rbfl::SamplerState stage{};   // host copy staged for the next run
+  uint64_t steps = 0;
+  hipStream_t cap = nullptr, last = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~rbfl_sampler_ctx() {
+    if (c && exec) c->graph_users -= 1;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace rbfl {
+// One sampler step: for each half, proposals, their ln L through the online
+// stage (the handle's work space, reserved beforehand), the Metropolis
+// decisions; then the step counter.
+static void sampler_step(rbfl_sampler_ctx &S, hipStream_t s) {
+  const bool prior_only = S.spec.flags & RBFL_SAMPLER_PRIOR_ONLY;
+  for (int half = 0; half < 2; ++half) {
+    launch_de_propose(S.st.p, S.spec.seed, S.M, half, S.gamma, S.spec.p_jump, S.X.p, S.Y.p, s);
+    if (!prior_only) eval(*S.c, S.Y.p, S.M, S.lnl_y.p, S.spec.form, s);
+    launch_de_accept(S.c->consts.p, S.prior, S.st.p, S.spec.seed, S.M, half, prior_only ? 1 : 0, S.Y.p, S.lnl_y.p,
+                     S.X.p, S.lnl_x.p, S.lp_x.p, S.acc.p, s);
+  }
+  launch_step_advance(S.st.p, s);
+}
+
+static rbfl_sampler_ctx *sampler_create(Ctx &c, const rbfl_sampler_spec *sp, const double *init, hipStream_t s) {
+  require(sp != nullptr, "spec is NULL");
+  const rbfl_sampler_spec &p = *sp;
+  require(p.walkers >= 8 && p.walkers % 2 == 0 && p.walkers <= (1 << 30), "walkers must be even, 8 .. 2^30");
+  require(p.form >= 0 && p.form <= RBFL_FORM_SURROGATE, "unknown form");
+  require(c.prepared[p.form], "form not prepared (call rbfl_prepare)");
+  require(p.t_lo < p.t_hi && std::isfinite(p.t_lo) && std::isfinite(p.t_hi), "need t_lo < t_hi");
+  require(p.d_lo > 0.0 && p.d_lo < p.d_hi && std::isfinite(p.d_hi), "need 0 < d_lo < d_hi");
+  require(std::isfinite(p.d_exp) && p.d_exp > -1.0, "d_exp must be finite and > -1");
+  require(p.gamma >= 0.0 && std::isfinite(p.gamma), "gamma must be >= 0");
+  require(p.p_jump >= 0.0 && p.p_jump <= 1.0, "p_jump must be in 0 .. 1");
+  require((p.flags & ~RBFL_SAMPLER_PRIOR_ONLY) == 0, "unknown sampler flag bits");
+  std::unique_ptr<rbfl_sampler_ctx> S(new rbfl_sampler_ctx());
+  S->c = &c;
+  S->spec = p;
+  S->prior = SamplerPrior{p.t_lo, p.t_hi, p.d_lo, p.d_hi, p.d_exp};
+  S->W = p.walkers;
+  S->M = p.walkers / 2;
+  S->gamma = p.gamma > 0.0 ? p.gamma : 2.38 / sqrt(22.0);
+  const int64_t W = S->W, M = S->M;
+  S->X.alloc(11 * W);
+  S->Y.alloc(11 * M);
+  S->lnl_x.alloc(W);
+  S->lnl_y.alloc(M);
+  S->lp_x.alloc(W);
+  S->acc.alloc(W);
+  S->st.alloc(1);
+  RBFL_HIP(hipMemsetAsync(S->acc.p, 0, sizeof(unsigned long long) * W, s));
+  if (init) {
+    RBFL_HIP(hipMemcpyAsync(S->X.p, init, sizeof(double) * 11 * W, hipMemcpyDeviceToDevice, s));
+    launch_log_prior(c.consts.p, S->prior, S->X.p, S->W, S->lp_x.p, s);
+  } else {
+    launch_sampler_init(c.consts.p, S->prior, p.seed, S->W, S->X.p, S->lp_x.p, s);
+  }
+  const bool prior_only = p.flags & RBFL_SAMPLER_PRIOR_ONLY;
+  if (prior_only) {
+    launch_fill(S->lnl_x.p, W, 0.0, s);
+  } else {
+    reserve(c, std::min<int64_t>(std::max<int64_t>(M, 1), 1 << 20));
+    eval(c, S->X.p, W, S->lnl_x.p, p.form, s);
+  }
+  S->stage = SamplerState{0, 0, nullptr, 0, 1};
+  RBFL_HIP(hipMemcpyAsync(S->st.p, &S->stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  // capture one step (profiling off: no events inside the graph)
+  const bool prof = c.profile;
+  c.profile = false;
+  RBFL_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
+  RBFL_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    sampler_step(*S, S->cap);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(S->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c.profile = prof;
+    throw;
+  }
+  c.profile = prof;
+  RBFL_HIP(hipStreamEndCapture(S->cap, &S->graph));
+  RBFL_HIP(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
+  S->last = s;
+  c.graph_users += 1;
+  return S.release();
+}
+
+static void sampler_run(rbfl_sampler_ctx &S, int64_t steps, int thin, double *chain, int64_t slots, hipStream_t s) {
+  require(steps >= 0, "steps must be >= 0");
+  require(thin >= 1, "thin must be >= 1");
+  require(chain == nullptr || slots >= 1, "chain needs slots >= 1");
+  if (S.last && S.last != s) RBFL_HIP(hipStreamSynchronize(S.last));
+  // the staged state is read by an asynchronous copy: let the previous one finish
+  RBFL_HIP(hipStreamSynchronize(s));
+  S.stage = SamplerState{S.steps, S.steps, chain, chain ? slots : 0, thin};
+  RBFL_HIP(hipMemcpyAsync(S.st.p, &S.stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
+  for (int64_t i = 0; i < steps; ++i) RBFL_HIP(hipGraphLaunch(S.exec, s));
+  S.steps += (uint64_t)steps;
+  S.last = s;
+}
+
+static void sampler_query(rbfl_sampler_ctx &S, int what, double *out, size_t bytes) {
+  require(out != nullptr, "out is NULL");
+  if (S.last) RBFL_HIP(hipStreamSynchronize(S.last));
+  const size_t W = (size_t)S.W;
+  switch (what) {
+    case 0: {
+      require(bytes >= sizeof(double) * 12 * W, "buffer too small");
+      RBFL_HIP(hipMemcpy(out, S.X.p, sizeof(double) * 11 * W, hipMemcpyDeviceToHost));
+      RBFL_HIP(hipMemcpy(out + 11 * W, S.lnl_x.p, sizeof(double) * W, hipMemcpyDeviceToHost));
+      return;
+    }
+    case 1:
+    case 2: {
+      std::vector<unsigned long long> a(W);
+      RBFL_HIP(hipMemcpy(a.data(), S.acc.p, sizeof(unsigned long long) * W, hipMemcpyDeviceToHost));
+      if (what == 1) {
+        require(bytes >= sizeof(double) * W, "buffer too small");
+        for (size_t i = 0; i < W; ++i) out[i] = (double)a[i];
+      } else {
+        require(bytes >= sizeof(double) * 2, "buffer too small");
+        double tot = 0.0;
+        for (auto v : a) tot += (double)v;
+        out[0] = (double)S.steps;
+        out[1] = S.steps ? tot / ((double)S.steps * (double)W) : 0.0;
+      }
+      return;
+    }
+    default:
+      throw Error(RBFL_E_INVALID_ARG, "unknown sampler query");
+  }
+}
+
+static void prior_weights(Ctx &c, const double *params, int64_t ld, int64_t n, const double box[8], double d_exp,
+                          double *logw, double *n_eff, hipStream_t s) {
+  require(params != nullptr && logw != nullptr && box != nullptr, "NULL argument");
+  require(n >= 0 && ld >= n, "need 0 <= n <= ld");
+  require(std::isfinite(d_exp), "d_exp must be finite");
+  PriorBox b;
+  for (int d = 0; d < 4; ++d) {
+    b.lo[d] = box[2 * d];
+    b.hi[d] = box[2 * d + 1];
+    require(b.lo[d] <= b.hi[d], "box bounds must satisfy lo <= hi");
+  }
+  b.d_exp = d_exp;
+  launch_prior_weights(c.consts.p, params, ld, n, b, logw, s);
+  if (n_eff) {
+    std::vector<double> w((size_t)n);
+    RBFL_HIP(hipMemcpyAsync(w.data(), logw, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    double mx = -std::numeric_limits<double>::infinity();
+    for (double v : w) mx = std::max(mx, v);
+    Sum s1, s2;
+    if (std::isfinite(mx))
+      for (double v : w) {
+        const double e = exp(v - mx);
+        s1.add(e);
+        s2.add(e * e);
+      }
+    *n_eff = s2.value() > 0.0 ? s1.value() * s1.value() / s2.value() : 0.0;
+  }
+}
+}  // namespace rbfl
+
 namespace rbfl {
 static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t *counts, const double *params,
                                   double *lnl, uint32_t flags, hipStream_t s) {
@@ -2020,6 +2203,44 @@ int32_t rbfl_mlp_get(rbfl_mlp m, int32_t what, float *out, size_t bytes) {
 
 int32_t rbfl_mlp_destroy(rbfl_mlp m) {
   return rbfl::guarded([&] { delete m; });
+}
+
+int32_t rbfl_sampler_create(rbfl_handle h, const rbfl_sampler_spec *spec, const double *init, void *stream,
+                            rbfl_sampler *out) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr && out != nullptr, "NULL argument");
+    *out = nullptr;
+    *out = rbfl::sampler_create(h->c, spec, init, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_sampler_run(rbfl_sampler s, int64_t steps, int32_t thin, double *chain, int64_t slots, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(s != nullptr, "sampler is NULL");
+    rbfl::sampler_run(*s, steps, thin, chain, slots, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_sampler_query(rbfl_sampler s, int32_t what, double *out, size_t bytes) {
+  return rbfl::guarded([&] {
+    rbfl::require(s != nullptr, "sampler is NULL");
+    rbfl::sampler_query(*s, what, out, bytes);
+  });
+}
+
+int32_t rbfl_sampler_destroy(rbfl_sampler s) {
+  return rbfl::guarded([&] {
+    if (s && s->last) (void)hipStreamSynchronize(s->last);
+    delete s;
+  });
+}
+
+int32_t rbfl_prior_weights(rbfl_handle h, const double *params, int64_t ld, int64_t n, const double box[8],
+                           double d_exp, double *logw, double *n_eff, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::prior_weights(h->c, params, ld, n, box, d_exp, logw, n_eff, reinterpret_cast<hipStream_t>(stream));
+  });
 }
 
 int32_t rbfl_destroy(rbfl_handle h) {

@@ -147,6 +147,7 @@ struct Ctx {
   DevBuf<double> Y;            // [cap][Kp]
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
   int64_t cap = 0;
+  int graph_users = 0;         // live samplers whose captured step uses Y / Bt / the weight copies
   EvalConsts host_consts;
   // surrogate (rbfl_surrogate_train)
   Mlp *sur = nullptr;

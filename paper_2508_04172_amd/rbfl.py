@@ -33,7 +33,9 @@ EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "
             "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
-            "rbfl_mlp_destroy", "rbfl_destroy")
+            "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_query",
+            "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_destroy")
+SAMPLER_PRIOR_ONLY = 0x1
 PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
 
 
@@ -67,6 +69,22 @@ class BuildSpec(C.Structure):
         ("chi_max", C.c_double),
         ("flags", C.c_uint32),
         ("f_ref", C.c_double),
+    ]
+
+
+class SamplerSpec(C.Structure):
+    _fields_ = [
+        ("walkers", C.c_int32),
+        ("form", C.c_int32),
+        ("seed", C.c_uint64),
+        ("t_lo", C.c_double),
+        ("t_hi", C.c_double),
+        ("d_lo", C.c_double),
+        ("d_hi", C.c_double),
+        ("d_exp", C.c_double),
+        ("gamma", C.c_double),
+        ("p_jump", C.c_double),
+        ("flags", C.c_uint32),
     ]
 
 
@@ -167,6 +185,18 @@ def load(path: str = LIB_PATH):
     lib.rbfl_mlp_get.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
     lib.rbfl_mlp_destroy.restype = C.c_int32
     lib.rbfl_mlp_destroy.argtypes = [C.c_void_p]
+    lib.rbfl_sampler_create.restype = C.c_int32
+    lib.rbfl_sampler_create.argtypes = [C.c_void_p, C.POINTER(SamplerSpec), C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_void_p)]
+    lib.rbfl_sampler_run.restype = C.c_int32
+    lib.rbfl_sampler_run.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]
+    lib.rbfl_sampler_query.restype = C.c_int32
+    lib.rbfl_sampler_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.rbfl_sampler_destroy.restype = C.c_int32
+    lib.rbfl_sampler_destroy.argtypes = [C.c_void_p]
+    lib.rbfl_prior_weights.restype = C.c_int32
+    lib.rbfl_prior_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                                       C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
     lib.rbfl_destroy.restype = C.c_int32
     lib.rbfl_destroy.argtypes = [C.c_void_p]
     _lib = lib
@@ -459,6 +489,63 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+class Sampler:
+    """Ensemble sampler driving a handle's online stage (rbfl_sampler_*)."""
+
+    def __init__(self, handle: "Handle", walkers: int, t_range, d_range, seed: int = 1, form: int = FORM_FP64,
+                 d_exp: float = 0.0, gamma: float = 0.0, p_jump: float = 0.1, prior_only: bool = False,
+                 init_ptr: int = 0, stream: int = 0):
+        spec = SamplerSpec(walkers=walkers, form=form, seed=seed, t_lo=t_range[0], t_hi=t_range[1],
+                           d_lo=d_range[0], d_hi=d_range[1], d_exp=d_exp, gamma=gamma, p_jump=p_jump,
+                           flags=SAMPLER_PRIOR_ONLY if prior_only else 0)
+        self.walkers = walkers
+        self._handle = handle          # the handle must outlive the sampler
+        self._s = C.c_void_p()
+        _check(load().rbfl_sampler_create(handle.ptr, C.byref(spec), C.c_void_p(init_ptr or None),
+                                          C.c_void_p(stream), C.byref(self._s)))
+
+    def run(self, steps: int, thin: int = 1, chain_ptr: int = 0, slots: int = 0, stream: int = 0):
+        _check(load().rbfl_sampler_run(self._s, steps, thin, C.c_void_p(chain_ptr or None), slots,
+                                       C.c_void_p(stream)))
+
+    def walkers_state(self) -> np.ndarray:
+        out = np.empty((12, self.walkers))
+        _check(load().rbfl_sampler_query(self._s, 0, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def accepted(self) -> np.ndarray:
+        out = np.empty(self.walkers)
+        _check(load().rbfl_sampler_query(self._s, 1, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def stats(self) -> tuple:
+        out = np.empty(2)
+        _check(load().rbfl_sampler_query(self._s, 2, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return int(out[0]), float(out[1])
+
+    def close(self):
+        if self._s is not None and self._s.value:
+            _check(load().rbfl_sampler_destroy(self._s))
+        self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def prior_weights(handle: "Handle", params_ptr: int, ld: int, n: int, box, d_exp: float, logw_ptr: int,
+                  stream: int = 0, want_n_eff: bool = True):
+    """Log importance weights to a prior uniform in (m1, m2, chi1, chi2) within
+    box (rbfl_prior_weights); returns N_eff when asked."""
+    b = (C.c_double * 8)(*[float(v) for v in box])
+    ne = C.c_double(0.0)
+    _check(load().rbfl_prior_weights(handle.ptr, C.c_void_p(params_ptr), ld, n, b, d_exp, C.c_void_p(logw_ptr),
+                                     C.byref(ne) if want_n_eff else None, C.c_void_p(stream)))
+    return ne.value if want_n_eff else None
 
 
 def eval_ragged(handles, counts, params_ptr: int, lnl_ptr: int, stream: int = 0):
