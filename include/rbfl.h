@@ -363,8 +363,9 @@ int32_t rbfl_mlp_destroy(rbfl_mlp m);
  * proposes X_i + g (X_j - X_k) with j != k from the other half, g = gamma
  * (1 + 0.01 n), n standard normal, or g = 1 with probability p_jump; the
  * angles wrap.  The proposal is symmetric, so a proposal is accepted with
- * probability min(1, posterior ratio); a walker at zero posterior takes any
- * proposal of non-zero posterior.  Random numbers: Philox4x32-10 (Salmon et
+ * probability min(1, posterior ratio) (with ln L weighted by beta during an
+ * annealed start); a walker at zero posterior takes any proposal of non-zero
+ * posterior.  Random numbers: Philox4x32-10 (Salmon et
  * al. 2011), key = seed, counter = (walker, step mod 2^32, step / 2^32 mod
  * 2^31 | half << 31, call): call 0 gives the partner indices
  * j = floor(u0 M), k = floor(u1 (M - 1)) (+1 if k >= j), call 1 the
@@ -383,6 +384,9 @@ typedef struct {
   double gamma;         /* differential-evolution scale; 0 = 2.38 / sqrt(2 * 11) */
   double p_jump;        /* probability of a g = 1 move, 0 .. 1 */
   uint32_t flags;       /* RBFL_SAMPLER_* */
+  int64_t anneal_steps; /* steps 0 .. anneal_steps-1 accept with ln L weighted by
+                           beta = beta0^(1 - step / anneal_steps) (a tempered start from the prior) */
+  double beta0;         /* first annealing weight, (0, 1] (unused without annealing) */
 } rbfl_sampler_spec;
 typedef struct rbfl_sampler_ctx *rbfl_sampler;
 
@@ -405,6 +409,21 @@ int32_t rbfl_sampler_create(rbfl_handle h, const rbfl_sampler_spec *spec, const 
  * [12][slots][W]: row m of sample (s, w) at m * slots * W + s * W + w, row 11
  * = ln L; at most `slots` samples kept; chain may be NULL). */
 int32_t rbfl_sampler_run(rbfl_sampler s, int64_t steps, int32_t thin, double *chain, int64_t slots, void *stream);
+
+/* Tempered sequential Monte Carlo start (Del Moral, Doucet and Jasra 2006)
+ * from the current walkers, taken as prior draws (ln L weight beta = 0):
+ * per stage, the increment db in (0, 1 - beta] for which the weights
+ * w = L^db keep an effective sample size ess_frac W (all of the remainder if
+ * it stays above that), found by 60 bisection halvings; log Z += log mean w
+ * (the evidence of the likelihood ratio relative to the prior); systematic
+ * resampling at positions (u + i) / W with u the first uniform of Philox call
+ * 4 of (walker 2^32 - 1, step = index of the stage over the sampler's life,
+ * half 1); then `moves` sampler steps with ln L weighted by the new beta.
+ * Stops at beta = 1 or after max_stages; later rbfl_sampler_run steps keep
+ * the final beta.  Synchronous on `stream`; log_evidence, stages and beta
+ * (host, optional) receive the results. */
+int32_t rbfl_sampler_smc(rbfl_sampler s, double ess_frac, int32_t moves, int32_t max_stages, void *stream,
+                         double *log_evidence, int32_t *stages, double *beta);
 
 /* what = 0: walkers, host FP64 [12][W] (positions, ln L); 1: accepted moves
  * per walker, host FP64 [W]; 2: host FP64 [2] = steps run, mean acceptance

@@ -16,7 +16,8 @@ over the two halves of the ensemble: walker i of a half proposes
 Y = X_i + g (X_j - X_k), j != k from the other half, g = gamma (1 + 0.01 n)
 or 1 with probability p_jump; the angles alpha, psi, phi wrap (periods 2 pi,
 pi, 2 pi, differences taken the shorter way round).  Accept with probability
-min(1, posterior ratio).
+min(1, posterior ratio), ln L weighted by beta = beta0^(1 - step / anneal)
+during an annealed start.
 """
 from __future__ import annotations
 
@@ -136,9 +137,11 @@ def init_walkers(frame, f0: float, chi_max: float, prior: Prior, seed: int, W: i
     return X
 
 
-def de_half_step(X, lnl_x, lp_x, seed: int, step: int, half: int, gamma: float, p_jump: float, lnl_fn, lp_fn):
+def de_half_step(X, lnl_x, lp_x, seed: int, step: int, half: int, gamma: float, p_jump: float, lnl_fn, lp_fn,
+                 beta: float = 1.0):
     """One half-step in place.  X: [11][W]; lnl_fn / lp_fn map proposals
-    [11][M] to ln L / log prior.  Returns (proposals, accepted mask)."""
+    [11][M] to ln L / log prior; beta weights ln L in the acceptance (an
+    annealed start).  Returns (proposals, accepted mask)."""
     W = X.shape[1]
     M = W // 2
     gi = half * M + np.arange(M)
@@ -168,11 +171,16 @@ def de_half_step(X, lnl_x, lp_x, seed: int, step: int, half: int, gamma: float, 
     cur = lnl_x[gi] + lp_x[gi]
     prop = ly + lpy
     with np.errstate(invalid="ignore"):
-        take = np.isfinite(prop) & (~np.isfinite(cur) | (np.log(ua) < prop - cur))
+        ratio = beta * (ly - lnl_x[gi]) + (lpy - lp_x[gi])
+        take = np.isfinite(prop) & (~np.isfinite(cur) | (np.log(ua) < ratio))
     X[:, gi[take]] = Y[:, take]
     lnl_x[gi[take]] = ly[take]
     lp_x[gi[take]] = lpy[take]
     return Y, take
+
+
+def anneal_beta(step: int, anneal_steps: int, beta0: float) -> float:
+    return beta0 ** (1.0 - step / anneal_steps) if step < anneal_steps else 1.0
 
 
 def log_prior_weights(frame, f0: float, params: np.ndarray, box, d_exp: float) -> np.ndarray:
@@ -201,3 +209,42 @@ def log_prior_weights(frame, f0: float, params: np.ndarray, box, d_exp: float) -
             J[:, m] = np.imag(np.array(q[:4])) / h                 # d phys / d Theta_m
         out[i] = math.log(abs(np.linalg.det(J))) + d_exp * math.log(params[10, i])
     return out
+
+
+def smc_stage(lnl: np.ndarray, beta: float, ess_frac: float, seed: int, stage: int):
+    """One stage of the tempered sequential Monte Carlo start (Del Moral,
+    Doucet and Jasra 2006): the increment db in (0, 1 - beta] that brings
+    the effective sample size of the weights w = L^db to ess_frac W (the
+    whole remainder if it stays above), found by bisection (60 halvings);
+    the log evidence increment log mean w; and systematic resampling
+    indices, position (u + i) / W with u from Philox (walker 2^32 - 1, step
+    = stage, half 1, call 4).  Walkers with ln L = -inf get weight 0."""
+    W = lnl.size
+    fin = np.isfinite(lnl)
+    m = np.max(lnl[fin])
+    d = np.where(fin, lnl - m, -np.inf)
+
+    def ess(db):
+        w = np.exp(db * d)
+        return math.fsum(w) ** 2 / math.fsum(w * w)
+
+    rem = 1.0 - beta
+    if ess(rem) >= ess_frac * W:
+        db = rem
+    else:
+        lo, hi = 0.0, rem
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if ess(mid) >= ess_frac * W:
+                lo = mid
+            else:
+                hi = mid
+        db = lo
+    w = np.exp(db * d)
+    logz = db * m + math.log(math.fsum(w) / W)
+    c = np.cumsum(w)
+    c /= c[-1]
+    u, _ = uniform_pair(seed, [0xFFFFFFFF], stage, 1, 4)
+    pos = (u[0] + np.arange(W)) / W
+    idx = np.minimum(np.searchsorted(c, pos, side="right"), W - 1)
+    return db, idx, logz

@@ -1769,6 +1769,8 @@ struct rbfl_sampler_ctx {
   rbfl::DevBuf<rbfl::SamplerState> st;
   rbfl::SamplerState stage{};   // host copy staged for the next run
   uint64_t steps = 0;
+  double beta_fixed = -1.0;     // ln L weight after a tempered SMC start (1), -1 = the spec's schedule
+  uint32_t smc_stages = 0;      // stages run so far (the resampling draws' counter)
   hipStream_t cap = nullptr, last = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1807,6 +1809,8 @@ static rbfl_sampler_ctx *sampler_create(Ctx &c, const rbfl_sampler_spec *sp, con
   require(p.gamma >= 0.0 && std::isfinite(p.gamma), "gamma must be >= 0");
   require(p.p_jump >= 0.0 && p.p_jump <= 1.0, "p_jump must be in 0 .. 1");
   require((p.flags & ~RBFL_SAMPLER_PRIOR_ONLY) == 0, "unknown sampler flag bits");
+  require(p.anneal_steps >= 0, "anneal_steps must be >= 0");
+  require(p.anneal_steps == 0 || (p.beta0 > 0.0 && p.beta0 <= 1.0), "beta0 must be in (0, 1]");
   std::unique_ptr<rbfl_sampler_ctx> S(new rbfl_sampler_ctx());
   S->c = &c;
   S->spec = p;
@@ -1836,7 +1840,7 @@ static rbfl_sampler_ctx *sampler_create(Ctx &c, const rbfl_sampler_spec *sp, con
     reserve(c, std::min<int64_t>(std::max<int64_t>(M, 1), 1 << 20));
     eval(c, S->X.p, W, S->lnl_x.p, p.form, s);
   }
-  S->stage = SamplerState{0, 0, nullptr, 0, 1};
+  S->stage = SamplerState{0, 0, nullptr, 0, 1, (uint64_t)p.anneal_steps, p.beta0, -1.0};
   RBFL_HIP(hipMemcpyAsync(S->st.p, &S->stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
   RBFL_HIP(hipStreamSynchronize(s));
   // capture one step (profiling off: no events inside the graph)
@@ -1868,11 +1872,100 @@ static void sampler_run(rbfl_sampler_ctx &S, int64_t steps, int thin, double *ch
   if (S.last && S.last != s) RBFL_HIP(hipStreamSynchronize(S.last));
   // the staged state is read by an asynchronous copy: let the previous one finish
   RBFL_HIP(hipStreamSynchronize(s));
-  S.stage = SamplerState{S.steps, S.steps, chain, chain ? slots : 0, thin};
+  S.stage = SamplerState{S.steps, S.steps, chain, chain ? slots : 0, thin, (uint64_t)S.spec.anneal_steps,
+                         S.spec.beta0, S.beta_fixed};
   RBFL_HIP(hipMemcpyAsync(S.st.p, &S.stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
   for (int64_t i = 0; i < steps; ++i) RBFL_HIP(hipGraphLaunch(S.exec, s));
   S.steps += (uint64_t)steps;
   S.last = s;
+}
+
+// Tempered sequential Monte Carlo from the current walkers (Del Moral, Doucet
+// and Jasra 2006), taking them as prior draws (weight beta = 0): per stage
+// the increment db in (0, 1 - beta] whose weights w = L^db keep an effective
+// sample size of ess_frac W (the whole remainder when that stays above),
+// found by 60 bisection halvings; ln Z += log mean w; systematic resampling
+// at positions (u + i) / W, u = Philox(walker 2^32 - 1, step = stage index,
+// half 1, call 4); then `moves` sampler steps at the new beta.
+static void sampler_smc(rbfl_sampler_ctx &S, double ess_frac, int moves, int max_stages, hipStream_t s,
+                        double *log_z, int32_t *stages_out, double *beta_out) {
+  require(!(S.spec.flags & RBFL_SAMPLER_PRIOR_ONLY), "a prior-only sampler has no likelihood to temper");
+  require(ess_frac > 0.0 && ess_frac < 1.0, "ess_frac must be in (0, 1)");
+  require(moves >= 1 && max_stages >= 1, "moves and max_stages must be >= 1");
+  if (S.last && S.last != s) RBFL_HIP(hipStreamSynchronize(S.last));
+  const int W = S.W;
+  std::vector<double> l(W), w(W), cum(W);
+  std::vector<int32_t> idx(W);
+  DevBuf<int32_t> d_idx;
+  d_idx.alloc(W);
+  DevBuf<double> Xt, lt, pt;
+  Xt.alloc((size_t)11 * W);
+  lt.alloc(W);
+  pt.alloc(W);
+  double beta = 0.0, lz = 0.0;
+  int st = 0;
+  for (; st < max_stages && beta < 1.0; ++st) {
+    RBFL_HIP(hipMemcpyAsync(l.data(), S.lnl_x.p, sizeof(double) * W, hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    double m = -std::numeric_limits<double>::infinity();
+    for (double v : l)
+      if (std::isfinite(v)) m = std::max(m, v);
+    require(std::isfinite(m), "no walker has a finite ln L");
+    auto ess = [&](double db) {
+      Sum s1, s2;
+      for (int i = 0; i < W; ++i) {
+        const double e = std::isfinite(l[i]) ? exp(db * (l[i] - m)) : 0.0;
+        s1.add(e);
+        s2.add(e * e);
+      }
+      return s1.value() * s1.value() / s2.value();
+    };
+    const double rem = 1.0 - beta;
+    double db = rem;
+    if (ess(rem) < ess_frac * W) {
+      double lo = 0.0, hi = rem;
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (ess(mid) >= ess_frac * W)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      db = lo;
+    }
+    double c = 0.0;
+    Sum tot;
+    for (int i = 0; i < W; ++i) {
+      w[i] = std::isfinite(l[i]) ? exp(db * (l[i] - m)) : 0.0;
+      c += w[i];
+      cum[i] = c;
+      tot.add(w[i]);
+    }
+    lz += db * m + log(tot.value() / W);
+    for (int i = 0; i < W; ++i) cum[i] /= c;
+    double u = 0.0, unused = 0.0;
+    philox_pair(S.spec.seed, 0xFFFFFFFFu, S.smc_stages, 1, 4, &u, &unused);
+    int j = 0;
+    for (int i = 0; i < W; ++i) {
+      const double pos = (u + (double)i) / (double)W;
+      while (j < W - 1 && cum[j] <= pos) ++j;
+      idx[i] = j;
+    }
+    RBFL_HIP(hipMemcpyAsync(d_idx.p, idx.data(), sizeof(int32_t) * W, hipMemcpyHostToDevice, s));
+    launch_gather_walkers(S.X.p, S.lnl_x.p, S.lp_x.p, d_idx.p, W, Xt.p, lt.p, pt.p, s);
+    RBFL_HIP(hipMemcpyAsync(S.X.p, Xt.p, sizeof(double) * 11 * W, hipMemcpyDeviceToDevice, s));
+    RBFL_HIP(hipMemcpyAsync(S.lnl_x.p, lt.p, sizeof(double) * W, hipMemcpyDeviceToDevice, s));
+    RBFL_HIP(hipMemcpyAsync(S.lp_x.p, pt.p, sizeof(double) * W, hipMemcpyDeviceToDevice, s));
+    beta = std::min(1.0, beta + db);
+    if (rem - db <= 0.0) beta = 1.0;
+    S.smc_stages += 1;
+    S.beta_fixed = beta;
+    sampler_run(S, moves, 1, nullptr, 0, s);
+  }
+  RBFL_HIP(hipStreamSynchronize(s));
+  if (log_z) *log_z = lz;
+  if (stages_out) *stages_out = st;
+  if (beta_out) *beta_out = beta;
 }
 
 static void sampler_query(rbfl_sampler_ctx &S, int what, double *out, size_t bytes) {
@@ -2218,6 +2311,15 @@ int32_t rbfl_sampler_run(rbfl_sampler s, int64_t steps, int32_t thin, double *ch
   return rbfl::guarded([&] {
     rbfl::require(s != nullptr, "sampler is NULL");
     rbfl::sampler_run(*s, steps, thin, chain, slots, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_sampler_smc(rbfl_sampler s, double ess_frac, int32_t moves, int32_t max_stages, void *stream,
+                         double *log_evidence, int32_t *stages, double *beta) {
+  return rbfl::guarded([&] {
+    rbfl::require(s != nullptr, "sampler is NULL");
+    rbfl::sampler_smc(*s, ess_frac, moves, max_stages, reinterpret_cast<hipStream_t>(stream), log_evidence, stages,
+                      beta);
   });
 }
 

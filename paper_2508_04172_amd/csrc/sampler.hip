@@ -17,49 +17,20 @@ namespace {
 
 constexpr int kSBlock = 256;
 
-// One Philox4x32-10 block: 10 rounds of two 32x32 -> 64-bit products with
-// the multipliers 0xD2511F53 and 0xCD9E8D57, key bumped by the Weyl
-// constants 0x9E3779B9 and 0xBB67AE85 between rounds.
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-// Uniform in (0, 1) from two 32-bit words: 53 bits, offset by half an ulp.
-__device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
-  const uint64_t m = ((uint64_t)(a >> 5) << 26) | (uint64_t)(b >> 6);
-  return ((double)m + 0.5) * 0x1p-53;
-}
-
-// Two uniforms from call t of a walker's counter for (step, half).
+// Two uniforms of call t of a walker's counter for (step, half).
 struct Draw {
-  uint32_t key0, key1, ctr0, ctr1, ctr2;
-  __device__ void pair(uint32_t t, double *u0, double *u1) const {
-    uint32_t c[4] = {ctr0, ctr1, ctr2, t};
-    philox(c, key0, key1);
-    *u0 = u01(c[0], c[1]);
-    *u1 = u01(c[2], c[3]);
-  }
+  uint64_t seed, step;
+  uint32_t walker;
+  int half;
+  __device__ void pair(uint32_t t, double *u0, double *u1) const { philox_pair(seed, walker, step, half, t, u0, u1); }
 };
 
 __device__ __forceinline__ Draw make_draw(uint64_t seed, uint32_t walker, uint64_t step, int half) {
   Draw d;
-  d.key0 = (uint32_t)seed;
-  d.key1 = (uint32_t)(seed >> 32);
-  d.ctr0 = walker;
-  d.ctr1 = (uint32_t)step;
-  d.ctr2 = (uint32_t)(step >> 32) & 0x7FFFFFFFu;
-  d.ctr2 |= (uint32_t)half << 31;
+  d.seed = seed;
+  d.step = step;
+  d.walker = walker;
+  d.half = half;
   return d;
 }
 
@@ -181,8 +152,9 @@ __global__ void __launch_bounds__(kSBlock) k_de_propose(const SamplerState *__re
   }
 }
 
-// Metropolis decision for one half (call 2 of the walker's counter); on the
-// second half also the chain sample of the completed step.
+// Metropolis decision for one half (call 2 of the walker's counter), with ln L
+// weighted by the annealing factor beta of the step; on the second half also
+// the chain sample of the completed step.
 __global__ void __launch_bounds__(kSBlock) k_de_accept(const EvalConsts *__restrict__ cp, SamplerPrior pr,
                                                        const SamplerState *__restrict__ st, uint64_t seed, int M,
                                                        int half, int prior_only, const double *__restrict__ Y,
@@ -202,10 +174,20 @@ __global__ void __launch_bounds__(kSBlock) k_de_accept(const EvalConsts *__restr
   const Draw dr = make_draw(seed, (uint32_t)gi, st->step, half);
   double u, unused;
   dr.pair(2, &u, &unused);
-  const double cur = lnl_x[gi] + lp_x[gi];
-  const double prop = ly + lpy;
+  const double lx = lnl_x[gi], lpx = lp_x[gi];
+  const double ninf = -__builtin_huge_val();
   bool take = false;
-  if (prop > -__builtin_huge_val()) take = !(cur > -__builtin_huge_val()) || log(u) < prop - cur;
+  if (ly + lpy > ninf) {
+    if (!(lx + lpx > ninf)) {
+      take = true;   // a walker at zero posterior takes any proposal of non-zero posterior
+    } else {
+      const double beta = st->beta_fixed >= 0.0 ? st->beta_fixed
+                          : st->step < st->anneal_steps
+                              ? pow(st->beta0, 1.0 - (double)st->step / (double)st->anneal_steps)
+                              : 1.0;
+      take = log(u) < beta * (ly - lx) + (lpy - lpx);
+    }
+  }
   if (take) {
     for (int m = 0; m < 11; ++m) X[(int64_t)m * W + gi] = p[m];
     lnl_x[gi] = ly;
@@ -228,6 +210,21 @@ __global__ void __launch_bounds__(kSBlock) k_de_accept(const EvalConsts *__restr
       }
     }
   }
+}
+
+// Walker w of the resampled ensemble is walker idx[w] of the current one.
+__global__ void __launch_bounds__(kSBlock) k_gather_walkers(const double *__restrict__ X,
+                                                            const double *__restrict__ lnl,
+                                                            const double *__restrict__ lp,
+                                                            const int32_t *__restrict__ idx, int W,
+                                                            double *__restrict__ Xo, double *__restrict__ lnlo,
+                                                            double *__restrict__ lpo) {
+  const int w = blockIdx.x * kSBlock + threadIdx.x;
+  if (w >= W) return;
+  const int src = idx[w];
+  for (int m = 0; m < 11; ++m) Xo[(int64_t)m * W + w] = X[(int64_t)m * W + src];
+  lnlo[w] = lnl[src];
+  lpo[w] = lp[src];
 }
 
 __global__ void k_step_advance(SamplerState *st) {
@@ -343,6 +340,13 @@ void launch_de_accept(const EvalConsts *c, const SamplerPrior &pr, const Sampler
 
 void launch_step_advance(SamplerState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, st);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_gather_walkers(const double *X, const double *lnl, const double *lp, const int32_t *idx, int W,
+                           double *Xo, double *lnlo, double *lpo, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_walkers, dim3((W + kSBlock - 1) / kSBlock), dim3(kSBlock), 0, s, X, lnl, lp, idx, W, Xo,
+                     lnlo, lpo);
   RBFL_HIP(hipGetLastError());
 }
 

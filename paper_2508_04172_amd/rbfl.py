@@ -33,7 +33,7 @@ EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "
             "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
-            "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_query",
+            "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
             "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_destroy")
 SAMPLER_PRIOR_ONLY = 0x1
 PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
@@ -85,6 +85,8 @@ class SamplerSpec(C.Structure):
         ("gamma", C.c_double),
         ("p_jump", C.c_double),
         ("flags", C.c_uint32),
+        ("anneal_steps", C.c_int64),
+        ("beta0", C.c_double),
     ]
 
 
@@ -190,6 +192,9 @@ def load(path: str = LIB_PATH):
                                         C.POINTER(C.c_void_p)]
     lib.rbfl_sampler_run.restype = C.c_int32
     lib.rbfl_sampler_run.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]
+    lib.rbfl_sampler_smc.restype = C.c_int32
+    lib.rbfl_sampler_smc.argtypes = [C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.rbfl_sampler_query.restype = C.c_int32
     lib.rbfl_sampler_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
     lib.rbfl_sampler_destroy.restype = C.c_int32
@@ -496,10 +501,11 @@ class Sampler:
 
     def __init__(self, handle: "Handle", walkers: int, t_range, d_range, seed: int = 1, form: int = FORM_FP64,
                  d_exp: float = 0.0, gamma: float = 0.0, p_jump: float = 0.1, prior_only: bool = False,
-                 init_ptr: int = 0, stream: int = 0):
+                 init_ptr: int = 0, anneal_steps: int = 0, beta0: float = 1.0, stream: int = 0):
         spec = SamplerSpec(walkers=walkers, form=form, seed=seed, t_lo=t_range[0], t_hi=t_range[1],
                            d_lo=d_range[0], d_hi=d_range[1], d_exp=d_exp, gamma=gamma, p_jump=p_jump,
-                           flags=SAMPLER_PRIOR_ONLY if prior_only else 0)
+                           flags=SAMPLER_PRIOR_ONLY if prior_only else 0, anneal_steps=anneal_steps,
+                           beta0=beta0)
         self.walkers = walkers
         self._handle = handle          # the handle must outlive the sampler
         self._s = C.c_void_p()
@@ -509,6 +515,13 @@ class Sampler:
     def run(self, steps: int, thin: int = 1, chain_ptr: int = 0, slots: int = 0, stream: int = 0):
         _check(load().rbfl_sampler_run(self._s, steps, thin, C.c_void_p(chain_ptr or None), slots,
                                        C.c_void_p(stream)))
+
+    def smc(self, ess_frac: float = 0.5, moves: int = 10, max_stages: int = 200, stream: int = 0):
+        """Tempered SMC start; returns (log evidence, stages, final beta)."""
+        lz, st, b = C.c_double(0.0), C.c_int32(0), C.c_double(0.0)
+        _check(load().rbfl_sampler_smc(self._s, ess_frac, moves, max_stages, C.c_void_p(stream), C.byref(lz),
+                                       C.byref(st), C.byref(b)))
+        return lz.value, st.value, b.value
 
     def walkers_state(self) -> np.ndarray:
         out = np.empty((12, self.walkers))

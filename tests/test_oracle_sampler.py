@@ -113,3 +113,26 @@ def test_log_prior_closed_form(frame_tiny):
     lp = sm.log_prior(fr, cfg.f_low, cfg.chi_max, prior, P)
     assert lp[0] == pytest.approx(math.log(math.cos(0.3)) + math.log(math.sin(1.1)) + 2 * math.log(15.0))
     assert lp[1] == -np.inf and lp[2] == -np.inf
+
+
+def test_smc_stage_effective_size_and_systematic_resampling():
+    """The chosen increment gives the target effective sample size; every
+    walker is copied floor or ceil of W w_i / sum w times (systematic
+    resampling); a constant ln L takes the whole remaining step at once and
+    adds exactly that constant times the step to log Z."""
+    rng = np.random.default_rng(8)
+    W = 4000
+    lnl = rng.normal(0.0, 30.0, W)
+    lnl[:5] = -np.inf
+    db, idx, dz = sm.smc_stage(lnl, 0.2, 0.5, 17, 3)
+    assert 0.0 < db < 0.8
+    w = np.where(np.isfinite(lnl), np.exp(db * (lnl - lnl[np.isfinite(lnl)].max())), 0.0)
+    assert w.sum() ** 2 / (w * w).sum() == pytest.approx(0.5 * W, rel=1e-9)
+    counts = np.bincount(idx, minlength=W)
+    expect = W * w / w.sum()
+    assert np.all(counts >= np.floor(expect) - 1e-9) and np.all(counts <= np.ceil(expect) + 1e-9)
+    assert np.all(counts[:5] == 0)
+    assert dz == pytest.approx(math.log(np.mean(np.exp(db * lnl[5:])) * (W - 5) / W), rel=1e-9)
+    db2, idx2, dz2 = sm.smc_stage(np.full(W, 7.0), 0.25, 0.5, 17, 4)
+    assert db2 == 0.75 and dz2 == pytest.approx(7.0 * 0.75, rel=1e-14)
+    assert np.array_equal(np.sort(idx2), np.arange(W))
