@@ -64,6 +64,15 @@ enum rbfl_form {
 
 /* Spec flags. */
 #define RBFL_FLAG_CENTER_NODE 0x1u  /* place the ellipsoid centre as node 0 before the Halton nodes */
+#define RBFL_FLAG_OPTIMISE_CENTRE 0x4u  /* move the centre to the network-SNR optimum (Sec. II C.1):
+                                           Nelder-Mead from center_phys with iota = phi = 0 over the intrinsic
+                                           parameters (coordinates Delta e / a of the ellipsoid at the seed) and
+                                           (iota, phi); per detector the SNR maximised over the plane of the two
+                                           polarisations h+, hx (mode factors at (F+, Fx) = (1, 0), (0, 1)),
+                                           over phase, and over time along the spline of the window samples
+                                           near the best one; summed over detectors.  RBFL_Q_CENTRE reports
+                                           the result.  The reference frequency and the injection stay those
+                                           of center_phys. */
 #define RBFL_FLAG_SQUEEZE 0x2u      /* squeeze the longest ellipsoid axis (Sec. II C.1, Fig. 2): scale it to
                                        the first point, scanning outward in steps of 1/64 along both
                                        directions, where the true match (Eq. Match) of the (2,2) template
@@ -241,8 +250,11 @@ enum rbfl_query_what {
   RBFL_Q_SPLIT_ERR = 15,    /* double[8]: per split-form variant, max |d ln L| against the FP64 form
                                on the last rbfl_autotune's proposals (0 = not measured) */
   RBFL_Q_F_REF = 16,        /* double[1]: template time/phase reference frequency [Hz] (0: coalescence) */
-  RBFL_Q_SQUEEZE = 17       /* double[2]: factor applied to the longest semi-axis (1 = none) and the true
+  RBFL_Q_SQUEEZE = 17,      /* double[2]: factor applied to the longest semi-axis (1 = none) and the true
                                match at the squeezed tip (0 when not squeezed) */
+  RBFL_Q_CENTRE = 18        /* double[8]: the ellipsoid centre used (m1, m2, chi1, chi2), the optimiser's
+                               iota and phi, the network SNR at center_phys (iota = phi = 0) and at the
+                               optimum (0, 0 without RBFL_FLAG_OPTIMISE_CENTRE) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 

@@ -55,11 +55,11 @@ def make_event(cfg, white: np.ndarray | None, inj_ext: np.ndarray) -> Event:
     n_det = len(D)
     psd = np.stack([ph.psd_on_grid(grid, cfg.psd_scale) for _ in range(n_det)])
     # template time/phase reference: as given, automatic (the mean frequency of
-    # the centre's band under the metric's weights; the centre is the
-    # injection here) or the coalescence (f_ref < 0)
+    # the seed centre's band under the metric's weights) or the coalescence
+    # (f_ref < 0)
     f_ref = getattr(cfg, "f_ref", 0.0)
     if f_ref == 0.0:
-        f_ref = ph.reference_frequency(grid, psd[0], cfg.inj_phys)
+        f_ref = ph.reference_frequency(grid, psd[0], cfg.seed_phys)
     grid.f_ref = max(f_ref, 0.0)
     # signal at 1 Mpc, then scale the distance to the requested SNR
     sig1 = [ph.detector_signal(grid, cfg.modes, cfg.inj_phys, 1.0, inj_ext, cfg.t_trig, D[k], pos[k])
@@ -190,6 +190,84 @@ def physical_mask(fr: Frame, x: np.ndarray, f0: float, chi_max: float = 1.0):
     with np.errstate(invalid="ignore"):
         ok = (eta <= 0.25) & (np.abs(c1) <= chi_max) & (np.abs(c2) <= chi_max)
     return ok & np.isfinite(c1) & np.isfinite(c2), np.stack([m1, m2, c1, c2], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# SNR-optimised centre (Sec. II C.1)
+# ----------------------------------------------------------------------------
+
+def network_snr2(ev: Event, phys, iota: float, phi: float, half_window: float, series=None) -> float:
+    """Network SNR^2 with each detector's SNR maximised over the plane of the
+    two polarisations h+ = sum_a c+_a h_a and hx = sum_a cx_a h_a (the mode
+    factors of Eq. logl_complete at (F+, Fx) = (1, 0) and (0, 1)): v^H G^+ v,
+    v_p(t) = <h_p e^{-2 pi i f t}|d_k>, G the polarisations' Gram matrix
+    (Moore-Penrose pseudo-inverse, relative cut 1e-10), and over time: the best
+    window sample b, then the maximum of that quadratic form along the
+    not-a-knot spline of v through the samples on [b - 1, b + 1] (the sample
+    value where the 10-sample stencil would leave the window)."""
+    import scipy.optimize
+    from .likelihood import spline_table, spline_weights
+    z, sig = series if series is not None else node_series_and_overlaps(ev, np.asarray(phys)[None], half_window)
+    yn = np.array([ph.ylm(l, -m, iota, phi) for (l, m) in ev.modes])
+    yp = np.array([(-1.0) ** l * np.conj(ph.ylm(l, m, iota, phi)) for (l, m) in ev.modes])
+    C = np.stack([0.5 * (yn + yp), 0.5j * (yn - yp)], axis=1)          # [mode][polarisation]
+    total = 0.0
+    for k in range(ev.n_det):
+        G = np.conj(C).T @ sig[k, 0] @ C
+        if not np.real(np.trace(G)) > 0.0:
+            continue
+        Gp = np.linalg.pinv(G, rcond=1e-10, hermitian=True)
+        V = np.conj(C).T @ z[k, :, 0, :]                                 # [polarisation][t]
+        v = np.real(np.einsum("pt,pq,qt->t", np.conj(V), Gp, V))
+        b = int(np.argmax(v))
+        peak = v[b]
+        T = v.size
+        if b - 5 >= 0 and b + 5 <= T - 1:
+            tab = spline_table()
+
+            def q(x):
+                n0 = min(int(math.floor(x)), b)
+                w = spline_weights(np.array([x - n0]), tab)[0]
+                a = V[:, n0 - 4:n0 + 6] @ w
+                return float(np.real(np.conj(a) @ Gp @ a))
+
+            r = scipy.optimize.minimize_scalar(lambda x: -q(x), bounds=(b - 1.0, b + 1.0), method="bounded",
+                                               options={"xatol": 1e-12})
+            peak = max(peak, -r.fun)
+        total += peak
+    return total
+
+
+def optimise_centre(ev: Event, seed_phys, match: float, half_window: float, chi_max: float = 1.0):
+    """Maximise network_snr2 over the intrinsic parameters and (iota, phi),
+    from seed_phys with iota = phi = 0, in the coordinates Delta e / a of the
+    seed's ellipsoid at M0 (Nelder-Mead; points outside the physical region
+    count as 0).  Returns (centre phys, iota, phi, SNR at the seed, SNR at
+    the optimum)."""
+    import scipy.optimize
+    grid = ev.grid
+    g = metric(grid, ev.psd[0], seed_phys)
+    fr = frame(g, ph.phys_to_theta(seed_phys, grid.f_low), match)
+    cache = {}
+
+    def series_at(u):
+        key = tuple(np.round(u, 15))
+        if key not in cache:
+            ok, phys = physical_mask(fr, np.asarray(u)[None], grid.f_low, chi_max)
+            cache[key] = (tuple(phys[0]), node_series_and_overlaps(ev, phys, half_window)) if ok[0] else None
+        return cache[key]
+
+    def neg(x):
+        s = series_at(x[:4])
+        return 0.0 if s is None else -network_snr2(ev, s[0], x[4], x[5], half_window, series=s[1])
+
+    x0 = np.zeros(6)
+    f0 = -neg(x0)
+    res = scipy.optimize.minimize(neg, x0, method="Nelder-Mead",
+                                  options={"xatol": 1e-7, "fatol": 1e-10, "maxiter": 4000, "maxfev": 8000,
+                                           "initial_simplex": np.vstack([x0, x0 + 0.1 * np.eye(6)])})
+    phys = series_at(res.x[:4])[0]
+    return phys, float(res.x[4]), float(res.x[5]), math.sqrt(f0), math.sqrt(-res.fun)
 
 
 # ----------------------------------------------------------------------------
@@ -440,6 +518,7 @@ class Artefacts:
     z_nodes: np.ndarray      # [n_det][n_modes][N][T]
     sigma_nodes: np.ndarray  # [n_det][N][n][n]
     squeeze_factor: float = 1.0   # scale applied to the longest semi-axis
+    centre_opt: tuple | None = None   # optimise_centre's result when the centre was optimised
 
     @property
     def d_ref(self) -> float:
@@ -464,12 +543,17 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
         inj_ext = wl.injection_extrinsics(cfg)
     ev = make_event(cfg, white, inj_ext)
     grid = ev.grid
-    theta_c = ph.phys_to_theta(cfg.inj_phys, grid.f_low)
-    g = metric(grid, ev.psd[0], cfg.inj_phys)
+    centre = tuple(cfg.seed_phys)
+    centre_opt = None
+    if getattr(cfg, "optimise_centre", False):
+        centre_opt = optimise_centre(ev, centre, cfg.match, cfg.half_window, cfg.chi_max)
+        centre = centre_opt[0]
+    theta_c = ph.phys_to_theta(centre, grid.f_low)
+    g = metric(grid, ev.psd[0], centre)
     fr = frame(g, theta_c, cfg.match)
     squeeze_factor = 1.0
     if getattr(cfg, "squeeze", False):
-        fr, squeeze_factor = squeeze(fr, grid, ev.psd[0], cfg.inj_phys, cfg.match, grid.f_low)
+        fr, squeeze_factor = squeeze(fr, grid, ev.psd[0], centre, cfg.match, grid.f_low)
     x, phys = place_nodes(fr, cfg.n_nodes, grid.f_low, cfg.chi_max, cfg.center_node)
     z, sig = node_series_and_overlaps(ev, phys, cfg.half_window, workers=workers)
     n_modes = len(ev.modes)
@@ -502,4 +586,4 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=x, phys_nodes=phys, W=W, basis=basis,
                      half_w=half_w, eps=cfg.eps, degree=cfg.poly_degree, q=cfg.q, cond=cond,
                      discarded=discarded, singular=singular, node_values=F, z_nodes=z,
-                     sigma_nodes=sig, squeeze_factor=squeeze_factor)
+                     sigma_nodes=sig, squeeze_factor=squeeze_factor, centre_opt=centre_opt)

@@ -7,6 +7,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -597,7 +598,8 @@ static void validate(const rbfl_build_spec *s) {
   require(s != nullptr, "spec is NULL");
   require(s->abi_version == RBFL_ABI_VERSION, "abi_version mismatch");
   require(std::isfinite(s->f_ref) && s->f_ref < 0.5 * s->fs, "f_ref must be finite and below fs / 2");
-  require((s->flags & ~(uint32_t)(RBFL_FLAG_CENTER_NODE | RBFL_FLAG_SQUEEZE)) == 0, "unknown flag bits");
+  require((s->flags & ~(uint32_t)(RBFL_FLAG_CENTER_NODE | RBFL_FLAG_SQUEEZE | RBFL_FLAG_OPTIMISE_CENTRE)) == 0,
+          "unknown flag bits");
   require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
   require(s->n_modes >= 1 && s->n_modes <= RBFL_MAX_MODES, "n_modes out of range");
   for (int a = 0; a < s->n_modes; ++a) {
@@ -684,6 +686,288 @@ struct BlasHandle {
   }
 };
 
+// ---- SNR-optimised centre (Sec. II C.1) -------------------------------------
+
+// Window-sample series z_ka(t) ([k][a][nb][T]) and mode overlaps sigma_k,ab
+// ([k][nb][a][b]) of templates at host-given binaries, whole band: the
+// start-up kernels with the data rotated to the window's first sample.
+static void ensure_win_D(Ctx &c, hipStream_t s) {
+  if (c.win_D.p) return;
+  const int64_t n_trig = (int64_t)std::llround(c.t_trig * c.fs);
+  const int64_t n0 = ((n_trig - c.half_w) % c.n_s + c.n_s) % c.n_s;
+  c.win_D.alloc((size_t)c.n_det * c.brute_J);
+  launch_rotate_band(c.brute_D.p, c.n_det, c.brute_J, c.brute_j_lo, n0, c.n_s, c.win_D.p, s);
+}
+
+static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector<double2> &Z,
+                            std::vector<double2> &S, hipStream_t s) {
+  const int nb = (int)bins.size(), nm = c.n_modes, nd = c.n_det, T = c.T;
+  const int64_t J = c.brute_J;
+  ensure_win_D(c, s);
+  int mode_lm[2 * RBFL_MAX_MODES] = {};
+  for (int a = 0; a < nm; ++a) {
+    mode_lm[2 * a] = c.modes[a][0];
+    mode_lm[2 * a + 1] = c.modes[a][1];
+  }
+  DevBuf<int> d_modes;
+  d_modes.alloc(2 * RBFL_MAX_MODES);
+  DevBuf<Binary> d_bins;
+  d_bins.alloc(nb);
+  DevBuf<double2> A, dZ, dS, part;
+  A.alloc((size_t)nm * nb * J);
+  dZ.alloc((size_t)nd * nm * nb * T);
+  dS.alloc((size_t)nd * nb * nm * nm);
+  const int t_here = ((nb + 63) / 64) * ((T + 63) / 64);
+  const int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + t_here - 1) / t_here, (J + 255) / 256));
+  part.alloc((size_t)n_split * nb * T);
+  RBFL_HIP(hipMemcpyAsync(d_modes.p, mode_lm, sizeof(mode_lm), hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * nb, hipMemcpyHostToDevice, s));
+  launch_waveforms(d_bins.p, nb, d_modes.p, nm, c.brute_j_lo, (int)J, c.df, 1.0, A.p, s);
+  launch_sigma(A.p, nb, nm, (int)J, c.brute_w.p, nd, nb, 0, dS.p, s);
+  for (int a = 0; a < nm; ++a)
+    for (int k = 0; k < nd; ++k) {
+      launch_window_dft(A.p + (size_t)a * nb * J, nb, (int)J, (int)J, c.win_D.p + (size_t)k * J, c.brute_j_lo, c.n_s,
+                        T, n_split, part.p, s);
+      launch_reduce_splits(part.p, n_split, nb, T, dZ.p + ((size_t)k * nm + a) * nb * T, s);
+    }
+  Z.resize(dZ.n);
+  S.resize(dS.n);
+  RBFL_HIP(hipMemcpyAsync(Z.data(), dZ.p, sizeof(double2) * dZ.n, hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipMemcpyAsync(S.data(), dS.p, sizeof(double2) * dS.n, hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+}
+
+// Network SNR^2 of point p of a batch at inclination iota and phase phi:
+// per detector the SNR maximised over the plane of the two polarisations
+// h+ = sum_a c+_a h_a, hx = sum_a cx_a h_a (the mode factors of
+// Eq. logl_complete at (F+, Fx) = (1, 0) and (0, 1): c+ = [Y_{l,-m} +
+// (-1)^l conj(Y_lm)] / 2, cx = i [Y_{l,-m} - (-1)^l conj(Y_lm)] / 2), i.e.
+// q = v^H G^+ v with v = (<h+|d>, <hx|d>) and G their Gram matrix
+// (pseudo-inverse: a rank-one G, as for the (2,2) mode alone, keeps its
+// leading direction), and over time: the best window sample b, then the
+// maximum of q along the not-a-knot spline of v through the window samples
+// on [b - 1, b + 1] (golden section, 60 steps; the sample value where the
+// stencil would leave the window).  Summed over the detectors.
+static double network_snr2(const Ctx &c, const YlmTerms *yneg, const YlmTerms *ypos, const std::vector<double2> &Z,
+                           const std::vector<double2> &S, int nb, int p, double iota, double phi) {
+  const int nm = c.n_modes, T = c.T;
+  cplx cp[RBFL_MAX_MODES], cx[RBFL_MAX_MODES];
+  for (int a = 0; a < nm; ++a) {
+    double nr, ni, pr, pi;
+    ylm_value(yneg[a], iota, phi, &nr, &ni);
+    ylm_value(ypos[a], iota, phi, &pr, &pi);
+    const double sg = (c.modes[a][0] & 1) ? -1.0 : 1.0;
+    cp[a] = 0.5 * (cplx(nr, ni) + sg * cplx(pr, -pi));
+    cx[a] = cplx(0.0, 0.5) * (cplx(nr, ni) - sg * cplx(pr, -pi));
+  }
+  double tab[kSplineTaps][4];
+  spline_table(tab);
+  double total = 0.0;
+  std::vector<cplx> v0(T), v1(T);
+  for (int k = 0; k < c.n_det; ++k) {
+    cplx G00(0.0, 0.0), G01(0.0, 0.0), G11(0.0, 0.0);
+    for (int a = 0; a < nm; ++a)
+      for (int b = 0; b < nm; ++b) {
+        const double2 sv = S[(((size_t)k * nb + p) * nm + a) * nm + b];
+        const cplx sg(sv.x, sv.y);
+        G00 += std::conj(cp[a]) * cp[b] * sg;
+        G01 += std::conj(cp[a]) * cx[b] * sg;
+        G11 += std::conj(cx[a]) * cx[b] * sg;
+      }
+    const double ga = G00.real(), gd = G11.real();
+    const double disc = sqrt(0.25 * (ga - gd) * (ga - gd) + std::norm(G01));
+    const double l1 = 0.5 * (ga + gd) + disc, l2 = 0.5 * (ga + gd) - disc;
+    if (!(l1 > 0.0)) continue;
+    const bool full = l2 > 1e-10 * l1;
+    cplx e0(1.0, 0.0), e1(0.0, 0.0);   // leading eigenvector when G is (nearly) rank one
+    if (!full) {
+      if (std::abs(G01) > 0.0) {
+        e0 = G01;
+        e1 = cplx(l1 - ga, 0.0);
+      } else if (gd > ga) {
+        e0 = 0.0;
+        e1 = 1.0;
+      }
+      const double nrm = sqrt(std::norm(e0) + std::norm(e1));
+      e0 /= nrm;
+      e1 /= nrm;
+    }
+    auto q = [&](cplx a0, cplx a1) {
+      if (full) return (gd * std::norm(a0) + ga * std::norm(a1) - 2.0 * (std::conj(a0) * G01 * a1).real()) / (l1 * l2);
+      return std::norm(std::conj(e0) * a0 + std::conj(e1) * a1) / l1;
+    };
+    int best = 0;
+    double qb = -1.0;
+    for (int t = 0; t < T; ++t) {
+      cplx a0(0.0, 0.0), a1(0.0, 0.0);
+      for (int a = 0; a < nm; ++a) {
+        const double2 zv = Z[(((size_t)k * nm + a) * nb + p) * T + t];
+        const cplx z(zv.x, zv.y);
+        a0 += std::conj(cp[a]) * z;
+        a1 += std::conj(cx[a]) * z;
+      }
+      v0[t] = a0;
+      v1[t] = a1;
+      const double qt = q(a0, a1);
+      if (qt > qb) {
+        qb = qt;
+        best = t;
+      }
+    }
+    double peak = qb;
+    if (best - 5 >= 0 && best + 5 <= T - 1) {
+      // q along the spline at position x in [best - 1, best + 1]
+      auto at = [&](double x) {
+        int n0 = (int)floor(x);
+        if (n0 > best) n0 = best;   // x = best + 1 stays in the last interval
+        const double f = x - n0;
+        cplx a0(0.0, 0.0), a1(0.0, 0.0);
+        for (int t = 0; t < kSplineTaps; ++t) {
+          const double w = tab[t][0] + f * (tab[t][1] + f * (tab[t][2] + f * tab[t][3]));
+          a0 += w * v0[n0 - 4 + t];
+          a1 += w * v1[n0 - 4 + t];
+        }
+        return q(a0, a1);
+      };
+      const double r = 0.5 * (sqrt(5.0) - 1.0);
+      double lo = best - 1.0, hi = best + 1.0;
+      double x1 = hi - r * (hi - lo), x2 = lo + r * (hi - lo);
+      double q1 = at(x1), q2 = at(x2);
+      for (int it = 0; it < 60; ++it) {
+        if (q1 >= q2) {
+          hi = x2;
+          x2 = x1;
+          q2 = q1;
+          x1 = hi - r * (hi - lo);
+          q1 = at(x1);
+        } else {
+          lo = x1;
+          x1 = x2;
+          q1 = q2;
+          x2 = lo + r * (hi - lo);
+          q2 = at(x2);
+        }
+      }
+      peak = std::max(q1, q2);
+    }
+    total += peak;
+  }
+  return total;
+}
+
+// Nelder-Mead maximisation of the network SNR^2 over the intrinsic
+// parameters and (iota, phi), from the given centre with iota = phi = 0
+// (Sec. II C.1 seeds the search with the best template, iota and phi zero).
+// Intrinsic coordinates u = Delta e / a in the seed's eigen-frame at M0;
+// initial simplex steps 0.1 (u) and 0.1 rad; reflection 1, expansion 2,
+// contraction 1/2, shrink 1/2; stops when the simplex's values agree to
+// 1e-12 relative and its extent is below 1e-8, or after 4000 evaluations.
+// Points outside the physical region count as SNR 0.  centre[] is updated.
+static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTerms *yneg, const YlmTerms *ypos,
+                            double centre[4], hipStream_t s) {
+  double g[16], lam[4], vec[16], V0[16], semi0[4], th0[4];
+  compute_metric(c, psd0, centre, g);
+  jacobi_eigen(g, lam, vec);
+  int order[4] = {0, 1, 2, 3};
+  std::sort(order, order + 4, [&](int x, int y) { return lam[x] > lam[y]; });
+  for (int i = 0; i < 4; ++i) {
+    const int o = order[i];
+    for (int r = 0; r < 4; ++r) V0[4 * r + i] = vec[4 * r + o];
+    semi0[i] = sqrt((1.0 - c.match) / lam[o]);
+  }
+  phys_to_theta(centre, c.f_low, th0);
+  auto to_phys = [&](const double u[4], double p[4]) {
+    double th[4];
+    for (int r = 0; r < 4; ++r) {
+      th[r] = th0[r];
+      for (int j = 0; j < 4; ++j) th[r] += V0[4 * r + j] * u[j] * semi0[j];
+    }
+    return theta_to_phys(th, c.f_low, c.chi_max, p);
+  };
+  std::vector<double2> Z, S;
+  int evals = 0;
+  auto value = [&](const std::array<double, 6> &x) {
+    ++evals;
+    double p[4];
+    if (!to_phys(x.data(), p)) return 0.0;
+    template_series(c, {make_binary(p[0], p[1], p[2], p[3], c.f_ref)}, Z, S, s);
+    return network_snr2(c, yneg, ypos, Z, S, 1, 0, x[4], x[5]);
+  };
+  const int n = 6;
+  std::vector<std::array<double, 6>> X(n + 1);
+  std::vector<double> F(n + 1);
+  for (int i = 0; i <= n; ++i) {
+    X[i].fill(0.0);
+    if (i > 0) X[i][i - 1] = 0.1;
+    F[i] = value(X[i]);
+  }
+  c.centre_snr[0] = sqrt(std::max(F[0], 0.0));
+  while (evals < 4000) {
+    // order by decreasing value (maximisation)
+    std::vector<int> idx(n + 1);
+    for (int i = 0; i <= n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return F[a] > F[b]; });
+    std::vector<std::array<double, 6>> Xs(n + 1);
+    std::vector<double> Fs(n + 1);
+    for (int i = 0; i <= n; ++i) {
+      Xs[i] = X[idx[i]];
+      Fs[i] = F[idx[i]];
+    }
+    X = Xs;
+    F = Fs;
+    double extent = 0.0;
+    for (int i = 1; i <= n; ++i)
+      for (int d = 0; d < n; ++d) extent = std::max(extent, fabs(X[i][d] - X[0][d]));
+    if (fabs(F[0] - F[n]) <= 1e-12 * fabs(F[0]) && extent < 1e-8) break;
+    std::array<double, 6> cen{};
+    for (int i = 0; i < n; ++i)
+      for (int d = 0; d < n; ++d) cen[d] += X[i][d] / n;
+    auto along = [&](double t) {
+      std::array<double, 6> y;
+      for (int d = 0; d < n; ++d) y[d] = cen[d] + t * (X[n][d] - cen[d]);
+      return y;
+    };
+    const std::array<double, 6> xr = along(-1.0);
+    const double fr = value(xr);
+    if (fr > F[0]) {
+      const std::array<double, 6> xe = along(-2.0);
+      const double fe = value(xe);
+      if (fe > fr) {
+        X[n] = xe;
+        F[n] = fe;
+      } else {
+        X[n] = xr;
+        F[n] = fr;
+      }
+    } else if (fr > F[n - 1]) {
+      X[n] = xr;
+      F[n] = fr;
+    } else {
+      const bool outside = fr > F[n];
+      const std::array<double, 6> xc = along(outside ? -0.5 : 0.5);
+      const double fc = value(xc);
+      if (fc > (outside ? fr : F[n])) {
+        X[n] = xc;
+        F[n] = fc;
+      } else {
+        for (int i = 1; i <= n; ++i) {
+          for (int d = 0; d < n; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
+          F[i] = value(X[i]);
+        }
+      }
+    }
+  }
+  int b = 0;
+  for (int i = 1; i <= n; ++i)
+    if (F[i] > F[b]) b = i;
+  double p[4];
+  to_phys(X[b].data(), p);
+  for (int i = 0; i < 4; ++i) centre[i] = c.centre_opt[i] = p[i];
+  c.centre_opt[4] = X[b][4];
+  c.centre_opt[5] = X[b][5];
+  c.centre_snr[1] = sqrt(std::max(F[b], 0.0));
+}
+
 static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   const auto t_all = Clock::now();
   validate(s);
@@ -746,15 +1030,40 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   } else {
     synthesise_data(*s, c, psd, yneg, ypos, data, &c.d_ref);
   }
+  {
+    // whole band, 4 df d_k / S_k and 4 df / S_k: the exact ln L at arbitrary
+    // proposals, the exact outputs and the centre's network SNR
+    const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+    const int64_t j_hi = c.n_s / 2;
+    c.brute_j_lo = j_lo;
+    c.brute_J = j_hi - j_lo;
+    std::vector<double2> bd((size_t)c.n_det * c.brute_J);
+    std::vector<double> bw((size_t)c.n_det * c.brute_J);
+    for (int k = 0; k < c.n_det; ++k)
+      for (int64_t j = j_lo; j < j_hi; ++j) {
+        const double sc = 4.0 * c.df / psd[k][j];
+        bd[(size_t)k * c.brute_J + (j - j_lo)] = make_double2(sc * data[k][j].x, sc * data[k][j].y);
+        bw[(size_t)k * c.brute_J + (j - j_lo)] = sc;
+      }
+    c.brute_D.alloc(bd.size());
+    c.brute_w.alloc(bw.size());
+    RBFL_HIP(hipMemcpyAsync(c.brute_D.p, bd.data(), sizeof(double2) * bd.size(), hipMemcpyHostToDevice, stream));
+    RBFL_HIP(hipMemcpyAsync(c.brute_w.p, bw.data(), sizeof(double) * bw.size(), hipMemcpyHostToDevice, stream));
+    RBFL_HIP(hipStreamSynchronize(stream));
+  }
   c.timing[0] = seconds_since(t0);
 
-  // frame
+  // frame, at the given centre or at the network-SNR optimum reached from it
   t0 = Clock::now();
-  phys_to_theta(s->center_phys, c.f_low, c.theta_c);
+  double centre[4] = {s->center_phys[0], s->center_phys[1], s->center_phys[2], s->center_phys[3]};
+  for (int i = 0; i < 4; ++i) c.centre_opt[i] = centre[i];
+  c.centre_snr[0] = c.centre_snr[1] = 0.0;
+  if (s->flags & RBFL_FLAG_OPTIMISE_CENTRE) optimise_centre(c, psd[0], yneg, ypos, centre, stream);
+  phys_to_theta(centre, c.f_low, c.theta_c);
   if (s->metric) {
     for (int i = 0; i < 16; ++i) c.metric[i] = s->metric[i];
   } else {
-    compute_metric(c, psd[0], s->center_phys, c.metric);
+    compute_metric(c, psd[0], centre, c.metric);
   }
   double lam[4], vec[16];
   jacobi_eigen(c.metric, lam, vec);
@@ -774,7 +1083,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.squeeze[0] = 1.0;
   c.squeeze[1] = 0.0;
   if (s->flags & RBFL_FLAG_SQUEEZE) {
-    c.squeeze[0] = squeeze_factor(c, psd[0], s->center_phys, &c.squeeze[1]);
+    c.squeeze[0] = squeeze_factor(c, psd[0], centre, &c.squeeze[1]);
     c.semi[3] *= c.squeeze[0];
   }
 
@@ -847,24 +1156,6 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
       Dk[(size_t)k * J + jj] = make_double2(sc * (d.x * cs - d.y * sn), sc * (d.x * sn + d.y * cs));
       wk[(size_t)k * J + jj] = sc;
     }
-  {
-    // whole band for the exact ln L at arbitrary proposals
-    c.brute_j_lo = j_lo;
-    c.brute_J = j_hi - j_lo;
-    std::vector<double2> bd((size_t)c.n_det * c.brute_J);
-    std::vector<double> bw((size_t)c.n_det * c.brute_J);
-    for (int k = 0; k < c.n_det; ++k)
-      for (int64_t j = j_lo; j < j_hi; ++j) {
-        const double sc = 4.0 * c.df / psd[k][j];
-        bd[(size_t)k * c.brute_J + (j - j_lo)] = make_double2(sc * data[k][j].x, sc * data[k][j].y);
-        bw[(size_t)k * c.brute_J + (j - j_lo)] = sc;
-      }
-    c.brute_D.alloc(bd.size());
-    c.brute_w.alloc(bw.size());
-    RBFL_HIP(hipMemcpyAsync(c.brute_D.p, bd.data(), sizeof(double2) * bd.size(), hipMemcpyHostToDevice, stream));
-    RBFL_HIP(hipMemcpyAsync(c.brute_w.p, bw.data(), sizeof(double) * bw.size(), hipMemcpyHostToDevice, stream));
-    RBFL_HIP(hipStreamSynchronize(stream));
-  }
   DevBuf<Binary> d_bins;
   d_bins.alloc(c.N);
   RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * c.N, hipMemcpyHostToDevice, stream));
@@ -1557,6 +1848,14 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_SQUEEZE:
       copy_out(out, bytes, c.squeeze, sizeof(c.squeeze));
       return;
+    case RBFL_Q_CENTRE: {
+      double v[8];
+      for (int i = 0; i < 6; ++i) v[i] = c.centre_opt[i];
+      v[6] = c.centre_snr[0];
+      v[7] = c.centre_snr[1];
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
     case RBFL_Q_NODES:
       copy_out(out, bytes, c.x_nodes.data(), sizeof(double) * c.x_nodes.size());
       return;

@@ -112,6 +112,8 @@ struct Ctx {
   double eps = 0, chi_max = 1, t_trig = 0, d_ref = 0, match = 0;
   double f_ref = 0;            // template time/phase reference frequency (0: coalescence)
   double squeeze[2] = {1, 0};  // factor applied to the longest semi-axis, true match at its new tip
+  double centre_opt[6] = {};   // centre used (m1, m2, chi1, chi2) and the optimiser's iota, phi
+  double centre_snr[2] = {};   // network SNR at the given centre (iota = phi = 0) and at the optimum
   // frame
   double theta_c[4] = {}, V[16] = {}, lam[4] = {}, semi[4] = {}, metric[16] = {};
   double D[RBFL_MAX_DET][9] = {}, r[RBFL_MAX_DET][3] = {};

@@ -23,10 +23,10 @@ MAX_DET = 4
 
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NUMERICAL, E_UNSUPPORTED, E_STATE = range(7)
 FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
-FLAG_CENTER_NODE, FLAG_SQUEEZE = 0x1, 0x2
+FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE = range(18)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE = range(19)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
@@ -245,7 +245,7 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
     s.metric = _dptr(met)
     for i in range(4):
         s.inj_phys[i] = cfg.inj_phys[i]
-        s.center_phys[i] = cfg.inj_phys[i]
+        s.center_phys[i] = cfg.seed_phys[i]
     for i in range(5):
         s.inj_ext[i] = float(inj_ext[i])
     s.inj_snr = cfg.inj_snr
@@ -258,7 +258,8 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
     s.eps = cfg.eps
     s.poly_degree = cfg.poly_degree
     s.chi_max = cfg.chi_max
-    s.flags = (FLAG_CENTER_NODE if cfg.center_node else 0) | (FLAG_SQUEEZE if cfg.squeeze else 0)
+    s.flags = ((FLAG_CENTER_NODE if cfg.center_node else 0) | (FLAG_SQUEEZE if cfg.squeeze else 0)
+               | (FLAG_OPTIMISE_CENTRE if getattr(cfg, "optimise_centre", False) else 0))
     s.f_ref = cfg.f_ref
     return s
 
@@ -332,6 +333,12 @@ class Handle:
         v = self._query(Q_FRAME, 44)
         return {"theta_c": v[0:4], "vecs": v[4:20].reshape(4, 4), "lam": v[20:24], "semi": v[24:28],
                 "metric": v[28:44].reshape(4, 4)}
+
+    def centre(self) -> dict:
+        """The centre used and the network-SNR optimisation's result (RBFL_Q_CENTRE)."""
+        v = self._query(Q_CENTRE, 8)
+        return {"phys": v[0:4], "iota": float(v[4]), "phi": float(v[5]), "snr_seed": float(v[6]),
+                "snr_opt": float(v[7])}
 
     def squeeze(self) -> tuple:
         """(factor applied to the longest semi-axis, true match at its new tip)."""

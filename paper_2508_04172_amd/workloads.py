@@ -69,6 +69,8 @@ class Config:
     center_node: bool = False
     f_ref: float = 0.0                            # template time/phase reference [Hz]; 0 = automatic, < 0 = coalescence
     squeeze: bool = False                         # contract the longest ellipsoid axis to the true-match crossing
+    optimise_centre: bool = False                 # move the centre to the network-SNR optimum first
+    centre_offset: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)   # seed = injection + offset
 
     @property
     def n_det(self) -> int:
@@ -96,6 +98,13 @@ class Config:
         """Interpolated real outputs per query: per detector 2q per mode + n^2 overlap reals."""
         n = len(self.modes)
         return self.n_det * (2 * self.q * n + n * n)
+
+    @property
+    def seed_phys(self) -> Tuple[float, float, float, float]:
+        """The ellipsoid centre handed to the start-up: the injection plus
+        centre_offset (a seed template off the injection, as a search's best
+        match would be)."""
+        return tuple(a + b for a, b in zip(self.inj_phys, self.centre_offset))
 
     def with_(self, **kw) -> "Config":
         return replace(self, **kw)

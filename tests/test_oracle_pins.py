@@ -556,3 +556,23 @@ def test_squeeze_stops_at_the_first_true_match_crossing():
     art = su.startup(cfg, None, workers=1)
     assert art.squeeze_factor == factor
     assert np.all(np.sum(art.x_nodes ** 2, axis=1) <= 1.0)
+
+
+# ---------------------------------------------------------------- SNR-optimised centre
+
+def test_centre_optimum_reaches_the_cauchy_schwarz_bound():
+    """One detector, the (2,2) mode, zero noise: the data are a template of
+    the family, so the best network SNR is the injection's optimal SNR
+    (Cauchy-Schwarz, equality only at the injected template); started from a
+    seed inside the match ellipsoid (as a template bank's best match would
+    be) with iota = phi = 0, the optimiser must reach it and return a centre
+    whose template matches the injection."""
+    cfg = TINY.with_(centre_offset=(0.002, 0.0, 0.01, 0.0))
+    ev = su.make_event(cfg, None, wl.injection_extrinsics(cfg))
+    phys, iota, phi, snr_seed, snr_opt = su.optimise_centre(ev, cfg.seed_phys, cfg.match, cfg.half_window)
+    assert snr_seed < 0.99 * cfg.inj_snr
+    assert cfg.inj_snr * (1 - 1e-4) <= snr_opt <= cfg.inj_snr * (1 + 1e-6)
+    assert su.match_22(ev.grid, ev.psd[0], cfg.inj_phys, phys) > 0.9999
+    # the objective at the injection itself is the bound (any iota, phi for the (2,2) mode)
+    s2 = su.network_snr2(ev, cfg.inj_phys, 0.4, 1.0, cfg.half_window)
+    assert s2 == pytest.approx(cfg.inj_snr ** 2, rel=1e-6)
