@@ -65,9 +65,11 @@ enum rbfl_form {
 /* Spec flags. */
 #define RBFL_FLAG_CENTER_NODE 0x1u  /* place the ellipsoid centre as node 0 before the Halton nodes */
 #define RBFL_FLAG_OPTIMISE_CENTRE 0x4u  /* move the centre to the network-SNR optimum (Sec. II C.1):
-                                           Nelder-Mead from center_phys with iota = phi = 0 over the intrinsic
-                                           parameters (coordinates Delta e / a of the ellipsoid at the seed) and
-                                           (iota, phi); per detector the SNR maximised over the plane of the two
+                                           Nelder-Mead from center_phys over the intrinsic parameters
+                                           (coordinates Delta e / a of the ellipsoid at the seed), each template's
+                                           SNR maximised over (iota, phi) (grid, then Nelder-Mead; the seed's SNR
+                                           is reported at iota = phi = 0); per detector the SNR maximised over
+                                           the plane of the two
                                            polarisations h+, hx (mode factors at (F+, Fx) = (1, 0), (0, 1)),
                                            over phase, and over time along the spline of the window samples
                                            near the best one; summed over detectors.  RBFL_Q_CENTRE reports

@@ -699,8 +699,16 @@ static void ensure_win_D(Ctx &c, hipStream_t s) {
   launch_rotate_band(c.brute_D.p, c.n_det, c.brute_J, c.brute_j_lo, n0, c.n_s, c.win_D.p, s);
 }
 
+// Device buffers of template_series, kept across calls of one search.
+struct SeriesWork {
+  int nb = 0;
+  DevBuf<int> modes;
+  DevBuf<Binary> bins;
+  DevBuf<double2> A, Z, S, part;
+};
+
 static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector<double2> &Z,
-                            std::vector<double2> &S, hipStream_t s) {
+                            std::vector<double2> &S, hipStream_t s, SeriesWork &w) {
   const int nb = (int)bins.size(), nm = c.n_modes, nd = c.n_det, T = c.T;
   const int64_t J = c.brute_J;
   ensure_win_D(c, s);
@@ -709,17 +717,23 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
     mode_lm[2 * a] = c.modes[a][0];
     mode_lm[2 * a + 1] = c.modes[a][1];
   }
-  DevBuf<int> d_modes;
-  d_modes.alloc(2 * RBFL_MAX_MODES);
-  DevBuf<Binary> d_bins;
-  d_bins.alloc(nb);
-  DevBuf<double2> A, dZ, dS, part;
-  A.alloc((size_t)nm * nb * J);
-  dZ.alloc((size_t)nd * nm * nb * T);
-  dS.alloc((size_t)nd * nb * nm * nm);
   const int t_here = ((nb + 63) / 64) * ((T + 63) / 64);
   const int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + t_here - 1) / t_here, (J + 255) / 256));
-  part.alloc((size_t)n_split * nb * T);
+  if (w.nb != nb) {
+    w.modes.alloc(2 * RBFL_MAX_MODES);
+    w.bins.alloc(nb);
+    w.A.alloc((size_t)nm * nb * J);
+    w.Z.alloc((size_t)nd * nm * nb * T);
+    w.S.alloc((size_t)nd * nb * nm * nm);
+    w.part.alloc((size_t)n_split * nb * T);
+    w.nb = nb;
+  }
+  auto &d_modes = w.modes;
+  auto &d_bins = w.bins;
+  auto &A = w.A;
+  auto &dZ = w.Z;
+  auto &dS = w.S;
+  auto &part = w.part;
   RBFL_HIP(hipMemcpyAsync(d_modes.p, mode_lm, sizeof(mode_lm), hipMemcpyHostToDevice, s));
   RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * nb, hipMemcpyHostToDevice, s));
   launch_waveforms(d_bins.p, nb, d_modes.p, nm, c.brute_j_lo, (int)J, c.df, 1.0, A.p, s);
@@ -855,14 +869,93 @@ static double network_snr2(const Ctx &c, const YlmTerms *yneg, const YlmTerms *y
   return total;
 }
 
-// Nelder-Mead maximisation of the network SNR^2 over the intrinsic
-// parameters and (iota, phi), from the given centre with iota = phi = 0
-// (Sec. II C.1 seeds the search with the best template, iota and phi zero).
-// Intrinsic coordinates u = Delta e / a in the seed's eigen-frame at M0;
-// initial simplex steps 0.1 (u) and 0.1 rad; reflection 1, expansion 2,
-// contraction 1/2, shrink 1/2; stops when the simplex's values agree to
-// 1e-12 relative and its extent is below 1e-8, or after 4000 evaluations.
-// Points outside the physical region count as SNR 0.  centre[] is updated.
+// Nelder-Mead maximisation of f over n coordinates from x0 with initial steps
+// `step` (reflection 1, expansion 2, contraction 1/2, shrink 1/2); stops when
+// the simplex's values agree to ftol relative and its extent is below xtol,
+// or after max_evals evaluations.  Returns the best value; x0 receives its
+// point.
+template <class F>
+static double nelder_mead_max(F &&f, std::vector<double> &x0, const std::vector<double> &step, double ftol,
+                              double xtol, int max_evals) {
+  const int n = (int)x0.size();
+  std::vector<std::vector<double>> X(n + 1, x0);
+  std::vector<double> V(n + 1);
+  int evals = 0;
+  for (int i = 0; i <= n; ++i) {
+    if (i > 0) X[i][i - 1] += step[i - 1];
+    V[i] = f(X[i]);
+    ++evals;
+  }
+  std::vector<int> idx(n + 1);
+  while (evals < max_evals) {
+    for (int i = 0; i <= n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return V[a] > V[b]; });
+    std::vector<std::vector<double>> Xs(n + 1);
+    std::vector<double> Vs(n + 1);
+    for (int i = 0; i <= n; ++i) {
+      Xs[i] = X[idx[i]];
+      Vs[i] = V[idx[i]];
+    }
+    X.swap(Xs);
+    V.swap(Vs);
+    double extent = 0.0;
+    for (int i = 1; i <= n; ++i)
+      for (int d = 0; d < n; ++d) extent = std::max(extent, fabs(X[i][d] - X[0][d]));
+    if (fabs(V[0] - V[n]) <= ftol * fabs(V[0]) && extent < xtol) break;
+    std::vector<double> cen(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int d = 0; d < n; ++d) cen[d] += X[i][d] / n;
+    auto along = [&](double t) {
+      std::vector<double> y(n);
+      for (int d = 0; d < n; ++d) y[d] = cen[d] + t * (X[n][d] - cen[d]);
+      return y;
+    };
+    const std::vector<double> xr = along(-1.0);
+    const double fr = f(xr);
+    ++evals;
+    if (fr > V[0]) {
+      const std::vector<double> xe = along(-2.0);
+      const double fe = f(xe);
+      ++evals;
+      X[n] = fe > fr ? xe : xr;
+      V[n] = std::max(fe, fr);
+    } else if (fr > V[n - 1]) {
+      X[n] = xr;
+      V[n] = fr;
+    } else {
+      const bool outside = fr > V[n];
+      const std::vector<double> xc = along(outside ? -0.5 : 0.5);
+      const double fc = f(xc);
+      ++evals;
+      if (fc > (outside ? fr : V[n])) {
+        X[n] = xc;
+        V[n] = fc;
+      } else {
+        for (int i = 1; i <= n; ++i) {
+          for (int d = 0; d < n; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
+          V[i] = f(X[i]);
+          ++evals;
+        }
+      }
+    }
+  }
+  int b = 0;
+  for (int i = 1; i <= n; ++i)
+    if (V[i] > V[b]) b = i;
+  x0 = X[b];
+  return V[b];
+}
+
+// The SNR-optimised centre (Sec. II C.1 seeds the search with the best
+// template, iota and phi zero).  Outer Nelder-Mead over the intrinsic
+// coordinates u = Delta e / a of the seed's eigen-frame at M0 (initial steps
+// 0.1, tolerances 1e-12 relative in SNR^2 and 1e-7 in u, at most 800
+// templates), restarted once from its result with steps 0.02; for each
+// template, the SNR^2 maximised over (iota, phi): the
+// best of a 7 x 8 grid (iota = j pi / 6, phi = k pi / 4), then a Nelder-Mead
+// from it (steps 0.1 rad, 1e-12, 1e-8, 300 evaluations), all on the host from
+// the template's series.  Points outside the physical region count as 0.
+// centre[] is updated.
 static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTerms *yneg, const YlmTerms *ypos,
                             double centre[4], hipStream_t s) {
   double g[16], lam[4], vec[16], V0[16], semi0[4], th0[4];
@@ -876,7 +969,7 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
     semi0[i] = sqrt((1.0 - c.match) / lam[o]);
   }
   phys_to_theta(centre, c.f_low, th0);
-  auto to_phys = [&](const double u[4], double p[4]) {
+  auto to_phys = [&](const double *u, double p[4]) {
     double th[4];
     for (int r = 0; r < 4; ++r) {
       th[r] = th0[r];
@@ -884,88 +977,48 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
     }
     return theta_to_phys(th, c.f_low, c.chi_max, p);
   };
+  SeriesWork work;
   std::vector<double2> Z, S;
-  int evals = 0;
-  auto value = [&](const std::array<double, 6> &x) {
-    ++evals;
-    double p[4];
-    if (!to_phys(x.data(), p)) return 0.0;
-    template_series(c, {make_binary(p[0], p[1], p[2], p[3], c.f_ref)}, Z, S, s);
-    return network_snr2(c, yneg, ypos, Z, S, 1, 0, x[4], x[5]);
-  };
-  const int n = 6;
-  std::vector<std::array<double, 6>> X(n + 1);
-  std::vector<double> F(n + 1);
-  for (int i = 0; i <= n; ++i) {
-    X[i].fill(0.0);
-    if (i > 0) X[i][i - 1] = 0.1;
-    F[i] = value(X[i]);
-  }
-  c.centre_snr[0] = sqrt(std::max(F[0], 0.0));
-  while (evals < 4000) {
-    // order by decreasing value (maximisation)
-    std::vector<int> idx(n + 1);
-    for (int i = 0; i <= n; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return F[a] > F[b]; });
-    std::vector<std::array<double, 6>> Xs(n + 1);
-    std::vector<double> Fs(n + 1);
-    for (int i = 0; i <= n; ++i) {
-      Xs[i] = X[idx[i]];
-      Fs[i] = F[idx[i]];
-    }
-    X = Xs;
-    F = Fs;
-    double extent = 0.0;
-    for (int i = 1; i <= n; ++i)
-      for (int d = 0; d < n; ++d) extent = std::max(extent, fabs(X[i][d] - X[0][d]));
-    if (fabs(F[0] - F[n]) <= 1e-12 * fabs(F[0]) && extent < 1e-8) break;
-    std::array<double, 6> cen{};
-    for (int i = 0; i < n; ++i)
-      for (int d = 0; d < n; ++d) cen[d] += X[i][d] / n;
-    auto along = [&](double t) {
-      std::array<double, 6> y;
-      for (int d = 0; d < n; ++d) y[d] = cen[d] + t * (X[n][d] - cen[d]);
-      return y;
-    };
-    const std::array<double, 6> xr = along(-1.0);
-    const double fr = value(xr);
-    if (fr > F[0]) {
-      const std::array<double, 6> xe = along(-2.0);
-      const double fe = value(xe);
-      if (fe > fr) {
-        X[n] = xe;
-        F[n] = fe;
-      } else {
-        X[n] = xr;
-        F[n] = fr;
-      }
-    } else if (fr > F[n - 1]) {
-      X[n] = xr;
-      F[n] = fr;
-    } else {
-      const bool outside = fr > F[n];
-      const std::array<double, 6> xc = along(outside ? -0.5 : 0.5);
-      const double fc = value(xc);
-      if (fc > (outside ? fr : F[n])) {
-        X[n] = xc;
-        F[n] = fc;
-      } else {
-        for (int i = 1; i <= n; ++i) {
-          for (int d = 0; d < n; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
-          F[i] = value(X[i]);
+  double cur_angles[2] = {0.0, 0.0};   // the inner search's angles for the last template
+  auto inner = [&]() {
+    double b = -1.0;
+    std::vector<double> a0 = {0.0, 0.0};
+    for (int j = 0; j <= 6; ++j)
+      for (int k = 0; k < 8; ++k) {
+        const double v = network_snr2(c, yneg, ypos, Z, S, 1, 0, j * kPi / 6.0, k * kPi / 4.0);
+        if (v > b) {
+          b = v;
+          a0 = {j * kPi / 6.0, k * kPi / 4.0};
         }
       }
-    }
+    b = nelder_mead_max([&](const std::vector<double> &a) { return network_snr2(c, yneg, ypos, Z, S, 1, 0, a[0], a[1]); },
+                        a0, {0.1, 0.1}, 1e-12, 1e-8, 300);
+    cur_angles[0] = a0[0];
+    cur_angles[1] = a0[1];
+    return b;
+  };
+  auto outer = [&](const std::vector<double> &u) {
+    double p[4];
+    if (!to_phys(u.data(), p)) return 0.0;
+    template_series(c, {make_binary(p[0], p[1], p[2], p[3], c.f_ref)}, Z, S, s, work);
+    return inner();
+  };
+  {
+    double p[4];
+    to_phys(std::vector<double>(4, 0.0).data(), p);
+    template_series(c, {make_binary(p[0], p[1], p[2], p[3], c.f_ref)}, Z, S, s, work);
+    c.centre_snr[0] = sqrt(std::max(network_snr2(c, yneg, ypos, Z, S, 1, 0, 0.0, 0.0), 0.0));
   }
-  int b = 0;
-  for (int i = 1; i <= n; ++i)
-    if (F[i] > F[b]) b = i;
+  std::vector<double> u(4, 0.0);
+  double v = nelder_mead_max(outer, u, {0.1, 0.1, 0.1, 0.1}, 1e-12, 1e-7, 800);
+  v = nelder_mead_max(outer, u, {0.02, 0.02, 0.02, 0.02}, 1e-12, 1e-7, 800);   // a restart: the simplex may collapse early
+  outer(u);   // the angles of the returned vertex
   double p[4];
-  to_phys(X[b].data(), p);
+  to_phys(u.data(), p);
   for (int i = 0; i < 4; ++i) centre[i] = c.centre_opt[i] = p[i];
-  c.centre_opt[4] = X[b][4];
-  c.centre_opt[5] = X[b][5];
-  c.centre_snr[1] = sqrt(std::max(F[b], 0.0));
+  c.centre_opt[4] = cur_angles[0];
+  c.centre_opt[5] = cur_angles[1];
+  c.centre_snr[1] = sqrt(std::max(v, 0.0));
 }
 
 static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
