@@ -1229,8 +1229,9 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.z_nodes.alloc((size_t)c.n_det * c.n_modes * c.N * c.T);
   DevBuf<double2> d_sig;
   d_sig.alloc((size_t)c.n_det * c.N * c.n_modes * c.n_modes);
-  // node batches sized so the templates of a batch stay within ~2 GiB
-  const size_t budget = (size_t)2 << 30;
+  // node batches sized so the templates of a batch stay within ~8 GiB of the
+  // 288 GB of HBM (the 2048 s third-generation case then takes 27 nodes per batch)
+  const size_t budget = (size_t)8 << 30;
   int nb_max = (int)std::max<size_t>(1, std::min<size_t>(c.N, budget / ((size_t)c.n_modes * J * sizeof(double2))));
   DevBuf<double2> d_A;
   d_A.alloc((size_t)c.n_modes * nb_max * J);

@@ -131,7 +131,7 @@ CFG3 = Config(name="cfg3_mixed_cubic", fs=2048.0, seg_len=256.0, f_low=10.0,
 CFG5 = Config(name="cfg5_triangle_snr200", fs=4096.0, seg_len=2048.0, f_low=5.0,
               modes=ALL_MODES, sites=SITES_TRIANGLE, psd_scale=0.1,
               inj_phys=(8.0, 1.4, 0.3, 0.0), inj_snr=200.0, match=0.97,
-              n_nodes=3000, q=80, eps=2.0, poly_degree=1, half_window=0.05,
+              n_nodes=3000, q=80, eps=3.0, poly_degree=1, half_window=0.05,
               n_queries=10_000_000, tc_span=0.027, random_sky=True)
 
 # Reduced cases that the oracle finishes in seconds, used for element-wise parity.
