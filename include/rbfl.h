@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 2
+#define RBFL_ABI_VERSION 3
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
 
@@ -152,6 +152,12 @@ typedef struct {
                                           0 = the mean frequency of the centre's (2,2) band under the
                                           weights f^(-7/3) / S_0 (the metric's), < 0 = the formal
                                           coalescence (no reference shift) */
+  double earth_rate;                   /* Earth's rotation rate [rad/s] for the exact likelihood and the
+                                          synthesised injection (0 = antenna patterns frozen at t_c, the
+                                          meshfree method's model, 7.2921150e-5 = sidereal): a source at
+                                          right ascension alpha has Earth-fixed longitude
+                                          alpha - earth_rate (t - t_trig), and each mode's frequency f is
+                                          emitted at its stationary-phase time t_c + Psi'(2f/m) / (2 pi) */
 } rbfl_build_spec;
 
 /* Thread-local description of the last failure on this thread; valid until

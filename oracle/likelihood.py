@@ -31,10 +31,12 @@ from .startup import Artefacts, Event, gaussian_kernel, output_layout, poly_matr
 
 def brute_lnl(ev: Event, phys, ext, t_c: float, d_l: float) -> float:
     """ln L = sum_k <h_k|d_k> - 1/2 <h_k|h_k> with the projected signal of
-    Eq. projected_h_fd (Eq. logl_basic)."""
+    Eq. projected_h_fd (Eq. logl_basic); on a rotating Earth (ev.earth_rate)
+    with each mode's antenna factor and delay at its stationary-phase time."""
     total = 0.0
     for k in range(ev.n_det):
-        h = ph.detector_signal(ev.grid, ev.modes, phys, d_l, ext, t_c, ev.det_tensor[k], ev.det_pos[k])
+        h = ph.detector_signal(ev.grid, ev.modes, phys, d_l, ext, t_c, ev.det_tensor[k], ev.det_pos[k],
+                               ev.earth_rate, ev.t_trig)
         total += ph.inner(h, ev.data[k], ev.psd[k], ev.grid) - 0.5 * ph.inner(h, h, ev.psd[k], ev.grid)
     return total
 

@@ -338,8 +338,62 @@ def polarizations(grid: Grid, modes, phys, d_mpc, iota, phi):
     return hp, hc
 
 
-def detector_signal(grid: Grid, modes, phys, d_mpc, ext, t_c, D, pos):
-    """Projected signal (Eq. projected_h_fd): [F+ h+ + Fx hx] e^{-2 pi i f (t_c + dt_k)}."""
+def spa_time(f: np.ndarray, m: int, phys, f_ref: float, t_c: float) -> np.ndarray:
+    """Stationary-phase time at which mode m has frequency f: the slope of its
+    phase (m/2) Psi(2f/m), i.e. t_c + Psi'(2f/m) / (2 pi) with the referenced
+    phase Psi; the derivative by the complex step."""
+    x = 2.0 * np.asarray(f, dtype=np.float64) / m
+    h = 1e-20 * x
+    d = np.imag(referenced_phase_22(x + 1j * h, *phys, f_ref)) / h
+    return t_c + d / (2.0 * math.pi)
+
+
+def rotating_detector_signal(grid: Grid, modes, phys, d_mpc, ext, t_c, D, pos, rate: float, t_ref: float):
+    """Projected signal on a rotating Earth: mode (l, m) at frequency f is
+    emitted at its stationary-phase time t_a(f), when the source (fixed right
+    ascension alpha) sits at Earth-fixed longitude alpha - rate (t_a - t_ref);
+    its antenna factor and delay are taken there:
+    sum_lm A_lm(t_a) h_{l,-m}(f) e^{-2 pi i f (t_c + dt(t_a))}."""
+    alpha, dec, psi, iota, phi = ext
+    out = np.zeros(grid.n_f, dtype=np.complex128)
+    m1, m2 = phys[0], phys[1]
+    for (l, m) in modes:
+        j0, j1 = mode_band(grid, m, m1, m2)
+        if j1 <= j0:
+            continue
+        j = np.arange(j0, j1)
+        f = j * grid.df
+        h = waveform_mode(grid, l, m, phys, d_mpc)[j0:j1]
+        ta = spa_time(f, m, phys, grid.f_ref, t_c)
+        for i in range(0, f.size, 65536):
+            sl = slice(i, min(f.size, i + 65536))
+            al = alpha - rate * (ta[sl] - t_ref)
+            # the frozen pattern's formulas, for an array of longitudes
+            e_a = np.stack([-np.sin(al), np.cos(al), np.zeros_like(al)], axis=1)
+            e_d = np.stack([-math.sin(dec) * np.cos(al), -math.sin(dec) * np.sin(al),
+                            np.full_like(al, math.cos(dec))], axis=1)
+            X = -math.cos(psi) * e_a + math.sin(psi) * e_d
+            Y = math.sin(psi) * e_a + math.cos(psi) * e_d
+            fp = np.einsum("ij,ni,nj->n", D, X, X) - np.einsum("ij,ni,nj->n", D, Y, Y)
+            fc = np.einsum("ij,ni,nj->n", D, X, Y) + np.einsum("ij,ni,nj->n", D, Y, X)
+            s_hat = np.stack([math.cos(dec) * np.cos(al), math.cos(dec) * np.sin(al),
+                              np.full_like(al, math.sin(dec))], axis=1)
+            dt = -(s_hat @ pos)
+            A = 0.5 * ((fp + 1j * fc) * ylm(l, -m, iota, phi)
+                       + (-1.0) ** l * (fp - 1j * fc) * np.conj(ylm(l, m, iota, phi)))
+            tau = t_c + dt
+            n = np.rint(tau * grid.fs).astype(np.int64)
+            rem = tau - n / grid.fs
+            frac = ((j[sl] * (n % grid.n_s)) % grid.n_s).astype(np.float64) / grid.n_s
+            out[j0 + i:j0 + i + f[sl].size] += A * h[sl] * np.exp(-2j * math.pi * (frac + f[sl] * rem))
+    return out
+
+
+def detector_signal(grid: Grid, modes, phys, d_mpc, ext, t_c, D, pos, rate: float = 0.0, t_ref: float = 0.0):
+    """Projected signal (Eq. projected_h_fd): [F+ h+ + Fx hx] e^{-2 pi i f (t_c + dt_k)};
+    on a rotating Earth (rate != 0) rotating_detector_signal."""
+    if rate != 0.0:
+        return rotating_detector_signal(grid, modes, phys, d_mpc, ext, t_c, D, pos, rate, t_ref)
     alpha, dec, psi, iota, phi = ext
     fp, fc = antenna_pattern(D, alpha, dec, psi)
     hp, hc = polarizations(grid, modes, phys, d_mpc, iota, phi)

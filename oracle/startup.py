@@ -35,6 +35,7 @@ class Event:
     t_trig: float
     d_inj: float               # injection distance [Mpc]; also the template reference distance
     snr_opt: float
+    earth_rate: float = 0.0    # Earth rotation [rad/s] of the exact model (0: frozen antenna patterns)
 
     @property
     def n_det(self) -> int:
@@ -62,7 +63,8 @@ def make_event(cfg, white: np.ndarray | None, inj_ext: np.ndarray) -> Event:
         f_ref = ph.reference_frequency(grid, psd[0], cfg.seed_phys)
     grid.f_ref = max(f_ref, 0.0)
     # signal at 1 Mpc, then scale the distance to the requested SNR
-    sig1 = [ph.detector_signal(grid, cfg.modes, cfg.inj_phys, 1.0, inj_ext, cfg.t_trig, D[k], pos[k])
+    rate = getattr(cfg, "earth_rate", 0.0)
+    sig1 = [ph.detector_signal(grid, cfg.modes, cfg.inj_phys, 1.0, inj_ext, cfg.t_trig, D[k], pos[k], rate, cfg.t_trig)
             for k in range(n_det)]
     rho1 = math.sqrt(sum(ph.inner(s, s, psd[k], grid) for k, s in enumerate(sig1)))
     d_inj = rho1 / cfg.inj_snr
@@ -75,7 +77,7 @@ def make_event(cfg, white: np.ndarray | None, inj_ext: np.ndarray) -> Event:
             data[k] += amp * (white[k, :, 0] + 1j * white[k, :, 1])
     return Event(grid=grid, modes=tuple(cfg.modes), psd=psd, data=data, det_tensor=D, det_pos=pos,
                  inj_phys=tuple(cfg.inj_phys), inj_ext=np.asarray(inj_ext, dtype=np.float64),
-                 t_trig=cfg.t_trig, d_inj=d_inj, snr_opt=cfg.inj_snr)
+                 t_trig=cfg.t_trig, d_inj=d_inj, snr_opt=cfg.inj_snr, earth_rate=rate)
 
 
 # ----------------------------------------------------------------------------

@@ -11,6 +11,9 @@
 //
 // One workgroup per proposal; the threads stride over the bins, one pass per
 // detector (20 complex accumulators per thread), fixed-order reductions.
+// With the Earth's rotation switched on the antenna factors and delays vary
+// along the band (each mode's frequency at its own stationary-phase time), so
+// <h_k|d_k> and <h_k|h_k> are summed directly instead.
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -78,6 +81,60 @@ __global__ void __launch_bounds__(kBruteThreads) k_brute(const EvalConsts *__res
   sincos(0.5 * iota, &sh, &ch);
   const double fs = (double)n_s * df;
   double total = 0.0, comp = 0.0;
+  if (c.earth_rate != 0.0) {
+    // rotating Earth: A and the delay of every (bin, mode) at the mode's
+    // stationary-phase time t_a = t_c + Psi'(2f/m) / (2 pi); <h_k|d_k> and
+    // <h_k|h_k> summed directly over the band
+    double ynr[RBFL_MAX_MODES], yni[RBFL_MAX_MODES], ypr[RBFL_MAX_MODES], ypi[RBFL_MAX_MODES];
+    for (int a = 0; a < n_modes; ++a) {
+      eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr[a], &yni[a]);
+      eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr[a], &ypi[a]);
+    }
+    for (int k = 0; k < c.n_det; ++k) {
+      const double2 *Dk = Dd + (int64_t)k * J;
+      const double *wkk = wk + (int64_t)k * J;
+      double zr = 0.0, sw = 0.0;
+      for (int64_t j = j_lo + threadIdx.x; j < jmax; j += kBruteThreads) {
+        const double f = (double)j * df;
+        double hr = 0.0, hi = 0.0;
+        for (int a = 0; a < n_modes; ++a) {
+          if (!(j < jend[a])) continue;
+          const int l = c.mode_l[a], m = c.mode_m[a];
+          const double x = 2.0 * f / (double)m;
+          const double ta = tc + (dphase22_pn(x, b) - b.dpsi_ref) / (2.0 * kPi);
+          double fp, fc, dt;
+          detector_response(c.D[k], c.r[k], alpha - c.earth_rate * (ta - c.t_trig), dec, psi, &fp, &fc, &dt);
+          const double sg = (l & 1) ? -1.0 : 1.0;
+          const double Ar = 0.5 * ((fp * ynr[a] - fc * yni[a]) + sg * (fp * ypr[a] - fc * ypi[a]));
+          const double Ai = 0.5 * ((fp * yni[a] + fc * ynr[a]) + sg * (-fp * ypi[a] - fc * ypr[a]));
+          const double ph = 0.5 * (double)m * phase22(x, b);
+          const double amp = mode_amp(l, m, b.eta, b.delta) * b.amp * inv_dref_s * exp(-7.0 / 6.0 * log(f));
+          double sn, cs;
+          sincos(ph, &sn, &cs);
+          const double xr = amp * cs, xi = -amp * sn;   // h_a = amp e^{-i ph}
+          const double tau = tc + dt;
+          const int64_t nsh = (int64_t)llrint(tau * fs);
+          const double rem = tau - (double)nsh / fs;
+          const int64_t nm_ = ((nsh % n_s) + n_s) % n_s;
+          const int64_t ph_int = ((j % n_s) * nm_) % n_s;
+          double se, ce;
+          sincospi(-2.0 * ((double)ph_int / (double)n_s + f * rem), &se, &ce);
+          const double vr = Ar * xr - Ai * xi, vi = Ar * xi + Ai * xr;
+          hr += vr * ce - vi * se;
+          hi += vr * se + vi * ce;
+        }
+        const double2 d = Dk[j - j_lo];
+        zr += hr * d.x + hi * d.y;                       // Re(conj(h) d)
+        sw += (hr * hr + hi * hi) * wkk[j - j_lo];
+      }
+      const double v = rr * block_sum(zr, red) - 0.5 * rr * rr * block_sum(sw, red);
+      const double t = total + v;
+      comp += fabs(total) >= fabs(v) ? (total - t) + v : (v - t) + total;
+      total = t;
+    }
+    if (threadIdx.x == 0) lnl[g] = total + comp;
+    return;
+  }
   for (int k = 0; k < c.n_det; ++k) {
     double fp, fc, dt;
     detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);

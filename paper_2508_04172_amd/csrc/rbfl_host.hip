@@ -528,6 +528,47 @@ static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
 }
 
 // Synthetic data: coloured noise + the projected injection (Eq. projected_h_fd).
+// Projected signal of detector k in bin j on a rotating Earth: each mode a
+// contributes at its stationary-phase time t_a = t_c + Psi'(2f/m) / (2 pi)
+// (the referenced phase's slope), with the antenna pattern and delay of the
+// source at Earth-fixed longitude alpha - earth_rate (t_a - t_trig):
+// sum_a A_ka(t_a) h_a(f) e^{-2 pi i f (t_c + dt_k(t_a))}; amp scales h_a.
+static double2 rotating_signal_bin(const Ctx &c, const Binary &b, const YlmTerms *yneg, const YlmTerms *ypos, int k,
+                                   double alpha, double dec, double psi, double iota, double phi, double tc, int64_t j,
+                                   double amp) {
+  const double f = (double)j * c.df;
+  double hr = 0.0, hi = 0.0;
+  for (int a = 0; a < c.n_modes; ++a) {
+    const int l = c.modes[a][0], m = c.modes[a][1];
+    if (!(f < (double)m * b.f_isco)) continue;
+    const double x = 2.0 * f / (double)m;
+    const double ta = tc + (dphase22_pn(x, b) - b.dpsi_ref) / (2.0 * kPi);
+    double fp, fc, dt;
+    detector_response(c.D[k], c.r[k], alpha - c.earth_rate * (ta - c.t_trig), dec, psi, &fp, &fc, &dt);
+    double nr, ni, pr, pi;
+    ylm_value(yneg[a], iota, phi, &nr, &ni);
+    ylm_value(ypos[a], iota, phi, &pr, &pi);
+    const double sg = (l & 1) ? -1.0 : 1.0;
+    const double Ar = 0.5 * ((fp * nr - fc * ni) + sg * (fp * pr - fc * pi));
+    const double Ai = 0.5 * ((fp * ni + fc * nr) + sg * (-fp * pi - fc * pr));
+    const double ph = 0.5 * (double)m * phase22(x, b);
+    const double am = mode_amp(l, m, b.eta, b.delta) * amp * exp(-7.0 / 6.0 * log(f));
+    const double xr = am * cos(ph), xi = -am * sin(ph);   // h = am e^{-i ph}
+    // e^{-2 pi i f tau}, tau = t_c + dt: whole samples reduced exactly, then the remainder
+    const double tau = tc + dt;
+    const int64_t nsh = (int64_t)llround(tau * c.fs);
+    const double rem = tau - (double)nsh / c.fs;
+    int64_t jm = (j % c.n_s) * (((nsh % c.n_s) + c.n_s) % c.n_s) % c.n_s;
+    const double frac = (double)jm / (double)c.n_s + f * rem;
+    double sn, cs;
+    sincos(-2.0 * kPi * frac, &sn, &cs);
+    const double vr = Ar * xr - Ai * xi, vi = Ar * xi + Ai * xr;
+    hr += vr * cs - vi * sn;
+    hi += vr * sn + vi * cs;
+  }
+  return make_double2(hr, hi);
+}
+
 static void synthesise_data(const rbfl_build_spec &s, const Ctx &c, const std::vector<std::vector<double>> &psd,
                             const YlmTerms *yneg, const YlmTerms *ypos, std::vector<std::vector<double2>> &data,
                             double *d_inj) {
@@ -540,6 +581,19 @@ static void synthesise_data(const rbfl_build_spec &s, const Ctx &c, const std::v
   Sum rho2;
   const double amp1 = b.amp / kMpcS;   // at 1 Mpc
   for (int k = 0; k < c.n_det; ++k) {
+    if (c.earth_rate != 0.0) {
+      // rotating Earth: every (bin, mode) at its own stationary-phase time
+      Sum e;
+      for (int64_t j = j_lo; j < j_hi; ++j) {
+        const double f = (double)j * c.df;
+        const double2 v = rotating_signal_bin(c, b, yneg, ypos, k, alpha, dec, psi, iota, phi, s.t_trig, j, amp1);
+        sig[k][j] = v;
+        e.add((v.x * v.x + v.y * v.y) / psd[k][j]);
+        (void)f;
+      }
+      rho2.add(4.0 * c.df * e.value());
+      continue;
+    }
     double fp, fc, dt;
     detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
     double Ar[RBFL_MAX_MODES], Ai[RBFL_MAX_MODES];
@@ -598,6 +652,7 @@ static void validate(const rbfl_build_spec *s) {
   require(s != nullptr, "spec is NULL");
   require(s->abi_version == RBFL_ABI_VERSION, "abi_version mismatch");
   require(std::isfinite(s->f_ref) && s->f_ref < 0.5 * s->fs, "f_ref must be finite and below fs / 2");
+  require(std::isfinite(s->earth_rate) && fabs(s->earth_rate) < 1.0, "earth_rate must be finite, |rate| < 1 rad/s");
   require((s->flags & ~(uint32_t)(RBFL_FLAG_CENTER_NODE | RBFL_FLAG_SQUEEZE | RBFL_FLAG_OPTIMISE_CENTRE)) == 0,
           "unknown flag bits");
   require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
@@ -1039,6 +1094,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.eps = s->eps;
   c.chi_max = s->chi_max;
   c.t_trig = s->t_trig;
+  c.earth_rate = s->earth_rate;
   c.match = s->match;
   c.q = s->q;
   c.half_w = (int)floor(s->half_window * s->fs + 1e-9);
@@ -1447,6 +1503,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   e.f0 = c.f_low;
   e.chi_max = c.chi_max;
   e.f_ref = c.f_ref;
+  e.earth_rate = c.earth_rate;
   for (int i = 0; i < 4; ++i) {
     e.theta_c[i] = c.theta_c[i];
     e.semi[i] = c.semi[i];

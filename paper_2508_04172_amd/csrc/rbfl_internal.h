@@ -35,6 +35,7 @@ struct EvalConsts {
   int poly_idx[kMaxPoly][3];                // variable indices of each monomial, -1 = unused
   double eps2, fs, t_trig, d_ref, f0, chi_max;
   double f_ref;                             // template time/phase reference frequency (0: coalescence)
+  double earth_rate;                        // Earth rotation [rad/s] in the exact likelihood (0: frozen)
   double theta_c[4], V[16], semi[4];        // V row-major: Theta_i = theta_c_i + sum_j V[i][j] de_j
   double D[RBFL_MAX_DET][9], r[RBFL_MAX_DET][3];
   int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
@@ -111,6 +112,7 @@ struct Ctx {
   double fs = 0, seg_len = 0, f_low = 0, df = 0;
   double eps = 0, chi_max = 1, t_trig = 0, d_ref = 0, match = 0;
   double f_ref = 0;            // template time/phase reference frequency (0: coalescence)
+  double earth_rate = 0;       // Earth rotation [rad/s] in the exact likelihood and the injection
   double squeeze[2] = {1, 0};  // factor applied to the longest semi-axis, true match at its new tip
   double centre_opt[6] = {};   // centre used (m1, m2, chi1, chi2) and the optimiser's iota, phi
   double centre_snr[2] = {};   // network SNR at the given centre (iota = phi = 0) and at the optimum

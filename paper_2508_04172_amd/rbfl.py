@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_MODES = 5
 MAX_DET = 4
 
@@ -69,6 +69,7 @@ class BuildSpec(C.Structure):
         ("chi_max", C.c_double),
         ("flags", C.c_uint32),
         ("f_ref", C.c_double),
+        ("earth_rate", C.c_double),
     ]
 
 
@@ -261,6 +262,7 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
     s.flags = ((FLAG_CENTER_NODE if cfg.center_node else 0) | (FLAG_SQUEEZE if cfg.squeeze else 0)
                | (FLAG_OPTIMISE_CENTRE if getattr(cfg, "optimise_centre", False) else 0))
     s.f_ref = cfg.f_ref
+    s.earth_rate = getattr(cfg, "earth_rate", 0.0)
     return s
 
 

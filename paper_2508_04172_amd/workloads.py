@@ -71,6 +71,7 @@ class Config:
     squeeze: bool = False                         # contract the longest ellipsoid axis to the true-match crossing
     optimise_centre: bool = False                 # move the centre to the network-SNR optimum first
     centre_offset: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)   # seed = injection + offset
+    earth_rate: float = 0.0                       # Earth rotation [rad/s] in the exact model and the injection
 
     @property
     def n_det(self) -> int:

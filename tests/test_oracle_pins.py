@@ -576,3 +576,45 @@ def test_centre_optimum_reaches_the_cauchy_schwarz_bound():
     # the objective at the injection itself is the bound (any iota, phi for the (2,2) mode)
     s2 = su.network_snr2(ev, cfg.inj_phys, 0.4, 1.0, cfg.half_window)
     assert s2 == pytest.approx(cfg.inj_snr ** 2, rel=1e-6)
+
+
+# ---------------------------------------------------------------- rotating Earth
+
+def test_rotating_signal_reduces_to_the_frozen_one():
+    """With a vanishing rotation rate the rotating-Earth signal (per-bin
+    antenna factors and delays at each mode's stationary-phase time) equals
+    the frozen projected signal of Eq. projected_h_fd."""
+    cfg = TINY_MULTI
+    ev = su.make_event(cfg, None, wl.injection_extrinsics(cfg))
+    ext = np.array([1.1, -0.4, 0.7, 1.2, 2.3])
+    for k in range(ev.n_det):
+        a = ph.detector_signal(ev.grid, ev.modes, cfg.inj_phys, 100.0, ext, ev.t_trig + 0.01, ev.det_tensor[k],
+                               ev.det_pos[k])
+        b = ph.detector_signal(ev.grid, ev.modes, cfg.inj_phys, 100.0, ext, ev.t_trig + 0.01, ev.det_tensor[k],
+                               ev.det_pos[k], 1e-30, ev.t_trig)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_rotating_signal_closed_form_on_the_equator():
+    """A face-on (2,2) source on the equator seen by an equatorial detector with
+    arms along x and y at the geocentre: |F+ - i Fx| = |cos 2(lon)| / 2 with
+    lon the source's Earth-fixed longitude, so |h_k(f)| / |h_22(f)| =
+    |Y_22(0)| |cos 2(alpha - rate (t(f) - t_ref))| / 4 at every bin; alpha is
+    off zero so that the sign of the rotation matters."""
+    grid = ph.Grid(1024.0, 8.0, 20.0, 137.0)
+    D = 0.5 * (np.outer([1.0, 0, 0], [1.0, 0, 0]) - np.outer([0, 1.0, 0], [0, 1.0, 0]))
+    pos = np.zeros(3)
+    phys = (8.0, 1.4, 0.3, 0.0)
+    alpha, rate, t_c, t_ref = 0.3, 0.02, 5.0, 4.0
+    ext = np.array([alpha, 0.0, 0.0, 0.0, 0.0])
+    h = ph.detector_signal(grid, ((2, 2),), phys, 100.0, ext, t_c, D, pos, rate, t_ref)
+    h22 = ph.waveform_mode(grid, 2, 2, phys, 100.0)
+    j0, j1 = ph.mode_band(grid, 2, phys[0], phys[1])
+    f = np.arange(j0, j1) * grid.df
+    t = ph.spa_time(f, 2, phys, grid.f_ref, t_c)
+    want = abs(ph.ylm(2, 2, 0.0, 0.0)) * np.abs(np.cos(2.0 * (alpha - rate * (t - t_ref)))) / 4.0
+    got = np.abs(h[j0:j1]) / np.abs(h22[j0:j1])
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-12)
+    # the band spans a sizeable rotation, and the (2,2) mode passes f_ref at t_c
+    assert np.ptp(rate * t) > 0.05
+    assert ph.spa_time(np.array([grid.f_ref]), 2, phys, grid.f_ref, t_c)[0] == pytest.approx(t_c, abs=1e-9)
