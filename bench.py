@@ -147,6 +147,9 @@ def main():
             h.prepare(form)
         tune[name] = h.autotune(params.data_ptr(), n, form, sp)
         log(f"autotune {name}: variant {tune[name]['variant']}, ms per launch {tune[name]['ms']}")
+        if form == rbfl.FORM_FP64:
+            tune["fp64_pipeline"] = h.pipeline()
+            log(f"autotune fp64 pipeline: {tune['fp64_pipeline']}")
 
     def run_form(form, steps, warmup):
         for _ in range(warmup):
@@ -222,6 +225,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg.name, "form": "plain FP64", "proposals_per_step": n,
+                   "pipeline_chunks": tune["fp64_pipeline"]["chunks"],
                    "n_det": cfg.n_det, "modes": len(cfg.modes), "nodes": cfg.n_nodes, "q": cfg.q,
                    "K": K, "poly_degree": cfg.poly_degree, "eps": cfg.eps, "fs": cfg.fs,
                    "seg_len": cfg.seg_len, "f_low": cfg.f_low, "startup_s": round(build_s, 3)},

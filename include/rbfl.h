@@ -17,9 +17,12 @@
  * only enqueues work and returns.  Asynchronous device faults surface as
  * RBFL_E_DEVICE from a later call or from the caller's own synchronisation.
  *
- * Threading: rbfl_eval may run concurrently on different streams with one
- * handle (the handle is read-only while evaluating) unless noted otherwise;
- * rbfl_build, rbfl_prepare and rbfl_destroy need exclusive use of a handle.
+ * Threading: a handle owns one work space (the interpolated outputs and
+ * basis rows of a chunk), so rbfl_eval and rbfl_interp calls on one handle
+ * must not overlap on the device: issue them on one stream, or order calls
+ * on different streams with events.  Different handles are independent.
+ * rbfl_build, rbfl_prepare, rbfl_autotune, rbfl_pipeline and rbfl_destroy
+ * need exclusive use of a handle.
  */
 #ifndef RBFL_H
 #define RBFL_H
@@ -31,7 +34,7 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 3
+#define RBFL_ABI_VERSION 4
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
 
@@ -260,9 +263,11 @@ enum rbfl_query_what {
   RBFL_Q_F_REF = 16,        /* double[1]: template time/phase reference frequency [Hz] (0: coalescence) */
   RBFL_Q_SQUEEZE = 17,      /* double[2]: factor applied to the longest semi-axis (1 = none) and the true
                                match at the squeezed tip (0 when not squeezed) */
-  RBFL_Q_CENTRE = 18        /* double[8]: the ellipsoid centre used (m1, m2, chi1, chi2), the optimiser's
+  RBFL_Q_CENTRE = 18,       /* double[8]: the ellipsoid centre used (m1, m2, chi1, chi2), the optimiser's
                                iota and phi, the network SNR at center_phys (iota = phi = 0) and at the
                                optimum (0, 0 without RBFL_FLAG_OPTIMISE_CENTRE) */
+  RBFL_Q_PIPELINE = 19      /* double[5]: chunks per FP64 evaluation in use (rbfl_pipeline), then the
+                               autotuner's median ms per evaluation at 1, 2, 4 and 8 chunks (0 = not timed) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
@@ -277,6 +282,21 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * exclusive use of the handle. */
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
+
+/* Pipelined FP64 evaluation (Sec. II D's online stage, reordered, not changed):
+ * rbfl_eval of the FP64 form splits a call into `chunks` chunks (1 = the
+ * serial order, at most 64) whose epilogues (arrival times, reconstruction
+ * and Eq. logl_complete) run on a second, handle-owned stream of default
+ * priority under the next chunk's basis rows and MFMA product; the work space
+ * is split in two halves that the chunks alternate between, and the caller's
+ * stream waits for every epilogue before the call returns, so the call stays
+ * ordered on `stream` as before.  ln L is bit-identical to the serial order.
+ * Used only when the work capacity holds two halves of at least 4096
+ * proposals, for calls of more than 4096 proposals, and never while `stream`
+ * is being captured.  rbfl_autotune of RBFL_FORM_FP64 times 1, 2, 4 and 8
+ * chunks and keeps the fastest (RBFL_Q_PIPELINE).  Needs exclusive use of
+ * the handle; RBFL_E_INVALID_ARG for chunks outside 1..64. */
+int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it
  * on, rbfl_eval records HIP events around the basis-row, contraction and

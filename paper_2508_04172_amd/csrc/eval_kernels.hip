@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
 // forms Re(conj(A) z), the detector's first lane the overlap term, lane 0 the
 // sum, all with compensated (Neumaier) additions.
 constexpr int kEpiBatch = 64;
+static_assert(kEpiBatch + RBFL_MAX_DET * RBFL_MAX_MODES <= kThreads, "offset copy threads");
 
 struct EpiSetup {
   int status;                       // 0 evaluate, 1 outside the domain (-inf), 2 NaN input
@@ -293,9 +294,17 @@ __device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__r
 }
 
 // ln L of one proposal from its setup o and interpolated row y; one whole
-// wave per call, result written to *out by lane 0.
+// wave per call, result written to *out by lane 0.  The loads of each stage
+// are issued together before their values are used (kEpiUnroll coefficients
+// per lane at a time, the detector's overlap reals one per lane), so a
+// proposal waits for a few memory round trips instead of one per coefficient.
+constexpr int kEpiUnroll = 4;
+
+// coef_off / sig_off: the output offsets of the consts (an LDS copy where the
+// block has one).
 __device__ __forceinline__ void epi_reduce(const EvalConsts &c, const EpiSetup &o, const double *__restrict__ y,
-                                           const double2 *__restrict__ basis4, double *__restrict__ out) {
+                                           const double2 *__restrict__ basis4, double *__restrict__ out,
+                                           const int (*coef_off)[RBFL_MAX_MODES], const int *sig_off) {
   const int lane = threadIdx.x & 63;
   if (o.status != 0) {
     if (lane == 0) *out = o.status == 2 ? __builtin_nan("") : -__builtin_huge_val();
@@ -312,19 +321,51 @@ __device__ __forceinline__ void epi_reduce(const EvalConsts &c, const EpiSetup &
   const double f = o.f[k];
   const int n0 = o.n0[k];
   const double ar = o.Ar[k][a], ai = o.Ai[k][a];
+  const int det_lead = k * n_modes * G;
+  // detector k's overlap reals: lane det_lead + t holds term t (t < n_modes:
+  // sigma_tt; then (Re, Im) sigma_ab for a < b in lexicographic order).  A
+  // detector owns n_modes * G >= n_modes (n_modes + 1) / 2 lanes for up to 4
+  // detectors and 5 modes.
+  const int n_terms = n_modes * (n_modes + 1) / 2;
+  const int t_own = lane - det_lead;
+  double sg_a = 0.0, sg_b = 0.0;
+  if (active && t_own < n_terms) {
+    const int so = sig_off[k];
+    if (t_own < n_modes) {
+      sg_a = y[so + t_own];
+    } else {
+      const int pidx = so + n_modes + 2 * (t_own - n_modes);
+      sg_a = y[pidx];
+      sg_b = y[pidx + 1];
+    }
+  }
   // a5: partial reconstruction of z_{k,a} over this lane's coefficients; the
   // spline-folded basis gives the interpolated basis value as a cubic in f
   double zr = 0.0, zi = 0.0;
   if (active) {
-    const int off = c.coef_off[k][a];
+    const int off = coef_off[k][a];
     const double2 *base = basis4 + ((int64_t)(k * n_modes + a) * T + n0) * q * 4;
-    for (int i = gl; i < q; i += G) {
-      const double2 cc = *reinterpret_cast<const double2 *>(y + off + 2 * i);
-      const double2 v0 = base[4 * i], v1 = base[4 * i + 1], v2 = base[4 * i + 2], v3 = base[4 * i + 3];
-      const double br = fma(fma(fma(v3.x, f, v2.x), f, v1.x), f, v0.x);
-      const double bi = fma(fma(fma(v3.y, f, v2.y), f, v1.y), f, v0.y);
-      zr += cc.x * br - cc.y * bi;
-      zi += cc.x * bi + cc.y * br;
+    for (int i0 = gl; i0 < q; i0 += kEpiUnroll * G) {
+      double2 cc[kEpiUnroll], v[kEpiUnroll][4];
+#pragma unroll
+      for (int u = 0; u < kEpiUnroll; ++u) {
+        // past the end: a valid entry is loaded and its coefficient zeroed,
+        // so that every load is issued before the first use
+        const bool ok = i0 + u * G < q;
+        const int i = ok ? i0 + u * G : i0;
+        const double2 cv = *reinterpret_cast<const double2 *>(y + off + 2 * i);
+        cc[u].x = ok ? cv.x : 0.0;
+        cc[u].y = ok ? cv.y : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[u][j] = base[4 * i + j];
+      }
+#pragma unroll
+      for (int u = 0; u < kEpiUnroll; ++u) {
+        const double br = fma(fma(fma(v[u][3].x, f, v[u][2].x), f, v[u][1].x), f, v[u][0].x);
+        const double bi = fma(fma(fma(v[u][3].y, f, v[u][2].y), f, v[u][1].y), f, v[u][0].y);
+        zr += cc[u].x * br - cc[u].y * bi;
+        zi += cc[u].x * bi + cc[u].y * br;
+      }
     }
   }
   // combine the G partials of each pair in its first lane (fixed order)
@@ -336,7 +377,6 @@ __device__ __forceinline__ void epi_reduce(const EvalConsts &c, const EpiSetup &
   }
   const double zterm = ar * tr + ai * ti;   // Re(conj(A) z), valid in pair leaders
   // overlap term of detector k: every A_{k,b} is in the setup
-  const int det_lead = k * n_modes * G;
   double st_s = 0.0, st_c = 0.0, zt_s = 0.0, zt_c = 0.0;
   {
     auto add = [](double &sum, double &comp, double v) {
@@ -344,16 +384,15 @@ __device__ __forceinline__ void epi_reduce(const EvalConsts &c, const EpiSetup &
       comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
       sum = t;
     };
-    const int so = c.sig_off[k];
     for (int m = 0; m < n_modes; ++m) {
       add(zt_s, zt_c, __shfl(zterm, det_lead + m * G, 64));
-      add(st_s, st_c, (o.Ar[k][m] * o.Ar[k][m] + o.Ai[k][m] * o.Ai[k][m]) * y[so + m]);
+      add(st_s, st_c, (o.Ar[k][m] * o.Ar[k][m] + o.Ai[k][m] * o.Ai[k][m]) * __shfl(sg_a, det_lead + m, 64));
     }
-    int pidx = so + n_modes;
+    int t = n_modes;
     for (int m = 0; m < n_modes; ++m)
       for (int mm = m + 1; mm < n_modes; ++mm) {
-        const double sr = y[pidx], si = y[pidx + 1];
-        pidx += 2;
+        const double sr = __shfl(sg_a, det_lead + t, 64), si = __shfl(sg_b, det_lead + t, 64);
+        ++t;
         const double pr = o.Ar[k][m] * o.Ar[k][mm] + o.Ai[k][m] * o.Ai[k][mm];
         const double pi = o.Ar[k][m] * o.Ai[k][mm] - o.Ai[k][m] * o.Ar[k][mm];
         add(st_s, st_c, 2.0 * (pr * sr - pi * si));
@@ -376,14 +415,20 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
                                                        int64_t nb, const double *__restrict__ Y,
                                                        const double2 *__restrict__ basis4, double *__restrict__ lnl) {
   __shared__ EpiSetup su[kEpiBatch];
+  __shared__ int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
   const EvalConsts &c = *cp;
   const int64_t first = (int64_t)blockIdx.x * kEpiBatch;
   if (threadIdx.x < kEpiBatch && first + threadIdx.x < nb) epi_setup(c, params, ld, b0 + first + threadIdx.x, su[threadIdx.x]);
+  if (threadIdx.x >= kEpiBatch && threadIdx.x < kEpiBatch + RBFL_MAX_DET * RBFL_MAX_MODES) {
+    const int e = threadIdx.x - kEpiBatch;
+    coef_off[e / RBFL_MAX_MODES][e % RBFL_MAX_MODES] = c.coef_off[e / RBFL_MAX_MODES][e % RBFL_MAX_MODES];
+    if (e < RBFL_MAX_DET) sig_off[e] = c.sig_off[e];
+  }
   __syncthreads();
   for (int j = threadIdx.x >> 6; j < kEpiBatch; j += kWaves) {
     const int64_t b = first + j;
     if (b >= nb) break;   // whole wave leaves together
-    epi_reduce(c, su[j], Y + b * c.Kp, basis4, lnl + b0 + b);
+    epi_reduce(c, su[j], Y + b * c.Kp, basis4, lnl + b0 + b, coef_off, sig_off);
   }
 }
 
@@ -492,7 +537,7 @@ __global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *_
     const int64_t g = first + j;
     if (g >= total) break;   // whole wave leaves together
     const EventDesc &d = ev[su[j].event];
-    epi_reduce(*d.consts, su[j], d.Y + (g - d.q0) * d.Kp, d.basis, lnl + g);
+    epi_reduce(*d.consts, su[j], d.Y + (g - d.q0) * d.Kp, d.basis, lnl + g, d.consts->coef_off, d.consts->sig_off);
   }
 }
 

@@ -1617,13 +1617,87 @@ static void reserve(Ctx &c, int64_t n) {
 static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64_t nb, int form, hipStream_t s,
                      hipEvent_t *marks = nullptr);
 
-static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
-  require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
-  require(n >= 0, "n must be >= 0");
-  if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
-  if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+// True when `s` is being captured into a graph (or its capture state cannot
+// be read): the pipelined order forks onto a second stream, so such calls
+// keep the serial order.
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Pipelined FP64 evaluation of proposals [0, n) (leading dimension ld): the
+// basis rows and MFMA product of each chunk run on the caller's stream, its
+// epilogue on the handle's side stream, so that the epilogue of chunk i
+// (bound by memory latency) runs under the product of chunk i + 1 (bound by
+// the matrix cores).  Chunks alternate between the two halves of the work
+// space; the product of chunk i + 2 waits for the epilogue of chunk i, and the
+// caller's stream waits for the last epilogues before the call returns.  Every
+// proposal goes through the same arithmetic as in the serial order, so ln L
+// is bit-identical.
+static void eval_pipelined(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, hipStream_t s) {
+  const int64_t half = (c.cap / 2) & ~int64_t(7);
+  int64_t ch = (n + c.pipe - 1) / c.pipe;
+  ch = std::min(half, (ch + 7) & ~int64_t(7));
+  if (!c.side) {
+    RBFL_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    for (int h = 0; h < 2; ++h) {
+      RBFL_HIP(hipEventCreateWithFlags(&c.pev_prod[h], hipEventDisableTiming));
+      RBFL_HIP(hipEventCreateWithFlags(&c.pev_epi[h], hipEventDisableTiming));
+    }
+  }
+  const int v = c.variant[RBFL_FORM_FP64];
+  const bool two_stage = v < gemm_fp64_variants();
+  int i = 0;
+  for (int64_t b0 = 0; b0 < n; b0 += ch, ++i) {
+    const int64_t nb = std::min(ch, n - b0);
+    const int h = i & 1;
+    double *Y = c.Y.p + (size_t)h * half * c.Kp;
+    double *Bt = c.Bt.p + (size_t)h * c.rows * half;
+    hipEvent_t ev[6];
+    auto mark = [&](int k, hipStream_t st) {
+      if (c.profile) RBFL_HIP(hipEventRecord(ev[k], st));
+    };
+    if (c.profile)
+      for (auto &e : ev) {
+        RBFL_HIP(hipEventCreate(&e));
+        c.timed_events.push_back(e);
+      }
+    mark(0, s);
+    if (two_stage) launch_rows_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, Bt, s);
+    mark(1, s);
+    if (i >= 2) RBFL_HIP(hipStreamWaitEvent(s, c.pev_epi[h], 0));
+    mark(2, s);
+    if (two_stage) launch_gemm_fp64(Bt, nb, c.host_consts, c.W.p, Y, s, v);
+    else launch_contract_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.W.p, Y, s, 2);
+    mark(3, s);
+    RBFL_HIP(hipEventRecord(c.pev_prod[h], s));
+    RBFL_HIP(hipStreamWaitEvent(c.side, c.pev_prod[h], 0));
+    mark(4, c.side);
+    launch_epilogue(c.consts.p, c.host_consts, params, ld, b0, nb, Y, c.basis4.p, lnl, c.side);
+    mark(5, c.side);
+    RBFL_HIP(hipEventRecord(c.pev_epi[h], c.side));
+    if (c.profile) {
+      if (two_stage) c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
+      c.timed.push_back(Ctx::Timed{ev[2], ev[3], 0, nb});
+      c.timed.push_back(Ctx::Timed{ev[4], ev[5], 1, nb});
+    }
+  }
+  for (int h = 0; h < std::min(i, 2); ++h) RBFL_HIP(hipStreamWaitEvent(s, c.pev_epi[h], 0));
+}
+
+// ln L of proposals [0, n) of a parameter array with leading dimension ld.
+static void eval_range(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, int form, hipStream_t s) {
   if (n == 0) return;
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
+  const bool fp64 = form == RBFL_FORM_FP64 || (form == RBFL_FORM_SURROGATE && !(c.sur && c.sur_ok));
+  if (fp64 && c.pipe > 1 && c.cap / 2 >= 4096 && n > 4096 && !capturing(s)) {
+    eval_pipelined(c, params, ld, n, lnl, s);
+    return;
+  }
   for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
     const int64_t nb = std::min(c.cap, n - b0);
     if (c.profile) {
@@ -1633,17 +1707,25 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
         RBFL_HIP(hipEventCreate(&e));
         c.timed_events.push_back(e);
       }
-      contract(c, params, n, b0, nb, form, s, ev);
-      launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis4.p, lnl, s);
+      contract(c, params, ld, b0, nb, form, s, ev);
+      launch_epilogue(c.consts.p, c.host_consts, params, ld, b0, nb, c.Y.p, c.basis4.p, lnl, s);
       RBFL_HIP(hipEventRecord(ev[3], s));
       c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
       c.timed.push_back(Ctx::Timed{ev[1], ev[2], 0, nb});
       c.timed.push_back(Ctx::Timed{ev[2], ev[3], 1, nb});
       continue;
     }
-    contract(c, params, n, b0, nb, form, s);
-    launch_epilogue(c.consts.p, c.host_consts, params, n, b0, nb, c.Y.p, c.basis4.p, lnl, s);
+    contract(c, params, ld, b0, nb, form, s);
+    launch_epilogue(c.consts.p, c.host_consts, params, ld, b0, nb, c.Y.p, c.basis4.p, lnl, s);
   }
+}
+
+static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
+  require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
+  require(n >= 0, "n must be >= 0");
+  if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
+  if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+  eval_range(c, params, n, n, lnl, form, s);
 }
 
 // The contraction of proposals [b0, b0 + nb) into the work space Y, in two
@@ -1802,6 +1884,42 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
       if (med[v] <= 1.02 * best_ms && gemm_fp64_reuse(v) > gemm_fp64_reuse(best)) best = v;
   }
   c.variant[form] = best >= 0 ? best : kSplitDefaultVariant;
+  // FP64: with the chosen tile, time whole evaluations of the nb proposals in
+  // 1 (serial), 2, 4 and 8 pipelined chunks and keep the fastest
+  if (form == RBFL_FORM_FP64 && c.cap / 2 >= 4096 && nb > 4096 && !capturing(s)) {
+    static const int depths[4] = {1, 2, 4, 8};
+    DevBuf<double> out;
+    out.alloc(nb);
+    const bool prof = c.profile;
+    c.profile = false;
+    double pm[4] = {1e300, 1e300, 1e300, 1e300};
+    for (int round = 0; round < 2; ++round)
+      for (int d = 0; d < 4; ++d) {
+        c.pipe = depths[d];
+        if (round == 0) eval_range(c, params, n, nb, out.p, form, s);
+        double t[3];
+        for (int r = 0; r < 3; ++r) {
+          RBFL_HIP(hipEventRecord(e0, s));
+          eval_range(c, params, n, nb, out.p, form, s);
+          RBFL_HIP(hipEventRecord(e1, s));
+          RBFL_HIP(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+          t[r] = ms;
+        }
+        std::sort(t, t + 3);
+        pm[d] = std::min(pm[d], t[1]);
+      }
+    // a pipelined order must beat the serial one by 1% (timing noise is
+    // about that size): otherwise the serial order is kept
+    int bd = 0;
+    for (int d = 1; d < 4; ++d)
+      if (pm[d] < 0.99 * pm[0] && pm[d] < pm[bd]) bd = d;
+    c.pipe = depths[bd];
+    for (int d = 0; d < 4; ++d) c.pipe_ms[d] = pm[d];
+    c.profile = prof;
+    RBFL_HIP(hipStreamSynchronize(s));
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -2015,6 +2133,11 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
         v[9 * f] = c.variant[f];
         for (int i = 0; i < 8; ++i) v[9 * f + 1 + i] = c.tune_ms[f][i];
       }
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
+    case RBFL_Q_PIPELINE: {
+      double v[5] = {(double)c.pipe, c.pipe_ms[0], c.pipe_ms[1], c.pipe_ms[2], c.pipe_ms[3]};
       copy_out(out, bytes, v, sizeof(v));
       return;
     }
@@ -2589,6 +2712,14 @@ int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t fo
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
     rbfl::autotune(h->c, params, n, form, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(chunks >= 1 && chunks <= 64, "chunks must be in 1..64");
+    h->c.pipe = chunks;
   });
 }
 

@@ -152,6 +152,13 @@ struct Ctx {
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
   int64_t cap = 0;
   int graph_users = 0;         // live samplers whose captured step uses Y / Bt / the weight copies
+  // pipelined FP64 evaluation (rbfl_pipeline): chunks per call (1 = serial),
+  // the side stream that runs the epilogues, per work-space half the events
+  // "product done" and "epilogue done", and the autotuner's timings
+  int pipe = 1;
+  double pipe_ms[4] = {};
+  hipStream_t side = nullptr;
+  hipEvent_t pev_prod[2] = {nullptr, nullptr}, pev_epi[2] = {nullptr, nullptr};
   EvalConsts host_consts;
   // surrogate (rbfl_surrogate_train)
   Mlp *sur = nullptr;
@@ -176,6 +183,11 @@ struct Ctx {
   ~Ctx() {
     delete sur;
     drop_timed();
+    for (auto e : pev_prod)
+      if (e) (void)hipEventDestroy(e);
+    for (auto e : pev_epi)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 

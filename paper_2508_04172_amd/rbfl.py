@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_MODES = 5
 MAX_DET = 4
 
@@ -26,11 +26,12 @@ FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
 FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
-    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE = range(19)
+    Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
+    Q_PIPELINE = range(20)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
-            "rbfl_query", "rbfl_autotune", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
+            "rbfl_query", "rbfl_autotune", "rbfl_pipeline", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
             "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
@@ -157,6 +158,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
     lib.rbfl_autotune.restype = C.c_int32
     lib.rbfl_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.rbfl_pipeline.restype = C.c_int32
+    lib.rbfl_pipeline.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_profile.restype = C.c_int32
     lib.rbfl_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_plan_create.restype = C.c_int32
@@ -414,6 +417,15 @@ class Handle:
         return {"accepted": bool(v[0]), "holdout_max_dlnl": float(v[1]), "holdout_median_dlnl": float(v[2]),
                 "first_loss": float(v[3]), "last_loss": float(v[4]), "epochs": int(v[5]),
                 "train_s": float(v[6]), "n_train": int(v[7])}
+
+    def set_pipeline(self, chunks: int):
+        """Chunks per FP64 evaluation (1 = serial order); the autotuner sets it."""
+        _check(load().rbfl_pipeline(self._h, chunks))
+
+    def pipeline(self) -> dict:
+        """Chunks in use and the autotuner's ms per evaluation at 1, 2, 4, 8 chunks (RBFL_Q_PIPELINE)."""
+        v = self._query(Q_PIPELINE, 5)
+        return {"chunks": int(v[0]), "ms": {d: float(x) for d, x in zip((1, 2, 4, 8), v[1:]) if x > 0}}
 
     def profile(self, on: bool):
         _check(load().rbfl_profile(self._h, 1 if on else 0))
