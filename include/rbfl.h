@@ -283,6 +283,17 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
+/* Number of contraction tile variants of `form` (RBFL_FORM_FP64 .. SPLIT),
+ * or RBFL_E_INVALID_ARG for another form. */
+int32_t rbfl_variants(int32_t form);
+
+/* Pins the contraction tile variant of `form` (0 <= variant <
+ * rbfl_variants(form)) instead of the autotuner's choice.  FP64 variants are
+ * tile shapes of one arithmetic (ln L identical); split-form variants are
+ * digit counts (S = 5 + variant).  RBFL_E_STATE if the form is not prepared;
+ * needs exclusive use of the handle. */
+int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant);
+
 /* Pipelined FP64 evaluation (Sec. II D's online stage, reordered, not changed):
  * rbfl_eval of the FP64 form splits a call into `chunks` chunks (1 = the
  * serial order, at most 64) whose epilogues (arrival times, reconstruction

@@ -2715,6 +2715,21 @@ int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t fo
   });
 }
 
+int32_t rbfl_variants(int32_t form) {
+  if (form < 0 || form > RBFL_FORM_SPLIT) return RBFL_E_INVALID_ARG;
+  return rbfl::contract_variants(form);
+}
+
+int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    if (form < 0 || form > RBFL_FORM_SPLIT) throw rbfl::Error(RBFL_E_INVALID_ARG, "unknown or untunable form");
+    if (!h->c.prepared[form]) throw rbfl::Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
+    rbfl::require(variant >= 0 && variant < rbfl::contract_variants(form), "variant out of range");
+    h->c.variant[form] = variant;
+  });
+}
+
 int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");

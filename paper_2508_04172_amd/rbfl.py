@@ -31,7 +31,8 @@ Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALU
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
-            "rbfl_query", "rbfl_autotune", "rbfl_pipeline", "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
+            "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
+            "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
             "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
@@ -158,6 +159,10 @@ def load(path: str = LIB_PATH):
     lib.rbfl_query.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
     lib.rbfl_autotune.restype = C.c_int32
     lib.rbfl_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.rbfl_variants.restype = C.c_int32
+    lib.rbfl_variants.argtypes = [C.c_int32]
+    lib.rbfl_set_variant.restype = C.c_int32
+    lib.rbfl_set_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.rbfl_pipeline.restype = C.c_int32
     lib.rbfl_pipeline.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_profile.restype = C.c_int32
@@ -418,6 +423,10 @@ class Handle:
                 "first_loss": float(v[3]), "last_loss": float(v[4]), "epochs": int(v[5]),
                 "train_s": float(v[6]), "n_train": int(v[7])}
 
+    def set_variant(self, form: int, variant: int):
+        """Pins the contraction tile variant of `form` (rbfl_set_variant)."""
+        _check(load().rbfl_set_variant(self._h, form, variant))
+
     def set_pipeline(self, chunks: int):
         """Chunks per FP64 evaluation (1 = serial order); the autotuner sets it."""
         _check(load().rbfl_pipeline(self._h, chunks))
@@ -435,6 +444,14 @@ class Handle:
         return {"contract_ms": v[0], "contract_launches": int(v[1]), "contract_n": int(v[2]),
                 "epilogue_ms": v[3], "epilogue_launches": int(v[4]), "epilogue_n": int(v[5]),
                 "rows_ms": v[6], "rows_launches": int(v[7]), "rows_n": int(v[8])}
+
+
+def variants(form: int) -> int:
+    """Number of contraction tile variants of `form` (rbfl_variants)."""
+    v = load().rbfl_variants(form)
+    if v < 0:
+        raise ValueError(f"no tile variants for form {form}")
+    return v
 
 
 def split_slices(variant: int) -> int:

@@ -171,6 +171,35 @@ def test_lnl_parity_near_nodes(name):
     assert d.max() <= 1e-3
 
 
+@pytest.mark.parametrize("name", ["small_multi", "ragged_tail"])
+def test_fp64_tile_variants(name):
+    """Every FP64 contraction tile variant (rows + GEMM tiles of several
+    shapes, chunk depths and prefetch distances, and the fused kernel) sums
+    each output over the same rows in the same order, so ln L is identical
+    across variants; variant 0 is held to the oracle bar as well."""
+    torch = _torch()
+    cfg, art, h = both(name)
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    q_gpu = qd.near_nodes(h.nodes(), idx, jit)
+    nv = rbfl.variants(rbfl.FORM_FP64)
+    outs = []
+    for v in range(nv):
+        h.set_variant(rbfl.FORM_FP64, v)
+        outs.append(torch.from_numpy(gpu_eval(h, q_gpu, cfg.t_trig)))
+    h.set_variant(rbfl.FORM_FP64, 0)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(outs[0].numpy()))
+    assert np.abs(outs[0].numpy()[fin] - lo[fin]).max() <= 1e-3
+    key = lambda t: torch.nan_to_num(t, nan=1.5, neginf=-2.5)
+    same = [bool(torch.equal(key(outs[0]), key(o))) for o in outs]
+    diff = [float((key(outs[0]) - key(o)).abs().max()) for o in outs]
+    print(f"[parity] {name}: {nv} FP64 variants, identical to variant 0: {same}, max |d| {diff}", flush=True)
+    assert all(same)
+
+
 @pytest.mark.timeout(1200)
 def test_cfg2_full_size_sampled():
     """The 3-detector, 5-mode workload at full size (N = 800, q = 40, 1e6
