@@ -298,7 +298,7 @@ __device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__r
 // are issued together before their values are used (kEpiUnroll coefficients
 // per lane at a time, the detector's overlap reals one per lane), so a
 // proposal waits for a few memory round trips instead of one per coefficient.
-constexpr int kEpiUnroll = 4;
+constexpr int kEpiUnroll = 2;
 
 // coef_off / sig_off: the output offsets of the consts (an LDS copy where the
 // block has one).

@@ -174,9 +174,9 @@ def test_lnl_parity_near_nodes(name):
 @pytest.mark.parametrize("name", ["small_multi", "ragged_tail"])
 def test_fp64_tile_variants(name):
     """Every FP64 contraction tile variant (rows + GEMM tiles of several
-    shapes, chunk depths and prefetch distances, and the fused kernel) sums
-    each output over the same rows in the same order, so ln L is identical
-    across variants; variant 0 is held to the oracle bar as well."""
+    shapes and chunk depths, and the fused kernel) sums each output over the
+    same rows in the same order, so ln L is identical across variants;
+    variant 0 is held to the oracle bar as well."""
     torch = _torch()
     cfg, art, h = both(name)
     n = min(cfg.n_queries, 3000)
