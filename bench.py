@@ -511,6 +511,9 @@ def bench_mixed(args, np, torch, rbfl, wl, cfg):
         if form == rbfl.FORM_SPLIT:
             f["slices"] = tune["slices"]
             f["max_dlnl_vs_fp64_per_slice_count"] = tune["max_dlnl_vs_fp64"][:4]
+        if form == rbfl.FORM_FP64:
+            f["order"] = h.pipeline()
+            log(f"mixed {cfg.name} fp64 order: {f['order']}")
         out["forms"][name] = f
         log(f"mixed {cfg.name} {name}: {n / wall:.4e} evals/s")
     if not args.no_cpu_baseline:

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 4
+#define RBFL_ABI_VERSION 5
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
 
@@ -266,8 +266,10 @@ enum rbfl_query_what {
   RBFL_Q_CENTRE = 18,       /* double[8]: the ellipsoid centre used (m1, m2, chi1, chi2), the optimiser's
                                iota and phi, the network SNR at center_phys (iota = phi = 0) and at the
                                optimum (0, 0 without RBFL_FLAG_OPTIMISE_CENTRE) */
-  RBFL_Q_PIPELINE = 19      /* double[5]: chunks per FP64 evaluation in use (rbfl_pipeline), then the
-                               autotuner's median ms per evaluation at 1, 2, 4 and 8 chunks (0 = not timed) */
+  RBFL_Q_PIPELINE = 19      /* double[7]: chunks per FP64 evaluation in use (rbfl_pipeline), the
+                               autotuner's median ms per evaluation at 1, 2, 4 and 8 chunks (0 = not
+                               timed), 1/0 for ln L finished inside the contraction (rbfl_fuse_epilogue)
+                               and the autotuner's ms per evaluation in that order (0 = not timed) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
@@ -308,6 +310,22 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant);
  * chunks and keeps the fastest (RBFL_Q_PIPELINE).  Needs exclusive use of
  * the handle; RBFL_E_INVALID_ARG for chunks outside 1..64. */
 int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks);
+
+/* ln L finished inside the FP64 contraction (Sec. II D's online stage, same
+ * terms regrouped): ln L of Eq. logl_complete (corrected reading) is linear in
+ * the interpolated outputs, ln L = sum_c coef_c Y[c], with coef_c formed from
+ * the proposal's distance ratio, amplitudes and spline-folded basis value.
+ * With `on` nonzero, rbfl_eval of the FP64 form writes each proposal's setup,
+ * contracts with a kernel that weights its output tile by coef_c and writes
+ * one partial sum per proposal and 128-column tile instead of the outputs,
+ * and adds the tiles' partials (compensated, in tile order).  The work space
+ * grows by 384 bytes + 8 Kp / 128 bytes per proposal of capacity
+ * (rbfl_reserve).  ln L agrees with the default order to rounding (the
+ * summation order differs); domain flags are the same.  Takes precedence
+ * over rbfl_pipeline; allowed under graph capture.  rbfl_autotune of
+ * RBFL_FORM_FP64 times it and keeps it if 1% faster than the best other
+ * order (RBFL_Q_PIPELINE).  Needs exclusive use of the handle. */
+int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it
  * on, rbfl_eval records HIP events around the basis-row, contraction and

@@ -17,6 +17,7 @@
 // accumulator element i is D[l/16 + 4i][l%16], measured on gfx950); row
 // chunks of KC rows of both operands staged through LDS, double-buffered.
 #include "basis_rows.h"
+#include "epilogue_setup.h"
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -62,12 +63,15 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
-// One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
-// columns tc*CW ..; called by every thread of the workgroup.
+// The accumulators of one output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]:
+// proposals tq*QT .., columns tc*CW ..; called by every thread of the
+// workgroup; acc[t][u][i] of lane l is Y at proposal
+// tq*QT + (wave % WQ)*RT*16 + 16t + l/16 + 4i and column
+// tc*CW + (wave / WQ)*CT*16 + 16u + l%16.
 template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
-__device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
-                                          const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
-                                          int tc) {
+__device__ __forceinline__ void gemm_accumulate(const double *__restrict__ Bt, int64_t ldb, int rows,
+                                                const double *__restrict__ W, int Kp, int64_t tq, int tc,
+                                                d4 (&acc)[RT][CT]) {
   constexpr int QT = WQ * RT * 16, CW = WC * CT * 16, NT = 64 * WQ * WC;
   constexpr int A2 = KC * QT / 2, W2 = KC * CW / 2;                 // double2 entries per chunk
   constexpr int LA = A2 / NT, LW = W2 / NT;
@@ -125,7 +129,6 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
     }
   };
 
-  d4 acc[RT][CT];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -155,6 +158,22 @@ __device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t
     if (ch + 1 < n_chunks) stash(cur ^ 1);
     __syncthreads();
   }
+}
+
+// One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
+// columns tc*CW ..; called by every thread of the workgroup.  Ends with a
+// block barrier (inside the accumulation), so a block may run another tile.
+template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
+__device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
+                                          const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
+                                          int tc) {
+  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16;
+  d4 acc[RT][CT];
+  gemm_accumulate<RT, CT, KC, WQ, WC>(Bt, ldb, rows, W, Kp, tq, tc, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wq = wave % WQ, wc = wave / WQ, kk = lane >> 4, ll = lane & 15;
+  const int c0 = tc * CW;
+  const int64_t q0 = tq * QT;
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -175,6 +194,96 @@ __global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
   const int n_ct = Kp / (WC * CT * 16);
   const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
   gemm_tile<RT, CT, KC, WQ, WC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
+}
+
+// The FP64 contraction that finishes ln L itself.  ln L is linear in the
+// interpolated outputs, ln L = sum_c coef_c Y[c] with, for a proposal's
+// setup (r = d_ref / d_L, amplitudes A_{k,a}, spline position n0 + f at
+// detector k):
+//   Re C_{k,a,i}:   r Re(conj(A_{k,a}) b_i),  b_i = sum_p f^p B4[n0][i][p]
+//   Im C_{k,a,i}:   r Im(conj(A_{k,a}) b_i) reversed in sign, i.e.
+//                   r (Ai br - Ar bi)
+//   sigma_{k,aa}:   -r^2 |A_{k,a}|^2 / 2
+//   Re sigma_{k,ab}: -r^2 Re(conj(A_a) A_b),  Im sigma_{k,ab}: r^2 Im(conj(A_a) A_b)
+// (the terms of Eq. logl_complete, corrected reading, as the epilogue kernel
+// sums them).  After the same accumulation as k_gemm_fp64's 128 x 128 tile
+// of 8 waves, each lane weights its 32 outputs, the 16 lanes of a row group
+// and the two column waves add theirs (a fixed tree), and the tile writes one
+// partial sum per proposal to part[column tile][proposal]; Y is never
+// written.  Proposals outside the domain contribute nothing here.
+constexpr int kLnlRT = 2, kLnlCT = 4, kLnlKC = 8, kLnlWQ = 4, kLnlWC = 2;
+
+__global__ void __launch_bounds__(64 * kLnlWQ * kLnlWC, 1)
+    k_gemm_lnl_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
+                    int Kp, const EvalConsts *__restrict__ cp, const EpiSetup *__restrict__ setups,
+                    const double2 *__restrict__ basis4, const int4 *__restrict__ coldesc, double *__restrict__ part,
+                    int64_t ldp) {
+  constexpr int RT = kLnlRT, CT = kLnlCT, WQ = kLnlWQ, WC = kLnlWC;
+  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16;
+  __shared__ double red[WC][QT];
+  const int n_ct = Kp / CW;
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int64_t tq = tile / n_ct;
+  const int tc = (int)(tile % n_ct);
+  d4 acc[RT][CT];
+  gemm_accumulate<RT, CT, kLnlKC, WQ, WC>(Bt, ldb, rows, W, Kp, tq, tc, acc);
+  const EvalConsts &c = *cp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wq = wave % WQ, wc = wave / WQ, kk = lane >> 4, ll = lane & 15;
+  const int n_modes = c.n_modes, T = c.T, q = c.q, K = c.K;
+  const int64_t q0 = tq * QT;
+  int4 dsc[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) {
+    const int j = tc * CW + wc * CT * 16 + 16 * u + ll;
+    dsc[u] = j < K ? coldesc[j] : make_int4(-1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wq * RT * 16 + 16 * t + kk + 4 * i;
+      const int64_t b = q0 + row;
+      double sum = 0.0;
+      if (b < nb && setups[b].status == 0) {
+        const EpiSetup &o = setups[b];
+        const double rr = o.rr;
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+          const int4 d = dsc[u];
+          if (d.x < 0) continue;
+          const int k = d.y, a = d.z;
+          const double ara = o.Ar[k][a], aia = o.Ai[k][a];
+          double cf;
+          if (d.x <= 1) {
+            const double f = o.f[k];
+            const double2 *v = basis4 + (((int64_t)(k * n_modes + a) * T + o.n0[k]) * q + d.w) * 4;
+            const double2 v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+            const double br = fma(fma(fma(v3.x, f, v2.x), f, v1.x), f, v0.x);
+            const double bi = fma(fma(fma(v3.y, f, v2.y), f, v1.y), f, v0.y);
+            cf = d.x == 0 ? rr * (ara * br + aia * bi) : rr * (aia * br - ara * bi);
+          } else {
+            const double arb = o.Ar[k][d.w], aib = o.Ai[k][d.w];
+            if (d.x == 2 && a == d.w) cf = -0.5 * rr * rr * (ara * ara + aia * aia);
+            else if (d.x == 2) cf = -rr * rr * (ara * arb + aia * aib);
+            else cf = rr * rr * (ara * aib - aia * arb);
+          }
+          sum = fma(cf, acc[t][u][i], sum);
+        }
+      }
+#pragma unroll
+      for (int m = 8; m >= 1; m >>= 1) sum += __shfl_xor(sum, m, 64);
+      if (ll == 0) red[wc][row] = sum;
+    }
+  __syncthreads();
+  for (int r = threadIdx.x; r < QT; r += 64 * WQ * WC) {
+    const int64_t b = q0 + r;
+    if (b >= nb) continue;
+    double v = red[0][r];
+#pragma unroll
+    for (int w = 1; w < WC; ++w) v += red[w][r];
+    part[(int64_t)tc * ldp + b] = v;
+  }
 }
 
 // Multi-event batches: basis rows of every event in one launch.  blockIdx.y
@@ -251,6 +360,21 @@ void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc
 }  // namespace
 
 int64_t rows_ld(int64_t n) { return (n + 7) & ~int64_t(7); }
+
+int gemm_lnl_col_tile() { return kLnlWC * kLnlCT * 16; }
+
+void launch_gemm_lnl_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const double *W, const EvalConsts *c,
+                          const void *setups, const double2 *basis4, const int4 *coldesc, double *part, int64_t ldp,
+                          hipStream_t s) {
+  constexpr int QT = kLnlWQ * kLnlRT * 16, CW = kLnlWC * kLnlCT * 16;
+  static_assert(kColTile % CW == 0 && kRowChunk % kLnlKC == 0, "K and the rows are padded to whole tiles");
+  if (nb <= 0) return;
+  const int64_t ldb = rows_ld(nb);
+  const int64_t nblk = (nb + QT - 1) / QT * (hc.Kp / CW);
+  hipLaunchKernelGGL(k_gemm_lnl_fp64, dim3((unsigned)nblk), dim3(64 * kLnlWQ * kLnlWC), 0, s, Bt, nb, ldb, hc.rows, W,
+                     hc.Kp, c, static_cast<const EpiSetup *>(setups), basis4, coldesc, part, ldp);
+  RBFL_HIP(hipGetLastError());
+}
 
 int gemm_fp64_variants() { return 7; }
 

@@ -10,6 +10,7 @@
 //   coefficients (Eq. SVD) and the extrinsic combination of Eq. logl_complete
 //   (corrected reading) with compensated summation.
 #include "basis_rows.h"
+#include "epilogue_setup.h"
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -226,73 +227,6 @@ __global__ void __launch_bounds__(kThreads) k_contract_fp32(const EvalConsts *__
 constexpr int kEpiBatch = 64;
 static_assert(kEpiBatch + RBFL_MAX_DET * RBFL_MAX_MODES <= kThreads, "offset copy threads");
 
-struct EpiSetup {
-  int status;                       // 0 evaluate, 1 outside the domain (-inf), 2 NaN input
-  int event;                        // multi-event batches: the proposal's event
-  int n0[RBFL_MAX_DET];             // spline stencil base sample per detector
-  double f[RBFL_MAX_DET];           // fractional sample position per detector
-  double rr;                        // d_ref / d_L
-  double Ar[RBFL_MAX_DET][RBFL_MAX_MODES], Ai[RBFL_MAX_DET][RBFL_MAX_MODES];
-};
-
-__device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
-                                          int64_t g, EpiSetup &o) {
-  double p[11];
-  bool any_nan = false;
-#pragma unroll
-  for (int i = 0; i < 11; ++i) {
-    p[i] = params[i * ld + g];
-    any_nan |= isnan(p[i]);
-  }
-  if (any_nan) {
-    o.status = 2;
-    return;
-  }
-  // a1: inside the ellipsoid and physical
-  double r2 = 0.0;
-  for (int d = 0; d < 4; ++d) {
-    const double x = p[d] / c.semi[d];
-    r2 += x * x;
-  }
-  bool valid = r2 <= 1.0;
-  {
-    double th[4], phys[4];
-    for (int i = 0; i < 4; ++i) {
-      double t = c.theta_c[i];
-      for (int j = 0; j < 4; ++j) t += c.V[4 * i + j] * p[j];
-      th[i] = t;
-    }
-    valid = valid && theta_to_phys(th, c.f0, c.chi_max, phys);
-  }
-  const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
-  o.rr = c.d_ref / dl;
-  double ch, sh;
-  sincos(0.5 * iota, &sh, &ch);
-  double ynr[RBFL_MAX_MODES], yni[RBFL_MAX_MODES], ypr[RBFL_MAX_MODES], ypi[RBFL_MAX_MODES];
-  for (int a = 0; a < c.n_modes; ++a) {
-    eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr[a], &yni[a]);
-    eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr[a], &ypi[a]);
-  }
-  const int T = c.T;
-  for (int k = 0; k < c.n_det; ++k) {
-    // a4: detector response, arrival time and spline stencil
-    double fp, fc, dt;
-    detector_response(c.D[k], c.r[k], alpha, dec, psi, &fp, &fc, &dt);
-    const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
-    const double fl = floor(s);
-    valid = valid && fl >= 4.0 && fl <= (double)(T - 6);
-    o.n0[k] = valid ? (int)fl : 4;
-    o.f[k] = s - fl;
-    // a6: amplitudes of every mode at this detector
-    for (int a = 0; a < c.n_modes; ++a) {
-      const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
-      o.Ar[k][a] = 0.5 * ((fp * ynr[a] - fc * yni[a]) + sg * (fp * ypr[a] - fc * ypi[a]));
-      o.Ai[k][a] = 0.5 * ((fp * yni[a] + fc * ynr[a]) + sg * (-fp * ypi[a] - fc * ypr[a]));
-    }
-  }
-  o.status = valid ? 0 : 1;
-}
-
 // ln L of one proposal from its setup o and interpolated row y; one whole
 // wave per call, result written to *out by lane 0.  The loads of each stage
 // are issued together before their values are used (kEpiUnroll coefficients
@@ -430,6 +364,39 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
     if (b >= nb) break;   // whole wave leaves together
     epi_reduce(c, su[j], Y + b * c.Kp, basis4, lnl + b0 + b, coef_off, sig_off);
   }
+}
+
+// Epilogue finished inside the contraction (FP64 form, optional): ln L is
+// linear in the interpolated outputs, ln L = sum_c coef_c(proposal) Y[c], so
+// the contraction kernel forms coef_c from each proposal's setup and sums
+// coef_c Y[c] over its column tile instead of writing Y; these two kernels
+// write the setups before it and add the column tiles' partial sums after it
+// (compensated, in tile order).
+__global__ void __launch_bounds__(kThreads) k_epi_setup(const EvalConsts *__restrict__ cp,
+                                                        const double *__restrict__ params, int64_t ld, int64_t b0,
+                                                        int64_t nb, EpiSetup *__restrict__ setups) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b < nb) epi_setup(*cp, params, ld, b0 + b, setups[b]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_lnl_tiles(const EpiSetup *__restrict__ setups, int64_t b0, int64_t nb,
+                                                        const double *__restrict__ part, int64_t ldp, int n_ct,
+                                                        double *__restrict__ lnl) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b >= nb) return;
+  const int st = setups[b].status;
+  if (st != 0) {
+    lnl[b0 + b] = st == 2 ? __builtin_nan("") : -__builtin_huge_val();
+    return;
+  }
+  double tot = 0.0, comp = 0.0;
+  for (int t = 0; t < n_ct; ++t) {
+    const double v = part[(int64_t)t * ldp + b];
+    const double u = tot + v;
+    comp += fabs(tot) >= fabs(v) ? (tot - u) + v : (v - u) + tot;
+    tot = u;
+  }
+  lnl[b0 + b] = tot + comp;
 }
 
 // ln L of a batch straight from window samples (no time basis): per detector
@@ -717,6 +684,24 @@ void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *pa
   (void)hc;
   dim3 grid((unsigned)((nb + kEpiBatch - 1) / kEpiBatch));
   hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
+  RBFL_HIP(hipGetLastError());
+}
+
+size_t epi_setup_bytes() { return sizeof(EpiSetup); }
+
+void launch_epi_setup(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int64_t nb, void *setups,
+                      hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_epi_setup, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, c, params,
+                     ld, b0, nb, static_cast<EpiSetup *>(setups));
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_lnl_tiles(const void *setups, int64_t b0, int64_t nb, const double *part, int64_t ldp, int n_ct,
+                      double *lnl, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_lnl_tiles, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     static_cast<const EpiSetup *>(setups), b0, nb, part, ldp, n_ct, lnl);
   RBFL_HIP(hipGetLastError());
 }
 

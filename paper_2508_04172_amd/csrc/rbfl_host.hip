@@ -1601,6 +1601,8 @@ static void reserve(Ctx &c, int64_t n) {
   if (c.graph_users > 0) throw Error(RBFL_E_STATE, "the work space is captured by a sampler: it cannot grow");
   c.Y.alloc((size_t)n * c.Kp);
   c.Bt.alloc((size_t)c.rows * rows_ld(n));
+  c.epi_su.alloc(epi_setup_bytes() * (size_t)n);
+  c.epi_part.alloc((size_t)(c.Kp / gemm_lnl_col_tile()) * n);
   c.cap = n;
   if (c.prepared[RBFL_FORM_BF16]) c.A16.alloc((size_t)c.rows * n);
   if (c.prepared[RBFL_FORM_SPLIT]) {
@@ -1689,11 +1691,51 @@ static void eval_pipelined(Ctx &c, const double *params, int64_t ld, int64_t n, 
   for (int h = 0; h < std::min(i, 2); ++h) RBFL_HIP(hipStreamWaitEvent(s, c.pev_epi[h], 0));
 }
 
+// FP64 evaluation with ln L finished inside the contraction: per chunk the
+// proposals' setups and basis rows, the contraction that weights its output
+// tile by the setups' coefficients and writes one partial sum per proposal
+// and column tile, and their compensated sum (see k_gemm_lnl_fp64).
+static void eval_lnl_gemm(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, hipStream_t s) {
+  const int n_ct = c.Kp / gemm_lnl_col_tile();
+  for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
+    const int64_t nb = std::min(c.cap, n - b0);
+    hipEvent_t ev[4];
+    auto mark = [&](int k) {
+      if (c.profile) RBFL_HIP(hipEventRecord(ev[k], s));
+    };
+    if (c.profile)
+      for (auto &e : ev) {
+        RBFL_HIP(hipEventCreate(&e));
+        c.timed_events.push_back(e);
+      }
+    mark(0);
+    launch_epi_setup(c.consts.p, params, ld, b0, nb, c.epi_su.p, s);
+    launch_rows_fp64(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.Bt.p, s);
+    mark(1);
+    launch_gemm_lnl_fp64(c.Bt.p, nb, c.host_consts, c.W.p, c.consts.p, c.epi_su.p, c.basis4.p, c.coldesc.p,
+                         c.epi_part.p, c.cap, s);
+    mark(2);
+    launch_lnl_tiles(c.epi_su.p, b0, nb, c.epi_part.p, c.cap, n_ct, lnl, s);
+    mark(3);
+    if (c.profile) {
+      // stages: setups + basis rows (kind 2), contraction with the weighting
+      // (kind 0), sum of the tile partials (kind 1)
+      c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
+      c.timed.push_back(Ctx::Timed{ev[1], ev[2], 0, nb});
+      c.timed.push_back(Ctx::Timed{ev[2], ev[3], 1, nb});
+    }
+  }
+}
+
 // ln L of proposals [0, n) of a parameter array with leading dimension ld.
 static void eval_range(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, int form, hipStream_t s) {
   if (n == 0) return;
   if (c.cap == 0) reserve(c, std::min<int64_t>(n, 65536));
   const bool fp64 = form == RBFL_FORM_FP64 || (form == RBFL_FORM_SURROGATE && !(c.sur && c.sur_ok));
+  if (fp64 && c.lnl_gemm) {
+    eval_lnl_gemm(c, params, ld, n, lnl, s);
+    return;
+  }
   if (fp64 && c.pipe > 1 && c.cap / 2 >= 4096 && n > 4096 && !capturing(s)) {
     eval_pipelined(c, params, ld, n, lnl, s);
     return;
@@ -1917,6 +1959,27 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
       if (pm[d] < 0.99 * pm[0] && pm[d] < pm[bd]) bd = d;
     c.pipe = depths[bd];
     for (int d = 0; d < 4; ++d) c.pipe_ms[d] = pm[d];
+    // then ln L finished inside the contraction, kept if 1% faster still
+    c.lnl_gemm = true;
+    double fm = 1e300;
+    for (int round = 0; round < 2; ++round) {
+      if (round == 0) eval_range(c, params, n, nb, out.p, form, s);
+      double t[3];
+      for (int r = 0; r < 3; ++r) {
+        RBFL_HIP(hipEventRecord(e0, s));
+        eval_range(c, params, n, nb, out.p, form, s);
+        RBFL_HIP(hipEventRecord(e1, s));
+        RBFL_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t[r] = ms;
+      }
+      std::sort(t, t + 3);
+      fm = std::min(fm, t[1]);
+    }
+    c.lnl_gemm_ms = fm;
+    c.lnl_gemm = fm < 0.99 * pm[bd];
+    if (c.lnl_gemm) c.pipe = 1;
     c.profile = prof;
     RBFL_HIP(hipStreamSynchronize(s));
   }
@@ -2137,7 +2200,8 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       return;
     }
     case RBFL_Q_PIPELINE: {
-      double v[5] = {(double)c.pipe, c.pipe_ms[0], c.pipe_ms[1], c.pipe_ms[2], c.pipe_ms[3]};
+      double v[7] = {(double)c.pipe, c.pipe_ms[0], c.pipe_ms[1], c.pipe_ms[2], c.pipe_ms[3],
+                     c.lnl_gemm ? 1.0 : 0.0, c.lnl_gemm_ms};
       copy_out(out, bytes, v, sizeof(v));
       return;
     }
@@ -2727,6 +2791,13 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant) {
     if (!h->c.prepared[form]) throw rbfl::Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
     rbfl::require(variant >= 0 && variant < rbfl::contract_variants(form), "variant out of range");
     h->c.variant[form] = variant;
+  });
+}
+
+int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    h->c.lnl_gemm = on != 0;
   });
 }
 

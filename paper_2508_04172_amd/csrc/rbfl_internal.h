@@ -150,6 +150,11 @@ struct Ctx {
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
+  // ln L finished inside the FP64 contraction (rbfl_fuse_epilogue)
+  bool lnl_gemm = false;
+  double lnl_gemm_ms = 0.0;           // the autotuner's time per evaluation of that order
+  DevBuf<unsigned char> epi_su;       // per-proposal setups [cap]
+  DevBuf<double> epi_part;            // partial sums per column tile [Kp / tile][cap]
   int64_t cap = 0;
   int graph_users = 0;         // live samplers whose captured step uses Y / Bt / the weight copies
   // pipelined FP64 evaluation (rbfl_pipeline): chunks per call (1 = serial),
@@ -259,6 +264,17 @@ void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params,
                             hipStream_t s);
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s);
+// Epilogue inside the FP64 contraction: per-proposal setups (epi_setup_bytes()
+// each), the contraction's partial sums part[column tile][ldp], their sum.
+size_t epi_setup_bytes();
+int gemm_lnl_col_tile();
+void launch_epi_setup(const EvalConsts *c, const double *params, int64_t ld, int64_t b0, int64_t nb, void *setups,
+                      hipStream_t s);
+void launch_gemm_lnl_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, const double *W, const EvalConsts *c,
+                          const void *setups, const double2 *basis4, const int4 *coldesc, double *part, int64_t ldp,
+                          hipStream_t s);
+void launch_lnl_tiles(const void *setups, int64_t b0, int64_t nb, const double *part, int64_t ldp, int n_ct,
+                      double *lnl, hipStream_t s);
 int split_max_slices();
 int split_max_rows();
 int split_variant_count();

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAX_MODES = 5
 MAX_DET = 4
 
@@ -32,6 +32,7 @@ SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
+            "rbfl_fuse_epilogue",
             "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
@@ -163,6 +164,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_variants.argtypes = [C.c_int32]
     lib.rbfl_set_variant.restype = C.c_int32
     lib.rbfl_set_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.rbfl_fuse_epilogue.restype = C.c_int32
+    lib.rbfl_fuse_epilogue.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_pipeline.restype = C.c_int32
     lib.rbfl_pipeline.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_profile.restype = C.c_int32
@@ -431,10 +434,16 @@ class Handle:
         """Chunks per FP64 evaluation (1 = serial order); the autotuner sets it."""
         _check(load().rbfl_pipeline(self._h, chunks))
 
+    def fuse_epilogue(self, on: bool):
+        """ln L finished inside the FP64 contraction (rbfl_fuse_epilogue); the autotuner sets it."""
+        _check(load().rbfl_fuse_epilogue(self._h, 1 if on else 0))
+
     def pipeline(self) -> dict:
-        """Chunks in use and the autotuner's ms per evaluation at 1, 2, 4, 8 chunks (RBFL_Q_PIPELINE)."""
-        v = self._query(Q_PIPELINE, 5)
-        return {"chunks": int(v[0]), "ms": {d: float(x) for d, x in zip((1, 2, 4, 8), v[1:]) if x > 0}}
+        """The FP64 evaluation order in use and the autotuner's ms per evaluation (RBFL_Q_PIPELINE):
+        chunks per call, ms at 1, 2, 4, 8 chunks, ln L inside the contraction and its ms."""
+        v = self._query(Q_PIPELINE, 7)
+        return {"chunks": int(v[0]), "ms": {d: float(x) for d, x in zip((1, 2, 4, 8), v[1:5]) if x > 0},
+                "fused_epilogue": bool(v[5]), "fused_epilogue_ms": float(v[6])}
 
     def profile(self, on: bool):
         _check(load().rbfl_profile(self._h, 1 if on else 0))

@@ -171,6 +171,34 @@ def test_lnl_parity_near_nodes(name):
     assert d.max() <= 1e-3
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_lnl_parity_fused_epilogue(name):
+    """ln L finished inside the FP64 contraction (coefficient-weighted output
+    tiles, no interpolated outputs written): the oracle bar, the same domain
+    flags, and agreement with the default order to rounding."""
+    cfg, art, h = both(name)
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    q_gpu = qd.near_nodes(h.nodes(), idx, jit)
+    ref = gpu_eval(h, q_gpu, cfg.t_trig)
+    h.fuse_epilogue(True)
+    try:
+        lg = gpu_eval(h, q_gpu, cfg.t_trig)
+    finally:
+        h.fuse_epilogue(False)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg)) and np.array_equal(np.isnan(ref), np.isnan(lg))
+    assert np.array_equal(np.isfinite(ref), np.isfinite(lg))
+    d = np.abs(lg[fin] - lo[fin])
+    dr = np.abs(lg[fin] - ref[fin]).max()
+    print(f"[parity] {name} fused epilogue: max |dlnL| vs oracle {d.max():.3e}, vs default order {dr:.3e}",
+          flush=True)
+    assert d.max() <= 1e-3
+    assert dr <= 1e-9 * max(1.0, np.abs(ref[fin]).max())
+
+
 @pytest.mark.parametrize("name", ["small_multi", "ragged_tail"])
 def test_fp64_tile_variants(name):
     """Every FP64 contraction tile variant (rows + GEMM tiles of several

@@ -134,3 +134,43 @@ def test_autotune_sets_pipeline(setup):
     got = run(h, p, n, pl["chunks"])
     assert same(ref, got)
     h.set_pipeline(1)
+
+
+def test_fused_epilogue_chunks_profile_and_capture(setup):
+    """ln L finished inside the contraction over several chunks of the work
+    space (50003 proposals, capacity 16384), with per-launch timing on, and
+    replayed from a captured graph: agreement with the default order to
+    rounding, identical domain flags, every replay identical."""
+    torch = _torch()
+    cfg, h, p, n = setup
+    ref = run(h, p, n, 1)
+    h.fuse_epilogue(True)
+    try:
+        h.profile(True)
+        got = run(h, p, n, 1)
+        h.profile(False)
+        ks = h.kernel_stats()
+        m = 12000
+        q = p[:, :m].contiguous()
+        eager = run(h, q, m, 1)
+        out = torch.zeros(m, dtype=torch.float64, device="cuda")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            h.eval(q.data_ptr(), m, out.data_ptr(), rbfl.FORM_FP64, torch.cuda.current_stream().cuda_stream)
+        for r in range(3):
+            out.fill_(3.0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert same(eager, out), f"replay {r}"
+            run(h, p, n, 1)
+        del g
+    finally:
+        h.fuse_epilogue(False)
+    fin = ref.isfinite()
+    assert torch.equal(fin, got.isfinite()) and torch.equal(ref.isnan(), got.isnan())
+    d = float((ref[fin] - got[fin]).abs().max())
+    print(f"[pipeline] fused epilogue: max |d| vs default order {d:.3e}; profile {ks}", flush=True)
+    assert d <= 1e-9 * max(1.0, float(ref[fin].abs().max()))
+    assert ks["contract_launches"] == ks["epilogue_launches"] == ks["rows_launches"] == 4
+    assert ks["contract_n"] == n
