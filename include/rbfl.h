@@ -318,11 +318,12 @@ int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks);
  * With `on` nonzero, rbfl_eval of the FP64 form writes each proposal's setup,
  * contracts with a kernel that weights its output tile by coef_c and writes
  * one partial sum per proposal and 128-column tile instead of the outputs,
- * and adds the tiles' partials (compensated, in tile order).  The work space
- * grows by 384 bytes + 8 Kp / 128 bytes per proposal of capacity
- * (rbfl_reserve).  ln L agrees with the default order to rounding (the
- * summation order differs); domain flags are the same.  Takes precedence
- * over rbfl_pipeline; allowed under graph capture.  rbfl_autotune of
+ * and adds the tiles' partials (compensated, in tile order).  Its work space,
+ * 384 bytes + 8 Kp / 128 bytes per proposal of capacity (rbfl_reserve), is
+ * allocated by the first evaluation in this order.  ln L agrees with the
+ * default order to rounding (the summation order differs); domain flags are
+ * the same.  Takes precedence over rbfl_pipeline; allowed under graph capture
+ * once that work space exists (else RBFL_E_STATE).  rbfl_autotune of
  * RBFL_FORM_FP64 times it and keeps it if 1% faster than the best other
  * order (RBFL_Q_PIPELINE).  Needs exclusive use of the handle. */
 int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on);

@@ -63,7 +63,124 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
-// The accumulators of one output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]:
+// One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
+// columns tc*CW ..; called by every thread of the workgroup.
+template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
+__device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
+                                          const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
+                                          int tc) {
+  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16, NT = 64 * WQ * WC;
+  constexpr int A2 = KC * QT / 2, W2 = KC * CW / 2;                 // double2 entries per chunk
+  constexpr int LA = A2 / NT, LW = W2 / NT;
+  static_assert(KC % 4 == 0 && A2 % NT == 0 && W2 % NT == 0, "whole k-steps, even staging");
+  __shared__ double As[2][KC][QT];
+  __shared__ double Ws[2][KC][CW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave % WQ, wc = wave / WQ;
+  const int c0 = tc * CW;
+  const int64_t q0 = tq * QT;
+
+  // per-thread source pointers of the staged entries, advanced by KC rows per chunk
+  const double *pa[LA];
+  const double *pw[LW];
+  bool va[LA];
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + u * NT;
+    const int k = e / (QT / 2), q2 = e % (QT / 2);
+    pa[u] = Bt + (int64_t)k * ldb + q0 + 2 * q2;
+    va[u] = q0 + 2 * q2 < ldb;
+  }
+#pragma unroll
+  for (int u = 0; u < LW; ++u) {
+    const int e = tid + u * NT;
+    pw[u] = W + (int64_t)(e / (CW / 2)) * Kp + c0 + 2 * (e % (CW / 2));
+  }
+  const int64_t stepA = (int64_t)KC * ldb, stepW = (int64_t)KC * Kp;
+  d2 ra[LA], rw[LW];
+  auto fetch = [&]() {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      ra[u] = va[u] ? *reinterpret_cast<const d2 *>(pa[u]) : d2{0.0, 0.0};
+      pa[u] += stepA;
+    }
+#pragma unroll
+    for (int u = 0; u < LW; ++u) {
+      rw[u] = *reinterpret_cast<const d2 *>(pw[u]);
+      pw[u] += stepW;
+    }
+  };
+  auto stash = [&](int buf) {
+    // keeps the compiler from hoisting these LDS writes (and the wait for
+    // their global loads) above the current chunk's MFMAs
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + u * NT;
+      *reinterpret_cast<d2 *>(&As[buf][e / (QT / 2)][2 * (e % (QT / 2))]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LW; ++u) {
+      const int e = tid + u * NT;
+      *reinterpret_cast<d2 *>(&Ws[buf][e / (CW / 2)][2 * (e % (CW / 2))]) = rw[u];
+    }
+  };
+
+  d4 acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int kk = lane >> 4, ll = lane & 15;
+  const int n_chunks = rows / KC;
+  fetch();
+  stash(0);
+  __syncthreads();
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < n_chunks) fetch();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = 4 * s + kk;
+      double a[RT], b[CT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = As[cur][k][wq * RT * 16 + 16 * t + ll];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[u] = Ws[cur][k][wc * CT * 16 + 16 * u + ll];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+    }
+    if (ch + 1 < n_chunks) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t q = q0 + wq * RT * 16 + 16 * t + kk + 4 * i;
+      if (q >= nb) continue;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) Y[q * Kp + c0 + wc * CT * 16 + 16 * u + ll] = acc[t][u][i];
+    }
+}
+
+// One-dimensional grid over (proposal tile, column tile), column tile fastest;
+// WQ x WC waves per workgroup.
+template <int RT, int CT, int KC, int WQ, int WC>
+__global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
+    k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
+                int Kp, double *__restrict__ Y) {
+  const int n_ct = Kp / (WC * CT * 16);
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  gemm_tile<RT, CT, KC, WQ, WC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
+}
+
+// The accumulators of one output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]
+// (the K loop of gemm_tile, kept as a copy so that gemm_tile's code is not
+// changed by this kernel):
 // proposals tq*QT .., columns tc*CW ..; called by every thread of the
 // workgroup; acc[t][u][i] of lane l is Y at proposal
 // tq*QT + (wave % WQ)*RT*16 + 16t + l/16 + 4i and column
@@ -158,42 +275,6 @@ __device__ __forceinline__ void gemm_accumulate(const double *__restrict__ Bt, i
     if (ch + 1 < n_chunks) stash(cur ^ 1);
     __syncthreads();
   }
-}
-
-// One output tile of Y[q][c] = sum_r Bt[r][q] W[r][c]: proposals tq*QT ..,
-// columns tc*CW ..; called by every thread of the workgroup.  Ends with a
-// block barrier (inside the accumulation), so a block may run another tile.
-template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
-__device__ __forceinline__ void gemm_tile(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows,
-                                          const double *__restrict__ W, int Kp, double *__restrict__ Y, int64_t tq,
-                                          int tc) {
-  constexpr int QT = WQ * RT * 16, CW = WC * CT * 16;
-  d4 acc[RT][CT];
-  gemm_accumulate<RT, CT, KC, WQ, WC>(Bt, ldb, rows, W, Kp, tq, tc, acc);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wq = wave % WQ, wc = wave / WQ, kk = lane >> 4, ll = lane & 15;
-  const int c0 = tc * CW;
-  const int64_t q0 = tq * QT;
-#pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t q = q0 + wq * RT * 16 + 16 * t + kk + 4 * i;
-      if (q >= nb) continue;
-#pragma unroll
-      for (int u = 0; u < CT; ++u) Y[q * Kp + c0 + wc * CT * 16 + 16 * u + ll] = acc[t][u][i];
-    }
-}
-
-// One-dimensional grid over (proposal tile, column tile), column tile fastest;
-// WQ x WC waves per workgroup.
-template <int RT, int CT, int KC, int WQ, int WC>
-__global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
-    k_gemm_fp64(const double *__restrict__ Bt, int64_t nb, int64_t ldb, int rows, const double *__restrict__ W,
-                int Kp, double *__restrict__ Y) {
-  const int n_ct = Kp / (WC * CT * 16);
-  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
-  gemm_tile<RT, CT, KC, WQ, WC>(Bt, nb, ldb, rows, W, Kp, Y, tile / n_ct, (int)(tile % n_ct));
 }
 
 // The FP64 contraction that finishes ln L itself.  ln L is linear in the

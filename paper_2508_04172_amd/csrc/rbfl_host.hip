@@ -1596,13 +1596,19 @@ static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hi
   RBFL_HIP(hipStreamSynchronize(s));
 }
 
+// Work space of the order that finishes ln L inside the contraction, for n
+// proposals; allocated on first use of that order (and grown with the rest).
+static void reserve_lnl_gemm(Ctx &c, int64_t n) {
+  c.epi_su.alloc(epi_setup_bytes() * (size_t)n);
+  c.epi_part.alloc((size_t)(c.Kp / gemm_lnl_col_tile()) * n);
+}
+
 static void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
   if (c.graph_users > 0) throw Error(RBFL_E_STATE, "the work space is captured by a sampler: it cannot grow");
   c.Y.alloc((size_t)n * c.Kp);
   c.Bt.alloc((size_t)c.rows * rows_ld(n));
-  c.epi_su.alloc(epi_setup_bytes() * (size_t)n);
-  c.epi_part.alloc((size_t)(c.Kp / gemm_lnl_col_tile()) * n);
+  if (c.epi_su.p) reserve_lnl_gemm(c, n);
   c.cap = n;
   if (c.prepared[RBFL_FORM_BF16]) c.A16.alloc((size_t)c.rows * n);
   if (c.prepared[RBFL_FORM_SPLIT]) {
@@ -1697,6 +1703,10 @@ static void eval_pipelined(Ctx &c, const double *params, int64_t ld, int64_t n, 
 // and column tile, and their compensated sum (see k_gemm_lnl_fp64).
 static void eval_lnl_gemm(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, hipStream_t s) {
   const int n_ct = c.Kp / gemm_lnl_col_tile();
+  if (!c.epi_su.p) {
+    if (capturing(s)) throw Error(RBFL_E_STATE, "work space of the fused epilogue not allocated (evaluate once before capture)");
+    reserve_lnl_gemm(c, c.cap);
+  }
   for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
     const int64_t nb = std::min(c.cap, n - b0);
     hipEvent_t ev[4];
