@@ -1989,7 +1989,13 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     }
     c.lnl_gemm_ms = fm;
     c.lnl_gemm = fm < 0.99 * pm[bd];
-    if (c.lnl_gemm) c.pipe = 1;
+    if (c.lnl_gemm) {
+      c.pipe = 1;
+    } else {
+      RBFL_HIP(hipStreamSynchronize(s));
+      c.epi_su.reset();     // its work space is not kept for an order not chosen
+      c.epi_part.reset();
+    }
     c.profile = prof;
     RBFL_HIP(hipStreamSynchronize(s));
   }

@@ -331,3 +331,28 @@ def test_invalid_spec_errors():
     with pytest.raises(rbfl.RbflError) as e:
         rbfl.Handle.build(spec)
     assert e.value.code == rbfl.E_INVALID_ARG
+
+
+def test_order_and_variant_arguments():
+    """Argument checks of the evaluation-order and tile-variant entry points."""
+    cfg, art, h = both("cfg1")
+    for bad in (0, 65, -1):
+        with pytest.raises(rbfl.RbflError) as e:
+            h.set_pipeline(bad)
+        assert e.value.code == rbfl.E_INVALID_ARG
+    nv = rbfl.variants(rbfl.FORM_FP64)
+    assert nv >= 2 and rbfl.variants(rbfl.FORM_SPLIT) >= 1
+    with pytest.raises(ValueError):
+        rbfl.variants(rbfl.FORM_SURROGATE)
+    for bad in (-1, nv):
+        with pytest.raises(rbfl.RbflError) as e:
+            h.set_variant(rbfl.FORM_FP64, bad)
+        assert e.value.code == rbfl.E_INVALID_ARG
+    fresh = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    with pytest.raises(rbfl.RbflError) as e:
+        fresh.set_variant(rbfl.FORM_BF16, 0)     # not prepared
+    assert e.value.code == rbfl.E_STATE
+    fresh.close()
+    h.set_variant(rbfl.FORM_FP64, 0)
+    h.set_pipeline(1)
+    h.fuse_epilogue(False)
