@@ -285,8 +285,8 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
-/* Number of contraction tile variants of `form` (RBFL_FORM_FP64 .. SPLIT),
- * or RBFL_E_INVALID_ARG for another form. */
+/* Number of contraction tile variants (at least 1) of `form` (RBFL_FORM_FP64
+ * .. SPLIT), or -RBFL_E_INVALID_ARG (negative) for another form. */
 int32_t rbfl_variants(int32_t form);
 
 /* Pins the contraction tile variant of `form` (0 <= variant <

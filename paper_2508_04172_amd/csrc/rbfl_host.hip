@@ -2796,7 +2796,7 @@ int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t fo
 }
 
 int32_t rbfl_variants(int32_t form) {
-  if (form < 0 || form > RBFL_FORM_SPLIT) return RBFL_E_INVALID_ARG;
+  if (form < 0 || form > RBFL_FORM_SPLIT) return -RBFL_E_INVALID_ARG;
   return rbfl::contract_variants(form);
 }
 

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 from paper_2508_04172_amd import rbfl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,3 +38,14 @@ def test_struct_layout_matches_header():
 def test_last_error_is_empty_string_initially():
     lib = rbfl.load()
     assert isinstance(lib.rbfl_last_error(), bytes)
+
+
+def test_variant_counts_without_a_device():
+    """rbfl_variants is host-only: a count per tunable form, a negative code
+    (raised as ValueError by the binding) for the surrogate form."""
+    assert rbfl.variants(rbfl.FORM_FP64) >= 2
+    assert rbfl.variants(rbfl.FORM_FP32) >= 1 and rbfl.variants(rbfl.FORM_BF16) >= 1
+    assert rbfl.variants(rbfl.FORM_SPLIT) == 4          # digit counts S = 5..8
+    assert rbfl.load().rbfl_variants(rbfl.FORM_SURROGATE) < 0
+    with pytest.raises(ValueError):
+        rbfl.variants(rbfl.FORM_SURROGATE)
