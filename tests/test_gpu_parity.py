@@ -228,32 +228,67 @@ def test_fp64_tile_variants(name):
     assert all(same)
 
 
-@pytest.mark.timeout(1200)
-def test_cfg2_full_size_sampled():
-    """The 3-detector, 5-mode workload at full size (N = 800, q = 40, 1e6
-    proposals) in the benchmark's launch configuration; the oracle checks a
-    seeded sample of the outputs one by one."""
-    cfg = wl.CFG2
+def _full_size_sampled(cfg, capacity, seed):
+    """A workload at full size in the benchmark's launch configuration (work
+    capacity, autotuned tile and evaluation order); the oracle checks a
+    seeded sample of the outputs one by one.  Then the other FP64 evaluation
+    order (ln L inside the contraction, or not) on the same proposals: the
+    same sample bar, and agreement with the first to rounding."""
+    torch = _torch()
     white = wl.white_noise(cfg)
     inj = wl.injection_extrinsics(cfg)
-    print("[parity] cfg2: GPU start-up", flush=True)
+    print(f"[parity] {cfg.name}: GPU start-up", flush=True)
     h = rbfl.Handle.from_config(cfg, white, inj)
-    print("[parity] cfg2: oracle start-up", flush=True)
+    print(f"[parity] {cfg.name}: oracle start-up", flush=True)
     art = su.startup(cfg, white, inj)
     n = cfg.n_queries
     idx, jit = wl.node_jitter(n, cfg.n_nodes)
     qd = wl.queries(cfg, n=n)
-    lg = gpu_eval(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig)
-    sample = np.random.default_rng(123).choice(n, 2000, replace=False)
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig)))
+    p = p.cuda()
+    sp = torch.cuda.current_stream().cuda_stream
+    h.reserve(capacity)
+    tune = h.autotune(p.data_ptr(), n, rbfl.FORM_FP64, sp)
+    order = h.pipeline()
+    print(f"[parity] {cfg.name}: tile {tune['variant']}, order {order}", flush=True)
+    sample = np.random.default_rng(seed).choice(n, 2000, replace=False)
     sample.sort()
-    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(sample).near_nodes(art.x_nodes, idx[sample], jit[sample])))
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(sample).near_nodes(art.x_nodes, idx[sample],
+                                                                                 jit[sample])))
     fin = np.isfinite(lo)
-    assert np.array_equal(fin, np.isfinite(lg[sample]))
-    d = np.abs(lg[sample][fin] - lo[fin])
-    print(f"[parity] cfg2 full size: {fin.sum()} valid of 2000 sampled, max |dlnL| {d.max():.3e}", flush=True)
-    assert d.max() <= 1e-3
-    # properties that hold at any size: finite where inside, -inf elsewhere, never NaN
-    assert not np.isnan(lg).any()
+    outs = []
+    for fused in (order["fused_epilogue"], not order["fused_epilogue"]):
+        h.fuse_epilogue(fused)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.eval(p.data_ptr(), n, out.data_ptr(), rbfl.FORM_FP64, sp)
+        torch.cuda.synchronize()
+        lg = out.cpu().numpy()
+        assert np.array_equal(fin, np.isfinite(lg[sample]))
+        d = np.abs(lg[sample][fin] - lo[fin])
+        print(f"[parity] {cfg.name} full size, ln L inside the contraction {fused}: {fin.sum()} valid of 2000 "
+              f"sampled, max |dlnL| {d.max():.3e}", flush=True)
+        assert d.max() <= 1e-3
+        # properties that hold at any size: finite where inside, -inf elsewhere, never NaN
+        assert not np.isnan(lg).any()
+        outs.append(lg)
+    a, b = outs
+    both_fin = np.isfinite(a)
+    assert np.array_equal(both_fin, np.isfinite(b))
+    assert np.abs(a[both_fin] - b[both_fin]).max() <= 1e-9 * max(1.0, np.abs(a[both_fin]).max())
+
+
+@pytest.mark.timeout(1200)
+def test_cfg2_full_size_sampled():
+    """3-detector, 5-mode workload (N = 800, q = 40, 1e6 proposals in one
+    launch, as timed by bench.py)."""
+    _full_size_sampled(wl.CFG2, 1 << 20, 123)
+
+
+@pytest.mark.timeout(1200)
+def test_cfg3_full_size_sampled():
+    """10 Hz single-detector cubic-tail workload (N = 1500, M = 35, q = 60,
+    4e6 proposals in launches of 65,536, as timed by bench.py --mixed-cfg3)."""
+    _full_size_sampled(wl.CFG3, 65536, 321)
 
 
 def test_edge_cases():
