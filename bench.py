@@ -177,7 +177,7 @@ def main():
     rows_ms = ks["rows_ms"] / max(1, ks["rows_launches"])
     epi_ms = ks["epilogue_ms"] / max(1, ks["epilogue_launches"])
     # basis-row stage: writes 8 bytes per padded row per proposal, reads 32 bytes of coordinates
-    rows_padded = (NM + 31) // 32 * 32      # the library pads N + M to a multiple of 32
+    rows_padded = (NM + 15) // 16 * 16      # the rows kernel writes N + M rounded up to 16-row groups
     rows_bytes = (8.0 * rows_padded + 32.0) * per_launch_n
     fp64_variant = tune["fp64"]["variant"]
     fused = fp64_variant == len(tune["fp64"]["ms"]) - 1    # the last FP64 variant is the fused kernel

@@ -427,14 +427,23 @@ __global__ void k_zero_item_counter(unsigned long long *counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
+// Rows the GEMMs contract: N + M rounded up to their chunk of KC rows.  The
+// padded rows up to hc.rows hold zeros in W (and in the basis rows), so the
+// chunks past this bound would only add zeros: the result is the same.
+int gemm_rows(const EvalConsts &hc, int kc) { return (hc.N + hc.M + kc - 1) / kc * kc; }
+
+// Basis rows that k_rows_fp64 writes: N + M rounded up to its 16-row groups
+// (at least gemm_rows for chunks of 8 or 16 rows).
+int basis_rows_written(const EvalConsts &hc) { return (hc.N + hc.M + 15) / 16 * 16; }
+
 template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
 void launch_gemm(const double *Bt, int64_t nb, int64_t ldb, const EvalConsts &hc, const double *W, double *Y,
                  hipStream_t s) {
   constexpr int QT = WQ * RT * 16, CW = WC * CT * 16;
-  static_assert(kColTile % CW == 0 && kRowChunk % KC == 0, "K and the rows are padded to whole tiles");
+  static_assert(kColTile % CW == 0 && kRowChunk % KC == 0 && 16 % KC == 0, "K and the rows are padded to whole tiles");
   const int64_t nblk = (nb + QT - 1) / QT * (hc.Kp / CW);
   hipLaunchKernelGGL((k_gemm_fp64<RT, CT, KC, WQ, WC>), dim3((unsigned)nblk), dim3(64 * WQ * WC), 0, s, Bt, nb, ldb,
-                     hc.rows, W, hc.Kp, Y);
+                     gemm_rows(hc, KC), W, hc.Kp, Y);
   RBFL_HIP(hipGetLastError());
 }
 
@@ -452,7 +461,8 @@ void launch_gemm_lnl_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, co
   if (nb <= 0) return;
   const int64_t ldb = rows_ld(nb);
   const int64_t nblk = (nb + QT - 1) / QT * (hc.Kp / CW);
-  hipLaunchKernelGGL(k_gemm_lnl_fp64, dim3((unsigned)nblk), dim3(64 * kLnlWQ * kLnlWC), 0, s, Bt, nb, ldb, hc.rows, W,
+  hipLaunchKernelGGL(k_gemm_lnl_fp64, dim3((unsigned)nblk), dim3(64 * kLnlWQ * kLnlWC), 0, s, Bt, nb, ldb,
+                     gemm_rows(hc, kLnlKC), W,
                      hc.Kp, c, static_cast<const EpiSetup *>(setups), basis4, coldesc, part, ldp);
   RBFL_HIP(hipGetLastError());
 }
@@ -476,7 +486,7 @@ double gemm_fp64_reuse(int v) {
 void launch_rows_fp64(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                       int64_t nb, const double *nodes, double *Bt, hipStream_t s) {
   const int64_t ldb = rows_ld(nb);
-  dim3 grid((unsigned)((ldb + 255) / 256), (unsigned)(hc.rows / 16));
+  dim3 grid((unsigned)((ldb + 255) / 256), (unsigned)(basis_rows_written(hc) / 16));
   hipLaunchKernelGGL(k_rows_fp64, grid, dim3(256), 0, s, c, params, ld, b0, nb, ldb, nodes, Bt);
   RBFL_HIP(hipGetLastError());
 }
