@@ -280,8 +280,11 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * variant v has S = 5 + v): only those whose ln L on these proposals stays
  * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
  * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible, or
- * without autotuning, the split form uses S = 7.  Synchronous; needs
- * exclusive use of the handle. */
+ * without autotuning, the split form uses S = 7.  For RBFL_FORM_FP64 it then
+ * times whole evaluations of those proposals in each evaluation order (serial,
+ * rbfl_pipeline with 2, 4 and 8 chunks, rbfl_fuse_epilogue) and keeps another
+ * order than the serial one only if it is at least 1% faster (RBFL_Q_PIPELINE
+ * reports the timings).  Synchronous; needs exclusive use of the handle. */
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
@@ -307,8 +310,8 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant);
  * Used only when the work capacity holds two halves of at least 4096
  * proposals, for calls of more than 4096 proposals, and never while `stream`
  * is being captured.  rbfl_autotune of RBFL_FORM_FP64 times 1, 2, 4 and 8
- * chunks and keeps the fastest (RBFL_Q_PIPELINE).  Needs exclusive use of
- * the handle; RBFL_E_INVALID_ARG for chunks outside 1..64. */
+ * chunks (RBFL_Q_PIPELINE).  Needs exclusive use of the handle;
+ * RBFL_E_INVALID_ARG for chunks outside 1..64. */
 int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks);
 
 /* ln L finished inside the FP64 contraction (Sec. II D's online stage, same
@@ -330,8 +333,11 @@ int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it
  * on, rbfl_eval records HIP events around the basis-row, contraction and
- * epilogue launches of every chunk on the caller's stream;
- * RBFL_Q_KERNEL_STATS reports the sums.  Not for use under graph capture. */
+ * epilogue launches of every chunk, each on the stream the launch runs on
+ * (the caller's; the handle's second stream for pipelined epilogues; with
+ * ln L inside the contraction the stages are setups + basis rows, the
+ * contraction, and the sum of its partials); RBFL_Q_KERNEL_STATS reports the
+ * sums.  Not for use under graph capture. */
 int32_t rbfl_profile(rbfl_handle h, int32_t on);
 
 /*
