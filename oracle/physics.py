@@ -1,6 +1,9 @@
 """Oracle physics: inner product, PSD, waveform family, coordinates, detector response.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain float64 numpy.
+
+Parity unpinned against the literature: the 2PN spin-spin and the 2.5PN to
+3.5PN terms of pn_phase_22 (its lower orders are pinned; see its docstring).
 """
 from __future__ import annotations
 
@@ -141,8 +144,11 @@ def pn_phase_22(f, m1, m2, chi1, chi2):
 
     Psi = -pi/4 + 3/(128 eta v^5) sum_k (phi_k + phi_kl log-terms) v^k, v = (pi M f)^(1/3),
     with 3.5PN non-spinning coefficients and aligned-spin spin-orbit /
-    spin-spin terms as transcribed in the design notes (literature values;
-    the transcription itself is not checked against an external source).
+    spin-spin terms (literature values).  Pinned in the tests: the Newtonian
+    chirp time, the 1PN, 1.5PN and 2PN non-spinning terms (through
+    dPsi/df = 2 pi t(f) and the time-to-coalescence series) and the 1.5PN
+    spin-orbit term; the 2PN spin-spin, 2.5PN, 3PN and 3.5PN terms are
+    parity unpinned against the literature.
     """
     m_s, eta, delta = mass_params(m1, m2)
     chi_s = 0.5 * (chi1 + chi2)

@@ -77,6 +77,36 @@ def test_phase_newtonian_chirp_time():
         assert abs(-t / tau0 - 1.0) < 10 * v2
 
 
+@pytest.mark.parametrize("m1,m2", [(5.0, 5.0), (30.0, 3.0)])
+def test_phase_time_series_through_2pn(m1, m2):
+    """Stationary phase fixes dPsi/df = 2 pi t(f), and the time to coalescence
+    of a non-spinning binary has the classic post-Newtonian series
+    t = -5M/(256 eta v^8) [1 + (743/252 + 11 eta/3) v^2 - (32 pi/5) v^3
+    + (3058673/508032 + 5429 eta/504 + 617 eta^2/72) v^4 + O(v^5)].  The
+    phase's derivative (complex step) divided by the Newtonian time is an
+    exact finite series in 1, v^2 .. v^7 and v^6 log v; a least-squares fit
+    over v in [0.02, 0.3] recovers its coefficients, and the 1PN, 1.5PN and
+    2PN ones must be those of the time series (a slip in the phase's
+    transcription of them fails here)."""
+    m_s, eta, _ = ph.mass_params(m1, m2)
+    v = np.linspace(0.02, 0.3, 120)
+    f = v ** 3 / (math.pi * m_s)
+    h = 1e-20 * f
+    dpsi = np.imag(ph.pn_phase_22(f + 1j * h, m1, m2, 0.0, 0.0)) / h
+    ratio = (dpsi / (2.0 * math.pi)) / (-5.0 * m_s / (256.0 * eta * v ** 8))
+    basis = np.stack([np.ones_like(v), v ** 2, v ** 3, v ** 4, v ** 5, v ** 6, v ** 6 * np.log(v), v ** 7], axis=1)
+    coef, *_ = np.linalg.lstsq(basis, ratio, rcond=None)
+    tau2 = 743.0 / 252.0 + 11.0 * eta / 3.0
+    tau3 = -32.0 * math.pi / 5.0
+    tau4 = 3058673.0 / 508032.0 + 5429.0 * eta / 504.0 + 617.0 * eta ** 2 / 72.0
+    # the fit recovers them to ~1e-10; a 1% slip in any of them moves its
+    # coefficient by ~1e-2
+    assert coef[0] == pytest.approx(1.0, abs=1e-9)
+    assert coef[1] == pytest.approx(tau2, rel=1e-8)
+    assert coef[2] == pytest.approx(tau3, rel=1e-8)
+    assert coef[3] == pytest.approx(tau4, rel=1e-7)
+
+
 def test_phase_spin_orbit_matches_reduced_spin_coordinate():
     """At low frequency the spin dependence of the phase is the 1.5PN
     spin-orbit term, which Eq. metric_coords writes as theta3s: the spin part
