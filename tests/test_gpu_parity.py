@@ -297,19 +297,33 @@ def test_edge_cases():
     # empty batch is a no-op
     out = torch.zeros(1, dtype=torch.float64, device="cuda")
     h.eval(out.data_ptr(), 0, out.data_ptr())
-    # outside the ellipsoid, outside the window, NaN input
+    # outside the ellipsoid, outside the window, NaN input; in both FP64
+    # evaluation orders (ln L inside the contraction or not), and a batch of one
     qd = wl.queries(cfg, n=4)
     qd.x[0] = [1.2, 0.0, 0.0, 0.0]
     qd.dt[1] = 0.049
-    lg = gpu_eval(h, qd, cfg.t_trig)
-    assert lg[0] == -np.inf and lg[1] == -np.inf
     p = rbfl.params_soa(h, qd, cfg.t_trig)
     p[5, 2] = np.nan
     pt = torch.from_numpy(np.ascontiguousarray(p)).cuda()
     o = torch.empty(4, dtype=torch.float64, device="cuda")
-    h.eval(pt.data_ptr(), 4, o.data_ptr())
-    torch.cuda.synchronize()
-    assert math.isnan(o[2].item())
+    one = torch.empty(1, dtype=torch.float64, device="cuda")
+    p3 = torch.from_numpy(np.ascontiguousarray(p[:, 3:4])).cuda()
+    lo3 = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(np.array([3]))))[0]
+    for fused in (False, True):
+        h.fuse_epilogue(fused)
+        try:
+            lg = gpu_eval(h, qd, cfg.t_trig)
+            assert lg[0] == -np.inf and lg[1] == -np.inf
+            h.eval(pt.data_ptr(), 4, o.data_ptr())
+            h.eval(p3.data_ptr(), 1, one.data_ptr())
+            torch.cuda.synchronize()
+        finally:
+            h.fuse_epilogue(False)
+        assert math.isnan(o[2].item()) and o[0].item() == -math.inf and o[1].item() == -math.inf
+        if np.isfinite(lo3):
+            assert abs(one.item() - lo3) <= 1e-3 and abs(o[3].item() - one.item()) <= 1e-9 * max(1.0, abs(lo3))
+        else:
+            assert one.item() == lo3
     # an unknown form is an argument error, an unprepared one a state error (on
     # a fresh handle: the cached ones may have been prepared by other tests)
     with pytest.raises(rbfl.RbflError) as e:
