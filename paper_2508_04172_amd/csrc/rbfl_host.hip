@@ -1991,9 +1991,11 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     c.lnl_gemm = fm < 0.99 * pm[bd];
     if (c.lnl_gemm) {
       c.pipe = 1;
-    } else {
+    } else if (c.graph_users == 0) {
+      // its work space is not kept for an order not chosen (unless a captured
+      // sampler step may be using it)
       RBFL_HIP(hipStreamSynchronize(s));
-      c.epi_su.reset();     // its work space is not kept for an order not chosen
+      c.epi_su.reset();
       c.epi_part.reset();
     }
     c.profile = prof;
