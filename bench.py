@@ -80,6 +80,10 @@ def main():
     ap.add_argument("--surrogate-train", type=int, default=200000,
                     help="training proposals for the surrogate form (0 = skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--third-generation", action="store_true",
+                    help="also report the FP64 form on the third-generation workload (2048 s at 4096 Hz, "
+                         "N=3000, K=2475, 1e6 proposals per pass; its oracle checks samples in "
+                         "tests/test_gpu_cfg5.py, not here)")
     ap.add_argument("--mixed-cfg3", action="store_true",
                     help="also report every arithmetic form on the 10 Hz single-detector cubic-tail workload "
                          "(N=1500, M=35, q=60, 4e6 proposals), errors against its oracle")
@@ -274,6 +278,8 @@ def main():
         result["sampler"] = bench_sampler(args, np, torch, rbfl, wl, cfg)
     if args.method_error:
         result["method_error"] = bench_method_error(np, torch, rbfl, wl, h, cfg, qd, idx, jit)
+    if args.third_generation:
+        result["third_generation"] = bench_third_generation(args, np, torch, rbfl, wl)
     if args.mixed_cfg3:
         result["mixed_cfg3"] = bench_mixed(args, np, torch, rbfl, wl, wl.CFG3)
     print(json.dumps(result), flush=True)
@@ -469,6 +475,56 @@ def bench_method_error(np, torch, rbfl, wl, h2, cfg2, qd2, idx2, jit2):
     cases[cfg2s.name]["squeeze_factor"] = h2s.squeeze()[0]
     log(f"method error {cfg2s.name}: {cases[cfg2s.name]}")
     out["cases"] = cases
+    return out
+
+
+def bench_third_generation(args, np, torch, rbfl, wl):
+    """The FP64 form on the third-generation workload: start-up time, then
+    1e6 near-node proposals per pass in one launch per stage (autotuned tile
+    and evaluation order), with the contraction's HIP-event time."""
+    cfg = wl.CFG5
+    n = 1_000_000
+    log(f"third generation {cfg.name}: GPU start-up")
+    t0 = time.time()
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    build_s = time.time() - t0
+    sz = h.sizes()
+    log(f"third generation: start-up {build_s:.1f} s, sizes {sz}")
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    qd = wl.queries(cfg, n=n)
+    params = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit),
+                                                                   cfg.t_trig))).cuda()
+    lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+    sp = torch.cuda.current_stream().cuda_stream
+    h.reserve(n)
+    tune = h.autotune(params.data_ptr(), n, rbfl.FORM_FP64, sp)
+    order = h.pipeline()
+    log(f"third generation: tile {tune['variant']}, order {order}")
+    h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_FP64, sp)
+    torch.cuda.synchronize()
+    reps = 3
+    h.profile(True)
+    t = time.perf_counter()
+    for _ in range(reps):
+        h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_FP64, sp)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / reps
+    h.profile(False)
+    ks = h.kernel_stats()
+    flop = 2.0 * (sz["N"] + sz["M"]) * sz["K"]
+    c_ms = ks["contract_ms"] / max(1, ks["contract_launches"])
+    per = ks["contract_n"] / max(1, ks["contract_launches"])
+    tflops = flop * per / (c_ms * 1e-3) / 1e12
+    fin = lnl.isfinite()
+    out = {"workload": cfg.name, "proposals_per_pass": n, "N": sz["N"], "M": sz["M"], "K": sz["K"], "q": sz["q"],
+           "startup_s": round(build_s, 1), "evals_per_s": n / wall, "ms_per_pass": wall * 1e3,
+           "tile_variant": tune["variant"], "order": order, "contract_ms_per_launch": c_ms,
+           "contract_tflops": tflops, "contract_frac_of_fp64_peak": tflops * 1e12 / PEAK_FP64,
+           "rows_ms_per_launch": ks["rows_ms"] / max(1, ks["rows_launches"]),
+           "epilogue_ms_per_launch": ks["epilogue_ms"] / max(1, ks["epilogue_launches"]),
+           "valid_fraction": float(fin.double().mean()), "any_nan": bool(lnl.isnan().any())}
+    log(f"third generation: {n / wall:.4e} evals/s, contraction {c_ms:.2f} ms ({tflops:.2f} TFLOP/s)")
+    h.close()
     return out
 
 

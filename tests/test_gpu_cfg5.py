@@ -136,6 +136,17 @@ def test_cfg5_exact_lnl_matches_oracle_and_method_error(cfg5):
     print(f"[cfg5] method error near the nodes: {fin.sum()} valid, median {np.median(d):.3e}, max {d.max():.3e} "
           f"(|ln L| median {np.median(np.abs(lb[fin])):.1f})", flush=True)
     assert fin.sum() > 0 and np.all(np.isfinite(lb[fin]))
+    # ln L finished inside the contraction (the order the autotuner picks at
+    # this size) agrees with the default order to rounding
+    h.fuse_epilogue(True)
+    try:
+        lf = gpu_call(h, lambda p, n_, o, s: h.eval(p, n_, o, rbfl.FORM_FP64, s), params)
+    finally:
+        h.fuse_epilogue(False)
+    assert np.array_equal(fin, np.isfinite(lf))
+    df = np.abs(lf[fin] - lm[fin]).max()
+    print(f"[cfg5] ln L inside the contraction vs the default order: max |d| {df:.3e}", flush=True)
+    assert df <= 1e-9 * max(1.0, np.abs(lm[fin]).max())
 
 
 @pytest.mark.timeout(1200)
