@@ -101,7 +101,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
-              "note, not part of this build", file=sys.stderr)
+              "note only", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -44,7 +44,7 @@ enum rbfl_status {
   RBFL_E_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
   RBFL_E_DEVICE = 3,        /* a HIP or rocSOLVER call failed */
   RBFL_E_NUMERICAL = 4,     /* singular RBF system, SVD not converged, metric not positive definite */
-  RBFL_E_UNSUPPORTED = 5,   /* a form or option this build does not provide */
+  RBFL_E_UNSUPPORTED = 5,   /* a form or option this library does not provide */
   RBFL_E_STATE = 6          /* call out of order (e.g. a form not prepared) */
 };
 
@@ -227,7 +227,7 @@ int32_t rbfl_interp(rbfl_handle h, const double *params, int64_t n, double *out,
 
 /* Converts the weights for a reduced-precision form (RBFL_FORM_FP32/BF16/SPLIT).
  * Synchronous; needs exclusive use of the handle.  RBFL_E_UNSUPPORTED for a
- * form this build or this handle's size does not support. */
+ * form this library or this handle's size does not support. */
 int32_t rbfl_prepare(rbfl_handle h, int32_t form);
 
 /* Pre-allocates work space for batches of up to n proposals (optional). */

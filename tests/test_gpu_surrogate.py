@@ -72,7 +72,7 @@ def test_training_judge_and_fallback():
     st = h.surrogate_train(z, tr.data_ptr(), 16384, ho.data_ptr(), 4096, hidden=hidden, batch=512, epochs=30,
                            lr=3e-3, threshold=1e-3)
     print(f"[surrogate] {st}", flush=True)
-    assert st["last_loss"] < 0.8 * st["first_loss"]     # the network learns (but underfits: see the design doc)
+    assert st["last_loss"] < 0.8 * st["first_loss"]     # the network learns (but underfits)
     n = 4096
     lf = torch.empty(n, dtype=torch.float64, device="cuda")
     ls = torch.empty(n, dtype=torch.float64, device="cuda")
