@@ -31,19 +31,33 @@ __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const floa
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wq = wave & 1, wc = wave >> 1;
   const int kk = lane >> 4, ll = lane & 15;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  // one-dimensional grid, column tile fastest; workgroups are dealt to the 8
+  // XCDs in turn, so logical tiles are remapped to give each XCD a contiguous
+  // range: the column tiles of one row tile share an XCD's L2 (and its rows
+  // of A are fetched from HBM once)
+  const int n_nt = (N + 63) / 64;
+  const int64_t nblk = gridDim.x, bx = blockIdx.x;
+  const int64_t xcd = bx & 7, slot = bx >> 3, base = nblk >> 3, extra = nblk & 7;
+  const int64_t tile = xcd * base + (xcd < extra ? xcd : extra) + slot;
+  const int m0 = (int)(tile / n_nt) * 64, n0 = (int)(tile % n_nt) * 64;
   f4 acc[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) acc[t][u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  // staging: consecutive threads walk the operand's contiguous dimension (k
+  // when its k stride is 1, else m or n), so that a wave's loads coalesce
+  const bool a_k = sak == 1, b_k = sbk == 1;
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = tid; e < 16 * 64; e += kT) {
-      const int ek = e >> 6, em = e & 63;
+      const int ek = a_k ? (e & 15) : (e >> 6), em = a_k ? (e >> 4) : (e & 63);
       const int m = m0 + em, k = k0 + ek;
       As[ek][em] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
-      const int n = n0 + em;
-      Bs[ek][em] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
+    }
+    for (int e = tid; e < 16 * 64; e += kT) {
+      const int ek = b_k ? (e & 15) : (e >> 6), en = b_k ? (e >> 4) : (e & 63);
+      const int n = n0 + en, k = k0 + ek;
+      Bs[ek][en] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -185,7 +199,7 @@ void Mlp::reserve(int64_t B) {
 
 static void gemm(int act, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
                  int64_t sbn, const float *bias, float *Z, float *C, int64_t ldc, hipStream_t s) {
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+  dim3 grid((unsigned)((int64_t)((N + 63) / 64) * ((M + 63) / 64)));
   if (act)
     hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(kT), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, Z, C, ldc);
   else
