@@ -93,6 +93,92 @@ __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const floa
     }
 }
 
+// Forward layers whose operands are both contiguous in k (activations
+// A[m][k], weights W[n][k]): 128 x 128 tiles of 8 waves (4 along m x 2 along
+// n, each 2 x 4 tiles of 16 x 16), 16-deep k chunks double-buffered through
+// LDS with one float4 of each operand per thread and chunk, the same
+// XCD-aware tile order.  The accumulation runs over k in the order of
+// k_gemm_f32 (chunks of 16, MFMA steps of 4), so the results are the same;
+// the caller guarantees K % 16 == 0 and 16-byte aligned rows.
+template <int ACT>
+__global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const float *__restrict__ A, int64_t lda,
+                                                     const float *__restrict__ B, int64_t ldb,
+                                                     const float *__restrict__ bias, float *__restrict__ Z,
+                                                     float *__restrict__ C, int64_t ldc) {
+  __shared__ float As[2][16][128 + 4];
+  __shared__ float Bs[2][16][128 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 3, wc = wave >> 2;
+  const int kk = lane >> 4, ll = lane & 15;
+  const int n_nt = (N + 127) / 128;
+  const int64_t nblk = gridDim.x, bx = blockIdx.x;
+  const int64_t xcd = bx & 7, slot = bx >> 3, base = nblk >> 3, extra = nblk & 7;
+  const int64_t tile = xcd * base + (xcd < extra ? xcd : extra) + slot;
+  const int m0 = (int)(tile / n_nt) * 128, n0 = (int)(tile % n_nt) * 128;
+  // staging: thread tid carries row tid / 4 of both tiles, k quad (tid % 4) * 4
+  const int sr = tid >> 2, sk = (tid & 3) * 4;
+  const int am = m0 + sr, bn = n0 + sr;
+  const float *pa = A + (int64_t)(am < M ? am : 0) * lda + sk;
+  const float *pb = B + (int64_t)(bn < N ? bn : 0) * ldb + sk;
+  f4 ra, rb;
+  auto fetch = [&](int k0) {
+    ra = am < M ? *reinterpret_cast<const f4 *>(pa + k0) : f4{0.0f, 0.0f, 0.0f, 0.0f};
+    rb = bn < N ? *reinterpret_cast<const f4 *>(pb + k0) : f4{0.0f, 0.0f, 0.0f, 0.0f};
+  };
+  auto stash = [&](int buf) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[buf][sk + j][sr] = ra[j];
+      Bs[buf][sk + j][sr] = rb[j];
+    }
+  };
+  f4 acc[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int n_chunks = K / 16;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < n_chunks) fetch(16 * (ch + 1));
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + kk;
+      float a[2], b[4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[t] = As[cur][k][wq * 32 + 16 * t + ll];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) b[u] = Bs[cur][k][wc * 64 + 16 * u + ll];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[u], acc[t][u], 0, 0, 0);
+    }
+    if (ch + 1 < n_chunks) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = m0 + wq * 32 + 16 * t + 4 * kk + i;
+      if (m >= M) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int n = n0 + wc * 64 + 16 * u + ll;
+        if (n >= N) continue;
+        float v = acc[t][u][i] + (bias ? bias[n] : 0.0f);
+        if (Z) Z[(int64_t)m * ldc + n] = v;
+        if (ACT == 1) v = v / (1.0f + __expf(-v));
+        C[(int64_t)m * ldc + n] = v;
+      }
+    }
+}
+
 // dY = 2 (Y - T) / count; per-block partial sums of (Y - T)^2 (fixed order).
 __global__ void __launch_bounds__(kT) k_mse(const float *__restrict__ Y, const float *__restrict__ T, int64_t n,
                                             float scale, float *__restrict__ dY, double *__restrict__ part) {
@@ -199,6 +285,16 @@ void Mlp::reserve(int64_t B) {
 
 static void gemm(int act, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
                  int64_t sbn, const float *bias, float *Z, float *C, int64_t ldc, hipStream_t s) {
+  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
+  if (sak == 1 && sbk == 1 && K % 16 == 0 && sam % 4 == 0 && sbn % 4 == 0 && aligned) {
+    dim3 g((unsigned)((int64_t)((N + 127) / 128) * ((M + 127) / 128)));
+    if (act)
+      hipLaunchKernelGGL(k_gemm_f32_nt<1>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc);
+    else
+      hipLaunchKernelGGL(k_gemm_f32_nt<0>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc);
+    RBFL_HIP(hipGetLastError());
+    return;
+  }
   dim3 grid((unsigned)((int64_t)((N + 63) / 64) * ((M + 63) / 64)));
   if (act)
     hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(kT), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, Z, C, ldc);
