@@ -282,9 +282,10 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible, or
  * without autotuning, the split form uses S = 7.  For RBFL_FORM_FP64 it then
  * times whole evaluations of those proposals in each evaluation order (serial,
- * rbfl_pipeline with 2, 4 and 8 chunks, rbfl_fuse_epilogue) and keeps another
- * order than the serial one only if it is at least 1% faster (RBFL_Q_PIPELINE
- * reports the timings).  Synchronous; needs exclusive use of the handle. */
+ * rbfl_pipeline with 2, 4 and 8 chunks, rbfl_fuse_epilogue) and keeps a
+ * pipelined order only if it is at least 3% faster than the serial one, ln L
+ * inside the contraction if it is at least 1% faster than the best of those
+ * (RBFL_Q_PIPELINE reports the timings).  Synchronous; needs exclusive use of the handle. */
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
 
