@@ -516,16 +516,6 @@ __global__ void k_sur_inputs(const double *__restrict__ params, int64_t ld, int6
   for (int d = 0; d < 4; ++d) x[b * 4 + d] = (float)(params[d * ld + b0 + b] / c->semi[d]);
 }
 
-// Surrogate outputs: Y[b][k] = mu_k + sd_k ys[b][k] in FP64, padded rows of Kp.
-__global__ void k_sur_outputs(const float *__restrict__ ys, const float *__restrict__ mu,
-                              const float *__restrict__ sd, int64_t nb, int K, int Kp, double *__restrict__ Y) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nb * K) return;
-  const int64_t b = e / K;
-  const int k = (int)(e % K);
-  Y[b * Kp + k] = (double)mu[k] + (double)sd[k] * (double)ys[e];
-}
-
 // Per-column mean and standard deviation of Y [n][K] (two passes, FP64).
 __global__ void k_col_stats(const double *__restrict__ Y, int64_t n, int K, float *__restrict__ mu,
                             float *__restrict__ sd) {
@@ -715,13 +705,6 @@ void launch_series_lnl(const EvalConsts *c, const double *params, int64_t ld, in
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_sur_inputs, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, params, ld, b0, nb, c, x);
-  RBFL_HIP(hipGetLastError());
-}
-
-void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_sur_outputs, dim3((unsigned)((nb * K + 255) / 256)), dim3(256), 0, s, ys, mu, sd, nb, K, Kp,
-                     Y);
   RBFL_HIP(hipGetLastError());
 }
 

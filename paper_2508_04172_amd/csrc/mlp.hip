@@ -100,11 +100,15 @@ __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const floa
 // XCD-aware tile order.  The accumulation runs over k in the order of
 // k_gemm_f32 (chunks of 16, MFMA steps of 4), so the results are the same;
 // the caller guarantees K % 16 == 0 and 16-byte aligned rows.
+// ACT 0: linear, 1: SiLU, 2: linear with the output standardisation undone
+// in FP64, Y[m][n] = mu[n] + sd[n] v into the interpolant's output layout
+// (row stride ldc), as the surrogate form's inference needs it.
 template <int ACT>
 __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const float *__restrict__ A, int64_t lda,
                                                      const float *__restrict__ B, int64_t ldb,
                                                      const float *__restrict__ bias, float *__restrict__ Z,
-                                                     float *__restrict__ C, int64_t ldc) {
+                                                     float *__restrict__ C, int64_t ldc, const float *__restrict__ mu,
+                                                     const float *__restrict__ sd, double *__restrict__ Y64) {
   __shared__ float As[2][16][128 + 4];
   __shared__ float Bs[2][16][128 + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,11 +176,26 @@ __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const 
         const int n = n0 + wc * 64 + 16 * u + ll;
         if (n >= N) continue;
         float v = acc[t][u][i] + (bias ? bias[n] : 0.0f);
+        if (ACT == 2) {
+          Y64[(int64_t)m * ldc + n] = (double)mu[n] + (double)sd[n] * (double)v;
+          continue;
+        }
         if (Z) Z[(int64_t)m * ldc + n] = v;
         if (ACT == 1) v = v / (1.0f + __expf(-v));
         C[(int64_t)m * ldc + n] = v;
       }
     }
+}
+
+// Y[b][c] = mu[c] + sd[c] y[b][c] in FP64 (row stride ldy) from FP32 y [B][out].
+__global__ void __launch_bounds__(kT) k_unstandardise(const float *__restrict__ y, int64_t B, int out,
+                                                      const float *__restrict__ mu, const float *__restrict__ sd,
+                                                      double *__restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (e >= B * out) return;
+  const int64_t b = e / out;
+  const int c = (int)(e - b * out);
+  Y[b * ldy + c] = (double)mu[c] + (double)sd[c] * (double)y[e];
 }
 
 // dY = 2 (Y - T) / count; per-block partial sums of (Y - T)^2 (fixed order).
@@ -283,15 +302,23 @@ void Mlp::reserve(int64_t B) {
   cap = B;
 }
 
+// Whether k_gemm_f32_nt applies: both operands contiguous in k, K a multiple
+// of its 16-deep chunks, rows of 16-byte aligned float4s.
+static bool nt_ok(int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk, int64_t sbn) {
+  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
+  return sak == 1 && sbk == 1 && K % 16 == 0 && sam % 4 == 0 && sbn % 4 == 0 && aligned;
+}
+
 static void gemm(int act, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk,
                  int64_t sbn, const float *bias, float *Z, float *C, int64_t ldc, hipStream_t s) {
-  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
-  if (sak == 1 && sbk == 1 && K % 16 == 0 && sam % 4 == 0 && sbn % 4 == 0 && aligned) {
+  if (nt_ok(K, A, sam, sak, B, sbk, sbn)) {
     dim3 g((unsigned)((int64_t)((N + 127) / 128) * ((M + 127) / 128)));
     if (act)
-      hipLaunchKernelGGL(k_gemm_f32_nt<1>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc);
+      hipLaunchKernelGGL(k_gemm_f32_nt<1>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc, nullptr,
+                         nullptr, nullptr);
     else
-      hipLaunchKernelGGL(k_gemm_f32_nt<0>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc);
+      hipLaunchKernelGGL(k_gemm_f32_nt<0>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc, nullptr,
+                         nullptr, nullptr);
     RBFL_HIP(hipGetLastError());
     return;
   }
@@ -309,6 +336,25 @@ void Mlp::forward(const float *X, int64_t B, float *Y, hipStream_t s) {
   gemm(1, b, hid, in, X, in, 1, p.p + o_w1, 1, in, p.p + o_b1, Z1.p, H1.p, hid, s);
   gemm(1, b, hid, hid, H1.p, hid, 1, p.p + o_w2, 1, hid, p.p + o_b2, Z2.p, H2.p, hid, s);
   gemm(0, b, out, hid, H2.p, hid, 1, p.p + o_w3, 1, hid, p.p + o_b3, nullptr, Y, out, s);
+}
+
+void Mlp::infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s) {
+  reserve(B);
+  const int b = (int)B;
+  gemm(1, b, hid, in, X, in, 1, p.p + o_w1, 1, in, p.p + o_b1, nullptr, H1.p, hid, s);
+  gemm(1, b, hid, hid, H1.p, hid, 1, p.p + o_w2, 1, hid, p.p + o_b2, nullptr, H2.p, hid, s);
+  const float *W3 = p.p + o_w3;
+  if (nt_ok(hid, H2.p, hid, 1, W3, 1, hid)) {
+    dim3 g((unsigned)((int64_t)((out + 127) / 128) * ((b + 127) / 128)));
+    hipLaunchKernelGGL(k_gemm_f32_nt<2>, g, dim3(512), 0, s, b, out, hid, H2.p, (int64_t)hid, W3, (int64_t)hid,
+                       p.p + o_b3, nullptr, nullptr, ldy, mu, sd, Y);
+    RBFL_HIP(hipGetLastError());
+    return;
+  }
+  gemm(0, b, out, hid, H2.p, hid, 1, W3, 1, hid, p.p + o_b3, nullptr, Yb.p, out, s);
+  hipLaunchKernelGGL(k_unstandardise, dim3((unsigned)(((int64_t)b * out + kT - 1) / kT)), dim3(kT), 0, s, Yb.p,
+                     (int64_t)b, out, mu, sd, Y, ldy);
+  RBFL_HIP(hipGetLastError());
 }
 
 void Mlp::loss_grad(const float *X, const float *T, int64_t B, hipStream_t s) {

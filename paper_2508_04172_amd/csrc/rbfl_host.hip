@@ -1617,7 +1617,6 @@ static void reserve(Ctx &c, int64_t n) {
   }
   if (c.sur) {
     c.sur_x.alloc((size_t)n * 4);
-    c.sur_y.alloc((size_t)n * c.K);
     c.sur->reserve(n);
   }
 }
@@ -1817,8 +1816,7 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
       if (c.sur && c.sur_ok) {
         launch_sur_inputs(params, ld, b0, nb, c.consts.p, c.sur_x.p, s);
         mark(1);
-        c.sur->forward(c.sur_x.p, nb, c.sur_y.p, s);
-        launch_sur_outputs(c.sur_y.p, c.sur_mu.p, c.sur_sd.p, nb, c.K, c.Kp, c.Y.p, s);
+        c.sur->infer(c.sur_x.p, nb, c.sur_mu.p, c.sur_sd.p, c.Y.p, c.Kp, s);
       } else {
         fp64();
       }
@@ -2060,7 +2058,6 @@ static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
   c.sur->init(4, sp->hidden, c.K, sp->init_normals);
   if (c.cap == 0) reserve(c, 65536);
   c.sur_x.alloc((size_t)c.cap * 4);
-  c.sur_y.alloc((size_t)c.cap * c.K);
   c.sur->reserve(std::max<int64_t>(c.cap, sp->batch));
   // targets: the FP64 interpolant at the training proposals, standardised per column
   const int64_t n = sp->n_train;

@@ -99,6 +99,10 @@ struct Mlp {
   void init(int n_in, int hidden, int n_out, const double *normals);
   void reserve(int64_t B);
   void forward(const float *X, int64_t B, float *Y, hipStream_t s);
+  // inference into the interpolant's output layout: Y[b][c] = mu[c] + sd[c] y[b][c]
+  // in FP64 (row stride ldy) for c < out, y as forward() computes it; no
+  // pre-activations stored
+  void infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s);
   void loss_grad(const float *X, const float *T, int64_t B, hipStream_t s);   // loss -> this->loss
   void adam(double lr, double b1, double b2, double eps, hipStream_t s);
 };
@@ -168,7 +172,7 @@ struct Ctx {
   // surrogate (rbfl_surrogate_train)
   Mlp *sur = nullptr;
   DevBuf<float> sur_mu, sur_sd;       // per-column standardisation of the outputs
-  DevBuf<float> sur_x, sur_y;         // work space [cap][4], [cap][K]
+  DevBuf<float> sur_x;                // work space [cap][4]
   bool sur_ok = false;                // held-out check passed
   double sur_stats[8] = {};
   // optional per-launch timing (rbfl_profile)
@@ -287,8 +291,6 @@ void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const doub
                            const double *scale, double *Y, hipStream_t s, int variant, hipEvent_t mid);
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s);
-void launch_sur_outputs(const float *ys, const float *mu, const float *sd, int64_t nb, int K, int Kp, double *Y,
-                        hipStream_t s);
 void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s);
 void launch_standardise(const double *Y, int64_t n, int K, const float *mu, const float *sd, float *T, hipStream_t s);
 void launch_convert_weights(const double *W, size_t n, float *hi, uint16_t *b16, hipStream_t s);
