@@ -26,7 +26,15 @@ sys.path.insert(0, ROOT)
 METRIC = "ln L evals/s at |dlnL|<=1e-3 vs FP64 oracle: plain vs mixed/batched/surrogate"
 PEAK_FP64 = 78.6e12     # dense FP64 MFMA, MI355X
 PEAK_FP32 = 157.3e12    # dense FP32 MFMA, MI355X
+PEAK_BF16 = 2.5e15      # dense bf16 MFMA, MI355X
 PEAK_INT8 = 5.0e15      # dense int8 MFMA, MI355X
+
+
+def roof(achieved, peak, unit="TFLOP/s", bound="mfma", **extra):
+    """Roofline object of one form's dominant kernel: achieved and peak in
+    units of 1e12 per second, and their ratio."""
+    return dict({"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
+                 "frac": achieved / peak}, **extra)
 
 
 def log(msg):
@@ -80,6 +88,8 @@ def main():
     ap.add_argument("--surrogate-train", type=int, default=200000,
                     help="training proposals for the surrogate form (0 = skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--third-generation-surrogate", type=int, default=100000,
+                    help="training proposals for the surrogate on the third-generation workload (0 = skip)")
     ap.add_argument("--third-generation", action="store_true",
                     help="also report the FP64 form on the third-generation workload (2048 s at 4096 Hz, "
                          "N=3000, K=2475, 1e6 proposals per pass; its oracle checks samples in "
@@ -198,20 +208,27 @@ def main():
         w2, ks2, lf = run_form(form, max(3, args.steps // 2), 1)
         v2 = n * max(3, args.steps // 2) / w2
         c2 = ks2["contract_ms"] / max(1, ks2["contract_launches"])
+        ach = flop_per_query * per_launch_n / (c2 * 1e-3)
         forms[name] = {"evals_per_s": v2, "ms_per_step": w2 / max(3, args.steps // 2) * 1e3,
-                       "contract_ms_per_launch": c2,
-                       "contract_tflops": flop_per_query * per_launch_n / (c2 * 1e-3) / 1e12}
+                       "contract_ms_per_launch": c2, "contract_tflops": ach / 1e12}
+        if form == rbfl.FORM_FP32:
+            forms[name]["roofline"] = roof(ach, PEAK_FP32, kernel="k_contract_fp32")
+        elif form == rbfl.FORM_BF16:
+            forms[name]["roofline"] = roof(ach, PEAK_BF16, kernel="k_bf16_contract (bf16 products issued)")
         if form == rbfl.FORM_SPLIT:
             # int8 products actually issued: one per slice pair i + j < S
             S = tune["split"]["slices"]
             pairs = S * (S + 1) // 2
             tops = pairs * flop_per_query * per_launch_n / (c2 * 1e-3)
-            forms[name].update({"slices": S, "int8_tops": tops / 1e12, "int8_frac": tops / PEAK_INT8})
+            forms[name].update({"slices": S, "int8_tops": tops / 1e12, "int8_frac": tops / PEAK_INT8,
+                                "roofline": roof(tops, PEAK_INT8, unit="TOP/s",
+                                                 kernel="k_split_contract (int8 products issued)")})
         outs[name] = lf
         log(f"{name}: {v2:.4e} evals/s, contraction {c2:.3f} ms/launch")
 
     if args.surrogate_train > 0:
-        forms["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64)
+        forms["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64,
+                                             args.surrogate_train, args.surrogate_epochs, max(3, args.steps // 2))
     if args.ragged_events > 0:
         forms["ragged"] = bench_ragged(args, np, torch, rbfl, wl)
 
@@ -285,11 +302,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
+def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64, n_train, epochs, steps):
     """Surrogate form: MLP 4 -> 256 -> 256 -> K trained by the library's own
     kernels on proposals whose targets the FP64 interpolant computes; judged on
     1e4 held-out proposals at |d ln L| <= 1e-3 (fallback to the interpolant
-    otherwise).  The network path's throughput is reported either way."""
+    otherwise).  The network path's throughput is reported either way, and the
+    network's own kernels (the three FP32 MFMA layers, HIP events) against the
+    FP32 matrix-core peak."""
     n = params.shape[1]
     K = h.sizes()["K"]
     hidden = 256
@@ -300,22 +319,25 @@ def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
         qd = wl.queries(cfg, n=m, seed=seed).near_nodes(h.nodes(), idx, jit)
         return torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))).cuda()
 
-    tr = dev(args.surrogate_train, 5)
+    tr = dev(n_train, 5)
     ho = dev(10000, 6)
-    log(f"surrogate: training on {args.surrogate_train} proposals, {args.surrogate_epochs} epochs")
-    st = h.surrogate_train(z, tr.data_ptr(), args.surrogate_train, ho.data_ptr(), 10000, hidden=hidden,
-                           batch=1024, epochs=args.surrogate_epochs, lr=1e-3, threshold=1e-3)
+    log(f"surrogate: training on {n_train} proposals, {epochs} epochs")
+    st = h.surrogate_train(z, tr.data_ptr(), n_train, ho.data_ptr(), 10000, hidden=hidden,
+                           batch=1024, epochs=epochs, lr=1e-3, threshold=1e-3)
+    del tr, ho
     log(f"surrogate: {st}")
     h.surrogate_force(True)
     sp = torch.cuda.current_stream().cuda_stream
     h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SURROGATE, sp)
     torch.cuda.synchronize()
-    steps = max(3, args.steps // 2)
+    h.profile(True)
     t = time.perf_counter()
     for _ in range(steps):
         h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SURROGATE, sp)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
+    h.profile(False)
+    ks = h.kernel_stats()
     ls = lnl.cpu().numpy()
     h.surrogate_force(False)
     fin = np.isfinite(l64) & np.isfinite(ls)
@@ -328,6 +350,12 @@ def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64):
            "last_loss": st["last_loss"], "max_dlnl_vs_fp64_gpu_all": float(d.max()),
            "median_dlnl_vs_fp64_gpu_all": float(np.median(d)), "network_flop_per_eval": flop,
            "note": "the surrogate form evaluates the FP64 interpolant unless accepted"}
+    net_ms = ks["contract_ms"] / max(1, ks["contract_launches"])
+    if net_ms > 0:
+        ach = flop * ks["contract_n"] / max(1, ks["contract_launches"]) / (net_ms * 1e-3)
+        res.update({"network_ms_per_launch": net_ms, "epilogue_ms_per_launch":
+                    ks["epilogue_ms"] / max(1, ks["epilogue_launches"]),
+                    "roofline": roof(ach, PEAK_FP32, kernel="k_gemm_f32 + k_gemm_f32_nt (MLP layers)")})
     log(f"surrogate: network path {res['network_evals_per_s']:.4e} evals/s, accepted={st['accepted']}")
     return res
 
@@ -522,8 +550,13 @@ def bench_third_generation(args, np, torch, rbfl, wl):
            "contract_tflops": tflops, "contract_frac_of_fp64_peak": tflops * 1e12 / PEAK_FP64,
            "rows_ms_per_launch": ks["rows_ms"] / max(1, ks["rows_launches"]),
            "epilogue_ms_per_launch": ks["epilogue_ms"] / max(1, ks["epilogue_launches"]),
-           "valid_fraction": float(fin.double().mean()), "any_nan": bool(lnl.isnan().any())}
+           "valid_fraction": float(fin.double().mean()), "any_nan": bool(lnl.isnan().any()),
+           "roofline": roof(tflops * 1e12, PEAK_FP64, kernel="k_gemm_lnl_fp64" if order["fused_epilogue"]
+                            else "k_gemm_fp64")}
     log(f"third generation: {n / wall:.4e} evals/s, contraction {c_ms:.2f} ms ({tflops:.2f} TFLOP/s)")
+    if args.third_generation_surrogate > 0:
+        out["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, lnl.cpu().numpy(),
+                                           args.third_generation_surrogate, 10, reps)
     h.close()
     return out
 
@@ -648,7 +681,9 @@ def bench_ragged(args, np, torch, rbfl, wl):
            "walkers_per_event": walkers, "per_event_loop_evals_per_s": total * steps / wall_loop,
            "contract_tflops_incl_epilogue": flops * steps / wall / 1e12, "startup_s": round(build_s, 2),
            "plan": plan.info(), "max_abs_diff_vs_per_event": dmax, "domain_agrees": agree,
-           "valid_fraction": float(fin.mean())}
+           "valid_fraction": float(fin.mean()),
+           "roofline": roof(flops * steps / wall, PEAK_FP64,
+                            kernel="k_ragged_contract_fp64 + k_ragged_epilogue (whole plan launch)")}
     log(f"ragged: {res['evals_per_s']:.4e} evals/s (graph plan) vs {res['per_event_loop_evals_per_s']:.4e} "
         f"(per-event loop); start-up {build_s:.1f} s")
     plan.close()
