@@ -266,10 +266,15 @@ enum rbfl_query_what {
   RBFL_Q_CENTRE = 18,       /* double[8]: the ellipsoid centre used (m1, m2, chi1, chi2), the optimiser's
                                iota and phi, the network SNR at center_phys (iota = phi = 0) and at the
                                optimum (0, 0 without RBFL_FLAG_OPTIMISE_CENTRE) */
-  RBFL_Q_PIPELINE = 19      /* double[7]: chunks per FP64 evaluation in use (rbfl_pipeline), the
+  RBFL_Q_PIPELINE = 19,     /* double[7]: chunks per FP64 evaluation in use (rbfl_pipeline), the
                                autotuner's median ms per evaluation at 1, 2, 4 and 8 chunks (0 = not
                                timed), 1/0 for ln L finished inside the contraction (rbfl_fuse_epilogue)
                                and the autotuner's ms per evaluation in that order (0 = not timed) */
+  RBFL_Q_SURROGATE_NET = 20 /* float[n_params + 2 K]: the surrogate's trained parameters (the layout
+                               of rbfl_mlp_get for n_in = 4, the width given to rbfl_surrogate_train,
+                               n_out = K), then the per-column mean and standard deviation that map
+                               its outputs to the interpolated quantities (out = mean + sd * y);
+                               RBFL_E_STATE before rbfl_surrogate_train.  Synchronises the device. */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 

@@ -2225,6 +2225,18 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_SPLIT_ERR:
       copy_out(out, bytes, c.split_err, sizeof(c.split_err));
       return;
+    case RBFL_Q_SURROGATE_NET: {
+      if (!c.sur) throw Error(RBFL_E_STATE, "no surrogate trained on this handle");
+      const size_t np = (size_t)c.sur->np, need = sizeof(float) * (np + 2 * (size_t)c.K);
+      require(out != nullptr, "out is NULL");
+      require(bytes >= need, "output buffer too small (need " + std::to_string(need) + " bytes)");
+      float *o = static_cast<float *>(out);
+      RBFL_HIP(hipDeviceSynchronize());
+      RBFL_HIP(hipMemcpy(o, c.sur->p.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+      RBFL_HIP(hipMemcpy(o + np, c.sur_mu.p, sizeof(float) * c.K, hipMemcpyDeviceToHost));
+      RBFL_HIP(hipMemcpy(o + np + c.K, c.sur_sd.p, sizeof(float) * c.K, hipMemcpyDeviceToHost));
+      return;
+    }
     case RBFL_Q_KERNEL_STATS: {
       double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (auto &t : c.timed) {

@@ -27,7 +27,7 @@ FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
-    Q_PIPELINE = range(20)
+    Q_PIPELINE, Q_SURROGATE_NET = range(21)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
@@ -425,6 +425,15 @@ class Handle:
         return {"accepted": bool(v[0]), "holdout_max_dlnl": float(v[1]), "holdout_median_dlnl": float(v[2]),
                 "first_loss": float(v[3]), "last_loss": float(v[4]), "epochs": int(v[5]),
                 "train_s": float(v[6]), "n_train": int(v[7])}
+
+    def surrogate_net(self, hidden: int):
+        """The trained surrogate (RBFL_Q_SURROGATE_NET): FP32 parameter vector
+        for 4 -> hidden -> hidden -> K, and the per-column mean and standard
+        deviation of its outputs."""
+        K = self.sizes()["K"]
+        n = mlp_param_count(4, hidden, K)
+        v = self._query(Q_SURROGATE_NET, n + 2 * K, np.float32)
+        return v[:n].copy(), v[n:n + K].copy(), v[n + K:].copy()
 
     def set_variant(self, form: int, variant: int):
         """Pins the contraction tile variant of `form` (rbfl_set_variant)."""

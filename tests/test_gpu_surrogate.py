@@ -126,3 +126,41 @@ def test_surrogate_gain_over_interpolant():
     print(f"[surrogate] evals/s fp64 {n / times['fp64']:.3e}, surrogate {n / times['surrogate']:.3e}, "
           f"held-out max |dlnL| {st['holdout_max_dlnl']:.3e}", flush=True)
     assert np.isfinite(times["surrogate"])
+
+
+@pytest.mark.parametrize("hidden", [64, 40])
+def test_surrogate_outputs_match_oracle_network(hidden):
+    """The surrogate form's interpolated quantities (rbfl_interp) against the
+    oracle network evaluated in FP64 on the trained FP32 parameters and the
+    stored output standardisation, out = mean + sd * y.  Width 64 takes the
+    inference path whose last layer writes the FP64 outputs itself; width 40
+    (not a multiple of 16) the generic layer and a separate conversion.  The
+    network inputs are the unit-ball coordinates Delta e / a (the library
+    rounds them to FP32, so the oracle is fed the same rounding)."""
+    torch = _torch()
+    cfg = wl.SMALL_MULTI
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    K = h.sizes()["K"]
+    z = wl.mlp_normals(rbfl.mlp_param_count(4, hidden, K))
+    tr = _params_device(torch, h, cfg, 8192, seed=5)
+    ho = _params_device(torch, h, cfg, 2048, seed=6)
+    st = h.surrogate_train(z, tr.data_ptr(), 8192, ho.data_ptr(), 2048, hidden=hidden, batch=512, epochs=3,
+                           lr=3e-3, threshold=1e12)
+    assert st["accepted"]
+    vec, mu, sd = h.surrogate_net(hidden)
+    n = 1000                                   # ragged against the 128-row tiles
+    p = _params_device(torch, h, cfg, n, seed=9)
+    out = torch.empty((n, K), dtype=torch.float64, device="cuda")
+    h.interp(p.data_ptr(), n, out.data_ptr(), rbfl.FORM_SURROGATE)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    semi = h.frame()["semi"]
+    pc = p.cpu().numpy()
+    X = (pc[:4] / semi[:, None]).T.astype(np.float32).astype(np.float64)
+    y, _ = omlp.forward(vec.astype(np.float64), X, 4, hidden, K)
+    want = mu.astype(np.float64) + sd.astype(np.float64) * y
+    err = np.abs(got - want) / (sd.astype(np.float64) * (1.0 + np.abs(y)))
+    print(f"[surrogate] width {hidden}: max scaled |out - oracle| {err.max():.3e}", flush=True)
+    assert np.isfinite(got).all()
+    assert err.max() <= 1e-4
+    h.close()
