@@ -27,6 +27,7 @@ METRIC = "ln L evals/s at |dlnL|<=1e-3 vs FP64 oracle: plain vs mixed/batched/su
 PEAK_FP64 = 78.6e12     # dense FP64 MFMA, MI355X
 PEAK_FP32 = 157.3e12    # dense FP32 MFMA, MI355X
 PEAK_BF16 = 2.5e15      # dense bf16 MFMA, MI355X
+PEAK_HBM = 8.0e12       # HBM3E, MI355X
 PEAK_INT8 = 5.0e15      # dense int8 MFMA, MI355X
 
 
@@ -214,7 +215,15 @@ def main():
         if form == rbfl.FORM_FP32:
             forms[name]["roofline"] = roof(ach, PEAK_FP32, kernel="k_contract_fp32")
         elif form == rbfl.FORM_BF16:
-            forms[name]["roofline"] = roof(ach, PEAK_BF16, kernel="k_bf16_contract (bf16 products issued)")
+            # reads (N+M) bf16 row entries and writes K FP64 outputs per proposal: at
+            # 2 (N+M) K / (2 (N+M) + 8 K) flop per byte it sits below the bf16 ridge
+            # (2.5e15 / 8e12 = 312 flop/B), so HBM bounds it
+            bytes_launch = per_launch_n * (2.0 * NM + 8.0 * K) + 2.0 * NM * K
+            gbs = bytes_launch / (c2 * 1e-3)
+            forms[name]["roofline"] = {"bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9,
+                                       "unit": "GB/s", "frac": gbs / PEAK_HBM, "kernel": "k_bf16_contract",
+                                       "bytes_per_launch": bytes_launch,
+                                       "mfma_tflops": ach / 1e12, "mfma_frac": ach / PEAK_BF16}
         if form == rbfl.FORM_SPLIT:
             # int8 products actually issued: one per slice pair i + j < S
             S = tune["split"]["slices"]
