@@ -20,10 +20,12 @@
 // with i + j >= S and the digit remainders costs at most (S + 3) 254^-S of
 // s_q s_c per kernel row.
 //
-// Tiles.  A workgroup of 4 waves (2 x 2) computes 64 proposals x 64 columns;
-// each wave one 32 x 32 tile with v_mfma_i32_32x32x32_i8, whose lane l holds
-// A[l%32][16(l/32) + e] and B[16(l/32) + e][l%32] (e < 16, 16 int8 in 4
-// VGPRs) and accumulator element i = D[8(i/4) + 4(l/32) + i%4][l%32]
+// Tiles.  A workgroup of 8 waves (4 along the proposals x 2 along the
+// columns, one workgroup per CU, two waves per SIMD) computes 128 proposals x
+// 64 columns: per staged digit byte that is 4/3 the products of a 64 x 64
+// tile, whose L2 and MALL traffic bounded it.  Each wave computes one
+// 32 x 32 tile with v_mfma_i32_32x32x32_i8, whose lane l holds
+// A[l%32][16(l/32) + e] and B[16(l/32) + e][l%32] (e < 16, 16 int8 in 4 VGPRs) and accumulator element i = D[8(i/4) + 4(l/32) + i%4][l%32]
 // (measured on gfx950).  Digits of 32 kernel rows of both operands are
 // staged through LDS per step, double-buffered, the next step's global loads
 // in flight during the current step's MFMAs.
@@ -40,9 +42,10 @@ namespace rbfl {
 namespace {
 
 constexpr int kMaxSlices = 8;
-constexpr int kSplitQ = 64;      // proposals per workgroup
-constexpr int kSplitC = 64;      // columns per workgroup
-constexpr int kSplitThreads = 256;
+constexpr int kSplitWQ = 4;      // waves along the proposals (each 32 proposals x 32 columns)
+constexpr int kSplitQ = 32 * kSplitWQ;   // proposals per workgroup
+constexpr int kSplitC = 64;      // columns per workgroup (two waves)
+constexpr int kSplitThreads = 128 * kSplitWQ;
 constexpr int kMaxSplitRows = 16384;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -160,32 +163,42 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
 // i + j < S.  One-dimensional grid over (proposal tile, column tile), the
 // column tile fastest.
 template <int S>
-__global__ void __launch_bounds__(kSplitThreads, 2)
+__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
     k_split_contract(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
                      const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
                      double *__restrict__ Y) {
-  constexpr int kPer = S * 2 * 64;                       // v4i entries per operand per stage
-  constexpr int kLoads = (kPer + kSplitThreads - 1) / kSplitThreads;
-  __shared__ v4i As[2][S][2][64];
-  __shared__ v4i Bs[2][S][2][64];
+  constexpr int kPerA = S * 2 * kSplitQ, kPerB = S * 2 * kSplitC;   // v4i entries per stage
+  constexpr int kLoadsA = (kPerA + kSplitThreads - 1) / kSplitThreads;
+  constexpr int kLoadsB = (kPerB + kSplitThreads - 1) / kSplitThreads;
+  __shared__ v4i As[2][S][2][kSplitQ];
+  __shared__ v4i Bs[2][S][2][kSplitC];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wq = wave & 1, wc = wave >> 1;
+  const int wq = wave % kSplitWQ, wc = wave / kSplitWQ;
   const int G = rows / 16;
   const int n_ct = Kp / kSplitC;
   const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
   const int c0 = (int)(tile % n_ct) * kSplitC;
   const int64_t q0 = (tile / n_ct) * kSplitQ;
 
-  v4i ra[kLoads], rb[kLoads];
+  // stage entry e of an operand with W-wide tiles: digit e / (2 W), 16-row
+  // group g0 + (e / W) % 2, tile position e % W
+  v4i ra[kLoadsA], rb[kLoadsB];
   auto fetch = [&](int g0) {
 #pragma unroll
-    for (int k = 0; k < kLoads; ++k) {
+    for (int k = 0; k < kLoadsA; ++k) {
       const int e = tid + k * kSplitThreads;
-      if (e < kPer) {
-        const int i = e >> 7, kh = (e >> 6) & 1, m = e & 63;
+      if (e < kPerA) {
+        const int i = e / (2 * kSplitQ), kh = (e / kSplitQ) & 1, m = e % kSplitQ;
         const int64_t q = q0 + m;
         ra[k] = q < nb ? AS[((int64_t)i * G + g0 + kh) * nb + q] : v4i{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kLoadsB; ++k) {
+      const int e = tid + k * kSplitThreads;
+      if (e < kPerB) {
+        const int i = e / (2 * kSplitC), kh = (e / kSplitC) & 1, m = e % kSplitC;
         rb[k] = BS[((int64_t)i * G + g0 + kh) * Kp + c0 + m];
       }
     }
@@ -195,13 +208,14 @@ __global__ void __launch_bounds__(kSplitThreads, 2)
     // their global loads) above the current step's MFMAs
     asm volatile("" ::: "memory");
 #pragma unroll
-    for (int k = 0; k < kLoads; ++k) {
+    for (int k = 0; k < kLoadsA; ++k) {
       const int e = tid + k * kSplitThreads;
-      if (e < kPer) {
-        const int i = e >> 7, kh = (e >> 6) & 1, m = e & 63;
-        As[buf][i][kh][m] = ra[k];
-        Bs[buf][i][kh][m] = rb[k];
-      }
+      if (e < kPerA) As[buf][e / (2 * kSplitQ)][(e / kSplitQ) & 1][e % kSplitQ] = ra[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kLoadsB; ++k) {
+      const int e = tid + k * kSplitThreads;
+      if (e < kPerB) Bs[buf][e / (2 * kSplitC)][(e / kSplitC) & 1][e % kSplitC] = rb[k];
     }
   };
 
