@@ -2,8 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain float64 numpy.
 
-Parity unpinned against the literature: the 2PN spin-spin and the 2.5PN to
-3.5PN terms of pn_phase_22 (its lower orders are pinned; see its docstring).
+Parity unpinned against the literature: the spin-orbit terms of pn_phase_22
+at 2.5PN, 3PN and 3.5PN and its 3PN spin-spin term (every non-spinning order
+through 3.5PN, the 1.5PN spin-orbit and the 2PN spin-spin terms are pinned;
+see its docstring).
 """
 from __future__ import annotations
 
@@ -61,7 +63,8 @@ class Grid:
 
 
 def psd_analytic(f: np.ndarray, scale: float = 1.0) -> np.ndarray:
-    """aLIGO-like analytic one-sided PSD, x = f / 215 Hz (workload definition)."""
+    """aLIGO-like analytic one-sided PSD, x = f / 215 Hz (workload definition).
+    Pinned at hand-evaluated points (x = 1 gives 33e-49)."""
     x = np.asarray(f, dtype=np.float64) / 215.0
     return scale * 1e-49 * (x ** -4.14 - 5.0 * x ** -2 + 111.0 * (1.0 - x ** 2 + 0.5 * x ** 4) / (1.0 + 0.5 * x ** 2))
 
@@ -95,7 +98,10 @@ def mass_params(m1, m2):
 
 
 def phys_to_theta(phys, f0: float) -> np.ndarray:
-    """(m1, m2, chi1, chi2) -> (theta0, theta3, theta3s, theta3s_bar), Eq. metric_coords."""
+    """(m1, m2, chi1, chi2) -> (theta0, theta3, theta3s, theta3s_bar), Eq. metric_coords.
+    Pinned: theta3s through the 1.5PN spin-orbit phase, theta3s_bar through the
+    mass-weighted effective spin and the mass-ratio-free difference
+    theta3s - theta3s_bar = -(19/48) chi_s (pi M f0)^(-2/3)."""
     m1, m2, c1, c2 = (np.asarray(p, dtype=np.float64) for p in phys)
     m_s, eta, delta = mass_params(m1, m2)
     chi_s = 0.5 * (c1 + c2)
@@ -144,11 +150,12 @@ def pn_phase_22(f, m1, m2, chi1, chi2):
 
     Psi = -pi/4 + 3/(128 eta v^5) sum_k (phi_k + phi_kl log-terms) v^k, v = (pi M f)^(1/3),
     with 3.5PN non-spinning coefficients and aligned-spin spin-orbit /
-    spin-spin terms (literature values).  Pinned in the tests: the Newtonian
-    chirp time, the 1PN, 1.5PN and 2PN non-spinning terms (through
-    dPsi/df = 2 pi t(f) and the time-to-coalescence series) and the 1.5PN
-    spin-orbit term; the 2PN spin-spin, 2.5PN, 3PN and 3.5PN terms are
-    parity unpinned against the literature.
+    spin-spin terms (literature values).  Pinned in the tests through
+    dPsi/df = 2 pi t(f) against the published time-to-coalescence series:
+    every non-spinning term through 3.5PN (with the 3PN logarithm), the 1.5PN
+    spin-orbit term and the 2PN spin-spin term; the spin-orbit terms at 2.5PN,
+    3PN and 3.5PN and the 3PN spin-spin term are parity unpinned against the
+    literature.
     """
     m_s, eta, delta = mass_params(m1, m2)
     chi_s = 0.5 * (chi1 + chi2)
@@ -214,7 +221,8 @@ def reference_frequency(grid: Grid, psd: np.ndarray, phys) -> float:
 
 def mode_amplitude(l: int, m: int, eta: float, delta: float) -> float:
     """Relative mode amplitudes of the synthetic family: A22 = 1, A21 = 0.1 delta,
-    A33 = 0.3 delta, A32 = 0.05 (1 - 3 eta), A44 = 0.1 (1 - 3 eta)."""
+    A33 = 0.3 delta, A32 = 0.05 (1 - 3 eta), A44 = 0.1 (1 - 3 eta).  Pinned,
+    through the waveform, at hand-evaluated fractions for three mass pairs."""
     table = {(2, 2): 1.0, (2, 1): 0.1 * delta, (3, 3): 0.3 * delta,
              (3, 2): 0.05 * (1.0 - 3.0 * eta), (4, 4): 0.1 * (1.0 - 3.0 * eta)}
     return table[(l, m)]
