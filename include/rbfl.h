@@ -212,7 +212,8 @@ int32_t rbfl_exact_parts(rbfl_handle h, const double *params, int64_t n, double 
  *   reading), -inf outside the ellipsoid, the physical region or the window.
  * form: RBFL_FORM_*; forms other than FP64 need rbfl_prepare first.
  * Enqueued on `stream`; no allocation when n <= the handle's work capacity
- * (rbfl_reserve), so a call can be captured in a HIP graph after a reserve. */
+ * (rbfl_reserve), so a call can be captured in a HIP graph after a reserve.
+ * Each call also counts its NaN results (RBFL_Q_NAN_COUNT). */
 int32_t rbfl_eval(rbfl_handle h, const double *params, int64_t n, double *lnl, int32_t form,
                   void *stream);
 
@@ -270,11 +271,18 @@ enum rbfl_query_what {
                                autotuner's median ms per evaluation at 1, 2, 4 and 8 chunks (0 = not
                                timed), 1/0 for ln L finished inside the contraction (rbfl_fuse_epilogue)
                                and the autotuner's ms per evaluation in that order (0 = not timed) */
-  RBFL_Q_SURROGATE_NET = 20 /* float[n_params + 2 K]: the surrogate's trained parameters (the layout
+  RBFL_Q_SURROGATE_NET = 20, /* float[n_params + 2 K]: the surrogate's trained parameters (the layout
                                of rbfl_mlp_get for n_in = 4, the width given to rbfl_surrogate_train,
                                n_out = K), then the per-column mean and standard deviation that map
                                its outputs to the interpolated quantities (out = mean + sd * y);
                                RBFL_E_STATE before rbfl_surrogate_train.  Synchronises the device. */
+  RBFL_Q_SPLIT_STATE = 21,  /* double[3]: 1/0 the split form's digit count was chosen by rbfl_autotune,
+                               1/0 that choice is within RBFL_SPLIT_TOL of the FP64 form (when no digit
+                               count is, the tuner keeps the most accurate one and reports 0 here:
+                               such a split form does not meet the tuner's bar), digits S in use */
+  RBFL_Q_NAN_COUNT = 22     /* int64[1]: NaN ln L values written by the last rbfl_eval call on this
+                               handle (a proposal with a NaN parameter gives NaN; any other NaN result
+                               is counted too).  Synchronises the device. */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
@@ -284,8 +292,9 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * reports the timings).  Split-form variants differ in digit count S (5..8,
  * variant v has S = 5 + v): only those whose ln L on these proposals stays
  * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
- * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible, or
- * without autotuning, the split form uses S = 7.  For RBFL_FORM_FP64 it then
+ * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible the
+ * most accurate variant is kept and RBFL_Q_SPLIT_STATE says that the bar was
+ * missed; without autotuning the split form uses S = 7.  For RBFL_FORM_FP64 it then
  * times whole evaluations of those proposals in each evaluation order (serial,
  * rbfl_pipeline with 2, 4 and 8 chunks, rbfl_fuse_epilogue) and keeps a
  * pipelined order only if it is at least 3% faster than the serial one, ln L
@@ -524,6 +533,28 @@ int32_t rbfl_sampler_destroy(rbfl_sampler s);
  * (sum w)^2 / sum w^2 there. */
 int32_t rbfl_prior_weights(rbfl_handle h, const double *params, int64_t ld, int64_t n, const double box[8],
                            double d_exp, double *logw, double *n_eff, void *stream);
+
+/* Start-up reuse (Sec. II D: the interpolants are built once in the start-up
+ * stage and then only evaluated while sampling).  rbfl_save writes every
+ * artefact of a built handle -- sizes, frame, the online stage's constants,
+ * nodes (unit-ball and physical), RBF weights, SVD basis and its
+ * spline-folded copy, singular values, node values and node series, output
+ * layout, and the exact likelihood's band data -- to `path` (a versioned file
+ * with a checksum; written to path + ".tmp" and renamed, so a failed save
+ * leaves no partial file at `path`).  Synchronises the device.  Reduced-
+ * precision weight copies, tile choices and a trained surrogate are not
+ * stored: a loaded handle starts with the FP64 form only (rbfl_prepare and
+ * rbfl_autotune again as needed).  RBFL_E_INVALID_ARG if the file cannot be
+ * written.
+ *
+ * rbfl_load creates a handle on the current device from such a file.  Its
+ * rbfl_eval, rbfl_interp, rbfl_brute, rbfl_exact_parts and rbfl_query results
+ * equal the saved handle's bit for bit.  RBFL_E_INVALID_ARG, with nothing
+ * allocated on the device, for a missing, truncated or damaged file (checksum),
+ * another format or ABI version, or sizes this library cannot have built;
+ * synchronous on `stream`. */
+int32_t rbfl_save(rbfl_handle h, const char *path);
+int32_t rbfl_load(const char *path, void *stream, rbfl_handle *out);
 
 /* Releases the handle and its device memory (NULL is allowed). */
 int32_t rbfl_destroy(rbfl_handle h);

@@ -509,6 +509,19 @@ __global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *_
 }
 
 // Surrogate inputs: x = delta_e / a in FP32, [nb][4].
+__global__ void __launch_bounds__(256) k_count_nan(const double *__restrict__ lnl, int64_t n,
+                                                   unsigned long long *__restrict__ part) {
+  __shared__ unsigned long long cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    mine += isnan(lnl[i]) ? 1ull : 0ull;
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = cnt;
+}
+
 __global__ void k_sur_inputs(const double *__restrict__ params, int64_t ld, int64_t b0, int64_t nb,
                              const EvalConsts *__restrict__ c, float *__restrict__ x) {
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -699,6 +712,11 @@ void launch_series_lnl(const EvalConsts *c, const double *params, int64_t ld, in
                        const double2 *Z, const double2 *sig, double *lnl, hipStream_t s) {
   hipLaunchKernelGGL(k_series_lnl, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, c, params,
                      ld, b0, nb, Z, sig, lnl);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_count_nan(const double *lnl, int64_t n, unsigned long long *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_nan, dim3(kNanParts), dim3(256), 0, s, lnl, n, part);
   RBFL_HIP(hipGetLastError());
 }
 

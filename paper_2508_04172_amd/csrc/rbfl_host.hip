@@ -24,7 +24,7 @@
 
 namespace rbfl {
 
-static thread_local std::string g_last_error;
+thread_local std::string g_last_error;
 
 void hip_check(hipError_t e, const char *what) {
   if (e != hipSuccess) {
@@ -39,10 +39,6 @@ static void blas_check(rocblas_status s, const char *what) {
   if (s != rocblas_status_success)
     throw Error(s == rocblas_status_memory_error ? RBFL_E_OUT_OF_MEMORY : RBFL_E_DEVICE,
                 std::string(what) + " failed with rocblas status " + std::to_string((int)s));
-}
-
-static void require(bool ok, const std::string &msg) {
-  if (!ok) throw Error(RBFL_E_INVALID_ARG, msg);
 }
 
 using Clock = std::chrono::steady_clock;
@@ -1079,6 +1075,7 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
 static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   const auto t_all = Clock::now();
   validate(s);
+  RBFL_HIP(hipGetDevice(&c.device));
   c.n_det = s->n_det;
   c.n_modes = s->n_modes;
   for (int a = 0; a < c.n_modes; ++a) {
@@ -1526,6 +1523,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   RBFL_HIP(hipMemcpyAsync(c.consts.p, &e, sizeof(e), hipMemcpyHostToDevice, stream));
   c.basis4.alloc((size_t)c.n_det * c.n_modes * c.T * c.q * 4);
   launch_fold_spline(c.basis.p, c.n_det * c.n_modes, c.T, c.q, c.consts.p, c.basis4.p, stream);
+  c.nan_part.alloc(kNanParts);
+  launch_count_nan(nullptr, 0, c.nan_part.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
   c.timing[5] = seconds_since(t_all);
 }
@@ -1777,6 +1776,7 @@ static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form,
   if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
   if (!c.prepared[form]) throw Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
   eval_range(c, params, n, n, lnl, form, s);
+  launch_count_nan(lnl, n, c.nan_part.p, s);
 }
 
 // The contraction of proposals [b0, b0 + nb) into the work space Y, in two
@@ -1934,7 +1934,18 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     for (int v = 0; v < gemm_fp64_variants() && v < nv && v < 8; ++v)
       if (med[v] <= 1.03 * best_ms && gemm_fp64_reuse(v) > gemm_fp64_reuse(best)) best = v;
   }
-  c.variant[form] = best >= 0 ? best : kSplitDefaultVariant;
+  if (best < 0) {
+    // no split variant within RBFL_SPLIT_TOL: keep the most accurate one
+    // (ties to more digits) and leave split_ok false for RBFL_Q_SPLIT_STATE
+    best = 0;
+    for (int v = 1; v < nv && v < 8; ++v)
+      if (c.split_err[v] <= c.split_err[best]) best = v;
+  }
+  if (form == RBFL_FORM_SPLIT) {
+    c.split_tuned = true;
+    c.split_ok = eligible[best];
+  }
+  c.variant[form] = best;
   // FP64: with the chosen tile, time whole evaluations of the nb proposals in
   // 1 (serial), 2, 4 and 8 pipelined chunks and keep the fastest
   if (form == RBFL_FORM_FP64 && c.cap / 2 >= 4096 && nb > 4096 && !capturing(s)) {
@@ -2225,6 +2236,22 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_SPLIT_ERR:
       copy_out(out, bytes, c.split_err, sizeof(c.split_err));
       return;
+    case RBFL_Q_SPLIT_STATE: {
+      double v[3] = {c.split_tuned ? 1.0 : 0.0, c.split_ok ? 1.0 : 0.0,
+                     (double)split_variant_slices(c.variant[RBFL_FORM_SPLIT])};
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
+    case RBFL_Q_NAN_COUNT: {
+      require(out != nullptr && bytes >= sizeof(int64_t), "output buffer too small (need 8 bytes)");
+      unsigned long long part[kNanParts];
+      RBFL_HIP(hipDeviceSynchronize());
+      RBFL_HIP(hipMemcpy(part, c.nan_part.p, sizeof(part), hipMemcpyDeviceToHost));
+      int64_t total = 0;
+      for (int i = 0; i < kNanParts; ++i) total += (int64_t)part[i];
+      std::memcpy(out, &total, sizeof(total));
+      return;
+    }
     case RBFL_Q_SURROGATE_NET: {
       if (!c.sur) throw Error(RBFL_E_STATE, "no surrogate trained on this handle");
       const size_t np = (size_t)c.sur->np, need = sizeof(float) * (np + 2 * (size_t)c.K);
@@ -2349,32 +2376,7 @@ static void plan_run(Plan &p, hipStream_t s) {
   launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
 }
 
-template <class F>
-static int32_t guarded(F &&f) {
-  try {
-    f();
-    g_last_error.clear();
-    return RBFL_OK;
-  } catch (const Error &e) {
-    g_last_error = e.what();
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    g_last_error = "host allocation failed";
-    return RBFL_E_OUT_OF_MEMORY;
-  } catch (const std::exception &e) {
-    g_last_error = e.what();
-    return RBFL_E_DEVICE;
-  } catch (...) {
-    g_last_error = "unknown failure";
-    return RBFL_E_DEVICE;
-  }
-}
-
 }  // namespace rbfl
-
-struct rbfl_ctx {
-  rbfl::Ctx c;
-};
 
 struct rbfl_plan_ctx {
   rbfl::Plan p;

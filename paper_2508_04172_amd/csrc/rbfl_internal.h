@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <new>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -26,6 +27,36 @@ struct Error : std::runtime_error {
 
 void hip_check(hipError_t e, const char *what);
 #define RBFL_HIP(x) ::rbfl::hip_check((x), #x)
+
+inline void require(bool ok, const std::string &msg) {
+  if (!ok) throw Error(RBFL_E_INVALID_ARG, msg);
+}
+
+// Thread-local text behind rbfl_last_error().
+extern thread_local std::string g_last_error;
+
+// Runs f and converts what it throws into an rbfl_status (no exception
+// crosses the C ABI).
+template <class F>
+int32_t guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return RBFL_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return RBFL_E_OUT_OF_MEMORY;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return RBFL_E_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return RBFL_E_DEVICE;
+  }
+}
 
 // Everything the online-stage kernels read, resident in device memory (one
 // copy per handle, read through a pointer so handles never share state).
@@ -107,7 +138,12 @@ struct Mlp {
   void adam(double lr, double b1, double b2, double eps, hipStream_t s);
 };
 
+// Partial counts of NaN ln L values of the last evaluation call (one per
+// block of the counting kernel, summed by rbfl_query).
+constexpr int kNanParts = 256;
+
 struct Ctx {
+  int device = 0;              // the device current at rbfl_build / rbfl_load; every artefact lives there
   // sizes and scalars
   int n_det = 0, n_modes = 0;
   int modes[RBFL_MAX_MODES][2] = {};
@@ -139,6 +175,7 @@ struct Ctx {
   int64_t brute_j_lo = 0, brute_J = 0;
   DevBuf<double2> win_D;       // exact outputs: brute_D with the window start's phase, made on first use
   DevBuf<int4> coldesc;        // output column layout (kind, detector, mode, index), [K]
+  DevBuf<unsigned long long> nan_part;   // [kNanParts] NaN counts of the last evaluation call
   // reduced-precision weight copies
   DevBuf<float> W32;           // [rows][Kp]
   DevBuf<uint16_t> W16;        // BF16 form: weights in 8-row groups [rows/8][Kp][8]
@@ -151,6 +188,8 @@ struct Ctx {
   int variant[5] = {0, 0, 0, 0, 0};   // contraction tile variant per form (rbfl_autotune)
   double tune_ms[5][8] = {};          // last autotune timings per variant
   double split_err[8] = {};           // last split autotune: max |d ln L| vs the FP64 form per variant
+  bool split_tuned = false;           // the split form's digit count was chosen by rbfl_autotune
+  bool split_ok = false;              // last split autotune found a variant within RBFL_SPLIT_TOL
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
@@ -289,6 +328,9 @@ void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                            int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
                            const double *scale, double *Y, hipStream_t s, int variant, hipEvent_t mid);
+// part[b] = number of NaN entries of lnl[0, n) in block b's grid-stride share
+// (kNanParts blocks; every slot is written, so no clearing is needed).
+void launch_count_nan(const double *lnl, int64_t n, unsigned long long *part, hipStream_t s);
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s);
 void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s);
@@ -296,3 +338,8 @@ void launch_standardise(const double *Y, int64_t n, int K, const float *mu, cons
 void launch_convert_weights(const double *W, size_t n, float *hi, uint16_t *b16, hipStream_t s);
 
 }  // namespace rbfl
+
+// The opaque handle of the C ABI.
+struct rbfl_ctx {
+  rbfl::Ctx c;
+};

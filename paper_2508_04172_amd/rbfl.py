@@ -27,7 +27,7 @@ FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
-    Q_PIPELINE, Q_SURROGATE_NET = range(21)
+    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT = range(23)
 SPLIT_TOL = 1e-4
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
@@ -37,7 +37,7 @@ EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "
             "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
             "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
-            "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_destroy")
+            "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_save", "rbfl_load", "rbfl_destroy")
 SAMPLER_PRIOR_ONLY = 0x1
 PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
 
@@ -214,6 +214,10 @@ def load(path: str = LIB_PATH):
     lib.rbfl_prior_weights.restype = C.c_int32
     lib.rbfl_prior_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                        C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+    lib.rbfl_save.restype = C.c_int32
+    lib.rbfl_save.argtypes = [C.c_void_p, C.c_char_p]
+    lib.rbfl_load.restype = C.c_int32
+    lib.rbfl_load.argtypes = [C.c_char_p, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.rbfl_destroy.restype = C.c_int32
     lib.rbfl_destroy.argtypes = [C.c_void_p]
     _lib = lib
@@ -295,6 +299,27 @@ class Handle:
         keep = []
         spec = spec_from_config(cfg, white, inj_ext, metric, keep)
         return cls.build(spec, stream)
+
+    @classmethod
+    def load(cls, path: str, stream: int = 0) -> "Handle":
+        """A handle restored from a file written by save() (rbfl_load)."""
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.rbfl_load(os.fsencode(path), C.c_void_p(stream), C.byref(h)))
+        return cls(h)
+
+    def save(self, path: str):
+        """Writes the handle's start-up artefacts to `path` (rbfl_save)."""
+        _check(load().rbfl_save(self._h, os.fsencode(path)))
+
+    def nan_count(self) -> int:
+        """NaN ln L values of the last rbfl_eval call (RBFL_Q_NAN_COUNT)."""
+        return int(self._query(Q_NAN_COUNT, 1, np.int64)[0])
+
+    def split_state(self) -> dict:
+        """Whether the split form's digit count was autotuned and met the tuner's bar (RBFL_Q_SPLIT_STATE)."""
+        v = self._query(Q_SPLIT_STATE, 3)
+        return {"tuned": bool(v[0]), "within_tol": bool(v[1]), "slices": int(v[2])}
 
     def close(self):
         if self._h is not None and self._h.value:

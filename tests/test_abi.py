@@ -49,3 +49,39 @@ def test_variant_counts_without_a_device():
     assert rbfl.load().rbfl_variants(rbfl.FORM_SURROGATE) < 0
     with pytest.raises(ValueError):
         rbfl.variants(rbfl.FORM_SURROGATE)
+
+
+def _store_file(sections, fmt=1, abi=rbfl.ABI_VERSION, magic=b"RBFLSTOR"):
+    """A store file with a valid checksum (FNV-1a over 8-byte words, the
+    layout rbfl_save writes) around the given raw sections."""
+    import struct
+    body = bytearray(magic + struct.pack("<IIQ", fmt, abi, len(sections)))
+    for tag, esize, payload in sections:
+        body += struct.pack("<IIQ", tag, esize, len(payload) // esize) + payload
+        body += bytes((8 - len(payload) % 8) % 8)
+    h = 0xcbf29ce484222325
+    for i in range(0, len(body), 8):
+        h = ((h ^ int.from_bytes(body[i:i + 8], "little")) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return bytes(body) + struct.pack("<Q", h)
+
+
+def test_load_refuses_bad_files_without_touching_the_device(tmp_path):
+    """rbfl_load checks a file completely before any device call: missing,
+    garbage, wrong-version and inconsistent files are RBFL_E_INVALID_ARG."""
+    lib = rbfl.load()
+    h = ctypes.c_void_p()
+    assert lib.rbfl_load(str(tmp_path / "missing").encode(), None, ctypes.byref(h)) == rbfl.E_INVALID_ARG
+    cases = {
+        "garbage": b"RBFLSTOR" + bytes(120),
+        "bad magic": _store_file([], magic=b"NOTRBFL!"),
+        "other format": _store_file([], fmt=2),
+        "other abi": _store_file([], abi=rbfl.ABI_VERSION + 1),
+        "no sections": _store_file([]),
+        "bad sizes": _store_file([(t, 8, bytes(8)) for t in range(1, 15)]),
+    }
+    for label, data in cases.items():
+        p = tmp_path / "f.rbfl"
+        p.write_bytes(data)
+        assert lib.rbfl_load(str(p).encode(), None, ctypes.byref(h)) == rbfl.E_INVALID_ARG, label
+        assert not h.value
+        assert b"rbfl store" in lib.rbfl_last_error() or label == "garbage", label

@@ -11,6 +11,7 @@ import time
 import numpy as np
 import pytest
 
+from full_size import handle
 from oracle import likelihood as lk
 from oracle import physics as ph
 from oracle import startup as su
@@ -28,16 +29,9 @@ def _torch():
 
 @pytest.fixture(scope="module")
 def cfg5():
-    cfg = wl.CFG5
-    white = wl.white_noise(cfg)
-    inj = wl.injection_extrinsics(cfg)
-    print("[cfg5] GPU start-up", flush=True)
-    t0 = time.time()
-    h = rbfl.Handle.from_config(cfg, white, inj)
-    print(f"[cfg5] start-up {time.time() - t0:.1f} s, stages {np.round(h.timing()[:6], 2)}, sizes {h.sizes()}, "
-          f"cond {h.cond():.2e}", flush=True)
+    cfg, h = handle("cfg5")          # shared with the eval-parity tier: one start-up per process
     print("[cfg5] oracle event", flush=True)
-    ev = su.make_event(cfg, white, inj)
+    ev = su.make_event(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
     return cfg, h, ev
 
 

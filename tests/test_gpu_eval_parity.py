@@ -1,0 +1,229 @@
+"""Eval parity: the oracle's online stage (Sec. II D: Eq. rbfcoeff, the
+reconstruction of Eq. SVD at the arrival time, Eq. logl_complete in the
+corrected reading) run on the library's own start-up artefacts -- nodes,
+frame, RBF weights, SVD basis, reference distance, exported through
+rbfl_query -- against the library's evaluation of the same proposals.  Both
+sides then contract the same W, so the 1e-6 bar on the interpolated
+coefficients holds without any allowance for two independent start-ups
+(the build-parity tier in test_gpu_parity.py compares those).
+
+Full sizes, in the launch configuration the benchmark times: 1e6 near-node
+proposals per launch for the 3-detector workload and the third-generation
+workload, 4e6 for the single-detector cubic-tail workload; the oracle checks
+a seeded sample of each launch.
+
+Bars: FP64 form -- every interpolated column within 1e-6 of its largest node
+value, max |d ln L| <= 1e-3, identical domain flags.  Split form -- max
+|d ln L| <= 1e-3 and each column within the split arithmetic's worst case
+(S + 3) 254^-S of the power-of-two scales per kernel row.  FP32 and BF16 --
+reported (their errors exceed 1e-3 here), domain flags and finiteness held.
+"""
+import numpy as np
+import pytest
+
+from full_size import handle
+from oracle import likelihood as lk
+from oracle import physics as ph
+from oracle import startup as su
+from paper_2508_04172_amd import rbfl
+from paper_2508_04172_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+LAUNCH = {"cfg2": 1_000_000, "cfg3": 4_000_000, "cfg5": 1_000_000}
+SAMPLE = 2000
+_cache = {}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def library_artefacts(h, cfg):
+    """Oracle artefacts whose every evaluation input is the library's export;
+    the detector geometry, layout and spline table are the oracle's own."""
+    fr = h.frame()
+    sz = h.sizes()
+    grid = ph.Grid(cfg.fs, cfg.seg_len, cfg.f_low, f_ref=h.f_ref())
+    geo = [ph.detector_geometry(s) for s in cfg.sites]
+    ev = su.Event(grid=grid, modes=tuple(cfg.modes), psd=None, data=None, det_tensor=[g[0] for g in geo],
+                  det_pos=[g[1] for g in geo], inj_phys=tuple(cfg.inj_phys),
+                  inj_ext=np.asarray(wl.injection_extrinsics(cfg)), t_trig=cfg.t_trig, d_inj=h.d_ref(),
+                  snr_opt=cfg.inj_snr)
+    frame = su.Frame(theta_c=fr["theta_c"], metric=fr["metric"], vecs=fr["vecs"], lam=fr["lam"], semi=fr["semi"])
+    return su.Artefacts(ev=ev, cfg=cfg, frame=frame, x_nodes=h.nodes(), phys_nodes=h.node_phys(), W=h.weights(),
+                        basis=h.basis(), half_w=sz["half_w"], eps=cfg.eps, degree=cfg.poly_degree, q=cfg.q,
+                        cond=h.cond(), discarded=None, singular=h.singular(), node_values=h.node_values(),
+                        z_nodes=None, sigma_nodes=None)
+
+
+def setup(name):
+    """The handle, oracle artefacts on its exports, the launch's proposals on
+    the device, the FP64 ln L of the whole launch and the sample's indices."""
+    if name not in _cache:
+        torch = _torch()
+        cfg, h = handle(name)
+        art = library_artefacts(h, cfg)
+        n = LAUNCH[name]
+        idx, jit = wl.node_jitter(n, cfg.n_nodes)
+        qd = wl.queries(cfg, n=n).near_nodes(h.nodes(), idx, jit)
+        params = np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))
+        p = torch.from_numpy(params).cuda()
+        lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+        sp = torch.cuda.current_stream().cuda_stream
+        h.reserve(65536)
+        h.eval(p.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_FP64, sp)
+        torch.cuda.synchronize()
+        sample = np.sort(np.random.default_rng(4242).choice(n, SAMPLE, replace=False))
+        _cache[name] = (cfg, h, art, p, params, lnl.cpu().numpy(), sample)
+    return _cache[name]
+
+
+def oracle_lnl(art, params):
+    return lk.meshfree_lnl(art, params[0:4].T.copy(), params[4:9].T.copy(), params[9].copy(), params[10].copy())
+
+
+def interp(h, params, form):
+    torch = _torch()
+    p = torch.from_numpy(np.ascontiguousarray(params)).cuda()
+    n = params.shape[1]
+    out = torch.empty((n, h.sizes()["K"]), dtype=torch.float64, device="cuda")
+    h.interp(p.data_ptr(), n, out.data_ptr(), form, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def column_scale(h):
+    """Largest node value per column, floored at 1e-9 of the largest column
+    (columns that vanish in exact arithmetic hold rounding noise)."""
+    s = np.abs(h.node_values()).max(axis=0)
+    return np.maximum(s, 1e-9 * s.max())
+
+
+def coefficient_sample(cfg, h, params, sample):
+    """The launch's sampled proposals plus as many uniform in the ball."""
+    qd = wl.queries(cfg, n=SAMPLE, seed=611)
+    return np.concatenate([params[:, sample], rbfl.params_soa(h, qd, cfg.t_trig)], axis=1)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name", list(LAUNCH))
+def test_fp64_coefficients_within_1e6(name):
+    cfg, h, art, _, params, _, sample = setup(name)
+    P = coefficient_sample(cfg, h, params, sample)
+    Yg = interp(h, P, rbfl.FORM_FP64)
+    x = P[0:4].T / art.frame.semi[None, :]
+    Yo = lk.rbf_eval(art, x)
+    col = column_scale(h)
+    err = np.abs(Yg - Yo).max(axis=0) / col
+    basis = np.concatenate([su.gaussian_kernel(x, art.x_nodes, art.eps), su.poly_matrix(x, art.degree)], 1)
+    amp = (np.abs(basis) @ np.abs(art.W)).max(axis=0) / col
+    print(f"[eval-parity] {name} FP64 coefficients: max column-relative error {err.max():.3e} "
+          f"(p99 over columns {np.quantile(err, 0.99):.3e}), cancellation factor up to {amp.max():.2e}", flush=True)
+    assert np.all(err <= 1e-6), f"column {int(err.argmax())}: {err.max():.3e}"
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name", list(LAUNCH))
+def test_fp64_lnl_full_launch(name):
+    cfg, h, art, _, params, lg, sample = setup(name)
+    lo = oracle_lnl(art, params[:, sample])
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg[sample])), "domain flags differ"
+    assert fin.sum() >= SAMPLE // 4
+    d = np.abs(lg[sample][fin] - lo[fin])
+    print(f"[eval-parity] {name} FP64 ln L on {SAMPLE} of {LAUNCH[name]} proposals: {fin.sum()} valid, "
+          f"max |dlnL| {d.max():.3e}, median {np.median(d):.3e}, |lnL| up to {np.abs(lo[fin]).max():.3e}",
+          flush=True)
+    assert d.max() <= 1e-3
+    # uniform in the ball too (mostly outside the physical region: domain flags)
+    qd = wl.queries(cfg, n=SAMPLE, seed=612)
+    pu = np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))
+    torch = _torch()
+    p = torch.from_numpy(pu).cuda()
+    out = torch.empty(SAMPLE, dtype=torch.float64, device="cuda")
+    h.eval(p.data_ptr(), SAMPLE, out.data_ptr(), rbfl.FORM_FP64, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    lu = out.cpu().numpy()
+    lo = oracle_lnl(art, pu)
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lu))
+    if fin.any():
+        assert np.abs(lu[fin] - lo[fin]).max() <= 1e-3
+
+
+def split_bound(art, h, x, S):
+    """Worst case of the split arithmetic per column and proposal set: (S + 3)
+    254^-S s_q s_c per kernel row, with the kernels' power-of-two scales
+    (2^e > the bound, e from frexp): s_q from max(1, |monomials|) of the row,
+    s_c from max_r |W_rc| (1 for an all-zero column)."""
+    basis = np.concatenate([su.gaussian_kernel(x, art.x_nodes, art.eps), su.poly_matrix(x, art.degree)], 1)
+    poly = su.poly_matrix(x, art.degree)
+    _, eq = np.frexp(np.maximum(1.0, np.abs(poly).max(axis=1)))
+    s_q = np.ldexp(1.0, eq)
+    wmax = np.abs(art.W).max(axis=0)
+    _, ec = np.frexp(wmax)
+    s_c = np.where(wmax > 0, np.ldexp(1.0, ec), 1.0)
+    return (S + 3) * 254.0 ** (-S) * basis.shape[1] * s_q.max() * s_c
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name", list(LAUNCH))
+def test_split_form_full_launch(name):
+    cfg, h, art, p, params, _, sample = setup(name)
+    torch = _torch()
+    sp = torch.cuda.current_stream().cuda_stream
+    h.prepare(rbfl.FORM_SPLIT)
+    tune = h.autotune(p.data_ptr(), LAUNCH[name], rbfl.FORM_SPLIT, sp)
+    state = h.split_state()
+    S = tune["slices"]
+    assert state["tuned"] and state["slices"] == S
+    n = LAUNCH[name]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.eval(p.data_ptr(), n, out.data_ptr(), rbfl.FORM_SPLIT, sp)
+    torch.cuda.synchronize()
+    ls = out.cpu().numpy()
+    lo = oracle_lnl(art, params[:, sample])
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(ls[sample]))
+    d = np.abs(ls[sample][fin] - lo[fin])
+    print(f"[eval-parity] {name} split S = {S} (within the tuner's 1e-4: {state['within_tol']}): "
+          f"max |dlnL| {d.max():.3e}, median {np.median(d):.3e}", flush=True)
+    assert d.max() <= 1e-3
+    P = coefficient_sample(cfg, h, params, sample)
+    x = P[0:4].T / art.frame.semi[None, :]
+    Ys = interp(h, P, rbfl.FORM_SPLIT)
+    Yo = lk.rbf_eval(art, x)
+    col = column_scale(h)
+    err = np.abs(Ys - Yo).max(axis=0)
+    bound = split_bound(art, h, x, S)
+    print(f"[eval-parity] {name} split coefficients: max column-relative error {(err / col).max():.3e}, "
+          f"largest fraction of the worst-case bound {(err / bound).max():.3e}", flush=True)
+    # the bound plus FP64 rounding of the level sums (1e-12 of the column scale)
+    assert np.all(err <= bound + 1e-12 * col)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("form_name,form", [("fp32", rbfl.FORM_FP32), ("bf16", rbfl.FORM_BF16)])
+def test_reduced_forms_cubic_tail_reported(form_name, form):
+    """FP32 and BF16 at the cubic-tail workload's shape (N = 1500, M = 35,
+    q = 60): their error distribution against the oracle on the same
+    artefacts is reported; domain flags and finiteness are held."""
+    cfg, h, art, p, params, _, sample = setup("cfg3")
+    torch = _torch()
+    h.prepare(form)
+    n = LAUNCH["cfg3"]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.eval(p.data_ptr(), n, out.data_ptr(), form, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    lr = out.cpu().numpy()[sample]
+    lo = oracle_lnl(art, params[:, sample])
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isinf(lr) == False)  # noqa: E712
+    assert not np.isnan(lr).any()
+    d = np.abs(lr[fin] - lo[fin])
+    q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    print(f"[eval-parity] cfg3 {form_name}: |dlnL| median {q[0]:.3e}, 90% {q[1]:.3e}, 99% {q[2]:.3e}, "
+          f"max {q[3]:.3e} (meets 1e-3: {q[3] <= 1e-3})", flush=True)
