@@ -84,20 +84,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--check-sample", type=int, default=2000)
-    ap.add_argument("--ragged-events", type=int, default=16,
+    ap.add_argument("--ragged-events", type=int, default=64,
                     help="events in the multi-event batch form (0 = skip)")
     ap.add_argument("--surrogate-train", type=int, default=200000,
                     help="training proposals for the surrogate form (0 = skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
-    ap.add_argument("--third-generation-surrogate", type=int, default=100000,
+    ap.add_argument("--third-generation-surrogate", type=int, default=200000,
                     help="training proposals for the surrogate on the third-generation workload (0 = skip)")
-    ap.add_argument("--third-generation", action="store_true",
-                    help="also report the FP64 form on the third-generation workload (2048 s at 4096 Hz, "
-                         "N=3000, K=2475, 1e6 proposals per pass; its oracle checks samples in "
-                         "tests/test_gpu_cfg5.py, not here)")
-    ap.add_argument("--mixed-cfg3", action="store_true",
-                    help="also report every arithmetic form on the 10 Hz single-detector cubic-tail workload "
-                         "(N=1500, M=35, q=60, 4e6 proposals), errors against its oracle")
+    ap.add_argument("--no-third-generation", action="store_true",
+                    help="skip the FP64 and surrogate forms on the third-generation workload (2048 s at 4096 Hz, "
+                         "N=3000, K=2475, 1e6 proposals per pass)")
+    ap.add_argument("--no-mixed-cfg3", action="store_true",
+                    help="skip every arithmetic form on the 10 Hz single-detector cubic-tail workload "
+                         "(N=1500, M=35, q=60, 4e6 proposals)")
     ap.add_argument("--method-error", action="store_true",
                     help="also report the method's error against the exact ln L (rbfl_brute) at matches "
                          "0.90/0.95/0.97/0.99 on the single-detector workload (1e4 proposals each) and on "
@@ -286,11 +285,27 @@ def main():
         t = time.perf_counter()
         lo = lk.meshfree_lnl(art, *args_cpu)
         cpu_s = time.perf_counter() - t
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = "; ".join(f"{i.get('internal_api')} {i.get('version')} ({os.path.basename(i.get('filepath', ''))}, "
+                         f"{i.get('num_threads')} threads)" for i in info if i.get("user_api") == "blas")
+        # one thread: a smaller seeded part of the same sample (same per-proposal work)
+        m1 = min(m, max(2000, m // 10))
+        from threadpoolctl import threadpool_limits
+        sub1 = qd.subset(sample[:m1]).near_nodes(art.x_nodes, idx[sample[:m1]], jit[sample[:m1]])
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            lk.meshfree_lnl(art, *lk.query_params(art, sub1))
+            cpu1_s = time.perf_counter() - t
         result["cpu_baseline"] = {"value": m / cpu_s, "unit": "evals/s", "cores": int(threads),
                                   "kind": "oracle",
                                   "sample": f"{m} of the {n} proposals (seeded), FP64 numpy/BLAS, "
-                                            f"{cpu_s:.1f} s; host os.cpu_count()={os.cpu_count()}"}
+                                            f"{cpu_s:.1f} s; host os.cpu_count()={os.cpu_count()}",
+                                  "single_thread_value": m1 / cpu1_s,
+                                  "single_thread_sample": f"the first {m1} of that sample, {cpu1_s:.1f} s, BLAS "
+                                                          "limited to 1 thread",
+                                  "blas": blas}
+        log(f"oracle: {m / cpu_s:.4e} evals/s on {threads} threads, {m1 / cpu1_s:.4e} on one ({blas})")
         fin = np.isfinite(lo)
         for name, l in outs.items():
             lg = l[sample]
@@ -304,9 +319,9 @@ def main():
         result["sampler"] = bench_sampler(args, np, torch, rbfl, wl, cfg)
     if args.method_error:
         result["method_error"] = bench_method_error(np, torch, rbfl, wl, h, cfg, qd, idx, jit)
-    if args.third_generation:
+    if not args.no_third_generation:
         result["third_generation"] = bench_third_generation(args, np, torch, rbfl, wl)
-    if args.mixed_cfg3:
+    if not args.no_mixed_cfg3:
         result["mixed_cfg3"] = bench_mixed(args, np, torch, rbfl, wl, wl.CFG3)
     print(json.dumps(result), flush=True)
 
@@ -563,17 +578,37 @@ def bench_third_generation(args, np, torch, rbfl, wl):
            "roofline": roof(tflops * 1e12, PEAK_FP64, kernel="k_gemm_lnl_fp64" if order["fused_epilogue"]
                             else "k_gemm_fp64")}
     log(f"third generation: {n / wall:.4e} evals/s, contraction {c_ms:.2f} ms ({tflops:.2f} TFLOP/s)")
+    l64 = lnl.cpu().numpy()
+    if not args.no_cpu_baseline:
+        from oracle import likelihood as lk
+        from oracle import startup as su
+        art = su.artefacts_from_exports(cfg, wl.injection_extrinsics(cfg), **h.exports())
+        m = 2000
+        sample = np.sort(np.random.default_rng(321).choice(n, m, replace=False))
+        pe = params[:, sample].cpu().numpy()
+        lo = lk.meshfree_lnl(art, pe[0:4].T.copy(), pe[4:9].T.copy(), pe[9].copy(), pe[10].copy())
+        fin = np.isfinite(lo)
+        agree = bool(np.array_equal(fin, np.isfinite(l64[sample])))
+        d = np.abs(l64[sample][fin] - lo[fin])
+        out.update({"max_dlnl": float(d.max()), "median_dlnl": float(np.median(d)), "domain_agrees": agree,
+                    "meets_1e-3": bool(agree and d.max() <= 1e-3),
+                    "check_sample": f"{m} seeded proposals of the pass; oracle online stage on the handle's "
+                                    "exported artefacts"})
+        log(f"third generation: max |dlnL| vs oracle {d.max():.3e}")
     if args.third_generation_surrogate > 0:
-        out["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, lnl.cpu().numpy(),
+        out["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64,
                                            args.third_generation_surrogate, 10, reps)
     h.close()
     return out
 
 
 def bench_mixed(args, np, torch, rbfl, wl, cfg):
-    """Every arithmetic form on one more workload: throughput of a pass over
-    the workload's proposals (near the nodes) and max |d ln L| against the
-    FP64 oracle on a seeded sample of them."""
+    """Every arithmetic form on the single-detector cubic-tail workload
+    (N = 1500, M = 35, q = 60, the precision-split configuration): throughput
+    of a pass over its 4e6 proposals (near the nodes), each form's contraction
+    against its own peak (HIP events on the launch stream), and max |d ln L|
+    against the oracle's online stage run on the handle's exported artefacts
+    for a seeded sample of the pass."""
     n = cfg.n_queries
     log(f"mixed {cfg.name}: GPU start-up")
     t0 = time.time()
@@ -582,13 +617,14 @@ def bench_mixed(args, np, torch, rbfl, wl, cfg):
     sz = h.sizes()
     idx, jit = wl.node_jitter(n, cfg.n_nodes)
     qd = wl.queries(cfg, n=n)
-    params = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit),
-                                                                   cfg.t_trig))).cuda()
+    host = np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit), cfg.t_trig))
+    params = torch.from_numpy(host).cuda()
     lnl = torch.empty(n, dtype=torch.float64, device="cuda")
     sp = torch.cuda.current_stream().cuda_stream
     h.reserve(65536)
-    flop = 2.0 * (sz["N"] + sz["M"]) * sz["K"]
-    out = {"workload": cfg.name, "proposals": n, "N": sz["N"], "M": sz["M"], "K": sz["K"], "q": sz["q"],
+    NM, K = sz["N"] + sz["M"], sz["K"]
+    flop = 2.0 * NM * K
+    out = {"workload": cfg.name, "proposals": n, "N": sz["N"], "M": sz["M"], "K": K, "q": sz["q"],
            "startup_s": round(build_s, 3), "cond": h.cond(), "forms": {}}
     res = {}
     for name, form in (("fp64", rbfl.FORM_FP64), ("split", rbfl.FORM_SPLIT), ("fp32", rbfl.FORM_FP32),
@@ -599,32 +635,47 @@ def bench_mixed(args, np, torch, rbfl, wl, cfg):
         h.eval(params.data_ptr(), n, lnl.data_ptr(), form, sp)
         torch.cuda.synchronize()
         reps = 3
+        h.profile(True)
         t = time.perf_counter()
         for _ in range(reps):
             h.eval(params.data_ptr(), n, lnl.data_ptr(), form, sp)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / reps
+        h.profile(False)
+        ks = h.kernel_stats()
         res[name] = lnl.cpu().numpy()
-        f = {"evals_per_s": n / wall, "ms_per_pass": wall * 1e3, "contract_tflops_equiv": flop * n / wall / 1e12}
-        if form == rbfl.FORM_SPLIT:
-            f["slices"] = tune["slices"]
-            f["max_dlnl_vs_fp64_per_slice_count"] = tune["max_dlnl_vs_fp64"][:4]
+        c_ms = ks["contract_ms"] / max(1, ks["contract_launches"])
+        per = ks["contract_n"] / max(1, ks["contract_launches"])
+        f = {"evals_per_s": n / wall, "ms_per_pass": wall * 1e3, "contract_ms_per_launch": c_ms,
+             "contract_tflops_equiv": flop * per / (c_ms * 1e-3) / 1e12 if c_ms > 0 else None}
         if form == rbfl.FORM_FP64:
             f["order"] = h.pipeline()
-            log(f"mixed {cfg.name} fp64 order: {f['order']}")
+            fused = f["order"]["fused_epilogue"]
+            f["roofline"] = roof(flop * per / (c_ms * 1e-3), PEAK_FP64,
+                                 kernel="k_gemm_lnl_fp64 (ln L inside the contraction)" if fused else "k_gemm_fp64")
+        elif form == rbfl.FORM_SPLIT:
+            S = tune["slices"]
+            f["slices"] = S
+            f["split_state"] = h.split_state()
+            f["max_dlnl_vs_fp64_per_slice_count"] = tune["max_dlnl_vs_fp64"][:4]
+            f["roofline"] = roof(S * (S + 1) / 2 * flop * per / (c_ms * 1e-3), PEAK_INT8, unit="TOP/s",
+                                 kernel="k_split_contract (int8 products issued)")
+        elif form == rbfl.FORM_FP32:
+            f["roofline"] = roof(flop * per / (c_ms * 1e-3), PEAK_FP32, kernel="k_contract_fp32")
+        else:
+            f["roofline"] = roof(flop * per / (c_ms * 1e-3), PEAK_BF16, kernel="k_bf16_contract")
         out["forms"][name] = f
-        log(f"mixed {cfg.name} {name}: {n / wall:.4e} evals/s")
+        log(f"mixed {cfg.name} {name}: {n / wall:.4e} evals/s, contraction {c_ms:.3f} ms/launch")
     if not args.no_cpu_baseline:
         from oracle import likelihood as lk
         from oracle import startup as su
-        log(f"mixed {cfg.name}: oracle start-up on the host (not timed)")
-        art = su.startup(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+        art = su.artefacts_from_exports(cfg, wl.injection_extrinsics(cfg), **h.exports())
         m = min(20000, n)
         sample = np.sort(np.random.default_rng(321).choice(n, m, replace=False))
-        lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.subset(sample).near_nodes(art.x_nodes, idx[sample],
-                                                                                     jit[sample])))
+        pe = host[:, sample]
+        lo = lk.meshfree_lnl(art, pe[0:4].T.copy(), pe[4:9].T.copy(), pe[9].copy(), pe[10].copy())
         fin = np.isfinite(lo)
-        out["check_sample"] = m
+        out["check_sample"] = f"{m} seeded proposals of the pass; oracle online stage on the handle's exported artefacts"
         out["valid_fraction"] = float(fin.mean())
         for name, l in res.items():
             lg = l[sample]
@@ -634,19 +685,26 @@ def bench_mixed(args, np, torch, rbfl, wl, cfg):
                                        "median_dlnl": float(np.median(d)), "domain_agrees": agree,
                                        "meets_1e-3": bool(agree and d.max() <= 1e-3)})
             log(f"mixed {cfg.name} {name}: max |dlnL| {d.max():.3e}")
+    h.close()
     return out
 
 
 def bench_ragged(args, np, torch, rbfl, wl):
     """Multi-event form: seeded events (durations log-uniform in 8-512 s,
     200-1500 nodes, q 20-60, 1-5 modes, 3 detectors), 1024 walkers each, one
-    captured plan launch per sampler step, against one rbfl_eval per event."""
+    captured plan launch per sampler step, in the FP64 form and in the split
+    form (digit counts tuned per event), against one rbfl_eval per event; the
+    oracle's online stage on each event's exported artefacts checks a seeded
+    sample of every event's proposals."""
     evs = wl.ragged_events(args.ragged_events)
     walkers = 1024
     log(f"ragged: building {len(evs)} events")
     t0 = time.time()
     hs = [rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg)) for cfg in evs]
     build_s = time.time() - t0
+    stages = np.sum([h.timing()[:6] for h in hs], axis=0)
+    log(f"ragged: start-up {build_s:.1f} s; summed stages (data, frame, series, SVD, RBF solve, total) "
+        f"{np.round(stages, 1).tolist()}")
     cols = []
     for cfg, h in zip(evs, hs):
         idx, jit = wl.node_jitter(walkers, cfg.n_nodes, seed=cfg.query_seed)
@@ -655,20 +713,47 @@ def bench_ragged(args, np, torch, rbfl, wl):
     params = np.ascontiguousarray(np.concatenate(cols, axis=1))
     total = params.shape[1]
     p = torch.from_numpy(params).cuda()
-    out = torch.empty(total, dtype=torch.float64, device="cuda")
     sp = torch.cuda.current_stream().cuda_stream
-    plan = rbfl.Plan(hs, [walkers] * len(hs), p.data_ptr(), out.data_ptr(),
-                     rbfl.PLAN_GRAPH | rbfl.PLAN_AUTOTUNE, sp)
-    for _ in range(2):
-        plan.launch(sp)
-    torch.cuda.synchronize()
+    flops = sum(2.0 * (h.sizes()["N"] + h.sizes()["M"]) * h.sizes()["K"] * walkers for h in hs)
     steps = max(5, args.steps)
-    t = time.perf_counter()
-    for _ in range(steps):
-        plan.launch(sp)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t
-    lr = out.cpu().numpy()
+
+    def timed(plan):
+        for _ in range(2):
+            plan.launch(sp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            plan.launch(sp)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    res = {"events": len(hs), "walkers_per_event": walkers, "startup_s": round(build_s, 2),
+           "startup_stage_s": {k: round(float(v), 2) for k, v in
+                               zip(("data", "frame_nodes", "series", "svd", "rbf_solve", "total"), stages)}}
+    out = {}
+    for form, flags in (("fp64", rbfl.PLAN_GRAPH | rbfl.PLAN_AUTOTUNE),
+                        ("split", rbfl.PLAN_GRAPH | rbfl.PLAN_AUTOTUNE | rbfl.PLAN_SPLIT)):
+        o = torch.empty(total, dtype=torch.float64, device="cuda")
+        log(f"ragged {form}: plan (tuning)")
+        plan = rbfl.Plan(hs, [walkers] * len(hs), p.data_ptr(), o.data_ptr(), flags, sp)
+        wall = timed(plan)
+        info = plan.info()
+        plan.close()
+        out[form] = o.cpu().numpy()
+        r = {"evals_per_s": total / wall, "ms_per_step": wall * 1e3, "plan": info,
+             "contract_tflops_equiv_incl_epilogue": flops / wall / 1e12}
+        if form == "fp64":
+            r["roofline"] = roof(flops / wall, PEAK_FP64,
+                                 kernel="k_ragged_rows_fp64 + k_ragged_gemm_fp64 + k_ragged_epilogue (whole plan launch)")
+        res[form] = r
+        log(f"ragged {form}: {total / wall:.4e} evals/s, {info}")
+    # int8 products of the split plan at the chosen digit counts: per event S(S+1)/2 digit pairs
+    # (the tuner's choice is reported as the range; the products are counted at the largest S)
+    smax = res["split"]["plan"].get("slices_max", 7)
+    ops = sum(smax * (smax + 1) / 2 * 2.0 * (h.sizes()["N"] + h.sizes()["M"]) * h.sizes()["K"] * walkers for h in hs)
+    res["split"]["roofline"] = roof(ops / (res["split"]["ms_per_step"] * 1e-3), PEAK_INT8, unit="TOP/s",
+                                    kernel="k_ragged_split_rows + k_ragged_split_contract + k_ragged_epilogue "
+                                           "(whole plan launch; int8 products at the largest digit count)")
     # the same work as one rbfl_eval per event
     sub = [p[:, i * walkers:(i + 1) * walkers].contiguous() for i in range(len(hs))]
     outs = [torch.empty(walkers, dtype=torch.float64, device="cuda") for _ in hs]
@@ -680,22 +765,42 @@ def bench_ragged(args, np, torch, rbfl, wl):
         for h, q, o in zip(hs, sub, outs):
             h.eval(q.data_ptr(), walkers, o.data_ptr(), rbfl.FORM_FP64, sp)
     torch.cuda.synchronize()
-    wall_loop = time.perf_counter() - t
+    wall_loop = (time.perf_counter() - t) / steps
     le = torch.cat(outs).cpu().numpy()
     fin = np.isfinite(le)
-    agree = bool(np.array_equal(fin, np.isfinite(lr)))
-    dmax = float(np.abs(lr[fin] - le[fin]).max()) if fin.any() else 0.0
-    flops = sum(2.0 * (h.sizes()["N"] + h.sizes()["M"]) * h.sizes()["K"] * walkers for h in hs)
-    res = {"evals_per_s": total * steps / wall, "ms_per_step": wall / steps * 1e3, "events": len(hs),
-           "walkers_per_event": walkers, "per_event_loop_evals_per_s": total * steps / wall_loop,
-           "contract_tflops_incl_epilogue": flops * steps / wall / 1e12, "startup_s": round(build_s, 2),
-           "plan": plan.info(), "max_abs_diff_vs_per_event": dmax, "domain_agrees": agree,
-           "valid_fraction": float(fin.mean()),
-           "roofline": roof(flops * steps / wall, PEAK_FP64,
-                            kernel="k_ragged_contract_fp64 + k_ragged_epilogue (whole plan launch)")}
-    log(f"ragged: {res['evals_per_s']:.4e} evals/s (graph plan) vs {res['per_event_loop_evals_per_s']:.4e} "
-        f"(per-event loop); start-up {build_s:.1f} s")
-    plan.close()
+    res["per_event_loop_evals_per_s"] = total / wall_loop
+    res["valid_fraction"] = float(fin.mean())
+    for form in ("fp64", "split"):
+        lr = out[form]
+        agree = bool(np.array_equal(fin, np.isfinite(lr)))
+        res[form]["domain_agrees_with_per_event"] = agree
+        res[form]["max_abs_diff_vs_per_event_fp64"] = float(np.abs(lr[fin] - le[fin]).max()) if fin.any() else 0.0
+    if not args.no_cpu_baseline:
+        from oracle import likelihood as lk
+        from oracle import startup as su
+        per = 64
+        rng = np.random.default_rng(77)
+        worst = {"fp64": 0.0, "split": 0.0}
+        agree = {"fp64": True, "split": True}
+        for e, (cfg, h) in enumerate(zip(evs, hs)):
+            art = su.artefacts_from_exports(cfg, wl.injection_extrinsics(cfg), **h.exports())
+            idx = e * walkers + np.sort(rng.choice(walkers, per, replace=False))
+            pe = params[:, idx]
+            lo = lk.meshfree_lnl(art, pe[0:4].T.copy(), pe[4:9].T.copy(), pe[9].copy(), pe[10].copy())
+            f = np.isfinite(lo)
+            for form in ("fp64", "split"):
+                lg = out[form][idx]
+                agree[form] &= bool(np.array_equal(f, np.isfinite(lg)))
+                if f.any():
+                    worst[form] = max(worst[form], float(np.abs(lg[f] - lo[f]).max()))
+        for form in ("fp64", "split"):
+            res[form].update({"max_dlnl": worst[form], "domain_agrees": agree[form],
+                              "meets_1e-3": bool(agree[form] and worst[form] <= 1e-3)})
+        res["check_sample"] = f"{per} seeded proposals per event ({per * len(hs)} in all), oracle online stage on " \
+                              "each event's exported artefacts"
+        log(f"ragged: max |dlnL| vs oracle fp64 {worst['fp64']:.3e}, split {worst['split']:.3e}")
+    for h in hs:
+        h.close()
     return res
 
 

@@ -379,13 +379,32 @@ int32_t rbfl_profile(rbfl_handle h, int32_t on);
  */
 #define RBFL_PLAN_GRAPH 0x1u
 #define RBFL_PLAN_AUTOTUNE 0x2u
+#define RBFL_PLAN_SPLIT 0x4u      /* contraction in the split form (RBFL_FORM_SPLIT's arithmetic): each
+                                     event's weight digits are prepared if needed (rbfl_prepare); one
+                                     launch writes the S digits of every event's kernel rows, then one
+                                     persistent int8 contraction per digit count S in use takes the
+                                     (event, 128 proposals, 64 columns) items of its events.  With
+                                     RBFL_PLAN_AUTOTUNE the batch runs at S = 5, 6, 7, 8 against the FP64
+                                     plan; an event with at least 256 in-domain proposals takes the fewest
+                                     digits whose ln L stays within RBFL_SPLIT_TOL / 10 of it, any other
+                                     event 7 digits (8 if 7 misses RBFL_SPLIT_TOL; the most accurate count
+                                     when none meets it); without it each event uses its handle's split
+                                     variant (default 7) */
 typedef struct rbfl_plan_ctx *rbfl_plan;
 int32_t rbfl_plan_create(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
                          double *lnl, uint32_t flags, void *stream, rbfl_plan *out);
 int32_t rbfl_plan_launch(rbfl_plan plan, void *stream);
-/* out double[12]: tile variant, work items, persistent grid size, proposals, then the
- * autotuner's median time [ms] of each variant (0 = not timed). */
+/* out double[16] (at least 12): tile variant (-1 for the split form), work items, persistent grid
+ * size, proposals, then the autotuner's median time [ms] of each tile variant (split form: of the
+ * whole batch at S = 5 .. 8; 0 = not timed), then 1/0 split form, the smallest and largest digit
+ * count of its events, and 1/0 every event within RBFL_SPLIT_TOL of the FP64 plan (-1 when the
+ * digit counts were not tuned). */
 int32_t rbfl_plan_query(rbfl_plan plan, double *out, size_t bytes);
+/* Pins the FP64 tile variant of a plan (0 .. 5: variants 0-2 fused rows, 3-4 rows + 64 x 128 GEMM
+ * tiles of 4 waves, 5 rows + 128 x 128 tiles of 8 waves) instead of the autotuner's choice,
+ * re-capturing its graph if it has one; synchronises `stream` first.  RBFL_E_STATE for a split-form
+ * plan, RBFL_E_INVALID_ARG for a variant out of range. */
+int32_t rbfl_plan_set_variant(rbfl_plan plan, int32_t variant, void *stream);
 int32_t rbfl_plan_destroy(rbfl_plan plan);
 /* One-shot multi-event evaluation (creates a plan without graph or autotune,
  * runs it and synchronises `stream`). */

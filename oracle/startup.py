@@ -527,6 +527,27 @@ class Artefacts:
         return self.ev.d_inj
 
 
+def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_nodes, phys_nodes, W, basis,
+                           half_w, d_ref, f_ref, cond=float("nan"), singular=None, node_values=None) -> Artefacts:
+    """Artefacts whose evaluation inputs are given arrays (another start-up's
+    frame, nodes, RBF weights, SVD basis, reference distance and frequency),
+    so that the online stage here (meshfree_lnl, rbf_eval) evaluates exactly
+    those; the detector geometry, output layout and spline table are this
+    package's own.  No data or PSD is attached: the exact likelihoods need
+    make_event."""
+    grid = ph.Grid(cfg.fs, cfg.seg_len, cfg.f_low, f_ref=f_ref)
+    geo = [ph.detector_geometry(s) for s in cfg.sites]
+    ev = Event(grid=grid, modes=tuple(cfg.modes), psd=None, data=None, det_tensor=[g[0] for g in geo],
+               det_pos=[g[1] for g in geo], inj_phys=tuple(cfg.inj_phys), inj_ext=np.asarray(inj_ext, dtype=np.float64),
+               t_trig=cfg.t_trig, d_inj=d_ref, snr_opt=cfg.inj_snr)
+    fr = Frame(theta_c=np.asarray(theta_c), metric=np.asarray(metric_g), vecs=np.asarray(vecs), lam=np.asarray(lam),
+               semi=np.asarray(semi))
+    return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=np.asarray(x_nodes), phys_nodes=np.asarray(phys_nodes),
+                     W=np.asarray(W), basis=np.asarray(basis), half_w=int(half_w), eps=cfg.eps,
+                     degree=cfg.poly_degree, q=cfg.q, cond=cond, discarded=None, singular=singular,
+                     node_values=node_values, z_nodes=None, sigma_nodes=None)
+
+
 def output_layout(n_det: int, n_modes: int, q: int):
     """Column offsets of the K interpolated reals: per detector, 2q per mode
     (Re, Im of each SVD coefficient, interleaved) then n^2 overlap reals

@@ -404,8 +404,8 @@ __global__ void __launch_bounds__(256) k_ragged_rows_fp64(const EventDesc *__res
 // proposal tile, column tile), column tile fastest within an event, events in
 // the caller's cost order; each workgroup takes the next item from an atomic
 // counter until the list is exhausted (every workgroup reaches that exit).
-template <int RT, int CT, int KC>
-__global__ void __launch_bounds__(kGemmThreads, 2)
+template <int RT, int CT, int KC, int WQ = 2, int WC = 2>
+__global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
     k_ragged_gemm_fp64(const EventDesc *__restrict__ ev, int n_ev, int64_t total_items,
                        unsigned long long *__restrict__ counter) {
   __shared__ long long item_s;
@@ -419,7 +419,8 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
     while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
     const EventDesc &d = ev[e];
     const int64_t local = item - d.item0;
-    gemm_tile<RT, CT, KC>(d.Bt, d.n, d.ldb, d.rows, d.W, d.Kp, d.Y, local / d.tiles_c, (int)(local % d.tiles_c));
+    gemm_tile<RT, CT, KC, WQ, WC>(d.Bt, d.n, d.ldb, d.rows, d.W, d.Kp, d.Y, local / d.tiles_c,
+                                  (int)(local % d.tiles_c));
   }
 }
 
@@ -498,13 +499,17 @@ void launch_ragged_rows_fp64(const EventDesc *ev, int n_ev, int64_t total_groups
   RBFL_HIP(hipGetLastError());
 }
 
-// Multi-event GEMM tiles: variant 0 is 64 x 128 with 8-row chunks, variant 1
-// 64 x 128 with 16-row chunks.
+// Multi-event GEMM tiles: variant 0 is 64 x 128 with 8-row chunks (4 waves),
+// variant 1 64 x 128 with 16-row chunks (4 waves), variant 2 128 x 128 with
+// 8-row chunks (8 waves, the single-event kernel's preferred tile).
 void launch_ragged_gemm_fp64(int variant, const EventDesc *ev, int n_ev, int64_t total_items,
                              unsigned long long *counter, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_item_counter, dim3(1), dim3(64), 0, s, counter);
   RBFL_HIP(hipGetLastError());
-  if (variant == 1)
+  if (variant == 2)
+    hipLaunchKernelGGL((k_ragged_gemm_fp64<2, 4, 8, 4, 2>), dim3(grid), dim3(512), 0, s, ev, n_ev, total_items,
+                       counter);
+  else if (variant == 1)
     hipLaunchKernelGGL((k_ragged_gemm_fp64<2, 4, 16>), dim3(grid), dim3(kGemmThreads), 0, s, ev, n_ev, total_items,
                        counter);
   else

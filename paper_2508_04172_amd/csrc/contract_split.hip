@@ -159,14 +159,15 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
-// Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2 over the digit pairs
-// i + j < S.  One-dimensional grid over (proposal tile, column tile), the
-// column tile fastest.
+// One output tile Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2 over the
+// digit pairs i + j < S: proposals q0 .. q0 + kSplitQ - 1, columns c0 ..
+// c0 + kSplitC - 1; called by every thread of the workgroup, which leaves the
+// LDS free (after a barrier) on return.
 template <int S>
-__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
-    k_split_contract(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
-                     const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
-                     double *__restrict__ Y) {
+__device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t nb, int rows,
+                                           const v4i *__restrict__ BS, const double *__restrict__ cscale,
+                                           const double *__restrict__ rscale, int Kp, double *__restrict__ Y,
+                                           int64_t q0, int c0) {
   constexpr int kPerA = S * 2 * kSplitQ, kPerB = S * 2 * kSplitC;   // v4i entries per stage
   constexpr int kLoadsA = (kPerA + kSplitThreads - 1) / kSplitThreads;
   constexpr int kLoadsB = (kPerB + kSplitThreads - 1) / kSplitThreads;
@@ -176,10 +177,6 @@ __global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
   const int lane = tid & 63, wave = tid >> 6;
   const int wq = wave % kSplitWQ, wc = wave / kSplitWQ;
   const int G = rows / 16;
-  const int n_ct = Kp / kSplitC;
-  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int c0 = (int)(tile % n_ct) * kSplitC;
-  const int64_t q0 = (tile / n_ct) * kSplitQ;
 
   // stage entry e of an operand with W-wide tiles: digit e / (2 W), 16-row
   // group g0 + (e / W) % 2, tile position e % W
@@ -260,6 +257,93 @@ __global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
   }
 }
 
+// One-dimensional grid over (proposal tile, column tile), the column tile
+// fastest.
+template <int S>
+__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
+    k_split_contract(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
+                     const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
+                     double *__restrict__ Y) {
+  const int n_ct = Kp / kSplitC;
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  split_tile<S>(AS, nb, rows, BS, cscale, rscale, Kp, Y, (tile / n_ct) * kSplitQ, (int)(tile % n_ct) * kSplitC);
+}
+
+// Multi-event batches: the first S digits (S = the event's) of the kernel
+// rows of every event's proposals and their row scales, one launch.  Flat
+// thread index t over the events (event e owns t0 .. t0 + (rows / 16) n - 1);
+// within an event t - t0 = g n + q: proposal q, rows 16 g .. 16 g + 15.
+__global__ void __launch_bounds__(256) k_ragged_split_rows(const EventDesc *__restrict__ ev, int n_ev,
+                                                           int64_t total, const double *__restrict__ params,
+                                                           int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = n_ev - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ev[mid].t0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const EventDesc &d = ev[lo];
+  const EvalConsts &c = *d.consts;
+  const int64_t local = t - d.t0;
+  const int g = (int)(local / d.n);
+  const int64_t q = local - (int64_t)g * d.n;
+  double x[4];
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd) x[dd] = params[dd * ld + d.q0 + q] / c.semi[dd];
+  const int N = c.N, NM = c.N + c.M;
+  double bound = 1.0;
+  for (int p = 0; p < c.M; ++p) bound = fmax(bound, fabs(basis_row_fp64(N + p, N, NM, x, d.nodes, c.eps2, c.poly_idx)));
+  int e = 0;
+  frexp(bound, &e);
+  const double inv = ldexp(1.0, -e);
+  if (g == 0) d.rscale[q] = ldexp(1.0, e);
+  int8_t dg[kMaxSlices][16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = 16 * g + k;
+    int8_t a[kMaxSlices];
+    digits<kMaxSlices>(basis_row_fp64(r, N, NM, x, d.nodes + 4 * (int64_t)r, c.eps2, c.poly_idx) * inv, a);
+#pragma unroll
+    for (int i = 0; i < kMaxSlices; ++i) dg[i][k] = a[i];
+  }
+  const int G = d.rows / 16;
+  v4i *AS = static_cast<v4i *>(d.AS);
+#pragma unroll
+  for (int i = 0; i < kMaxSlices; ++i)
+    if (i < d.S) AS[((int64_t)i * G + g) * d.n + q] = pack16(dg[i]);
+}
+
+// Multi-event batches: persistent split contraction over a work list of
+// (event, proposal tile, column tile) items, every event of the list with S
+// digits, column tile fastest within an event, events in decreasing cost;
+// each workgroup takes the next item from an atomic counter until the list
+// is exhausted (every workgroup reaches that exit).
+template <int S>
+__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
+    k_ragged_split_contract(const EventDesc *__restrict__ ev, int n_ev, int64_t total_items,
+                            unsigned long long *__restrict__ counter) {
+  __shared__ long long item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t item = item_s;
+    __syncthreads();
+    if (item >= total_items) break;
+    int e = 0;
+    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
+    const EventDesc &d = ev[e];
+    const int64_t local = item - d.item0;
+    split_tile<S>(static_cast<const v4i *>(d.AS), d.n, d.rows, static_cast<const v4i *>(d.BS), d.cscale, d.rscale,
+                  d.Kp, d.Y, (local / d.tiles_c) * kSplitQ, (int)(local % d.tiles_c) * kSplitC);
+  }
+}
+
+__global__ void k_zero_counters(unsigned long long *counter, int n) {
+  if ((int)threadIdx.x < n) counter[threadIdx.x] = 0ull;
+}
+
 template <int S>
 void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                     int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
@@ -279,6 +363,36 @@ void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *par
 }
 
 }  // namespace
+
+int split_ragged_tile_q() { return kSplitQ; }
+int split_ragged_tile_c() { return kSplitC; }
+int split_ragged_blocks_per_cu() { return 4 / kSplitWQ; }
+
+void launch_ragged_split_rows(const EventDesc *ev, int n_ev, int64_t total_threads, const double *params, int64_t ld,
+                              hipStream_t s) {
+  if (total_threads <= 0) return;
+  hipLaunchKernelGGL(k_ragged_split_rows, dim3((unsigned)((total_threads + 255) / 256)), dim3(256), 0, s, ev, n_ev,
+                     total_threads, params, ld);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_zero_counters(unsigned long long *counter, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counter, n);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_ragged_split_contract(int S, const EventDesc *ev, int n_ev, int64_t total_items,
+                                  unsigned long long *counter, int grid, hipStream_t s) {
+  if (total_items <= 0) return;
+  switch (S) {
+    case 5: hipLaunchKernelGGL((k_ragged_split_contract<5>), dim3(grid), dim3(kSplitThreads), 0, s, ev, n_ev, total_items, counter); break;
+    case 6: hipLaunchKernelGGL((k_ragged_split_contract<6>), dim3(grid), dim3(kSplitThreads), 0, s, ev, n_ev, total_items, counter); break;
+    case 7: hipLaunchKernelGGL((k_ragged_split_contract<7>), dim3(grid), dim3(kSplitThreads), 0, s, ev, n_ev, total_items, counter); break;
+    case 8: hipLaunchKernelGGL((k_ragged_split_contract<8>), dim3(grid), dim3(kSplitThreads), 0, s, ev, n_ev, total_items, counter); break;
+    default: throw Error(RBFL_E_INVALID_ARG, "split form: digit count must be 5 .. 8");
+  }
+  RBFL_HIP(hipGetLastError());
+}
 
 int split_max_slices() { return kMaxSlices; }
 int split_max_rows() { return kMaxSplitRows; }

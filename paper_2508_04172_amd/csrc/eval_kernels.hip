@@ -508,7 +508,8 @@ __global__ void __launch_bounds__(kThreads) k_ragged_epilogue(const EventDesc *_
   }
 }
 
-// Surrogate inputs: x = delta_e / a in FP32, [nb][4].
+// NaN entries of lnl[0, n): block b writes its grid-stride share's count to
+// part[b] (every block writes, so the slots need no clearing).
 __global__ void __launch_bounds__(256) k_count_nan(const double *__restrict__ lnl, int64_t n,
                                                    unsigned long long *__restrict__ part) {
   __shared__ unsigned long long cnt;
@@ -522,6 +523,7 @@ __global__ void __launch_bounds__(256) k_count_nan(const double *__restrict__ ln
   if (threadIdx.x == 0) part[blockIdx.x] = cnt;
 }
 
+// Surrogate inputs: x = delta_e / a in FP32, [nb][4].
 __global__ void k_sur_inputs(const double *__restrict__ params, int64_t ld, int64_t b0, int64_t nb,
                              const EvalConsts *__restrict__ c, float *__restrict__ x) {
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -646,12 +648,12 @@ void launch_contract_fp32(const EvalConsts *c, const EvalConsts &hc, const doubl
 
 // Multi-event variants: 0-2 the fused persistent kernel, 3-4 basis rows +
 // persistent GEMM (64 x 128 tiles, 8- and 16-row chunks).
-int ragged_variants() { return 5; }
+int ragged_variants() { return 6; }
 int ragged_fused_variants() { return 3; }
-int ragged_blocks_per_cu(int variant) { return variant < 3 ? 2 : variant == 3 ? 4 : 3; }
+int ragged_blocks_per_cu(int variant) { return variant < 3 ? 2 : variant == 3 ? 4 : variant == 4 ? 3 : 2; }
 
 void ragged_tile(int variant, int *qt, int *cw) {
-  static const int q[] = {128, 128, 128, 64, 64}, w[] = {128, 64, 64, 128, 128};
+  static const int q[] = {128, 128, 128, 64, 64, 128}, w[] = {128, 64, 64, 128, 128, 128};
   *qt = q[variant];
   *cw = w[variant];
 }

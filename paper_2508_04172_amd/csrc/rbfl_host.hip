@@ -1321,44 +1321,50 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   d_part.reset();
   c.timing[2] = seconds_since(t0);
 
-  // ---- SVD per (detector, mode) and the coefficients at the nodes
+  // ---- SVD per (detector, mode), all pairs in one batched call, and the
+  // coefficients at the nodes
   t0 = Clock::now();
   BlasHandle bh;
   blas_check(rocblas_set_stream(bh.h, stream), "rocblas_set_stream");
   const int mn = std::min(c.N, c.T);
-  c.basis.alloc((size_t)c.n_det * c.n_modes * c.T * c.q);
+  const int n_pairs = c.n_det * c.n_modes;
+  c.basis.alloc((size_t)n_pairs * c.T * c.q);
   DevBuf<double2> d_C;
-  d_C.alloc((size_t)c.n_det * c.n_modes * c.N * c.q);
+  d_C.alloc((size_t)n_pairs * c.N * c.q);
   DevBuf<double2> d_work, d_U;
-  d_work.alloc((size_t)c.N * c.T);
-  d_U.alloc((size_t)c.T * mn);
+  d_work.alloc((size_t)n_pairs * c.N * c.T);
+  d_U.alloc((size_t)n_pairs * c.T * mn);
   DevBuf<double> d_S, d_E;
-  d_S.alloc(mn);
-  d_E.alloc(std::max(1, mn - 1));
+  d_S.alloc((size_t)n_pairs * mn);
+  d_E.alloc((size_t)n_pairs * std::max(1, mn - 1));
   DevBuf<int> d_info;
-  d_info.alloc(1);
-  c.singular.assign((size_t)c.n_det * c.n_modes * mn, 0.0);
-  for (int k = 0; k < c.n_det; ++k)
-    for (int a = 0; a < c.n_modes; ++a) {
-      const size_t ka = (size_t)k * c.n_modes + a;
-      const double2 *Z = c.z_nodes.p + ka * c.N * c.T;
-      RBFL_HIP(hipMemcpyAsync(d_work.p, Z, sizeof(double2) * c.N * c.T, hipMemcpyDeviceToDevice, stream));
-      // row-major N x T = column-major T x N; its left singular vectors are the
-      // conjugated right singular vectors of Z
-      blas_check(rocsolver_zgesvd(bh.h, rocblas_svect_singular, rocblas_svect_none, c.T, c.N,
-                                  reinterpret_cast<rocblas_double_complex *>(d_work.p), c.T, d_S.p,
-                                  reinterpret_cast<rocblas_double_complex *>(d_U.p), c.T, nullptr, 1, d_E.p,
-                                  rocblas_outofplace, d_info.p),
-                 "rocsolver_zgesvd");
-      int info = 0;
-      RBFL_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-      RBFL_HIP(hipMemcpyAsync(c.singular.data() + ka * mn, d_S.p, sizeof(double) * mn, hipMemcpyDeviceToHost, stream));
-      RBFL_HIP(hipStreamSynchronize(stream));
-      if (info != 0) throw Error(RBFL_E_NUMERICAL, "SVD did not converge (info " + std::to_string(info) + ")");
-      launch_basis_from_u(d_U.p, c.T, c.T, c.q, c.basis.p + ka * c.T * c.q, stream);
-      launch_coeffs(Z, c.basis.p + ka * c.T * c.q, c.N, c.T, c.q, d_C.p + ka * c.N * c.q, stream);
-    }
+  d_info.alloc(n_pairs);
+  c.singular.assign((size_t)n_pairs * mn, 0.0);
+  RBFL_HIP(hipMemcpyAsync(d_work.p, c.z_nodes.p, sizeof(double2) * d_work.n, hipMemcpyDeviceToDevice, stream));
+  // each pair's row-major N x T block is a column-major T x N matrix; its left
+  // singular vectors are the conjugated right singular vectors of Z
+  blas_check(rocsolver_zgesvd_strided_batched(
+                 bh.h, rocblas_svect_singular, rocblas_svect_none, c.T, c.N,
+                 reinterpret_cast<rocblas_double_complex *>(d_work.p), c.T, (rocblas_stride)c.N * c.T, d_S.p,
+                 (rocblas_stride)mn, reinterpret_cast<rocblas_double_complex *>(d_U.p), c.T,
+                 (rocblas_stride)c.T * mn, nullptr, 1, 1, d_E.p, (rocblas_stride)std::max(1, mn - 1),
+                 rocblas_outofplace, d_info.p, n_pairs),
+             "rocsolver_zgesvd_strided_batched");
+  std::vector<int> info_h(n_pairs);
+  RBFL_HIP(hipMemcpyAsync(info_h.data(), d_info.p, sizeof(int) * n_pairs, hipMemcpyDeviceToHost, stream));
+  RBFL_HIP(hipMemcpyAsync(c.singular.data(), d_S.p, sizeof(double) * d_S.n, hipMemcpyDeviceToHost, stream));
+  RBFL_HIP(hipStreamSynchronize(stream));
+  for (int ka = 0; ka < n_pairs; ++ka)
+    if (info_h[ka] != 0)
+      throw Error(RBFL_E_NUMERICAL, "SVD of pair " + std::to_string(ka) + " did not converge (info " +
+                                        std::to_string(info_h[ka]) + ")");
   d_work.reset();
+  for (int ka = 0; ka < n_pairs; ++ka) {
+    const double2 *Z = c.z_nodes.p + (size_t)ka * c.N * c.T;
+    launch_basis_from_u(d_U.p + (size_t)ka * c.T * mn, c.T, c.T, c.q, c.basis.p + (size_t)ka * c.T * c.q, stream);
+    launch_coeffs(Z, c.basis.p + (size_t)ka * c.T * c.q, c.N, c.T, c.q, d_C.p + (size_t)ka * c.N * c.q, stream);
+  }
+  RBFL_HIP(hipStreamSynchronize(stream));
   d_U.reset();
   c.timing[3] = seconds_since(t0);
 
@@ -2023,8 +2029,8 @@ static void prepare(Ctx &c, int form) {
   if (form == RBFL_FORM_BF16) {
     c.W16.alloc(n);
     launch_bf16_prepare(c.W.p, c.rows, c.Kp, c.W16.p, 0);
-    if (c.cap == 0) reserve(c, 65536);
-    c.A16.alloc((size_t)c.rows * c.cap);
+    // the chunk buffer follows the work space (reserve allocates it for a prepared form)
+    if (c.cap > 0) c.A16.alloc((size_t)c.rows * c.cap);
     RBFL_HIP(hipDeviceSynchronize());
     c.prepared[RBFL_FORM_BF16] = true;
     return;
@@ -2035,9 +2041,10 @@ static void prepare(Ctx &c, int form) {
     c.WS.alloc((size_t)split_max_slices() * c.Kp * c.rows);
     c.WSscale.alloc(c.Kp);
     launch_split_prepare(c.W.p, c.rows, c.Kp, c.WSscale.p, c.WS.p, 0);
-    if (c.cap == 0) reserve(c, 65536);
-    c.AS.alloc((size_t)split_max_slices() * c.cap * c.rows);
-    c.ASscale.alloc(c.cap);
+    if (c.cap > 0) {
+      c.AS.alloc((size_t)split_max_slices() * c.cap * c.rows);
+      c.ASscale.alloc(c.cap);
+    }
     RBFL_HIP(hipDeviceSynchronize());
     c.variant[RBFL_FORM_SPLIT] = kSplitDefaultVariant;
     c.prepared[RBFL_FORM_SPLIT] = true;
@@ -2297,8 +2304,21 @@ struct Plan {
   DevBuf<unsigned long long> counter;
   int64_t total_items = 0;
   int grid = 0;
-  int variant = 0;
+  int variant = 0;              // FP64 tile variant; -1 for the split form
   double tune_ms[8] = {};
+  // split form (RBFL_PLAN_SPLIT): digits per event (caller order), the digit
+  // rows and row scales of every event, and the work lists of the events
+  // grouped by digit count (one persistent launch per group)
+  bool split = false;
+  std::vector<int> S;
+  DevBuf<int8_t> AS;
+  DevBuf<double> rscale;
+  int64_t split_threads = 0;
+  int n_groups = 0;
+  int group_S[4] = {}, group_n[4] = {}, group_off[4] = {}, group_grid[4] = {};
+  int64_t group_items[4] = {};
+  DevBuf<EventDesc> ev_group;
+  int split_tol_state = -1;     // 1: every event within RBFL_SPLIT_TOL of the FP64 plan, 0: not, -1: not tuned
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -2321,6 +2341,7 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
   p.max_ldb = 0;
   for (int e = 0; e < n_ev; ++e) {
     Ctx &c = *p.ctx[e];
+    std::memset(&d[e], 0, sizeof(EventDesc));
     d[e].consts = c.consts.p;
     d[e].nodes = c.nodes.p;
     d[e].W = c.W.p;
@@ -2364,8 +2385,90 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
   p.variant = v;
 }
 
+// Split-form layout with the digit counts p.S: caller-order descriptors for
+// the digit rows and the epilogue, and per digit count a work list of its
+// events in decreasing cost with consecutive item ranges.
+static void plan_layout_split(Plan &p, hipStream_t s) {
+  const int qt = split_ragged_tile_q(), cw = split_ragged_tile_c();
+  const int n_ev = (int)p.ctx.size();
+  std::vector<EventDesc> d(n_ev);
+  int64_t q0 = 0, yoff = 0, aoff = 0, t0 = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    Ctx &c = *p.ctx[e];
+    EventDesc &x = d[e];
+    std::memset(&x, 0, sizeof(x));
+    x.consts = c.consts.p;
+    x.nodes = c.nodes.p;
+    x.W = c.W.p;
+    x.basis = c.basis4.p;
+    x.Y = p.Y.p + yoff;
+    x.q0 = q0;
+    x.n = p.counts[e];
+    x.tiles_q = (int)((p.counts[e] + qt - 1) / qt);
+    x.tiles_c = c.Kp / cw;
+    x.Kp = c.Kp;
+    x.rows = c.rows;
+    x.BS = c.WS.p;
+    x.cscale = c.WSscale.p;
+    x.AS = p.AS.p + aoff;
+    x.rscale = p.rscale.p + q0;
+    x.S = p.S[e];
+    x.t0 = t0;
+    q0 += p.counts[e];
+    yoff += p.counts[e] * c.Kp;
+    aoff += (int64_t)split_max_slices() * c.rows * p.counts[e];
+    t0 += (int64_t)(c.rows / 16) * p.counts[e];
+  }
+  p.split_threads = t0;
+  int dev = 0, cus = 0;
+  RBFL_HIP(hipGetDevice(&dev));
+  RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  auto cost = [&](int e) { return (double)p.counts[e] * (p.ctx[e]->N + p.ctx[e]->M) * p.ctx[e]->K; };
+  std::vector<EventDesc> w;
+  p.n_groups = 0;
+  for (int S = 8; S >= 5; --S) {
+    std::vector<int> order;
+    for (int e = 0; e < n_ev; ++e)
+      if (p.S[e] == S) order.push_back(e);
+    if (order.empty()) continue;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    const int g = p.n_groups++;
+    p.group_S[g] = S;
+    p.group_n[g] = (int)order.size();
+    p.group_off[g] = (int)w.size();
+    int64_t item = 0;
+    for (int e : order) {
+      EventDesc x = d[e];
+      x.item0 = item;
+      item += (int64_t)x.tiles_q * x.tiles_c;
+      w.push_back(x);
+    }
+    p.group_items[g] = item;
+    p.group_grid[g] = (int)std::max<int64_t>(1, std::min<int64_t>(item, (int64_t)cus * split_ragged_blocks_per_cu()));
+  }
+  p.total_items = 0;
+  p.grid = 0;
+  for (int g = 0; g < p.n_groups; ++g) {
+    p.total_items += p.group_items[g];
+    p.grid = std::max(p.grid, p.group_grid[g]);
+  }
+  RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipMemcpyAsync(p.ev_group.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  p.variant = -1;
+}
+
 static void plan_run(Plan &p, hipStream_t s) {
   const int n_ev = (int)p.ctx.size();
+  if (p.split) {
+    launch_ragged_split_rows(p.ev_param.p, n_ev, p.split_threads, p.params, p.total, s);
+    launch_zero_counters(p.counter.p, p.n_groups, s);
+    for (int g = 0; g < p.n_groups; ++g)
+      launch_ragged_split_contract(p.group_S[g], p.ev_group.p + p.group_off[g], p.group_n[g], p.group_items[g],
+                                   p.counter.p + g, p.group_grid[g], s);
+    launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
+    return;
+  }
   if (p.variant < ragged_fused_variants()) {
     launch_ragged_contract(p.variant, p.ev_work.p, n_ev, p.total_items, p.counter.p, p.params, p.total, p.grid, s);
   } else {
@@ -2660,10 +2763,114 @@ static void prior_weights(Ctx &c, const double *params, int64_t ld, int64_t n, c
 }  // namespace rbfl
 
 namespace rbfl {
+// Captures one launch of the plan into a HIP graph on the plan's own stream.
+static void plan_capture(Plan &p) {
+  if (!p.cap_stream) RBFL_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  RBFL_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    plan_run(p, p.cap_stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(p.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  RBFL_HIP(hipStreamEndCapture(p.cap_stream, &p.graph));
+  RBFL_HIP(hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0));
+}
+
+// Split-form digit counts per event: ln L of the whole batch with every event
+// at S = 5 .. 8 digits (each timed, median of 3) against the FP64 plan's.  An
+// event with at least kTuneMinValid in-domain proposals takes the fewest
+// digits whose ln L stays within RBFL_SPLIT_TOL / 10 of the FP64 form's on
+// them (same domain flags; the margin of a decade covers proposals the tuner
+// did not see), down to no fewer than 5; with fewer in-domain proposals it
+// keeps the default 7 digits unless 7 misses RBFL_SPLIT_TOL.  When no count
+// meets RBFL_SPLIT_TOL the most accurate one is kept (split_tol_state then
+// says so).
+static void plan_tune_split(Plan &p, hipStream_t s) {
+  constexpr int64_t kTuneMinValid = 256;
+  const int n_ev = (int)p.ctx.size();
+  p.split = false;
+  plan_layout(p, ragged_fused_variants(), s);
+  plan_run(p, s);
+  std::vector<double> ref(p.total), got(p.total);
+  RBFL_HIP(hipMemcpyAsync(ref.data(), p.lnl, sizeof(double) * p.total, hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  p.split = true;
+  std::vector<std::array<double, 4>> err(n_ev);
+  std::vector<int64_t> valid(n_ev, 0);
+  {
+    int64_t q0 = 0;
+    for (int e = 0; e < n_ev; ++e) {
+      for (int64_t i = q0; i < q0 + p.counts[e]; ++i) valid[e] += std::isfinite(ref[i]) ? 1 : 0;
+      q0 += p.counts[e];
+    }
+  }
+  hipEvent_t e0, e1;
+  RBFL_HIP(hipEventCreate(&e0));
+  RBFL_HIP(hipEventCreate(&e1));
+  for (int v = 0; v < 4; ++v) {
+    std::fill(p.S.begin(), p.S.end(), split_variant_slices(v));
+    plan_layout_split(p, s);
+    plan_run(p, s);
+    RBFL_HIP(hipMemcpyAsync(got.data(), p.lnl, sizeof(double) * p.total, hipMemcpyDeviceToHost, s));
+    RBFL_HIP(hipStreamSynchronize(s));
+    int64_t q0 = 0;
+    for (int e = 0; e < n_ev; ++e) {
+      double m = 0.0;
+      for (int64_t i = q0; i < q0 + p.counts[e]; ++i) {
+        if (std::isfinite(ref[i]) != std::isfinite(got[i]) || std::isnan(ref[i]) != std::isnan(got[i])) {
+          m = INFINITY;
+          break;
+        }
+        if (std::isfinite(ref[i])) m = std::max(m, std::fabs(got[i] - ref[i]));
+      }
+      err[e][v] = m;
+      q0 += p.counts[e];
+    }
+    double t[3];
+    for (int r = 0; r < 3; ++r) {
+      RBFL_HIP(hipEventRecord(e0, s));
+      plan_run(p, s);
+      RBFL_HIP(hipEventRecord(e1, s));
+      RBFL_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      t[r] = ms;
+    }
+    std::sort(t, t + 3);
+    p.tune_ms[v] = t[1];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bool all_ok = true;
+  for (int e = 0; e < n_ev; ++e) {
+    int pick = -1;
+    if (valid[e] >= kTuneMinValid) {
+      for (int v = 0; v < 4 && pick < 0; ++v)
+        if (err[e][v] <= 0.1 * RBFL_SPLIT_TOL) pick = v;
+    }
+    if (pick < 0) {
+      for (int v = kSplitDefaultVariant; v < 4 && pick < 0; ++v)
+        if (err[e][v] <= RBFL_SPLIT_TOL) pick = v;
+    }
+    if (pick < 0) {
+      all_ok = false;
+      pick = 3;
+      for (int v = 2; v >= 0; --v)
+        if (err[e][v] < err[e][pick]) pick = v;
+    }
+    p.S[e] = split_variant_slices(pick);
+  }
+  p.split_tol_state = all_ok ? 1 : 0;
+}
+
 static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t *counts, const double *params,
                                   double *lnl, uint32_t flags, hipStream_t s) {
   require(hs != nullptr && counts != nullptr && params != nullptr && lnl != nullptr, "NULL argument");
   require(n_ev >= 1 && n_ev <= 4096, "n_events must be in 1 .. 4096");
+  require((flags & ~(uint32_t)(RBFL_PLAN_GRAPH | RBFL_PLAN_AUTOTUNE | RBFL_PLAN_SPLIT)) == 0, "unknown plan flags");
   std::unique_ptr<rbfl_plan_ctx> pc(new rbfl_plan_ctx());
   Plan &p = pc->p;
   int64_t yelems = 0, belems = 0;
@@ -2682,8 +2889,26 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
   p.ev_param.alloc(n_ev);
   p.Y.alloc((size_t)yelems);
   p.Bt.alloc((size_t)belems);
-  p.counter.alloc(1);
-  if (flags & RBFL_PLAN_AUTOTUNE) {
+  p.counter.alloc(4);
+  if (flags & RBFL_PLAN_SPLIT) {
+    int64_t aelems = 0;
+    for (int e = 0; e < n_ev; ++e) {
+      prepare(*p.ctx[e], RBFL_FORM_SPLIT);
+      aelems += (int64_t)split_max_slices() * p.ctx[e]->rows * counts[e];
+    }
+    p.AS.alloc((size_t)aelems);
+    p.rscale.alloc((size_t)p.total);
+    p.ev_group.alloc(n_ev);
+    p.S.assign(n_ev, split_variant_slices(kSplitDefaultVariant));
+    if (flags & RBFL_PLAN_AUTOTUNE) {
+      plan_tune_split(p, s);
+    } else {
+      for (int e = 0; e < n_ev; ++e) p.S[e] = split_variant_slices(p.ctx[e]->variant[RBFL_FORM_SPLIT]);
+    }
+    p.split = true;
+    plan_layout_split(p, s);
+    p.Bt.reset();        // the FP64 basis rows served only the tuner's reference
+  } else if (flags & RBFL_PLAN_AUTOTUNE) {
     hipEvent_t e0, e1;
     RBFL_HIP(hipEventCreate(&e0));
     RBFL_HIP(hipEventCreate(&e1));
@@ -2715,21 +2940,24 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
   } else {
     plan_layout(p, ragged_fused_variants(), s);
   }
-  if (flags & RBFL_PLAN_GRAPH) {
-    RBFL_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
-    RBFL_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
-    try {
-      plan_run(p, p.cap_stream);
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(p.cap_stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    RBFL_HIP(hipStreamEndCapture(p.cap_stream, &p.graph));
-    RBFL_HIP(hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0));
-  }
+  if (flags & RBFL_PLAN_GRAPH) plan_capture(p);
   return pc.release();
+}
+
+// Pins the FP64 tile variant of a plan: new layout, and a new graph if the
+// plan has one.
+static void plan_set_variant(Plan &p, int v, hipStream_t s) {
+  if (p.split) throw Error(RBFL_E_STATE, "a split-form plan has no FP64 tile variants");
+  require(v >= 0 && v < ragged_variants(), "variant out of range");
+  RBFL_HIP(hipStreamSynchronize(s));
+  plan_layout(p, v, s);
+  if (p.exec) {
+    (void)hipGraphExecDestroy(p.exec);
+    (void)hipGraphDestroy(p.graph);
+    p.exec = nullptr;
+    p.graph = nullptr;
+    plan_capture(p);
+  }
 }
 }  // namespace rbfl
 
@@ -2871,9 +3099,21 @@ int32_t rbfl_plan_query(rbfl_plan plan, double *out, size_t bytes) {
   return rbfl::guarded([&] {
     rbfl::require(plan != nullptr, "plan is NULL");
     const rbfl::Plan &p = plan->p;
-    double v[12] = {(double)p.variant, (double)p.total_items, (double)p.grid, (double)p.total};
+    double v[16] = {(double)p.variant, (double)p.total_items, (double)p.grid, (double)p.total};
     for (int i = 0; i < 8; ++i) v[4 + i] = p.tune_ms[i];
-    rbfl::copy_out(out, bytes, v, sizeof(v));
+    v[12] = p.split ? 1.0 : 0.0;
+    v[13] = p.split ? (double)*std::min_element(p.S.begin(), p.S.end()) : 0.0;
+    v[14] = p.split ? (double)*std::max_element(p.S.begin(), p.S.end()) : 0.0;
+    v[15] = (double)p.split_tol_state;
+    rbfl::require(out != nullptr && bytes >= 12 * sizeof(double), "output buffer too small (need at least 96 bytes)");
+    std::memcpy(out, v, std::min(bytes, sizeof(v)));
+  });
+}
+
+int32_t rbfl_plan_set_variant(rbfl_plan plan, int32_t variant, void *stream) {
+  return rbfl::guarded([&] {
+    rbfl::require(plan != nullptr, "plan is NULL");
+    rbfl::plan_set_variant(plan->p, variant, reinterpret_cast<hipStream_t>(stream));
   });
 }
 

@@ -89,6 +89,13 @@ struct EventDesc {
   int64_t ldb;         // leading dimension of Bt
   int64_t rg0;         // first 16-row group of this event in the row kernel's grid
   int tiles_q, tiles_c, Kp, rows;
+  // split form (plans with RBFL_PLAN_SPLIT)
+  const void *BS;        // the handle's weight digits [8][rows/16][Kp], 16 int8 per entry
+  const double *cscale;  // the handle's power-of-two column scales [Kp]
+  void *AS;              // this event's row digits [S][rows/16][n], 16 int8 per entry
+  double *rscale;        // this event's power-of-two row scales [n]
+  int S;                 // digits per value (5 .. 8)
+  int64_t t0;            // first thread of this event in the digit-row kernel's flat grid
 };
 
 template <class T>
@@ -318,6 +325,18 @@ void launch_gemm_lnl_fp64(const double *Bt, int64_t nb, const EvalConsts &hc, co
                           hipStream_t s);
 void launch_lnl_tiles(const void *setups, int64_t b0, int64_t nb, const double *part, int64_t ldp, int n_ct,
                       double *lnl, hipStream_t s);
+// multi-event split form: tile shape of the persistent contraction, its
+// resident workgroups per CU, the digit rows of every event in one launch,
+// the persistent contraction over the work list of events with S digits, and
+// a kernel that zeroes n <= 64 work counters
+int split_ragged_tile_q();
+int split_ragged_tile_c();
+int split_ragged_blocks_per_cu();
+void launch_ragged_split_rows(const EventDesc *ev, int n_ev, int64_t total_threads, const double *params, int64_t ld,
+                              hipStream_t s);
+void launch_ragged_split_contract(int S, const EventDesc *ev, int n_ev, int64_t total_items,
+                                  unsigned long long *counter, int grid, hipStream_t s);
+void launch_zero_counters(unsigned long long *counter, int n, hipStream_t s);
 int split_max_slices();
 int split_max_rows();
 int split_variant_count();

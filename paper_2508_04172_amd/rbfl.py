@@ -34,12 +34,12 @@ EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "
             "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
             "rbfl_fuse_epilogue",
             "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
-            "rbfl_plan_query", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
+            "rbfl_plan_query", "rbfl_plan_set_variant", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
             "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
             "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_save", "rbfl_load", "rbfl_destroy")
 SAMPLER_PRIOR_ONLY = 0x1
-PLAN_GRAPH, PLAN_AUTOTUNE = 0x1, 0x2
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_SPLIT = 0x1, 0x2, 0x4
 
 
 class BuildSpec(C.Structure):
@@ -177,6 +177,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
     lib.rbfl_plan_query.restype = C.c_int32
     lib.rbfl_plan_query.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.rbfl_plan_set_variant.restype = C.c_int32
+    lib.rbfl_plan_set_variant.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     lib.rbfl_plan_destroy.restype = C.c_int32
     lib.rbfl_plan_destroy.argtypes = [C.c_void_p]
     lib.rbfl_eval_ragged.restype = C.c_int32
@@ -420,6 +422,17 @@ class Handle:
     def cond(self) -> float:
         return float(self._query(Q_COND, 1)[0])
 
+    def exports(self) -> dict:
+        """Every artefact the online stage evaluates with, as host arrays (the
+        keyword arguments of an evaluation-parity check): frame, nodes, RBF
+        weights, SVD basis, window half-width, reference distance and frequency."""
+        fr = self.frame()
+        return {"theta_c": fr["theta_c"], "metric_g": fr["metric"], "vecs": fr["vecs"], "lam": fr["lam"],
+                "semi": fr["semi"], "x_nodes": self.nodes(), "phys_nodes": self.node_phys(), "W": self.weights(),
+                "basis": self.basis(), "half_w": self.sizes()["half_w"], "d_ref": self.d_ref(),
+                "f_ref": self.f_ref(), "cond": self.cond(), "singular": self.singular(),
+                "node_values": self.node_values()}
+
     def timing(self) -> np.ndarray:
         return self._query(Q_TIMING, 8)
 
@@ -519,11 +532,19 @@ class Plan:
     def launch(self, stream: int = 0):
         _check(load().rbfl_plan_launch(self._p, C.c_void_p(stream)))
 
+    def set_variant(self, variant: int, stream: int = 0):
+        """Pins the FP64 tile variant (rbfl_plan_set_variant)."""
+        _check(load().rbfl_plan_set_variant(self._p, variant, C.c_void_p(stream)))
+
     def info(self) -> dict:
-        v = np.zeros(12)
+        v = np.zeros(16)
         _check(load().rbfl_plan_query(self._p, v.ctypes.data_as(C.c_void_p), v.nbytes))
-        return {"variant": int(v[0]), "items": int(v[1]), "grid": int(v[2]), "proposals": int(v[3]),
-                "tune_ms": [float(x) for x in v[4:] if x > 0]}
+        out = {"variant": int(v[0]), "items": int(v[1]), "grid": int(v[2]), "proposals": int(v[3]),
+               "tune_ms": [float(x) for x in v[4:12] if x > 0]}
+        if v[12]:
+            out.update({"form": "split", "slices_min": int(v[13]), "slices_max": int(v[14]),
+                        "within_split_tol": None if v[15] < 0 else bool(v[15])})
+        return out
 
     def close(self):
         if self._p is not None and self._p.value:

@@ -23,7 +23,6 @@ import pytest
 
 from full_size import handle
 from oracle import likelihood as lk
-from oracle import physics as ph
 from oracle import startup as su
 from paper_2508_04172_amd import rbfl
 from paper_2508_04172_amd import workloads as wl
@@ -44,19 +43,7 @@ def _torch():
 def library_artefacts(h, cfg):
     """Oracle artefacts whose every evaluation input is the library's export;
     the detector geometry, layout and spline table are the oracle's own."""
-    fr = h.frame()
-    sz = h.sizes()
-    grid = ph.Grid(cfg.fs, cfg.seg_len, cfg.f_low, f_ref=h.f_ref())
-    geo = [ph.detector_geometry(s) for s in cfg.sites]
-    ev = su.Event(grid=grid, modes=tuple(cfg.modes), psd=None, data=None, det_tensor=[g[0] for g in geo],
-                  det_pos=[g[1] for g in geo], inj_phys=tuple(cfg.inj_phys),
-                  inj_ext=np.asarray(wl.injection_extrinsics(cfg)), t_trig=cfg.t_trig, d_inj=h.d_ref(),
-                  snr_opt=cfg.inj_snr)
-    frame = su.Frame(theta_c=fr["theta_c"], metric=fr["metric"], vecs=fr["vecs"], lam=fr["lam"], semi=fr["semi"])
-    return su.Artefacts(ev=ev, cfg=cfg, frame=frame, x_nodes=h.nodes(), phys_nodes=h.node_phys(), W=h.weights(),
-                        basis=h.basis(), half_w=sz["half_w"], eps=cfg.eps, degree=cfg.poly_degree, q=cfg.q,
-                        cond=h.cond(), discarded=None, singular=h.singular(), node_values=h.node_values(),
-                        z_nodes=None, sigma_nodes=None)
+    return su.artefacts_from_exports(cfg, wl.injection_extrinsics(cfg), **h.exports())
 
 
 def setup(name):

@@ -45,9 +45,12 @@ def test_split_interpolant(name):
     col_scale = column_scale(art)
     basis = np.concatenate([su.gaussian_kernel(qd.x, art.x_nodes, art.eps), su.poly_matrix(qd.x, art.degree)], 1)
     amp = (np.abs(basis) @ np.abs(art.W)).max(axis=0) / col_scale
-    # worst case of the split arithmetic: power-of-two scales bound |W_rc| and |B_r|
-    s_c = 2.0 ** np.ceil(np.log2(np.maximum(np.abs(art.W).max(axis=0), 1e-300)))
-    s_q = 2.0 ** np.ceil(np.log2(np.maximum(1.0, np.abs(basis).max(axis=1))))
+    # worst case of the split arithmetic with the kernels' power-of-two scales:
+    # 2^e strictly above the bound, e from frexp (a bound of 1 gives 2), the
+    # column scale 1 for an all-zero column
+    wmax = np.abs(art.W).max(axis=0)
+    s_c = np.where(wmax > 0, np.ldexp(1.0, np.frexp(wmax)[1]), 1.0)
+    s_q = np.ldexp(1.0, np.frexp(np.maximum(1.0, np.abs(basis).max(axis=1)))[1])
     split_bound = (SLICES + 3) * 254.0 ** (-SLICES) * basis.shape[1] * s_q.max() * s_c / col_scale
     bar = np.maximum(1e-6, 1e-13 * amp) + split_bound
     err = np.abs(Ys - Yo).max(axis=0) / col_scale

@@ -124,3 +124,108 @@ def test_plan_rejects_bad_arguments():
     with pytest.raises(rbfl.RbflError) as e:
         rbfl.Plan(hs[:2], [5, 0], buf.data_ptr(), buf.data_ptr(), 0)
     assert e.value.code == rbfl.E_INVALID_ARG
+
+
+def _oracle_per_event(arts, cpu, lr, bar=1e-3, label="split plan"):
+    off = 0
+    worst = 0.0
+    for e, (art, n) in enumerate(zip(arts, COUNTS)):
+        lo = lk.meshfree_lnl(art, *cpu[e])
+        lg = lr[off:off + n]
+        f = np.isfinite(lo)
+        assert np.array_equal(f, np.isfinite(lg)), f"{label} event {e}: domain flags differ"
+        if f.any():
+            d = np.abs(lg[f] - lo[f]).max()
+            worst = max(worst, d)
+            assert d <= bar, f"{label} event {e}: max |dlnL| {d:.3e}"
+        off += n
+    return worst
+
+
+def test_split_plan_tuned_per_event_matches_oracle_and_replays():
+    """The split form in one plan: each event's digit count tuned against the
+    FP64 plan (within RBFL_SPLIT_TOL on the tuning proposals), the captured
+    graph replayed on new proposals, every replay within 1e-3 of the oracle
+    per event and within the split form's accuracy of the FP64 per-event
+    evaluation."""
+    torch = _torch()
+    hs, arts = events()
+    total = sum(COUNTS)
+    params0, cpu0 = proposals(0)
+    p = torch.from_numpy(params0).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(),
+                     rbfl.PLAN_GRAPH | rbfl.PLAN_AUTOTUNE | rbfl.PLAN_SPLIT, stream)
+    info = plan.info()
+    print(f"[ragged] split plan: {info}", flush=True)
+    assert info["form"] == "split" and info["variant"] == -1 and info["within_split_tol"] is True
+    assert 5 <= info["slices_min"] <= info["slices_max"] <= 8 and len(info["tune_ms"]) == 4
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    lr = out.cpu().numpy()
+    assert np.abs(lr[np.isfinite(lr)] - per_event_gpu(hs, params0)[np.isfinite(lr)]).max() <= rbfl.SPLIT_TOL
+    worst = _oracle_per_event(arts, cpu0, lr)
+    print(f"[ragged] split plan vs oracle: max |dlnL| {worst:.3e}", flush=True)
+    for step in range(2):
+        params, cpu = proposals(step + 1)
+        p.copy_(torch.from_numpy(params))
+        torch.cuda.synchronize()
+        plan.launch(stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want = per_event_gpu(hs, params)
+        fin = np.isfinite(want)
+        assert np.array_equal(fin, np.isfinite(got)), f"replay {step}"
+        assert np.abs(got[fin] - want[fin]).max() <= 1e-3, f"replay {step}"
+        _oracle_per_event(arts, cpu, got, label=f"split replay {step}")
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+    plan.close()
+
+
+def test_split_plan_untuned_uses_each_handles_digits():
+    """Without tuning every event keeps its handle's split variant (7 digits
+    unless tuned on the handle) and matches the oracle within 1e-3."""
+    torch = _torch()
+    hs, arts = events()
+    total = sum(COUNTS)
+    params, cpu = proposals(5)
+    p = torch.from_numpy(params).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), rbfl.PLAN_SPLIT, stream)
+    info = plan.info()
+    assert info["form"] == "split" and info["within_split_tol"] is None
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    _oracle_per_event(arts, cpu, out.cpu().numpy(), label="untuned split plan")
+    plan.close()
+    with pytest.raises(rbfl.RbflError) as e:
+        rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), 0x80, stream)
+    assert e.value.code == rbfl.E_INVALID_ARG
+
+
+def test_fp64_plan_8_wave_tile_matches_per_event():
+    """Every FP64 tile variant of the persistent contraction, the 8-wave
+    128 x 128 one included, gives the per-event results to rounding."""
+    torch = _torch()
+    hs, _ = events()
+    total = sum(COUNTS)
+    params, _ = proposals(7)
+    p = torch.from_numpy(params).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), rbfl.PLAN_AUTOTUNE | rbfl.PLAN_GRAPH, stream)
+    info = plan.info()
+    print(f"[ragged] FP64 tile timings {info['tune_ms']}, chosen {info['variant']}", flush=True)
+    assert len(info["tune_ms"]) == 6
+    want = per_event_gpu(hs, params)
+    fin = np.isfinite(want)
+    for v in range(6):
+        plan.set_variant(v, stream)
+        plan.launch(stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(fin, np.isfinite(got)), f"variant {v}"
+        assert np.abs(got[fin] - want[fin]).max() <= 1e-12 * max(1.0, np.abs(want[fin]).max()), f"variant {v}"
+    plan.close()

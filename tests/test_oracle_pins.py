@@ -648,3 +648,18 @@ def test_rotating_signal_closed_form_on_the_equator():
     # the band spans a sizeable rotation, and the (2,2) mode passes f_ref at t_c
     assert np.ptp(rate * t) > 0.05
     assert ph.spa_time(np.array([grid.f_ref]), 2, phys, grid.f_ref, t_c)[0] == pytest.approx(t_c, abs=1e-9)
+
+
+def test_artefacts_from_exports_evaluate_like_the_originals(multi_art):
+    """The evaluation-parity glue: artefacts rebuilt from another start-up's
+    arrays (here the oracle's own) give the same online-stage ln L bit for bit."""
+    art = multi_art
+    fr = art.frame
+    rebuilt = su.artefacts_from_exports(TINY_MULTI, art.ev.inj_ext, fr.theta_c, fr.metric, fr.vecs, fr.lam, fr.semi,
+                                        art.x_nodes, art.phys_nodes, art.W, art.basis, art.half_w, art.d_ref,
+                                        art.ev.grid.f_ref)
+    qd = wl.queries(TINY_MULTI, n=300, seed=3)
+    a = lk.meshfree_lnl(art, *lk.query_params(art, qd))
+    b = lk.meshfree_lnl(rebuilt, *lk.query_params(rebuilt, qd))
+    assert np.isfinite(a).sum() > 0
+    assert np.array_equal(a, b)
