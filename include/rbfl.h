@@ -217,6 +217,27 @@ int32_t rbfl_exact_parts(rbfl_handle h, const double *params, int64_t n, double 
 int32_t rbfl_eval(rbfl_handle h, const double *params, int64_t n, double *lnl, int32_t form,
                   void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rbfl_eval of
+ * the FP64 form with its work space -- each chunk's basis rows and
+ * interpolated outputs -- in a fixed device array of RBFL_STATIC_SCRATCH_BYTES
+ * compiled into the library (one per GPU, held until the process ends)
+ * instead of the handle's work space; it calls nothing that allocates.
+ * Proposals run in chunks of floor(RBFL_STATIC_SCRATCH_BYTES / (8 (rows + Kp)))
+ * rounded down to a multiple of 8 (rows = N + M padded to 32, Kp = K padded
+ * to 128), always in the serial order (basis rows, contraction with the
+ * handle's FP64 tile variant, epilogue), then the NaN count
+ * (RBFL_Q_NAN_COUNT).  params, n, lnl: as rbfl_eval; ln L equals rbfl_eval's
+ * in its default serial order bit for bit (to rounding when rbfl_eval
+ * finishes ln L inside the contraction).  Enqueued on `stream`.  The
+ * handle's device must be current (else RBFL_E_INVALID_ARG).  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, threads or handles) race and
+ * give wrong results, so order them.  RBFL_E_INVALID_ARG when 64 proposals
+ * of the handle do not fit the array (8 (rows + Kp) bytes each). */
+#define RBFL_STATIC_SCRATCH_BYTES (128u << 20)
+int32_t rbfl_eval_static(rbfl_handle h, const double *params, int64_t n, double *lnl, void *stream);
+
 /* Interpolated quantities at n proposals (Eq. rbfcoeff): out[b][c], c < K,
  * device FP64, row stride K.  Per detector k the K reals are, in order, for
  * each mode the interleaved (Re, Im) of the q SVD coefficients (Eq. SVD),

@@ -29,6 +29,7 @@ Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALU
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
     Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT = range(23)
 SPLIT_TOL = 1e-4
+STATIC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
@@ -37,7 +38,8 @@ EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "
             "rbfl_plan_query", "rbfl_plan_set_variant", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
             "rbfl_mlp_destroy", "rbfl_sampler_create", "rbfl_sampler_run", "rbfl_sampler_smc", "rbfl_sampler_query",
-            "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_save", "rbfl_load", "rbfl_destroy")
+            "rbfl_sampler_destroy", "rbfl_prior_weights", "rbfl_save", "rbfl_load", "rbfl_eval_static",
+            "rbfl_destroy")
 SAMPLER_PRIOR_ONLY = 0x1
 PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_SPLIT = 0x1, 0x2, 0x4
 
@@ -216,6 +218,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_prior_weights.restype = C.c_int32
     lib.rbfl_prior_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                        C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+    lib.rbfl_eval_static.restype = C.c_int32
+    lib.rbfl_eval_static.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     lib.rbfl_save.restype = C.c_int32
     lib.rbfl_save.argtypes = [C.c_void_p, C.c_char_p]
     lib.rbfl_load.restype = C.c_int32
@@ -349,6 +353,11 @@ class Handle:
     def eval(self, params_ptr: int, n: int, lnl_ptr: int, form: int = FORM_FP64, stream: int = 0):
         _check(load().rbfl_eval(self._h, C.c_void_p(params_ptr), n, C.c_void_p(lnl_ptr), form,
                                 C.c_void_p(stream)))
+
+    def eval_static(self, params_ptr: int, n: int, lnl_ptr: int, stream: int = 0):
+        """FP64 ln L with the library's fixed work-space array, no allocation (rbfl_eval_static)."""
+        _check(load().rbfl_eval_static(self._h, C.c_void_p(params_ptr), n, C.c_void_p(lnl_ptr),
+                                       C.c_void_p(stream)))
 
     def interp(self, params_ptr: int, n: int, out_ptr: int, form: int = FORM_FP64, stream: int = 0):
         _check(load().rbfl_interp(self._h, C.c_void_p(params_ptr), n, C.c_void_p(out_ptr), form,
