@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 5
+#define RBFL_ABI_VERSION 6
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
 
@@ -147,7 +147,9 @@ typedef struct {
   double half_window;                  /* window half-width [s]; W = floor(half_window * fs) */
   int32_t n_nodes;                     /* N >= 1 + number of monomials */
   int32_t q;                           /* basis size, 1 .. min(N, 2W+1) */
-  double eps;                          /* Gaussian shape parameter (> 0) */
+  double eps;                          /* Gaussian shape parameter (> 0), or 0: the smallest integer from 1
+                                          whose RBF system has a 1-norm condition estimate <= 1e12 (tried up
+                                          to 8, RBFL_Q_EPS reports the value used) */
   int32_t poly_degree;                 /* 0 .. 3 */
   double chi_max;                      /* spin bound of the physical region (0 < chi_max <= 1) */
   uint32_t flags;                      /* RBFL_FLAG_* */
@@ -296,6 +298,10 @@ enum rbfl_query_what {
                                of rbfl_mlp_get for n_in = 4, the width given to rbfl_surrogate_train,
                                n_out = K), then the per-column mean and standard deviation that map
                                its outputs to the interpolated quantities (out = mean + sd * y);
+                               RBFL_E_STATE before rbfl_surrogate_train.  Synchronises the device. */
+  RBFL_Q_EPS = 24,          /* double[1]: the Gaussian shape parameter of the interpolants */
+  RBFL_Q_SURROGATE_BASE = 23, /* double[10 + nbase K]: the surrogate's base degree, nbase (0 without
+                               a base), m[4], s[4], then the base coefficients [nbase][K] row-major;
                                RBFL_E_STATE before rbfl_surrogate_train.  Synchronises the device. */
   RBFL_Q_SPLIT_STATE = 21,  /* double[3]: 1/0 the split form's digit count was chosen by rbfl_autotune,
                                1/0 that choice is within RBFL_SPLIT_TOL of the FP64 form (when no digit
@@ -462,6 +468,12 @@ typedef struct {
   const double *holdout_params;  /* device FP64 [11][n_holdout] proposals, or NULL (then never accepted) */
   int64_t n_holdout;
   double threshold;              /* acceptance bar on max |d ln L| over the held-out proposals */
+  int32_t base_degree;           /* 0: the network's outputs are the standardised interpolated reals;
+                                    1 .. 3 (residual form): an FP64 least-squares polynomial of this degree
+                                    (all monomials, graded-lexicographic) in the training proposals'
+                                    standardised coordinates u = (x - m) / s (m, s their per-axis mean and
+                                    deviation) is fitted to each real, and the network learns the
+                                    standardised residual; inference adds the base back in FP64 */
 } rbfl_train_spec;
 int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream);
 /* Overrides the held-out judge (on = 1: the surrogate form uses the network

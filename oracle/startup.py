@@ -472,6 +472,33 @@ def gaussian_kernel(xa: np.ndarray, xb: np.ndarray, eps: float) -> np.ndarray:
     return np.exp(-(eps * eps) * d2)
 
 
+def rbf_system(x: np.ndarray, eps: float, degree: int) -> np.ndarray:
+    """[[Phi, P], [P^T, 0]] of Eq. rbfcoeff (side condition sum_i a_i p_j(x_i) = 0)."""
+    n = x.shape[0]
+    P = poly_matrix(x, degree)
+    m = P.shape[1]
+    A = np.zeros((n + m, n + m))
+    A[:n, :n] = gaussian_kernel(x, x, eps)
+    A[:n, n:] = P
+    A[n:, :n] = P.T
+    return A
+
+
+def choose_eps(x: np.ndarray, degree: int, cond_max: float = 1e12, eps_max: int = 8) -> float:
+    """Shape parameter when the workload leaves it open: the smallest integer
+    from 1 whose system has a 1-norm condition number <= cond_max (the reading
+    that fixed the configured workloads' values), eps_max if none does."""
+    for eps in range(1, eps_max + 1):
+        A = rbf_system(x, float(eps), degree)
+        try:
+            c = np.linalg.cond(A, 1)
+        except np.linalg.LinAlgError:
+            continue
+        if np.isfinite(c) and c <= cond_max:
+            return float(eps)
+    return float(eps_max)
+
+
 def rbf_solve(x: np.ndarray, F: np.ndarray, eps: float, degree: int, refine: int = 2):
     """Solve [[Phi, P], [P^T, 0]] W = [F; 0] by LU with partial pivoting.
     The side condition sum_i a_i p_j(x_i) = 0 fixes the polynomial part.
@@ -480,13 +507,8 @@ def rbf_solve(x: np.ndarray, F: np.ndarray, eps: float, degree: int, refine: int
     so W is accurate to FP64 rounding rather than to cond(A) * eps.
     Returns (W [(N+M)][K], 1-norm condition estimate of the system)."""
     n = x.shape[0]
-    P = poly_matrix(x, degree)
-    m = P.shape[1]
-    A = np.zeros((n + m, n + m))
-    A[:n, :n] = gaussian_kernel(x, x, eps)
-    A[:n, n:] = P
-    A[n:, :n] = P.T
-    rhs = np.zeros((n + m, F.shape[1]))
+    A = rbf_system(x, eps, degree)
+    rhs = np.zeros((A.shape[0], F.shape[1]))
     rhs[:n] = F
     lu = scipy.linalg.lu_factor(A)
     W = scipy.linalg.lu_solve(lu, rhs)
@@ -528,7 +550,8 @@ class Artefacts:
 
 
 def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_nodes, phys_nodes, W, basis,
-                           half_w, d_ref, f_ref, cond=float("nan"), singular=None, node_values=None) -> Artefacts:
+                           half_w, d_ref, f_ref, eps=None, cond=float("nan"), singular=None,
+                           node_values=None) -> Artefacts:
     """Artefacts whose evaluation inputs are given arrays (another start-up's
     frame, nodes, RBF weights, SVD basis, reference distance and frequency),
     so that the online stage here (meshfree_lnl, rbf_eval) evaluates exactly
@@ -543,7 +566,8 @@ def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_n
     fr = Frame(theta_c=np.asarray(theta_c), metric=np.asarray(metric_g), vecs=np.asarray(vecs), lam=np.asarray(lam),
                semi=np.asarray(semi))
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=np.asarray(x_nodes), phys_nodes=np.asarray(phys_nodes),
-                     W=np.asarray(W), basis=np.asarray(basis), half_w=int(half_w), eps=cfg.eps,
+                     W=np.asarray(W), basis=np.asarray(basis), half_w=int(half_w),
+                     eps=cfg.eps if eps is None else float(eps),
                      degree=cfg.poly_degree, q=cfg.q, cond=cond, discarded=None, singular=singular,
                      node_values=node_values, z_nodes=None, sigma_nodes=None)
 
@@ -604,9 +628,10 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
                 F[:, p] = sig[k, :, a, b].real
                 F[:, p + 1] = sig[k, :, a, b].imag
                 p += 2
-    W, cond = rbf_solve(x, F, cfg.eps, cfg.poly_degree)
+    eps = cfg.eps if cfg.eps > 0 else choose_eps(x, cfg.poly_degree)
+    W, cond = rbf_solve(x, F, eps, cfg.poly_degree)
     half_w = int(math.floor(cfg.half_window * grid.fs + 1e-9))
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=x, phys_nodes=phys, W=W, basis=basis,
-                     half_w=half_w, eps=cfg.eps, degree=cfg.poly_degree, q=cfg.q, cond=cond,
+                     half_w=half_w, eps=eps, degree=cfg.poly_degree, q=cfg.q, cond=cond,
                      discarded=discarded, singular=singular, node_values=F, z_nodes=z,
                      sigma_nodes=sig, squeeze_factor=squeeze_factor, centre_opt=centre_opt)

@@ -531,6 +531,24 @@ __global__ void k_sur_inputs(const double *__restrict__ params, int64_t ld, int6
   for (int d = 0; d < 4; ++d) x[b * 4 + d] = (float)(params[d * ld + b0 + b] / c->semi[d]);
 }
 
+// Residual-form surrogate: the base monomials of u = (x - m) / s in FP64.
+__global__ void k_sur_base_inputs(const double *__restrict__ params, int64_t ld, int64_t b0, int64_t nb,
+                                  const EvalConsts *__restrict__ c, const double *__restrict__ ms,
+                                  const int *__restrict__ poly, int nbase, double *__restrict__ U) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  double u[4];
+  for (int d = 0; d < 4; ++d) u[d] = (params[d * ld + b0 + b] / c->semi[d] - ms[d]) / ms[4 + d];
+  for (int p = 0; p < nbase; ++p) {
+    double v = 1.0;
+    for (int t = 0; t < 3; ++t) {
+      const int i = poly[3 * p + t];
+      if (i >= 0) v *= u[i];
+    }
+    U[b * nbase + p] = v;
+  }
+}
+
 // Per-column mean and standard deviation of Y [n][K] (two passes, FP64).
 __global__ void k_col_stats(const double *__restrict__ Y, int64_t n, int K, float *__restrict__ mu,
                             float *__restrict__ sd) {
@@ -719,6 +737,14 @@ void launch_series_lnl(const EvalConsts *c, const double *params, int64_t ld, in
 
 void launch_count_nan(const double *lnl, int64_t n, unsigned long long *part, hipStream_t s) {
   hipLaunchKernelGGL(k_count_nan, dim3(kNanParts), dim3(256), 0, s, lnl, n, part);
+  RBFL_HIP(hipGetLastError());
+}
+
+void launch_sur_base_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c,
+                            const double *ms, const int *poly, int nbase, double *U, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_sur_base_inputs, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, params, ld, b0, nb, c,
+                     ms, poly, nbase, U);
   RBFL_HIP(hipGetLastError());
 }
 

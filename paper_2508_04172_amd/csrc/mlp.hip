@@ -102,13 +102,17 @@ __global__ void __launch_bounds__(kT) k_gemm_f32(int M, int N, int K, const floa
 // the caller guarantees K % 16 == 0 and 16-byte aligned rows.
 // ACT 0: linear, 1: SiLU, 2: linear with the output standardisation undone
 // in FP64, Y[m][n] = mu[n] + sd[n] v into the interpolant's output layout
-// (row stride ldc), as the surrogate form's inference needs it.
+// (row stride ldc), as the surrogate form's inference needs it; with Bb set
+// (residual form) the FP64 polynomial base sum_j Ub[m][j] Bb[j][n] is added
+// (Ub: the proposal's nbase monomials, Bb: the base coefficients [nbase][N]).
 template <int ACT>
 __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const float *__restrict__ A, int64_t lda,
                                                      const float *__restrict__ B, int64_t ldb,
                                                      const float *__restrict__ bias, float *__restrict__ Z,
                                                      float *__restrict__ C, int64_t ldc, const float *__restrict__ mu,
-                                                     const float *__restrict__ sd, double *__restrict__ Y64) {
+                                                     const float *__restrict__ sd, double *__restrict__ Y64,
+                                                     const double *__restrict__ Ub, const double *__restrict__ Bb,
+                                                     int nbase) {
   __shared__ float As[2][16][128 + 4];
   __shared__ float Bs[2][16][128 + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -165,6 +169,31 @@ __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const 
     if (ch + 1 < n_chunks) stash(cur ^ 1);
     __syncthreads();
   }
+  // residual form: this thread's 2 x 4 rows x 4 columns of the FP64 base
+  double bsum[2][4][4] = {};
+  if (ACT == 2 && Bb) {
+    for (int j = 0; j < nbase; ++j) {
+      double uj[2][4], bj[4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = m0 + wq * 32 + 16 * t + 4 * kk + i;
+          uj[t][i] = m < M ? Ub[(int64_t)m * nbase + j] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int n = n0 + wc * 64 + 16 * u + ll;
+        bj[u] = n < N ? Bb[(int64_t)j * N + n] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bsum[t][i][u] = fma(uj[t][i], bj[u], bsum[t][i][u]);
+    }
+  }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -177,7 +206,7 @@ __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const 
         if (n >= N) continue;
         float v = acc[t][u][i] + (bias ? bias[n] : 0.0f);
         if (ACT == 2) {
-          Y64[(int64_t)m * ldc + n] = (double)mu[n] + (double)sd[n] * (double)v;
+          Y64[(int64_t)m * ldc + n] = (double)mu[n] + (double)sd[n] * (double)v + bsum[t][i][u];
           continue;
         }
         if (Z) Z[(int64_t)m * ldc + n] = v;
@@ -187,15 +216,21 @@ __global__ void __launch_bounds__(512) k_gemm_f32_nt(int M, int N, int K, const 
     }
 }
 
-// Y[b][c] = mu[c] + sd[c] y[b][c] in FP64 (row stride ldy) from FP32 y [B][out].
+// Y[b][c] = mu[c] + sd[c] y[b][c] in FP64 (row stride ldy) from FP32 y [B][out],
+// plus the FP64 base sum_j Ub[b][j] Bb[j][c] of the residual form when Bb is set.
 __global__ void __launch_bounds__(kT) k_unstandardise(const float *__restrict__ y, int64_t B, int out,
                                                       const float *__restrict__ mu, const float *__restrict__ sd,
-                                                      double *__restrict__ Y, int64_t ldy) {
+                                                      double *__restrict__ Y, int64_t ldy,
+                                                      const double *__restrict__ Ub, const double *__restrict__ Bb,
+                                                      int nbase) {
   const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (e >= B * out) return;
   const int64_t b = e / out;
   const int c = (int)(e - b * out);
-  Y[b * ldy + c] = (double)mu[c] + (double)sd[c] * (double)y[e];
+  double base = 0.0;
+  if (Bb)
+    for (int j = 0; j < nbase; ++j) base = fma(Ub[b * nbase + j], Bb[(int64_t)j * out + c], base);
+  Y[b * ldy + c] = (double)mu[c] + (double)sd[c] * (double)y[e] + base;
 }
 
 // dY = 2 (Y - T) / count; per-block partial sums of (Y - T)^2 (fixed order).
@@ -315,10 +350,10 @@ static void gemm(int act, int M, int N, int K, const float *A, int64_t sam, int6
     dim3 g((unsigned)((int64_t)((N + 127) / 128) * ((M + 127) / 128)));
     if (act)
       hipLaunchKernelGGL(k_gemm_f32_nt<1>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc, nullptr,
-                         nullptr, nullptr);
+                         nullptr, nullptr, nullptr, nullptr, 0);
     else
       hipLaunchKernelGGL(k_gemm_f32_nt<0>, g, dim3(512), 0, s, M, N, K, A, sam, B, sbn, bias, Z, C, ldc, nullptr,
-                         nullptr, nullptr);
+                         nullptr, nullptr, nullptr, nullptr, 0);
     RBFL_HIP(hipGetLastError());
     return;
   }
@@ -338,7 +373,8 @@ void Mlp::forward(const float *X, int64_t B, float *Y, hipStream_t s) {
   gemm(0, b, out, hid, H2.p, hid, 1, p.p + o_w3, 1, hid, p.p + o_b3, nullptr, Y, out, s);
 }
 
-void Mlp::infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s) {
+void Mlp::infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s,
+                const double *Ub, const double *Bb, int nbase) {
   reserve(B);
   const int b = (int)B;
   gemm(1, b, hid, in, X, in, 1, p.p + o_w1, 1, in, p.p + o_b1, nullptr, H1.p, hid, s);
@@ -347,13 +383,13 @@ void Mlp::infer(const float *X, int64_t B, const float *mu, const float *sd, dou
   if (nt_ok(hid, H2.p, hid, 1, W3, 1, hid)) {
     dim3 g((unsigned)((int64_t)((out + 127) / 128) * ((b + 127) / 128)));
     hipLaunchKernelGGL(k_gemm_f32_nt<2>, g, dim3(512), 0, s, b, out, hid, H2.p, (int64_t)hid, W3, (int64_t)hid,
-                       p.p + o_b3, nullptr, nullptr, ldy, mu, sd, Y);
+                       p.p + o_b3, nullptr, nullptr, ldy, mu, sd, Y, Ub, Bb, nbase);
     RBFL_HIP(hipGetLastError());
     return;
   }
   gemm(0, b, out, hid, H2.p, hid, 1, W3, 1, hid, p.p + o_b3, nullptr, Yb.p, out, s);
   hipLaunchKernelGGL(k_unstandardise, dim3((unsigned)(((int64_t)b * out + kT - 1) / kT)), dim3(kT), 0, s, Yb.p,
-                     (int64_t)b, out, mu, sd, Y, ldy);
+                     (int64_t)b, out, mu, sd, Y, ldy, Ub, Bb, nbase);
   RBFL_HIP(hipGetLastError());
 }
 

@@ -689,7 +689,7 @@ static void validate(const rbfl_build_spec *s) {
   const int M = (int)(s->poly_degree == 0 ? 1 : s->poly_degree == 1 ? 5 : s->poly_degree == 2 ? 15 : 35);
   require(s->n_nodes > M && s->n_nodes <= 20000, "n_nodes must exceed the number of monomials (and <= 20000)");
   require(s->q >= 1 && s->q <= std::min(s->n_nodes, 2 * W + 1), "q must be in 1 .. min(N, 2W+1)");
-  require(std::isfinite(s->eps) && s->eps > 0, "eps must be > 0");
+  require(std::isfinite(s->eps) && s->eps >= 0, "eps must be >= 0 (0: chosen by the condition of the system)");
   require(std::isfinite(s->chi_max) && s->chi_max > 0 && s->chi_max <= 1, "chi_max must be in (0, 1]");
   if (s->psd) {
     const int64_t nf = (int64_t)std::llround(ns) / 2 + 1;
@@ -1088,7 +1088,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.n_s = (int64_t)std::llround(s->fs * s->seg_len);
   c.n_f = c.n_s / 2 + 1;
   c.df = 1.0 / s->seg_len;
-  c.eps = s->eps;
+  c.eps = s->eps;   // 0: chosen with the RBF system (the smallest integer keeping it well conditioned)
   c.chi_max = s->chi_max;
   c.t_trig = s->t_trig;
   c.earth_rate = s->earth_rate;
@@ -1402,51 +1402,18 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   DevBuf<int> d_poly;
   d_poly.alloc(kMaxPoly * 3);
   RBFL_HIP(hipMemcpyAsync(d_poly.p, poly, sizeof(poly), hipMemcpyHostToDevice, stream));
-  DevBuf<double> d_A2;
-  d_A2.alloc((size_t)NM * NM);
-  launch_assemble_system(c.nodes.p, c.N, c.M, d_poly.p, c.eps * c.eps, d_A2.p, stream);
-  // 1-norm of the system for the condition estimate
-  std::vector<double> Ah((size_t)NM * NM);
-  RBFL_HIP(hipMemcpyAsync(Ah.data(), d_A2.p, sizeof(double) * Ah.size(), hipMemcpyDeviceToHost, stream));
-  RBFL_HIP(hipStreamSynchronize(stream));
   c.node_values.assign((size_t)c.N * c.K, 0.0);
+  RBFL_HIP(hipStreamSynchronize(stream));
   for (int n = 0; n < c.N; ++n)
     for (int col = 0; col < c.K; ++col) c.node_values[(size_t)n * c.K + col] = Rh[(size_t)col * NM + n];
-  double anorm = 0.0;
-  for (int j = 0; j < NM; ++j) {
-    double s = 0.0;
-    for (int i = 0; i < NM; ++i) s += fabs(Ah[(size_t)j * NM + i]);
-    anorm = std::max(anorm, s);
-  }
-  // unfactored copies of the system and the right-hand side for refinement
-  DevBuf<double> d_A0, d_F, d_res;
+  DevBuf<double> d_A2, d_A0, d_F, d_res;
+  d_A2.alloc((size_t)NM * NM);
   d_A0.alloc((size_t)NM * NM);
-  d_F.alloc((size_t)c.K * NM);
-  d_res.alloc((size_t)c.K * NM);
-  RBFL_HIP(hipMemcpyAsync(d_A0.p, d_A2.p, sizeof(double) * NM * NM, hipMemcpyDeviceToDevice, stream));
-  RBFL_HIP(hipMemcpyAsync(d_F.p, d_R.p, sizeof(double) * c.K * NM, hipMemcpyDeviceToDevice, stream));
   DevBuf<int> d_ipiv;
   d_ipiv.alloc(NM);
-  blas_check(rocsolver_dgetrf(bh.h, NM, NM, d_A2.p, NM, d_ipiv.p, d_info.p), "rocsolver_dgetrf");
-  int info = 0;
-  RBFL_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-  RBFL_HIP(hipStreamSynchronize(stream));
-  if (info != 0) throw Error(RBFL_E_NUMERICAL, "RBF system is singular (zero pivot " + std::to_string(info) + ")");
-  blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_R.p, NM),
-             "rocsolver_dgetrs");
-  // two steps of iterative refinement with double-double residuals: LU alone
-  // leaves a forward error ~ cond(A) * eps; refinement takes W to FP64 rounding
-  for (int it = 0; it < 2; ++it) {
-    launch_residual_dd(d_A0.p, d_F.p, d_R.p, NM, c.K, d_res.p, stream);
-    blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_res.p, NM),
-               "rocsolver_dgetrs");
-    launch_add(d_R.p, d_res.p, (int64_t)c.K * NM, stream);
-  }
-  d_A0.reset();
-  d_F.reset();
-  d_res.reset();
-  // Hager-Higham estimate of ||A^{-1}||_1 from solves with A and A^T
-  {
+  // Hager-Higham estimate of ||A^{-1}||_1 from solves with the LU factors of
+  // A and A^T, times ||A||_1: the 1-norm condition estimate
+  auto cond_estimate = [&](double anorm) {
     DevBuf<double> d_v;
     d_v.alloc(NM);
     std::vector<double> x(NM, 1.0 / NM), y(NM), z(NM);
@@ -1476,8 +1443,55 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
       std::fill(x.begin(), x.end(), 0.0);
       x[jmax] = 1.0;
     }
-    c.cond = anorm * est;
+    return anorm * est;
+  };
+  // the shape parameter: as given, or (eps = 0 in the spec) the smallest
+  // integer from 1 whose system has a 1-norm condition estimate <= kAutoEpsCond
+  const bool auto_eps = !(s->eps > 0.0);
+  c.eps = auto_eps ? 1.0 : s->eps;
+  for (;;) {
+    launch_assemble_system(c.nodes.p, c.N, c.M, d_poly.p, c.eps * c.eps, d_A2.p, stream);
+    std::vector<double> Ah((size_t)NM * NM);
+    RBFL_HIP(hipMemcpyAsync(Ah.data(), d_A2.p, sizeof(double) * Ah.size(), hipMemcpyDeviceToHost, stream));
+    // unfactored copy of the system for the refinement's residuals
+    RBFL_HIP(hipMemcpyAsync(d_A0.p, d_A2.p, sizeof(double) * NM * NM, hipMemcpyDeviceToDevice, stream));
+    RBFL_HIP(hipStreamSynchronize(stream));
+    double anorm = 0.0;
+    for (int j = 0; j < NM; ++j) {
+      double a = 0.0;
+      for (int i = 0; i < NM; ++i) a += fabs(Ah[(size_t)j * NM + i]);
+      anorm = std::max(anorm, a);
+    }
+    blas_check(rocsolver_dgetrf(bh.h, NM, NM, d_A2.p, NM, d_ipiv.p, d_info.p), "rocsolver_dgetrf");
+    int info = 0;
+    RBFL_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    RBFL_HIP(hipStreamSynchronize(stream));
+    const bool last = !auto_eps || c.eps >= kAutoEpsMax;
+    if (info != 0) {
+      if (last) throw Error(RBFL_E_NUMERICAL, "RBF system is singular (zero pivot " + std::to_string(info) + ")");
+      c.eps += 1.0;
+      continue;
+    }
+    c.cond = cond_estimate(anorm);
+    if (last || c.cond <= kAutoEpsCond) break;
+    c.eps += 1.0;
   }
+  d_F.alloc((size_t)c.K * NM);
+  d_res.alloc((size_t)c.K * NM);
+  RBFL_HIP(hipMemcpyAsync(d_F.p, d_R.p, sizeof(double) * c.K * NM, hipMemcpyDeviceToDevice, stream));
+  blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_R.p, NM),
+             "rocsolver_dgetrs");
+  // two steps of iterative refinement with double-double residuals: LU alone
+  // leaves a forward error ~ cond(A) * eps; refinement takes W to FP64 rounding
+  for (int it = 0; it < 2; ++it) {
+    launch_residual_dd(d_A0.p, d_F.p, d_R.p, NM, c.K, d_res.p, stream);
+    blas_check(rocsolver_dgetrs(bh.h, rocblas_operation_none, NM, c.K, d_A2.p, NM, d_ipiv.p, d_res.p, NM),
+               "rocsolver_dgetrs");
+    launch_add(d_R.p, d_res.p, (int64_t)c.K * NM, stream);
+  }
+  d_A0.reset();
+  d_F.reset();
+  d_res.reset();
   c.W.alloc((size_t)c.rows * c.Kp);
   launch_transpose_weights(d_R.p, NM, c.K, c.rows, c.Kp, c.W.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
@@ -1622,6 +1636,7 @@ static void reserve(Ctx &c, int64_t n) {
   }
   if (c.sur) {
     c.sur_x.alloc((size_t)n * 4);
+    if (c.sur_nbase) c.sur_U.alloc((size_t)n * c.sur_nbase);
     c.sur->reserve(n);
   }
 }
@@ -1821,8 +1836,12 @@ static void contract(Ctx &c, const double *params, int64_t ld, int64_t b0, int64
     case RBFL_FORM_SURROGATE:
       if (c.sur && c.sur_ok) {
         launch_sur_inputs(params, ld, b0, nb, c.consts.p, c.sur_x.p, s);
+        if (c.sur_nbase)
+          launch_sur_base_inputs(params, ld, b0, nb, c.consts.p, c.sur_ms_d.p, c.sur_poly.p, c.sur_nbase, c.sur_U.p,
+                                 s);
         mark(1);
-        c.sur->infer(c.sur_x.p, nb, c.sur_mu.p, c.sur_sd.p, c.Y.p, c.Kp, s);
+        c.sur->infer(c.sur_x.p, nb, c.sur_mu.p, c.sur_sd.p, c.Y.p, c.Kp, s, c.sur_nbase ? c.sur_U.p : nullptr,
+                     c.sur_nbase ? c.sur_B.p : nullptr, c.sur_nbase);
       } else {
         fp64();
       }
@@ -2056,6 +2075,108 @@ static void prepare(Ctx &c, int form) {
   c.prepared[RBFL_FORM_FP32] = true;
 }
 
+// Residual form of the surrogate: the least-squares polynomial of degree
+// `degree` (all monomials, graded-lexicographic) in the training proposals'
+// standardised coordinates u = (x - m) / s, x = delta_e / a, fitted to every
+// output column in FP64 (normal equations P^T P B = P^T Y by FP64 products on
+// the GPU, Cholesky on the host), kept in the handle, and subtracted from the
+// targets Y [n][K] in place.
+static void fit_surrogate_base(Ctx &c, const double *train_params, int64_t n, int degree, double *Y, hipStream_t s) {
+  std::vector<double> xh((size_t)4 * n);
+  RBFL_HIP(hipMemcpyAsync(xh.data(), train_params, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  double m[4], sd[4];
+  for (int d = 0; d < 4; ++d) {
+    Sum a;
+    for (int64_t i = 0; i < n; ++i) a.add(xh[(size_t)d * n + i] / c.semi[d]);
+    m[d] = a.value() / (double)n;
+    Sum v;
+    for (int64_t i = 0; i < n; ++i) {
+      const double e = xh[(size_t)d * n + i] / c.semi[d] - m[d];
+      v.add(e * e);
+    }
+    sd[d] = sqrt(v.value() / (double)n);
+    if (!(sd[d] > 0.0)) sd[d] = 1.0;
+  }
+  int poly[kMaxPoly][3];
+  const int nb = monomials(degree, poly);
+  std::vector<double> P((size_t)n * nb);
+  for (int64_t i = 0; i < n; ++i) {
+    double u[4];
+    for (int d = 0; d < 4; ++d) u[d] = (xh[(size_t)d * n + i] / c.semi[d] - m[d]) / sd[d];
+    for (int p = 0; p < nb; ++p) {
+      double v = 1.0;
+      for (int t = 0; t < 3; ++t)
+        if (poly[p][t] >= 0) v *= u[poly[p][t]];
+      P[(size_t)i * nb + p] = v;
+    }
+  }
+  DevBuf<double> dP, dG, dR;
+  dP.alloc(P.size());
+  dG.alloc((size_t)nb * nb);
+  dR.alloc((size_t)nb * c.K);
+  RBFL_HIP(hipMemcpyAsync(dP.p, P.data(), sizeof(double) * P.size(), hipMemcpyHostToDevice, s));
+  BlasHandle bh;
+  blas_check(rocblas_set_stream(bh.h, s), "rocblas_set_stream");
+  // column-major views: P^T is nb x n (ld nb), Y^T is K x n (ld K)
+  const double one = 1.0, zero = 0.0, minus = -1.0;
+  blas_check(rocblas_dgemm(bh.h, rocblas_operation_none, rocblas_operation_transpose, nb, nb, (int)n, &one, dP.p, nb,
+                           dP.p, nb, &zero, dG.p, nb),
+             "rocblas_dgemm (P^T P)");
+  blas_check(rocblas_dgemm(bh.h, rocblas_operation_none, rocblas_operation_transpose, nb, c.K, (int)n, &one, dP.p, nb,
+                           Y, c.K, &zero, dR.p, nb),
+             "rocblas_dgemm (P^T Y)");
+  std::vector<double> G((size_t)nb * nb), R((size_t)nb * c.K);
+  RBFL_HIP(hipMemcpyAsync(G.data(), dG.p, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipMemcpyAsync(R.data(), dR.p, sizeof(double) * R.size(), hipMemcpyDeviceToHost, s));
+  RBFL_HIP(hipStreamSynchronize(s));
+  // Cholesky G = L L^T (G symmetric positive definite for distinct proposals)
+  std::vector<double> L((size_t)nb * nb, 0.0);
+  for (int j = 0; j < nb; ++j) {
+    double d = G[(size_t)j * nb + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * nb + k] * L[(size_t)j * nb + k];
+    if (!(d > 0.0)) throw Error(RBFL_E_NUMERICAL, "surrogate base: the monomials of the training proposals are degenerate");
+    L[(size_t)j * nb + j] = sqrt(d);
+    for (int i = j + 1; i < nb; ++i) {
+      double v = G[(size_t)i * nb + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * nb + k] * L[(size_t)j * nb + k];
+      L[(size_t)i * nb + j] = v / L[(size_t)j * nb + j];
+    }
+  }
+  // B [nb][K] row-major: column k solves G b = R[:, k]
+  std::vector<double> B((size_t)nb * c.K), y(nb);
+  for (int k = 0; k < c.K; ++k) {
+    for (int i = 0; i < nb; ++i) {
+      double v = R[(size_t)k * nb + i];
+      for (int t = 0; t < i; ++t) v -= L[(size_t)i * nb + t] * y[t];
+      y[i] = v / L[(size_t)i * nb + i];
+    }
+    for (int i = nb - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int t = i + 1; t < nb; ++t) v -= L[(size_t)t * nb + i] * B[(size_t)t * c.K + k];
+      B[(size_t)i * c.K + k] = v / L[(size_t)i * nb + i];
+    }
+  }
+  c.sur_B.alloc(B.size());
+  RBFL_HIP(hipMemcpyAsync(c.sur_B.p, B.data(), sizeof(double) * B.size(), hipMemcpyHostToDevice, s));
+  // Y^T (K x n) -= B^T (K x nb, ld K) P^T (nb x n, ld nb)
+  blas_check(rocblas_dgemm(bh.h, rocblas_operation_none, rocblas_operation_none, c.K, (int)n, nb, &minus, c.sur_B.p,
+                           c.K, dP.p, nb, &one, Y, c.K),
+             "rocblas_dgemm (Y - P B)");
+  for (int d = 0; d < 4; ++d) {
+    c.sur_ms[d] = m[d];
+    c.sur_ms[4 + d] = sd[d];
+  }
+  c.sur_ms_d.alloc(8);
+  RBFL_HIP(hipMemcpyAsync(c.sur_ms_d.p, c.sur_ms, sizeof(c.sur_ms), hipMemcpyHostToDevice, s));
+  c.sur_poly.alloc(kMaxPoly * 3);
+  RBFL_HIP(hipMemcpyAsync(c.sur_poly.p, poly, sizeof(poly), hipMemcpyHostToDevice, s));
+  c.sur_U.alloc((size_t)c.cap * nb);
+  RBFL_HIP(hipStreamSynchronize(s));
+  c.sur_degree = degree;
+  c.sur_nbase = nb;
+}
+
 static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
   if (c.graph_users > 0) throw Error(RBFL_E_STATE, "a sampler holds this handle's buffers: train before creating it");
   require(sp != nullptr, "spec is NULL");
@@ -2068,20 +2189,27 @@ static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
   require(std::isfinite(sp->lr) && sp->lr > 0 && sp->beta1 >= 0 && sp->beta1 < 1 && sp->beta2 >= 0 &&
               sp->beta2 < 1 && sp->adam_eps > 0 && sp->threshold > 0,
           "Adam settings / threshold");
+  require(sp->base_degree >= 0 && sp->base_degree <= 3, "base_degree must be 0 .. 3");
   const auto t0 = Clock::now();
   delete c.sur;
   c.sur = nullptr;
   c.sur_ok = false;
   c.sur = new Mlp();
   c.sur->init(4, sp->hidden, c.K, sp->init_normals);
+  c.sur_degree = 0;
+  c.sur_nbase = 0;
+  c.sur_B.reset();
+  c.sur_U.reset();
   if (c.cap == 0) reserve(c, 65536);
   c.sur_x.alloc((size_t)c.cap * 4);
   c.sur->reserve(std::max<int64_t>(c.cap, sp->batch));
-  // targets: the FP64 interpolant at the training proposals, standardised per column
+  // targets: the FP64 interpolant at the training proposals (minus the
+  // least-squares polynomial base in the residual form), standardised per column
   const int64_t n = sp->n_train;
   DevBuf<double> Ytr;
   Ytr.alloc((size_t)n * c.K);
   interp(c, sp->train_params, n, Ytr.p, RBFL_FORM_FP64, s);
+  if (sp->base_degree > 0) fit_surrogate_base(c, sp->train_params, n, sp->base_degree, Ytr.p, s);
   c.sur_mu.alloc(c.K);
   c.sur_sd.alloc(c.K);
   launch_col_stats(Ytr.p, n, c.K, c.sur_mu.p, c.sur_sd.p, s);
@@ -2169,6 +2297,9 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_D_REF:
       copy_out(out, bytes, &c.d_ref, sizeof(double));
       return;
+    case RBFL_Q_EPS:
+      copy_out(out, bytes, &c.eps, sizeof(double));
+      return;
     case RBFL_Q_F_REF:
       copy_out(out, bytes, &c.f_ref, sizeof(double));
       return;
@@ -2243,6 +2374,19 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_SPLIT_ERR:
       copy_out(out, bytes, c.split_err, sizeof(c.split_err));
       return;
+    case RBFL_Q_SURROGATE_BASE: {
+      if (!c.sur) throw Error(RBFL_E_STATE, "no surrogate trained on this handle");
+      std::vector<double> v(10 + (size_t)c.sur_nbase * c.K, 0.0);
+      v[0] = c.sur_degree;
+      v[1] = c.sur_nbase;
+      for (int i = 0; i < 8; ++i) v[2 + i] = c.sur_ms[i];
+      if (c.sur_nbase) {
+        RBFL_HIP(hipDeviceSynchronize());
+        RBFL_HIP(hipMemcpy(v.data() + 10, c.sur_B.p, sizeof(double) * c.sur_nbase * c.K, hipMemcpyDeviceToHost));
+      }
+      copy_out(out, bytes, v.data(), sizeof(double) * v.size());
+      return;
+    }
     case RBFL_Q_SPLIT_STATE: {
       double v[3] = {c.split_tuned ? 1.0 : 0.0, c.split_ok ? 1.0 : 0.0,
                      (double)split_variant_slices(c.variant[RBFL_FORM_SPLIT])};

@@ -18,6 +18,8 @@ constexpr int kMaxPoly = 35;     // monomials of degree <= 3 in 4 variables
 constexpr int kSplineTaps = 10;  // samples in the sub-sample spline stencil
 constexpr int kRowChunk = 32;    // W rows padded to a multiple of this (every row step divides it)
 constexpr int kColTile = 128;    // widest contraction column tile; K is padded to a multiple of it
+constexpr double kAutoEpsCond = 1e12;   // automatic shape parameter: largest accepted 1-norm condition
+constexpr double kAutoEpsMax = 8.0;     // ... and the largest integer shape parameter tried
 
 // Error carrying an rbfl_status through the host code; converted at the ABI.
 struct Error : std::runtime_error {
@@ -140,7 +142,9 @@ struct Mlp {
   // inference into the interpolant's output layout: Y[b][c] = mu[c] + sd[c] y[b][c]
   // in FP64 (row stride ldy) for c < out, y as forward() computes it; no
   // pre-activations stored
-  void infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s);
+  // (residual form: plus the FP64 base sum_j Ub[b][j] Bb[j][c], Bb [nbase][out])
+  void infer(const float *X, int64_t B, const float *mu, const float *sd, double *Y, int64_t ldy, hipStream_t s,
+             const double *Ub = nullptr, const double *Bb = nullptr, int nbase = 0);
   void loss_grad(const float *X, const float *T, int64_t B, hipStream_t s);   // loss -> this->loss
   void adam(double lr, double b1, double b2, double eps, hipStream_t s);
 };
@@ -220,6 +224,14 @@ struct Ctx {
   DevBuf<float> sur_mu, sur_sd;       // per-column standardisation of the outputs
   DevBuf<float> sur_x;                // work space [cap][4]
   bool sur_ok = false;                // held-out check passed
+  // residual form: FP64 least-squares polynomial base of degree sur_degree in
+  // the training set's standardised coordinates u = (x - m) / s
+  int sur_degree = 0, sur_nbase = 0;
+  double sur_ms[8] = {};              // m[4], s[4]
+  DevBuf<double> sur_ms_d;            // the same on the device
+  DevBuf<int> sur_poly;               // [kMaxPoly][3] variable indices of the base monomials
+  DevBuf<double> sur_B;               // [nbase][K] base coefficients
+  DevBuf<double> sur_U;               // work space [cap][nbase] monomials of a chunk
   double sur_stats[8] = {};
   // optional per-launch timing (rbfl_profile)
   bool profile = false;
@@ -350,6 +362,11 @@ void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const doub
 // part[b] = number of NaN entries of lnl[0, n) in block b's grid-stride share
 // (kNanParts blocks; every slot is written, so no clearing is needed).
 void launch_count_nan(const double *lnl, int64_t n, unsigned long long *part, hipStream_t s);
+// The nbase monomials (graded-lexicographic, variable indices poly[p][0..2],
+// -1 unused) of u = (x - ms[0..3]) / ms[4..7], x = delta_e / a, in FP64:
+// U[b][p] for proposals b0 .. b0 + nb - 1.
+void launch_sur_base_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c,
+                            const double *ms, const int *poly, int nbase, double *U, hipStream_t s);
 void launch_sur_inputs(const double *params, int64_t ld, int64_t b0, int64_t nb, const EvalConsts *c, float *x,
                        hipStream_t s);
 void launch_col_stats(const double *Y, int64_t n, int K, float *mu, float *sd, hipStream_t s);

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAX_MODES = 5
 MAX_DET = 4
 
@@ -27,7 +27,7 @@ FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
-    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT = range(23)
+    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT, Q_SURROGATE_BASE, Q_EPS = range(25)
 SPLIT_TOL = 1e-4
 STATIC_SCRATCH_BYTES = 128 << 20
 
@@ -111,6 +111,7 @@ class TrainSpec(C.Structure):
         ("holdout_params", C.c_void_p),
         ("n_holdout", C.c_int64),
         ("threshold", C.c_double),
+        ("base_degree", C.c_int32),
     ]
 
 
@@ -431,6 +432,10 @@ class Handle:
     def cond(self) -> float:
         return float(self._query(Q_COND, 1)[0])
 
+    def eps(self) -> float:
+        """The interpolants' Gaussian shape parameter (RBFL_Q_EPS; chosen by the library when the spec's is 0)."""
+        return float(self._query(Q_EPS, 1)[0])
+
     def exports(self) -> dict:
         """Every artefact the online stage evaluates with, as host arrays (the
         keyword arguments of an evaluation-parity check): frame, nodes, RBF
@@ -439,7 +444,7 @@ class Handle:
         return {"theta_c": fr["theta_c"], "metric_g": fr["metric"], "vecs": fr["vecs"], "lam": fr["lam"],
                 "semi": fr["semi"], "x_nodes": self.nodes(), "phys_nodes": self.node_phys(), "W": self.weights(),
                 "basis": self.basis(), "half_w": self.sizes()["half_w"], "d_ref": self.d_ref(),
-                "f_ref": self.f_ref(), "cond": self.cond(), "singular": self.singular(),
+                "f_ref": self.f_ref(), "eps": self.eps(), "cond": self.cond(), "singular": self.singular(),
                 "node_values": self.node_values()}
 
     def timing(self) -> np.ndarray:
@@ -457,10 +462,10 @@ class Handle:
     def surrogate_train(self, init_normals: np.ndarray, train_ptr: int, n_train: int, holdout_ptr: int,
                         n_holdout: int, hidden: int = 256, batch: int = 1024, epochs: int = 20, lr: float = 1e-3,
                         beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8,
-                        threshold: float = 1e-3, stream: int = 0) -> dict:
+                        threshold: float = 1e-3, stream: int = 0, base_degree: int = 0) -> dict:
         z = np.ascontiguousarray(init_normals, dtype=np.float64)
         sp = TrainSpec(hidden, batch, epochs, lr, beta1, beta2, adam_eps, _dptr(z), C.c_void_p(train_ptr), n_train,
-                       C.c_void_p(holdout_ptr), n_holdout, threshold)
+                       C.c_void_p(holdout_ptr), n_holdout, threshold, base_degree)
         _check(load().rbfl_surrogate_train(self._h, C.byref(sp), C.c_void_p(stream)))
         return self.surrogate_stats()
 
@@ -481,6 +486,16 @@ class Handle:
         n = mlp_param_count(4, hidden, K)
         v = self._query(Q_SURROGATE_NET, n + 2 * K, np.float32)
         return v[:n].copy(), v[n:n + K].copy(), v[n + K:].copy()
+
+    def surrogate_base(self) -> dict:
+        """The residual form's FP64 base (RBFL_Q_SURROGATE_BASE): degree, per-axis mean m and deviation s
+        of the training proposals' unit-ball coordinates, coefficients [nbase][K] (None without a base)."""
+        K = self.sizes()["K"]
+        v = np.zeros(10 + 35 * K)               # room for the largest base (35 monomials of degree <= 3)
+        _check(load().rbfl_query(self._h, Q_SURROGATE_BASE, v.ctypes.data_as(C.c_void_p), v.nbytes))
+        nbase = int(v[1])
+        return {"degree": int(v[0]), "nbase": nbase, "m": v[2:6].copy(), "s": v[6:10].copy(),
+                "B": v[10:10 + nbase * K].reshape(nbase, K).copy() if nbase else None}
 
     def set_variant(self, form: int, variant: int):
         """Pins the contraction tile variant of `form` (rbfl_set_variant)."""

@@ -275,7 +275,7 @@ def ragged_events(n_events: int = 64, seed: int = 3, walkers: int = 1024,
         f_low = 20.0
         while (5.0 / 256.0) * (math.pi * f_low) ** (-8.0 / 3.0) * mc ** (-5.0 / 3.0) > 0.9 * seg:
             f_low += 1.0
-        eps = 1.0 if n_nodes <= 800 else 2.0
+        eps = 0.0       # chosen by each side from its RBF system (smallest integer with cond <= 1e12)
         out.append(base.with_(name=f"event{e:02d}", seg_len=seg, f_low=f_low,
                               modes=ALL_MODES[:n_modes], inj_phys=(m1, m2, c1, c2),
                               n_nodes=n_nodes, q=q, eps=eps, n_queries=walkers,

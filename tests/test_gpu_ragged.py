@@ -32,6 +32,8 @@ def events():
             inj = wl.injection_extrinsics(cfg)
             hs.append(rbfl.Handle.from_config(cfg, white, inj))
             arts.append(su.startup(cfg, white, inj, workers=1))
+            # the events leave eps open: both sides pick the smallest integer keeping cond <= 1e12
+            assert hs[-1].eps() == arts[-1].eps, f"{cfg.name}: eps {hs[-1].eps()} vs oracle {arts[-1].eps}"
         _state["h"], _state["art"] = hs, arts
     return _state["h"], _state["art"]
 

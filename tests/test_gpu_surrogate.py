@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as omlp
+from oracle import startup as su
 from paper_2508_04172_amd import rbfl
 from paper_2508_04172_amd import workloads as wl
 
@@ -98,45 +99,102 @@ def test_training_judge_and_fallback():
     assert d.max() > 0.0
 
 
-def test_surrogate_gain_over_interpolant():
-    """Throughput of the network path against the FP64 interpolant it
-    replaces, on the same proposals (accuracy is what the judge reports)."""
+def _timed_evals_per_s(torch, h, p, n, form, reps=5):
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.eval(p.data_ptr(), n, out.data_ptr(), form)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        h.eval(p.data_ptr(), n, out.data_ptr(), form)
+    torch.cuda.synchronize()
+    return n * reps / (time.perf_counter() - t), out
+
+
+@pytest.mark.timeout(900)
+def test_surrogate_gain_at_the_bar():
+    """What the trained network gains over the interpolant at the 1e-3 bar.
+
+    Single-detector workload (K = 41 interpolated reals), the network
+    4 -> 256 -> 256 -> K trained on 2e5 proposals of a converged sampler's
+    region (Gaussian of width 0.05 about the centre) and judged on 1e4
+    held-out proposals of the same region, plain and in the residual form
+    (FP64 cubic least-squares base plus the network on the standardised
+    residual).  Asserted: the judge applies the bar (its maximum equals the
+    one recomputed here through the forced network path, and it accepts
+    exactly when that maximum is <= 1e-3); a rejected surrogate leaves the
+    interpolant's ln L bit for bit; an accepted one stays within 1e-3 on
+    fresh proposals of the region.  Reported: the held-out errors of both
+    variants and the network path's evals/s against the FP64 form (here
+    neither variant reaches the bar: the held-out maximum stays at a few
+    units of ln L, and the network path is slower than the K = 41
+    contraction it would replace)."""
     torch = _torch()
-    cfg = wl.SMALL_MULTI.with_(n_nodes=400)
+    cfg = wl.CFG1
     h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
     K = h.sizes()["K"]
-    z = wl.mlp_normals(rbfl.mlp_param_count(4, 64, K))
-    tr = _params_device(torch, h, cfg, 8192, seed=5)
-    ho = _params_device(torch, h, cfg, 2048, seed=6)
-    st = h.surrogate_train(z, tr.data_ptr(), 8192, ho.data_ptr(), 2048, hidden=64, batch=512, epochs=5,
-                           threshold=1e12)
-    assert st["accepted"]
-    n = 262144
-    p = _params_device(torch, h, cfg, n, seed=8)
-    out = torch.empty(n, dtype=torch.float64, device="cuda")
-    times = {}
-    for name, form in (("fp64", rbfl.FORM_FP64), ("surrogate", rbfl.FORM_SURROGATE)):
-        h.eval(p.data_ptr(), n, out.data_ptr(), form)
+    hidden = 256
+    z = wl.mlp_normals(rbfl.mlp_param_count(4, hidden, K))
+
+    def region(n, seed):
+        qd = wl.queries(cfg, n=n, seed=seed, clustered=0.05)
+        return torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))).cuda()
+
+    tr, ho, fresh = region(200000, 5), region(10000, 6), region(262144, 8)
+    results = {}
+    for degree in (0, 3):
+        st = h.surrogate_train(z, tr.data_ptr(), 200000, ho.data_ptr(), 10000, hidden=hidden, batch=1024,
+                               epochs=20, lr=1e-3, threshold=1e-3, base_degree=degree)
+        base = h.surrogate_base()
+        assert base["degree"] == degree and (base["nbase"] == 35) == (degree == 3)
+        n_ho = 10000
+        lf = torch.empty(n_ho, dtype=torch.float64, device="cuda")
+        ls = torch.empty(n_ho, dtype=torch.float64, device="cuda")
+        h.eval(ho.data_ptr(), n_ho, lf.data_ptr(), rbfl.FORM_FP64)
+        h.eval(ho.data_ptr(), n_ho, ls.data_ptr(), rbfl.FORM_SURROGATE)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(5):
-            h.eval(p.data_ptr(), n, out.data_ptr(), form)
+        a, b = lf.cpu().numpy(), ls.cpu().numpy()
+        if not st["accepted"]:
+            assert np.array_equal(np.isfinite(a), np.isfinite(b))
+            fin = np.isfinite(a)
+            assert np.array_equal(a[fin], b[fin]), "a rejected surrogate must leave the interpolant's ln L"
+        h.surrogate_force(True)
+        net_rate, _ = _timed_evals_per_s(torch, h, fresh, 262144, rbfl.FORM_SURROGATE)
+        h.eval(ho.data_ptr(), n_ho, ls.data_ptr(), rbfl.FORM_SURROGATE)
         torch.cuda.synchronize()
-        times[name] = (time.perf_counter() - t) / 5
-    print(f"[surrogate] evals/s fp64 {n / times['fp64']:.3e}, surrogate {n / times['surrogate']:.3e}, "
-          f"held-out max |dlnL| {st['holdout_max_dlnl']:.3e}", flush=True)
-    assert np.isfinite(times["surrogate"])
+        h.surrogate_force(False)
+        b = ls.cpu().numpy()
+        fin = np.isfinite(a) & np.isfinite(b)
+        d = np.abs(a[fin] - b[fin])
+        assert d.max() == pytest.approx(st["holdout_max_dlnl"], rel=1e-9)
+        assert st["accepted"] == bool(np.array_equal(np.isfinite(a), np.isfinite(b)) and d.max() <= 1e-3)
+        if st["accepted"]:
+            out_f = torch.empty(262144, dtype=torch.float64, device="cuda")
+            h.eval(fresh.data_ptr(), 262144, out_f.data_ptr(), rbfl.FORM_FP64)
+            _, out_s = _timed_evals_per_s(torch, h, fresh, 262144, rbfl.FORM_SURROGATE, reps=1)
+            x, y = out_f.cpu().numpy(), out_s.cpu().numpy()
+            f2 = np.isfinite(x)
+            assert np.array_equal(f2, np.isfinite(y)) and np.abs(x[f2] - y[f2]).max() <= 1e-3
+        results[degree] = (st, net_rate)
+    fp64_rate, _ = _timed_evals_per_s(torch, h, fresh, 262144, rbfl.FORM_FP64)
+    for degree, (st, rate) in results.items():
+        print(f"[surrogate] single-detector, converged region, base degree {degree}: accepted {st['accepted']}, "
+              f"held-out max |dlnL| {st['holdout_max_dlnl']:.3e}, median {st['holdout_median_dlnl']:.3e}, "
+              f"loss {st['first_loss']:.3e} -> {st['last_loss']:.3e}; network path {rate:.3e} evals/s "
+              f"against the FP64 form's {fp64_rate:.3e}", flush=True)
+    h.close()
 
 
-@pytest.mark.parametrize("hidden", [64, 40])
-def test_surrogate_outputs_match_oracle_network(hidden):
+@pytest.mark.parametrize("hidden,degree", [(64, 0), (40, 0), (64, 2), (40, 3)])
+def test_surrogate_outputs_match_oracle_network(hidden, degree):
     """The surrogate form's interpolated quantities (rbfl_interp) against the
     oracle network evaluated in FP64 on the trained FP32 parameters and the
-    stored output standardisation, out = mean + sd * y.  Width 64 takes the
-    inference path whose last layer writes the FP64 outputs itself; width 40
-    (not a multiple of 16) the generic layer and a separate conversion.  The
-    network inputs are the unit-ball coordinates Delta e / a (the library
-    rounds them to FP32, so the oracle is fed the same rounding)."""
+    stored output standardisation, out = mean + sd * y (+ the residual form's
+    FP64 base, evaluated here from the exported coefficients with the
+    oracle's own monomials).  Width 64 takes the inference path whose last
+    layer writes the FP64 outputs itself; width 40 (not a multiple of 16) the
+    generic layer and a separate conversion.  The network inputs are the
+    unit-ball coordinates Delta e / a (the library rounds them to FP32, so the
+    oracle is fed the same rounding; the base takes them in FP64)."""
     torch = _torch()
     cfg = wl.SMALL_MULTI
     h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
@@ -145,9 +203,10 @@ def test_surrogate_outputs_match_oracle_network(hidden):
     tr = _params_device(torch, h, cfg, 8192, seed=5)
     ho = _params_device(torch, h, cfg, 2048, seed=6)
     st = h.surrogate_train(z, tr.data_ptr(), 8192, ho.data_ptr(), 2048, hidden=hidden, batch=512, epochs=3,
-                           lr=3e-3, threshold=1e12)
+                           lr=3e-3, threshold=1e12, base_degree=degree)
     assert st["accepted"]
     vec, mu, sd = h.surrogate_net(hidden)
+    base = h.surrogate_base()
     n = 1000                                   # ragged against the 128-row tiles
     p = _params_device(torch, h, cfg, n, seed=9)
     out = torch.empty((n, K), dtype=torch.float64, device="cuda")
@@ -156,9 +215,15 @@ def test_surrogate_outputs_match_oracle_network(hidden):
     got = out.cpu().numpy()
     semi = h.frame()["semi"]
     pc = p.cpu().numpy()
-    X = (pc[:4] / semi[:, None]).T.astype(np.float32).astype(np.float64)
+    x64 = (pc[:4] / semi[:, None]).T
+    X = x64.astype(np.float32).astype(np.float64)
     y, _ = omlp.forward(vec.astype(np.float64), X, 4, hidden, K)
     want = mu.astype(np.float64) + sd.astype(np.float64) * y
+    if degree:
+        assert base["nbase"] == len(su.monomial_exponents(degree))
+        want = want + su.poly_matrix((x64 - base["m"]) / base["s"], degree) @ base["B"]
+    else:
+        assert base["nbase"] == 0
     err = np.abs(got - want) / (sd.astype(np.float64) * (1.0 + np.abs(y)))
     print(f"[surrogate] width {hidden}: max scaled |out - oracle| {err.max():.3e}", flush=True)
     assert np.isfinite(got).all()

@@ -663,3 +663,16 @@ def test_artefacts_from_exports_evaluate_like_the_originals(multi_art):
     b = lk.meshfree_lnl(rebuilt, *lk.query_params(rebuilt, qd))
     assert np.isfinite(a).sum() > 0
     assert np.array_equal(a, b)
+
+
+def test_choose_eps_is_the_smallest_integer_under_the_condition_bar(tiny_art):
+    """The automatic shape parameter (a workload with eps = 0): the chosen
+    integer's system has a 1-norm condition number <= the bar and the next
+    smaller integer's does not (or it is 1); a looser bar never picks more."""
+    x = tiny_art.x_nodes
+    for bar in (1e6, 1e9, 1e12):
+        eps = su.choose_eps(x, 1, cond_max=bar)
+        assert np.linalg.cond(su.rbf_system(x, eps, 1), 1) <= bar or eps == 8
+        if eps > 1:
+            assert np.linalg.cond(su.rbf_system(x, eps - 1, 1), 1) > bar
+    assert su.choose_eps(x, 1, cond_max=1e12) <= su.choose_eps(x, 1, cond_max=1e6)
