@@ -66,6 +66,68 @@ def combine(A: np.ndarray, z: np.ndarray, sigma: np.ndarray, r) -> np.ndarray:
     return r * zt - 0.5 * r * r * st
 
 
+def band_overlap(a: np.ndarray, b: np.ndarray, psd: np.ndarray, grid, j0: int, j1: int) -> complex:
+    """(a|b) over the bins j0 .. j1 - 1 only."""
+    sl = slice(j0, j1)
+    return complex(4.0 * grid.df * np.sum(np.conj(a[sl]) * b[sl] / psd[sl]))
+
+
+def band_alpha(ev: Event, alpha, t_c, t_band):
+    """Right ascension as the rotating Earth sees it at time t_c + t_band:
+    alpha - rate (t_c + t_band - t_trig) (the Earth-fixed frame is taken at
+    the trigger time, as in the exact rotating-Earth likelihood)."""
+    return alpha - ev.earth_rate * (t_c + t_band - ev.t_trig)
+
+
+def banded_signal(ev: Event, phys, ext, t_c: float, d_l: float, bands, k: int) -> np.ndarray:
+    """The signal the time-banded form models in detector k: in band b every
+    mode a takes its antenna factor and delay at its band time t_ba
+    (startup.time_bands), sum_a A_a(t_ba) h_a(f) e^{-2 pi i f (t_c + dt(t_ba))}."""
+    edges, times = bands
+    alpha, dec, psi, iota, phi = ext
+    out = np.zeros(ev.grid.n_f, dtype=np.complex128)
+    for a, (l, m) in enumerate(ev.modes):
+        h = ph.waveform_mode(ev.grid, l, m, phys, d_l)
+        for b in range(len(edges) - 1):
+            sl = slice(edges[b], edges[b + 1])
+            al = band_alpha(ev, alpha, t_c, times[b, a])
+            fp, fc = ph.antenna_pattern(ev.det_tensor[k], al, dec, psi)
+            tau = t_c + ph.time_delay(ev.det_pos[k], al, dec)
+            out[sl] += ph.mode_factor(l, m, fp, fc, iota, phi) * h[sl] * ph.shift_factor(ev.grid, tau)[sl]
+    return out
+
+
+def factorised_lnl_banded(ev: Event, phys, ext, t_c: float, d_l: float, bands) -> float:
+    """Eq. logl_complete (corrected reading) with time-banded antenna
+    patterns, z and sigma computed exactly over each band's bins: block
+    (detector k, band b) is the frozen-pattern form over the band with mode
+    a's factor A_ba and delay at its band time.  The overlaps carry no delay,
+    so the cross terms between modes drop the phase 2 pi f (dt_ba - dt_bc)
+    their delays would give them (the one approximation beyond
+    banded_signal: with a single mode the two agree exactly)."""
+    edges, times = bands
+    alpha, dec, psi, iota, phi = ext
+    r = ev.d_inj / d_l
+    hs = [ph.waveform_mode(ev.grid, l, m, phys, ev.d_inj) for (l, m) in ev.modes]
+    n = len(hs)
+    total = 0.0
+    for k in range(ev.n_det):
+        for b in range(len(edges) - 1):
+            A = np.zeros(n, dtype=np.complex128)
+            z = np.zeros(n, dtype=np.complex128)
+            for a, (l, m) in enumerate(ev.modes):
+                al = band_alpha(ev, alpha, t_c, times[b, a])
+                fp, fc = ph.antenna_pattern(ev.det_tensor[k], al, dec, psi)
+                tau = t_c + ph.time_delay(ev.det_pos[k], al, dec)
+                A[a] = ph.mode_factor(l, m, fp, fc, iota, phi)
+                z[a] = band_overlap(hs[a] * ph.shift_factor(ev.grid, tau), ev.data[k], ev.psd[k], ev.grid,
+                                    edges[b], edges[b + 1])
+            sig = np.array([[band_overlap(hs[i], hs[j], ev.psd[k], ev.grid, edges[b], edges[b + 1])
+                             for j in range(n)] for i in range(n)])
+            total += float(combine(A, z, sig, r))
+    return total
+
+
 def factorised_lnl(ev: Event, phys, ext, t_c: float, d_l: float) -> float:
     """Eq. logl_complete (corrected reading) with z and sigma computed exactly."""
     alpha, dec, psi, iota, phi = ext
@@ -159,12 +221,29 @@ def domain(art: Artefacts, x: np.ndarray) -> np.ndarray:
     return inside & ok
 
 
+def virtual_detectors(art: Artefacts, alpha, t_c):
+    """The blocks of interpolated outputs, each with its detector and the
+    right ascension every mode sees there: without time bands block k is
+    detector k with the source's alpha for all modes (patterns frozen,
+    Sec. II B); with B time bands block v = k B + b is detector k over band
+    b, mode a at band_alpha(alpha, t_c, t_ba).  Returns [(detector,
+    [alpha per mode])]."""
+    ev = art.ev
+    n_modes = len(ev.modes)
+    if art.bands is None:
+        return [(k, [alpha] * n_modes) for k in range(ev.n_det)]
+    times = art.bands[1]
+    return [(k, [band_alpha(ev, alpha, t_c, times[b, a]) for a in range(n_modes)])
+            for k in range(ev.n_det) for b in range(times.shape[0])]
+
+
 def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np.ndarray, d_l: np.ndarray,
                    Y: np.ndarray | None = None):
     """Online stage for a batch.  delta_e: [n][4] displacement along the
     eigen-axes; ext: [n][5] (alpha, dec, psi, iota, phi); t_c, d_l: [n].
     Returns (ln L [n] with -inf outside the domain or the time window,
-    z [n][n_det][n_modes], sigma [n][n_det][n][n], valid mask)."""
+    z [n][n_v][n_modes], sigma [n][n_v][n][n], valid mask), n_v the
+    detectors or, with time bands, the (detector, band) blocks."""
     ev = art.ev
     x = delta_e / art.frame.semi[None, :]
     n_q = x.shape[0]
@@ -172,26 +251,30 @@ def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np
     if Y is None:
         Y = rbf_eval(art, x)
     n_modes = len(ev.modes)
-    K, coef_off, sig_off = output_layout(ev.n_det, n_modes, art.q)
+    alpha, dec, psi, iota, phi = (ext[:, i] for i in range(5))
+    blocks = virtual_detectors(art, alpha, t_c)
+    K, coef_off, sig_off = output_layout(len(blocks), n_modes, art.q)
     tab = spline_table()
     T = art.basis.shape[2]
     r = art.d_ref / d_l
-    alpha, dec, psi, iota, phi = (ext[:, i] for i in range(5))
     lnl = np.zeros(n_q)
-    zs = np.zeros((n_q, ev.n_det, n_modes), dtype=np.complex128)
-    sigs = np.zeros((n_q, ev.n_det, n_modes, n_modes), dtype=np.complex128)
-    for k in range(ev.n_det):
-        fp, fc = antenna_patterns(ev.det_tensor[k], alpha, dec, psi)
-        s = (t_c + time_delays(ev.det_pos[k], alpha, dec) - ev.t_trig) * ev.grid.fs + art.half_w
-        n0 = np.floor(s)
-        f = s - n0
-        n0 = n0.astype(np.int64)
-        ok = (n0 >= 4) & (n0 <= T - 6)
-        valid &= ok
-        n0c = np.where(ok, n0, 4)
-        w = spline_weights(f, tab)                                   # [n][10]
-        rows = n0c[:, None] + np.arange(-4, 6)[None, :]              # [n][10]
+    zs = np.zeros((n_q, len(blocks), n_modes), dtype=np.complex128)
+    sigs = np.zeros((n_q, len(blocks), n_modes, n_modes), dtype=np.complex128)
+    for k, (det, als) in enumerate(blocks):
+        A = np.zeros((n_q, n_modes), dtype=np.complex128)
         for a in range(n_modes):
+            # antenna factor and arrival-time stencil of mode a in block k
+            fp, fc = antenna_patterns(ev.det_tensor[det], als[a], dec, psi)
+            A[:, a] = mode_factors(ev.modes, fp, fc, iota, phi)[:, a]
+            s = (t_c + time_delays(ev.det_pos[det], als[a], dec) - ev.t_trig) * ev.grid.fs + art.half_w
+            n0 = np.floor(s)
+            f = s - n0
+            n0 = n0.astype(np.int64)
+            ok = (n0 >= 4) & (n0 <= T - 6)
+            valid &= ok
+            n0c = np.where(ok, n0, 4)
+            w = spline_weights(f, tab)                                   # [n][10]
+            rows = n0c[:, None] + np.arange(-4, 6)[None, :]              # [n][10]
             o = coef_off[k][a]
             C = Y[:, o:o + 2 * art.q:2] + 1j * Y[:, o + 1:o + 2 * art.q:2]
             btilde = np.einsum("ns,nsi->ni", w, art.basis[k, a][rows])
@@ -205,7 +288,6 @@ def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np
                 sigs[:, k, a, b] = Y[:, p] + 1j * Y[:, p + 1]
                 sigs[:, k, b, a] = Y[:, p] - 1j * Y[:, p + 1]
                 p += 2
-        A = mode_factors(ev.modes, fp, fc, iota, phi)
         lnl += combine(A, zs[:, k], sigs[:, k], r)
     lnl = np.where(valid, lnl, -np.inf)
     return lnl, zs, sigs, valid
@@ -227,6 +309,8 @@ def exact_parts(art: Artefacts, delta_e, ext, t_c, d_l):
       samples:   the spline through the exact window samples, no basis --
                  everything but the basis truncation and the RBF."""
     from .startup import node_series_and_overlaps, physical_mask
+    if art.bands is not None:
+        raise NotImplementedError("exact_parts covers frozen antenna patterns only")
     ev = art.ev
     n_q = delta_e.shape[0]
     x = delta_e / art.frame.semi[None, :]

@@ -394,38 +394,89 @@ def window_indices(grid: ph.Grid, t_trig: float, half_window: float) -> np.ndarr
     return (n_trig + np.arange(-w, w + 1)) % grid.n_s
 
 
+def time_bands(grid: ph.Grid, psd0: np.ndarray, centre_phys, modes, n_bands: int):
+    """Frequency bands for time-dependent antenna patterns.  Sec. II B
+    freezes the patterns over the signal; on a rotating Earth the source's
+    longitude drifts while a long signal sweeps up in frequency, so the
+    frequency axis is cut into n_bands bands, within each of which every
+    mode's patterns and delay are taken at one time.
+
+    Cut: the centre template's (2,2) stationary-phase track t(f) = Psi'(f) /
+    (2 pi) (Psi referenced at grid.f_ref, times relative to t_c) carries the
+    gravitational-wave phase Phi(f) = f Psi'(f) - Psi(f) (2 pi times the
+    cycles emitted up to f); the bands hold equal shares of Phi between the
+    lowest bin and the (2,2) cut-off -- the delay's phase error, 2 pi f
+    d(delay)/dt (t - t_band), then has the same bound in every band.  Band b
+    holds the bins edges[b] .. edges[b + 1] - 1 (the first band starts at
+    the lowest bin, the last runs to the top of the grid).
+
+    Time of band b for mode a: mode a has frequency f at the (2,2) track time
+    of 2 f / m; its band time is the mean of that time over the mode's bins
+    in the band, weighted by f^2 |h_a|^2 / S = f^(-1/3) / S (detector 0's
+    PSD): the delay error, which dominates the pattern error by
+    2 pi f |r| / c, is then matched to first order.  A band where the mode
+    has no bins gets time 0 (t_c).
+
+    Returns (bin edges [n_bands + 1] int64, times [n_bands][n_modes])."""
+    j0, j1 = ph.mode_band(grid, 2, centre_phys[0], centre_phys[1])
+    f = np.arange(j0, j1) * grid.df
+    psi = ph.referenced_phase_22(f, *centre_phys, grid.f_ref)
+    t = ph.spa_time(f, 2, centre_phys, grid.f_ref, 0.0)
+    gw_phase = 2.0 * math.pi * f * t - psi
+    cut = gw_phase[0] + (gw_phase[-1] - gw_phase[0]) * np.arange(n_bands + 1) / n_bands
+    edges = [grid.j_lo] + [j0 + int(np.searchsorted(gw_phase, cut[b], side="left")) for b in range(1, n_bands)] \
+        + [grid.j_hi]
+    times = np.zeros((n_bands, len(modes)))
+    for a, (l, m) in enumerate(modes):
+        a0, a1 = ph.mode_band(grid, m, centre_phys[0], centre_phys[1])
+        for b in range(n_bands):
+            lo, hi = max(edges[b], a0), min(edges[b + 1], a1)
+            if hi <= lo:
+                continue
+            fb = np.arange(lo, hi) * grid.df
+            w = fb ** (-1.0 / 3.0) / psd0[lo:hi]
+            times[b, a] = np.sum(w * ph.spa_time(fb, m, centre_phys, grid.f_ref, 0.0)) / np.sum(w)
+    return np.array(edges, dtype=np.int64), times
+
+
 def node_series_and_overlaps(ev: Event, node_phys: np.ndarray, half_window: float,
-                             workers: int = -1, batch: int = 16):
+                             workers: int = -1, batch: int = 16, band_edges=None):
     """Per node batch, the templates of every mode are formed once and give
     z[k][a][node][t] = (h_a e^{-2 pi i f tau_t} | d_k) at the window times
     tau_t -- the inverse FFT of X_j = conj(h_a(f_j)) d_k(f_j) / S_k(f_j) on
     the band, scaled by 4 fs, read at the window's sample indices -- and
     sigma[k][node][a][b] = (h_a | h_b)_k, Hermitian in (a, b)
-    (Eq. conjugation_symmetry)."""
+    (Eq. conjugation_symmetry).  With band_edges (time_bands) every sum runs
+    over one band's bins at a time and the first index is v = k * B + b
+    (detector k, band b)."""
     grid = ev.grid
     idx = window_indices(grid, ev.t_trig, half_window)
     n_nodes = node_phys.shape[0]
     n_modes = len(ev.modes)
-    z = np.zeros((ev.n_det, n_modes, n_nodes, idx.size), dtype=np.complex128)
-    sig = np.zeros((ev.n_det, n_nodes, n_modes, n_modes), dtype=np.complex128)
-    sl = grid.band()
+    edges = [grid.j_lo, grid.j_hi] if band_edges is None else list(band_edges)
+    n_b = len(edges) - 1
+    z = np.zeros((ev.n_det * n_b, n_modes, n_nodes, idx.size), dtype=np.complex128)
+    sig = np.zeros((ev.n_det * n_b, n_nodes, n_modes, n_modes), dtype=np.complex128)
     weights = [np.zeros(grid.n_f, dtype=np.complex128) for _ in range(ev.n_det)]
     for k in range(ev.n_det):
+        sl = grid.band()
         weights[k][sl] = ev.data[k, sl] / ev.psd[k, sl]
     for start in range(0, n_nodes, batch):
         stop = min(n_nodes, start + batch)
         hs = np.stack([np.stack([ph.waveform_mode(grid, l, m, tuple(node_phys[i]), ev.d_inj)
                                  for i in range(start, stop)]) for (l, m) in ev.modes])   # [a][node][f]
         for k in range(ev.n_det):
-            wk = 4.0 * grid.df / ev.psd[k, sl]
-            hb = hs[:, :, sl]
-            sig[k, start:stop] = np.einsum("anf,bnf->nab", np.conj(hb) * wk, hb)
-            for a in range(n_modes):
-                X = np.zeros((stop - start, grid.n_s), dtype=np.complex128)
-                X[:, :grid.n_f] = np.conj(hs[a]) * weights[k][None, :]
-                X[:, grid.j_hi:] = 0.0
-                series = scipy.fft.ifft(X, axis=1, workers=workers)
-                z[k, a, start:stop] = 4.0 * grid.fs * series[:, idx]
+            for b in range(n_b):
+                sl = slice(edges[b], edges[b + 1])
+                v = k * n_b + b
+                wk = 4.0 * grid.df / ev.psd[k, sl]
+                hb = hs[:, :, sl]
+                sig[v, start:stop] = np.einsum("anf,bnf->nab", np.conj(hb) * wk, hb)
+                for a in range(n_modes):
+                    X = np.zeros((stop - start, grid.n_s), dtype=np.complex128)
+                    X[:, sl] = np.conj(hs[a][:, sl]) * weights[k][None, sl]
+                    series = scipy.fft.ifft(X, axis=1, workers=workers)
+                    z[v, a, start:stop] = 4.0 * grid.fs * series[:, idx]
     return z, sig
 
 
@@ -543,6 +594,7 @@ class Artefacts:
     sigma_nodes: np.ndarray  # [n_det][N][n][n]
     squeeze_factor: float = 1.0   # scale applied to the longest semi-axis
     centre_opt: tuple | None = None   # optimise_centre's result when the centre was optimised
+    bands: tuple | None = None    # (bin edges [B + 1], times [B][n_modes]) of time_bands, or None (frozen patterns)
 
     @property
     def d_ref(self) -> float:
@@ -551,7 +603,7 @@ class Artefacts:
 
 def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_nodes, phys_nodes, W, basis,
                            half_w, d_ref, f_ref, eps=None, cond=float("nan"), singular=None,
-                           node_values=None) -> Artefacts:
+                           node_values=None, bands=None, earth_rate=0.0) -> Artefacts:
     """Artefacts whose evaluation inputs are given arrays (another start-up's
     frame, nodes, RBF weights, SVD basis, reference distance and frequency),
     so that the online stage here (meshfree_lnl, rbf_eval) evaluates exactly
@@ -562,14 +614,14 @@ def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_n
     geo = [ph.detector_geometry(s) for s in cfg.sites]
     ev = Event(grid=grid, modes=tuple(cfg.modes), psd=None, data=None, det_tensor=[g[0] for g in geo],
                det_pos=[g[1] for g in geo], inj_phys=tuple(cfg.inj_phys), inj_ext=np.asarray(inj_ext, dtype=np.float64),
-               t_trig=cfg.t_trig, d_inj=d_ref, snr_opt=cfg.inj_snr)
+               t_trig=cfg.t_trig, d_inj=d_ref, snr_opt=cfg.inj_snr, earth_rate=earth_rate)
     fr = Frame(theta_c=np.asarray(theta_c), metric=np.asarray(metric_g), vecs=np.asarray(vecs), lam=np.asarray(lam),
                semi=np.asarray(semi))
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=np.asarray(x_nodes), phys_nodes=np.asarray(phys_nodes),
                      W=np.asarray(W), basis=np.asarray(basis), half_w=int(half_w),
                      eps=cfg.eps if eps is None else float(eps),
                      degree=cfg.poly_degree, q=cfg.q, cond=cond, discarded=None, singular=singular,
-                     node_values=node_values, z_nodes=None, sigma_nodes=None)
+                     node_values=node_values, z_nodes=None, sigma_nodes=None, bands=bands)
 
 
 def output_layout(n_det: int, n_modes: int, q: int):
@@ -602,15 +654,19 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     if getattr(cfg, "squeeze", False):
         fr, squeeze_factor = squeeze(fr, grid, ev.psd[0], centre, cfg.match, grid.f_low)
     x, phys = place_nodes(fr, cfg.n_nodes, grid.f_low, cfg.chi_max, cfg.center_node)
-    z, sig = node_series_and_overlaps(ev, phys, cfg.half_window, workers=workers)
+    n_bands = getattr(cfg, "n_bands", 1)
+    bands = time_bands(grid, ev.psd[0], centre, ev.modes, n_bands) if n_bands > 1 else None
+    z, sig = node_series_and_overlaps(ev, phys, cfg.half_window, workers=workers,
+                                      band_edges=None if bands is None else bands[0])
     n_modes = len(ev.modes)
-    K, coef_off, sig_off = output_layout(ev.n_det, n_modes, cfg.q)
+    n_v = z.shape[0]                # detectors, or (detector, band) pairs
+    K, coef_off, sig_off = output_layout(n_v, n_modes, cfg.q)
     F = np.zeros((cfg.n_nodes, K))
     T = z.shape[-1]
-    basis = np.zeros((ev.n_det, n_modes, T, cfg.q), dtype=np.complex128)
-    discarded = np.zeros((ev.n_det, n_modes))
-    singular = np.zeros((ev.n_det, n_modes, min(cfg.n_nodes, T)))
-    for k in range(ev.n_det):
+    basis = np.zeros((n_v, n_modes, T, cfg.q), dtype=np.complex128)
+    discarded = np.zeros((n_v, n_modes))
+    singular = np.zeros((n_v, n_modes, min(cfg.n_nodes, T)))
+    for k in range(n_v):
         for a in range(n_modes):
             B, C, s = svd_basis(z[k, a], cfg.q)
             basis[k, a] = B
@@ -634,4 +690,4 @@ def startup(cfg, white: np.ndarray | None = None, inj_ext: np.ndarray | None = N
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=x, phys_nodes=phys, W=W, basis=basis,
                      half_w=half_w, eps=eps, degree=cfg.poly_degree, q=cfg.q, cond=cond,
                      discarded=discarded, singular=singular, node_values=F, z_nodes=z,
-                     sigma_nodes=sig, squeeze_factor=squeeze_factor, centre_opt=centre_opt)
+                     sigma_nodes=sig, squeeze_factor=squeeze_factor, centre_opt=centre_opt, bands=bands)

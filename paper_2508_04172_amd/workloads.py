@@ -72,6 +72,7 @@ class Config:
     optimise_centre: bool = False                 # move the centre to the network-SNR optimum first
     centre_offset: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)   # seed = injection + offset
     earth_rate: float = 0.0                       # Earth rotation [rad/s] in the exact model and the injection
+    n_bands: int = 1                              # time bands of the antenna patterns in the meshfree model (1: frozen)
 
     @property
     def n_det(self) -> int:
