@@ -34,9 +34,11 @@
 extern "C" {
 #endif
 
-#define RBFL_ABI_VERSION 6
+#define RBFL_ABI_VERSION 7
 #define RBFL_MAX_MODES 5
 #define RBFL_MAX_DET 4
+#define RBFL_MAX_BANDS 16     /* time bands of the antenna patterns (rbfl_build_spec.n_bands) */
+#define RBFL_MAX_BLOCKS 64    /* n_det * n_bands: blocks of interpolated outputs */
 
 enum rbfl_status {
   RBFL_OK = 0,
@@ -163,7 +165,32 @@ typedef struct {
                                           right ascension alpha has Earth-fixed longitude
                                           alpha - earth_rate (t - t_trig), and each mode's frequency f is
                                           emitted at its stationary-phase time t_c + Psi'(2f/m) / (2 pi) */
+  int32_t n_bands;                     /* time bands B of the antenna patterns: 0 or 1 = patterns frozen at
+                                          t_c over the whole signal (Sec. II B); 2 .. RBFL_MAX_BANDS with
+                                          n_det * B <= RBFL_MAX_BLOCKS = the time-banded form below */
 } rbfl_build_spec;
+
+/* Time-banded antenna patterns (n_bands = B > 1).  Sec. II B freezes the
+ * patterns over the signal, which Sec. IV names as the limit for long
+ * third-generation signals on a rotating Earth.  The banded form cuts the
+ * frequency axis into B bands holding equal shares of the centre template's
+ * (2,2) gravitational-wave phase f Psi'(f) - Psi(f) (between the lowest bin
+ * and the centre's (2,2) cut-off; the last band runs to the top of the
+ * grid).  In band b, mode (l, m) takes its antenna factor and delay at one
+ * time t_bm relative to t_c: the mean of its stationary-phase time
+ * Psi'(2f/m) / (2 pi) over its bins in the band under the weights
+ * f^(-1/3) / S_0 (0 where the mode has no bins there); the source's
+ * Earth-fixed longitude is then alpha - earth_rate (t_c + t_bm - t_trig).
+ * Each (detector k, band b) is one block v = k B + b of Eq. logl_complete's
+ * terms, with z and the mode overlaps summed over the band's bins only and
+ * interpolated like the frozen form's (K = n_det B (2 q n_modes +
+ * n_modes^2) outputs); the overlaps carry no delay, so cross terms between
+ * modes drop the small phase their different delays would give them.
+ * RBFL_Q_BANDS reports the bands.  A banded handle evaluates through
+ * rbfl_eval, rbfl_interp, rbfl_eval_static and the samplers in every form
+ * but the surrogate; rbfl_fuse_epilogue(on), rbfl_exact_parts,
+ * rbfl_surrogate_train, rbfl_plan_create and rbfl_eval_ragged return
+ * RBFL_E_INVALID_ARG for it. */
 
 /* Thread-local description of the last failure on this thread; valid until
  * the next rbfl_* call on the same thread. */
@@ -266,12 +293,13 @@ enum rbfl_query_what {
   RBFL_Q_NODES = 3,        /* double[N][4] unit-ball node coordinates */
   RBFL_Q_NODE_PHYS = 4,    /* double[N][4] m1, m2, chi1, chi2 of the nodes */
   RBFL_Q_WEIGHTS = 5,      /* double[N+M][K] RBF weights */
-  RBFL_Q_BASIS = 6,        /* double[n_det][n_modes][T][q][2] SVD basis */
+  RBFL_Q_BASIS = 6,        /* double[n_blocks][n_modes][T][q][2] SVD basis (n_blocks = n_det, or
+                              n_det * n_bands with time bands, block v = k n_bands + b) */
   RBFL_Q_NODE_VALUES = 7,  /* double[N][K] interpolated quantities at the nodes */
-  RBFL_Q_SINGULAR = 8,     /* double[n_det][n_modes][min(N,T)] singular values */
+  RBFL_Q_SINGULAR = 8,     /* double[n_blocks][n_modes][min(N,T)] singular values */
   RBFL_Q_COND = 9,         /* double[1]: 1-norm condition estimate of the RBF system */
   RBFL_Q_TIMING = 10,      /* double[8]: start-up stage wall times [s] */
-  RBFL_Q_Z_NODES = 11,     /* double[n_det][n_modes][N][T][2] time series at the nodes */
+  RBFL_Q_Z_NODES = 11,     /* double[n_blocks][n_modes][N][T][2] time series at the nodes */
   RBFL_Q_KERNEL_STATS = 12, /* double[9]: MFMA contraction ms, launches, proposals; epilogue ms,
                                launches, proposals; basis-row stage ms, launches, proposals (zero time
                                for forms without one) -- summed HIP-event durations since
@@ -307,9 +335,13 @@ enum rbfl_query_what {
                                1/0 that choice is within RBFL_SPLIT_TOL of the FP64 form (when no digit
                                count is, the tuner keeps the most accurate one and reports 0 here:
                                such a split form does not meet the tuner's bar), digits S in use */
-  RBFL_Q_NAN_COUNT = 22     /* int64[1]: NaN ln L values written by the last rbfl_eval call on this
+  RBFL_Q_NAN_COUNT = 22,    /* int64[1]: NaN ln L values written by the last rbfl_eval call on this
                                handle (a proposal with a NaN parameter gives NaN; any other NaN result
                                is counted too).  Synchronises the device. */
+  RBFL_Q_BANDS = 25         /* double[2 + (B + 1) + B n_modes]: B = n_bands (1 when frozen), n_blocks,
+                               the band edges as bin indices [B + 1] (band b holds bins edges[b] ..
+                               edges[b+1] - 1), then the band times t_bm relative to t_c [B][n_modes]
+                               (rbfl_build_spec.n_bands) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 

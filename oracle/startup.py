@@ -603,7 +603,7 @@ class Artefacts:
 
 def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_nodes, phys_nodes, W, basis,
                            half_w, d_ref, f_ref, eps=None, cond=float("nan"), singular=None,
-                           node_values=None, bands=None, earth_rate=0.0) -> Artefacts:
+                           node_values=None, bands=None, earth_rate=None) -> Artefacts:
     """Artefacts whose evaluation inputs are given arrays (another start-up's
     frame, nodes, RBF weights, SVD basis, reference distance and frequency),
     so that the online stage here (meshfree_lnl, rbf_eval) evaluates exactly
@@ -614,7 +614,8 @@ def artefacts_from_exports(cfg, inj_ext, theta_c, metric_g, vecs, lam, semi, x_n
     geo = [ph.detector_geometry(s) for s in cfg.sites]
     ev = Event(grid=grid, modes=tuple(cfg.modes), psd=None, data=None, det_tensor=[g[0] for g in geo],
                det_pos=[g[1] for g in geo], inj_phys=tuple(cfg.inj_phys), inj_ext=np.asarray(inj_ext, dtype=np.float64),
-               t_trig=cfg.t_trig, d_inj=d_ref, snr_opt=cfg.inj_snr, earth_rate=earth_rate)
+               t_trig=cfg.t_trig, d_inj=d_ref, snr_opt=cfg.inj_snr,
+               earth_rate=getattr(cfg, "earth_rate", 0.0) if earth_rate is None else earth_rate)
     fr = Frame(theta_c=np.asarray(theta_c), metric=np.asarray(metric_g), vecs=np.asarray(vecs), lam=np.asarray(lam),
                semi=np.asarray(semi))
     return Artefacts(ev=ev, cfg=cfg, frame=fr, x_nodes=np.asarray(x_nodes), phys_nodes=np.asarray(phys_nodes),

@@ -34,19 +34,21 @@ __global__ void __launch_bounds__(kBlock) k_waveforms(const Binary *__restrict__
   out[((int64_t)a * nb + i) * J + jj] = v;
 }
 
-// sigma_k,ab = sum_j conj(h_a) h_b w_k(j) over the band, w_k = 4 df / S_k.
-// A holds conj(h), so conj(h_a) h_b = A_a conj(A_b).  One block per
-// (node, detector); fixed-order tree reduction (deterministic).
+// sigma_k,ab = sum_j conj(h_a) h_b w_k(j) over bins j0 .. j1 - 1 of the
+// band (all of it, or one time band), w_k = 4 df / S_k.  A holds conj(h), so
+// conj(h_a) h_b = A_a conj(A_b).  One block per (node, detector); the
+// detector's results go to sig[k * det_stride + node_base + node]; fixed-order
+// tree reduction (deterministic).
 __global__ void __launch_bounds__(kBlock) k_sigma(const double2 *__restrict__ A, int nb, int n_modes, int J,
-                                                  const double *__restrict__ wk, int N_total, int node_base,
-                                                  double2 *__restrict__ sig) {
+                                                  int j0, int j1, const double *__restrict__ wk,
+                                                  int64_t det_stride, int node_base, double2 *__restrict__ sig) {
   const int i = blockIdx.x;
   const int k = blockIdx.y;
   const int npair = n_modes * (n_modes + 1) / 2;
   double2 acc[15];
   for (int p = 0; p < 15; ++p) acc[p] = make_double2(0.0, 0.0);
   const double *w = wk + (int64_t)k * J;
-  for (int jj = threadIdx.x; jj < J; jj += kBlock) {
+  for (int jj = j0 + threadIdx.x; jj < j1; jj += kBlock) {
     double2 h[RBFL_MAX_MODES];
     for (int a = 0; a < n_modes; ++a) h[a] = A[((int64_t)a * nb + i) * J + jj];
     const double ww = w[jj];
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) k_sigma(const double2 *__restrict__ A,
     }
   }
   __shared__ double2 red[kBlock];
-  double2 *out = sig + ((int64_t)k * N_total + node_base + i) * n_modes * n_modes;
+  double2 *out = sig + ((int64_t)k * det_stride + node_base + i) * n_modes * n_modes;
   int p = 0;
   for (int a = 0; a < n_modes; ++a) {
     for (int b = a; b < n_modes; ++b, ++p) {
@@ -331,9 +333,10 @@ void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_mode
   RBFL_HIP(hipGetLastError());
 }
 
-void launch_sigma(const double2 *A, int nb, int n_modes, int J, const double *wk, int n_det, int N_total,
-                  int node_base, double2 *sig, hipStream_t s) {
-  hipLaunchKernelGGL(k_sigma, dim3(nb, n_det), dim3(kBlock), 0, s, A, nb, n_modes, J, wk, N_total, node_base, sig);
+void launch_sigma(const double2 *A, int nb, int n_modes, int J, int j0, int j1, const double *wk, int n_det,
+                  int64_t det_stride, int node_base, double2 *sig, hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma, dim3(nb, n_det), dim3(kBlock), 0, s, A, nb, n_modes, J, j0, j1, wk, det_stride,
+                     node_base, sig);
   RBFL_HIP(hipGetLastError());
 }
 

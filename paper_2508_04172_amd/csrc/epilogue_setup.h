@@ -19,20 +19,17 @@ struct EpiSetup {
   double Ar[RBFL_MAX_DET][RBFL_MAX_MODES], Ai[RBFL_MAX_DET][RBFL_MAX_MODES];
 };
 
-__device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
-                                          int64_t g, EpiSetup &o) {
-  double p[11];
+// a1 for proposal g: loads its 11 parameters into p; 2 for a NaN input, else
+// 1 outside the ellipsoid or the physical region, else 0.
+__device__ __forceinline__ int epi_prelude(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
+                                           int64_t g, double p[11]) {
   bool any_nan = false;
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
     p[i] = params[i * ld + g];
     any_nan |= isnan(p[i]);
   }
-  if (any_nan) {
-    o.status = 2;
-    return;
-  }
-  // a1: inside the ellipsoid and physical
+  if (any_nan) return 2;
   double r2 = 0.0;
   for (int d = 0; d < 4; ++d) {
     const double x = p[d] / c.semi[d];
@@ -48,6 +45,18 @@ __device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__r
     }
     valid = valid && theta_to_phys(th, c.f0, c.chi_max, phys);
   }
+  return valid ? 0 : 1;
+}
+
+__device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__restrict__ params, int64_t ld,
+                                          int64_t g, EpiSetup &o) {
+  double p[11];
+  const int pre = epi_prelude(c, params, ld, g, p);
+  if (pre == 2) {
+    o.status = 2;
+    return;
+  }
+  bool valid = pre == 0;
   const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
   o.rr = c.d_ref / dl;
   double ch, sh;

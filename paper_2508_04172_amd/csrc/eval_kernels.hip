@@ -366,6 +366,109 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(const EvalConsts *__restr
   }
 }
 
+// Epilogue of the time-banded form (n_bands = B > 1): one wave per proposal,
+// one lane per (block v, mode a) pair at a time.  Block v = k B + b is
+// detector k over band b, where mode a sees the source at right ascension
+// alpha - rate (t_c + t_ba - t_trig); that gives the lane its own antenna
+// factor A_va and arrival-time stencil.  The lane reconstructs z_va from all
+// q coefficients (spline-folded basis, as the frozen epilogue) and forms
+// r Re(conj(A_va) z_va) - r^2/2 [|A_va|^2 sigma_aa + 2 sum_{c > a}
+// Re(conj(A_va) A_vc sigma_ac)], taking A_vc from the lanes of the same block
+// (a chunk of lanes holds whole blocks, floor(64 / n_modes) of them).  A
+// stencil outside the window makes the proposal -inf, as in the frozen form;
+// the lanes' terms meet in lane order with compensated additions.
+__global__ void __launch_bounds__(kThreads) k_epilogue_banded(const EvalConsts *__restrict__ cp,
+                                                              const double *__restrict__ params, int64_t ld,
+                                                              int64_t b0, int64_t nb, const double *__restrict__ Y,
+                                                              const double2 *__restrict__ basis4,
+                                                              double *__restrict__ lnl) {
+  const EvalConsts &c = *cp;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (g >= nb) return;   // whole wave leaves together
+  double p[11];
+  const int pre = epi_prelude(c, params, ld, b0 + g, p);
+  if (pre == 2) {
+    if (lane == 0) lnl[b0 + g] = __builtin_nan("");
+    return;
+  }
+  const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
+  const double rr = c.d_ref / dl;
+  double ch, sh;
+  sincos(0.5 * iota, &sh, &ch);
+  const int nm = c.n_modes, q = c.q, T = c.T, B = c.n_bands;
+  const int per = (64 / nm) * nm;
+  const int n_pairs = c.n_v * nm;
+  const double *y = Y + g * c.Kp;
+  bool ok = pre == 0;
+  double sum = 0.0, comp = 0.0;
+  for (int p0 = 0; p0 < n_pairs; p0 += per) {
+    const int pr = p0 + lane;
+    const bool active = lane < per && pr < n_pairs;
+    const int v = active ? pr / nm : 0;
+    const int a = active ? pr - v * nm : 0;
+    const int k = v / B, bd = v - k * B;
+    double ar = 0.0, ai = 0.0, term = 0.0;
+    if (active) {
+      const double al = alpha - c.earth_rate * (tc + c.band_t[bd][a] - c.t_trig);
+      double fp, fc, dt;
+      detector_response(c.D[k], c.r[k], al, dec, psi, &fp, &fc, &dt);
+      double ynr, yni, ypr, ypi;
+      eval_ylm(c.ylm_neg[a], ch, sh, phi, &ynr, &yni);
+      eval_ylm(c.ylm_pos[a], ch, sh, phi, &ypr, &ypi);
+      const double sg = (c.mode_l[a] & 1) ? -1.0 : 1.0;
+      ar = 0.5 * ((fp * ynr - fc * yni) + sg * (fp * ypr - fc * ypi));
+      ai = 0.5 * ((fp * yni + fc * ynr) + sg * (-fp * ypi - fc * ypr));
+      const double s = (tc + dt - c.t_trig) * c.fs + (double)c.half_w;
+      const double fl = floor(s);
+      const bool in = fl >= 4.0 && fl <= (double)(T - 6);
+      ok = ok && in;
+      if (in) {
+        const double f = s - fl;
+        const double2 *base = basis4 + ((int64_t)pr * T + (int)fl) * q * 4;   // pair pr = v n_modes + a
+        const double *cf = y + c.coef_off[v][a];
+        double zr = 0.0, zi = 0.0;
+        for (int i = 0; i < q; ++i) {
+          const double cr = cf[2 * i], ci = cf[2 * i + 1];
+          const double2 w0 = base[4 * i], w1 = base[4 * i + 1], w2 = base[4 * i + 2], w3 = base[4 * i + 3];
+          const double br = fma(fma(fma(w3.x, f, w2.x), f, w1.x), f, w0.x);
+          const double bi = fma(fma(fma(w3.y, f, w2.y), f, w1.y), f, w0.y);
+          zr += cr * br - ci * bi;
+          zi += cr * bi + ci * br;
+        }
+        term = rr * (ar * zr + ai * zi);
+      }
+    }
+    // the pair's row of the overlap term; the block's lanes are lead .. lead + nm - 1
+    const int lead = lane - a;
+    const int so = c.sig_off[v];
+    double st = active ? (ar * ar + ai * ai) * y[so + a] : 0.0;
+    for (int cc = 1; cc < nm; ++cc) {
+      const double br = __shfl(ar, (lead + cc) & 63, 64), bi = __shfl(ai, (lead + cc) & 63, 64);
+      if (active && cc > a) {
+        const int idx = a * nm - a * (a + 1) / 2 + (cc - a - 1);   // (a, cc) in lexicographic order
+        const double sr = y[so + nm + 2 * idx], si = y[so + nm + 2 * idx + 1];
+        const double pr_ = ar * br + ai * bi, pi_ = ar * bi - ai * br;
+        st += 2.0 * (pr_ * sr - pi_ * si);
+      }
+    }
+    term -= 0.5 * rr * rr * st;
+    const double t = sum + term;
+    comp += fabs(sum) >= fabs(term) ? (sum - t) + term : (term - t) + sum;
+    sum = t;
+  }
+  const bool all_ok = __all(ok ? 1 : 0) != 0;
+  const double mine = sum + comp;
+  double tot = 0.0, tc_ = 0.0;
+  for (int j = 0; j < 64; ++j) {
+    const double vj = __shfl(mine, j, 64);
+    const double t = tot + vj;
+    tc_ += fabs(tot) >= fabs(vj) ? (tot - t) + vj : (vj - t) + tot;
+    tot = t;
+  }
+  if (lane == 0) lnl[b0 + g] = all_ok ? tot + tc_ : -__builtin_huge_val();
+}
+
 // Epilogue finished inside the contraction (FP64 form, optional): ln L is
 // linear in the interpolated outputs, ln L = sum_c coef_c(proposal) Y[c], so
 // the contraction kernel forms coef_c from each proposal's setup and sums
@@ -704,9 +807,14 @@ void launch_ragged_epilogue(const EventDesc *ev, int n_ev, const double *params,
 
 void launch_epilogue(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                      int64_t nb, const double *Y, const double2 *basis, double *lnl, hipStream_t s) {
-  (void)hc;
-  dim3 grid((unsigned)((nb + kEpiBatch - 1) / kEpiBatch));
-  hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
+  if (nb <= 0) return;
+  if (hc.n_bands > 1) {
+    hipLaunchKernelGGL(k_epilogue_banded, dim3((unsigned)((nb + kWaves - 1) / kWaves)), dim3(kThreads), 0, s, c,
+                       params, ld, b0, nb, Y, basis, lnl);
+  } else {
+    dim3 grid((unsigned)((nb + kEpiBatch - 1) / kEpiBatch));
+    hipLaunchKernelGGL(k_epilogue, grid, dim3(kThreads), 0, s, c, params, ld, b0, nb, Y, basis, lnl);
+  }
   RBFL_HIP(hipGetLastError());
 }
 

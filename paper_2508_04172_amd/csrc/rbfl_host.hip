@@ -319,6 +319,59 @@ static double reference_frequency(const Ctx &c, const std::vector<double> &psd0,
   return fw.value() / w.value();
 }
 
+// Time bands of the antenna patterns (rbfl_build_spec.n_bands > 1).  The
+// centre's (2,2) stationary-phase track t(f) = Psi'(f) / (2 pi) carries the
+// gravitational-wave phase Phi(f) = f Psi'(f) - Psi(f); the bands cut
+// [lowest bin, (2,2) cut-off) into equal shares of Phi, so the phase error
+// of a delay drifting linearly in time has the same bound in every band, and
+// the last band runs on to the top of the grid.  Mode (l, m) passes f at the
+// (2,2) track time of 2 f / m; its time in band b is the mean of that time
+// over its own bins there under f^(-1/3) / S_0 (the delay error's weight
+// f^2 |h|^2 / S), or 0 where it has no bins.  edges: [B + 1] bin indices.
+static void time_bands(const Ctx &c, const std::vector<double> &psd0, const double centre[4],
+                       std::vector<int64_t> &edges, double times[RBFL_MAX_BANDS][RBFL_MAX_MODES]) {
+  const int B = c.n_bands;
+  const Binary b = make_binary(centre[0], centre[1], centre[2], centre[3], c.f_ref);
+  const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
+  const int64_t j_hi = c.n_s / 2;
+  auto cut_bin = [&](int m) {
+    const int64_t jc = (int64_t)ceil((double)m * b.f_isco * c.seg_len);
+    return std::min(std::max(jc, j_lo), j_hi);
+  };
+  const int64_t j22 = cut_bin(2);
+  if (j22 - j_lo < 2) throw Error(RBFL_E_INVALID_ARG, "the (2,2) band at the centre is too short for time bands");
+  std::vector<double> phi((size_t)(j22 - j_lo));
+  for (int64_t j = j_lo; j < j22; ++j) {
+    const double f = (double)j * c.df;
+    phi[(size_t)(j - j_lo)] = f * (dphase22_pn(f, b) - b.dpsi_ref) - phase22(f, b);
+  }
+  edges.assign((size_t)B + 1, 0);
+  edges[0] = j_lo;
+  edges[(size_t)B] = j_hi;
+  const double p0 = phi.front(), p1 = phi.back();
+  for (int i = 1; i < B; ++i) {
+    const double cut = p0 + (p1 - p0) * (double)i / (double)B;
+    const auto it = std::lower_bound(phi.begin(), phi.end(), cut);
+    edges[(size_t)i] = j_lo + (int64_t)(it - phi.begin());
+  }
+  for (int a = 0; a < c.n_modes; ++a) {
+    const int m = c.modes[a][1];
+    const int64_t jc = cut_bin(m);
+    for (int i = 0; i < B; ++i) {
+      const int64_t lo = std::max(edges[(size_t)i], j_lo), hi = std::min(edges[(size_t)i + 1], jc);
+      Sum w, tw;
+      for (int64_t j = lo; j < hi; ++j) {
+        const double f = (double)j * c.df;
+        const double v = pow(f, -1.0 / 3.0) / psd0[j];
+        const double t = (dphase22_pn(2.0 * f / (double)m, b) - b.dpsi_ref) / (2.0 * kPi);
+        w.add(v);
+        tw.add(v * t);
+      }
+      times[i][a] = hi > lo ? tw.value() / w.value() : 0.0;
+    }
+  }
+}
+
 // ---- true match (Eq. Match) and the squeeze of the longest axis (Sec. II C.1)
 
 typedef std::complex<double> cplx;
@@ -652,6 +705,8 @@ static void validate(const rbfl_build_spec *s) {
   require((s->flags & ~(uint32_t)(RBFL_FLAG_CENTER_NODE | RBFL_FLAG_SQUEEZE | RBFL_FLAG_OPTIMISE_CENTRE)) == 0,
           "unknown flag bits");
   require(s->n_det >= 1 && s->n_det <= RBFL_MAX_DET, "n_det out of range");
+  require(s->n_bands >= 0 && s->n_bands <= RBFL_MAX_BANDS && s->n_det * std::max(1, s->n_bands) <= RBFL_MAX_BLOCKS,
+          "n_bands must be in 0 .. RBFL_MAX_BANDS with n_det * n_bands <= RBFL_MAX_BLOCKS");
   require(s->n_modes >= 1 && s->n_modes <= RBFL_MAX_MODES, "n_modes out of range");
   for (int a = 0; a < s->n_modes; ++a) {
     const int l = s->modes[a][0], m = s->modes[a][1];
@@ -788,7 +843,7 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
   RBFL_HIP(hipMemcpyAsync(d_modes.p, mode_lm, sizeof(mode_lm), hipMemcpyHostToDevice, s));
   RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * nb, hipMemcpyHostToDevice, s));
   launch_waveforms(d_bins.p, nb, d_modes.p, nm, c.brute_j_lo, (int)J, c.df, 1.0, A.p, s);
-  launch_sigma(A.p, nb, nm, (int)J, c.brute_w.p, nd, nb, 0, dS.p, s);
+  launch_sigma(A.p, nb, nm, (int)J, 0, (int)J, c.brute_w.p, nd, nb, 0, dS.p, s);
   for (int a = 0; a < nm; ++a)
     for (int k = 0; k < nd; ++k) {
       launch_window_dft(A.p + (size_t)a * nb * J, nb, (int)J, (int)J, c.win_D.p + (size_t)k * J, c.brute_j_lo, c.n_s,
@@ -1100,7 +1155,9 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   int poly[kMaxPoly][3];
   c.M = monomials(c.degree, poly);
   c.N = s->n_nodes;
-  c.K = c.n_det * (2 * c.q * c.n_modes + c.n_modes * c.n_modes);
+  c.n_bands = std::max(1, s->n_bands);
+  c.n_v = c.n_det * c.n_bands;
+  c.K = c.n_v * (2 * c.q * c.n_modes + c.n_modes * c.n_modes);
   c.Kp = ((c.K + kColTile - 1) / kColTile) * kColTile;
   c.rows = ((c.N + c.M + kRowChunk - 1) / kRowChunk) * kRowChunk;
   const int NM = c.N + c.M;
@@ -1228,10 +1285,16 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   }
   c.timing[1] = seconds_since(t0);
 
-  // ---- device: templates, overlaps and windowed DFT at the nodes
+  // ---- device: templates, overlaps and windowed DFT at the nodes, per
+  // output block (detector, or detector and time band)
   t0 = Clock::now();
   const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
   const int64_t j_hi = c.n_s / 2;
+  double band_t[RBFL_MAX_BANDS][RBFL_MAX_MODES] = {};
+  if (c.n_bands > 1)
+    time_bands(c, psd[0], centre, c.band_edges, band_t);
+  else
+    c.band_edges = {j_lo, j_hi};
   std::vector<Binary> bins(c.N);
   int J_mode[RBFL_MAX_MODES] = {};
   for (int i = 0; i < c.N; ++i) {
@@ -1279,9 +1342,11 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   DevBuf<double> d_wk;
   d_wk.alloc(wk.size());
   RBFL_HIP(hipMemcpyAsync(d_wk.p, wk.data(), sizeof(double) * wk.size(), hipMemcpyHostToDevice, stream));
-  c.z_nodes.alloc((size_t)c.n_det * c.n_modes * c.N * c.T);
+  const int nm2 = c.n_modes * c.n_modes;
+  c.z_nodes.alloc((size_t)c.n_v * c.n_modes * c.N * c.T);
   DevBuf<double2> d_sig;
-  d_sig.alloc((size_t)c.n_det * c.N * c.n_modes * c.n_modes);
+  d_sig.alloc((size_t)c.n_v * c.N * nm2);
+  RBFL_HIP(hipMemsetAsync(d_sig.p, 0, sizeof(double2) * d_sig.n, stream));
   // node batches sized so the templates of a batch stay within ~8 GiB of the
   // 288 GB of HBM (the 2048 s third-generation case then takes 27 nodes per batch)
   const size_t budget = (size_t)8 << 30;
@@ -1289,14 +1354,16 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   DevBuf<double2> d_A;
   d_A.alloc((size_t)c.n_modes * nb_max * J);
   // split the bin range of the windowed DFT so each launch has >= ~1024 blocks
-  auto n_splits = [&](int nb, int a) {
+  // (a band's bins: no more splits than its whole mode's)
+  auto n_splits = [&](int nb, int len) {
     const int t_here = ((nb + 63) / 64) * ((c.T + 63) / 64);
-    return std::max(1, std::min((1024 + t_here - 1) / t_here, (J_mode[a] + 255) / 256));
+    return std::max(1, std::min((1024 + t_here - 1) / t_here, (len + 255) / 256));
   };
   size_t part_elems = 1;
   for (int base = 0; base < c.N; base += nb_max) {
     const int nb = std::min(nb_max, c.N - base);
-    for (int a = 0; a < c.n_modes; ++a) part_elems = std::max(part_elems, (size_t)n_splits(nb, a) * nb * c.T);
+    for (int a = 0; a < c.n_modes; ++a)
+      part_elems = std::max(part_elems, (size_t)n_splits(nb, J_mode[a]) * nb * c.T);
   }
   DevBuf<double2> d_part;
   d_part.alloc(part_elems);
@@ -1304,15 +1371,25 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   for (int base = 0; base < c.N; base += nb_max) {
     const int nb = std::min(nb_max, c.N - base);
     launch_waveforms(d_bins.p + base, nb, d_modes.p, c.n_modes, j_lo, J, c.df, 1.0 / (c.d_ref * kMpcS), d_A.p, stream);
-    launch_sigma(d_A.p, nb, c.n_modes, J, d_wk.p, c.n_det, c.N, base, d_sig.p, stream);
-    for (int a = 0; a < c.n_modes; ++a) {
-      if (J_mode[a] <= 0) continue;
-      const int n_split = n_splits(nb, a);
-      for (int k = 0; k < c.n_det; ++k) {
-        launch_window_dft(d_A.p + (size_t)a * nb * J, nb, J_mode[a], J, d_Dk.p + (size_t)k * J, j_lo, c.n_s, c.T,
-                          n_split, d_part.p, stream);
-        launch_reduce_splits(d_part.p, n_split, nb, c.T,
-                             c.z_nodes.p + (((size_t)k * c.n_modes + a) * c.N + base) * c.T, stream);
+    for (int b = 0; b < c.n_bands; ++b) {
+      // band b's bins, relative to j_lo, within the templates' extent
+      const int jb0 = (int)std::min<int64_t>(c.band_edges[b] - j_lo, J);
+      const int jb1 = (int)std::min<int64_t>(c.band_edges[b + 1] - j_lo, J);
+      if (jb1 <= jb0) continue;
+      // block v = k B + b: detector k's results at stride B N
+      launch_sigma(d_A.p, nb, c.n_modes, J, jb0, jb1, d_wk.p, c.n_det, (int64_t)c.n_bands * c.N, base,
+                   d_sig.p + (size_t)b * c.N * nm2, stream);
+      for (int a = 0; a < c.n_modes; ++a) {
+        const int len = std::min(J_mode[a], jb1) - jb0;
+        if (len <= 0) continue;
+        const int n_split = n_splits(nb, len);
+        for (int k = 0; k < c.n_det; ++k) {
+          const size_t v = (size_t)k * c.n_bands + b;
+          launch_window_dft(d_A.p + (size_t)a * nb * J + jb0, nb, len, J, d_Dk.p + (size_t)k * J + jb0, j_lo + jb0,
+                            c.n_s, c.T, n_split, d_part.p, stream);
+          launch_reduce_splits(d_part.p, n_split, nb, c.T, c.z_nodes.p + ((v * c.n_modes + a) * c.N + base) * c.T,
+                               stream);
+        }
       }
     }
   }
@@ -1321,13 +1398,13 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   d_part.reset();
   c.timing[2] = seconds_since(t0);
 
-  // ---- SVD per (detector, mode), all pairs in one batched call, and the
+  // ---- SVD per (block, mode), all pairs in one batched call, and the
   // coefficients at the nodes
   t0 = Clock::now();
   BlasHandle bh;
   blas_check(rocblas_set_stream(bh.h, stream), "rocblas_set_stream");
   const int mn = std::min(c.N, c.T);
-  const int n_pairs = c.n_det * c.n_modes;
+  const int n_pairs = c.n_v * c.n_modes;
   c.basis.alloc((size_t)n_pairs * c.T * c.q);
   DevBuf<double2> d_C;
   d_C.alloc((size_t)n_pairs * c.N * c.q);
@@ -1371,8 +1448,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   // ---- RBF system (Eq. rbfcoeff) and FP64 LU solve
   t0 = Clock::now();
   std::vector<int4> coldesc;
-  int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
-  for (int k = 0; k < c.n_det; ++k) {
+  int coef_off[RBFL_MAX_BLOCKS][RBFL_MAX_MODES], sig_off[RBFL_MAX_BLOCKS];
+  for (int k = 0; k < c.n_v; ++k) {
     for (int a = 0; a < c.n_modes; ++a) {
       coef_off[k][a] = (int)coldesc.size();
       for (int i = 0; i < c.q; ++i) {
@@ -1529,9 +1606,15 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   for (int k = 0; k < c.n_det; ++k) {
     for (int i = 0; i < 9; ++i) e.D[k][i] = c.D[k][i];
     for (int i = 0; i < 3; ++i) e.r[k][i] = c.r[k][i];
-    for (int a = 0; a < c.n_modes; ++a) e.coef_off[k][a] = coef_off[k][a];
-    e.sig_off[k] = sig_off[k];
   }
+  e.n_bands = c.n_bands;
+  e.n_v = c.n_v;
+  for (int v = 0; v < c.n_v; ++v) {
+    for (int a = 0; a < c.n_modes; ++a) e.coef_off[v][a] = coef_off[v][a];
+    e.sig_off[v] = sig_off[v];
+  }
+  for (int b = 0; b < RBFL_MAX_BANDS; ++b)
+    for (int a = 0; a < RBFL_MAX_MODES; ++a) e.band_t[b][a] = band_t[b][a];
   for (int a = 0; a < c.n_modes; ++a) {
     e.mode_l[a] = c.modes[a][0];
     e.mode_m[a] = c.modes[a][1];
@@ -1541,8 +1624,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   spline_table(e.spline);
   c.consts.alloc(1);
   RBFL_HIP(hipMemcpyAsync(c.consts.p, &e, sizeof(e), hipMemcpyHostToDevice, stream));
-  c.basis4.alloc((size_t)c.n_det * c.n_modes * c.T * c.q * 4);
-  launch_fold_spline(c.basis.p, c.n_det * c.n_modes, c.T, c.q, c.consts.p, c.basis4.p, stream);
+  c.basis4.alloc((size_t)c.n_v * c.n_modes * c.T * c.q * 4);
+  launch_fold_spline(c.basis.p, c.n_v * c.n_modes, c.T, c.q, c.consts.p, c.basis4.p, stream);
   c.nan_part.alloc(kNanParts);
   launch_count_nan(nullptr, 0, c.nan_part.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
@@ -1595,7 +1678,7 @@ static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hi
     const int nb = (int)std::min<int64_t>(nb_max, n - b0);
     launch_proposal_bins(c.consts.p, params, n, b0, nb, bins.p, s);
     launch_waveforms(bins.p, nb, d_modes.p, nm, j_lo, (int)J, c.df, 1.0 / (c.d_ref * kMpcS), A.p, s);
-    launch_sigma(A.p, nb, nm, (int)J, c.brute_w.p, nd, nb, 0, sig.p, s);
+    launch_sigma(A.p, nb, nm, (int)J, 0, (int)J, c.brute_w.p, nd, nb, 0, sig.p, s);
     const int n_split = n_splits(nb);
     for (int a = 0; a < nm; ++a)
       for (int k = 0; k < nd; ++k) {
@@ -2006,9 +2089,11 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     c.pipe = depths[bd];
     for (int d = 0; d < 4; ++d) c.pipe_ms[d] = pm[d];
     // then ln L finished inside the contraction, kept if 1% faster still
-    c.lnl_gemm = true;
+    // (frozen patterns only: its per-proposal setup has one arrival time per
+    // detector)
+    c.lnl_gemm = c.n_bands == 1;
     double fm = 1e300;
-    for (int round = 0; round < 2; ++round) {
+    for (int round = 0; round < 2 && c.lnl_gemm; ++round) {
       if (round == 0) eval_range(c, params, n, nb, out.p, form, s);
       double t[3];
       for (int r = 0; r < 3; ++r) {
@@ -2023,7 +2108,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
       std::sort(t, t + 3);
       fm = std::min(fm, t[1]);
     }
-    c.lnl_gemm_ms = fm;
+    c.lnl_gemm_ms = fm < 1e300 ? fm : 0.0;
     c.lnl_gemm = fm < 0.99 * pm[bd];
     if (c.lnl_gemm) {
       c.pipe = 1;
@@ -2300,6 +2385,17 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
     case RBFL_Q_EPS:
       copy_out(out, bytes, &c.eps, sizeof(double));
       return;
+    case RBFL_Q_BANDS: {
+      // B, blocks, edges [B + 1], band times [B][n_modes]
+      std::vector<double> v;
+      v.push_back(c.n_bands);
+      v.push_back(c.n_v);
+      for (int64_t e : c.band_edges) v.push_back((double)e);
+      for (int b = 0; b < c.n_bands; ++b)
+        for (int a = 0; a < c.n_modes; ++a) v.push_back(c.host_consts.band_t[b][a]);
+      copy_out(out, bytes, v.data(), sizeof(double) * v.size());
+      return;
+    }
     case RBFL_Q_F_REF:
       copy_out(out, bytes, &c.f_ref, sizeof(double));
       return;
@@ -3020,6 +3116,7 @@ static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t
   int64_t yelems = 0, belems = 0;
   for (int e = 0; e < n_ev; ++e) {
     require(hs[e] != nullptr, "NULL handle in the event list");
+    require(hs[e]->c.n_bands == 1, "multi-event plans cover frozen antenna patterns only (n_bands = 1)");
     require(counts[e] >= 1, "every event needs at least one proposal");
     p.ctx.push_back(&hs[e]->c);
     p.counts.push_back(counts[e]);
@@ -3135,6 +3232,7 @@ int32_t rbfl_exact_parts(rbfl_handle h, const double *params, int64_t n, double 
     rbfl::require(h != nullptr, "handle is NULL");
     rbfl::require(params != nullptr && out != nullptr, "params/out is NULL");
     rbfl::require(n >= 0 && n <= 2147483647, "n must be in 0 .. 2^31 - 1");
+    rbfl::require(h->c.n_bands == 1, "rbfl_exact_parts covers frozen antenna patterns only (n_bands = 1)");
     rbfl::exact_parts(h->c, params, n, out, reinterpret_cast<hipStream_t>(stream));
   });
 }
@@ -3200,6 +3298,7 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant) {
 int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(!(on && h->c.n_bands > 1), "the fused epilogue covers frozen antenna patterns only (n_bands = 1)");
     h->c.lnl_gemm = on != 0;
   });
 }
@@ -3278,6 +3377,7 @@ int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t 
 int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(h->c.n_bands == 1, "the surrogate covers frozen antenna patterns only (n_bands = 1)");
     rbfl::surrogate_train(h->c, spec, reinterpret_cast<hipStream_t>(stream));
   });
 }

@@ -71,7 +71,11 @@ struct EvalConsts {
   double earth_rate;                        // Earth rotation [rad/s] in the exact likelihood (0: frozen)
   double theta_c[4], V[16], semi[4];        // V row-major: Theta_i = theta_c_i + sum_j V[i][j] de_j
   double D[RBFL_MAX_DET][9], r[RBFL_MAX_DET][3];
-  int coef_off[RBFL_MAX_DET][RBFL_MAX_MODES], sig_off[RBFL_MAX_DET];
+  // blocks of interpolated outputs: detector k (frozen patterns, n_bands = 1)
+  // or (detector k, band b) as block v = k n_bands + b (time bands)
+  int n_bands, n_v;
+  int coef_off[RBFL_MAX_BLOCKS][RBFL_MAX_MODES], sig_off[RBFL_MAX_BLOCKS];
+  double band_t[RBFL_MAX_BANDS][RBFL_MAX_MODES];   // time of each (band, mode) relative to t_c
   int mode_l[RBFL_MAX_MODES], mode_m[RBFL_MAX_MODES];
   YlmTerms ylm_neg[RBFL_MAX_MODES];         // -2Y_{l,-m}
   YlmTerms ylm_pos[RBFL_MAX_MODES];         // -2Y_{l,m}
@@ -157,6 +161,8 @@ struct Ctx {
   int device = 0;              // the device current at rbfl_build / rbfl_load; every artefact lives there
   // sizes and scalars
   int n_det = 0, n_modes = 0;
+  int n_bands = 1, n_v = 0;    // time bands of the antenna patterns; output blocks n_det * n_bands
+  std::vector<int64_t> band_edges;   // [n_bands + 1] bin index of each band's first bin, then the end
   int modes[RBFL_MAX_MODES][2] = {};
   int N = 0, M = 0, K = 0, Kp = 0, rows = 0, q = 0, T = 0, half_w = 0, degree = 0;
   int64_t n_s = 0, n_f = 0;
@@ -178,9 +184,9 @@ struct Ctx {
   DevBuf<EvalConsts> consts;
   DevBuf<double> nodes;        // [rows][4] unit-ball coordinates, zero-padded
   DevBuf<double> W;            // [rows][Kp] RBF weights, zero-padded
-  DevBuf<double2> basis;       // [n_det][n_modes][T][q]
-  DevBuf<double2> basis4;      // spline-folded basis [n_det][n_modes][T][q][4]
-  DevBuf<double2> z_nodes;     // [n_det][n_modes][N][T] (kept for export)
+  DevBuf<double2> basis;       // [n_v][n_modes][T][q]
+  DevBuf<double2> basis4;      // spline-folded basis [n_v][n_modes][T][q][4]
+  DevBuf<double2> z_nodes;     // [n_v][n_modes][N][T] (kept for export)
   DevBuf<double2> brute_D;     // exact ln L: 4 df d_k / S_k over bins j_lo .. n_s/2 - 1, [n_det][brute_J]
   DevBuf<double> brute_w;      // exact ln L: 4 df / S_k, [n_det][brute_J]
   int64_t brute_j_lo = 0, brute_J = 0;
@@ -261,8 +267,8 @@ struct Ctx {
 // ---- start-up kernels (build_kernels.hip) ----
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
                       double df, double inv_dref_s, double2 *out, hipStream_t s);
-void launch_sigma(const double2 *A, int nb, int n_modes, int J, const double *wk, int n_det, int N_total,
-                  int node_base, double2 *sig, hipStream_t s);
+void launch_sigma(const double2 *A, int nb, int n_modes, int J, int j0, int j1, const double *wk, int n_det,
+                  int64_t det_stride, int node_base, double2 *sig, hipStream_t s);
 void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
                        int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s);
 void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, double2 *Z_rows, hipStream_t s);

@@ -44,6 +44,7 @@ enum Tag : uint32_t {
   kBruteD,
   kBruteW,
   kColdesc,
+  kBands,
   kTagEnd
 };
 
@@ -52,6 +53,7 @@ enum Tag : uint32_t {
 struct Scalars {
   int32_t n_det, n_modes, modes[RBFL_MAX_MODES][2];
   int32_t N, M, K, Kp, rows, q, T, half_w, degree;
+  int32_t n_bands, n_v;
   int64_t n_s, n_f, brute_j_lo, brute_J;
   double fs, seg_len, f_low, df, eps, chi_max, t_trig, d_ref, match, f_ref, earth_rate;
   double squeeze[2], centre_opt[6], centre_snr[2];
@@ -121,6 +123,8 @@ void save(const Ctx &c, const char *path) {
   sc.T = c.T;
   sc.half_w = c.half_w;
   sc.degree = c.degree;
+  sc.n_bands = c.n_bands;
+  sc.n_v = c.n_v;
   sc.n_s = c.n_s;
   sc.n_f = c.n_f;
   sc.brute_j_lo = c.brute_j_lo;
@@ -165,6 +169,7 @@ void save(const Ctx &c, const char *path) {
   secs.push_back(device_section(kBruteD, c.brute_D));
   secs.push_back(device_section(kBruteW, c.brute_w));
   secs.push_back(device_section(kColdesc, c.coldesc));
+  secs.push_back(host_section(kBands, c.band_edges.data(), c.band_edges.size()));
 
   // written to a temporary name and renamed, so that a failed save leaves no
   // partial file under `path`
@@ -292,21 +297,23 @@ void load(const char *path, hipStream_t st, Ctx &c) {
     corrupt("sizes");
   static const int kMonomials[4] = {1, 5, 15, 35};
   if (sc.M != kMonomials[sc.degree]) corrupt("sizes");
-  if (sc.K != sc.n_det * (2 * sc.q * sc.n_modes + sc.n_modes * sc.n_modes)) corrupt("sizes");
+  if (sc.n_bands < 1 || sc.n_bands > RBFL_MAX_BANDS || sc.n_v != sc.n_det * sc.n_bands || sc.n_v > RBFL_MAX_BLOCKS)
+    corrupt("sizes");
+  if (sc.K != sc.n_v * (2 * sc.q * sc.n_modes + sc.n_modes * sc.n_modes)) corrupt("sizes");
   if (sc.Kp != ((sc.K + kColTile - 1) / kColTile) * kColTile) corrupt("sizes");
   if (sc.rows != ((sc.N + sc.M + kRowChunk - 1) / kRowChunk) * kRowChunk) corrupt("sizes");
   if (sc.n_s < 16 || sc.n_f != sc.n_s / 2 + 1 || sc.brute_J < 0 || sc.brute_j_lo < 1 ||
       sc.brute_j_lo + sc.brute_J > sc.n_s / 2 + 1)
     corrupt("sizes");
   const int mn = sc.N < sc.T ? sc.N : sc.T;
-  const size_t pairs = (size_t)sc.n_det * sc.n_modes;
+  const size_t pairs = (size_t)sc.n_v * sc.n_modes;
   EvalConsts ec;
   std::memcpy(&ec, need(kConsts, sizeof(EvalConsts), 1).data.data(), sizeof(EvalConsts));
   if (ec.n_det != sc.n_det || ec.n_modes != sc.n_modes || ec.N != sc.N || ec.M != sc.M || ec.K != sc.K ||
       ec.Kp != sc.Kp || ec.rows != sc.rows || ec.q != sc.q || ec.T != sc.T || ec.half_w != sc.half_w ||
-      ec.degree != sc.degree)
+      ec.degree != sc.degree || ec.n_bands != sc.n_bands || ec.n_v != sc.n_v)
     corrupt("constants disagree with the sizes");
-  for (int k = 0; k < sc.n_det; ++k) {
+  for (int k = 0; k < sc.n_v; ++k) {
     if (ec.sig_off[k] < 0 || ec.sig_off[k] + sc.n_modes * sc.n_modes > sc.K) corrupt("output layout");
     for (int a = 0; a < sc.n_modes; ++a)
       if (ec.coef_off[k][a] < 0 || ec.coef_off[k][a] + 2 * sc.q > sc.K) corrupt("output layout");
@@ -323,6 +330,12 @@ void load(const char *path, hipStream_t st, Ctx &c) {
   const Section &bd = need(kBruteD, sizeof(double2), (uint64_t)sc.n_det * sc.brute_J);
   const Section &bw = need(kBruteW, sizeof(double), (uint64_t)sc.n_det * sc.brute_J);
   const Section &cd = need(kColdesc, sizeof(int4), (uint64_t)sc.K);
+  const Section &be = need(kBands, sizeof(int64_t), (uint64_t)sc.n_bands + 1);
+  std::vector<int64_t> edges;
+  to_vector(edges, be);
+  if (edges.front() != sc.brute_j_lo || edges.back() != sc.n_s / 2) corrupt("band edges");
+  for (int b = 0; b < sc.n_bands; ++b)
+    if (edges[b + 1] < edges[b]) corrupt("band edges");
 
   RBFL_HIP(hipGetDevice(&c.device));
   c.n_det = sc.n_det;
@@ -337,6 +350,9 @@ void load(const char *path, hipStream_t st, Ctx &c) {
   c.T = sc.T;
   c.half_w = sc.half_w;
   c.degree = sc.degree;
+  c.n_bands = sc.n_bands;
+  c.n_v = sc.n_v;
+  c.band_edges = edges;
   c.n_s = sc.n_s;
   c.n_f = sc.n_f;
   c.brute_j_lo = sc.brute_j_lo;

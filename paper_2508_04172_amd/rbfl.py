@@ -17,9 +17,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbfl.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 MAX_MODES = 5
 MAX_DET = 4
+MAX_BANDS = 16
+MAX_BLOCKS = 64
 
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NUMERICAL, E_UNSUPPORTED, E_STATE = range(7)
 FORM_FP64, FORM_FP32, FORM_BF16, FORM_SPLIT, FORM_SURROGATE = range(5)
@@ -27,7 +29,7 @@ FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
-    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT, Q_SURROGATE_BASE, Q_EPS = range(25)
+    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT, Q_SURROGATE_BASE, Q_EPS, Q_BANDS = range(26)
 SPLIT_TOL = 1e-4
 STATIC_SCRATCH_BYTES = 128 << 20
 
@@ -75,6 +77,7 @@ class BuildSpec(C.Structure):
         ("flags", C.c_uint32),
         ("f_ref", C.c_double),
         ("earth_rate", C.c_double),
+        ("n_bands", C.c_int32),
     ]
 
 
@@ -285,6 +288,7 @@ def spec_from_config(cfg, white: Optional[np.ndarray], inj_ext, metric: Optional
                | (FLAG_OPTIMISE_CENTRE if getattr(cfg, "optimise_centre", False) else 0))
     s.f_ref = cfg.f_ref
     s.earth_rate = getattr(cfg, "earth_rate", 0.0)
+    s.n_bands = getattr(cfg, "n_bands", 1)
     return s
 
 
@@ -413,7 +417,7 @@ class Handle:
 
     def basis(self) -> np.ndarray:
         s = self.sizes()
-        v = self._query(Q_BASIS, (s["n_det"], s["n_modes"], s["T"], s["q"], 2))
+        v = self._query(Q_BASIS, (self.n_blocks(), s["n_modes"], s["T"], s["q"], 2))
         return v[..., 0] + 1j * v[..., 1]
 
     def node_values(self) -> np.ndarray:
@@ -422,11 +426,11 @@ class Handle:
 
     def singular(self) -> np.ndarray:
         s = self.sizes()
-        return self._query(Q_SINGULAR, (s["n_det"], s["n_modes"], min(s["N"], s["T"])))
+        return self._query(Q_SINGULAR, (self.n_blocks(), s["n_modes"], min(s["N"], s["T"])))
 
     def z_nodes(self) -> np.ndarray:
         s = self.sizes()
-        v = self._query(Q_Z_NODES, (s["n_det"], s["n_modes"], s["N"], s["T"], 2))
+        v = self._query(Q_Z_NODES, (self.n_blocks(), s["n_modes"], s["N"], s["T"], 2))
         return v[..., 0] + 1j * v[..., 1]
 
     def cond(self) -> float:
@@ -435,6 +439,20 @@ class Handle:
     def eps(self) -> float:
         """The interpolants' Gaussian shape parameter (RBFL_Q_EPS; chosen by the library when the spec's is 0)."""
         return float(self._query(Q_EPS, 1)[0])
+
+    def bands(self):
+        """Time bands of the antenna patterns (RBFL_Q_BANDS): (bin edges [B + 1]
+        int64, band times [B][n_modes]), or None for frozen patterns (B = 1)."""
+        n_modes = self.sizes()["n_modes"]
+        v = self._query(Q_BANDS, 2 + (MAX_BANDS + 1) + MAX_BANDS * MAX_MODES)
+        B = int(v[0])
+        if B == 1:
+            return None
+        return v[2:B + 3].astype(np.int64), v[B + 3:B + 3 + B * n_modes].reshape(B, n_modes).copy()
+
+    def n_blocks(self) -> int:
+        """Blocks of interpolated outputs: detectors, or (detector, band) pairs."""
+        return int(self._query(Q_BANDS, 2 + (MAX_BANDS + 1) + MAX_BANDS * MAX_MODES)[1])
 
     def exports(self) -> dict:
         """Every artefact the online stage evaluates with, as host arrays (the
@@ -445,7 +463,7 @@ class Handle:
                 "semi": fr["semi"], "x_nodes": self.nodes(), "phys_nodes": self.node_phys(), "W": self.weights(),
                 "basis": self.basis(), "half_w": self.sizes()["half_w"], "d_ref": self.d_ref(),
                 "f_ref": self.f_ref(), "eps": self.eps(), "cond": self.cond(), "singular": self.singular(),
-                "node_values": self.node_values()}
+                "node_values": self.node_values(), "bands": self.bands()}
 
     def timing(self) -> np.ndarray:
         return self._query(Q_TIMING, 8)

@@ -97,9 +97,10 @@ class Config:
 
     @property
     def n_out(self) -> int:
-        """Interpolated real outputs per query: per detector 2q per mode + n^2 overlap reals."""
+        """Interpolated real outputs per query: per detector (and time band) 2q
+        per mode + n^2 overlap reals."""
         n = len(self.modes)
-        return self.n_det * (2 * self.q * n + n * n)
+        return self.n_det * max(1, self.n_bands) * (2 * self.q * n + n * n)
 
     @property
     def seed_phys(self) -> Tuple[float, float, float, float]:
@@ -141,7 +142,15 @@ SMALL_MULTI = CFG2.with_(name="small_hlv_3mode", fs=2048.0, seg_len=8.0,
                          modes=ALL_MODES[:3], n_nodes=150, q=12, n_queries=3000,
                          tc_span=0.027)
 
-CONFIGS = {c.name: c for c in (CFG1, CFG2, CFG3, CFG5, SMALL_MULTI)}
+# Long signals on a rotating Earth: the source's Earth-fixed longitude drifts
+# during the signal.  The small case turns the Earth fast (2e-2 rad/s, 0.1 rad
+# over its 5.6 s signal) so that a few time bands matter at 8 s of data; the
+# third-generation case rotates at the sidereal rate over its 1694 s signal.
+SIDEREAL = 7.2921150e-5
+SMALL_BANDED = SMALL_MULTI.with_(name="small_hlv_banded", earth_rate=2e-2, n_bands=4)
+CFG5_ROTATING = CFG5.with_(name="cfg5_triangle_rotating", earth_rate=SIDEREAL)
+
+CONFIGS = {c.name: c for c in (CFG1, CFG2, CFG3, CFG5, SMALL_MULTI, SMALL_BANDED, CFG5_ROTATING)}
 
 
 # ----------------------------------------------------------------------------
