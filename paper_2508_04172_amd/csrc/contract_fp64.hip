@@ -415,9 +415,7 @@ __global__ void __launch_bounds__(64 * WQ * WC, 512 / (64 * WQ * WC))
     const int64_t item = item_s;
     __syncthreads();
     if (item >= total_items) break;
-    int e = 0;
-    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
-    const EventDesc &d = ev[e];
+    const EventDesc &d = ev[work_event(ev, n_ev, item)];
     const int64_t local = item - d.item0;
     gemm_tile<RT, CT, KC, WQ, WC>(d.Bt, d.n, d.ldb, d.rows, d.W, d.Kp, d.Y, local / d.tiles_c,
                                   (int)(local % d.tiles_c));

@@ -331,9 +331,7 @@ __global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
     const int64_t item = item_s;
     __syncthreads();
     if (item >= total_items) break;
-    int e = 0;
-    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
-    const EventDesc &d = ev[e];
+    const EventDesc &d = ev[work_event(ev, n_ev, item)];
     const int64_t local = item - d.item0;
     split_tile<S>(static_cast<const v4i *>(d.AS), d.n, d.rows, static_cast<const v4i *>(d.BS), d.cscale, d.rscale,
                   d.Kp, d.Y, (local / d.tiles_c) * kSplitQ, (int)(local % d.tiles_c) * kSplitC);

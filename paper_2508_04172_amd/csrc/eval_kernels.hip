@@ -569,9 +569,7 @@ __global__ void __launch_bounds__(kThreads) k_ragged_contract_fp64(const EventDe
     const int64_t item = item_s;
     __syncthreads();
     if (item >= total_items) break;
-    int e = 0;
-    while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
-    const EventDesc &d = ev[e];
+    const EventDesc &d = ev[work_event(ev, n_ev, item)];
     const int64_t local = item - d.item0;
     const int tq = (int)(local % d.tiles_q);
     const int tc = (int)(local / d.tiles_q);

@@ -1127,6 +1127,65 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
   c.centre_snr[1] = sqrt(std::max(v, 0.0));
 }
 
+// ---- RBFL_DEBUG: host-side bounds checks of everything the kernels index
+// with.  With the environment variable RBFL_DEBUG set (to anything but "0"),
+// every handle's output layout, sizes, band table and device constants are
+// checked after rbfl_build and rbfl_load, and every work item of a
+// multi-event plan is replayed through the kernels' own event lookup
+// (work_event) against the plan's buffers; the first violation is
+// RBFL_E_STATE.  The epilogues' spline stencils need no table: a stencil
+// outside the window marks the proposal -inf before any row is read.
+
+bool debug_mode() {
+  const char *v = std::getenv("RBFL_DEBUG");
+  return v != nullptr && *v != 0 && std::strcmp(v, "0") != 0;
+}
+
+static void debug_require(bool ok, const std::string &what) {
+  if (!ok) throw Error(RBFL_E_STATE, "RBFL_DEBUG: " + what);
+}
+
+void debug_check_layout(const Ctx &c) {
+  const EvalConsts &e = c.host_consts;
+  const int nm = c.n_modes, q = c.q;
+  debug_require(c.n_v == c.n_det * c.n_bands && c.n_v >= 1 && c.n_v <= RBFL_MAX_BLOCKS && e.n_v == c.n_v &&
+                    e.n_bands == c.n_bands && e.n_det == c.n_det && e.n_modes == nm,
+                "block counts");
+  debug_require(c.K == c.n_v * (2 * q * nm + nm * nm) && e.K == c.K && c.Kp >= c.K && c.Kp % kColTile == 0,
+                "output width");
+  // every output column in exactly one (block, mode) coefficient range or one
+  // block's overlap range
+  std::vector<int> cover((size_t)c.K, 0);
+  auto mark = [&](int off, int len, const char *what) {
+    debug_require(off >= 0 && off + len <= c.K, std::string(what) + " offset out of range");
+    for (int i = off; i < off + len; ++i) ++cover[(size_t)i];
+  };
+  for (int v = 0; v < c.n_v; ++v) {
+    for (int a = 0; a < nm; ++a) mark(e.coef_off[v][a], 2 * q, "coefficient");
+    mark(e.sig_off[v], nm * nm, "overlap");
+  }
+  for (int x : cover) debug_require(x == 1, "output columns not covered exactly once");
+  // buffers the epilogues and contractions index
+  const size_t pairs = (size_t)c.n_v * nm;
+  debug_require(c.T >= 11 && e.T == c.T && e.q == q, "window too short for the 10-tap spline stencil");
+  debug_require(c.basis.n == pairs * c.T * q && c.basis4.n == pairs * c.T * q * 4, "basis sizes");
+  debug_require(c.W.n == (size_t)c.rows * c.Kp && c.nodes.n == (size_t)c.rows * 4 && c.coldesc.n == (size_t)c.K,
+                "weight, node or layout sizes");
+  debug_require(c.rows >= c.N + c.M && c.rows % kRowChunk == 0, "padded rows");
+  // band table
+  debug_require((int)c.band_edges.size() == c.n_bands + 1 && c.band_edges.front() == c.brute_j_lo &&
+                    c.band_edges.back() == c.n_s / 2,
+                "band edges");
+  for (int b = 0; b < c.n_bands; ++b) {
+    debug_require(c.band_edges[b + 1] >= c.band_edges[b], "band edges decrease");
+    for (int a = 0; a < nm; ++a) debug_require(std::isfinite(e.band_t[b][a]), "band time not finite");
+  }
+  // the device copy of the constants is the host's
+  EvalConsts d;
+  RBFL_HIP(hipMemcpy(&d, c.consts.p, sizeof(EvalConsts), hipMemcpyDeviceToHost));
+  debug_require(std::memcmp(&d, &e, sizeof(EvalConsts)) == 0, "device constants differ from the host copy");
+}
+
 static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   const auto t_all = Clock::now();
   validate(s);
@@ -1630,6 +1689,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   launch_count_nan(nullptr, 0, c.nan_part.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
   c.timing[5] = seconds_since(t_all);
+  if (debug_mode()) debug_check_layout(c);
 }
 
 // The quantities the interpolants approximate, computed exactly at each
@@ -2569,6 +2629,55 @@ struct Plan {
   }
 };
 
+// A plan's caller-order descriptors d and its work lists (work order, one
+// per group of items): proposal ranges partition [0, total), each event's
+// rows of the shared buffers lie inside them without overlap, and every
+// work item maps through work_event to a tile inside its event.
+static void debug_check_plan(const Plan &p, const std::vector<EventDesc> &d,
+                             const std::vector<std::pair<std::vector<EventDesc>, int64_t>> &lists) {
+  const int n_ev = (int)d.size();
+  int64_t q0 = 0;
+  const double *y_end = p.Y.p;
+  const double *b_end = p.Bt.p;
+  for (int e = 0; e < n_ev; ++e) {
+    const EventDesc &x = d[e];
+    const Ctx &c = *p.ctx[e];
+    debug_require(x.q0 == q0 && x.n == p.counts[e] && x.n >= 1, "proposal ranges");
+    debug_require(x.Kp == c.Kp && x.rows == c.rows && x.consts == c.consts.p && x.W == c.W.p, "event constants");
+    debug_require(x.Y == y_end && x.Y + x.n * x.Kp <= p.Y.p + p.Y.n, "output rows outside the plan's buffer");
+    y_end = x.Y + x.n * x.Kp;
+    if (!p.split) {
+      debug_require(x.Bt == b_end && x.ldb >= x.n && x.Bt + (int64_t)x.rows * x.ldb <= p.Bt.p + p.Bt.n,
+                    "basis rows outside the plan's buffer");
+      b_end = x.Bt + (int64_t)x.rows * x.ldb;
+    } else {
+      const int8_t *as = static_cast<const int8_t *>(x.AS);
+      debug_require(x.S >= 5 && x.S <= split_max_slices() && as >= p.AS.p &&
+                        as + (int64_t)split_max_slices() * x.rows * x.n <= p.AS.p + p.AS.n &&
+                        x.rscale == p.rscale.p + x.q0 && x.q0 + x.n <= (int64_t)p.rscale.n,
+                    "digit rows outside the plan's buffers");
+    }
+    q0 += x.n;
+  }
+  debug_require(q0 == p.total, "proposal ranges do not cover the batch");
+  for (const auto &lw : lists) {
+    const std::vector<EventDesc> &w = lw.first;
+    const int nw = (int)w.size();
+    int64_t next = 0;
+    for (int i = 0; i < nw; ++i) {
+      debug_require(w[i].item0 == next && w[i].tiles_q >= 1 && w[i].tiles_c >= 1, "work list ranges");
+      next += (int64_t)w[i].tiles_q * w[i].tiles_c;
+    }
+    debug_require(next == lw.second, "work list length");
+    for (int64_t item = 0; item < lw.second; ++item) {
+      const int e = work_event(w.data(), nw, item);
+      const int64_t local = item - w[e].item0;
+      debug_require(e >= 0 && e < nw && local >= 0 && local < (int64_t)w[e].tiles_q * w[e].tiles_c,
+                    "work item " + std::to_string(item) + " outside its event's tiles");
+    }
+  }
+}
+
 // Event descriptors for tile variant v: caller order (for the epilogue) and
 // decreasing-cost order with consecutive work-item ranges (for the persistent
 // contraction).  Cost of an event = proposals x (N+M) x K.
@@ -2619,6 +2728,7 @@ static void plan_layout(Plan &p, int v, hipStream_t s) {
   RBFL_HIP(hipGetDevice(&dev));
   RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.total_items, (int64_t)cus * ragged_blocks_per_cu(v)));
+  if (debug_mode()) debug_check_plan(p, d, {{w, p.total_items}});
   RBFL_HIP(hipMemcpyAsync(p.ev_work.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
   RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
   RBFL_HIP(hipStreamSynchronize(s));
@@ -2691,6 +2801,13 @@ static void plan_layout_split(Plan &p, hipStream_t s) {
   for (int g = 0; g < p.n_groups; ++g) {
     p.total_items += p.group_items[g];
     p.grid = std::max(p.grid, p.group_grid[g]);
+  }
+  if (debug_mode()) {
+    std::vector<std::pair<std::vector<EventDesc>, int64_t>> lists;
+    for (int g = 0; g < p.n_groups; ++g)
+      lists.push_back({std::vector<EventDesc>(w.begin() + p.group_off[g], w.begin() + p.group_off[g] + p.group_n[g]),
+                       p.group_items[g]});
+    debug_check_plan(p, d, lists);
   }
   RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
   RBFL_HIP(hipMemcpyAsync(p.ev_group.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));

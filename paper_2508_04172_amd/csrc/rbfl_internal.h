@@ -104,6 +104,16 @@ struct EventDesc {
   int64_t t0;            // first thread of this event in the digit-row kernel's flat grid
 };
 
+// The event of work item `item` in a work list (events in work order, each
+// with the first item of its consecutive range): the last event whose first
+// item is <= item.  The persistent kernels and the host's bounds check
+// (RBFL_DEBUG) share it.
+__host__ __device__ inline int work_event(const EventDesc *ev, int n_ev, int64_t item) {
+  int e = 0;
+  while (e + 1 < n_ev && ev[e + 1].item0 <= item) ++e;
+  return e;
+}
+
 template <class T>
 struct DevBuf {
   T *p = nullptr;
@@ -263,6 +273,10 @@ struct Ctx {
     if (side) (void)hipStreamDestroy(side);
   }
 };
+
+// RBFL_DEBUG host-side bounds checks (rbfl_host.hip)
+bool debug_mode();
+void debug_check_layout(const Ctx &c);
 
 // ---- start-up kernels (build_kernels.hip) ----
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,

@@ -398,6 +398,7 @@ void load(const char *path, hipStream_t st, Ctx &c) {
   c.nan_part.alloc(kNanParts);
   launch_count_nan(nullptr, 0, c.nan_part.p, st);
   RBFL_HIP(hipStreamSynchronize(st));
+  if (debug_mode()) debug_check_layout(c);
 }
 
 }  // namespace

@@ -186,3 +186,33 @@ def test_banded_save_load_round_trip(tmp_path):
     e1, t1 = h.bands()
     e2, t2 = h2.bands()
     assert np.array_equal(e1, e2) and np.array_equal(t1, t2)
+
+
+@pytest.mark.timeout(900)
+def test_banded_third_generation_eval_parity_sampled():
+    """The third-generation workload on a rotating Earth (sidereal rate, N =
+    3000, q = 80, five modes, three detectors) with 16 bands: K = 39600
+    outputs.  The oracle's banded online stage on the handle's exported
+    artefacts against the library on 300 seeded near-node proposals of a
+    1e5-proposal launch: same domain flags, max |d ln L| <= 1e-3."""
+    cfg = wl.CFG5_ROTATING.with_(name="cfg5_rotating_b16", n_bands=16)
+    torch = _torch()
+    h = handle(cfg)
+    assert h.sizes()["K"] == cfg.n_out == 39600
+    n = 100_000
+    idx, jit = wl.node_jitter(n, cfg.n_nodes)
+    P = np.ascontiguousarray(rbfl.params_soa(h, wl.queries(cfg, n=n).near_nodes(h.nodes(), idx, jit), cfg.t_trig))
+    lg = run(h, P)
+    art = su.artefacts_from_exports(cfg, wl.injection_extrinsics(cfg), **h.exports())
+    sample = np.sort(np.random.default_rng(17).choice(n, 300, replace=False))
+    ps = P[:, sample]
+    lo = lk.meshfree_lnl(art, ps[0:4].T.copy(), ps[4:9].T.copy(), ps[9].copy(), ps[10].copy())
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg[sample]))
+    assert fin.sum() >= 100
+    d = np.abs(lg[sample][fin] - lo[fin])
+    print(f"[banded] third generation, 16 bands: max |dlnL| vs oracle {d.max():.3e} on {fin.sum()} proposals",
+          flush=True)
+    assert d.max() <= 1e-3
+    _cache.pop(cfg.name).close()
+    del torch

@@ -231,3 +231,46 @@ def test_fp64_plan_8_wave_tile_matches_per_event():
         assert np.array_equal(fin, np.isfinite(got)), f"variant {v}"
         assert np.abs(got[fin] - want[fin]).max() <= 1e-12 * max(1.0, np.abs(want[fin]).max()), f"variant {v}"
     plan.close()
+
+
+def test_debug_bounds_checks_pass_on_every_layout(monkeypatch, tmp_path):
+    """With RBFL_DEBUG set, the library checks on the host every offset its
+    kernels index with -- each handle's output layout and device constants
+    after build and load, and every work item of the FP64 plan (all six tile
+    variants) and of the split plan replayed through the kernels' event
+    lookup -- and raises RBFL_E_STATE on a violation.  Every layout here
+    passes, and the results are those of the unchecked run."""
+    torch = _torch()
+    hs, _ = events()
+    total = sum(COUNTS)
+    params, _ = proposals(9)
+    p = torch.from_numpy(params).cuda()
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    want = per_event_gpu(hs, params)
+    fin = np.isfinite(want)
+    monkeypatch.setenv("RBFL_DEBUG", "1")
+    # build and load under the checks (one small event, and a banded handle)
+    cfg = EVENTS[2]
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    h.save(str(tmp_path / "e.rbfl"))
+    rbfl.Handle.load(str(tmp_path / "e.rbfl")).close()
+    h.close()
+    bcfg = wl.SMALL_BANDED.with_(name="debug_banded", seg_len=4.0, n_nodes=80, q=10, n_bands=3)
+    rbfl.Handle.from_config(bcfg, wl.white_noise(bcfg), wl.injection_extrinsics(bcfg)).close()
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), rbfl.PLAN_AUTOTUNE, stream)
+    for v in range(6):
+        plan.set_variant(v, stream)
+        plan.launch(stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(fin, np.isfinite(got))
+        assert np.abs(got[fin] - want[fin]).max() <= 1e-12 * max(1.0, np.abs(want[fin]).max())
+    plan.close()
+    plan = rbfl.Plan(hs, COUNTS, p.data_ptr(), out.data_ptr(), rbfl.PLAN_SPLIT, stream)
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.abs(got[fin] - want[fin]).max() <= 1e-3
+    plan.close()
