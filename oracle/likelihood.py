@@ -223,17 +223,17 @@ def domain(art: Artefacts, x: np.ndarray) -> np.ndarray:
 
 def virtual_detectors(art: Artefacts, alpha, t_c):
     """The blocks of interpolated outputs, each with its detector and the
-    right ascension every mode sees there: without time bands block k is
+    right ascensions its modes see, grouped: without time bands block k is
     detector k with the source's alpha for all modes (patterns frozen,
     Sec. II B); with B time bands block v = k B + b is detector k over band
     b, mode a at band_alpha(alpha, t_c, t_ba).  Returns [(detector,
-    [alpha per mode])]."""
+    [(alpha, mode indices)])]."""
     ev = art.ev
     n_modes = len(ev.modes)
     if art.bands is None:
-        return [(k, [alpha] * n_modes) for k in range(ev.n_det)]
+        return [(k, [(alpha, list(range(n_modes)))]) for k in range(ev.n_det)]
     times = art.bands[1]
-    return [(k, [band_alpha(ev, alpha, t_c, times[b, a]) for a in range(n_modes)])
+    return [(k, [(band_alpha(ev, alpha, t_c, times[b, a]), [a]) for a in range(n_modes)])
             for k in range(ev.n_det) for b in range(times.shape[0])]
 
 
@@ -260,13 +260,14 @@ def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np
     lnl = np.zeros(n_q)
     zs = np.zeros((n_q, len(blocks), n_modes), dtype=np.complex128)
     sigs = np.zeros((n_q, len(blocks), n_modes, n_modes), dtype=np.complex128)
-    for k, (det, als) in enumerate(blocks):
+    for k, (det, groups) in enumerate(blocks):
         A = np.zeros((n_q, n_modes), dtype=np.complex128)
-        for a in range(n_modes):
-            # antenna factor and arrival-time stencil of mode a in block k
-            fp, fc = antenna_patterns(ev.det_tensor[det], als[a], dec, psi)
-            A[:, a] = mode_factors(ev.modes, fp, fc, iota, phi)[:, a]
-            s = (t_c + time_delays(ev.det_pos[det], als[a], dec) - ev.t_trig) * ev.grid.fs + art.half_w
+        for al, members in groups:
+            # antenna factors and arrival-time stencil of the modes that see
+            # right ascension al in block k
+            fp, fc = antenna_patterns(ev.det_tensor[det], al, dec, psi)
+            A_all = mode_factors(ev.modes, fp, fc, iota, phi)
+            s = (t_c + time_delays(ev.det_pos[det], al, dec) - ev.t_trig) * ev.grid.fs + art.half_w
             n0 = np.floor(s)
             f = s - n0
             n0 = n0.astype(np.int64)
@@ -275,10 +276,12 @@ def meshfree_parts(art: Artefacts, delta_e: np.ndarray, ext: np.ndarray, t_c: np
             n0c = np.where(ok, n0, 4)
             w = spline_weights(f, tab)                                   # [n][10]
             rows = n0c[:, None] + np.arange(-4, 6)[None, :]              # [n][10]
-            o = coef_off[k][a]
-            C = Y[:, o:o + 2 * art.q:2] + 1j * Y[:, o + 1:o + 2 * art.q:2]
-            btilde = np.einsum("ns,nsi->ni", w, art.basis[k, a][rows])
-            zs[:, k, a] = np.sum(C * btilde, axis=1)
+            for a in members:
+                A[:, a] = A_all[:, a]
+                o = coef_off[k][a]
+                C = Y[:, o:o + 2 * art.q:2] + 1j * Y[:, o + 1:o + 2 * art.q:2]
+                btilde = np.einsum("ns,nsi->ni", w, art.basis[k, a][rows])
+                zs[:, k, a] = np.sum(C * btilde, axis=1)
         o = sig_off[k]
         for a in range(n_modes):
             sigs[:, k, a, a] = Y[:, o + a]
