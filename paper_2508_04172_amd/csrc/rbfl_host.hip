@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "host_math.h"
 #include "rbfl_internal.h"
 #include "sampler.h"
 
@@ -49,192 +50,6 @@ static double seconds_since(Clock::time_point t) {
 // ---------------------------------------------------------------------------
 // Host FP64 pieces of the start-up stage
 // ---------------------------------------------------------------------------
-
-// aLIGO-like analytic PSD, x = f / 215 Hz.
-static double psd_analytic(double f, double scale) {
-  const double x = f / 215.0;
-  return scale * 1e-49 *
-         (pow(x, -4.14) - 5.0 / (x * x) + 111.0 * (1.0 - x * x + 0.5 * x * x * x * x) / (1.0 + 0.5 * x * x));
-}
-
-// Detector tensor and position from (lat, lon, x-arm azimuth, opening, radius).
-static void detector_geometry(const double g[5], double D[9], double r[3]) {
-  const double lat = g[0], lon = g[1], az = g[2], op = g[3], rad = g[4];
-  const double east[3] = {-sin(lon), cos(lon), 0.0};
-  const double north[3] = {-sin(lat) * cos(lon), -sin(lat) * sin(lon), cos(lat)};
-  const double up[3] = {cos(lat) * cos(lon), cos(lat) * sin(lon), sin(lat)};
-  double u[3], v[3];
-  for (int i = 0; i < 3; ++i) {
-    u[i] = cos(az) * north[i] + sin(az) * east[i];
-    v[i] = cos(az + op) * north[i] + sin(az + op) * east[i];
-    r[i] = rad * up[i];
-  }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) D[3 * i + j] = 0.5 * (u[i] * u[j] - v[i] * v[j]);
-}
-
-static double factorial(int n) {
-  double f = 1.0;
-  for (int i = 2; i <= n; ++i) f *= i;
-  return f;
-}
-
-// -2Y_{l m}(iota, phi) = sqrt((2l+1)/4pi) d^l_{m,2}(iota) e^{i m phi}, with the
-// Wigner small-d element written as its finite sum over k.
-static YlmTerms ylm_terms(int l, int m) {
-  YlmTerms t{};
-  t.m = m;
-  t.n = 0;
-  const int m1 = m, m2 = 2;
-  const double norm = sqrt((2.0 * l + 1.0) / (4.0 * kPi));
-  const double pre = sqrt(factorial(l + m1) * factorial(l - m1) * factorial(l + m2) * factorial(l - m2));
-  for (int k = 0; k <= 2 * l; ++k) {
-    const int a1 = l + m2 - k, a2 = k, a3 = m1 - m2 + k, a4 = l - m1 - k;
-    if (a1 < 0 || a2 < 0 || a3 < 0 || a4 < 0) continue;
-    const double sign = ((k + m1 - m2) & 1) ? -1.0 : 1.0;
-    t.coef[t.n] = norm * sign * pre / (factorial(a1) * factorial(a2) * factorial(a3) * factorial(a4));
-    t.cpow[t.n] = 2 * l + m2 - m1 - 2 * k;
-    t.spow[t.n] = m1 - m2 + 2 * k;
-    ++t.n;
-  }
-  return t;
-}
-
-static void ylm_value(const YlmTerms &t, double iota, double phi, double *re, double *im) {
-  eval_ylm(t, cos(0.5 * iota), sin(0.5 * iota), phi, re, im);
-}
-
-// Not-a-knot cubic spline through 10 unit-spaced samples, evaluated in the
-// central interval [4, 5]: its value is linear in the samples, sum_s w_s(f) y_s,
-// with each w_s a cubic in f.  Second derivatives m_i solve
-// m_{i-1} + 4 m_i + m_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}) (i = 1..8) with the
-// not-a-knot conditions m_0 - 2 m_1 + m_2 = 0 and m_7 - 2 m_8 + m_9 = 0; on
-// [4, 5], S(f) = y4 + (y5 - y4 - m4/3 - m5/6) f + m4/2 f^2 + (m5 - m4)/6 f^3.
-static void spline_table(double tab[kSplineTaps][4]) {
-  constexpr int n = kSplineTaps;
-  for (int s = 0; s < n; ++s) {
-    double A[n][n + 1] = {};
-    double y[n] = {};
-    y[s] = 1.0;
-    A[0][0] = 1.0;
-    A[0][1] = -2.0;
-    A[0][2] = 1.0;
-    A[n - 1][n - 3] = 1.0;
-    A[n - 1][n - 2] = -2.0;
-    A[n - 1][n - 1] = 1.0;
-    for (int i = 1; i < n - 1; ++i) {
-      A[i][i - 1] = 1.0;
-      A[i][i] = 4.0;
-      A[i][i + 1] = 1.0;
-      A[i][n] = 6.0 * (y[i + 1] - 2.0 * y[i] + y[i - 1]);
-    }
-    // Gaussian elimination with partial pivoting
-    for (int c = 0; c < n; ++c) {
-      int piv = c;
-      for (int r = c + 1; r < n; ++r)
-        if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-      if (piv != c)
-        for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
-      for (int r = c + 1; r < n; ++r) {
-        const double f = A[r][c] / A[c][c];
-        for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
-      }
-    }
-    double m[n];
-    for (int r = n - 1; r >= 0; --r) {
-      double v = A[r][n];
-      for (int k = r + 1; k < n; ++k) v -= A[r][k] * m[k];
-      m[r] = v / A[r][r];
-    }
-    tab[s][0] = y[4];
-    tab[s][1] = y[5] - y[4] - m[4] / 3.0 - m[5] / 6.0;
-    tab[s][2] = 0.5 * m[4];
-    tab[s][3] = (m[5] - m[4]) / 6.0;
-  }
-}
-
-// Van der Corput radical inverse as an exact integer ratio, rounded once.
-static double radical_inverse(uint64_t i, uint64_t base) {
-  uint64_t num = 0, den = 1;
-  while (i > 0) {
-    num = num * base + i % base;
-    den *= base;
-    i /= base;
-  }
-  return (double)num / (double)den;
-}
-
-// ---- metric: generic-real versions of the phase and the inverse map, so the
-// derivatives can be taken by the complex step.
-template <class R>
-static R phase22_generic(R f, R m1, R m2, R c1, R c2) {
-  using std::log;
-  using std::pow;
-  const double pi = kPi;
-  const R mt = m1 + m2;
-  const R eta = m1 * m2 / (mt * mt);
-  const R dl = (m1 - m2) / mt;
-  const R cs = 0.5 * (c1 + c2), ca = 0.5 * (c1 - c2);
-  const R v = pow(pi * mt * kMsunS * f, 1.0 / 3.0);
-  const R lv = log(v);
-  const R e2 = eta * eta, e3 = e2 * eta;
-  const R p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
-  const R p3 = -16.0 * pi + 113.0 / 3.0 * dl * ca + (113.0 / 3.0 - 76.0 / 3.0 * eta) * cs;
-  const R p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * e2 +
-               (-405.0 / 8.0 + 200.0 * eta) * ca * ca - 405.0 / 4.0 * dl * ca * cs +
-               (-405.0 / 8.0 + 2.5 * eta) * cs * cs;
-  const R p5 = pi * (38645.0 / 756.0 - 65.0 / 9.0 * eta) + dl * ca * (-732985.0 / 2268.0 - 140.0 / 9.0 * eta) +
-               cs * (-732985.0 / 2268.0 + 24260.0 / 81.0 * eta + 340.0 / 9.0 * e2);
-  const R p6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * pi * pi - 6848.0 / 21.0 * kEulerGamma +
-               eta * (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * pi * pi) + 76055.0 / 1728.0 * e2 -
-               127825.0 / 1296.0 * e3 + pi * (2270.0 / 3.0 * dl * ca + (2270.0 / 3.0 - 520.0 * eta) * cs) +
-               (75515.0 / 144.0 - 8225.0 / 18.0 * eta) * dl * ca * cs +
-               (75515.0 / 288.0 - 263245.0 / 252.0 * eta - 480.0 * e2) * ca * ca +
-               (75515.0 / 288.0 - 232415.0 / 504.0 * eta + 1255.0 / 9.0 * e2) * cs * cs;
-  const double p6l = -6848.0 / 21.0;
-  const R p7 = pi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2) +
-               dl * ca * (-25150083775.0 / 3048192.0 + 26804935.0 / 6048.0 * eta - 1985.0 / 48.0 * e2) +
-               cs * (-25150083775.0 / 3048192.0 + 10566655595.0 / 762048.0 * eta - 1042165.0 / 3024.0 * e2 +
-                     5345.0 / 36.0 * e3);
-  const R v2 = v * v;
-  R s = p7;
-  s = s * v + (p6 + p6l * (std::log(4.0) + lv));
-  s = s * v + p5 * (1.0 + 3.0 * lv);
-  s = s * v + p4;
-  s = s * v + p3;
-  s = s * v + p2;
-  s = s * v2 + 1.0;
-  return -0.25 * pi + 3.0 / (128.0 * eta * v2 * v2 * v) * s;
-}
-
-template <class R>
-static void theta_to_phys_generic(const R th[4], double f0, R p[4]) {
-  using std::pow;
-  using std::sqrt;
-  const R u = 5.0 * th[1] / (32.0 * kPi * th[0]);
-  const R eta = kPi / (4.0 * th[1]) * pow(u, -2.0 / 3.0);
-  const R mt = u / (kPi * f0) / kMsunS;
-  const R dl = sqrt(1.0 - 4.0 * eta);
-  const R chi_r = 48.0 * kPi * th[2] / (113.0 * th[1]);
-  const R chi_eff = 48.0 * kPi * th[3] / (113.0 * th[1]);
-  const R cs = 113.0 * (chi_eff - chi_r) / (76.0 * eta);
-  const R ca = (chi_eff - cs) / dl;
-  p[0] = 0.5 * mt * (1.0 + dl);
-  p[1] = 0.5 * mt * (1.0 - dl);
-  p[2] = cs + ca;
-  p[3] = cs - ca;
-}
-
-// Neumaier-compensated sum.
-struct Sum {
-  double s = 0.0, c = 0.0;
-  void add(double v) {
-    const double t = s + v;
-    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-    s = t;
-  }
-  double value() const { return s + c; }
-};
 
 // Projected metric of the normalised (2,2) template (Eq. MisMatch): half the
 // weighted inner products of the Theta-derivatives of the phase after their
@@ -295,81 +110,6 @@ static void compute_metric(const Ctx &c, const std::vector<double> &psd0, const 
       for (int64_t k = 0; k < n; ++k) s.add(w[k] * d[i][k] * d[j][k]);
       g[4 * i + j] = g[4 * j + i] = 0.5 * s.value();
     }
-}
-
-// Reference frequency of the template time and phase: the mean frequency of
-// the centre's (2,2) band under the metric's weights |h22|^2 / S_0, i.e.
-// f^(-7/3) / S_0.  There the time and constant-phase shifts that the match
-// maximises over are uncorrelated, so with the template phase referenced
-// there the overlap series of neighbouring templates stay aligned in time
-// and phase across the ellipsoid.
-static double reference_frequency(const Ctx &c, const std::vector<double> &psd0, const double center[4]) {
-  const Binary b = make_binary(center[0], center[1], center[2], center[3], 0.0);
-  const int64_t j0 = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
-  int64_t j1 = (int64_t)ceil(2.0 * b.f_isco * c.seg_len);
-  j1 = std::min<int64_t>(std::max<int64_t>(j1, j0), c.n_s / 2);
-  if (j1 <= j0) throw Error(RBFL_E_INVALID_ARG, "the (2,2) band at the centre is empty");
-  Sum w, fw;
-  for (int64_t j = j0; j < j1; ++j) {
-    const double f = (double)j * c.df;
-    const double v = pow(f, -7.0 / 3.0) / psd0[j];
-    w.add(v);
-    fw.add(f * v);
-  }
-  return fw.value() / w.value();
-}
-
-// Time bands of the antenna patterns (rbfl_build_spec.n_bands > 1).  The
-// centre's (2,2) stationary-phase track t(f) = Psi'(f) / (2 pi) carries the
-// gravitational-wave phase Phi(f) = f Psi'(f) - Psi(f); the bands cut
-// [lowest bin, (2,2) cut-off) into equal shares of Phi, so the phase error
-// of a delay drifting linearly in time has the same bound in every band, and
-// the last band runs on to the top of the grid.  Mode (l, m) passes f at the
-// (2,2) track time of 2 f / m; its time in band b is the mean of that time
-// over its own bins there under f^(-1/3) / S_0 (the delay error's weight
-// f^2 |h|^2 / S), or 0 where it has no bins.  edges: [B + 1] bin indices.
-static void time_bands(const Ctx &c, const std::vector<double> &psd0, const double centre[4],
-                       std::vector<int64_t> &edges, double times[RBFL_MAX_BANDS][RBFL_MAX_MODES]) {
-  const int B = c.n_bands;
-  const Binary b = make_binary(centre[0], centre[1], centre[2], centre[3], c.f_ref);
-  const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
-  const int64_t j_hi = c.n_s / 2;
-  auto cut_bin = [&](int m) {
-    const int64_t jc = (int64_t)ceil((double)m * b.f_isco * c.seg_len);
-    return std::min(std::max(jc, j_lo), j_hi);
-  };
-  const int64_t j22 = cut_bin(2);
-  if (j22 - j_lo < 2) throw Error(RBFL_E_INVALID_ARG, "the (2,2) band at the centre is too short for time bands");
-  std::vector<double> phi((size_t)(j22 - j_lo));
-  for (int64_t j = j_lo; j < j22; ++j) {
-    const double f = (double)j * c.df;
-    phi[(size_t)(j - j_lo)] = f * (dphase22_pn(f, b) - b.dpsi_ref) - phase22(f, b);
-  }
-  edges.assign((size_t)B + 1, 0);
-  edges[0] = j_lo;
-  edges[(size_t)B] = j_hi;
-  const double p0 = phi.front(), p1 = phi.back();
-  for (int i = 1; i < B; ++i) {
-    const double cut = p0 + (p1 - p0) * (double)i / (double)B;
-    const auto it = std::lower_bound(phi.begin(), phi.end(), cut);
-    edges[(size_t)i] = j_lo + (int64_t)(it - phi.begin());
-  }
-  for (int a = 0; a < c.n_modes; ++a) {
-    const int m = c.modes[a][1];
-    const int64_t jc = cut_bin(m);
-    for (int i = 0; i < B; ++i) {
-      const int64_t lo = std::max(edges[(size_t)i], j_lo), hi = std::min(edges[(size_t)i + 1], jc);
-      Sum w, tw;
-      for (int64_t j = lo; j < hi; ++j) {
-        const double f = (double)j * c.df;
-        const double v = pow(f, -1.0 / 3.0) / psd0[j];
-        const double t = (dphase22_pn(2.0 * f / (double)m, b) - b.dpsi_ref) / (2.0 * kPi);
-        w.add(v);
-        tw.add(v * t);
-      }
-      times[i][a] = hi > lo ? tw.value() / w.value() : 0.0;
-    }
-  }
 }
 
 // ---- true match (Eq. Match) and the squeeze of the longest axis (Sec. II C.1)
@@ -535,45 +275,6 @@ static double squeeze_factor(const Ctx &c, const std::vector<double> &psd0, cons
   bool ok = false;
   *tip_match = factor < 1.0 ? at(factor_sign * factor, &ok) : 0.0;
   return factor;
-}
-
-// Cyclic Jacobi eigen-decomposition of a symmetric 4x4 matrix.
-static void jacobi_eigen(const double a_in[16], double lam[4], double V[16]) {
-  double a[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      a[i][j] = a_in[4 * i + j];
-      V[4 * i + j] = i == j ? 1.0 : 0.0;
-    }
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) (i == j ? diag : off) += a[i][j] * a[i][j];
-    if (off <= 1e-34 * diag) break;
-    for (int p = 0; p < 3; ++p)
-      for (int q = p + 1; q < 4; ++q) {
-        if (a[p][q] == 0.0) continue;
-        const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < 4; ++k) {
-          const double akp = a[k][p], akq = a[k][q];
-          a[k][p] = cs * akp - sn * akq;
-          a[k][q] = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < 4; ++k) {
-          const double apk = a[p][k], aqk = a[q][k];
-          a[p][k] = cs * apk - sn * aqk;
-          a[q][k] = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < 4; ++k) {
-          const double vkp = V[4 * k + p], vkq = V[4 * k + q];
-          V[4 * k + p] = cs * vkp - sn * vkq;
-          V[4 * k + q] = sn * vkp + cs * vkq;
-        }
-      }
-  }
-  for (int i = 0; i < 4; ++i) lam[i] = a[i][i];
 }
 
 // Synthetic data: coloured noise + the projected injection (Eq. projected_h_fd).
@@ -751,37 +452,6 @@ static void validate(const rbfl_build_spec *s) {
     for (int64_t i = 0; i < nf * s->n_det; ++i)
       require((std::isfinite(s->psd[i]) && s->psd[i] > 0) || (i % nf) == 0, "psd must be finite and > 0");
   }
-}
-
-static int monomials(int degree, int idx[kMaxPoly][3]) {
-  int n = 0;
-  for (int d = 0; d <= degree; ++d) {
-    if (d == 0) {
-      idx[n][0] = idx[n][1] = idx[n][2] = -1;
-      ++n;
-    } else if (d == 1) {
-      for (int i = 0; i < 4; ++i, ++n) {
-        idx[n][0] = i;
-        idx[n][1] = idx[n][2] = -1;
-      }
-    } else if (d == 2) {
-      for (int i = 0; i < 4; ++i)
-        for (int j = i; j < 4; ++j, ++n) {
-          idx[n][0] = i;
-          idx[n][1] = j;
-          idx[n][2] = -1;
-        }
-    } else {
-      for (int i = 0; i < 4; ++i)
-        for (int j = i; j < 4; ++j)
-          for (int k = j; k < 4; ++k, ++n) {
-            idx[n][0] = i;
-            idx[n][1] = j;
-            idx[n][2] = k;
-          }
-    }
-  }
-  return n;
 }
 
 struct BlasHandle {
@@ -1141,7 +811,7 @@ bool debug_mode() {
   return v != nullptr && *v != 0 && std::strcmp(v, "0") != 0;
 }
 
-static void debug_require(bool ok, const std::string &what) {
+void debug_require(bool ok, const std::string &what) {
   if (!ok) throw Error(RBFL_E_STATE, "RBFL_DEBUG: " + what);
 }
 
@@ -1239,7 +909,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   if (s->f_ref > 0.0)
     c.f_ref = s->f_ref;
   else if (s->f_ref == 0.0)
-    c.f_ref = reference_frequency(c, psd[0], s->center_phys);
+    c.f_ref = reference_frequency(c.f_low, c.seg_len, c.n_s, psd[0].data(), s->center_phys);
   else
     c.f_ref = 0.0;
   std::vector<std::vector<double2>> data;
@@ -1332,14 +1002,11 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
     const double zero[4] = {0, 0, 0, 0};
     if (!try_point(zero)) throw Error(RBFL_E_INVALID_ARG, "centre is not a physical point");
   }
-  const uint64_t bases[4] = {2, 3, 5, 7};
   for (uint64_t i = 1; have < c.N; ++i) {
     if (i > 50000000ull) throw Error(RBFL_E_NUMERICAL, "too few physical Halton points in the ellipsoid");
-    double x[4], r2 = 0.0;
-    for (int d = 0; d < 4; ++d) {
-      x[d] = 2.0 * radical_inverse(i, bases[d]) - 1.0;
-      r2 += x[d] * x[d];
-    }
+    double x[4];
+    halton_point(i, x);
+    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
     if (r2 <= 1.0) try_point(x);
   }
   c.timing[1] = seconds_since(t0);
@@ -1351,7 +1018,8 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   const int64_t j_hi = c.n_s / 2;
   double band_t[RBFL_MAX_BANDS][RBFL_MAX_MODES] = {};
   if (c.n_bands > 1)
-    time_bands(c, psd[0], centre, c.band_edges, band_t);
+    time_bands(centre, c.f_ref, c.f_low, c.seg_len, c.n_s, c.n_modes, c.modes, c.n_bands, psd[0].data(), c.band_edges,
+               band_t);
   else
     c.band_edges = {j_lo, j_hi};
   std::vector<Binary> bins(c.N);
@@ -1765,7 +1433,7 @@ static void reserve_lnl_gemm(Ctx &c, int64_t n) {
   c.epi_part.alloc((size_t)(c.Kp / gemm_lnl_col_tile()) * n);
 }
 
-static void reserve(Ctx &c, int64_t n) {
+void reserve(Ctx &c, int64_t n) {
   if (n <= c.cap) return;
   if (c.graph_users > 0) throw Error(RBFL_E_STATE, "the work space is captured by a sampler: it cannot grow");
   c.Y.alloc((size_t)n * c.Kp);
@@ -1934,7 +1602,7 @@ static void eval_range(Ctx &c, const double *params, int64_t ld, int64_t n, doub
   }
 }
 
-static void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
+void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s) {
   require(params != nullptr && lnl != nullptr, "params/lnl is NULL");
   require(n >= 0, "n must be >= 0");
   if (form < 0 || form > RBFL_FORM_SURROGATE) throw Error(RBFL_E_INVALID_ARG, "unknown form");
@@ -2186,7 +1854,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
   (void)hipEventDestroy(e1);
 }
 
-static void prepare(Ctx &c, int form) {
+void prepare(Ctx &c, int form) {
   if (form < 0 || form > RBFL_FORM_SPLIT) throw Error(RBFL_E_INVALID_ARG, "unknown form");
   if (c.prepared[form]) return;
   const size_t n = (size_t)c.rows * c.Kp;
@@ -2590,734 +2258,12 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
   }
 }
 
-// ---- multi-event batches -----------------------------------------------------
-
-struct Plan {
-  std::vector<Ctx *> ctx;
-  std::vector<int64_t> counts;
-  int64_t total = 0;
-  const double *params = nullptr;
-  double *lnl = nullptr;
-  DevBuf<EventDesc> ev_work, ev_param;
-  DevBuf<double> Y, Bt;
-  int64_t total_groups = 0, max_ldb = 0;
-  DevBuf<unsigned long long> counter;
-  int64_t total_items = 0;
-  int grid = 0;
-  int variant = 0;              // FP64 tile variant; -1 for the split form
-  double tune_ms[8] = {};
-  // split form (RBFL_PLAN_SPLIT): digits per event (caller order), the digit
-  // rows and row scales of every event, and the work lists of the events
-  // grouped by digit count (one persistent launch per group)
-  bool split = false;
-  std::vector<int> S;
-  DevBuf<int8_t> AS;
-  DevBuf<double> rscale;
-  int64_t split_threads = 0;
-  int n_groups = 0;
-  int group_S[4] = {}, group_n[4] = {}, group_off[4] = {}, group_grid[4] = {};
-  int64_t group_items[4] = {};
-  DevBuf<EventDesc> ev_group;
-  int split_tol_state = -1;     // 1: every event within RBFL_SPLIT_TOL of the FP64 plan, 0: not, -1: not tuned
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~Plan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  }
-};
-
-// A plan's caller-order descriptors d and its work lists (work order, one
-// per group of items): proposal ranges partition [0, total), each event's
-// rows of the shared buffers lie inside them without overlap, and every
-// work item maps through work_event to a tile inside its event.
-static void debug_check_plan(const Plan &p, const std::vector<EventDesc> &d,
-                             const std::vector<std::pair<std::vector<EventDesc>, int64_t>> &lists) {
-  const int n_ev = (int)d.size();
-  int64_t q0 = 0;
-  const double *y_end = p.Y.p;
-  const double *b_end = p.Bt.p;
-  for (int e = 0; e < n_ev; ++e) {
-    const EventDesc &x = d[e];
-    const Ctx &c = *p.ctx[e];
-    debug_require(x.q0 == q0 && x.n == p.counts[e] && x.n >= 1, "proposal ranges");
-    debug_require(x.Kp == c.Kp && x.rows == c.rows && x.consts == c.consts.p && x.W == c.W.p, "event constants");
-    debug_require(x.Y == y_end && x.Y + x.n * x.Kp <= p.Y.p + p.Y.n, "output rows outside the plan's buffer");
-    y_end = x.Y + x.n * x.Kp;
-    if (!p.split) {
-      debug_require(x.Bt == b_end && x.ldb >= x.n && x.Bt + (int64_t)x.rows * x.ldb <= p.Bt.p + p.Bt.n,
-                    "basis rows outside the plan's buffer");
-      b_end = x.Bt + (int64_t)x.rows * x.ldb;
-    } else {
-      const int8_t *as = static_cast<const int8_t *>(x.AS);
-      debug_require(x.S >= 5 && x.S <= split_max_slices() && as >= p.AS.p &&
-                        as + (int64_t)split_max_slices() * x.rows * x.n <= p.AS.p + p.AS.n &&
-                        x.rscale == p.rscale.p + x.q0 && x.q0 + x.n <= (int64_t)p.rscale.n,
-                    "digit rows outside the plan's buffers");
-    }
-    q0 += x.n;
-  }
-  debug_require(q0 == p.total, "proposal ranges do not cover the batch");
-  for (const auto &lw : lists) {
-    const std::vector<EventDesc> &w = lw.first;
-    const int nw = (int)w.size();
-    int64_t next = 0;
-    for (int i = 0; i < nw; ++i) {
-      debug_require(w[i].item0 == next && w[i].tiles_q >= 1 && w[i].tiles_c >= 1, "work list ranges");
-      next += (int64_t)w[i].tiles_q * w[i].tiles_c;
-    }
-    debug_require(next == lw.second, "work list length");
-    for (int64_t item = 0; item < lw.second; ++item) {
-      const int e = work_event(w.data(), nw, item);
-      const int64_t local = item - w[e].item0;
-      debug_require(e >= 0 && e < nw && local >= 0 && local < (int64_t)w[e].tiles_q * w[e].tiles_c,
-                    "work item " + std::to_string(item) + " outside its event's tiles");
-    }
-  }
-}
-
-// Event descriptors for tile variant v: caller order (for the epilogue) and
-// decreasing-cost order with consecutive work-item ranges (for the persistent
-// contraction).  Cost of an event = proposals x (N+M) x K.
-static void plan_layout(Plan &p, int v, hipStream_t s) {
-  int qt, cw;
-  ragged_tile(v, &qt, &cw);
-  const int n_ev = (int)p.ctx.size();
-  std::vector<EventDesc> d(n_ev);
-  int64_t q0 = 0, yoff = 0, boff = 0, rg = 0;
-  p.max_ldb = 0;
-  for (int e = 0; e < n_ev; ++e) {
-    Ctx &c = *p.ctx[e];
-    std::memset(&d[e], 0, sizeof(EventDesc));
-    d[e].consts = c.consts.p;
-    d[e].nodes = c.nodes.p;
-    d[e].W = c.W.p;
-    d[e].basis = c.basis4.p;
-    d[e].Y = p.Y.p + yoff;
-    d[e].Bt = p.Bt.p + boff;
-    d[e].q0 = q0;
-    d[e].n = p.counts[e];
-    d[e].ldb = rows_ld(p.counts[e]);
-    d[e].rg0 = rg;
-    d[e].tiles_q = (int)((p.counts[e] + qt - 1) / qt);
-    d[e].tiles_c = c.Kp / cw;
-    d[e].Kp = c.Kp;
-    d[e].rows = c.rows;
-    q0 += p.counts[e];
-    yoff += p.counts[e] * c.Kp;
-    boff += (int64_t)c.rows * d[e].ldb;
-    rg += c.rows / 16;
-    p.max_ldb = std::max(p.max_ldb, d[e].ldb);
-  }
-  p.total_groups = rg;
-  std::vector<int> order(n_ev);
-  for (int e = 0; e < n_ev; ++e) order[e] = e;
-  auto cost = [&](int e) { return (double)p.counts[e] * (p.ctx[e]->N + p.ctx[e]->M) * p.ctx[e]->K; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  std::vector<EventDesc> w(n_ev);
-  int64_t item = 0;
-  for (int i = 0; i < n_ev; ++i) {
-    w[i] = d[order[i]];
-    w[i].item0 = item;
-    item += (int64_t)w[i].tiles_q * w[i].tiles_c;
-  }
-  p.total_items = item;
-  int dev = 0, cus = 0;
-  RBFL_HIP(hipGetDevice(&dev));
-  RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.total_items, (int64_t)cus * ragged_blocks_per_cu(v)));
-  if (debug_mode()) debug_check_plan(p, d, {{w, p.total_items}});
-  RBFL_HIP(hipMemcpyAsync(p.ev_work.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
-  RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
-  RBFL_HIP(hipStreamSynchronize(s));
-  p.variant = v;
-}
-
-// Split-form layout with the digit counts p.S: caller-order descriptors for
-// the digit rows and the epilogue, and per digit count a work list of its
-// events in decreasing cost with consecutive item ranges.
-static void plan_layout_split(Plan &p, hipStream_t s) {
-  const int qt = split_ragged_tile_q(), cw = split_ragged_tile_c();
-  const int n_ev = (int)p.ctx.size();
-  std::vector<EventDesc> d(n_ev);
-  int64_t q0 = 0, yoff = 0, aoff = 0, t0 = 0;
-  for (int e = 0; e < n_ev; ++e) {
-    Ctx &c = *p.ctx[e];
-    EventDesc &x = d[e];
-    std::memset(&x, 0, sizeof(x));
-    x.consts = c.consts.p;
-    x.nodes = c.nodes.p;
-    x.W = c.W.p;
-    x.basis = c.basis4.p;
-    x.Y = p.Y.p + yoff;
-    x.q0 = q0;
-    x.n = p.counts[e];
-    x.tiles_q = (int)((p.counts[e] + qt - 1) / qt);
-    x.tiles_c = c.Kp / cw;
-    x.Kp = c.Kp;
-    x.rows = c.rows;
-    x.BS = c.WS.p;
-    x.cscale = c.WSscale.p;
-    x.AS = p.AS.p + aoff;
-    x.rscale = p.rscale.p + q0;
-    x.S = p.S[e];
-    x.t0 = t0;
-    q0 += p.counts[e];
-    yoff += p.counts[e] * c.Kp;
-    aoff += (int64_t)split_max_slices() * c.rows * p.counts[e];
-    t0 += (int64_t)(c.rows / 16) * p.counts[e];
-  }
-  p.split_threads = t0;
-  int dev = 0, cus = 0;
-  RBFL_HIP(hipGetDevice(&dev));
-  RBFL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  auto cost = [&](int e) { return (double)p.counts[e] * (p.ctx[e]->N + p.ctx[e]->M) * p.ctx[e]->K; };
-  std::vector<EventDesc> w;
-  p.n_groups = 0;
-  for (int S = 8; S >= 5; --S) {
-    std::vector<int> order;
-    for (int e = 0; e < n_ev; ++e)
-      if (p.S[e] == S) order.push_back(e);
-    if (order.empty()) continue;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    const int g = p.n_groups++;
-    p.group_S[g] = S;
-    p.group_n[g] = (int)order.size();
-    p.group_off[g] = (int)w.size();
-    int64_t item = 0;
-    for (int e : order) {
-      EventDesc x = d[e];
-      x.item0 = item;
-      item += (int64_t)x.tiles_q * x.tiles_c;
-      w.push_back(x);
-    }
-    p.group_items[g] = item;
-    p.group_grid[g] = (int)std::max<int64_t>(1, std::min<int64_t>(item, (int64_t)cus * split_ragged_blocks_per_cu()));
-  }
-  p.total_items = 0;
-  p.grid = 0;
-  for (int g = 0; g < p.n_groups; ++g) {
-    p.total_items += p.group_items[g];
-    p.grid = std::max(p.grid, p.group_grid[g]);
-  }
-  if (debug_mode()) {
-    std::vector<std::pair<std::vector<EventDesc>, int64_t>> lists;
-    for (int g = 0; g < p.n_groups; ++g)
-      lists.push_back({std::vector<EventDesc>(w.begin() + p.group_off[g], w.begin() + p.group_off[g] + p.group_n[g]),
-                       p.group_items[g]});
-    debug_check_plan(p, d, lists);
-  }
-  RBFL_HIP(hipMemcpyAsync(p.ev_param.p, d.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
-  RBFL_HIP(hipMemcpyAsync(p.ev_group.p, w.data(), sizeof(EventDesc) * n_ev, hipMemcpyHostToDevice, s));
-  RBFL_HIP(hipStreamSynchronize(s));
-  p.variant = -1;
-}
-
-static void plan_run(Plan &p, hipStream_t s) {
-  const int n_ev = (int)p.ctx.size();
-  if (p.split) {
-    launch_ragged_split_rows(p.ev_param.p, n_ev, p.split_threads, p.params, p.total, s);
-    launch_zero_counters(p.counter.p, p.n_groups, s);
-    for (int g = 0; g < p.n_groups; ++g)
-      launch_ragged_split_contract(p.group_S[g], p.ev_group.p + p.group_off[g], p.group_n[g], p.group_items[g],
-                                   p.counter.p + g, p.group_grid[g], s);
-    launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
-    return;
-  }
-  if (p.variant < ragged_fused_variants()) {
-    launch_ragged_contract(p.variant, p.ev_work.p, n_ev, p.total_items, p.counter.p, p.params, p.total, p.grid, s);
-  } else {
-    launch_ragged_rows_fp64(p.ev_param.p, n_ev, p.total_groups, p.max_ldb, p.params, p.total, s);
-    launch_ragged_gemm_fp64(p.variant - ragged_fused_variants(), p.ev_work.p, n_ev, p.total_items, p.counter.p,
-                            p.grid, s);
-  }
-  launch_ragged_epilogue(p.ev_param.p, n_ev, p.params, p.total, p.lnl, s);
-}
-
 }  // namespace rbfl
-
-struct rbfl_plan_ctx {
-  rbfl::Plan p;
-};
 
 struct rbfl_mlp_ctx {
   rbfl::Mlp m;
 };
 
-struct rbfl_sampler_ctx {
-  rbfl::Ctx *c = nullptr;
-  rbfl_sampler_spec spec{};
-  rbfl::SamplerPrior prior{};
-  int W = 0, M = 0;
-  double gamma = 0.0;
-  rbfl::DevBuf<double> X, Y, lnl_x, lnl_y, lp_x;
-  rbfl::DevBuf<unsigned long long> acc;
-  rbfl::DevBuf<rbfl::SamplerState> st;
-  rbfl::SamplerState stage{};   // host copy staged for the next run
-  uint64_t steps = 0;
-  double beta_fixed = -1.0;     // ln L weight after a tempered SMC start (1), -1 = the spec's schedule
-  uint32_t smc_stages = 0;      // stages run so far (the resampling draws' counter)
-  hipStream_t cap = nullptr, last = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~rbfl_sampler_ctx() {
-    if (c && exec) c->graph_users -= 1;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
-  }
-};
-
-namespace rbfl {
-// One sampler step: for each half, proposals, their ln L through the online
-// stage (the handle's work space, reserved beforehand), the Metropolis
-// decisions; then the step counter.
-static void sampler_step(rbfl_sampler_ctx &S, hipStream_t s) {
-  const bool prior_only = S.spec.flags & RBFL_SAMPLER_PRIOR_ONLY;
-  for (int half = 0; half < 2; ++half) {
-    launch_de_propose(S.st.p, S.spec.seed, S.M, half, S.gamma, S.spec.p_jump, S.X.p, S.Y.p, s);
-    if (!prior_only) eval(*S.c, S.Y.p, S.M, S.lnl_y.p, S.spec.form, s);
-    launch_de_accept(S.c->consts.p, S.prior, S.st.p, S.spec.seed, S.M, half, prior_only ? 1 : 0, S.Y.p, S.lnl_y.p,
-                     S.X.p, S.lnl_x.p, S.lp_x.p, S.acc.p, s);
-  }
-  launch_step_advance(S.st.p, s);
-}
-
-static rbfl_sampler_ctx *sampler_create(Ctx &c, const rbfl_sampler_spec *sp, const double *init, hipStream_t s) {
-  require(sp != nullptr, "spec is NULL");
-  const rbfl_sampler_spec &p = *sp;
-  require(p.walkers >= 8 && p.walkers % 2 == 0 && p.walkers <= (1 << 30), "walkers must be even, 8 .. 2^30");
-  require(p.form >= 0 && p.form <= RBFL_FORM_SURROGATE, "unknown form");
-  require(c.prepared[p.form], "form not prepared (call rbfl_prepare)");
-  require(p.t_lo < p.t_hi && std::isfinite(p.t_lo) && std::isfinite(p.t_hi), "need t_lo < t_hi");
-  require(p.d_lo > 0.0 && p.d_lo < p.d_hi && std::isfinite(p.d_hi), "need 0 < d_lo < d_hi");
-  require(std::isfinite(p.d_exp) && p.d_exp > -1.0, "d_exp must be finite and > -1");
-  require(p.gamma >= 0.0 && std::isfinite(p.gamma), "gamma must be >= 0");
-  require(p.p_jump >= 0.0 && p.p_jump <= 1.0, "p_jump must be in 0 .. 1");
-  require((p.flags & ~RBFL_SAMPLER_PRIOR_ONLY) == 0, "unknown sampler flag bits");
-  require(p.anneal_steps >= 0, "anneal_steps must be >= 0");
-  require(p.anneal_steps == 0 || (p.beta0 > 0.0 && p.beta0 <= 1.0), "beta0 must be in (0, 1]");
-  std::unique_ptr<rbfl_sampler_ctx> S(new rbfl_sampler_ctx());
-  S->c = &c;
-  S->spec = p;
-  S->prior = SamplerPrior{p.t_lo, p.t_hi, p.d_lo, p.d_hi, p.d_exp};
-  S->W = p.walkers;
-  S->M = p.walkers / 2;
-  S->gamma = p.gamma > 0.0 ? p.gamma : 2.38 / sqrt(22.0);
-  const int64_t W = S->W, M = S->M;
-  S->X.alloc(11 * W);
-  S->Y.alloc(11 * M);
-  S->lnl_x.alloc(W);
-  S->lnl_y.alloc(M);
-  S->lp_x.alloc(W);
-  S->acc.alloc(W);
-  S->st.alloc(1);
-  RBFL_HIP(hipMemsetAsync(S->acc.p, 0, sizeof(unsigned long long) * W, s));
-  if (init) {
-    RBFL_HIP(hipMemcpyAsync(S->X.p, init, sizeof(double) * 11 * W, hipMemcpyDeviceToDevice, s));
-    launch_log_prior(c.consts.p, S->prior, S->X.p, S->W, S->lp_x.p, s);
-  } else {
-    launch_sampler_init(c.consts.p, S->prior, p.seed, S->W, S->X.p, S->lp_x.p, s);
-  }
-  const bool prior_only = p.flags & RBFL_SAMPLER_PRIOR_ONLY;
-  if (prior_only) {
-    launch_fill(S->lnl_x.p, W, 0.0, s);
-  } else {
-    reserve(c, std::min<int64_t>(std::max<int64_t>(M, 1), 1 << 20));
-    eval(c, S->X.p, W, S->lnl_x.p, p.form, s);
-  }
-  S->stage = SamplerState{0, 0, nullptr, 0, 1, (uint64_t)p.anneal_steps, p.beta0, -1.0};
-  RBFL_HIP(hipMemcpyAsync(S->st.p, &S->stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
-  RBFL_HIP(hipStreamSynchronize(s));
-  // capture one step (profiling off: no events inside the graph)
-  const bool prof = c.profile;
-  c.profile = false;
-  RBFL_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
-  RBFL_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
-  try {
-    sampler_step(*S, S->cap);
-  } catch (...) {
-    hipGraph_t g = nullptr;
-    (void)hipStreamEndCapture(S->cap, &g);
-    if (g) (void)hipGraphDestroy(g);
-    c.profile = prof;
-    throw;
-  }
-  c.profile = prof;
-  RBFL_HIP(hipStreamEndCapture(S->cap, &S->graph));
-  RBFL_HIP(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
-  S->last = s;
-  c.graph_users += 1;
-  return S.release();
-}
-
-static void sampler_run(rbfl_sampler_ctx &S, int64_t steps, int thin, double *chain, int64_t slots, hipStream_t s) {
-  require(steps >= 0, "steps must be >= 0");
-  require(thin >= 1, "thin must be >= 1");
-  require(chain == nullptr || slots >= 1, "chain needs slots >= 1");
-  if (S.last && S.last != s) RBFL_HIP(hipStreamSynchronize(S.last));
-  // the staged state is read by an asynchronous copy: let the previous one finish
-  RBFL_HIP(hipStreamSynchronize(s));
-  S.stage = SamplerState{S.steps, S.steps, chain, chain ? slots : 0, thin, (uint64_t)S.spec.anneal_steps,
-                         S.spec.beta0, S.beta_fixed};
-  RBFL_HIP(hipMemcpyAsync(S.st.p, &S.stage, sizeof(SamplerState), hipMemcpyHostToDevice, s));
-  for (int64_t i = 0; i < steps; ++i) RBFL_HIP(hipGraphLaunch(S.exec, s));
-  S.steps += (uint64_t)steps;
-  S.last = s;
-}
-
-// Tempered sequential Monte Carlo from the current walkers (Del Moral, Doucet
-// and Jasra 2006), taking them as prior draws (weight beta = 0): per stage
-// the increment db in (0, 1 - beta] whose weights w = L^db keep an effective
-// sample size of ess_frac W (the whole remainder when that stays above),
-// found by 60 bisection halvings; ln Z += log mean w; systematic resampling
-// at positions (u + i) / W, u = Philox(walker 2^32 - 1, step = stage index,
-// half 1, call 4); then `moves` sampler steps at the new beta.
-static void sampler_smc(rbfl_sampler_ctx &S, double ess_frac, int moves, int max_stages, hipStream_t s,
-                        double *log_z, int32_t *stages_out, double *beta_out) {
-  require(!(S.spec.flags & RBFL_SAMPLER_PRIOR_ONLY), "a prior-only sampler has no likelihood to temper");
-  require(ess_frac > 0.0 && ess_frac < 1.0, "ess_frac must be in (0, 1)");
-  require(moves >= 1 && max_stages >= 1, "moves and max_stages must be >= 1");
-  if (S.last && S.last != s) RBFL_HIP(hipStreamSynchronize(S.last));
-  const int W = S.W;
-  std::vector<double> l(W), w(W), cum(W);
-  std::vector<int32_t> idx(W);
-  DevBuf<int32_t> d_idx;
-  d_idx.alloc(W);
-  DevBuf<double> Xt, lt, pt;
-  Xt.alloc((size_t)11 * W);
-  lt.alloc(W);
-  pt.alloc(W);
-  double beta = 0.0, lz = 0.0;
-  int st = 0;
-  for (; st < max_stages && beta < 1.0; ++st) {
-    RBFL_HIP(hipMemcpyAsync(l.data(), S.lnl_x.p, sizeof(double) * W, hipMemcpyDeviceToHost, s));
-    RBFL_HIP(hipStreamSynchronize(s));
-    double m = -std::numeric_limits<double>::infinity();
-    for (double v : l)
-      if (std::isfinite(v)) m = std::max(m, v);
-    require(std::isfinite(m), "no walker has a finite ln L");
-    auto ess = [&](double db) {
-      Sum s1, s2;
-      for (int i = 0; i < W; ++i) {
-        const double e = std::isfinite(l[i]) ? exp(db * (l[i] - m)) : 0.0;
-        s1.add(e);
-        s2.add(e * e);
-      }
-      return s1.value() * s1.value() / s2.value();
-    };
-    const double rem = 1.0 - beta;
-    double db = rem;
-    if (ess(rem) < ess_frac * W) {
-      double lo = 0.0, hi = rem;
-      for (int it = 0; it < 60; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (ess(mid) >= ess_frac * W)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      db = lo;
-    }
-    double c = 0.0;
-    Sum tot;
-    for (int i = 0; i < W; ++i) {
-      w[i] = std::isfinite(l[i]) ? exp(db * (l[i] - m)) : 0.0;
-      c += w[i];
-      cum[i] = c;
-      tot.add(w[i]);
-    }
-    lz += db * m + log(tot.value() / W);
-    for (int i = 0; i < W; ++i) cum[i] /= c;
-    double u = 0.0, unused = 0.0;
-    philox_pair(S.spec.seed, 0xFFFFFFFFu, S.smc_stages, 1, 4, &u, &unused);
-    int j = 0;
-    for (int i = 0; i < W; ++i) {
-      const double pos = (u + (double)i) / (double)W;
-      while (j < W - 1 && cum[j] <= pos) ++j;
-      idx[i] = j;
-    }
-    RBFL_HIP(hipMemcpyAsync(d_idx.p, idx.data(), sizeof(int32_t) * W, hipMemcpyHostToDevice, s));
-    launch_gather_walkers(S.X.p, S.lnl_x.p, S.lp_x.p, d_idx.p, W, Xt.p, lt.p, pt.p, s);
-    RBFL_HIP(hipMemcpyAsync(S.X.p, Xt.p, sizeof(double) * 11 * W, hipMemcpyDeviceToDevice, s));
-    RBFL_HIP(hipMemcpyAsync(S.lnl_x.p, lt.p, sizeof(double) * W, hipMemcpyDeviceToDevice, s));
-    RBFL_HIP(hipMemcpyAsync(S.lp_x.p, pt.p, sizeof(double) * W, hipMemcpyDeviceToDevice, s));
-    beta = std::min(1.0, beta + db);
-    if (rem - db <= 0.0) beta = 1.0;
-    S.smc_stages += 1;
-    S.beta_fixed = beta;
-    sampler_run(S, moves, 1, nullptr, 0, s);
-  }
-  RBFL_HIP(hipStreamSynchronize(s));
-  if (log_z) *log_z = lz;
-  if (stages_out) *stages_out = st;
-  if (beta_out) *beta_out = beta;
-}
-
-static void sampler_query(rbfl_sampler_ctx &S, int what, double *out, size_t bytes) {
-  require(out != nullptr, "out is NULL");
-  if (S.last) RBFL_HIP(hipStreamSynchronize(S.last));
-  const size_t W = (size_t)S.W;
-  switch (what) {
-    case 0: {
-      require(bytes >= sizeof(double) * 12 * W, "buffer too small");
-      RBFL_HIP(hipMemcpy(out, S.X.p, sizeof(double) * 11 * W, hipMemcpyDeviceToHost));
-      RBFL_HIP(hipMemcpy(out + 11 * W, S.lnl_x.p, sizeof(double) * W, hipMemcpyDeviceToHost));
-      return;
-    }
-    case 1:
-    case 2: {
-      std::vector<unsigned long long> a(W);
-      RBFL_HIP(hipMemcpy(a.data(), S.acc.p, sizeof(unsigned long long) * W, hipMemcpyDeviceToHost));
-      if (what == 1) {
-        require(bytes >= sizeof(double) * W, "buffer too small");
-        for (size_t i = 0; i < W; ++i) out[i] = (double)a[i];
-      } else {
-        require(bytes >= sizeof(double) * 2, "buffer too small");
-        double tot = 0.0;
-        for (auto v : a) tot += (double)v;
-        out[0] = (double)S.steps;
-        out[1] = S.steps ? tot / ((double)S.steps * (double)W) : 0.0;
-      }
-      return;
-    }
-    default:
-      throw Error(RBFL_E_INVALID_ARG, "unknown sampler query");
-  }
-}
-
-static void prior_weights(Ctx &c, const double *params, int64_t ld, int64_t n, const double box[8], double d_exp,
-                          double *logw, double *n_eff, hipStream_t s) {
-  require(params != nullptr && logw != nullptr && box != nullptr, "NULL argument");
-  require(n >= 0 && ld >= n, "need 0 <= n <= ld");
-  require(std::isfinite(d_exp), "d_exp must be finite");
-  PriorBox b;
-  for (int d = 0; d < 4; ++d) {
-    b.lo[d] = box[2 * d];
-    b.hi[d] = box[2 * d + 1];
-    require(b.lo[d] <= b.hi[d], "box bounds must satisfy lo <= hi");
-  }
-  b.d_exp = d_exp;
-  launch_prior_weights(c.consts.p, params, ld, n, b, logw, s);
-  if (n_eff) {
-    std::vector<double> w((size_t)n);
-    RBFL_HIP(hipMemcpyAsync(w.data(), logw, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    RBFL_HIP(hipStreamSynchronize(s));
-    double mx = -std::numeric_limits<double>::infinity();
-    for (double v : w) mx = std::max(mx, v);
-    Sum s1, s2;
-    if (std::isfinite(mx))
-      for (double v : w) {
-        const double e = exp(v - mx);
-        s1.add(e);
-        s2.add(e * e);
-      }
-    *n_eff = s2.value() > 0.0 ? s1.value() * s1.value() / s2.value() : 0.0;
-  }
-}
-}  // namespace rbfl
-
-namespace rbfl {
-// Captures one launch of the plan into a HIP graph on the plan's own stream.
-static void plan_capture(Plan &p) {
-  if (!p.cap_stream) RBFL_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
-  RBFL_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
-  try {
-    plan_run(p, p.cap_stream);
-  } catch (...) {
-    hipGraph_t g = nullptr;
-    (void)hipStreamEndCapture(p.cap_stream, &g);
-    if (g) (void)hipGraphDestroy(g);
-    throw;
-  }
-  RBFL_HIP(hipStreamEndCapture(p.cap_stream, &p.graph));
-  RBFL_HIP(hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0));
-}
-
-// Split-form digit counts per event: ln L of the whole batch with every event
-// at S = 5 .. 8 digits (each timed, median of 3) against the FP64 plan's.  An
-// event with at least kTuneMinValid in-domain proposals takes the fewest
-// digits whose ln L stays within RBFL_SPLIT_TOL / 10 of the FP64 form's on
-// them (same domain flags; the margin of a decade covers proposals the tuner
-// did not see), down to no fewer than 5; with fewer in-domain proposals it
-// keeps the default 7 digits unless 7 misses RBFL_SPLIT_TOL.  When no count
-// meets RBFL_SPLIT_TOL the most accurate one is kept (split_tol_state then
-// says so).
-static void plan_tune_split(Plan &p, hipStream_t s) {
-  constexpr int64_t kTuneMinValid = 256;
-  const int n_ev = (int)p.ctx.size();
-  p.split = false;
-  plan_layout(p, ragged_fused_variants(), s);
-  plan_run(p, s);
-  std::vector<double> ref(p.total), got(p.total);
-  RBFL_HIP(hipMemcpyAsync(ref.data(), p.lnl, sizeof(double) * p.total, hipMemcpyDeviceToHost, s));
-  RBFL_HIP(hipStreamSynchronize(s));
-  p.split = true;
-  std::vector<std::array<double, 4>> err(n_ev);
-  std::vector<int64_t> valid(n_ev, 0);
-  {
-    int64_t q0 = 0;
-    for (int e = 0; e < n_ev; ++e) {
-      for (int64_t i = q0; i < q0 + p.counts[e]; ++i) valid[e] += std::isfinite(ref[i]) ? 1 : 0;
-      q0 += p.counts[e];
-    }
-  }
-  hipEvent_t e0, e1;
-  RBFL_HIP(hipEventCreate(&e0));
-  RBFL_HIP(hipEventCreate(&e1));
-  for (int v = 0; v < 4; ++v) {
-    std::fill(p.S.begin(), p.S.end(), split_variant_slices(v));
-    plan_layout_split(p, s);
-    plan_run(p, s);
-    RBFL_HIP(hipMemcpyAsync(got.data(), p.lnl, sizeof(double) * p.total, hipMemcpyDeviceToHost, s));
-    RBFL_HIP(hipStreamSynchronize(s));
-    int64_t q0 = 0;
-    for (int e = 0; e < n_ev; ++e) {
-      double m = 0.0;
-      for (int64_t i = q0; i < q0 + p.counts[e]; ++i) {
-        if (std::isfinite(ref[i]) != std::isfinite(got[i]) || std::isnan(ref[i]) != std::isnan(got[i])) {
-          m = INFINITY;
-          break;
-        }
-        if (std::isfinite(ref[i])) m = std::max(m, std::fabs(got[i] - ref[i]));
-      }
-      err[e][v] = m;
-      q0 += p.counts[e];
-    }
-    double t[3];
-    for (int r = 0; r < 3; ++r) {
-      RBFL_HIP(hipEventRecord(e0, s));
-      plan_run(p, s);
-      RBFL_HIP(hipEventRecord(e1, s));
-      RBFL_HIP(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
-      t[r] = ms;
-    }
-    std::sort(t, t + 3);
-    p.tune_ms[v] = t[1];
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  bool all_ok = true;
-  for (int e = 0; e < n_ev; ++e) {
-    int pick = -1;
-    if (valid[e] >= kTuneMinValid) {
-      for (int v = 0; v < 4 && pick < 0; ++v)
-        if (err[e][v] <= 0.1 * RBFL_SPLIT_TOL) pick = v;
-    }
-    if (pick < 0) {
-      for (int v = kSplitDefaultVariant; v < 4 && pick < 0; ++v)
-        if (err[e][v] <= RBFL_SPLIT_TOL) pick = v;
-    }
-    if (pick < 0) {
-      all_ok = false;
-      pick = 3;
-      for (int v = 2; v >= 0; --v)
-        if (err[e][v] < err[e][pick]) pick = v;
-    }
-    p.S[e] = split_variant_slices(pick);
-  }
-  p.split_tol_state = all_ok ? 1 : 0;
-}
-
-static rbfl_plan_ctx *plan_create(const rbfl_handle *hs, int n_ev, const int64_t *counts, const double *params,
-                                  double *lnl, uint32_t flags, hipStream_t s) {
-  require(hs != nullptr && counts != nullptr && params != nullptr && lnl != nullptr, "NULL argument");
-  require(n_ev >= 1 && n_ev <= 4096, "n_events must be in 1 .. 4096");
-  require((flags & ~(uint32_t)(RBFL_PLAN_GRAPH | RBFL_PLAN_AUTOTUNE | RBFL_PLAN_SPLIT)) == 0, "unknown plan flags");
-  std::unique_ptr<rbfl_plan_ctx> pc(new rbfl_plan_ctx());
-  Plan &p = pc->p;
-  int64_t yelems = 0, belems = 0;
-  for (int e = 0; e < n_ev; ++e) {
-    require(hs[e] != nullptr, "NULL handle in the event list");
-    require(hs[e]->c.n_bands == 1, "multi-event plans cover frozen antenna patterns only (n_bands = 1)");
-    require(counts[e] >= 1, "every event needs at least one proposal");
-    p.ctx.push_back(&hs[e]->c);
-    p.counts.push_back(counts[e]);
-    p.total += counts[e];
-    yelems += counts[e] * hs[e]->c.Kp;
-    belems += (int64_t)hs[e]->c.rows * rows_ld(counts[e]);
-  }
-  p.params = params;
-  p.lnl = lnl;
-  p.ev_work.alloc(n_ev);
-  p.ev_param.alloc(n_ev);
-  p.Y.alloc((size_t)yelems);
-  p.Bt.alloc((size_t)belems);
-  p.counter.alloc(4);
-  if (flags & RBFL_PLAN_SPLIT) {
-    int64_t aelems = 0;
-    for (int e = 0; e < n_ev; ++e) {
-      prepare(*p.ctx[e], RBFL_FORM_SPLIT);
-      aelems += (int64_t)split_max_slices() * p.ctx[e]->rows * counts[e];
-    }
-    p.AS.alloc((size_t)aelems);
-    p.rscale.alloc((size_t)p.total);
-    p.ev_group.alloc(n_ev);
-    p.S.assign(n_ev, split_variant_slices(kSplitDefaultVariant));
-    if (flags & RBFL_PLAN_AUTOTUNE) {
-      plan_tune_split(p, s);
-    } else {
-      for (int e = 0; e < n_ev; ++e) p.S[e] = split_variant_slices(p.ctx[e]->variant[RBFL_FORM_SPLIT]);
-    }
-    p.split = true;
-    plan_layout_split(p, s);
-    p.Bt.reset();        // the FP64 basis rows served only the tuner's reference
-  } else if (flags & RBFL_PLAN_AUTOTUNE) {
-    hipEvent_t e0, e1;
-    RBFL_HIP(hipEventCreate(&e0));
-    RBFL_HIP(hipEventCreate(&e1));
-    int best = 0;
-    double best_ms = 1e300;
-    for (int v = 0; v < ragged_variants() && v < 8; ++v) {
-      plan_layout(p, v, s);
-      plan_run(p, s);
-      double t[3];
-      for (int r = 0; r < 3; ++r) {
-        RBFL_HIP(hipEventRecord(e0, s));
-        plan_run(p, s);
-        RBFL_HIP(hipEventRecord(e1, s));
-        RBFL_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
-        t[r] = ms;
-      }
-      std::sort(t, t + 3);
-      p.tune_ms[v] = t[1];
-      if (t[1] < best_ms) {
-        best_ms = t[1];
-        best = v;
-      }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    plan_layout(p, best, s);
-  } else {
-    plan_layout(p, ragged_fused_variants(), s);
-  }
-  if (flags & RBFL_PLAN_GRAPH) plan_capture(p);
-  return pc.release();
-}
-
-// Pins the FP64 tile variant of a plan: new layout, and a new graph if the
-// plan has one.
-static void plan_set_variant(Plan &p, int v, hipStream_t s) {
-  if (p.split) throw Error(RBFL_E_STATE, "a split-form plan has no FP64 tile variants");
-  require(v >= 0 && v < ragged_variants(), "variant out of range");
-  RBFL_HIP(hipStreamSynchronize(s));
-  plan_layout(p, v, s);
-  if (p.exec) {
-    (void)hipGraphExecDestroy(p.exec);
-    (void)hipGraphDestroy(p.graph);
-    p.exec = nullptr;
-    p.graph = nullptr;
-    plan_capture(p);
-  }
-}
-}  // namespace rbfl
 
 extern "C" {
 
@@ -3435,62 +2381,6 @@ int32_t rbfl_profile(rbfl_handle h, int32_t on) {
   });
 }
 
-int32_t rbfl_plan_create(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
-                         double *lnl, uint32_t flags, void *stream, rbfl_plan *out) {
-  return rbfl::guarded([&] {
-    rbfl::require(out != nullptr, "out is NULL");
-    *out = nullptr;
-    *out = rbfl::plan_create(hs, n_events, counts, params, lnl, flags, reinterpret_cast<hipStream_t>(stream));
-  });
-}
-
-int32_t rbfl_plan_launch(rbfl_plan plan, void *stream) {
-  return rbfl::guarded([&] {
-    rbfl::require(plan != nullptr, "plan is NULL");
-    rbfl::Plan &p = plan->p;
-    if (p.exec)
-      RBFL_HIP(hipGraphLaunch(p.exec, reinterpret_cast<hipStream_t>(stream)));
-    else
-      rbfl::plan_run(p, reinterpret_cast<hipStream_t>(stream));
-  });
-}
-
-int32_t rbfl_plan_query(rbfl_plan plan, double *out, size_t bytes) {
-  return rbfl::guarded([&] {
-    rbfl::require(plan != nullptr, "plan is NULL");
-    const rbfl::Plan &p = plan->p;
-    double v[16] = {(double)p.variant, (double)p.total_items, (double)p.grid, (double)p.total};
-    for (int i = 0; i < 8; ++i) v[4 + i] = p.tune_ms[i];
-    v[12] = p.split ? 1.0 : 0.0;
-    v[13] = p.split ? (double)*std::min_element(p.S.begin(), p.S.end()) : 0.0;
-    v[14] = p.split ? (double)*std::max_element(p.S.begin(), p.S.end()) : 0.0;
-    v[15] = (double)p.split_tol_state;
-    rbfl::require(out != nullptr && bytes >= 12 * sizeof(double), "output buffer too small (need at least 96 bytes)");
-    std::memcpy(out, v, std::min(bytes, sizeof(v)));
-  });
-}
-
-int32_t rbfl_plan_set_variant(rbfl_plan plan, int32_t variant, void *stream) {
-  return rbfl::guarded([&] {
-    rbfl::require(plan != nullptr, "plan is NULL");
-    rbfl::plan_set_variant(plan->p, variant, reinterpret_cast<hipStream_t>(stream));
-  });
-}
-
-int32_t rbfl_plan_destroy(rbfl_plan plan) {
-  return rbfl::guarded([&] { delete plan; });
-}
-
-int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t *counts, const double *params,
-                         double *lnl, void *stream) {
-  return rbfl::guarded([&] {
-    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::unique_ptr<rbfl_plan_ctx> hold(rbfl::plan_create(hs, n_events, counts, params, lnl, 0u, s));
-    rbfl::plan_run(hold->p, s);
-    RBFL_HIP(hipStreamSynchronize(s));
-  });
-}
-
 int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
@@ -3555,53 +2445,6 @@ int32_t rbfl_mlp_get(rbfl_mlp m, int32_t what, float *out, size_t bytes) {
 
 int32_t rbfl_mlp_destroy(rbfl_mlp m) {
   return rbfl::guarded([&] { delete m; });
-}
-
-int32_t rbfl_sampler_create(rbfl_handle h, const rbfl_sampler_spec *spec, const double *init, void *stream,
-                            rbfl_sampler *out) {
-  return rbfl::guarded([&] {
-    rbfl::require(h != nullptr && out != nullptr, "NULL argument");
-    *out = nullptr;
-    *out = rbfl::sampler_create(h->c, spec, init, reinterpret_cast<hipStream_t>(stream));
-  });
-}
-
-int32_t rbfl_sampler_run(rbfl_sampler s, int64_t steps, int32_t thin, double *chain, int64_t slots, void *stream) {
-  return rbfl::guarded([&] {
-    rbfl::require(s != nullptr, "sampler is NULL");
-    rbfl::sampler_run(*s, steps, thin, chain, slots, reinterpret_cast<hipStream_t>(stream));
-  });
-}
-
-int32_t rbfl_sampler_smc(rbfl_sampler s, double ess_frac, int32_t moves, int32_t max_stages, void *stream,
-                         double *log_evidence, int32_t *stages, double *beta) {
-  return rbfl::guarded([&] {
-    rbfl::require(s != nullptr, "sampler is NULL");
-    rbfl::sampler_smc(*s, ess_frac, moves, max_stages, reinterpret_cast<hipStream_t>(stream), log_evidence, stages,
-                      beta);
-  });
-}
-
-int32_t rbfl_sampler_query(rbfl_sampler s, int32_t what, double *out, size_t bytes) {
-  return rbfl::guarded([&] {
-    rbfl::require(s != nullptr, "sampler is NULL");
-    rbfl::sampler_query(*s, what, out, bytes);
-  });
-}
-
-int32_t rbfl_sampler_destroy(rbfl_sampler s) {
-  return rbfl::guarded([&] {
-    if (s && s->last) (void)hipStreamSynchronize(s->last);
-    delete s;
-  });
-}
-
-int32_t rbfl_prior_weights(rbfl_handle h, const double *params, int64_t ld, int64_t n, const double box[8],
-                           double d_exp, double *logw, double *n_eff, void *stream) {
-  return rbfl::guarded([&] {
-    rbfl::require(h != nullptr, "handle is NULL");
-    rbfl::prior_weights(h->c, params, ld, n, box, d_exp, logw, n_eff, reinterpret_cast<hipStream_t>(stream));
-  });
 }
 
 int32_t rbfl_destroy(rbfl_handle h) {

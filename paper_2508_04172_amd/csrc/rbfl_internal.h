@@ -277,6 +277,14 @@ struct Ctx {
 // RBFL_DEBUG host-side bounds checks (rbfl_host.hip)
 bool debug_mode();
 void debug_check_layout(const Ctx &c);
+void debug_require(bool ok, const std::string &what);   // RBFL_E_STATE "RBFL_DEBUG: what" unless ok
+
+// Handle operations shared by the host files (rbfl_host.hip): reduced-
+// precision weights of a form, work space for n proposals, and a batched
+// evaluation in a form (rbfl_prepare, rbfl_reserve, rbfl_eval).
+void prepare(Ctx &c, int form);
+void reserve(Ctx &c, int64_t n);
+void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s);
 
 // ---- start-up kernels (build_kernels.hip) ----
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
