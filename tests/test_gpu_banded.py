@@ -173,6 +173,28 @@ def test_banded_handle_tracks_the_rotating_exact_likelihood_better_than_frozen()
     assert lib.rbfl_fuse_epilogue(hb._h, 0) == rbfl.OK
 
 
+def test_sampler_drives_the_banded_handle():
+    """The GPU-resident sampler on a banded handle: its captured step graph
+    runs the banded epilogue, and after a few steps every walker's stored
+    ln L is the handle's own evaluation of that walker (same bits)."""
+    torch = _torch()
+    h = handle(CFG)
+    W = 512
+    s = rbfl.Sampler(h, W, (CFG.t_trig - CFG.tc_span, CFG.t_trig + CFG.tc_span), (0.5 * h.d_ref(), 2.0 * h.d_ref()),
+                     seed=7, p_jump=0.1)
+    s.run(4)
+    st = s.walkers_state()
+    n_acc, _ = s.stats()
+    s.close()
+    P = np.ascontiguousarray(st[:11])
+    got = run(h, P)
+    fin = np.isfinite(st[11])
+    assert fin.sum() >= W // 2 and n_acc >= 0
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.array_equal(st[11][fin], got[fin])
+    del torch
+
+
 def test_banded_save_load_round_trip(tmp_path):
     h = handle(CFG)
     path = str(tmp_path / "banded.rbfl")

@@ -55,6 +55,28 @@ def test_eval_static_equals_eval_on_two_calls():
         assert nan_a == nan_b == 1
 
 
+@pytest.mark.timeout(600)
+def test_eval_static_equals_eval_time_banded():
+    """The same on a handle with time-banded antenna patterns (4 bands, 12
+    output blocks): the banded epilogue behind both entry points."""
+    cfg = wl.SMALL_BANDED
+    h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
+    sz = h.sizes()
+    rows = (sz["N"] + sz["M"] + 31) // 32 * 32
+    kp = (sz["K"] + 127) // 128 * 128
+    chunk = (rbfl.STATIC_SCRATCH_BYTES // (8 * (rows + kp))) // 8 * 8
+    for call, n in enumerate((3 * chunk + 1237, chunk + 5)):
+        idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=41 + call)
+        params = rbfl.params_soa(h, wl.queries(cfg, n=n, seed=43 + call).near_nodes(h.nodes(), idx, jit),
+                                 cfg.t_trig)
+        params[5, 11] = np.nan
+        a, b, nan_a, nan_b = both_entry_points(h, params)
+        assert np.isfinite(a).sum() > n // 4
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), f"banded call {call}: ln L differs"
+        assert nan_a == nan_b == 1
+    h.close()
+
+
 def test_eval_static_rejects_bad_arguments():
     cfg, h = handle("cfg2")
     lib = rbfl.load()
