@@ -388,8 +388,8 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_banded(const EvalConsts *
   if (g >= nb) return;   // whole wave leaves together
   double p[11];
   const int pre = epi_prelude(c, params, ld, b0 + g, p);
-  if (pre == 2) {
-    if (lane == 0) lnl[b0 + g] = __builtin_nan("");
+  if (pre != 0) {   // NaN input, or outside the ellipsoid or the physical region
+    if (lane == 0) lnl[b0 + g] = pre == 2 ? __builtin_nan("") : -__builtin_huge_val();
     return;
   }
   const double alpha = p[4], dec = p[5], psi = p[6], iota = p[7], phi = p[8], tc = p[9], dl = p[10];
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_banded(const EvalConsts *
   const int per = (64 / nm) * nm;
   const int n_pairs = c.n_v * nm;
   const double *y = Y + g * c.Kp;
-  bool ok = pre == 0;
+  bool ok = true;
   double sum = 0.0, comp = 0.0;
   for (int p0 = 0; p0 < n_pairs; p0 += per) {
     const int pr = p0 + lane;
