@@ -334,7 +334,7 @@ def main():
 
 def bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64, n_train, epochs, steps):
     """Surrogate form: MLP 4 -> 256 -> 256 -> K trained by the library's own
-    kernels on proposals whose targets the FP64 interpolant computes; judged on
+    kernels on proposals whose targets the FP64 interpolant computes; checked on
     1e4 held-out proposals at |d ln L| <= 1e-3 (fallback to the interpolant
     otherwise).  The network path's throughput is reported either way, and the
     network's own kernels (the three FP32 MFMA layers, HIP events) against the

@@ -472,7 +472,7 @@ int32_t rbfl_eval_ragged(const rbfl_handle *hs, int32_t n_events, const int64_t 
 
 /*
  * Learned surrogate (not in the paper: a network that replaces the
- * interpolant contraction, keeping the interpolant as fallback and judge).
+ * interpolant contraction, keeping the interpolant as fallback and reference).
  * A multilayer perceptron x -> H -> H -> K with SiLU activations maps the
  * unit-ball coordinates x = delta_e / a to the K interpolated reals
  * (standardised per column by the training set's mean and deviation).  It is
@@ -508,8 +508,8 @@ typedef struct {
                                     standardised residual; inference adds the base back in FP64 */
 } rbfl_train_spec;
 int32_t rbfl_surrogate_train(rbfl_handle h, const rbfl_train_spec *spec, void *stream);
-/* Overrides the held-out judge (on = 1: the surrogate form uses the network
- * even if it failed the check; 0: back to the judge's decision).  For
+/* Overrides the held-out check (on = 1: the surrogate form uses the network
+ * even if it failed the check; 0: back to the check's decision).  For
  * measuring the network path; RBFL_E_STATE if no surrogate was trained. */
 int32_t rbfl_surrogate_force(rbfl_handle h, int32_t on);
 

@@ -2048,7 +2048,7 @@ static void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s) {
     last = l;
   }
   const double train_s = seconds_since(t0);
-  // held-out judge: ln L through the network against ln L through the interpolant
+  // held-out check: ln L through the network against ln L through the interpolant
   double dmax = std::numeric_limits<double>::infinity(), dmed = dmax;
   bool accepted = false;
   if (sp->n_holdout > 0) {

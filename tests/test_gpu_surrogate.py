@@ -1,5 +1,5 @@
 """Surrogate network: GPU forward/backward/Adam against the FP64 oracle,
-training, the held-out judge and the RBF fallback, and what the network
+training, the held-out check and the RBF fallback, and what the network
 gains over the interpolant it replaces."""
 import time
 
@@ -61,7 +61,7 @@ def _params_device(torch, h, cfg, n, seed, near=True):
     return torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd, cfg.t_trig))).cuda()
 
 
-def test_training_judge_and_fallback():
+def test_training_check_and_fallback():
     torch = _torch()
     cfg = wl.SMALL_MULTI
     h = rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))
@@ -116,10 +116,10 @@ def test_surrogate_gain_at_the_bar():
 
     Single-detector workload (K = 41 interpolated reals), the network
     4 -> 256 -> 256 -> K trained on 2e5 proposals of a converged sampler's
-    region (Gaussian of width 0.05 about the centre) and judged on 1e4
+    region (Gaussian of width 0.05 about the centre) and checked on 1e4
     held-out proposals of the same region, plain and in the residual form
     (FP64 cubic least-squares base plus the network on the standardised
-    residual).  Asserted: the judge applies the bar (its maximum equals the
+    residual).  Asserted: the check applies the bar (its maximum equals the
     one recomputed here through the forced network path, and it accepts
     exactly when that maximum is <= 1e-3); a rejected surrogate leaves the
     interpolant's ln L bit for bit; an accepted one stays within 1e-3 on
