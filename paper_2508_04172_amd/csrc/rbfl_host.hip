@@ -1074,10 +1074,13 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   DevBuf<double2> d_sig;
   d_sig.alloc((size_t)c.n_v * c.N * nm2);
   RBFL_HIP(hipMemsetAsync(d_sig.p, 0, sizeof(double2) * d_sig.n, stream));
-  // node batches sized so the templates of a batch stay within ~8 GiB of the
-  // 288 GB of HBM (the 2048 s third-generation case then takes 27 nodes per batch)
-  const size_t budget = (size_t)8 << 30;
+  // node batches sized so the templates of a batch stay within 32 GiB of the
+  // 288 GB of HBM: long segments (2048 s at 4096 Hz from 5 Hz: ~150 MB of
+  // templates per node) then still fill the windowed DFT's 64-node tiles
+  const size_t budget = (size_t)32 << 30;
   int nb_max = (int)std::max<size_t>(1, std::min<size_t>(c.N, budget / ((size_t)c.n_modes * J * sizeof(double2))));
+  // whole 64-node tiles of the windowed DFT where the batch is cut by the budget
+  if (nb_max < c.N && nb_max >= 64) nb_max &= ~63;
   DevBuf<double2> d_A;
   d_A.alloc((size_t)c.n_modes * nb_max * J);
   // split the bin range of the windowed DFT so each launch has >= ~1024 blocks
