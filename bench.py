@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--check-sample", type=int, default=2000)
+    ap.add_argument("--ragged-build-threads", type=int, default=4,
+                    help="host threads (one stream each) building the multi-event batch's handles")
     ap.add_argument("--ragged-events", type=int, default=64,
                     help="events in the multi-event batch form (0 = skip)")
     ap.add_argument("--surrogate-train", type=int, default=200000,
@@ -794,9 +796,28 @@ def bench_ragged(args, np, torch, rbfl, wl):
     sample of every event's proposals."""
     evs = wl.ragged_events(args.ragged_events)
     walkers = 1024
-    log(f"ragged: building {len(evs)} events")
+    n_thr = max(1, args.ragged_build_threads)
+    log(f"ragged: building {len(evs)} events on {n_thr} host threads (one stream each)")
     t0 = time.time()
-    hs = [rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg)) for cfg in evs]
+    # independent start-ups overlap: each worker builds its events on its own
+    # stream (rbfl_build is synchronous on the stream it is given)
+    import queue
+    from concurrent.futures import ThreadPoolExecutor
+    free = queue.Queue()
+    for _ in range(n_thr):
+        free.put(torch.cuda.Stream())
+
+    def build_one(cfg):
+        st = free.get()
+        try:
+            return rbfl.Handle.from_config(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg),
+                                           stream=st.cuda_stream)
+        finally:
+            free.put(st)
+
+    with ThreadPoolExecutor(max_workers=n_thr) as ex:
+        hs = list(ex.map(build_one, evs))
+    torch.cuda.synchronize()
     build_s = time.time() - t0
     stages = np.sum([h.timing()[:6] for h in hs], axis=0)
     log(f"ragged: start-up {build_s:.1f} s; summed stages (data, frame, series, SVD, RBF solve, total) "
@@ -824,6 +845,7 @@ def bench_ragged(args, np, torch, rbfl, wl):
         return (time.perf_counter() - t) / steps
 
     res = {"events": len(hs), "walkers_per_event": walkers, "startup_s": round(build_s, 2),
+           "startup_threads": n_thr,
            "startup_stage_s": {k: round(float(v), 2) for k, v in
                                zip(("data", "frame_nodes", "series", "svd", "rbf_solve", "total"), stages)}}
     out = {}
