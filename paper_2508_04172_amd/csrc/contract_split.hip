@@ -20,15 +20,23 @@
 // with i + j >= S and the digit remainders costs at most (S + 3) 254^-S of
 // s_q s_c per kernel row.
 //
-// Tiles.  A workgroup of 8 waves (4 along the proposals x 2 along the
-// columns, one workgroup per CU, two waves per SIMD) computes 128 proposals x
-// 64 columns: per staged digit byte that is 4/3 the products of a 64 x 64
-// tile, whose L2 and MALL traffic bounded it.  Each wave computes one
-// 32 x 32 tile with v_mfma_i32_32x32x32_i8, whose lane l holds
-// A[l%32][16(l/32) + e] and B[16(l/32) + e][l%32] (e < 16, 16 int8 in 4 VGPRs) and accumulator element i = D[8(i/4) + 4(l/32) + i%4][l%32]
-// (measured on gfx950).  Digits of 32 kernel rows of both operands are
-// staged through LDS per step, double-buffered, the next step's global loads
-// in flight during the current step's MFMAs.
+// Tiles.  A workgroup of 4 waves (one per SIMD, so each wave may hold 512
+// registers: the S level accumulators of two 32 x 32 blocks sit in AGPRs)
+// computes 128 proposals x 64 columns; wave w computes proposals
+// 32 w .. 32 w + 31 against all 64 columns with v_mfma_i32_32x32x32_i8,
+// whose lane l holds A[l%32][16(l/32) + e] and B[16(l/32) + e][l%32] (e < 16,
+// 16 int8 in 4 VGPRs) and accumulator element i = D[8(i/4) + 4(l/32) + i%4][l%32]
+// (measured on gfx950).  Every wave loads its own operands straight from
+// global memory into those registers (the four waves' B fragments coincide
+// and are served by the CU's L1), one 32-row step ahead: no LDS, no
+// barriers.  Against the LDS-staged 8-wave tile (two waves per SIMD, one
+// barrier per 32-row step) this took 11-17% less time for S = 5..8 on the
+// 3-detector shape; staging through LDS by direct global-to-LDS loads in a
+// three- or four-stage ring was within 3% of it.  With any of these the
+// kernel runs far below the matrix cores' own rate (the same MFMA sequence
+// from registers alone reaches 0.88 of the int8 peak, from LDS alone 0.84):
+// the digit traffic lowers the clock by about 18% under this load and
+// stalls the rest.
 //
 // Memory layout of the digits (16-row groups g, G = rows / 16 of them):
 //   rows   AS[i][g][q][16]   (q < nb, one chunk of proposals)
@@ -42,10 +50,9 @@ namespace rbfl {
 namespace {
 
 constexpr int kMaxSlices = 8;
-constexpr int kSplitWQ = 4;      // waves along the proposals (each 32 proposals x 32 columns)
-constexpr int kSplitQ = 32 * kSplitWQ;   // proposals per workgroup
-constexpr int kSplitC = 64;      // columns per workgroup (two waves)
-constexpr int kSplitThreads = 128 * kSplitWQ;
+constexpr int kSplitQ = 128;     // proposals per workgroup (four waves of 32)
+constexpr int kSplitC = 64;      // columns per workgroup (two 32-column blocks per wave)
+constexpr int kSplitThreads = 256;
 constexpr int kMaxSplitRows = 16384;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -161,106 +168,84 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
 
 // One output tile Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2 over the
 // digit pairs i + j < S: proposals q0 .. q0 + kSplitQ - 1, columns c0 ..
-// c0 + kSplitC - 1; called by every thread of the workgroup, which leaves the
-// LDS free (after a barrier) on return.
+// c0 + kSplitC - 1.  Proposals past nb read the last proposal's digits and
+// are not stored.  Uses no LDS.
 template <int S>
 __device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t nb, int rows,
                                            const v4i *__restrict__ BS, const double *__restrict__ cscale,
                                            const double *__restrict__ rscale, int Kp, double *__restrict__ Y,
                                            int64_t q0, int c0) {
-  constexpr int kPerA = S * 2 * kSplitQ, kPerB = S * 2 * kSplitC;   // v4i entries per stage
-  constexpr int kLoadsA = (kPerA + kSplitThreads - 1) / kSplitThreads;
-  constexpr int kLoadsB = (kPerB + kSplitThreads - 1) / kSplitThreads;
-  __shared__ v4i As[2][S][2][kSplitQ];
-  __shared__ v4i Bs[2][S][2][kSplitC];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wq = wave % kSplitWQ, wc = wave / kSplitWQ;
-  const int G = rows / 16;
-
-  // stage entry e of an operand with W-wide tiles: digit e / (2 W), 16-row
-  // group g0 + (e / W) % 2, tile position e % W
-  v4i ra[kLoadsA], rb[kLoadsB];
-  auto fetch = [&](int g0) {
-#pragma unroll
-    for (int k = 0; k < kLoadsA; ++k) {
-      const int e = tid + k * kSplitThreads;
-      if (e < kPerA) {
-        const int i = e / (2 * kSplitQ), kh = (e / kSplitQ) & 1, m = e % kSplitQ;
-        const int64_t q = q0 + m;
-        ra[k] = q < nb ? AS[((int64_t)i * G + g0 + kh) * nb + q] : v4i{0, 0, 0, 0};
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kLoadsB; ++k) {
-      const int e = tid + k * kSplitThreads;
-      if (e < kPerB) {
-        const int i = e / (2 * kSplitC), kh = (e / kSplitC) & 1, m = e % kSplitC;
-        rb[k] = BS[((int64_t)i * G + g0 + kh) * Kp + c0 + m];
-      }
-    }
-  };
-  auto stash = [&](int buf) {
-    // keeps the compiler from hoisting these LDS writes (and the wait for
-    // their global loads) above the current step's MFMAs
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int k = 0; k < kLoadsA; ++k) {
-      const int e = tid + k * kSplitThreads;
-      if (e < kPerA) As[buf][e / (2 * kSplitQ)][(e / kSplitQ) & 1][e % kSplitQ] = ra[k];
-    }
-#pragma unroll
-    for (int k = 0; k < kLoadsB; ++k) {
-      const int e = tid + k * kSplitThreads;
-      if (e < kPerB) Bs[buf][e / (2 * kSplitC)][(e / kSplitC) & 1][e % kSplitC] = rb[k];
-    }
-  };
-
-  v16i acc[S];
-#pragma unroll
-  for (int l = 0; l < S; ++l)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[l][r] = 0;
-
-  const int n_steps = rows / 32;
-  fetch(0);
-  stash(0);
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
+  const int G = rows / 16, n_steps = rows / 32;
   const int kh = lane >> 5, ml = lane & 31;
-  for (int st = 0; st < n_steps; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < n_steps) fetch(2 * (st + 1));
-    v4i b[S];
+  int64_t qa = q0 + wq * 32 + ml;
+  qa = qa < nb ? qa : nb - 1;
+  // per-lane byte offsets within a (digit, 16-row group) plane, added to
+  // wave-uniform plane addresses
+  const uint32_t oa = (uint32_t)(((int64_t)kh * nb + qa) * 16);
+  const uint32_t ob = (uint32_t)(((int64_t)kh * Kp + c0 + ml) * 16);
+  const char *ca = reinterpret_cast<const char *>(AS), *cb = reinterpret_cast<const char *>(BS);
+
+  v16i acc[2][S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) b[j] = Bs[cur][j][kh][wc * 32 + ml];
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[n][l][r] = 0;
+  // operands of one 32-row step: digit i of the wave's 32 proposals, digit j
+  // of its two 32-column blocks; two register sets, the next step's in flight
+  v4i a0[S], b0[2][S], a1[S], b1[2][S];
+  auto load = [&](int st, v4i *a, v4i (*b)[S]) {
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      const v4i a = As[cur][i][kh][wq * 32 + ml];
+      const char *pa = ca + ((int64_t)i * G + 2 * st) * nb * 16;
+      const char *pb = cb + ((int64_t)i * G + 2 * st) * Kp * 16;
+      a[i] = *reinterpret_cast<const v4i *>(pa + oa);
 #pragma unroll
-      for (int j = 0; i + j < S; ++j) acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[j], acc[i + j], 0, 0, 0);
+      for (int n = 0; n < 2; ++n) b[n][i] = *reinterpret_cast<const v4i *>(pb + ob + 512 * n);
     }
-    if (st + 1 < n_steps) stash(cur ^ 1);
-    __syncthreads();
+  };
+  auto multiply = [&](const v4i *a, v4i (*b)[S]) {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; i + j < S; ++j)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          acc[n][i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[n][j], acc[n][i + j], 0, 0, 0);
+  };
+  load(0, a0, b0);
+  int st = 0;
+  for (; st + 1 < n_steps; st += 2) {
+    load(st + 1, a1, b1);
+    multiply(a0, b0);
+    if (st + 2 < n_steps) load(st + 2, a0, b0);
+    multiply(a1, b1);
   }
+  if (st < n_steps) multiply(a0, b0);     // an odd step count leaves the last step in set 0
 
-  const int col = c0 + wc * 32 + ml;
-  const double sc = cscale[col] * (1.0 / 16129.0);
   constexpr double kInv254 = 1.0 / 254.0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t q = q0 + wq * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-    if (q >= nb) continue;
-    double y = (double)acc[S - 1][r];
+  for (int n = 0; n < 2; ++n) {
+    const int col = c0 + 32 * n + ml;
+    const double sc = cscale[col] * (1.0 / 16129.0);
 #pragma unroll
-    for (int l = S - 2; l >= 0; --l) y = fma(y, kInv254, (double)acc[l][r]);
-    Y[q * Kp + col] = y * sc * rscale[q];
+    for (int r = 0; r < 16; ++r) {
+      const int64_t q = q0 + wq * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+      if (q >= nb) continue;
+      double y = (double)acc[n][S - 1][r];
+#pragma unroll
+      for (int l = S - 2; l >= 0; --l) y = fma(y, kInv254, (double)acc[n][l][r]);
+      Y[q * Kp + col] = y * sc * rscale[q];
+    }
   }
 }
 
 // One-dimensional grid over (proposal tile, column tile), the column tile
 // fastest.
 template <int S>
-__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
+__global__ void __launch_bounds__(kSplitThreads, 1)
     k_split_contract(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
                      const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
                      double *__restrict__ Y) {
@@ -321,7 +306,7 @@ __global__ void __launch_bounds__(256) k_ragged_split_rows(const EventDesc *__re
 // each workgroup takes the next item from an atomic counter until the list
 // is exhausted (every workgroup reaches that exit).
 template <int S>
-__global__ void __launch_bounds__(kSplitThreads, 4 / kSplitWQ)
+__global__ void __launch_bounds__(kSplitThreads, 1)
     k_ragged_split_contract(const EventDesc *__restrict__ ev, int n_ev, int64_t total_items,
                             unsigned long long *__restrict__ counter) {
   __shared__ long long item_s;
@@ -364,7 +349,7 @@ void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *par
 
 int split_ragged_tile_q() { return kSplitQ; }
 int split_ragged_tile_c() { return kSplitC; }
-int split_ragged_blocks_per_cu() { return 4 / kSplitWQ; }
+int split_ragged_blocks_per_cu() { return 1; }
 
 void launch_ragged_split_rows(const EventDesc *ev, int n_ev, int64_t total_threads, const double *params, int64_t ld,
                               hipStream_t s) {
