@@ -9,9 +9,11 @@
 // digits of a value do not depend on S: the weights are cut once into
 // kMaxSlices digits and an S-digit variant reads the first S.
 //
-// Scales.  Each proposal's kernel row is divided by a power of two s_q above
-// max_r |B_r(x_q)| (Gaussian rows are at most 1; the M monomials are
-// evaluated), each weight column by a power of two s_c above max_r |W_rc|.
+// Scales.  Each proposal's kernel row is divided by a power of two s_q at
+// or above max_r |B_r(x_q)| (Gaussian rows are at most 1, monomials of degree
+// <= 3 at most max(1, max_d |x_d|)^3), each weight column by a power of two
+// s_c above max_r |W_rc|.  Inside the unit ball s_q = 1, so the first digit
+// spans the whole of [-127, 127].
 //
 // Products.  sum_r B_r W_rc = s_q s_c sum_l 254^-l D_l / 127^2 with
 // D_l = sum_{i+j=l} sum_r a_i(r) b_j(r).  Every D_l with l < S is an exact
@@ -58,18 +60,32 @@ constexpr int kMaxSplitRows = 16384;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-// Base-254 digits of v (|v| <= 1), packed one per byte.
+// Base-254 digits of v (|v| <= 1), packed one per byte.  No clamp is
+// needed: |127 v| <= 127, and every remainder r has |r| <= 1/2 up to the
+// FMA's rounding, so |254 r| rounds to at most 127.
 template <int S>
 __device__ __forceinline__ void digits(double v, int8_t out[S]) {
-  double a = fmin(127.0, fmax(-127.0, rint(v * 127.0)));
+  double a = rint(v * 127.0);
   out[0] = (int8_t)a;
   double r = fma(v, 127.0, -a);
 #pragma unroll
   for (int i = 1; i < S; ++i) {
-    a = fmin(127.0, fmax(-127.0, rint(r * 254.0)));
+    a = rint(r * 254.0);
     out[i] = (int8_t)a;
     r = fma(r, 254.0, -a);
   }
+}
+
+// The power-of-two row scale s_q >= max_r |B_r(x)| (see Scales above).  The
+// bound m^3 is rounded as a monomial's own product is, so it also holds in
+// floating point; a NaN coordinate leaves s_q = 1 (the epilogue flags it).
+__device__ __forceinline__ double row_scale(const double x[4]) {
+  double m = 1.0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) m = fmax(m, fabs(x[d]));
+  int e = 0;
+  const double f = frexp(m * m * m, &e);    // m^3 = f 2^e, f in [1/2, 1)
+  return ldexp(1.0, f == 0.5 ? e - 1 : e);
 }
 
 __device__ __forceinline__ v4i pack16(const int8_t *b) {
@@ -98,12 +114,8 @@ __global__ void __launch_bounds__(256) k_split_rows(const EvalConsts *__restrict
 #pragma unroll
   for (int d = 0; d < 4; ++d) x[d] = params[d * ld + b0 + q] / c.semi[d];
   const int N = c.N, NM = c.N + c.M;
-  double bound = 1.0;
-  for (int p = 0; p < c.M; ++p) bound = fmax(bound, fabs(basis_row_fp64(N + p, N, NM, x, nodes, c.eps2, c.poly_idx)));
-  int e = 0;
-  frexp(bound, &e);
-  const double inv = ldexp(1.0, -e);
-  if (g == 0) rscale[q] = ldexp(1.0, e);
+  const double sq = row_scale(x), inv = 1.0 / sq;    // powers of two: exact
+  if (g == 0) rscale[q] = sq;
   int8_t dg[S][16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -278,12 +290,8 @@ __global__ void __launch_bounds__(256) k_ragged_split_rows(const EventDesc *__re
 #pragma unroll
   for (int dd = 0; dd < 4; ++dd) x[dd] = params[dd * ld + d.q0 + q] / c.semi[dd];
   const int N = c.N, NM = c.N + c.M;
-  double bound = 1.0;
-  for (int p = 0; p < c.M; ++p) bound = fmax(bound, fabs(basis_row_fp64(N + p, N, NM, x, d.nodes, c.eps2, c.poly_idx)));
-  int e = 0;
-  frexp(bound, &e);
-  const double inv = ldexp(1.0, -e);
-  if (g == 0) d.rscale[q] = ldexp(1.0, e);
+  const double sq = row_scale(x), inv = 1.0 / sq;    // powers of two: exact
+  if (g == 0) d.rscale[q] = sq;
   int8_t dg[kMaxSlices][16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
