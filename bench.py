@@ -170,6 +170,9 @@ def main():
         if form == rbfl.FORM_FP64:
             tune["fp64_pipeline"] = h.pipeline()
             log(f"autotune fp64 pipeline: {tune['fp64_pipeline']}")
+        if form == rbfl.FORM_SPLIT:
+            tune["split_order"] = h.split_order()
+            log(f"autotune split order: {tune['split_order']}")
 
     def run_form(form, steps, warmup):
         for _ in range(warmup):
@@ -234,9 +237,13 @@ def main():
             S = tune["split"]["slices"]
             pairs = S * (S + 1) // 2
             tops = pairs * flop_per_query * per_launch_n / (c2 * 1e-3)
+            fused = tune["split_order"]["fused_epilogue"]
             forms[name].update({"slices": S, "int8_tops": tops / 1e12, "int8_frac": tops / PEAK_INT8,
+                                "order": tune["split_order"],
                                 "roofline": roof(tops, PEAK_INT8, unit="TOP/s",
-                                                 kernel="k_split_contract (int8 products issued)")})
+                                                 kernel="k_split_lnl (ln L inside the contraction; int8 products "
+                                                        "issued)" if fused else
+                                                 "k_split_contract (int8 products issued)")})
         outs[name] = lf
         log(f"{name}: {v2:.4e} evals/s, contraction {c2:.3f} ms/launch")
 
@@ -755,9 +762,12 @@ def bench_mixed(args, np, torch, rbfl, wl, cfg):
             S = tune["slices"]
             f["slices"] = S
             f["split_state"] = h.split_state()
+            f["order"] = h.split_order()
             f["max_dlnl_vs_fp64_per_slice_count"] = tune["max_dlnl_vs_fp64"][:4]
+            fused = f["order"]["fused_epilogue"]
             f["roofline"] = roof(S * (S + 1) / 2 * flop * per / (c_ms * 1e-3), PEAK_INT8, unit="TOP/s",
-                                 kernel="k_split_contract (int8 products issued)")
+                                 kernel="k_split_lnl (ln L inside the contraction; int8 products issued)" if fused
+                                 else "k_split_contract (int8 products issued)")
         elif form == rbfl.FORM_FP32:
             f["roofline"] = roof(flop * per / (c_ms * 1e-3), PEAK_FP32, kernel="k_contract_fp32")
         else:

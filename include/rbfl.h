@@ -338,10 +338,13 @@ enum rbfl_query_what {
   RBFL_Q_NAN_COUNT = 22,    /* int64[1]: NaN ln L values written by the last rbfl_eval call on this
                                handle (a proposal with a NaN parameter gives NaN; any other NaN result
                                is counted too).  Synchronises the device. */
-  RBFL_Q_BANDS = 25         /* double[2 + (B + 1) + B n_modes]: B = n_bands (1 when frozen), n_blocks,
+  RBFL_Q_BANDS = 25,        /* double[2 + (B + 1) + B n_modes]: B = n_bands (1 when frozen), n_blocks,
                                the band edges as bin indices [B + 1] (band b holds bins edges[b] ..
                                edges[b+1] - 1), then the band times t_bm relative to t_c [B][n_modes]
                                (rbfl_build_spec.n_bands) */
+  RBFL_Q_SPLIT_ORDER = 26   /* double[3]: 1/0 the split form finishes ln L inside its contraction
+                               (rbfl_fuse_epilogue bit 1), then the split autotune's ms per evaluation
+                               with the separate epilogue and in that order (0 = not timed) */
 };
 int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
 
@@ -353,7 +356,10 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
  * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible the
  * most accurate variant is kept and RBFL_Q_SPLIT_STATE says that the bar was
- * missed; without autotuning the split form uses S = 7.  For RBFL_FORM_FP64 it then
+ * missed; without autotuning the split form uses S = 7.  With the chosen S it
+ * then times whole split evaluations with the separate epilogue and with ln L
+ * inside the contraction (frozen patterns, more than 4096 proposals) and
+ * keeps the latter if at least 1% faster (RBFL_Q_SPLIT_ORDER).  For RBFL_FORM_FP64 it then
  * times whole evaluations of those proposals in each evaluation order (serial,
  * rbfl_pipeline with 2, 4 and 8 chunks, rbfl_fuse_epilogue) and keeps a
  * pipelined order only if it is at least 3% faster than the serial one, ln L
@@ -388,21 +394,24 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant);
  * RBFL_E_INVALID_ARG for chunks outside 1..64. */
 int32_t rbfl_pipeline(rbfl_handle h, int32_t chunks);
 
-/* ln L finished inside the FP64 contraction (Sec. II D's online stage, same
+/* ln L finished inside the FP64 or split contraction (Sec. II D's online stage, same
  * terms regrouped): ln L of Eq. logl_complete (corrected reading) is linear in
  * the interpolated outputs, ln L = sum_c coef_c Y[c], with coef_c formed from
  * the proposal's distance ratio, amplitudes and spline-folded basis value.
- * With `on` nonzero, rbfl_eval of the FP64 form writes each proposal's setup,
- * contracts with a kernel that weights its output tile by coef_c and writes
- * one partial sum per proposal and 128-column tile instead of the outputs,
- * and adds the tiles' partials (compensated, in tile order).  Its work space,
- * 384 bytes + 8 Kp / 128 bytes per proposal of capacity (rbfl_reserve), is
- * allocated by the first evaluation in this order.  ln L agrees with the
- * default order to rounding (the summation order differs); domain flags are
- * the same.  Takes precedence over rbfl_pipeline; allowed under graph capture
- * once that work space exists (else RBFL_E_STATE).  rbfl_autotune of
- * RBFL_FORM_FP64 times it and keeps it if 1% faster than the best other
- * order (RBFL_Q_PIPELINE).  Needs exclusive use of the handle. */
+ * `on` is a bit mask: bit 0 for the FP64 form, bit 1 for the split form
+ * (0..3; each call sets both).  In that order rbfl_eval writes each
+ * proposal's setup, contracts with a kernel that weights its output tile by
+ * coef_c and writes one partial sum per proposal and column tile (128 columns
+ * for FP64, 64 for the split form) instead of the outputs, and adds the
+ * tiles' partials (compensated, in tile order).  Its work space, 384 bytes +
+ * 8 Kp / 64 bytes per proposal of capacity (rbfl_reserve), is allocated by
+ * the first evaluation in either order.  ln L agrees with the default order
+ * to rounding (the summation order differs); domain flags are the same.
+ * Takes precedence over rbfl_pipeline; allowed under graph capture once that
+ * work space exists (else RBFL_E_STATE).  rbfl_autotune times each form's
+ * order and keeps it if 1% faster than the best other order
+ * (RBFL_Q_PIPELINE, RBFL_Q_SPLIT_ORDER).  RBFL_E_INVALID_ARG for `on` outside
+ * 0..3, or nonzero on a banded handle.  Needs exclusive use of the handle. */
 int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on);
 
 /* Switches per-launch timing of the online kernels on (1) or off (0): with it

@@ -278,20 +278,13 @@ __device__ __forceinline__ void gemm_accumulate(const double *__restrict__ Bt, i
 }
 
 // The FP64 contraction that finishes ln L itself.  ln L is linear in the
-// interpolated outputs, ln L = sum_c coef_c Y[c] with, for a proposal's
-// setup (r = d_ref / d_L, amplitudes A_{k,a}, spline position n0 + f at
-// detector k):
-//   Re C_{k,a,i}:   r Re(conj(A_{k,a}) b_i),  b_i = sum_p f^p B4[n0][i][p]
-//   Im C_{k,a,i}:   r Im(conj(A_{k,a}) b_i) reversed in sign, i.e.
-//                   r (Ai br - Ar bi)
-//   sigma_{k,aa}:   -r^2 |A_{k,a}|^2 / 2
-//   Re sigma_{k,ab}: -r^2 Re(conj(A_a) A_b),  Im sigma_{k,ab}: r^2 Im(conj(A_a) A_b)
-// (the terms of Eq. logl_complete, corrected reading, as the epilogue kernel
-// sums them).  After the same accumulation as k_gemm_fp64's 128 x 128 tile
-// of 8 waves, each lane weights its 32 outputs, the 16 lanes of a row group
-// and the two column waves add theirs (a fixed tree), and the tile writes one
-// partial sum per proposal to part[column tile][proposal]; Y is never
-// written.  Proposals outside the domain contribute nothing here.
+// interpolated outputs, ln L = sum_c w_c Y[c], with the weights w_c of
+// lnl_weight (the terms of Eq. logl_complete, corrected reading, as the
+// epilogue kernel sums them).  After the same accumulation as k_gemm_fp64's
+// 128 x 128 tile of 8 waves, each lane weights its 32 outputs, the 16 lanes
+// of a row group and the two column waves add theirs (a fixed tree), and the
+// tile writes one partial sum per proposal to part[column tile][proposal];
+// Y is never written.  Proposals outside the domain contribute nothing here.
 constexpr int kLnlRT = 2, kLnlCT = 4, kLnlKC = 8, kLnlWQ = 4, kLnlWC = 2;
 
 __global__ void __launch_bounds__(64 * kLnlWQ * kLnlWC, 1)
@@ -328,28 +321,11 @@ __global__ void __launch_bounds__(64 * kLnlWQ * kLnlWC, 1)
       double sum = 0.0;
       if (b < nb && setups[b].status == 0) {
         const EpiSetup &o = setups[b];
-        const double rr = o.rr;
 #pragma unroll
         for (int u = 0; u < CT; ++u) {
           const int4 d = dsc[u];
           if (d.x < 0) continue;
-          const int k = d.y, a = d.z;
-          const double ara = o.Ar[k][a], aia = o.Ai[k][a];
-          double cf;
-          if (d.x <= 1) {
-            const double f = o.f[k];
-            const double2 *v = basis4 + (((int64_t)(k * n_modes + a) * T + o.n0[k]) * q + d.w) * 4;
-            const double2 v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
-            const double br = fma(fma(fma(v3.x, f, v2.x), f, v1.x), f, v0.x);
-            const double bi = fma(fma(fma(v3.y, f, v2.y), f, v1.y), f, v0.y);
-            cf = d.x == 0 ? rr * (ara * br + aia * bi) : rr * (aia * br - ara * bi);
-          } else {
-            const double arb = o.Ar[k][d.w], aib = o.Ai[k][d.w];
-            if (d.x == 2 && a == d.w) cf = -0.5 * rr * rr * (ara * ara + aia * aia);
-            else if (d.x == 2) cf = -rr * rr * (ara * arb + aia * aib);
-            else cf = rr * rr * (ara * aib - aia * arb);
-          }
-          sum = fma(cf, acc[t][u][i], sum);
+          sum = fma(lnl_weight(d, o, n_modes, T, q, basis4), acc[t][u][i], sum);
         }
       }
 #pragma unroll

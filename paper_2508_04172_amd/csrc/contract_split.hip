@@ -45,6 +45,7 @@
 //   weights BS[j][g][c][16]  (c < Kp)
 // so a workgroup's stage is one contiguous 1 KiB run per (digit, group).
 #include "basis_rows.h"
+#include "epilogue_setup.h"
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -178,15 +179,15 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
-// One output tile Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2 over the
-// digit pairs i + j < S: proposals q0 .. q0 + kSplitQ - 1, columns c0 ..
-// c0 + kSplitC - 1.  Proposals past nb read the last proposal's digits and
-// are not stored.  Uses no LDS.
+// The level sums D_l of one tile, proposals q0 .. q0 + kSplitQ - 1 and
+// columns c0 .. c0 + kSplitC - 1, over the digit pairs i + j < S: wave w
+// holds acc[n][l] for proposals q0 + 32 w .. + 31 and columns c0 + 32 n ..
+// + 31 (the 32 x 32 accumulator layout above).  Proposals past nb read the
+// last proposal's digits.  Uses no LDS.
 template <int S>
-__device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t nb, int rows,
-                                           const v4i *__restrict__ BS, const double *__restrict__ cscale,
-                                           const double *__restrict__ rscale, int Kp, double *__restrict__ Y,
-                                           int64_t q0, int c0) {
+__device__ __forceinline__ void split_accumulate(const v4i *__restrict__ AS, int64_t nb, int rows,
+                                                 const v4i *__restrict__ BS, int Kp, int64_t q0, int c0,
+                                                 v16i (&acc)[2][S]) {
   const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
   const int G = rows / 16, n_steps = rows / 32;
   const int kh = lane >> 5, ml = lane & 31;
@@ -198,7 +199,6 @@ __device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t n
   const uint32_t ob = (uint32_t)(((int64_t)kh * Kp + c0 + ml) * 16);
   const char *ca = reinterpret_cast<const char *>(AS), *cb = reinterpret_cast<const char *>(BS);
 
-  v16i acc[2][S];
 #pragma unroll
   for (int n = 0; n < 2; ++n)
 #pragma unroll
@@ -236,8 +236,30 @@ __device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t n
     multiply(a1, b1);
   }
   if (st < n_steps) multiply(a0, b0);     // an odd step count leaves the last step in set 0
+}
 
+// Output r of block n of a lane: sum_l 254^-l D_l (Horner from the highest
+// level) scaled by s_c / 127^2 (sc) and s_q (rs).
+template <int S>
+__device__ __forceinline__ double split_value(const v16i (&acc)[2][S], int n, int r, double sc, double rs) {
   constexpr double kInv254 = 1.0 / 254.0;
+  double y = (double)acc[n][S - 1][r];
+#pragma unroll
+  for (int l = S - 2; l >= 0; --l) y = fma(y, kInv254, (double)acc[n][l][r]);
+  return y * sc * rs;
+}
+
+// One output tile Y[q][c] = s_q s_c sum_l 254^-l D_l[q][c] / 127^2: the tile
+// of split_accumulate, stored for proposals below nb.
+template <int S>
+__device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t nb, int rows,
+                                           const v4i *__restrict__ BS, const double *__restrict__ cscale,
+                                           const double *__restrict__ rscale, int Kp, double *__restrict__ Y,
+                                           int64_t q0, int c0) {
+  v16i acc[2][S];
+  split_accumulate<S>(AS, nb, rows, BS, Kp, q0, c0, acc);
+  const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
+  const int kh = lane >> 5, ml = lane & 31;
 #pragma unroll
   for (int n = 0; n < 2; ++n) {
     const int col = c0 + 32 * n + ml;
@@ -246,10 +268,7 @@ __device__ __forceinline__ void split_tile(const v4i *__restrict__ AS, int64_t n
     for (int r = 0; r < 16; ++r) {
       const int64_t q = q0 + wq * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
       if (q >= nb) continue;
-      double y = (double)acc[n][S - 1][r];
-#pragma unroll
-      for (int l = S - 2; l >= 0; --l) y = fma(y, kInv254, (double)acc[n][l][r]);
-      Y[q * Kp + col] = y * sc * rscale[q];
+      Y[q * Kp + col] = split_value<S>(acc, n, r, sc, rscale[q]);
     }
   }
 }
@@ -264,6 +283,56 @@ __global__ void __launch_bounds__(kSplitThreads, 1)
   const int n_ct = Kp / kSplitC;
   const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
   split_tile<S>(AS, nb, rows, BS, cscale, rscale, Kp, Y, (tile / n_ct) * kSplitQ, (int)(tile % n_ct) * kSplitC);
+}
+
+// The split contraction that finishes ln L itself (frozen antenna
+// patterns): the tile of split_accumulate, then each lane weights its 2 x 16
+// outputs (the values split_tile would store) by their columns' ln L weights
+// (lnl_weight), the 32 lanes of a row set add theirs (a fixed tree) and each
+// wave writes one partial sum for each of its 32 proposals to
+// part[column tile][proposal]; Y is never written.  Proposals outside the
+// domain contribute 0 here (k_lnl_tiles writes their flag).
+template <int S>
+__global__ void __launch_bounds__(kSplitThreads, 1)
+    k_split_lnl(const v4i *__restrict__ AS, int64_t nb, int rows, const v4i *__restrict__ BS,
+                const double *__restrict__ cscale, const double *__restrict__ rscale, int Kp,
+                const EvalConsts *__restrict__ cp, const EpiSetup *__restrict__ setups,
+                const double2 *__restrict__ basis4, const int4 *__restrict__ coldesc, double *__restrict__ part,
+                int64_t ldp) {
+  const int n_ct = Kp / kSplitC;
+  const int64_t tile = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int64_t q0 = (tile / n_ct) * kSplitQ;
+  const int tc = (int)(tile % n_ct), c0 = tc * kSplitC;
+  v16i acc[2][S];
+  split_accumulate<S>(AS, nb, rows, BS, Kp, q0, c0, acc);
+  const EvalConsts &c = *cp;
+  const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
+  const int kh = lane >> 5, ml = lane & 31;
+  int4 dsc[2];
+  double sc[2];
+#pragma unroll
+  for (int n = 0; n < 2; ++n) {
+    const int col = c0 + 32 * n + ml;
+    dsc[n] = col < c.K ? coldesc[col] : make_int4(-1, 0, 0, 0);
+    sc[n] = cscale[col] * (1.0 / 16129.0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t q = q0 + wq * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+    double sum = 0.0;
+    if (q < nb && setups[q].status == 0) {
+      const EpiSetup &o = setups[q];
+      const double rs = rscale[q];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        if (dsc[n].x < 0) continue;
+        sum = fma(lnl_weight(dsc[n], o, c.n_modes, c.T, c.q, basis4), split_value<S>(acc, n, r, sc[n], rs), sum);
+      }
+    }
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) sum += __shfl_xor(sum, m, 64);
+    if (ml == 0 && q < nb) part[(int64_t)tc * ldp + q] = sum;
+  }
 }
 
 // Multi-event batches: the first S digits (S = the event's) of the kernel
@@ -353,6 +422,23 @@ void launch_variant(const EvalConsts *c, const EvalConsts &hc, const double *par
   RBFL_HIP(hipGetLastError());
 }
 
+template <int S>
+void launch_lnl_variant(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                        int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                        const double *cscale, const void *setups, const double2 *basis4, const int4 *coldesc,
+                        double *part, int64_t ldp, hipStream_t s, hipEvent_t mid) {
+  const int64_t G = hc.rows / 16;
+  hipLaunchKernelGGL((k_split_rows<S>), dim3((unsigned)((G * nb + 255) / 256)), dim3(256), 0, s, c, params, ld, b0,
+                     nb, nodes, reinterpret_cast<v4i *>(AS), rscale);
+  RBFL_HIP(hipGetLastError());
+  if (mid) RBFL_HIP(hipEventRecord(mid, s));
+  const int64_t nblk = (nb + kSplitQ - 1) / kSplitQ * (hc.Kp / kSplitC);
+  hipLaunchKernelGGL((k_split_lnl<S>), dim3((unsigned)nblk), dim3(kSplitThreads), 0, s,
+                     reinterpret_cast<const v4i *>(AS), nb, hc.rows, reinterpret_cast<const v4i *>(BS), cscale,
+                     rscale, hc.Kp, c, static_cast<const EpiSetup *>(setups), basis4, coldesc, part, ldp);
+  RBFL_HIP(hipGetLastError());
+}
+
 }  // namespace
 
 int split_ragged_tile_q() { return kSplitQ; }
@@ -402,6 +488,23 @@ void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8
   hipLaunchKernelGGL(k_split_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, rows, Kp, scale,
                      reinterpret_cast<v4i *>(BS));
   RBFL_HIP(hipGetLastError());
+}
+
+int split_col_tile() { return kSplitC; }
+
+void launch_split_lnl(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                      int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                      const double *cscale, const void *setups, const double2 *basis4, const int4 *coldesc,
+                      double *part, int64_t ldp, hipStream_t s, int variant, hipEvent_t mid) {
+  if (hc.rows > kMaxSplitRows || hc.rows % 32 != 0 || hc.Kp % kSplitC != 0)
+    throw Error(RBFL_E_UNSUPPORTED, "split form: rows must be a multiple of 32 and at most 16384");
+  switch (variant) {
+    case 0: launch_lnl_variant<5>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, setups, basis4, coldesc, part, ldp, s, mid); break;
+    case 1: launch_lnl_variant<6>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, setups, basis4, coldesc, part, ldp, s, mid); break;
+    case 2: launch_lnl_variant<7>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, setups, basis4, coldesc, part, ldp, s, mid); break;
+    case 3: launch_lnl_variant<8>(c, hc, params, ld, b0, nb, nodes, AS, rscale, BS, cscale, setups, basis4, coldesc, part, ldp, s, mid); break;
+    default: throw Error(RBFL_E_INVALID_ARG, "unknown split-form variant");
+  }
 }
 
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,

@@ -1,8 +1,8 @@
 // Per-proposal setup of the online stage's epilogue (Sec. II D): domain
 // flags, each detector's arrival-time position in the window and each
 // (detector, mode) amplitude of Eq. logl_complete (corrected reading).
-// Shared by the epilogue kernels and the contraction kernel that finishes
-// ln L in its own epilogue.
+// Shared by the epilogue kernels and the contraction kernels that finish
+// ln L in their own epilogues.
 #pragma once
 
 #include "rbfl_internal.h"
@@ -84,6 +84,34 @@ __device__ __forceinline__ void epi_setup(const EvalConsts &c, const double *__r
     }
   }
   o.status = valid ? 0 : 1;
+}
+
+// Weight of one interpolated output in ln L = sum_c w_c Y[c] (Eq.
+// logl_complete, corrected reading, frozen antenna patterns) for a proposal
+// with setup o, r = d_ref / d_L, amplitudes A_{k,a} and spline position
+// n0 + f at detector k.  d is the output's column descriptor: d.x = 0 / 1 for
+// Re / Im of SVD coefficient d.w of mode d.z at detector d.y,
+//   w = r Re(conj(A) b) / r (Ai br - Ar bi),  b = sum_p f^p B4[n0][d.w][p];
+// d.x = 2 / 3 for Re / Im of the overlap of modes d.z, d.w,
+//   w = -r^2 |A_a|^2 / 2 on the diagonal, else -r^2 Re(conj(A_a) A_b) /
+//   r^2 Im(conj(A_a) A_b).
+__device__ __forceinline__ double lnl_weight(const int4 d, const EpiSetup &o, int n_modes, int T, int q,
+                                             const double2 *__restrict__ basis4) {
+  const int k = d.y, a = d.z;
+  const double rr = o.rr;
+  const double ara = o.Ar[k][a], aia = o.Ai[k][a];
+  if (d.x <= 1) {
+    const double f = o.f[k];
+    const double2 *v = basis4 + (((int64_t)(k * n_modes + a) * T + o.n0[k]) * q + d.w) * 4;
+    const double2 v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+    const double br = fma(fma(fma(v3.x, f, v2.x), f, v1.x), f, v0.x);
+    const double bi = fma(fma(fma(v3.y, f, v2.y), f, v1.y), f, v0.y);
+    return d.x == 0 ? rr * (ara * br + aia * bi) : rr * (aia * br - ara * bi);
+  }
+  const double arb = o.Ar[k][d.w], aib = o.Ai[k][d.w];
+  if (d.x == 2 && a == d.w) return -0.5 * rr * rr * (ara * ara + aia * aia);
+  if (d.x == 2) return -rr * rr * (ara * arb + aia * aib);
+  return rr * rr * (ara * aib - aia * arb);
 }
 
 }  // namespace rbfl

@@ -1429,11 +1429,13 @@ static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hi
   RBFL_HIP(hipStreamSynchronize(s));
 }
 
-// Work space of the order that finishes ln L inside the contraction, for n
-// proposals; allocated on first use of that order (and grown with the rest).
+// Work space of the orders that finish ln L inside the contraction (FP64 or
+// split), for n proposals; allocated on first use of either (and grown with
+// the rest): one partial sum per proposal and column tile of the narrower of
+// the two tiles.
 static void reserve_lnl_gemm(Ctx &c, int64_t n) {
   c.epi_su.alloc(epi_setup_bytes() * (size_t)n);
-  c.epi_part.alloc((size_t)(c.Kp / gemm_lnl_col_tile()) * n);
+  c.epi_part.alloc((size_t)(c.Kp / std::min(gemm_lnl_col_tile(), split_col_tile())) * n);
 }
 
 void reserve(Ctx &c, int64_t n) {
@@ -1570,6 +1572,39 @@ static void eval_lnl_gemm(Ctx &c, const double *params, int64_t ld, int64_t n, d
   }
 }
 
+// The split form with ln L finished inside its contraction, chunk by chunk.
+static void eval_split_lnl(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, hipStream_t s) {
+  const int n_ct = c.Kp / split_col_tile();
+  if (!c.epi_su.p) {
+    if (capturing(s)) throw Error(RBFL_E_STATE, "work space of the fused epilogue not allocated (evaluate once before capture)");
+    reserve_lnl_gemm(c, c.cap);
+  }
+  for (int64_t b0 = 0; b0 < n; b0 += c.cap) {
+    const int64_t nb = std::min(c.cap, n - b0);
+    hipEvent_t ev[4];
+    if (c.profile)
+      for (auto &e : ev) {
+        RBFL_HIP(hipEventCreate(&e));
+        c.timed_events.push_back(e);
+      }
+    if (c.profile) RBFL_HIP(hipEventRecord(ev[0], s));
+    launch_epi_setup(c.consts.p, params, ld, b0, nb, c.epi_su.p, s);
+    launch_split_lnl(c.consts.p, c.host_consts, params, ld, b0, nb, c.nodes.p, c.AS.p, c.ASscale.p, c.WS.p,
+                     c.WSscale.p, c.epi_su.p, c.basis4.p, c.coldesc.p, c.epi_part.p, c.cap, s,
+                     c.variant[RBFL_FORM_SPLIT], c.profile ? ev[1] : nullptr);
+    if (c.profile) RBFL_HIP(hipEventRecord(ev[2], s));
+    launch_lnl_tiles(c.epi_su.p, b0, nb, c.epi_part.p, c.cap, n_ct, lnl, s);
+    if (c.profile) {
+      RBFL_HIP(hipEventRecord(ev[3], s));
+      // stages: setups + digit rows (kind 2), contraction with the weighting
+      // (kind 0), sum of the tile partials (kind 1)
+      c.timed.push_back(Ctx::Timed{ev[0], ev[1], 2, nb});
+      c.timed.push_back(Ctx::Timed{ev[1], ev[2], 0, nb});
+      c.timed.push_back(Ctx::Timed{ev[2], ev[3], 1, nb});
+    }
+  }
+}
+
 // ln L of proposals [0, n) of a parameter array with leading dimension ld.
 static void eval_range(Ctx &c, const double *params, int64_t ld, int64_t n, double *lnl, int form, hipStream_t s) {
   if (n == 0) return;
@@ -1577,6 +1612,10 @@ static void eval_range(Ctx &c, const double *params, int64_t ld, int64_t n, doub
   const bool fp64 = form == RBFL_FORM_FP64 || (form == RBFL_FORM_SURROGATE && !(c.sur && c.sur_ok));
   if (fp64 && c.lnl_gemm) {
     eval_lnl_gemm(c, params, ld, n, lnl, s);
+    return;
+  }
+  if (form == RBFL_FORM_SPLIT && c.split_lnl) {
+    eval_split_lnl(c, params, ld, n, lnl, s);
     return;
   }
   if (fp64 && c.pipe > 1 && c.cap / 2 >= 4096 && n > 4096 && !capturing(s)) {
@@ -1843,7 +1882,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     c.lnl_gemm = fm < 0.99 * pm[bd];
     if (c.lnl_gemm) {
       c.pipe = 1;
-    } else if (c.graph_users == 0) {
+    } else if (c.graph_users == 0 && !c.split_lnl) {
       // its work space is not kept for an order not chosen (unless a captured
       // sampler step may be using it)
       RBFL_HIP(hipStreamSynchronize(s));
@@ -1852,6 +1891,42 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
     }
     c.profile = prof;
     RBFL_HIP(hipStreamSynchronize(s));
+  }
+  // split form: with the chosen digit count, time whole evaluations with the
+  // separate epilogue and with ln L finished inside the contraction (frozen
+  // patterns only) and keep the latter if 1% faster
+  if (form == RBFL_FORM_SPLIT && c.n_bands == 1 && nb > 4096 && !capturing(s)) {
+    DevBuf<double> out;
+    out.alloc(nb);
+    const bool prof = c.profile;
+    c.profile = false;
+    double om[2] = {1e300, 1e300};
+    for (int round = 0; round < 2; ++round)
+      for (int o = 0; o < 2; ++o) {
+        c.split_lnl = o == 1;
+        if (round == 0) eval_range(c, params, n, nb, out.p, form, s);
+        double t[3];
+        for (int r = 0; r < 3; ++r) {
+          RBFL_HIP(hipEventRecord(e0, s));
+          eval_range(c, params, n, nb, out.p, form, s);
+          RBFL_HIP(hipEventRecord(e1, s));
+          RBFL_HIP(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          RBFL_HIP(hipEventElapsedTime(&ms, e0, e1));
+          t[r] = ms;
+        }
+        std::sort(t, t + 3);
+        om[o] = std::min(om[o], t[1]);
+      }
+    c.split_order_ms[0] = om[0];
+    c.split_order_ms[1] = om[1];
+    c.split_lnl = om[1] < 0.99 * om[0];
+    RBFL_HIP(hipStreamSynchronize(s));
+    if (!c.split_lnl && !c.lnl_gemm && c.graph_users == 0) {
+      c.epi_su.reset();
+      c.epi_part.reset();
+    }
+    c.profile = prof;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2220,6 +2295,11 @@ static void query(Ctx &c, int what, void *out, size_t bytes) {
       copy_out(out, bytes, v, sizeof(v));
       return;
     }
+    case RBFL_Q_SPLIT_ORDER: {
+      double v[3] = {c.split_lnl ? 1.0 : 0.0, c.split_order_ms[0], c.split_order_ms[1]};
+      copy_out(out, bytes, v, sizeof(v));
+      return;
+    }
     case RBFL_Q_NAN_COUNT: {
       require(out != nullptr && bytes >= sizeof(int64_t), "output buffer too small (need 8 bytes)");
       unsigned long long part[kNanParts];
@@ -2364,8 +2444,10 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant) {
 int32_t rbfl_fuse_epilogue(rbfl_handle h, int32_t on) {
   return rbfl::guarded([&] {
     rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(on >= 0 && on <= 3, "on must be 0..3 (bit 0 the FP64 form, bit 1 the split form)");
     rbfl::require(!(on && h->c.n_bands > 1), "the fused epilogue covers frozen antenna patterns only (n_bands = 1)");
-    h->c.lnl_gemm = on != 0;
+    h->c.lnl_gemm = (on & 1) != 0;
+    h->c.split_lnl = (on & 2) != 0;
   });
 }
 

@@ -220,9 +220,12 @@ struct Ctx {
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]
-  // ln L finished inside the FP64 contraction (rbfl_fuse_epilogue)
+  // ln L finished inside the FP64 contraction (rbfl_fuse_epilogue bit 0) and
+  // inside the split contraction (bit 1)
   bool lnl_gemm = false;
   double lnl_gemm_ms = 0.0;           // the autotuner's time per evaluation of that order
+  bool split_lnl = false;
+  double split_order_ms[2] = {};      // the split autotune's ms per evaluation: separate epilogue, fused
   DevBuf<unsigned char> epi_su;       // per-proposal setups [cap]
   DevBuf<double> epi_part;            // partial sums per column tile [Kp / tile][cap]
   int64_t cap = 0;
@@ -387,6 +390,15 @@ void launch_split_prepare(const double *W, int rows, int Kp, double *scale, int8
 void launch_contract_split(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
                            int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
                            const double *scale, double *Y, hipStream_t s, int variant, hipEvent_t mid);
+// The split form with ln L finished inside its contraction (frozen patterns):
+// digit rows, then one partial sum per proposal and split_col_tile()-column
+// tile into part[tile][ldp] from the setups of launch_epi_setup; mid, when
+// given, is recorded between the two.
+int split_col_tile();
+void launch_split_lnl(const EvalConsts *c, const EvalConsts &hc, const double *params, int64_t ld, int64_t b0,
+                      int64_t nb, const double *nodes, int8_t *AS, double *rscale, const int8_t *BS,
+                      const double *cscale, const void *setups, const double2 *basis4, const int4 *coldesc,
+                      double *part, int64_t ldp, hipStream_t s, int variant, hipEvent_t mid);
 // part[b] = number of NaN entries of lnl[0, n) in block b's grid-stride share
 // (kNanParts blocks; every slot is written, so no clearing is needed).
 void launch_count_nan(const double *lnl, int64_t n, unsigned long long *part, hipStream_t s);

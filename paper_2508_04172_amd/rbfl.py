@@ -29,7 +29,8 @@ FLAG_CENTER_NODE, FLAG_SQUEEZE, FLAG_OPTIMISE_CENTRE = 0x1, 0x2, 0x4
 
 Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALUES, Q_SINGULAR, Q_COND, \
     Q_TIMING, Q_Z_NODES, Q_KERNEL_STATS, Q_TUNE, Q_SURROGATE, Q_SPLIT_ERR, Q_F_REF, Q_SQUEEZE, Q_CENTRE, \
-    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT, Q_SURROGATE_BASE, Q_EPS, Q_BANDS = range(26)
+    Q_PIPELINE, Q_SURROGATE_NET, Q_SPLIT_STATE, Q_NAN_COUNT, Q_SURROGATE_BASE, Q_EPS, Q_BANDS, \
+    Q_SPLIT_ORDER = range(27)
 SPLIT_TOL = 1e-4
 STATIC_SCRATCH_BYTES = 128 << 20
 
@@ -332,6 +333,12 @@ class Handle:
         v = self._query(Q_SPLIT_STATE, 3)
         return {"tuned": bool(v[0]), "within_tol": bool(v[1]), "slices": int(v[2])}
 
+    def split_order(self) -> dict:
+        """Whether the split form finishes ln L inside its contraction, and the autotuner's ms per
+        evaluation with the separate epilogue and in that order (RBFL_Q_SPLIT_ORDER)."""
+        v = self._query(Q_SPLIT_ORDER, 3)
+        return {"fused_epilogue": bool(v[0]), "ms": float(v[1]), "fused_epilogue_ms": float(v[2])}
+
     def close(self):
         if self._h is not None and self._h.value:
             _check(load().rbfl_destroy(self._h))
@@ -523,9 +530,10 @@ class Handle:
         """Chunks per FP64 evaluation (1 = serial order); the autotuner sets it."""
         _check(load().rbfl_pipeline(self._h, chunks))
 
-    def fuse_epilogue(self, on: bool):
-        """ln L finished inside the FP64 contraction (rbfl_fuse_epilogue); the autotuner sets it."""
-        _check(load().rbfl_fuse_epilogue(self._h, 1 if on else 0))
+    def fuse_epilogue(self, on: bool, split: bool = False):
+        """ln L finished inside the FP64 contraction (`on`) and inside the split contraction
+        (`split`) (rbfl_fuse_epilogue; sets both); the autotuner sets them."""
+        _check(load().rbfl_fuse_epilogue(self._h, (1 if on else 0) | (2 if split else 0)))
 
     def pipeline(self) -> dict:
         """The FP64 evaluation order in use and the autotuner's ms per evaluation (RBFL_Q_PIPELINE):

@@ -46,11 +46,15 @@ def test_split_interpolant(name):
     basis = np.concatenate([su.gaussian_kernel(qd.x, art.x_nodes, art.eps), su.poly_matrix(qd.x, art.degree)], 1)
     amp = (np.abs(basis) @ np.abs(art.W)).max(axis=0) / col_scale
     # worst case of the split arithmetic with the kernels' power-of-two scales:
-    # 2^e strictly above the bound, e from frexp (a bound of 1 gives 2), the
-    # column scale 1 for an all-zero column
+    # a weight column's 2^e strictly above its largest |W| (e from frexp; 1 for
+    # an all-zero column), a proposal's the smallest power of two at or above
+    # max(1, max_d |x_d|)^3
     wmax = np.abs(art.W).max(axis=0)
     s_c = np.where(wmax > 0, np.ldexp(1.0, np.frexp(wmax)[1]), 1.0)
-    s_q = np.ldexp(1.0, np.frexp(np.maximum(1.0, np.abs(basis).max(axis=1)))[1])
+    cube = np.maximum(1.0, np.abs(qd.x).max(axis=1)) ** 3
+    mant, ex = np.frexp(cube)
+    s_q = np.ldexp(1.0, np.where(mant == 0.5, ex - 1, ex))
+    assert np.all(s_q >= np.abs(basis).max(axis=1))
     split_bound = (SLICES + 3) * 254.0 ** (-SLICES) * basis.shape[1] * s_q.max() * s_c / col_scale
     bar = np.maximum(1e-6, 1e-13 * amp) + split_bound
     err = np.abs(Ys - Yo).max(axis=0) / col_scale
@@ -109,6 +113,66 @@ def test_bf16_reported(name):
     q = np.quantile(d, [0.5, 0.9, 0.99, 1.0])
     print(f"[mixed] {name} bf16: |dlnL| median {q[0]:.3e}, 90% {q[1]:.3e}, 99% {q[2]:.3e}, max {q[3]:.3e}",
           flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_fused_epilogue(name):
+    """ln L finished inside the split contraction (rbfl_fuse_epilogue bit 1):
+    the tile's outputs are the values the default order stores, weighted in
+    place, so ln L agrees with the default split order to rounding (summation
+    order only), keeps its domain flags and stays within 1e-3 of the oracle."""
+    cfg, art, h = _prepared(name, rbfl.FORM_SPLIT)
+    n = min(cfg.n_queries, 3000)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=23)
+    qd = wl.queries(cfg, n=n, seed=23)
+    qg = qd.near_nodes(h.nodes(), idx, jit)
+    ref = gpu_eval(h, qg, cfg.t_trig, rbfl.FORM_SPLIT)
+    h.fuse_epilogue(False, split=True)
+    try:
+        assert h.split_order()["fused_epilogue"]
+        lg = gpu_eval(h, qg, cfg.t_trig, rbfl.FORM_SPLIT)
+        l64 = gpu_eval(h, qg, cfg.t_trig, rbfl.FORM_FP64)     # the FP64 form keeps its own order
+    finally:
+        h.fuse_epilogue(False)
+    assert not h.split_order()["fused_epilogue"]
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+    fin = np.isfinite(lo)
+    assert np.array_equal(np.isfinite(ref), np.isfinite(lg)) and np.array_equal(np.isnan(ref), np.isnan(lg))
+    assert np.array_equal(fin, np.isfinite(lg)) and np.array_equal(fin, np.isfinite(l64))
+    d = np.abs(lg[fin] - lo[fin])
+    dr = np.abs(lg[fin] - ref[fin]).max()
+    print(f"[mixed] {name} split fused epilogue: {fin.sum()} valid, max |dlnL| vs oracle {d.max():.3e}, "
+          f"vs the default order {dr:.3e}", flush=True)
+    assert d.max() <= 1e-3
+    assert dr <= 1e-9 * max(1.0, np.abs(ref[fin]).max())
+
+
+def test_split_order_autotuned():
+    """With more than 4096 tuning proposals (and a work space that holds
+    them) rbfl_autotune of the split form times both evaluation orders and
+    keeps the fused one only if 1% faster; the evaluation it leaves in place
+    matches the oracle."""
+    torch = pytest.importorskip("torch")
+    cfg, art, h = _prepared("small_multi", rbfl.FORM_SPLIT)
+    n = 8192
+    h.reserve(n)
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=31)
+    qd = wl.queries(cfg, n=n, seed=31)
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qd.near_nodes(h.nodes(), idx, jit),
+                                                              cfg.t_trig))).cuda()
+    h.autotune(p.data_ptr(), n, rbfl.FORM_SPLIT, torch.cuda.current_stream().cuda_stream)
+    o = h.split_order()
+    print(f"[mixed] split order: separate epilogue {o['ms']:.4f} ms, fused {o['fused_epilogue_ms']:.4f} ms, "
+          f"fused kept {o['fused_epilogue']}", flush=True)
+    assert o["ms"] > 0 and o["fused_epilogue_ms"] > 0
+    assert o["fused_epilogue"] == (o["fused_epilogue_ms"] < 0.99 * o["ms"])
+    sub = np.arange(0, n, 7)
+    lg = gpu_eval(h, qd.near_nodes(h.nodes(), idx, jit).subset(sub), cfg.t_trig, rbfl.FORM_SPLIT)
+    lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit).subset(sub)))
+    fin = np.isfinite(lo)
+    assert np.array_equal(fin, np.isfinite(lg))
+    assert np.abs(lg[fin] - lo[fin]).max() <= 1e-3
+    h.fuse_epilogue(False)
 
 
 def test_split_chunked_matches_single_pass():
