@@ -332,7 +332,7 @@ enum rbfl_query_what {
                                a base), m[4], s[4], then the base coefficients [nbase][K] row-major;
                                RBFL_E_STATE before rbfl_surrogate_train.  Synchronises the device. */
   RBFL_Q_SPLIT_STATE = 21,  /* double[3]: 1/0 the split form's digit count was chosen by rbfl_autotune,
-                               1/0 that choice is within RBFL_SPLIT_TOL of the FP64 form (when no digit
+                               1/0 that choice is within the handle's split tolerance of the FP64 form (when no digit
                                count is, the tuner keeps the most accurate one and reports 0 here:
                                such a split form does not meet the tuner's bar), digits S in use */
   RBFL_Q_NAN_COUNT = 22,    /* int64[1]: NaN ln L values written by the last rbfl_eval call on this
@@ -353,7 +353,8 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * events on `stream` and keeps the fastest for this handle (RBFL_Q_TUNE
  * reports the timings).  Split-form variants differ in digit count S (5..8,
  * variant v has S = 5 + v): only those whose ln L on these proposals stays
- * within RBFL_SPLIT_TOL of the FP64 form's (and keeps its domain flags) are
+ * within the handle's split tolerance (rbfl_set_split_tol, default
+ * RBFL_SPLIT_TOL) of the FP64 form's (and keeps its domain flags) are
  * eligible (RBFL_Q_SPLIT_ERR reports the differences); with none eligible the
  * most accurate variant is kept and RBFL_Q_SPLIT_STATE says that the bar was
  * missed; without autotuning the split form uses S = 7.  With the chosen S it
@@ -367,6 +368,16 @@ int32_t rbfl_query(rbfl_handle h, int32_t what, void *out, size_t bytes);
  * (RBFL_Q_PIPELINE reports the timings).  Synchronous; needs exclusive use of the handle. */
 #define RBFL_SPLIT_TOL 1e-4
 int32_t rbfl_autotune(rbfl_handle h, const double *params, int64_t n, int32_t form, void *stream);
+
+/* The bar rbfl_autotune holds split-form digit counts to against the FP64
+ * form on its tuning proposals, for this handle: RBFL_SPLIT_TOL (a tenth of
+ * the online stage's 1e-3 accuracy target) until set.  A looser bar lets the
+ * tuner keep fewer digits (faster, each proposal's ln L further from the FP64
+ * form's, but never by more than tol on the tuning proposals).  Takes effect
+ * at the next rbfl_autotune of RBFL_FORM_SPLIT; multi-event plans keep
+ * RBFL_SPLIT_TOL.  RBFL_E_INVALID_ARG for a NULL handle or tol outside
+ * (0, 1e-3]; needs exclusive use of the handle. */
+int32_t rbfl_set_split_tol(rbfl_handle h, double tol);
 
 /* Number of contraction tile variants (at least 1) of `form` (RBFL_FORM_FP64
  * .. SPLIT), or -RBFL_E_INVALID_ARG (negative) for another form. */

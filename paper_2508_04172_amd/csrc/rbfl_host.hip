@@ -1743,7 +1743,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
   const int64_t nb = std::min(c.cap, n);
   const int nv = contract_variants(form);
   // The split form's slice count sets its accuracy: a variant is eligible
-  // only if its ln L stays within RBFL_SPLIT_TOL of the FP64 form's on these
+  // only if its ln L stays within split_tol of the FP64 form's on these
   // proposals (same domain flags, finite entries compared).
   std::vector<double> ref;
   DevBuf<double> probe;
@@ -1772,7 +1772,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
         if (std::isfinite(ref[i])) err = std::max(err, std::fabs(got[i] - ref[i]));
       }
       c.split_err[v] = err;
-      eligible[v] = err <= RBFL_SPLIT_TOL;
+      eligible[v] = err <= c.split_tol;
     }
     contract(c, params, n, 0, nb, form, s);
   }
@@ -1813,7 +1813,7 @@ static void autotune(Ctx &c, const double *params, int64_t n, int form, hipStrea
       if (med[v] <= 1.03 * best_ms && gemm_fp64_reuse(v) > gemm_fp64_reuse(best)) best = v;
   }
   if (best < 0) {
-    // no split variant within RBFL_SPLIT_TOL: keep the most accurate one
+    // no split variant within split_tol: keep the most accurate one
     // (ties to more digits) and leave split_ok false for RBFL_Q_SPLIT_STATE
     best = 0;
     for (int v = 1; v < nv && v < 8; ++v)
@@ -2438,6 +2438,14 @@ int32_t rbfl_set_variant(rbfl_handle h, int32_t form, int32_t variant) {
     if (!h->c.prepared[form]) throw rbfl::Error(RBFL_E_STATE, "form not prepared (call rbfl_prepare)");
     rbfl::require(variant >= 0 && variant < rbfl::contract_variants(form), "variant out of range");
     h->c.variant[form] = variant;
+  });
+}
+
+int32_t rbfl_set_split_tol(rbfl_handle h, double tol) {
+  return rbfl::guarded([&] {
+    rbfl::require(h != nullptr, "handle is NULL");
+    rbfl::require(std::isfinite(tol) && tol > 0.0 && tol <= 1e-3, "tol must be in (0, 1e-3]");
+    h->c.split_tol = tol;
   });
 }
 

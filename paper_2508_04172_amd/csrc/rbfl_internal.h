@@ -216,7 +216,8 @@ struct Ctx {
   double tune_ms[5][8] = {};          // last autotune timings per variant
   double split_err[8] = {};           // last split autotune: max |d ln L| vs the FP64 form per variant
   bool split_tuned = false;           // the split form's digit count was chosen by rbfl_autotune
-  bool split_ok = false;              // last split autotune found a variant within RBFL_SPLIT_TOL
+  bool split_ok = false;              // last split autotune found a variant within split_tol
+  double split_tol = RBFL_SPLIT_TOL;  // the split autotune's bar against the FP64 form (rbfl_set_split_tol)
   // work space
   DevBuf<double> Y;            // [cap][Kp]
   DevBuf<double> Bt;           // FP64 basis rows of one chunk [rows][rows_ld(cap)]

@@ -36,7 +36,7 @@ STATIC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
-            "rbfl_fuse_epilogue",
+            "rbfl_fuse_epilogue", "rbfl_set_split_tol",
             "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
             "rbfl_plan_query", "rbfl_plan_set_variant", "rbfl_plan_destroy", "rbfl_eval_ragged", "rbfl_surrogate_train", "rbfl_surrogate_force",
             "rbfl_mlp_create", "rbfl_mlp_forward", "rbfl_mlp_loss_grad", "rbfl_mlp_adam", "rbfl_mlp_get",
@@ -173,6 +173,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_set_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.rbfl_fuse_epilogue.restype = C.c_int32
     lib.rbfl_fuse_epilogue.argtypes = [C.c_void_p, C.c_int32]
+    lib.rbfl_set_split_tol.restype = C.c_int32
+    lib.rbfl_set_split_tol.argtypes = [C.c_void_p, C.c_double]
     lib.rbfl_pipeline.restype = C.c_int32
     lib.rbfl_pipeline.argtypes = [C.c_void_p, C.c_int32]
     lib.rbfl_profile.restype = C.c_int32
@@ -529,6 +531,10 @@ class Handle:
     def set_pipeline(self, chunks: int):
         """Chunks per FP64 evaluation (1 = serial order); the autotuner sets it."""
         _check(load().rbfl_pipeline(self._h, chunks))
+
+    def set_split_tol(self, tol: float):
+        """The split autotune's bar against the FP64 form (rbfl_set_split_tol; default SPLIT_TOL)."""
+        _check(load().rbfl_set_split_tol(self._h, float(tol)))
 
     def fuse_epilogue(self, on: bool, split: bool = False):
         """ln L finished inside the FP64 contraction (`on`) and inside the split contraction

@@ -126,6 +126,8 @@ def main(path):
     expect(lib.rbfl_save(nul, b"/nonexistent"), rbfl.E_INVALID_ARG, "save NULL handle")
     expect(lib.rbfl_eval_static(nul, buf, C.c_int64(1), buf, nul), rbfl.E_INVALID_ARG, "static NULL handle")
     expect(lib.rbfl_fuse_epilogue(nul, 1), rbfl.E_INVALID_ARG, "fuse NULL handle")
+    lib.rbfl_set_split_tol.argtypes = [C.c_void_p, C.c_double]
+    expect(lib.rbfl_set_split_tol(nul, C.c_double(5e-4)), rbfl.E_INVALID_ARG, "split tol NULL handle")
     expect(lib.rbfl_eval_ragged(None, 1, None, None, None, nul), rbfl.E_INVALID_ARG, "ragged NULL")
     counts = (C.c_int64 * 1)(1)
     out = C.c_void_p()

@@ -175,6 +175,42 @@ def test_split_order_autotuned():
     h.fuse_epilogue(False)
 
 
+def test_split_tolerance_per_handle():
+    """rbfl_set_split_tol: a looser bar never keeps more digits than the
+    default one on the same proposals, the kept count is within the bar it
+    was tuned to, ln L stays within 1e-3 of the oracle, and bars outside
+    (0, 1e-3] are refused."""
+    torch = pytest.importorskip("torch")
+    cfg, art, h = _prepared("small_multi", rbfl.FORM_SPLIT)
+    n = 3000
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=41)
+    qd = wl.queries(cfg, n=n, seed=41)
+    qg = qd.near_nodes(h.nodes(), idx, jit)
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h, qg, cfg.t_trig))).cuda()
+    sp = torch.cuda.current_stream().cuda_stream
+    chosen = {}
+    try:
+        for tol in (rbfl.SPLIT_TOL, 1e-3):
+            h.set_split_tol(tol)
+            tune = h.autotune(p.data_ptr(), n, rbfl.FORM_SPLIT, sp)
+            v = tune["variant"]
+            assert tune["max_dlnl_vs_fp64"][v] <= tol
+            assert h.split_state()["within_tol"]
+            chosen[tol] = tune["slices"]
+            lg = gpu_eval(h, qg, cfg.t_trig, rbfl.FORM_SPLIT)
+            lo = lk.meshfree_lnl(art, *lk.query_params(art, qd.near_nodes(art.x_nodes, idx, jit)))
+            fin = np.isfinite(lo)
+            assert np.array_equal(fin, np.isfinite(lg))
+            assert np.abs(lg[fin] - lo[fin]).max() <= 1e-3
+        print(f"[mixed] split digits kept at bar 1e-4: {chosen[rbfl.SPLIT_TOL]}, at 1e-3: {chosen[1e-3]}", flush=True)
+        assert chosen[1e-3] <= chosen[rbfl.SPLIT_TOL]
+        lib = rbfl.load()
+        for bad in (0.0, -1e-4, 2e-3, float("nan")):
+            assert lib.rbfl_set_split_tol(h._h, bad) == rbfl.E_INVALID_ARG
+    finally:
+        h.set_split_tol(rbfl.SPLIT_TOL)
+
+
 def test_split_chunked_matches_single_pass():
     """Batches above the work-space capacity give the same split-form results
     as one pass (the digit buffer is re-filled per chunk)."""
