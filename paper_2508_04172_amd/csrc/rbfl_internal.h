@@ -283,12 +283,15 @@ bool debug_mode();
 void debug_check_layout(const Ctx &c);
 void debug_require(bool ok, const std::string &what);   // RBFL_E_STATE "RBFL_DEBUG: what" unless ok
 
-// Handle operations shared by the host files (rbfl_host.hip): reduced-
-// precision weights of a form, work space for n proposals, and a batched
-// evaluation in a form (rbfl_prepare, rbfl_reserve, rbfl_eval).
+// Online-stage operations of a handle (rbfl_eval.hip), shared by the host
+// files: reduced-precision weights of a form, work space for n proposals, a
+// batched evaluation in a form, the interpolated outputs, and the autotuner
+// (rbfl_prepare, rbfl_reserve, rbfl_eval, rbfl_interp, rbfl_autotune).
 void prepare(Ctx &c, int form);
 void reserve(Ctx &c, int64_t n);
 void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s);
+void interp(Ctx &c, const double *params, int64_t n, double *out, int form, hipStream_t s);
+void autotune(Ctx &c, const double *params, int64_t n, int form, hipStream_t s);
 
 // ---- start-up kernels (build_kernels.hip) ----
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
