@@ -1,6 +1,8 @@
 // Start-up stage kernels (Sec. II C): templates at the nodes, mode overlaps,
 // windowed DFT for the overlap time series, SVD post-processing and the RBF
 // system assembly.  All FP64.
+#include <algorithm>
+
 #include "rbfl_internal.h"
 
 namespace rbfl {
@@ -10,6 +12,8 @@ namespace {
 constexpr int kBlock = 256;
 
 inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 // conj(h_{l,-m}(f_j)) for every node of a batch, every mode and bins
 // j_lo .. j_lo + J - 1; zero outside the mode's band f < |m| F_isco.
@@ -36,122 +40,185 @@ __global__ void __launch_bounds__(kBlock) k_waveforms(const Binary *__restrict__
 
 // sigma_k,ab = sum_j conj(h_a) h_b w_k(j) over bins j0 .. j1 - 1 of the
 // band (all of it, or one time band), w_k = 4 df / S_k.  A holds conj(h), so
-// conj(h_a) h_b = A_a conj(A_b).  One block per (node, detector); the
-// detector's results go to sig[k * det_stride + node_base + node]; fixed-order
-// tree reduction (deterministic).
-__global__ void __launch_bounds__(kBlock) k_sigma(const double2 *__restrict__ A, int nb, int n_modes, int J,
-                                                  int j0, int j1, const double *__restrict__ wk,
-                                                  int64_t det_stride, int node_base, double2 *__restrict__ sig) {
+// conj(h_a) h_b = A_a conj(A_b).  One block of 1024 threads per (node,
+// detector), NM modes known at compile time so that the NM (NM + 1) / 2
+// running sums stay in registers; each wave adds its lanes' sums in a fixed
+// shuffle tree and the block adds its waves' in order (deterministic).  The
+// detector's results go to sig[k * det_stride + node_base + node].
+constexpr int kSigmaThreads = 1024;
+
+template <int NM>
+__global__ void __launch_bounds__(kSigmaThreads) k_sigma(const double2 *__restrict__ A, int nb, int J, int j0,
+                                                         int j1, const double *__restrict__ wk, int64_t det_stride,
+                                                         int node_base, double2 *__restrict__ sig) {
+  constexpr int NP = NM * (NM + 1) / 2;
+  constexpr int NW = kSigmaThreads / 64;
   const int i = blockIdx.x;
   const int k = blockIdx.y;
-  const int npair = n_modes * (n_modes + 1) / 2;
-  double2 acc[15];
-  for (int p = 0; p < 15; ++p) acc[p] = make_double2(0.0, 0.0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double2 acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = make_double2(0.0, 0.0);
   const double *w = wk + (int64_t)k * J;
-  for (int jj = j0 + threadIdx.x; jj < j1; jj += kBlock) {
-    double2 h[RBFL_MAX_MODES];
-    for (int a = 0; a < n_modes; ++a) h[a] = A[((int64_t)a * nb + i) * J + jj];
+  for (int jj = j0 + threadIdx.x; jj < j1; jj += kSigmaThreads) {
+    double2 h[NM];
+#pragma unroll
+    for (int a = 0; a < NM; ++a) h[a] = A[((int64_t)a * nb + i) * J + jj];
     const double ww = w[jj];
     int p = 0;
-    for (int a = 0; a < n_modes; ++a) {
-      for (int b = a; b < n_modes; ++b, ++p) {
+#pragma unroll
+    for (int a = 0; a < NM; ++a)
+#pragma unroll
+      for (int b = a; b < NM; ++b, ++p) {
         // A_a * conj(A_b)
         acc[p].x += (h[a].x * h[b].x + h[a].y * h[b].y) * ww;
         acc[p].y += (h[a].y * h[b].x - h[a].x * h[b].y) * ww;
       }
-    }
   }
-  __shared__ double2 red[kBlock];
-  double2 *out = sig + ((int64_t)k * det_stride + node_base + i) * n_modes * n_modes;
-  int p = 0;
-  for (int a = 0; a < n_modes; ++a) {
-    for (int b = a; b < n_modes; ++b, ++p) {
-      red[threadIdx.x] = acc[p];
-      __syncthreads();
-      for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-          red[threadIdx.x].x += red[threadIdx.x + s].x;
-          red[threadIdx.x].y += red[threadIdx.x + s].y;
-        }
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) {
-        const double2 v = red[0];
-        out[a * n_modes + b] = v;
-        out[b * n_modes + a] = make_double2(v.x, -v.y);
-      }
-      __syncthreads();
+  __shared__ double2 red[NW][NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    double2 v = acc[p];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      v.x += __shfl_xor(v.x, m, 64);
+      v.y += __shfl_xor(v.y, m, 64);
     }
+    if (lane == 0) red[wave][p] = v;
   }
-  (void)npair;
+  __syncthreads();
+  if (threadIdx.x < NP) {
+    const int p = threadIdx.x;
+    double2 v = red[0][p];
+    for (int wv = 1; wv < NW; ++wv) {
+      v.x += red[wv][p].x;
+      v.y += red[wv][p].y;
+    }
+    int a = 0, r = p;
+    while (r >= NM - a) {   // pair p = (a, b) in the order a <= b, a slowest
+      r -= NM - a;
+      ++a;
+    }
+    const int bm = a + r;
+    double2 *out = sig + ((int64_t)k * det_stride + node_base + i) * NM * NM;
+    out[a * NM + bm] = v;
+    out[bm * NM + a] = make_double2(v.x, -v.y);
+  }
 }
 
-// Windowed DFT: partial[s][i][t] = sum_{jj in split s} A[i][jj] Dk[jj] e^{2 pi i (j_lo+jj) t / n_s},
+// Windowed DFT on the FP64 matrix cores:
+//   partial[s][i][t] = sum_{jj in split s} A[i][jj] B[jj][t],
+//   B[jj][t] = Dk[jj] e^{2 pi i (j_lo + jj) t / n_s},
 // where Dk already carries 4 df d_k / S_k and the phase of the window start.
-// Tile: 64 nodes x 64 taps per block, 16 bins per step; thread (ty, tx)
-// owns nodes ty + 16u and taps tx + 16v (u, v < 4).
-constexpr int kDftTile = 64;
-constexpr int kDftStep = 16;
+// The complex product is taken as a real one, A'[i][2jj + r] B'[2jj + r][2t + u]:
+// A' is A's own memory read as doubles (interleaved re, im) and each complex
+// B entry becomes the 2 x 2 real block (Re, Im; -Im, Re), so a real output
+// row is the interleaved complex partial row.  Tile: 128 nodes x 128 real
+// columns (64 taps) per workgroup of 8 waves, 4 along the nodes x 2 along
+// the columns, each wave 32 x 64 from 2 x 4 v_mfma_f64_16x16x4f64 blocks
+// (lane l holds A'[l%16][l/16], B'[l/16][l%16]; accumulator element i is
+// row l/16 + 4i, column l%16 of its block; at most 128 registers, so two
+// workgroups share a CU).  Per step 8 bins (16 real k) go
+// through LDS, A' loaded one step ahead; B' is formed in the step, one
+// sincospi per (bin, tap) with the phase (j t) mod n_s reduced exactly in
+// integers.
+constexpr int kDftNodes = 128, kDftTaps = 64, kDftBins = 8, kDftThreads = 512;
 
-__global__ void __launch_bounds__(kBlock) k_window_dft(const double2 *__restrict__ A, int nb, int J_mode,
-                                                       int J_stride, const double2 *__restrict__ Dk,
-                                                       int64_t j_lo, int64_t n_s, int T, int split_len,
-                                                       double2 *__restrict__ partial) {
-  __shared__ double2 As[kDftTile][kDftStep + 1];
-  __shared__ double2 Bs[kDftStep][kDftTile];
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  const int node0 = blockIdx.x * kDftTile;
-  const int tap0 = blockIdx.y * kDftTile;
+__global__ void __launch_bounds__(kDftThreads, 4) k_window_dft(const double2 *__restrict__ A, int nb, int J_mode,
+                                                            int J_stride, const double2 *__restrict__ Dk,
+                                                            int64_t j_lo, int64_t n_s, int T, int split_len,
+                                                            double2 *__restrict__ partial) {
+  constexpr int QT = kDftNodes, CW = 2 * kDftTaps, KC = 2 * kDftBins, RT = 2, CT = 4;
+  __shared__ double As[KC][QT];
+  __shared__ double Bs[KC][CW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 3, wc = wave >> 2;
+  const int kk = lane >> 4, ll = lane & 15;
+  const int node0 = blockIdx.x * QT, tap0 = blockIdx.y * kDftTaps;
   const int split = blockIdx.z;
   const int jb = split * split_len;
   const int je = min(J_mode, jb + split_len);
-  double2 acc[4][4];
-  for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  d4 acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
   const double inv_ns2 = 2.0 / (double)n_s;
-  for (int j0 = jb; j0 < je; j0 += kDftStep) {
-    for (int e = tid; e < kDftTile * kDftStep; e += kBlock) {
-      const int n = e / kDftStep, bb = e % kDftStep;
-      const int node = node0 + n, jj = j0 + bb;
-      As[n][bb] = (node < nb && jj < je) ? A[(int64_t)node * J_stride + jj] : make_double2(0.0, 0.0);
+  // A': QT nodes x 8 bins per step, two entries per thread (bins of one
+  // node), loaded one step ahead into registers
+  constexpr int LA = QT * kDftBins / kDftThreads;
+  double2 ra[LA];
+  auto load_a = [&](int j0) {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + u * kDftThreads;
+      const int node = node0 + e / kDftBins, jj = j0 + e % kDftBins;
+      ra[u] = (node < nb && jj < je) ? A[(int64_t)node * J_stride + jj] : make_double2(0.0, 0.0);
     }
-    for (int e = tid; e < kDftTile * kDftStep; e += kBlock) {
-      const int bb = e / kDftTile, t = e % kDftTile;
-      const int jj = j0 + bb, tap = tap0 + t;
-      double2 v = make_double2(0.0, 0.0);
-      if (jj < je && tap < T) {
-        const int64_t j = j_lo + jj;
-        const int64_t ph = (j * (int64_t)tap) % n_s;
-        double sn, cs;
-        sincospi((double)ph * inv_ns2, &sn, &cs);
-        const double2 d = Dk[jj];
-        v = make_double2(d.x * cs - d.y * sn, d.x * sn + d.y * cs);
+  };
+  auto stash = [&](int j0) {
+    // keeps the compiler from hoisting these LDS writes (and the wait for
+    // their global loads) above the previous step's MFMAs
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + u * kDftThreads;
+      const int n = e / kDftBins, bb = e % kDftBins;
+      As[2 * bb][n] = ra[u].x;
+      As[2 * bb + 1][n] = ra[u].y;
+    }
+    // B': 8 bins x 64 taps, one per thread
+    const int bb = tid / kDftTaps, t = tid % kDftTaps;
+    const int jj = j0 + bb, tap = tap0 + t;
+    double br = 0.0, bi = 0.0;
+    if (jj < je && tap < T) {
+      const int64_t j = j_lo + jj;
+      const int64_t ph = (j * (int64_t)tap) % n_s;
+      double sn, cs;
+      sincospi((double)ph * inv_ns2, &sn, &cs);
+      const double2 d = Dk[jj];
+      br = d.x * cs - d.y * sn;
+      bi = d.x * sn + d.y * cs;
+    }
+    Bs[2 * bb][2 * t] = br;
+    Bs[2 * bb][2 * t + 1] = bi;
+    Bs[2 * bb + 1][2 * t] = -bi;
+    Bs[2 * bb + 1][2 * t + 1] = br;
+  };
+  if (jb < je) load_a(jb);
+  for (int j0 = jb; j0 < je; j0 += kDftBins) {
+    stash(j0);
+    __syncthreads();
+    if (j0 + kDftBins < je) load_a(j0 + kDftBins);
+#pragma unroll
+    for (int st = 0; st < KC / 4; ++st) {
+      const int k = 4 * st + kk;
+      double a[RT], b[CT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = As[k][wq * RT * 16 + 16 * t + ll];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[u] = Bs[k][wc * CT * 16 + 16 * u + ll];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double *out = reinterpret_cast<double *>(partial);
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int node = node0 + wq * RT * 16 + 16 * t + kk + 4 * i;
+      if (node >= nb) continue;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const int col = wc * CT * 16 + 16 * u + ll;     // real column: tap col / 2, part col % 2
+        const int tap = tap0 + (col >> 1);
+        if (tap < T) out[(((int64_t)split * nb + node) * T + tap) * 2 + (col & 1)] = acc[t][u][i];
       }
-      Bs[bb][t] = v;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int bb = 0; bb < kDftStep; ++bb) {
-      double2 a[4], b[4];
-      for (int u = 0; u < 4; ++u) a[u] = As[ty + 16 * u][bb];
-      for (int v = 0; v < 4; ++v) b[v] = Bs[bb][tx + 16 * v];
-      for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
-          acc[u][v].x = fma(a[u].x, b[v].x, fma(-a[u].y, b[v].y, acc[u][v].x));
-          acc[u][v].y = fma(a[u].x, b[v].y, fma(a[u].y, b[v].x, acc[u][v].y));
-        }
-    }
-    __syncthreads();
-  }
-  for (int u = 0; u < 4; ++u) {
-    const int node = node0 + ty + 16 * u;
-    if (node >= nb) continue;
-    for (int v = 0; v < 4; ++v) {
-      const int tap = tap0 + tx + 16 * v;
-      if (tap < T) partial[((int64_t)split * nb + node) * T + tap] = acc[u][v];
-    }
-  }
 }
 
 __global__ void k_reduce_splits(const double2 *__restrict__ partial, int n_split, int64_t count,
@@ -335,17 +402,33 @@ void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_mode
 
 void launch_sigma(const double2 *A, int nb, int n_modes, int J, int j0, int j1, const double *wk, int n_det,
                   int64_t det_stride, int node_base, double2 *sig, hipStream_t s) {
-  hipLaunchKernelGGL(k_sigma, dim3(nb, n_det), dim3(kBlock), 0, s, A, nb, n_modes, J, j0, j1, wk, det_stride,
-                     node_base, sig);
+  const dim3 grid(nb, n_det), block(kSigmaThreads);
+  switch (n_modes) {
+    case 1: hipLaunchKernelGGL(k_sigma<1>, grid, block, 0, s, A, nb, J, j0, j1, wk, det_stride, node_base, sig); break;
+    case 2: hipLaunchKernelGGL(k_sigma<2>, grid, block, 0, s, A, nb, J, j0, j1, wk, det_stride, node_base, sig); break;
+    case 3: hipLaunchKernelGGL(k_sigma<3>, grid, block, 0, s, A, nb, J, j0, j1, wk, det_stride, node_base, sig); break;
+    case 4: hipLaunchKernelGGL(k_sigma<4>, grid, block, 0, s, A, nb, J, j0, j1, wk, det_stride, node_base, sig); break;
+    case 5: hipLaunchKernelGGL(k_sigma<5>, grid, block, 0, s, A, nb, J, j0, j1, wk, det_stride, node_base, sig); break;
+    default: throw Error(RBFL_E_INVALID_ARG, "mode overlaps: 1 .. 5 modes");
+  }
   RBFL_HIP(hipGetLastError());
+}
+
+int window_dft_splits(int nb, int T, int64_t len) {
+  // as many splits of the bin range as keep the workgroups within one round
+  // of the GPU (two 8-wave workgroups per CU, 512 in all: a partly filled
+  // second round would leave most CUs idle for its length), and no split
+  // shorter than 256 bins
+  const int64_t tiles = (int64_t)grid1(nb, kDftNodes) * grid1(T, kDftTaps);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(512 / tiles, (len + 255) / 256));
 }
 
 void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
                        int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s) {
   int split_len = (J_mode + n_split - 1) / n_split;
-  split_len = ((split_len + kDftStep - 1) / kDftStep) * kDftStep;
-  dim3 grid(grid1(nb, kDftTile), grid1(T, kDftTile), n_split);
-  hipLaunchKernelGGL(k_window_dft, grid, dim3(kBlock), 0, s, A_mode, nb, J_mode, J_stride, Dk, j_lo, n_s, T,
+  split_len = ((split_len + kDftBins - 1) / kDftBins) * kDftBins;
+  dim3 grid(grid1(nb, kDftNodes), grid1(T, kDftTaps), n_split);
+  hipLaunchKernelGGL(k_window_dft, grid, dim3(kDftThreads), 0, s, A_mode, nb, J_mode, J_stride, Dk, j_lo, n_s, T,
                      split_len, partial);
   RBFL_HIP(hipGetLastError());
 }

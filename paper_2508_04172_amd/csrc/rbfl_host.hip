@@ -494,8 +494,7 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
     mode_lm[2 * a] = c.modes[a][0];
     mode_lm[2 * a + 1] = c.modes[a][1];
   }
-  const int t_here = ((nb + 63) / 64) * ((T + 63) / 64);
-  const int n_split = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + t_here - 1) / t_here, (J + 255) / 256));
+  const int n_split = window_dft_splits(nb, T, J);
   if (w.nb != nb) {
     w.modes.alloc(2 * RBFL_MAX_MODES);
     w.bins.alloc(nb);
@@ -1084,12 +1083,9 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   if (nb_max < c.N && nb_max >= 64) nb_max &= ~63;
   DevBuf<double2> d_A;
   d_A.alloc((size_t)c.n_modes * nb_max * J);
-  // split the bin range of the windowed DFT so each launch has >= ~1024 blocks
+  // split the bin range of the windowed DFT so each launch fills the GPU
   // (a band's bins: no more splits than its whole mode's)
-  auto n_splits = [&](int nb, int len) {
-    const int t_here = ((nb + 63) / 64) * ((c.T + 63) / 64);
-    return std::max(1, std::min((1024 + t_here - 1) / t_here, (len + 255) / 256));
-  };
+  auto n_splits = [&](int nb, int len) { return window_dft_splits(nb, c.T, len); };
   size_t part_elems = 1;
   for (int base = 0; base < c.N; base += nb_max) {
     const int nb = std::min(nb_max, c.N - base);
@@ -1383,10 +1379,7 @@ static void exact_parts(Ctx &c, const double *params, int64_t n, double *out, hi
   const size_t budget = (size_t)2 << 30;
   const int nb_max = (int)std::max<int64_t>(
       1, std::min<int64_t>({n, 4096, (int64_t)(budget / ((size_t)nm * J * sizeof(double2)))}));
-  auto n_splits = [&](int nb) {
-    const int t_here = ((nb + 63) / 64) * ((T + 63) / 64);
-    return (int)std::max<int64_t>(1, std::min<int64_t>((1024 + t_here - 1) / t_here, (J + 255) / 256));
-  };
+  auto n_splits = [&](int nb) { return window_dft_splits(nb, T, J); };
   DevBuf<Binary> bins;
   bins.alloc(nb_max);
   DevBuf<double2> A, Z, sig, C, part;

@@ -298,6 +298,9 @@ void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_mode
                       double df, double inv_dref_s, double2 *out, hipStream_t s);
 void launch_sigma(const double2 *A, int nb, int n_modes, int J, int j0, int j1, const double *wk, int n_det,
                   int64_t det_stride, int node_base, double2 *sig, hipStream_t s);
+// Bin-range splits of the windowed DFT for nb nodes, T taps and len bins:
+// enough to fill the GPU, none shorter than 256 bins.
+int window_dft_splits(int nb, int T, int64_t len);
 void launch_window_dft(const double2 *A_mode, int nb, int J_mode, int J_stride, const double2 *Dk, int64_t j_lo,
                        int64_t n_s, int T, int n_split, double2 *partial, hipStream_t s);
 void launch_reduce_splits(const double2 *partial, int n_split, int nb, int T, double2 *Z_rows, hipStream_t s);
