@@ -623,6 +623,39 @@ def bench_third_generation(args, np, torch, rbfl, wl):
                     "check_sample": f"{m} seeded proposals of the pass; oracle online stage on the handle's "
                                     "exported artefacts"})
         log(f"third generation: max |dlnL| vs oracle {d.max():.3e}")
+    # the split form on this workload: digit count and evaluation order tuned on
+    # the pass (within RBFL_SPLIT_TOL of the FP64 form), then timed like it
+    h.prepare(rbfl.FORM_SPLIT)
+    tune_s = h.autotune(params.data_ptr(), n, rbfl.FORM_SPLIT, sp)
+    h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SPLIT, sp)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t = time.perf_counter()
+    for _ in range(reps):
+        h.eval(params.data_ptr(), n, lnl.data_ptr(), rbfl.FORM_SPLIT, sp)
+    torch.cuda.synchronize()
+    wall_s = (time.perf_counter() - t) / reps
+    h.profile(False)
+    ks = h.kernel_stats()
+    c_s = ks["contract_ms"] / max(1, ks["contract_launches"])
+    S = tune_s["slices"]
+    tops = S * (S + 1) / 2 * flop * per / (c_s * 1e-3)
+    ls = lnl.cpu().numpy()
+    order_s = h.split_order()
+    out["split"] = {"evals_per_s": n / wall_s, "ms_per_pass": wall_s * 1e3, "slices": S,
+                    "max_dlnl_vs_fp64_per_slice_count": tune_s["max_dlnl_vs_fp64"][:4], "order": order_s,
+                    "contract_ms_per_launch": c_s, "speedup_vs_fp64": wall / wall_s,
+                    "roofline": roof(tops, PEAK_INT8, unit="TOP/s",
+                                     kernel="k_split_lnl (ln L inside the contraction; int8 products issued)"
+                                     if order_s["fused_epilogue"] else "k_split_contract (int8 products issued)")}
+    if not args.no_cpu_baseline:
+        fin_s = np.isfinite(ls[sample])
+        d = np.abs(ls[sample][fin] - lo[fin])
+        out["split"].update({"max_dlnl": float(d.max()), "median_dlnl": float(np.median(d)),
+                             "domain_agrees": bool(np.array_equal(fin, fin_s)),
+                             "meets_1e-3": bool(np.array_equal(fin, fin_s) and d.max() <= 1e-3)})
+    log(f"third generation split: S = {S}, {n / wall_s:.4e} evals/s ({wall / wall_s:.2f}x FP64), "
+        f"contraction {c_s:.2f} ms, order {order_s}")
     if args.third_generation_surrogate > 0:
         out["surrogate"] = bench_surrogate(args, np, torch, rbfl, wl, cfg, h, params, lnl, l64,
                                            args.third_generation_surrogate, 10, reps)
