@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librbfl.so")
-SOURCES = ["rbfl_host.hip", "rbfl_eval.hip", "host_math.hip", "rbfl_plan.hip", "sampler_host.hip", "rbfl_store.hip", "rbfl_static.hip", "build_kernels.hip", "eval_kernels.hip", "contract_fp64.hip",
+SOURCES = ["rbfl_host.hip", "rbfl_eval.hip", "surrogate_host.hip", "rbfl_query.hip", "host_math.hip", "rbfl_plan.hip", "sampler_host.hip", "rbfl_store.hip", "rbfl_static.hip", "build_kernels.hip", "eval_kernels.hip", "contract_fp64.hip",
            "contract_split.hip", "contract_bf16.hip", "brute.hip", "mlp.hip", "sampler.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 

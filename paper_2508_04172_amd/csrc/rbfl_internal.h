@@ -292,6 +292,10 @@ void reserve(Ctx &c, int64_t n);
 void eval(Ctx &c, const double *params, int64_t n, double *lnl, int form, hipStream_t s);
 void interp(Ctx &c, const double *params, int64_t n, double *out, int form, hipStream_t s);
 void autotune(Ctx &c, const double *params, int64_t n, int form, hipStream_t s);
+// The surrogate's training driver (surrogate_host.hip, rbfl_surrogate_train)
+// and the artefact export (rbfl_query.hip, rbfl_query).
+void surrogate_train(Ctx &c, const rbfl_train_spec *sp, hipStream_t s);
+void query(Ctx &c, int what, void *out, size_t bytes);
 
 // ---- start-up kernels (build_kernels.hip) ----
 void launch_waveforms(const Binary *bins, int nb, const int *mode_lm, int n_modes, int64_t j_lo, int J,
