@@ -479,14 +479,17 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
     mode_lm[2 * a] = c.modes[a][0];
     mode_lm[2 * a + 1] = c.modes[a][1];
   }
-  const int n_split = window_dft_splits(nb, T, J);
+  // A is [a][binary][J]: its nm * nb rows go through one windowed DFT per
+  // detector, which writes that detector's [a][binary][T] block of Z
+  const int rows = nm * nb;
+  const int n_split = window_dft_splits(rows, T, J);
   if (w.nb != nb) {
     w.modes.alloc(2 * RBFL_MAX_MODES);
     w.bins.alloc(nb);
-    w.A.alloc((size_t)nm * nb * J);
-    w.Z.alloc((size_t)nd * nm * nb * T);
+    w.A.alloc((size_t)rows * J);
+    w.Z.alloc((size_t)nd * rows * T);
     w.S.alloc((size_t)nd * nb * nm * nm);
-    w.part.alloc((size_t)n_split * nb * T);
+    w.part.alloc((size_t)n_split * rows * T);
     w.nb = nb;
   }
   auto &d_modes = w.modes;
@@ -499,12 +502,11 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
   RBFL_HIP(hipMemcpyAsync(d_bins.p, bins.data(), sizeof(Binary) * nb, hipMemcpyHostToDevice, s));
   launch_waveforms(d_bins.p, nb, d_modes.p, nm, c.brute_j_lo, (int)J, c.df, 1.0, A.p, s);
   launch_sigma(A.p, nb, nm, (int)J, 0, (int)J, c.brute_w.p, nd, nb, 0, dS.p, s);
-  for (int a = 0; a < nm; ++a)
-    for (int k = 0; k < nd; ++k) {
-      launch_window_dft(A.p + (size_t)a * nb * J, nb, (int)J, (int)J, c.win_D.p + (size_t)k * J, c.brute_j_lo, c.n_s,
-                        T, n_split, part.p, s);
-      launch_reduce_splits(part.p, n_split, nb, T, dZ.p + ((size_t)k * nm + a) * nb * T, s);
-    }
+  for (int k = 0; k < nd; ++k) {
+    launch_window_dft(A.p, rows, (int)J, (int)J, c.win_D.p + (size_t)k * J, c.brute_j_lo, c.n_s, T, n_split, part.p,
+                      s);
+    launch_reduce_splits(part.p, n_split, rows, T, dZ.p + (size_t)k * rows * T, s);
+  }
   Z.resize(dZ.n);
   S.resize(dS.n);
   RBFL_HIP(hipMemcpyAsync(Z.data(), dZ.p, sizeof(double2) * dZ.n, hipMemcpyDeviceToHost, s));
@@ -522,9 +524,18 @@ static void template_series(Ctx &c, const std::vector<Binary> &bins, std::vector
 // leading direction), and over time: the best window sample b, then the
 // maximum of q along the not-a-knot spline of v through the window samples
 // on [b - 1, b + 1] (golden section, 60 steps; the sample value where the
-// stencil would leave the window).  Summed over the detectors.
+// stencil would leave the window).  Summed over the detectors.  w holds the
+// spline weights and the per-sample work arrays, kept across the calls of
+// one search.
+struct SnrWork {
+  double tab[kSplineTaps][4];
+  std::vector<double> r0, i0, r1, i1;
+  std::vector<cplx> v0, v1;
+  explicit SnrWork(int T) : r0(T), i0(T), r1(T), i1(T), v0(T), v1(T) { spline_table(tab); }
+};
+
 static double network_snr2(const Ctx &c, const YlmTerms *yneg, const YlmTerms *ypos, const std::vector<double2> &Z,
-                           const std::vector<double2> &S, int nb, int p, double iota, double phi) {
+                           const std::vector<double2> &S, int nb, int p, double iota, double phi, SnrWork &w) {
   const int nm = c.n_modes, T = c.T;
   cplx cp[RBFL_MAX_MODES], cx[RBFL_MAX_MODES];
   for (int a = 0; a < nm; ++a) {
@@ -535,10 +546,9 @@ static double network_snr2(const Ctx &c, const YlmTerms *yneg, const YlmTerms *y
     cp[a] = 0.5 * (cplx(nr, ni) + sg * cplx(pr, -pi));
     cx[a] = cplx(0.0, 0.5) * (cplx(nr, ni) - sg * cplx(pr, -pi));
   }
-  double tab[kSplineTaps][4];
-  spline_table(tab);
+  const double(&tab)[kSplineTaps][4] = w.tab;
+  std::vector<cplx> &v0 = w.v0, &v1 = w.v1;
   double total = 0.0;
-  std::vector<cplx> v0(T), v1(T);
   for (int k = 0; k < c.n_det; ++k) {
     cplx G00(0.0, 0.0), G01(0.0, 0.0), G11(0.0, 0.0);
     for (int a = 0; a < nm; ++a)
@@ -573,14 +583,26 @@ static double network_snr2(const Ctx &c, const YlmTerms *yneg, const YlmTerms *y
     };
     int best = 0;
     double qb = -1.0;
-    for (int t = 0; t < T; ++t) {
-      cplx a0(0.0, 0.0), a1(0.0, 0.0);
-      for (int a = 0; a < nm; ++a) {
-        const double2 zv = Z[(((size_t)k * nm + a) * nb + p) * T + t];
-        const cplx z(zv.x, zv.y);
-        a0 += std::conj(cp[a]) * z;
-        a1 += std::conj(cx[a]) * z;
+    // v(t) = (sum_a conj(c+_a) z_a(t), sum_a conj(cx_a) z_a(t)), mode by mode
+    // over contiguous sample rows
+    double *r0 = w.r0.data(), *i0 = w.i0.data(), *r1 = w.r1.data(), *i1 = w.i1.data();
+    std::fill(r0, r0 + T, 0.0);
+    std::fill(i0, i0 + T, 0.0);
+    std::fill(r1, r1 + T, 0.0);
+    std::fill(i1, i1 + T, 0.0);
+    for (int a = 0; a < nm; ++a) {
+      const double2 *za = &Z[(((size_t)k * nm + a) * nb + p) * T];
+      const double pr = cp[a].real(), pi = -cp[a].imag(), xr = cx[a].real(), xi = -cx[a].imag();
+      for (int t = 0; t < T; ++t) {
+        const double zx = za[t].x, zy = za[t].y;
+        r0[t] += pr * zx - pi * zy;
+        i0[t] += pr * zy + pi * zx;
+        r1[t] += xr * zx - xi * zy;
+        i1[t] += xr * zy + xi * zx;
       }
+    }
+    for (int t = 0; t < T; ++t) {
+      const cplx a0(r0[t], i0[t]), a1(r1[t], i1[t]);
       v0[t] = a0;
       v1[t] = a1;
       const double qt = q(a0, a1);
@@ -739,6 +761,7 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
     return theta_to_phys(th, c.f_low, c.chi_max, p);
   };
   SeriesWork work;
+  SnrWork snr_work(c.T);
   std::vector<double2> Z, S;
   double cur_angles[2] = {0.0, 0.0};   // the inner search's angles for the last template
   auto inner = [&]() {
@@ -746,14 +769,15 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
     std::vector<double> a0 = {0.0, 0.0};
     for (int j = 0; j <= 6; ++j)
       for (int k = 0; k < 8; ++k) {
-        const double v = network_snr2(c, yneg, ypos, Z, S, 1, 0, j * kPi / 6.0, k * kPi / 4.0);
+        const double v = network_snr2(c, yneg, ypos, Z, S, 1, 0, j * kPi / 6.0, k * kPi / 4.0, snr_work);
         if (v > b) {
           b = v;
           a0 = {j * kPi / 6.0, k * kPi / 4.0};
         }
       }
-    b = nelder_mead_max([&](const std::vector<double> &a) { return network_snr2(c, yneg, ypos, Z, S, 1, 0, a[0], a[1]); },
-                        a0, {0.1, 0.1}, 1e-12, 1e-8, 300);
+    b = nelder_mead_max(
+        [&](const std::vector<double> &a) { return network_snr2(c, yneg, ypos, Z, S, 1, 0, a[0], a[1], snr_work); },
+        a0, {0.1, 0.1}, 1e-12, 1e-8, 300);
     cur_angles[0] = a0[0];
     cur_angles[1] = a0[1];
     return b;
@@ -768,7 +792,7 @@ static void optimise_centre(Ctx &c, const std::vector<double> &psd0, const YlmTe
     double p[4];
     to_phys(std::vector<double>(4, 0.0).data(), p);
     template_series(c, {make_binary(p[0], p[1], p[2], p[3], c.f_ref)}, Z, S, s, work);
-    c.centre_snr[0] = sqrt(std::max(network_snr2(c, yneg, ypos, Z, S, 1, 0, 0.0, 0.0), 0.0));
+    c.centre_snr[0] = sqrt(std::max(network_snr2(c, yneg, ypos, Z, S, 1, 0, 0.0, 0.0, snr_work), 0.0));
   }
   std::vector<double> u(4, 0.0);
   double v = nelder_mead_max(outer, u, {0.1, 0.1, 0.1, 0.1}, 1e-12, 1e-7, 800);
