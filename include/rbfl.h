@@ -202,6 +202,21 @@ const char *rbfl_last_error(void);
  * Synchronous on `stream`.  *out receives a new handle. */
 int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out);
 
+/* The start-up stage (Sec. II C) of n events at once, for multi-event
+ * batches: the stages before and after the SVD run for specs[0 .. n) on
+ * n_threads host threads (1 .. 16, each with a stream of its own that the
+ * library creates and destroys), and the FP64 SVDs of every event's
+ * (detector, mode) pairs (Eq. SVD) go through one batched call per window
+ * length on `stream`, each pair's node-by-sample matrix padded with zero node
+ * rows to the largest node count of the call (this leaves the time basis and
+ * the nonzero singular values as they are; the results agree with rbfl_build's
+ * to rounding).  Synchronous; n in 1 .. 4096.  out[0 .. n) receives n new
+ * handles, each owned by the caller as if made by rbfl_build; RBFL_Q_TIMING's
+ * SVD entry of each is the batched stage's time.  On any failure (the first
+ * event's error is returned) every out[i] is NULL and nothing is kept. */
+int32_t rbfl_build_many(const rbfl_build_spec *specs, int32_t n, int32_t n_threads, void *stream,
+                        rbfl_handle *out);
+
 /* Exact ln L for n proposals, without the interpolant: the reference the
  * meshfree method approximates (Eq. logl_basic for the projected signal of
  * Eq. projected_h_fd, evaluated as Eq. logl_complete with z and the mode

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -18,7 +19,9 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_math.h"
@@ -865,8 +868,18 @@ void debug_check_layout(const Ctx &c) {
   debug_require(std::memcmp(&d, &e, sizeof(EvalConsts)) == 0, "device constants differ from the host copy");
 }
 
-static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
-  const auto t_all = Clock::now();
+// What the start-up's stages hand on: the mode overlaps and SVD coefficients
+// at the nodes, the bands' reference times and the start-up's start.
+struct BuildCarry {
+  DevBuf<double2> sig, C;
+  double band_t[RBFL_MAX_BANDS][RBFL_MAX_MODES] = {};
+  Clock::time_point t_all;
+};
+
+// Start-up up to the window series at the nodes: data, frame, nodes,
+// templates, overlaps and windowed DFT.
+static void build_front(const rbfl_build_spec *s, hipStream_t stream, Ctx &c, BuildCarry &carry) {
+  carry.t_all = Clock::now();
   validate(s);
   RBFL_HIP(hipGetDevice(&c.device));
   c.n_det = s->n_det;
@@ -898,7 +911,6 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.K = c.n_v * (2 * c.q * c.n_modes + c.n_modes * c.n_modes);
   c.Kp = ((c.K + kColTile - 1) / kColTile) * kColTile;
   c.rows = ((c.N + c.M + kRowChunk - 1) / kRowChunk) * kRowChunk;
-  const int NM = c.N + c.M;
   for (int k = 0; k < c.n_det; ++k) detector_geometry(s->det_geom + 5 * k, c.D[k], c.r[k]);
 
   YlmTerms yneg[RBFL_MAX_MODES], ypos[RBFL_MAX_MODES];
@@ -1025,7 +1037,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   t0 = Clock::now();
   const int64_t j_lo = std::max<int64_t>(1, (int64_t)ceil(c.f_low * c.seg_len - 1e-9));
   const int64_t j_hi = c.n_s / 2;
-  double band_t[RBFL_MAX_BANDS][RBFL_MAX_MODES] = {};
+  double(&band_t)[RBFL_MAX_BANDS][RBFL_MAX_MODES] = carry.band_t;
   if (c.n_bands > 1)
     time_bands(centre, c.f_ref, c.f_low, c.seg_len, c.n_s, c.n_modes, c.modes, c.n_bands, psd[0].data(), c.band_edges,
                band_t);
@@ -1080,7 +1092,7 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   RBFL_HIP(hipMemcpyAsync(d_wk.p, wk.data(), sizeof(double) * wk.size(), hipMemcpyHostToDevice, stream));
   const int nm2 = c.n_modes * c.n_modes;
   c.z_nodes.alloc((size_t)c.n_v * c.n_modes * c.N * c.T);
-  DevBuf<double2> d_sig;
+  DevBuf<double2> &d_sig = carry.sig;
   d_sig.alloc((size_t)c.n_v * c.N * nm2);
   RBFL_HIP(hipMemsetAsync(d_sig.p, 0, sizeof(double2) * d_sig.n, stream));
   // node batches sized so the templates of a batch stay within 32 GiB of the
@@ -1133,56 +1145,119 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   d_A.reset();
   d_part.reset();
   c.timing[2] = seconds_since(t0);
+}
 
-  // ---- SVD per (block, mode), all pairs in one batched call, and the
-  // coefficients at the nodes
-  t0 = Clock::now();
+// SVD per (block, mode) of one or more start-ups (Eq. SVD), and each one's
+// basis and coefficients at the nodes.  The pairs of all start-ups with the
+// same window length T go through one batched call: each pair's row-major
+// N x T block of window series is a column-major T x N matrix, padded with
+// zero columns to the largest N among them (zero columns change neither the
+// left singular vectors nor the nonzero singular values); its left singular
+// vectors are the conjugated right singular vectors of Z.  A single start-up
+// is not padded.
+static void svd_stage(const std::vector<std::pair<Ctx *, BuildCarry *>> &jobs, hipStream_t stream) {
+  const auto t0 = Clock::now();
   BlasHandle bh;
   blas_check(rocblas_set_stream(bh.h, stream), "rocblas_set_stream");
-  const int mn = std::min(c.N, c.T);
-  const int n_pairs = c.n_v * c.n_modes;
-  c.basis.alloc((size_t)n_pairs * c.T * c.q);
-  DevBuf<double2> d_C;
-  d_C.alloc((size_t)n_pairs * c.N * c.q);
-  DevBuf<double2> d_work, d_U;
-  d_work.alloc((size_t)n_pairs * c.N * c.T);
-  d_U.alloc((size_t)n_pairs * c.T * mn);
-  DevBuf<double> d_S, d_E;
-  d_S.alloc((size_t)n_pairs * mn);
-  d_E.alloc((size_t)n_pairs * std::max(1, mn - 1));
-  DevBuf<int> d_info;
-  d_info.alloc(n_pairs);
-  c.singular.assign((size_t)n_pairs * mn, 0.0);
-  RBFL_HIP(hipMemcpyAsync(d_work.p, c.z_nodes.p, sizeof(double2) * d_work.n, hipMemcpyDeviceToDevice, stream));
-  // each pair's row-major N x T block is a column-major T x N matrix; its left
-  // singular vectors are the conjugated right singular vectors of Z
-  blas_check(rocsolver_zgesvd_strided_batched(
-                 bh.h, rocblas_svect_singular, rocblas_svect_none, c.T, c.N,
-                 reinterpret_cast<rocblas_double_complex *>(d_work.p), c.T, (rocblas_stride)c.N * c.T, d_S.p,
-                 (rocblas_stride)mn, reinterpret_cast<rocblas_double_complex *>(d_U.p), c.T,
-                 (rocblas_stride)c.T * mn, nullptr, 1, 1, d_E.p, (rocblas_stride)std::max(1, mn - 1),
-                 rocblas_outofplace, d_info.p, n_pairs),
-             "rocsolver_zgesvd_strided_batched");
-  std::vector<int> info_h(n_pairs);
-  RBFL_HIP(hipMemcpyAsync(info_h.data(), d_info.p, sizeof(int) * n_pairs, hipMemcpyDeviceToHost, stream));
-  RBFL_HIP(hipMemcpyAsync(c.singular.data(), d_S.p, sizeof(double) * d_S.n, hipMemcpyDeviceToHost, stream));
-  RBFL_HIP(hipStreamSynchronize(stream));
-  for (int ka = 0; ka < n_pairs; ++ka)
-    if (info_h[ka] != 0)
-      throw Error(RBFL_E_NUMERICAL, "SVD of pair " + std::to_string(ka) + " did not converge (info " +
-                                        std::to_string(info_h[ka]) + ")");
-  d_work.reset();
-  for (int ka = 0; ka < n_pairs; ++ka) {
-    const double2 *Z = c.z_nodes.p + (size_t)ka * c.N * c.T;
-    launch_basis_from_u(d_U.p + (size_t)ka * c.T * mn, c.T, c.T, c.q, c.basis.p + (size_t)ka * c.T * c.q, stream);
-    launch_coeffs(Z, c.basis.p + (size_t)ka * c.T * c.q, c.N, c.T, c.q, d_C.p + (size_t)ka * c.N * c.q, stream);
+  std::vector<bool> taken(jobs.size(), false);
+  for (size_t g = 0; g < jobs.size(); ++g) {
+    if (taken[g]) continue;
+    const int T = jobs[g].first->T;
+    std::vector<size_t> grp;
+    int N_max = 0, n_prob = 0;
+    for (size_t i = g; i < jobs.size(); ++i)
+      if (!taken[i] && jobs[i].first->T == T) {
+        const Ctx &c = *jobs[i].first;
+        taken[i] = true;
+        grp.push_back(i);
+        N_max = std::max(N_max, c.N);
+        n_prob += c.n_v * c.n_modes;
+      }
+    const int mn = std::min(N_max, T);
+    DevBuf<double2> d_work, d_U;
+    d_work.alloc((size_t)n_prob * N_max * T);
+    d_U.alloc((size_t)n_prob * T * mn);
+    DevBuf<double> d_S, d_E;
+    d_S.alloc((size_t)n_prob * mn);
+    d_E.alloc((size_t)n_prob * std::max(1, mn - 1));
+    DevBuf<int> d_info;
+    d_info.alloc(n_prob);
+    int first = 0;
+    for (size_t i : grp) {
+      const Ctx &c = *jobs[i].first;
+      const int n_pairs = c.n_v * c.n_modes;
+      double2 *dst = d_work.p + (size_t)first * N_max * T;
+      if (c.N == N_max) {
+        RBFL_HIP(hipMemcpyAsync(dst, c.z_nodes.p, sizeof(double2) * n_pairs * c.N * T, hipMemcpyDeviceToDevice,
+                                stream));
+      } else {
+        for (int ka = 0; ka < n_pairs; ++ka) {
+          double2 *d = dst + (size_t)ka * N_max * T;
+          RBFL_HIP(hipMemcpyAsync(d, c.z_nodes.p + (size_t)ka * c.N * T, sizeof(double2) * c.N * T,
+                                  hipMemcpyDeviceToDevice, stream));
+          RBFL_HIP(hipMemsetAsync(d + (size_t)c.N * T, 0, sizeof(double2) * (N_max - c.N) * T, stream));
+        }
+      }
+      first += n_pairs;
+    }
+    blas_check(rocsolver_zgesvd_strided_batched(
+                   bh.h, rocblas_svect_singular, rocblas_svect_none, T, N_max,
+                   reinterpret_cast<rocblas_double_complex *>(d_work.p), T, (rocblas_stride)N_max * T, d_S.p,
+                   (rocblas_stride)mn, reinterpret_cast<rocblas_double_complex *>(d_U.p), T, (rocblas_stride)T * mn,
+                   nullptr, 1, 1, d_E.p, (rocblas_stride)std::max(1, mn - 1), rocblas_outofplace, d_info.p, n_prob),
+               "rocsolver_zgesvd_strided_batched");
+    std::vector<int> info_h(n_prob);
+    std::vector<double> S_h(d_S.n);
+    RBFL_HIP(hipMemcpyAsync(info_h.data(), d_info.p, sizeof(int) * n_prob, hipMemcpyDeviceToHost, stream));
+    RBFL_HIP(hipMemcpyAsync(S_h.data(), d_S.p, sizeof(double) * d_S.n, hipMemcpyDeviceToHost, stream));
+    RBFL_HIP(hipStreamSynchronize(stream));
+    d_work.reset();
+    first = 0;
+    for (size_t i : grp) {
+      Ctx &c = *jobs[i].first;
+      DevBuf<double2> &d_C = jobs[i].second->C;
+      const int n_pairs = c.n_v * c.n_modes, mn_c = std::min(c.N, T);
+      for (int ka = 0; ka < n_pairs; ++ka)
+        if (info_h[first + ka] != 0)
+          throw Error(RBFL_E_NUMERICAL, "SVD of pair " + std::to_string(ka) + " did not converge (info " +
+                                            std::to_string(info_h[first + ka]) + ")");
+      c.singular.assign((size_t)n_pairs * mn_c, 0.0);
+      for (int ka = 0; ka < n_pairs; ++ka)
+        for (int j = 0; j < mn_c; ++j) c.singular[(size_t)ka * mn_c + j] = S_h[(size_t)(first + ka) * mn + j];
+      c.basis.alloc((size_t)n_pairs * T * c.q);
+      d_C.alloc((size_t)n_pairs * c.N * c.q);
+      for (int ka = 0; ka < n_pairs; ++ka) {
+        const double2 *Z = c.z_nodes.p + (size_t)ka * c.N * T;
+        launch_basis_from_u(d_U.p + (size_t)(first + ka) * T * mn, T, T, c.q, c.basis.p + (size_t)ka * T * c.q,
+                            stream);
+        launch_coeffs(Z, c.basis.p + (size_t)ka * T * c.q, c.N, T, c.q, d_C.p + (size_t)ka * c.N * c.q, stream);
+      }
+      first += n_pairs;
+    }
+    RBFL_HIP(hipStreamSynchronize(stream));
   }
-  RBFL_HIP(hipStreamSynchronize(stream));
-  d_U.reset();
-  c.timing[3] = seconds_since(t0);
+  const double dt = seconds_since(t0);
+  for (const auto &j : jobs) j.first->timing[3] = dt;
+}
 
-  // ---- RBF system (Eq. rbfcoeff) and FP64 LU solve
-  t0 = Clock::now();
+// RBF system (Eq. rbfcoeff) and FP64 LU solve, then the online stage's
+// constants and spline-folded basis.
+static void build_back(const rbfl_build_spec *s, hipStream_t stream, Ctx &c, BuildCarry &carry) {
+  const auto t0 = Clock::now();
+  int poly[kMaxPoly][3];
+  monomials(c.degree, poly);
+  const int NM = c.N + c.M;
+  YlmTerms yneg[RBFL_MAX_MODES], ypos[RBFL_MAX_MODES];
+  for (int a = 0; a < c.n_modes; ++a) {
+    yneg[a] = ylm_terms(c.modes[a][0], -c.modes[a][1]);
+    ypos[a] = ylm_terms(c.modes[a][0], c.modes[a][1]);
+  }
+  const double(&band_t)[RBFL_MAX_BANDS][RBFL_MAX_MODES] = carry.band_t;
+  const DevBuf<double2> &d_C = carry.C, &d_sig = carry.sig;
+  BlasHandle bh;
+  blas_check(rocblas_set_stream(bh.h, stream), "rocblas_set_stream");
+  DevBuf<int> d_info;
+  d_info.alloc(1);
   std::vector<int4> coldesc;
   int coef_off[RBFL_MAX_BLOCKS][RBFL_MAX_MODES], sig_off[RBFL_MAX_BLOCKS];
   for (int k = 0; k < c.n_v; ++k) {
@@ -1365,8 +1440,79 @@ static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
   c.nan_part.alloc(kNanParts);
   launch_count_nan(nullptr, 0, c.nan_part.p, stream);
   RBFL_HIP(hipStreamSynchronize(stream));
-  c.timing[5] = seconds_since(t_all);
+  c.timing[5] = seconds_since(carry.t_all);
   if (debug_mode()) debug_check_layout(c);
+}
+
+static void build(const rbfl_build_spec *s, hipStream_t stream, Ctx &c) {
+  BuildCarry carry;
+  build_front(s, stream, c, carry);
+  svd_stage({{&c, &carry}}, stream);
+  build_back(s, stream, c, carry);
+}
+
+// Runs fn(i, stream) for i = 0 .. n-1 on up to n_threads host threads, each
+// with the given device current and a stream of its own; the first failure
+// stops the others from taking further items and is rethrown here.
+template <class F>
+static void run_on_threads(int n, int n_threads, int device, F &&fn) {
+  std::atomic<int> next{0};
+  std::atomic<bool> stop{false};
+  std::mutex mu;
+  int32_t err_code = RBFL_OK;
+  std::string err_msg;
+  auto fail = [&](int32_t code, const std::string &msg) {
+    std::lock_guard<std::mutex> lock(mu);
+    if (err_code == RBFL_OK) {
+      err_code = code;
+      err_msg = msg;
+    }
+    stop = true;
+  };
+  auto worker = [&]() {
+    hipStream_t st = nullptr;
+    try {
+      RBFL_HIP(hipSetDevice(device));
+      RBFL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      for (int i = next++; i < n && !stop; i = next++) fn(i, st);
+    } catch (const Error &e) {
+      fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+      fail(RBFL_E_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::exception &e) {
+      fail(RBFL_E_DEVICE, e.what());
+    }
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = std::max(1, std::min(n_threads, n));
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto &t : pool) t.join();
+  if (err_code != RBFL_OK) throw Error(err_code, err_msg);
+}
+
+// Several start-ups at once: the stages before and after the SVD run on
+// n_threads host threads (one stream each), and the SVDs of all start-ups
+// go through one batched call per window length on the caller's stream.
+static void build_many(const rbfl_build_spec *specs, int n, int n_threads, hipStream_t stream,
+                       std::vector<std::unique_ptr<rbfl_ctx>> &hs) {
+  for (int i = 0; i < n; ++i) validate(specs + i);   // every spec checked before any device call
+  int device = 0;
+  RBFL_HIP(hipGetDevice(&device));
+  hs.clear();
+  for (int i = 0; i < n; ++i) hs.emplace_back(new rbfl_ctx());
+  std::vector<BuildCarry> carry(n);
+  run_on_threads(n, n_threads, device,
+                 [&](int i, hipStream_t st) { build_front(specs + i, st, hs[i]->c, carry[i]); });
+  std::vector<std::pair<Ctx *, BuildCarry *>> jobs;
+  for (int i = 0; i < n; ++i) jobs.emplace_back(&hs[i]->c, &carry[i]);
+  svd_stage(jobs, stream);
+  run_on_threads(n, n_threads, device,
+                 [&](int i, hipStream_t st) { build_back(specs + i, st, hs[i]->c, carry[i]); });
 }
 
 // The quantities the interpolants approximate, computed exactly at each
@@ -1450,6 +1596,19 @@ int32_t rbfl_build(const rbfl_build_spec *spec, void *stream, rbfl_handle *out) 
     std::unique_ptr<rbfl_ctx> h(new rbfl_ctx());
     rbfl::build(spec, reinterpret_cast<hipStream_t>(stream), h->c);
     *out = h.release();
+  });
+}
+
+int32_t rbfl_build_many(const rbfl_build_spec *specs, int32_t n, int32_t n_threads, void *stream, rbfl_handle *out) {
+  return rbfl::guarded([&] {
+    rbfl::require(out != nullptr, "out is NULL");
+    rbfl::require(n >= 1 && n <= 4096, "n must be in 1 .. 4096");
+    for (int i = 0; i < n; ++i) out[i] = nullptr;
+    rbfl::require(specs != nullptr, "specs is NULL");
+    rbfl::require(n_threads >= 1 && n_threads <= 16, "n_threads must be in 1 .. 16");
+    std::vector<std::unique_ptr<rbfl_ctx>> hs;
+    rbfl::build_many(specs, n, n_threads, reinterpret_cast<hipStream_t>(stream), hs);
+    for (int i = 0; i < n; ++i) out[i] = hs[i].release();
   });
 }
 

@@ -34,7 +34,7 @@ Q_SIZES, Q_FRAME, Q_D_REF, Q_NODES, Q_NODE_PHYS, Q_WEIGHTS, Q_BASIS, Q_NODE_VALU
 SPLIT_TOL = 1e-4
 STATIC_SCRATCH_BYTES = 128 << 20
 
-EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
+EXPORTED = ("rbfl_last_error", "rbfl_build", "rbfl_build_many", "rbfl_brute", "rbfl_exact_parts", "rbfl_eval", "rbfl_interp", "rbfl_prepare", "rbfl_reserve",
             "rbfl_query", "rbfl_autotune", "rbfl_variants", "rbfl_set_variant", "rbfl_pipeline",
             "rbfl_fuse_epilogue", "rbfl_set_split_tol",
             "rbfl_profile", "rbfl_plan_create", "rbfl_plan_launch",
@@ -151,6 +151,8 @@ def load(path: str = LIB_PATH):
     lib.rbfl_last_error.argtypes = []
     lib.rbfl_build.restype = C.c_int32
     lib.rbfl_build.argtypes = [C.POINTER(BuildSpec), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.rbfl_build_many.restype = C.c_int32
+    lib.rbfl_build_many.argtypes = [C.POINTER(BuildSpec), C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.rbfl_brute.restype = C.c_int32
     lib.rbfl_brute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     lib.rbfl_exact_parts.restype = C.c_int32
@@ -313,6 +315,25 @@ class Handle:
         keep = []
         spec = spec_from_config(cfg, white, inj_ext, metric, keep)
         return cls.build(spec, stream)
+
+    @classmethod
+    def build_many(cls, specs, n_threads: int = 4, stream: int = 0) -> list:
+        """Handles of several start-ups at once (rbfl_build_many): their SVDs
+        share batched calls on `stream`, the other stages run on n_threads
+        host threads."""
+        lib = load()
+        n = len(specs)
+        arr = (BuildSpec * n)(*specs)
+        hs = (C.c_void_p * n)()
+        _check(lib.rbfl_build_many(arr, n, n_threads, C.c_void_p(stream), hs))
+        return [cls(C.c_void_p(hs[i])) for i in range(n)]
+
+    @classmethod
+    def from_configs(cls, items, n_threads: int = 4, stream: int = 0) -> list:
+        """build_many over (cfg, white, inj_ext) triples."""
+        keep = []
+        specs = [spec_from_config(cfg, white, inj, None, keep) for cfg, white, inj in items]
+        return cls.build_many(specs, n_threads, stream)
 
     @classmethod
     def load(cls, path: str, stream: int = 0) -> "Handle":

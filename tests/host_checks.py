@@ -115,6 +115,19 @@ def main(path):
         expect(lib.rbfl_build(C.byref(s), None, C.byref(h)), rbfl.E_INVALID_ARG, f"spec {label}")
         assert not h.value, label
     expect(lib.rbfl_build(None, None, None), rbfl.E_INVALID_ARG, "NULL spec")
+    # several start-ups: argument checks, and a broken second spec fails the
+    # call before any device work with every output left NULL
+    lib.rbfl_build_many.argtypes = [C.POINTER(rbfl.BuildSpec), C.c_int32, C.c_int32, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]
+    pair = (rbfl.BuildSpec * 2)(spec(), spec())
+    pair[1].q = 0
+    outs = (C.c_void_p * 2)()
+    expect(lib.rbfl_build_many(pair, 2, 2, None, outs), rbfl.E_INVALID_ARG, "build_many broken second spec")
+    assert not outs[0] and not outs[1]
+    expect(lib.rbfl_build_many(None, 1, 1, None, outs), rbfl.E_INVALID_ARG, "build_many NULL specs")
+    expect(lib.rbfl_build_many(pair, 0, 1, None, outs), rbfl.E_INVALID_ARG, "build_many n = 0")
+    expect(lib.rbfl_build_many(pair, 1, 0, None, outs), rbfl.E_INVALID_ARG, "build_many no threads")
+    expect(lib.rbfl_build_many(pair, 1, 1, None, None), rbfl.E_INVALID_ARG, "build_many NULL out")
 
     # ---- NULL handles and arguments
     nul = C.c_void_p()

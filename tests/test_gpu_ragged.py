@@ -90,6 +90,53 @@ def test_ragged_matches_oracle_and_per_event():
         off += n
 
 
+def test_build_many_matches_single_builds():
+    """rbfl_build_many (stages before and after the SVD on 3 host threads, the
+    six events' SVDs in one batched call with their node counts padded to the
+    largest) against one rbfl_build per event: nodes and frame identical, the
+    leading q singular values within 1e-10 of the largest, each basis vector
+    the same up to a phase, the ln L of every event within 1e-3 of the single
+    build's and of the oracle's, with the same domain flags."""
+    torch = _torch()
+    hs, arts = events()
+    items = [(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg)) for cfg in EVENTS]
+    print(f"[ragged] build_many: {len(items)} events, node counts {[c.n_nodes for c in EVENTS]}", flush=True)
+    hm = rbfl.Handle.from_configs(items, n_threads=3)
+    params, cpu = proposals(0)
+    lm = per_event_gpu(hm, params)
+    le = per_event_gpu(hs, params)
+    off = 0
+    for e, (h1, h2, art, n) in enumerate(zip(hs, hm, arts, COUNTS)):
+        assert np.array_equal(h1.nodes(), h2.nodes()) and h1.eps() == h2.eps()
+        assert np.array_equal(h1.frame()["semi"], h2.frame()["semi"])
+        q = h1.sizes()["q"]
+        s1, s2 = h1.singular(), h2.singular()
+        assert s1.shape == s2.shape
+        ds = np.abs(s1[..., :q] - s2[..., :q]).max() / s1[..., 0].max()
+        b1, b2 = h1.basis(), h2.basis()
+        overlap = np.abs(np.einsum("vatq,vatq->vaq", b1.conj(), b2))
+        # vectors compared where their singular value is apart from its
+        # neighbours' (a near-repeated value leaves only the pair's plane fixed)
+        sv = s1[..., :q + 1] / s1[..., :1]
+        gap = np.minimum(np.diff(sv, prepend=np.inf)[..., :q] * -1.0, -np.diff(sv)[..., :q])
+        sep = np.abs(gap) > 1e-6
+        du = np.abs(1.0 - overlap[sep]).max() if sep.any() else 0.0
+        a, b = le[off:off + n], lm[off:off + n]
+        f = np.isfinite(a)
+        assert np.array_equal(f, np.isfinite(b)), f"event {e}: domain flags differ"
+        d = np.abs(a[f] - b[f]).max() if f.any() else 0.0
+        lo = lk.meshfree_lnl(art, *cpu[e])
+        do = np.abs(b[f] - lo[f]).max() if f.any() else 0.0
+        print(f"[ragged] build_many event {e}: N {h1.sizes()['N']}, singular values {ds:.1e}, basis "
+              f"{du:.1e}, max |dlnL| vs single build {d:.1e}, vs oracle {do:.1e}", flush=True)
+        assert ds <= 1e-10 and du <= 1e-8 and d <= 1e-3 and do <= 1e-3
+        off += n
+    t = np.array([h.timing()[3] for h in hm])
+    assert np.all(t == t[0]) and t[0] > 0     # one batched SVD stage for all
+    for h in hm:
+        h.close()
+
+
 def test_plan_graph_replays_follow_new_proposals():
     """Capture once, then per sampler step write new proposals into the same
     device buffer, with eager work in between, and check every replay."""
