@@ -137,6 +137,43 @@ def test_build_many_matches_single_builds():
         h.close()
 
 
+def test_build_many_two_window_lengths():
+    """rbfl_build_many over events with two window lengths (one SVD call per
+    length: the second event's window is 30 ms instead of 50 ms) against one
+    rbfl_build per event: same singular values, basis up to a phase, ln L
+    within 1e-3 with the same domain flags."""
+    torch = _torch()
+    cfgs = [EVENTS[1], EVENTS[4].with_(name=EVENTS[4].name + "_w30", half_window=0.03), EVENTS[0]]
+    items = [(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg)) for cfg in cfgs]
+    hm = rbfl.Handle.from_configs(items, n_threads=2)
+    Ts = [h.sizes()["T"] for h in hm]
+    assert len(set(Ts)) == 2, Ts
+    for e, (cfg, h2, (c, white, inj)) in enumerate(zip(cfgs, hm, items)):
+        h1 = rbfl.Handle.from_config(cfg, white, inj)
+        q = h1.sizes()["q"]
+        ds = np.abs(h1.singular()[..., :q] - h2.singular()[..., :q]).max() / h1.singular()[..., 0].max()
+        n = 512
+        idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=70 + e)
+        qd = wl.queries(cfg, n=n, seed=80 + e)
+        p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h1, qd.near_nodes(h1.nodes(), idx, jit),
+                                                                  cfg.t_trig))).cuda()
+        a = torch.empty(n, dtype=torch.float64, device="cuda")
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        h1.eval(p.data_ptr(), n, a.data_ptr())
+        h2.eval(p.data_ptr(), n, b.data_ptr())
+        torch.cuda.synchronize()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        f = np.isfinite(a)
+        assert np.array_equal(f, np.isfinite(b)), f"event {e}: domain flags differ"
+        d = np.abs(a[f] - b[f]).max() if f.any() else 0.0
+        print(f"[ragged] build_many, two windows, event {e}: T {Ts[e]}, N {cfg.n_nodes}, {f.sum()}/{n} valid, "
+              f"singular values {ds:.1e}, max |dlnL| vs single build {d:.1e}", flush=True)
+        assert ds <= 1e-10 and d <= 1e-3
+        h1.close()
+    for h in hm:
+        h.close()
+
+
 def test_plan_graph_replays_follow_new_proposals():
     """Capture once, then per sampler step write new proposals into the same
     device buffer, with eager work in between, and check every replay."""
