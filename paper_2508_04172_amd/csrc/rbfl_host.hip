@@ -1489,7 +1489,11 @@ static void run_on_threads(int n, int n_threads, int device, F &&fn) {
   };
   std::vector<std::thread> pool;
   const int nt = std::max(1, std::min(n_threads, n));
-  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  try {
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  } catch (const std::exception &) {
+    // fewer threads than asked: the ones running (and this one) take every item
+  }
   worker();
   for (auto &t : pool) t.join();
   if (err_code != RBFL_OK) throw Error(err_code, err_msg);
