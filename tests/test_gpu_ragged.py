@@ -137,6 +137,32 @@ def test_build_many_matches_single_builds():
         h.close()
 
 
+def test_build_many_single_event_is_rbfl_build():
+    """rbfl_build_many over one event runs the same stages and the same
+    unpadded SVD as rbfl_build: identical artefacts and ln L bit for bit."""
+    torch = _torch()
+    hs, _ = events()
+    cfg = EVENTS[2]
+    (h2,) = rbfl.Handle.from_configs([(cfg, wl.white_noise(cfg), wl.injection_extrinsics(cfg))], n_threads=4)
+    h1 = hs[2]
+    assert np.array_equal(h1.weights(), h2.weights()) and np.array_equal(h1.singular(), h2.singular())
+    assert np.array_equal(h1.basis(), h2.basis())
+    n = 700
+    idx, jit = wl.node_jitter(n, cfg.n_nodes, seed=5)
+    qd = wl.queries(cfg, n=n, seed=6)
+    p = torch.from_numpy(np.ascontiguousarray(rbfl.params_soa(h1, qd.near_nodes(h1.nodes(), idx, jit),
+                                                              cfg.t_trig))).cuda()
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    h1.eval(p.data_ptr(), n, a.data_ptr())
+    h2.eval(p.data_ptr(), n, b.data_ptr())
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    assert np.array_equal(a[np.isfinite(a)], b[np.isfinite(b)])
+    h2.close()
+
+
 def test_build_many_two_window_lengths():
     """rbfl_build_many over events with two window lengths (one SVD call per
     length: the second event's window is 30 ms instead of 50 ms) against one
