@@ -300,8 +300,11 @@ def main():
         from threadpoolctl import threadpool_info
         from oracle import likelihood as lk
         from oracle import startup as su
-        log("oracle start-up on the host (not timed)")
+        log("oracle start-up on the host")
+        t = time.perf_counter()
         art = su.startup(cfg, white, inj)
+        oracle_startup_s = time.perf_counter() - t
+        log(f"oracle start-up {oracle_startup_s:.1f} s (rbfl_build {build_s:.2f} s)")
         rng = np.random.default_rng(321)
         m = min(args.cpu_sample, n)
         sample = np.sort(rng.choice(n, m, replace=False))
@@ -330,7 +333,11 @@ def main():
                                   "single_thread_value": m1 / cpu1_s,
                                   "single_thread_sample": f"the first {m1} of that sample, {cpu1_s:.1f} s, BLAS "
                                                           "limited to 1 thread",
-                                  "blas": blas}
+                                  "blas": blas,
+                                  "startup_s": round(oracle_startup_s, 1),
+                                  "startup_note": "the oracle's start-up (data, frame, nodes, FFT overlap series, "
+                                                  "SVD, RBF solve) on the same host; rbfl_build took "
+                                                  f"{build_s:.2f} s on the GPU"}
         log(f"oracle: {m / cpu_s:.4e} evals/s on {threads} threads, {m1 / cpu1_s:.4e} on one ({blas})")
         fin = np.isfinite(lo)
         for name, l in outs.items():
